@@ -1,0 +1,366 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each check uses numpy's stable
+sort (the closed form of a sort), brute-force counting, rocRAND's Philox, a
+special case with a known answer, or an invariant the paper states.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import refcheck as R
+
+U64 = np.uint64
+
+
+def _keys(kind, n, seed, bits=64):
+    k = synth.make(kind, n, seed)
+    return k if bits == 64 else (k >> U64(32)).astype(np.uint32)
+
+
+# ---------------------------------------------------------------- Philox ----
+
+def test_philox_matches_rocrand(rocrand_philox):
+    rng = np.random.default_rng(7)
+    seeds = [0, 1, 2, 0xFFFFFFFF, 1 << 32, (1 << 64) - 1] + [int(x) for x in rng.integers(0, 2**63, 20)]
+    js = [1, 2, 3, 7, 14, 1 << 20]
+    gs = [0, 1, 2, 3, 4, 5, 1023, 1 << 20, (1 << 34) + 3, (1 << 40) + 2]
+    S, J, G = [], [], []
+    for s in seeds:
+        for j in js:
+            for g in gs:
+                S.append(s); J.append(j); G.append(g)
+    ref = rocrand_philox(S, J, G)
+    got = [oracle.philox_word(s, g, j) for s, j, g in zip(S, J, G)]
+    assert got == ref
+
+
+def test_philox_block_words_are_distinct_words():
+    # word g & 3 of one block: four consecutive tags share one counter
+    blk = oracle.philox4x32_10([5, 0, 3, 0], [9, 0])
+    assert [oracle.philox_word(9, 20 + w, 3) for w in range(4)] == [int(x) for x in blk]
+
+
+# ------------------------------------------------------------- constants ----
+
+@pytest.mark.parametrize("n,p,eps", [(1 << 20, 16, 0.05), (1 << 28, 1024, 0.02),
+                                     (1 << 28, 4096, 0.05), (1000, 7, 0.3), (12345, 100, 0.9),
+                                     (64, 64, 0.5), (1 << 40, 1 << 20, 0.01)])
+def test_constants_closed_forms(n, p, eps):
+    c = oracle.constants(n, p, eps)
+    # target range half-width: tol <= N eps / (2p) < tol + 1 (section 2)
+    x = Fraction(n) * Fraction(eps) / (2 * p)
+    assert c.tol <= x < c.tol + 1
+    # final ratio s_k = 2 ln p / eps (lemma on the k-th round)
+    assert c.a == pytest.approx(2 * math.log(p) / eps, rel=1e-15)
+    # k = ceil(ln a): e^(k-1) < a <= e^k, at least one round
+    if c.a > math.e:
+        assert math.exp(c.k - 1) < c.a <= math.exp(c.k) * (1 + 1e-12)
+    else:
+        assert c.k == 1
+    # per-round acceptance probability p s_j / N with s_j = a^(j/k) (section 4.2)
+    for j in range(1, 40):
+        q = p * c.a ** (j / c.k) / n
+        if q >= 1:
+            assert c.all[j - 1] == 1
+        else:
+            assert c.all[j - 1] == 0
+            assert abs(c.thresh[j - 1] / 2**32 - q) <= 2**-32 + q * 1e-12
+    # thresholds grow round over round by the ratio a^(1/k)
+    th = [int(t) for t, a in zip(c.thresh, c.all) if not a]
+    assert all(x <= y for x, y in zip(th, th[1:]))
+    if len(th) >= 3 and th[1] > 1 << 16:
+        assert th[2] / th[1] == pytest.approx(c.a ** (1 / c.k), rel=1e-4)
+
+
+def test_constants_one_round_rate():
+    # k = 1 is the one-round method of section 4.1: rate 2 p ln p / (eps N)
+    n, p, eps = 1 << 26, 512, 0.05
+    c = oracle.constants(n, p, eps, k_override=1)
+    assert c.k == 1
+    assert c.thresh[0] / 2**32 == pytest.approx(2 * p * math.log(p) / (eps * n), abs=2**-32)
+
+
+def test_constants_section7_worked_numbers():
+    # Section 7.2: with p = 2048 and eps = 2%, 2p max(1/eps, log p) is about 100 p.
+    p, eps = 2048, 0.02
+    assert 2 * p * max(1 / eps, math.log2(p)) == pytest.approx(100 * p)
+    # and the final HSS ratio 2 ln p / eps for that run
+    c = oracle.constants(2048 * 1_000_000, p, eps)
+    assert c.a == pytest.approx(2 * math.log(2048) / 0.02)
+    # section 4.1: (p-1)/p^2 < 1/p
+    assert (p - 1) / p**2 < 1 / p
+
+
+# ------------------------------------------------------------ local sort ----
+
+@pytest.mark.parametrize("kind,bits", [("uniform64", 64), ("SKEW2", 64), ("uniform32", 32),
+                                       ("ALLZEROS", 64), ("zipf_morton", 64)])
+@pytest.mark.parametrize("n,p", [(1000, 7), (4096, 16), (513, 512)])
+def test_local_sort_is_stable_sort_per_segment(kind, bits, n, p):
+    keys = synth.make(kind, n, 11)
+    if bits == 32:
+        keys = keys.astype(np.uint32) if kind == "uniform32" else (keys & U64(0xFFFF)).astype(np.uint32)
+    vals = np.arange(n, dtype=np.uint64) * U64(3)
+    ko, vo = oracle.local_sort(keys, p, vals)
+    lo = R.local_order(keys, p)
+    assert np.array_equal(ko, keys[lo])
+    assert np.array_equal(vo, vals[lo])
+
+
+# ------------------------------------------------- whole-method outputs ----
+
+CASES = [
+    # kind, n, p, eps, seed, bits, payload
+    ("uniform64", 1 << 16, 16, 0.05, 1, 64, False),
+    ("uniform64", 50_000, 37, 0.02, 2, 64, True),
+    ("uniform32", 30_001, 64, 0.1, 3, 32, True),
+    ("SKEW1", 20_000, 32, 0.05, 4, 64, False),
+    ("SKEW2", 20_000, 32, 0.05, 5, 64, True),
+    ("SKEW3", 20_000, 20, 0.05, 6, 64, False),
+    ("GAUSS", 20_000, 20, 0.05, 7, 64, False),
+    ("ALLZEROS", 10_000, 25, 0.05, 8, 64, True),
+    ("zipf_morton", 40_000, 128, 0.05, 9, 64, True),
+    ("uniform64", 5000, 1, 0.05, 10, 64, True),       # p = 1: one segment, no rounds
+    ("uniform64", 300, 300, 0.5, 11, 64, True),       # p = N
+    ("uniform64", 4000, 9, 1e-6, 12, 64, False),      # tol = 0: exact splitting
+    ("SKEW2", 3333, 10, 0.003, 13, 64, True),         # tol = 0 with duplicates
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-{c[1]}-{c[2]}" for c in CASES])
+def test_sort_equals_stable_sort(case):
+    kind, n, p, eps, seed, bits, payload = case
+    keys = synth.make(kind, n, seed)
+    if bits == 32:
+        keys = keys.astype(np.uint32)
+    vals = np.arange(n, dtype=np.uint64) if payload else None
+    r = oracle.hss(keys, p, eps, seed, vals=vals, mode="sort")
+    assert r.status == 0
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(r.keys, keys[order])
+    if payload:
+        assert np.array_equal(r.vals, vals[order])
+    R.check_balance(r.offsets, n, p, r.tol)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-{c[1]}-{c[2]}" for c in CASES])
+def test_partition_matches_definition(case):
+    kind, n, p, eps, seed, bits, payload = case
+    keys = synth.make(kind, n, seed)
+    if bits == 32:
+        keys = keys.astype(np.uint32)
+    vals = np.arange(n, dtype=np.uint64) if payload else None
+    r = oracle.hss(keys, p, eps, seed, vals=vals, mode="partition")
+    assert r.status == 0
+    R.check_balance(r.chi, n, p, r.tol)
+    assert np.array_equal(r.offsets, r.chi)
+    ek, ev = R.expected_partition(keys, vals, p, r.chi)
+    assert np.array_equal(r.keys, ek)
+    if payload:
+        assert np.array_equal(r.vals, ev)
+    # splitter S(i) is the element of global rank chi(i)
+    tr = R.tag_rank(keys, p)
+    for i in range(1, p):
+        assert tr[int(r.s_tag[i])] == int(r.chi[i])
+    # piece matrix row b = per-segment counts of S(b)
+    if n <= 50_000 and p <= 64:
+        for i in range(1, p):
+            assert np.array_equal(r.pieces[i], R.brute_counts(keys, p, int(r.s_tag[i])))
+
+
+def test_full_sample_settles_exactly():
+    # every key is a probe in round 1, so each splitter lands on N i / p exactly
+    for kind, n, p in [("uniform64", 3000, 13), ("SKEW2", 2000, 16), ("ALLZEROS", 999, 10)]:
+        keys = synth.make(kind, n, 3)
+        r = oracle.hss(keys, p, 0.05, 1, force_full_sample=True)
+        assert r.status == 0
+        assert len(r.rounds) == (1 if p > 1 else 0)
+        assert [int(c) for c in r.chi] == list(R.ideal(n, p))
+        assert r.rounds[0].m == n
+
+
+def test_ranks_and_counts_by_brute_force():
+    keys = synth.make("SKEW2", 1500, 21)      # many duplicates across segments
+    p = 7
+    r = oracle.hss(keys, p, 0.05, 5, trace_level=2)
+    assert r.status == 0
+    tr = R.tag_rank(keys, p)
+    for rd in r.rounds:
+        assert rd.m == len(rd.probe_tag)
+        for e in range(rd.m):
+            g = int(rd.probe_tag[e])
+            c = R.brute_counts(keys, p, g)
+            assert np.array_equal(rd.counts[e], c)
+            assert int(rd.probe_rank[e]) == int(c.sum()) == int(tr[g])
+        # probes listed in the strict order (key, tag)
+        ks = [(int(a), int(b)) for a, b in zip(rd.probe_key, rd.probe_tag)]
+        assert ks == sorted(ks)
+        assert np.all(np.diff(rd.probe_rank.astype(np.int64)) > 0)
+
+
+def _domain_from_state(n, p, tr_rank, prev, ideal, tol):
+    """Tags strictly inside an unsettled interval, from the previous round's state."""
+    if prev is None:
+        return np.ones(n, dtype=bool)
+    dom = np.zeros(n, dtype=bool)
+    for i in range(1, p):
+        if prev.settled[i - 1]:
+            continue
+        lo = -1 if int(prev.lo_rank[i - 1]) == R.NONE else int(prev.lo_rank[i - 1])
+        hi = n if int(prev.hi_rank[i - 1]) == R.NONE else int(prev.hi_rank[i - 1])
+        dom |= (tr_rank > lo) & (tr_rank < hi)
+    return dom
+
+
+@pytest.mark.parametrize("kind,n,p,eps,seed", [("uniform64", 20_000, 16, 0.05, 3),
+                                               ("SKEW2", 8000, 12, 0.02, 4),
+                                               ("zipf_morton", 30_000, 40, 0.05, 5),
+                                               ("uniform64", 6000, 33, 0.01, 6)])
+def test_round_probe_sets_follow_sampling_rule(kind, n, p, eps, seed, rocrand_philox):
+    """Each round's probes are exactly the keys of the previous round's
+    unsettled intervals whose rocRAND Philox word is below the threshold; the
+    state after each round is the tightest one the probes allow."""
+    keys = synth.make(kind, n, seed)
+    r = oracle.hss(keys, p, eps, seed)
+    assert r.status == 0
+    tr = R.tag_rank(keys, p)
+    idl = R.ideal(n, p)
+    seen = []          # ranks of all probes so far
+    prev = None
+    for j, rd in enumerate(r.rounds, start=1):
+        dom = _domain_from_state(n, p, tr, prev, idl, r.tol)
+        assert rd.domain == int(dom.sum())
+        tags = np.nonzero(dom)[0]
+        if rd.all:
+            chosen = tags
+        else:
+            w = np.array(rocrand_philox([seed] * len(tags), [j] * len(tags), tags.tolist()),
+                         dtype=np.uint64) if len(tags) else np.zeros(0, dtype=np.uint64)
+            chosen = tags[w < rd.thresh]
+        assert sorted(chosen.tolist()) == sorted(int(t) for t in rd.probe_tag)
+        seen_before = list(seen)
+        seen += [int(x) for x in rd.probe_rank]
+        this = sorted(int(x) for x in rd.probe_rank)
+        for i in range(1, p):
+            ideal_i = int(idl[i])
+            was = prev is not None and prev.settled[i - 1]
+            if was:
+                assert rd.settled[i - 1] and rd.chi[i - 1] == prev.chi[i - 1]
+                continue
+            # never settled earlier: no earlier probe was inside the target range
+            assert all(abs(x - ideal_i) > r.tol for x in seen_before)
+            if rd.settled[i - 1]:
+                c = int(rd.chi[i - 1])
+                assert c in this and abs(c - ideal_i) <= r.tol
+                # no probe of this round strictly closer; ties go to the lower rank
+                for x in this:
+                    assert abs(x - ideal_i) > abs(c - ideal_i) or (abs(x - ideal_i) == abs(c - ideal_i) and x >= c)
+            else:
+                lo = int(rd.lo_rank[i - 1]); hi = int(rd.hi_rank[i - 1])
+                lo = -1 if lo == R.NONE else lo
+                hi = n if hi == R.NONE else hi
+                assert lo < ideal_i - r.tol and hi > ideal_i + r.tol
+                assert lo == -1 or lo in seen
+                assert hi == n or hi in seen
+                assert not any(lo < x < hi for x in seen)   # tightest bounds
+        # unsettled intervals are disjoint or identical (section 4.2.2)
+        ivs = sorted({(int(rd.lo_rank[i]), int(rd.hi_rank[i])) for i in range(p - 1)
+                      if not rd.settled[i]})
+        for (a1, b1), (a2, b2) in zip(ivs, ivs[1:]):
+            a1 = -1 if a1 == R.NONE else a1
+            a2 = -1 if a2 == R.NONE else a2
+            b1 = n if b1 == R.NONE else b1
+            assert b1 <= a2 + 0 or (a1, b1) == (a2, b2)
+        prev = rd
+    assert all(prev.settled) if prev is not None else p == 1
+
+
+def test_bounds_monotone_across_rounds():
+    keys = synth.make("uniform64", 1 << 15, 2)
+    n, p = len(keys), 64
+    r = oracle.hss(keys, p, 0.01, 9)
+    for a, b in zip(r.rounds, r.rounds[1:]):
+        for i in range(p - 1):
+            if b.settled[i]:
+                continue
+            la = -1 if int(a.lo_rank[i]) == R.NONE else int(a.lo_rank[i])
+            lb = -1 if int(b.lo_rank[i]) == R.NONE else int(b.lo_rank[i])
+            ha = n if int(a.hi_rank[i]) == R.NONE else int(a.hi_rank[i])
+            hb = n if int(b.hi_rank[i]) == R.NONE else int(b.hi_rank[i])
+            assert la <= lb and hb <= ha
+
+
+# ----------------------------------------------------------- statistics ----
+
+def test_sampling_statistics_round1():
+    """Round 1 takes each key with probability p s_1 / N (section 4.2.1)."""
+    n, p, eps = 1 << 17, 64, 0.05
+    c = oracle.constants(n, p, eps)
+    q = c.thresh[0] / 2**32
+    ms = []
+    for seed in range(40):
+        keys = synth.make("uniform64", n, 100 + seed)
+        r = oracle.hss(keys, p, eps, seed, trace_level=0)
+        ms.append(r.rounds[0].m)
+    mean = np.mean(ms)
+    sd = math.sqrt(n * q * (1 - q) / len(ms))
+    assert abs(mean - n * q) < 5 * sd
+    assert n * q == pytest.approx(p * c.a ** (1 / c.k), rel=1e-6)
+
+
+def test_interval_union_and_sample_size_lemmas():
+    """E|gamma_j| <= 2N/s_j (section 4.2, expectation lemma) and
+    Z_j <= 5 p s_j / s_{j-1} (sample-size lemma), checked loosely over seeds."""
+    n, p, eps = 1 << 18, 256, 0.02
+    c = oracle.constants(n, p, eps)
+    sj = lambda j: c.a ** (j / c.k)
+    dom = {}
+    over = 0
+    total = 0
+    rounds = []
+    for seed in range(12):
+        keys = synth.make("uniform64", n, 500 + seed)
+        r = oracle.hss(keys, p, eps, seed, trace_level=0)
+        rounds.append(len(r.rounds))
+        for j, rd in enumerate(r.rounds, start=1):
+            dom.setdefault(j, []).append(rd.domain)
+            if j >= 2:
+                total += 1
+                over += rd.m > 5 * p * sj(j) / sj(j - 1)
+    for j in range(2, 5):
+        # the domain of round j+1 is gamma_j; rounds that never happen have 0
+        vals = dom.get(j + 1, []) + [0] * (12 - len(dom.get(j + 1, [])))
+        assert np.mean(vals) <= 1.25 * 2 * n / sj(j)
+    assert over <= max(1, total // 10)
+    assert np.mean(rounds) <= c.k + 1
+
+
+def test_rounds_independent_of_distribution_in_law():
+    # The rank process does not depend on key values (section 7.5): with the
+    # same seed, an all-equal input and a uniform input sample the same tags
+    # in round 1.
+    n, p = 20_000, 16
+    a = oracle.hss(synth.make("uniform64", n, 1), p, 0.05, 77)
+    b = oracle.hss(synth.make("ALLZEROS", n, 1), p, 0.05, 77)
+    assert sorted(a.rounds[0].probe_tag.tolist()) == sorted(b.rounds[0].probe_tag.tolist())
+
+
+# ----------------------------------------------------------- arguments ----
+
+@pytest.mark.parametrize("n,p,eps", [(10, 0, 0.1), (10, 11, 0.1), (10, 2, 0.0), (10, 2, 1.0),
+                                     (10, 2, -0.5), (0, 1, 0.1)])
+def test_invalid_arguments(n, p, eps):
+    keys = np.arange(max(n, 1), dtype=np.uint64)[:n]
+    r = oracle.hss(keys, p, eps, 1)
+    assert r.status == -1
+
+
+def test_round_cap_reports_not_converged():
+    keys = synth.make("uniform64", 1 << 16, 3)
+    r = oracle.hss(keys, 64, 0.01, 3, max_rounds=1)
+    assert r.status == -5
