@@ -1,0 +1,166 @@
+/*
+ * hss.h -- Histogram Sort with Sampling on one MI355X (gfx950).
+ *
+ * C ABI of libhss.so.  The method is the one of Harsh, Kale and Solomonik,
+ * "Histogram Sort with Sampling" (SPAA'19): the p processors of the paper are
+ * p contiguous segments of one device buffer, segment s holding the input
+ * positions [floor(s N / p), floor((s+1) N / p)).
+ *
+ * Conventions shared by every entry point
+ *   - Device pointers are caller-owned and must stay valid until the work
+ *     enqueued on `stream` has completed.  Inputs are never modified.
+ *     Outputs must not overlap inputs; every device pointer must be 16-byte
+ *     aligned.  Violations return HSS_ERR_INVALID_ARG before any work is
+ *     enqueued.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All work is enqueued on `stream`.  The splitter rounds read a few words
+ *     back to the host once per round, and hss_partition / hss_sort read the
+ *     device consistency word once more at the end, so both return after
+ *     their work on `stream` has completed.  hss_local_sort is asynchronous.
+ *   - Keys are unsigned integers (32 or 64 bit) compared as unsigned.  Equal
+ *     keys are ordered by (source segment, position in the segment), the
+ *     implicit tags of section 6.1, which makes every result equal to what a
+ *     stable sort of the input would give.
+ *   - A payload, when given, is one uint64_t per key moved with its key.
+ *   - No C++ exception crosses this interface.  On failure the status is
+ *     returned and hss_last_error() holds a message for the calling thread.
+ */
+#ifndef HSS_H
+#define HSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { HSS_U32 = 0, HSS_U64 = 1 } hss_key_type;
+
+typedef enum {
+    HSS_OK = 0,
+    HSS_ERR_INVALID_ARG = -1,    /* bad sizes, null or misaligned pointers, overlap */
+    HSS_ERR_UNSUPPORTED = -2,    /* a valid request this build does not handle      */
+    HSS_ERR_OUT_OF_MEMORY = -3,  /* device allocation failed                        */
+    HSS_ERR_DEVICE = -4,         /* HIP error or a failed device-side consistency check */
+    HSS_ERR_NOT_CONVERGED = -5   /* tuning.max_rounds reached with splitters unsettled */
+} hss_status;
+
+typedef struct hss_plan_s* hss_plan_t;
+
+/* Optional knobs; zero-initialise for the defaults. */
+typedef struct {
+    uint32_t max_rounds;        /* 0: no cap.  The schedule reaches rate 1 after a
+                                   bounded number of rounds, which settles every
+                                   splitter, so the default always converges.    */
+    uint32_t k_override;        /* 0: k = max(1, ceil(ln(2 ln p / eps))) (section 4.2) */
+    uint32_t force_full_sample; /* 1: every key is a probe in round 1 (one round) */
+    uint32_t trace_level;       /* 0: per-round counts only; 1: also probes, ranks
+                                   and splitter state per round (host copies)    */
+    uint32_t reserved[4];       /* must be zero */
+} hss_tuning;
+
+/*
+ * hss_plan -- validate (N, p, eps, key type) and prepare a plan.
+ *   n            number of keys N, 1 <= p <= N (section 2: N/p keys per processor)
+ *   p            number of segments ("processors") and of output buckets
+ *   eps          balance tolerance, 0 < eps < 1: every splitter rank lies in
+ *                [N i/p - tol, N i/p + tol] with tol = floor(N eps / (2p))
+ *                (target range, section 2), so no bucket exceeds
+ *                ceil(N/p) + 2 tol <= N (1 + eps) / p + 1 keys
+ *   kt           HSS_U32 or HSS_U64 keys
+ *   with_payload 1 if calls will pass a uint64_t payload per key
+ *   tuning       NULL for defaults
+ * The plan owns a device workspace of hss_workspace_bytes(plan) bytes,
+ * allocated on the current device.  A plan may be reused for any number of
+ * calls; calls on one plan must not overlap in time.
+ */
+hss_status hss_plan(hss_plan_t* out, uint64_t n, uint32_t p, double eps, hss_key_type kt,
+                    int with_payload, const hss_tuning* tuning);
+
+/* Release a plan and its device memory (synchronises the device). NULL is ok. */
+void hss_plan_destroy(hss_plan_t plan);
+
+/* Bytes of device memory held by the plan. */
+size_t hss_workspace_bytes(hss_plan_t plan);
+
+/*
+ * hss_partition -- the partition of HSS (section 4.2.2 steps 1-5, then the
+ * data exchange of section 3.1 step 3 done as one bucketed scatter).
+ *   seed          selects the Philox4x32-10 stream of the sampling rounds
+ *   d_keys_in     N keys (uint32_t or uint64_t per the plan)
+ *   d_vals_in     N payload words, or NULL for a keys-only plan
+ *   d_keys_out    N keys: bucket b = 0..p-1 occupies [chi(b), chi(b+1)) and holds
+ *                 the keys of global rank chi(b)..chi(b+1)-1, as pieces in
+ *                 ascending source segment, each piece in local sorted order
+ *   d_vals_out    N payload words moved with the keys (NULL iff d_vals_in NULL)
+ *   d_offsets     p+1 uint64_t: chi(0) = 0, chi(1..p-1) = splitter ranks, chi(p) = N
+ */
+hss_status hss_partition(hss_plan_t plan, uint64_t seed, const void* d_keys_in,
+                         const uint64_t* d_vals_in, void* d_keys_out, uint64_t* d_vals_out,
+                         uint64_t* d_offsets, void* stream);
+
+/*
+ * hss_sort -- hss_partition followed by a stable sort of every bucket
+ * (the local merge after the exchange, section 5): the output is the stable
+ * sort of the input by key.  Same arguments and offsets as hss_partition.
+ */
+hss_status hss_sort(hss_plan_t plan, uint64_t seed, const void* d_keys_in,
+                    const uint64_t* d_vals_in, void* d_keys_out, uint64_t* d_vals_out,
+                    uint64_t* d_offsets, void* stream);
+
+/*
+ * hss_local_sort -- only the first phase (section 6, local sort): every
+ * segment sorted stably by key, payload moved with its key.  The output
+ * position of an element is its tag g.
+ */
+hss_status hss_local_sort(hss_plan_t plan, const void* d_keys_in, const uint64_t* d_vals_in,
+                          void* d_keys_out, uint64_t* d_vals_out, void* stream);
+
+/*
+ * hss_get_constants -- the plan's round constants (section 4.2).
+ *   tol         floor(N eps / (2p))
+ *   k           rounds of the rate schedule s_j = a^(j/k)
+ *   a           2 ln p / eps (= s_k)
+ *   thresh[j-1] for j = 1..max_j: a key of the round-j domain is a probe when
+ *               its Philox word is below thresh; all[j-1] = 1 when every key
+ *               is taken (p s_j / N >= 1).  Either array may be NULL.
+ */
+hss_status hss_get_constants(hss_plan_t plan, uint64_t* tol, uint32_t* k, double* a,
+                             uint32_t max_j, uint32_t* thresh, uint32_t* all);
+
+/* Trace of the last hss_partition / hss_sort call on the plan (host data). */
+uint32_t hss_trace_rounds(hss_plan_t plan);
+
+/* Round j (0-based): domain size |gamma_{j}| sampled from, probe count m,
+ * acceptance threshold and the all-keys flag. */
+hss_status hss_trace_round_info(hss_plan_t plan, uint32_t j, uint64_t* domain, uint64_t* m,
+                                uint32_t* thresh, uint32_t* all);
+
+/* Round j probes in sorted order: keys, tags g and global ranks R (m each;
+ * any pointer may be NULL).  Needs trace_level >= 1. */
+hss_status hss_trace_round_probes(hss_plan_t plan, uint32_t j, uint64_t* keys, uint64_t* tags,
+                                  uint64_t* ranks);
+
+/* Splitter state after round j, p-1 entries each: rank of the bounding probe
+ * below / above N i/p (UINT64_MAX for none or settled), settled flag, chi
+ * (0 while unsettled).  Needs trace_level >= 1. */
+hss_status hss_trace_round_state(hss_plan_t plan, uint32_t j, uint64_t* lo_rank,
+                                 uint64_t* hi_rank, uint8_t* settled, uint64_t* chi);
+
+/* Final splitters: chi (p+1), key and tag of S(i) (p+1; entries 0 and p are
+ * unused), and the piece matrix ((p+1) x p, row b = per-segment count of
+ * keys preceding S(b)).  Any pointer may be NULL. */
+hss_status hss_trace_splitters(hss_plan_t plan, uint64_t* chi, uint64_t* s_key, uint64_t* s_tag,
+                               uint64_t* pieces);
+
+const char* hss_status_string(hss_status status);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* hss_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSS_H */

@@ -1,0 +1,281 @@
+"""Histogram Sort with Sampling on one MI355X -- Python binding of libhss.so.
+
+Argument marshalling only: every step runs in the HIP kernels of libhss.so,
+declared in include/hss.h.  PyTorch supplies device memory and the stream.
+Importing this package fails loudly when the library has not been built.
+
+    import paper_1803_01237_amd as hss
+    keys_out, vals_out, offsets = hss.partition(keys, p=1024, eps=0.02, seed=2)
+    keys_sorted, _, _ = hss.sort(keys, p=1024, eps=0.02, seed=2)
+
+Keys are torch tensors of 4- or 8-byte integers (int32/uint32/int64/uint64),
+compared as unsigned integers.  A payload is an 8-byte integer tensor.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhss.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it first (__graft_entry__.build() or "
+                      f"python -m paper_1803_01237_amd.build)")
+
+_lib = C.CDLL(LIB_PATH)
+
+HSS_U32, HSS_U64 = 0, 1
+STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "out of memory",
+          -4: "device error", -5: "not converged"}
+NONE = (1 << 64) - 1
+
+EXPORTS = [
+    "hss_plan", "hss_plan_destroy", "hss_workspace_bytes", "hss_partition", "hss_sort",
+    "hss_local_sort", "hss_get_constants", "hss_trace_rounds", "hss_trace_round_info",
+    "hss_trace_round_probes", "hss_trace_round_state", "hss_trace_splitters",
+    "hss_status_string", "hss_last_error",
+]
+
+
+class HssError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.hss_last_error().decode()
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({msg})")
+        self.status = status
+
+
+class _Tuning(C.Structure):
+    _fields_ = [("max_rounds", C.c_uint32), ("k_override", C.c_uint32),
+                ("force_full_sample", C.c_uint32), ("trace_level", C.c_uint32),
+                ("reserved", C.c_uint32 * 4)]
+
+
+_vp, _u64, _u32, _dbl = C.c_void_p, C.c_uint64, C.c_uint32, C.c_double
+_lib.hss_plan.argtypes = [C.POINTER(_vp), _u64, _u32, _dbl, C.c_int, C.c_int, C.POINTER(_Tuning)]
+_lib.hss_plan.restype = C.c_int
+_lib.hss_plan_destroy.argtypes = [_vp]
+_lib.hss_plan_destroy.restype = None
+_lib.hss_workspace_bytes.argtypes = [_vp]
+_lib.hss_workspace_bytes.restype = C.c_size_t
+for _f in (_lib.hss_partition, _lib.hss_sort):
+    _f.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp, _vp, _vp]
+    _f.restype = C.c_int
+_lib.hss_local_sort.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+_lib.hss_local_sort.restype = C.c_int
+_lib.hss_get_constants.argtypes = [_vp, _vp, _vp, _vp, _u32, _vp, _vp]
+_lib.hss_get_constants.restype = C.c_int
+_lib.hss_trace_rounds.argtypes = [_vp]
+_lib.hss_trace_rounds.restype = _u32
+_lib.hss_trace_round_info.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp]
+_lib.hss_trace_round_info.restype = C.c_int
+_lib.hss_trace_round_probes.argtypes = [_vp, _u32, _vp, _vp, _vp]
+_lib.hss_trace_round_probes.restype = C.c_int
+_lib.hss_trace_round_state.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp]
+_lib.hss_trace_round_state.restype = C.c_int
+_lib.hss_trace_splitters.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.hss_trace_splitters.restype = C.c_int
+_lib.hss_status_string.argtypes = [C.c_int]
+_lib.hss_status_string.restype = C.c_char_p
+_lib.hss_last_error.argtypes = []
+_lib.hss_last_error.restype = C.c_char_p
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise HssError(st, where)
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle():
+    torch = _torch()
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _key_type(t) -> int:
+    if t.element_size() == 8:
+        return HSS_U64
+    if t.element_size() == 4:
+        return HSS_U32
+    raise TypeError("keys must be 4- or 8-byte integers")
+
+
+@dataclass
+class RoundTrace:
+    domain: int
+    m: int
+    thresh: int
+    all: int
+    probe_key: np.ndarray | None = None
+    probe_tag: np.ndarray | None = None
+    probe_rank: np.ndarray | None = None
+    lo_rank: np.ndarray | None = None
+    hi_rank: np.ndarray | None = None
+    settled: np.ndarray | None = None
+    chi: np.ndarray | None = None
+
+
+class Plan:
+    """A plan for (N, p, eps, key type, payload).  Owns its device workspace."""
+
+    def __init__(self, n: int, p: int, eps: float, key_bytes: int = 8, payload: bool = False,
+                 max_rounds: int = 0, k_override: int = 0, force_full_sample: bool = False,
+                 trace_level: int = 0):
+        tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, trace_level)
+        h = _vp()
+        kt = HSS_U64 if key_bytes == 8 else HSS_U32
+        _check(_lib.hss_plan(C.byref(h), n, p, eps, kt, 1 if payload else 0, C.byref(tun)),
+               "hss_plan")
+        self._h = h
+        self.n, self.p, self.eps = n, p, eps
+        self.key_bytes, self.payload = key_bytes, payload
+        self.trace_level = trace_level
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hss_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(_lib.hss_workspace_bytes(self._h))
+
+    def _outputs(self, keys, vals, keys_out, vals_out, offsets):
+        torch = _torch()
+        if keys_out is None:
+            keys_out = torch.empty_like(keys)
+        if vals is not None and vals_out is None:
+            vals_out = torch.empty_like(vals)
+        if offsets is None:
+            offsets = torch.empty(self.p + 1, dtype=torch.int64, device=keys.device)
+        return keys_out, vals_out, offsets
+
+    def _validate(self, keys, vals):
+        if not keys.is_cuda or not keys.is_contiguous():
+            raise ValueError("keys must be a contiguous device tensor")
+        if keys.numel() != self.n or keys.element_size() != self.key_bytes:
+            raise ValueError("keys do not match the plan")
+        if (vals is not None) != self.payload:
+            raise ValueError("payload presence does not match the plan")
+        if vals is not None and (vals.numel() != self.n or vals.element_size() != 8
+                                 or not vals.is_contiguous() or not vals.is_cuda):
+            raise ValueError("payload must be a contiguous device tensor of N 8-byte words")
+
+    def _run(self, fn, name, keys, seed, vals, keys_out, vals_out, offsets):
+        self._validate(keys, vals)
+        keys_out, vals_out, offsets = self._outputs(keys, vals, keys_out, vals_out, offsets)
+        st = fn(self._h, seed & NONE, keys.data_ptr(),
+                None if vals is None else vals.data_ptr(), keys_out.data_ptr(),
+                None if vals_out is None else vals_out.data_ptr(), offsets.data_ptr(),
+                _stream_handle())
+        _check(st, name)
+        return keys_out, vals_out, offsets
+
+    def partition(self, keys, seed: int, vals=None, keys_out=None, vals_out=None, offsets=None):
+        return self._run(_lib.hss_partition, "hss_partition", keys, seed, vals, keys_out,
+                         vals_out, offsets)
+
+    def sort(self, keys, seed: int, vals=None, keys_out=None, vals_out=None, offsets=None):
+        return self._run(_lib.hss_sort, "hss_sort", keys, seed, vals, keys_out, vals_out, offsets)
+
+    def local_sort(self, keys, vals=None, keys_out=None, vals_out=None):
+        self._validate(keys, vals)
+        torch = _torch()
+        if keys_out is None:
+            keys_out = torch.empty_like(keys)
+        if vals is not None and vals_out is None:
+            vals_out = torch.empty_like(vals)
+        st = _lib.hss_local_sort(self._h, keys.data_ptr(),
+                                 None if vals is None else vals.data_ptr(), keys_out.data_ptr(),
+                                 None if vals_out is None else vals_out.data_ptr(),
+                                 _stream_handle())
+        _check(st, "hss_local_sort")
+        return keys_out, vals_out
+
+    def constants(self, max_j: int = 64):
+        tol, k, a = C.c_uint64(), C.c_uint32(), C.c_double()
+        th = np.zeros(max_j, dtype=np.uint32)
+        al = np.zeros(max_j, dtype=np.uint32)
+        _check(_lib.hss_get_constants(self._h, C.byref(tol), C.byref(k), C.byref(a), max_j,
+                                      _np_ptr(th), _np_ptr(al)), "hss_get_constants")
+        return int(tol.value), int(k.value), float(a.value), th, al
+
+    def trace(self) -> list:
+        out = []
+        for j in range(_lib.hss_trace_rounds(self._h)):
+            d, m, th, al = C.c_uint64(), C.c_uint64(), C.c_uint32(), C.c_uint32()
+            _check(_lib.hss_trace_round_info(self._h, j, C.byref(d), C.byref(m), C.byref(th),
+                                             C.byref(al)), "hss_trace_round_info")
+            r = RoundTrace(int(d.value), int(m.value), int(th.value), int(al.value))
+            if self.trace_level >= 1:
+                r.probe_key = np.zeros(r.m, dtype=np.uint64)
+                r.probe_tag = np.zeros(r.m, dtype=np.uint64)
+                r.probe_rank = np.zeros(r.m, dtype=np.uint64)
+                _check(_lib.hss_trace_round_probes(self._h, j, _np_ptr(r.probe_key),
+                                                   _np_ptr(r.probe_tag), _np_ptr(r.probe_rank)),
+                       "hss_trace_round_probes")
+                q = self.p - 1
+                r.lo_rank = np.zeros(q, dtype=np.uint64)
+                r.hi_rank = np.zeros(q, dtype=np.uint64)
+                r.settled = np.zeros(q, dtype=np.uint8)
+                r.chi = np.zeros(q, dtype=np.uint64)
+                _check(_lib.hss_trace_round_state(self._h, j, _np_ptr(r.lo_rank),
+                                                  _np_ptr(r.hi_rank), _np_ptr(r.settled),
+                                                  _np_ptr(r.chi)), "hss_trace_round_state")
+            out.append(r)
+        return out
+
+    def splitters(self):
+        p = self.p
+        chi = np.zeros(p + 1, dtype=np.uint64)
+        sk = np.zeros(p + 1, dtype=np.uint64)
+        stg = np.zeros(p + 1, dtype=np.uint64)
+        pieces = np.zeros((p + 1) * p, dtype=np.uint64)
+        _check(_lib.hss_trace_splitters(self._h, _np_ptr(chi), _np_ptr(sk), _np_ptr(stg),
+                                        _np_ptr(pieces)), "hss_trace_splitters")
+        return chi, sk, stg, pieces.reshape(p + 1, p)
+
+
+def _plan_for(keys, p, eps, vals, tuning):
+    return Plan(keys.numel(), p, eps, key_bytes=keys.element_size(), payload=vals is not None,
+                **tuning)
+
+
+def partition(keys, p: int, eps: float, seed: int, vals=None, **tuning):
+    """HSS partition of `keys` into p buckets; returns (keys_out, vals_out, offsets)."""
+    with _plan_for(keys, p, eps, vals, tuning) as plan:
+        return plan.partition(keys, seed, vals)
+
+
+def sort(keys, p: int, eps: float, seed: int, vals=None, **tuning):
+    """Stable sort of `keys` through HSS; returns (keys_out, vals_out, offsets)."""
+    with _plan_for(keys, p, eps, vals, tuning) as plan:
+        return plan.sort(keys, seed, vals)
+
+
+def exported_symbols():
+    """Names of the C-ABI entry points present in the loaded library."""
+    return [name for name in EXPORTS if hasattr(_lib, name)]

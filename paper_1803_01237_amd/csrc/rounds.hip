@@ -1,0 +1,536 @@
+// Splitter rounds of HSS (section 4.2.2, steps 1-5), all on the device.
+//
+// Round j, given the splitter state after round j-1:
+//   intervals -- the distinct open intervals (L_i, U_i) of unsettled splitters
+//                (identical intervals are taken once: they are either disjoint
+//                or identical, section 4.2.2)
+//   slices    -- per (interval, segment) the slice of the locally sorted
+//                segment strictly inside the interval, as a run of 4-tag
+//                Philox blocks in one flattened block space
+//   sample    -- every tag of the domain draws its Philox word and becomes a
+//                probe when the word is below the round threshold
+//                (section 4.2.1: independent Bernoulli with rate p s_j / N)
+//   probe sort-- probes ordered by (key, tag), the strict order of section 6.1
+//   rank      -- per probe, the number of keys of every segment that precede
+//                it (the local histograms), summed over segments in the same
+//                workgroup (the reduction of section 5.2)
+//   settle    -- per unsettled splitter, a probe in its target range settles
+//                it (closest to N i/p, lower rank on a tie); otherwise L and U
+//                move to the closest probe ranks below and above N i/p
+//   locate    -- per-segment counts of every new bound / splitter probe, which
+//                become the next round's slice ends and the piece boundaries
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace hss {
+
+namespace {
+
+constexpr int kT = 256;           // threads of most round kernels
+constexpr int kRun = 8;           // consecutive Philox blocks per lane in the sampler
+constexpr int kSampleGrid = 4096; // workgroups of the grid-stride sampler
+constexpr uint64_t kCountSortMax = 32768;   // probe sort by pairwise counting up to here
+constexpr int kCountTile = 1024;
+
+__global__ void round_init_kernel(uint32_t p, uint32_t* settled, uint64_t* chi, uint64_t* lrank,
+                                  uint64_t* urank, RoundCounters* ctr) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= p; i += gridDim.x * blockDim.x) {
+        settled[i] = 0;
+        chi[i] = 0;
+        lrank[i] = kNone;
+        urank[i] = kNone;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctr->m = 0;
+        ctr->domain = 0;
+        ctr->blocks = 0;
+        ctr->n_ivl = 0;
+        ctr->n_unsettled = 0;
+        ctr->n_req = 0;
+        ctr->err = 0;
+    }
+}
+
+// One workgroup: leaders of runs of identical unsettled intervals, in
+// splitter order, compacted into ivl_row.
+__global__ __launch_bounds__(1024) void leaders_kernel(RoundArgs a) {
+    __shared__ uint32_t scratch[1024 / kWave];
+    uint32_t base = 0, unsettled = 0;
+    for (uint32_t c = 1; c < a.p; c += 1024) {
+        const uint32_t i = c + threadIdx.x;
+        const bool u = i < a.p && a.settled[i] == 0;
+        bool lead = u;
+        if (u && i > 1 && a.settled[i - 1] == 0 && a.lrank[i - 1] == a.lrank[i] &&
+            a.urank[i - 1] == a.urank[i])
+            lead = false;
+        uint32_t tot;
+        const uint32_t pre = block_exclusive_scan<uint32_t, 1024>(lead ? 1u : 0u, scratch, &tot);
+        if (lead) a.ivl_row[base + pre] = i;
+        base += tot;
+        uint32_t ut;
+        block_exclusive_scan<uint32_t, 1024>(u ? 1u : 0u, scratch, &ut);
+        unsettled += ut;
+    }
+    if (threadIdx.x == 0) {
+        a.ctr->n_ivl = base;
+        a.ctr->n_unsettled = unsettled;
+        a.ctr->m = 0;
+        a.ctr->n_req = 0;
+    }
+}
+
+__device__ __forceinline__ void slice_bounds(const RoundArgs& a, uint32_t row, uint32_t s,
+                                             bool lnone, bool unone, uint64_t* ga, uint64_t* gb) {
+    const uint64_t sb = a.seg_off[s];
+    const uint64_t slen = a.seg_off[s + 1] - sb;
+    const uint64_t lo = lnone ? 0 : a.lpos[(uint64_t)row * a.p + s];
+    const uint64_t hi = unone ? slen : a.upos[(uint64_t)row * a.p + s];
+    *ga = sb + lo;
+    *gb = sb + (hi > lo ? hi : lo);
+}
+
+__device__ __forceinline__ uint64_t blocks_of(uint64_t ga, uint64_t gb) {
+    return gb > ga ? ((gb - 1) >> 2) - (ga >> 2) + 1 : 0;
+}
+
+// Workgroup per interval k: block counts of its p slices, scanned.
+__global__ __launch_bounds__(kT) void slices_kernel(RoundArgs a) {
+    __shared__ uint64_t scratch[kT / kWave];
+    const uint32_t k = blockIdx.x;
+    if (k >= a.ctr->n_ivl) return;
+    const uint32_t row = a.ivl_row[k];
+    const bool lnone = a.lrank[row] == kNone;
+    const bool unone = a.urank[row] == kNone;
+    uint64_t run = 0, dom = 0;
+    for (uint32_t s0 = 0; s0 < a.p; s0 += kT) {
+        const uint32_t s = s0 + threadIdx.x;
+        uint64_t nb = 0, len = 0;
+        if (s < a.p) {
+            uint64_t ga, gb;
+            slice_bounds(a, row, s, lnone, unone, &ga, &gb);
+            nb = blocks_of(ga, gb);
+            len = gb - ga;
+        }
+        uint64_t tot;
+        const uint64_t pre = block_exclusive_scan<uint64_t, kT>(nb, scratch, &tot);
+        if (s < a.p) a.ivl_blk[(uint64_t)k * a.p + s] = (uint32_t)(run + pre);
+        run += tot;
+        dom += block_sum<uint64_t, kT>(len, scratch);
+    }
+    if (threadIdx.x == 0) {
+        a.ivl_tot[k] = run;
+        a.ivl_dom[k] = dom;
+    }
+}
+
+// One workgroup: exclusive scan of the interval block totals.
+__global__ __launch_bounds__(1024) void ivl_scan_kernel(RoundArgs a) {
+    __shared__ uint64_t scratch[1024 / kWave];
+    const uint32_t n = a.ctr->n_ivl;
+    uint64_t run = 0, dom = 0;
+    for (uint32_t c = 0; c < n; c += 1024) {
+        const uint32_t k = c + threadIdx.x;
+        const uint64_t v = k < n ? a.ivl_tot[k] : 0;
+        const uint64_t d = k < n ? a.ivl_dom[k] : 0;
+        uint64_t tot;
+        const uint64_t pre = block_exclusive_scan<uint64_t, 1024>(v, scratch, &tot);
+        if (k < n) a.ivl_tot[k] = run + pre;
+        run += tot;
+        dom += block_sum<uint64_t, 1024>(d, scratch);
+    }
+    if (threadIdx.x == 0) {
+        a.ivl_tot[n] = run;
+        a.ctr->blocks = run;
+        a.ctr->domain = dom;
+    }
+}
+
+// Last index i in [0, n) with v[i] <= x (v non-decreasing, v[0] <= x).
+template <typename T>
+__device__ __forceinline__ uint32_t last_le(const T* v, uint32_t n, uint64_t x) {
+    uint32_t lo = 0, hi = n;   // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((uint64_t)v[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint64_t seed, uint32_t round,
+                                                    uint32_t thresh, int take_all) {
+    const uint64_t total = a.ctr->blocks;
+    const uint32_t n_ivl = a.ctr->n_ivl;
+    const K* B = (const K*)a.B;
+    const uint32_t lane = lane_id();
+    const uint64_t wave_global = ((uint64_t)blockIdx.x * kT + threadIdx.x) / kWave;
+    const uint64_t n_waves = (uint64_t)gridDim.x * kT / kWave;
+    const uint64_t p = a.p;
+
+    for (uint64_t w0 = wave_global * kWave * kRun; w0 < total; w0 += n_waves * kWave * kRun) {
+        uint64_t bi = w0 + (uint64_t)lane * kRun;
+        const uint64_t bend = min(bi + kRun, total);
+        // current slice of this lane
+        uint32_t k = 0, s = 0, row = 0;
+        uint64_t ga = 0, gb = 0, sstart = 0, send = 0;
+        bool lnone = false, unone = false;
+        if (bi < bend) {
+            k = last_le(a.ivl_tot, n_ivl, bi);
+            const uint64_t kbase = a.ivl_tot[k];
+            s = last_le(a.ivl_blk + (uint64_t)k * p, a.p, bi - kbase);
+            row = a.ivl_row[k];
+            lnone = a.lrank[row] == kNone;
+            unone = a.urank[row] == kNone;
+            slice_bounds(a, row, s, lnone, unone, &ga, &gb);
+            sstart = kbase + a.ivl_blk[(uint64_t)k * p + s];
+            send = sstart + blocks_of(ga, gb);
+        }
+        for (int r = 0; r < kRun; ++r) {
+            uint32_t hits = 0;     // bit w: tag 4*blk + w is a probe
+            uint64_t blk = 0;
+            const bool act = bi < bend;
+            if (act) {
+                while (bi >= send) {   // move to the slice holding block bi
+                    ++s;
+                    if (s == a.p) {
+                        s = 0;
+                        ++k;
+                        row = a.ivl_row[k];
+                        lnone = a.lrank[row] == kNone;
+                        unone = a.urank[row] == kNone;
+                    }
+                    slice_bounds(a, row, s, lnone, unone, &ga, &gb);
+                    sstart = a.ivl_tot[k] + a.ivl_blk[(uint64_t)k * p + s];
+                    send = sstart + blocks_of(ga, gb);
+                }
+                blk = (ga >> 2) + (bi - sstart);
+                const Philox4 w = sample_block(seed, blk, round);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint64_t g = blk * 4 + q;
+                    if (g >= ga && g < gb && (take_all || w.v[q] < thresh)) hits |= 1u << q;
+                }
+            }
+            if (__ballot(hits != 0)) {
+                const uint32_t c = __popc(hits);
+                const uint32_t inc = wave_inclusive_scan<uint32_t>(c);
+                unsigned long long base = 0;
+                if (lane == kWave - 1) base = atomicAdd(&a.ctr->m, (unsigned long long)inc);
+                base = shfl_u64(base, kWave - 1);
+                uint64_t o = base + inc - c;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (hits & (1u << q)) {
+                        if (o < a.cap) {
+                            const uint64_t g = blk * 4 + q;
+                            a.pr_key[o] = (uint64_t)B[g];
+                            a.pr_tag[o] = g;
+                            a.pr_ivl[o] = k;
+                        }
+                        ++o;
+                    }
+                }
+            }
+            ++bi;
+        }
+    }
+}
+
+// Sorted position of every probe: the number of probes before it in the
+// order (key, tag), counted against one tile of kCountTile probes per
+// workgroup row.
+__global__ __launch_bounds__(kT) void probe_count_kernel(const uint64_t* __restrict__ key,
+                                                         const uint64_t* __restrict__ tag,
+                                                         uint64_t m, uint32_t* __restrict__ pos) {
+    __shared__ uint64_t sk[kCountTile];
+    __shared__ uint64_t st[kCountTile];
+    const uint64_t j0 = (uint64_t)blockIdx.y * kCountTile;
+    const uint32_t nj = (uint32_t)min((uint64_t)kCountTile, m - j0);
+    for (uint32_t j = threadIdx.x; j < nj; j += kT) {
+        sk[j] = key[j0 + j];
+        st[j] = tag[j0 + j];
+    }
+    __syncthreads();
+    const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= m) return;
+    const uint64_t k = key[i], t = tag[i];
+    uint32_t c = 0;
+    for (uint32_t j = 0; j < nj; ++j) {
+        const uint64_t kj = sk[j];
+        c += (kj < k || (kj == k && st[j] < t)) ? 1u : 0u;
+    }
+    if (c) atomicAdd(&pos[i], c);
+}
+
+__global__ void probe_permute_kernel(RoundArgs a, uint64_t m, const uint64_t* order) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t src, dst;
+        if (order) { src = order[i]; dst = i; }      // order[i] = emitted index of sorted i
+        else { src = i; dst = a.pr_pos[i]; }          // pr_pos[i] = sorted index of emitted i
+        a.ps_key[dst] = a.pr_key[src];
+        a.ps_tag[dst] = a.pr_tag[src];
+        a.ps_ivl[dst] = a.pr_ivl[src];
+    }
+}
+
+__global__ void iota_kernel(uint64_t* v, uint64_t m) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        v[i] = i;
+}
+
+__global__ void gather_kernel(const uint64_t* __restrict__ src, const uint64_t* __restrict__ idx,
+                              uint64_t* __restrict__ dst, uint64_t m) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[idx[i]];
+}
+
+__global__ void one_segment_kernel(uint64_t* seg, uint64_t m) {
+    seg[0] = 0;
+    seg[1] = m;
+}
+
+__device__ __forceinline__ uint32_t segment_of(const uint64_t* seg_off, uint32_t p, uint64_t g) {
+    return last_le(seg_off, p + 1, g);
+}
+
+// Workgroup per sorted probe: c_s for every segment s inside the slice of the
+// probe's own interval, summed -> R(e).
+template <typename K>
+__global__ __launch_bounds__(kT) void rank_kernel(RoundArgs a) {
+    __shared__ uint64_t scratch[kT / kWave];
+    __shared__ uint32_t sh_t;
+    const uint64_t e = blockIdx.x;
+    const K key = (K)a.ps_key[e];
+    const uint64_t g = a.ps_tag[e];
+    const uint32_t row = a.ivl_row[a.ps_ivl[e]];
+    if (threadIdx.x == 0) sh_t = segment_of(a.seg_off, a.p, g);
+    __syncthreads();
+    const uint32_t t = sh_t;
+    const bool lnone = a.lrank[row] == kNone;
+    const bool unone = a.urank[row] == kNone;
+    const K* B = (const K*)a.B;
+    uint64_t sum = 0;
+    for (uint32_t s = threadIdx.x; s < a.p; s += kT) {
+        const uint64_t sb = a.seg_off[s];
+        const uint64_t slen = a.seg_off[s + 1] - sb;
+        const uint64_t lo = lnone ? 0 : a.lpos[(uint64_t)row * a.p + s];
+        const uint64_t hi = unone ? slen : a.upos[(uint64_t)row * a.p + s];
+        uint64_t c;
+        if (s == t) {
+            c = g - sb;
+            if (c < lo || c >= hi) atomicOr(&a.ctr->err, kErrProbeOutside);
+        } else {
+            // equal keys of earlier segments precede the probe, of later ones follow
+            c = count_before<K>(B + sb, lo, hi, key, s < t);
+        }
+        sum += c;
+    }
+    sum = block_sum<uint64_t, kT>(sum, scratch);
+    if (threadIdx.x == 0) a.pr_rank[e] = sum;
+}
+
+__device__ __forceinline__ void emit_request(const RoundArgs& a, uint32_t e, uint32_t row,
+                                             uint32_t kind) {
+    const uint32_t r = atomicAdd(&a.ctr->n_req, 1u);
+    a.req_probe[r] = e;
+    a.req_row[r] = row;
+    a.req_kind[r] = kind;
+}
+
+// Thread per splitter i = 1..p-1.
+__global__ __launch_bounds__(kT) void settle_kernel(RoundArgs a, uint64_t m) {
+    const uint64_t gid = (uint64_t)blockIdx.x * kT + threadIdx.x;
+    for (uint64_t e = gid; e + 1 < m; e += (uint64_t)gridDim.x * kT)
+        if (a.pr_rank[e] >= a.pr_rank[e + 1]) atomicOr(&a.ctr->err, kErrRankOrder);
+    const uint64_t i = gid + 1;
+    if (i >= a.p || a.settled[i]) return;
+    const uint64_t target = a.ideal[i];
+    // first probe with R >= N i / p
+    uint64_t lo = 0, hi = m;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (a.pr_rank[mid] < target) lo = mid + 1; else hi = mid;
+    }
+    const bool has_above = lo < m;
+    const bool has_below = lo > 0;
+    const uint64_t r_above = has_above ? a.pr_rank[lo] : 0;
+    const uint64_t r_below = has_below ? a.pr_rank[lo - 1] : 0;
+    const uint64_t d_above = r_above - target;
+    const uint64_t d_below = target - r_below;
+    int64_t pick = -1;
+    if (has_below && d_below <= a.tol) pick = (int64_t)lo - 1;
+    if (has_above && d_above <= a.tol && (pick < 0 || d_above < d_below)) pick = (int64_t)lo;
+    if (pick >= 0) {
+        a.settled[i] = 1;
+        a.chi[i] = a.pr_rank[pick];
+        a.s_key[i] = a.ps_key[pick];
+        a.s_tag[i] = a.ps_tag[pick];
+        emit_request(a, (uint32_t)pick, (uint32_t)i, 2u);
+        return;
+    }
+    if (has_below && (a.lrank[i] == kNone || r_below > a.lrank[i])) {
+        a.lrank[i] = r_below;
+        emit_request(a, (uint32_t)(lo - 1), (uint32_t)i, 0u);
+    }
+    if (has_above && r_above < a.urank[i]) {
+        a.urank[i] = r_above;
+        emit_request(a, (uint32_t)lo, (uint32_t)i, 1u);
+    }
+}
+
+// Workgroup per request: per-segment counts of a new bound / splitter probe.
+template <typename K>
+__global__ __launch_bounds__(kT) void locate_kernel(RoundArgs a) {
+    __shared__ uint32_t sh_t;
+    const uint32_t r = blockIdx.x;
+    if (r >= a.ctr->n_req) return;
+    const uint32_t e = a.req_probe[r];
+    const uint64_t row = a.req_row[r];
+    const uint32_t kind = a.req_kind[r];
+    const K key = (K)a.ps_key[e];
+    const uint64_t g = a.ps_tag[e];
+    if (threadIdx.x == 0) sh_t = segment_of(a.seg_off, a.p, g);
+    __syncthreads();
+    const uint32_t t = sh_t;
+    const K* B = (const K*)a.B;
+    uint32_t* dst = kind == 0 ? a.lpos : (kind == 1 ? a.upos : a.prow);
+    for (uint32_t s = threadIdx.x; s < a.p; s += kT) {
+        const uint64_t sb = a.seg_off[s];
+        const uint64_t slen = a.seg_off[s + 1] - sb;
+        uint64_t c;
+        if (s == t) c = g - sb + (kind == 0 ? 1 : 0);   // the L probe itself is excluded
+        else c = count_before<K>(B + sb, 0, slen, key, s < t);
+        dst[row * a.p + s] = (uint32_t)c;
+    }
+}
+
+__global__ void finalize_kernel(RoundArgs a, uint64_t* offsets) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= a.p; i += gridDim.x * blockDim.x)
+        offsets[i] = i == 0 ? 0 : (i == a.p ? a.n : a.chi[i]);
+}
+
+unsigned grid_for(uint64_t n, unsigned threads, unsigned cap = 65535u) {
+    const uint64_t g = (n + threads - 1) / threads;
+    return (unsigned)(g == 0 ? 1 : (g > cap ? cap : g));
+}
+
+}  // namespace
+
+hipError_t launch_round_init(const RoundArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(round_init_kernel, dim3(grid_for(a.p + 1, kT)), dim3(kT), 0, s, a.p,
+                       a.settled, a.chi, a.lrank, a.urank, a.ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_intervals(const RoundArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(leaders_kernel, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(slices_kernel, dim3(a.p > 1 ? a.p - 1 : 1), dim3(kT), 0, s, a);
+    hipLaunchKernelGGL(ivl_scan_kernel, dim3(1), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(const RoundArgs& a, uint64_t seed, uint32_t round, uint32_t thresh,
+                         int take_all, hipStream_t s) {
+    if (a.key_bytes == 4)
+        hipLaunchKernelGGL(sample_kernel<uint32_t>, dim3(kSampleGrid), dim3(kT), 0, s, a, seed,
+                           round, thresh, take_all);
+    else
+        hipLaunchKernelGGL(sample_kernel<uint64_t>, dim3(kSampleGrid), dim3(kT), 0, s, a, seed,
+                           round, thresh, take_all);
+    return hipGetLastError();
+}
+
+size_t probe_sort_scratch_bytes(uint64_t m) {
+    if (m <= kCountSortMax) return 0;
+    // seg(2) + idx + idx_tmp + key_a + key_b, 8 bytes each
+    return 16 + 4 * m * 8 + 256;
+}
+
+hipError_t launch_probe_sort(const RoundArgs& a, uint64_t m, void* scratch, size_t scratch_bytes,
+                             uint32_t* counts, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    if (m <= kCountSortMax) {
+        hipError_t err = hipMemsetAsync(a.pr_pos, 0, m * sizeof(uint32_t), s);
+        if (err != hipSuccess) return err;
+        dim3 grid((unsigned)((m + kT - 1) / kT), (unsigned)((m + kCountTile - 1) / kCountTile));
+        hipLaunchKernelGGL(probe_count_kernel, grid, dim3(kT), 0, s, a.pr_key, a.pr_tag, m,
+                           a.pr_pos);
+        hipLaunchKernelGGL(probe_permute_kernel, dim3(grid_for(m, kT)), dim3(kT), 0, s, a, m,
+                           (const uint64_t*)nullptr);
+        return hipGetLastError();
+    }
+    if (scratch_bytes < probe_sort_scratch_bytes(m)) return hipErrorInvalidValue;
+    // Two stable LSD sorts: by tag, then by key -> order (key, tag).
+    uint64_t* seg = (uint64_t*)scratch;
+    uint64_t* idx = seg + 2;
+    uint64_t* idx_tmp = idx + m;
+    uint64_t* ka = idx_tmp + m;
+    uint64_t* kb = ka + m;
+    hipLaunchKernelGGL(one_segment_kernel, dim3(1), dim3(1), 0, s, seg, m);
+    hipLaunchKernelGGL(iota_kernel, dim3(grid_for(m, kT)), dim3(kT), 0, s, ka, m);
+    SegSort ss;
+    ss.key_bytes = 8;
+    ss.seg_off = seg;
+    ss.num_segs = 1;
+    ss.max_seg_len = m;
+    ss.counts = counts;
+    // by tag: keys = tags, payload = emitted index
+    ss.keys_in = a.pr_tag;
+    ss.vals_in = ka;
+    ss.keys_out = kb;
+    ss.vals_out = idx;
+    ss.keys_tmp = a.ps_tag;          // free until the permute below
+    ss.vals_tmp = idx_tmp;
+    ss.begin_bit = 0;
+    ss.end_bit = 64;
+    hipError_t err = segmented_radix_sort(ss, s);
+    if (err != hipSuccess) return err;
+    // by key, stably: keys = key of each index in tag order
+    hipLaunchKernelGGL(gather_kernel, dim3(grid_for(m, kT)), dim3(kT), 0, s, a.pr_key, idx, ka, m);
+    ss.keys_in = ka;
+    ss.vals_in = idx;
+    ss.keys_out = kb;
+    ss.vals_out = idx_tmp;
+    ss.keys_tmp = a.ps_key;
+    ss.vals_tmp = a.ps_tag;
+    ss.end_bit = a.key_bytes * 8;
+    err = segmented_radix_sort(ss, s);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(probe_permute_kernel, dim3(grid_for(m, kT)), dim3(kT), 0, s, a, m,
+                       (const uint64_t*)idx_tmp);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank(const RoundArgs& a, uint64_t m, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    if (a.key_bytes == 4)
+        hipLaunchKernelGGL(rank_kernel<uint32_t>, dim3((unsigned)m), dim3(kT), 0, s, a);
+    else
+        hipLaunchKernelGGL(rank_kernel<uint64_t>, dim3((unsigned)m), dim3(kT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_settle(const RoundArgs& a, uint64_t m, hipStream_t s) {
+    hipLaunchKernelGGL(settle_kernel, dim3(grid_for(a.p, kT)), dim3(kT), 0, s, a, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_locate(const RoundArgs& a, hipStream_t s) {
+    const unsigned grid = 2u * (a.p > 1 ? a.p - 1 : 1);
+    if (a.key_bytes == 4)
+        hipLaunchKernelGGL(locate_kernel<uint32_t>, dim3(grid), dim3(kT), 0, s, a);
+    else
+        hipLaunchKernelGGL(locate_kernel<uint64_t>, dim3(grid), dim3(kT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const RoundArgs& a, uint64_t* d_offsets, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(grid_for(a.p + 1, kT)), dim3(kT), 0, s, a, d_offsets);
+    return hipGetLastError();
+}
+
+}  // namespace hss

@@ -1,0 +1,60 @@
+"""The C-ABI library loads on a host without a GPU and exports every entry
+point that include/hss.h declares.  No compute call is made here."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(hss_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("hss_plan", "hss_partition", "hss_sort", "hss_plan_destroy"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pytest.importorskip("paper_1803_01237_amd")
+    import ctypes
+    dll = ctypes.CDLL(lib.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(dll, n)]
+    assert not missing, missing
+    assert sorted(lib.EXPORTS) == declared_functions()
+
+
+def test_status_strings_without_gpu():
+    import paper_1803_01237_amd as lib
+    assert lib._lib.hss_status_string(0) == b"ok"
+    assert lib._lib.hss_status_string(-5) == b"not converged"
+    assert lib._lib.hss_last_error() == b""
+
+
+def test_plan_rejects_invalid_arguments_before_touching_the_device():
+    import paper_1803_01237_amd as lib
+    for n, p, eps in [(0, 1, 0.1), (10, 0, 0.1), (10, 11, 0.1), (10, 2, 0.0), (10, 2, 1.0),
+                      (10, 2, float("nan"))]:
+        with pytest.raises(lib.HssError) as ei:
+            lib.Plan(n, p, eps)
+        assert ei.value.status == -1
+
+
+def test_no_oracle_in_product_path():
+    """The product package never imports or loads the oracle."""
+    pkg = os.path.join(ROOT, "paper_1803_01237_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "liboracle" not in text, fn
+                assert "hss_oracle" not in text, fn

@@ -1,0 +1,191 @@
+"""GPU parity: libhss (through the C ABI) against the CPU oracle, bit-exact.
+
+Every case prints what it runs before touching the device.  Small and medium
+cases compare the whole round trace (probe sets, ranks, splitter state per
+round), the splitters, the piece matrix and the outputs.  Full-size cases
+(2^28 keys) check the outputs by properties that hold at any size and
+compare sampled splitters with their definition.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import refcheck as R
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1803_01237_amd as lib
+    return lib
+
+
+def _dev(a):
+    if a.dtype == np.uint64:
+        return torch.from_numpy(a.view(np.int64)).cuda()
+    if a.dtype == np.uint32:
+        return torch.from_numpy(a.view(np.int32)).cuda()
+    raise TypeError(a.dtype)
+
+
+def _host(t, dtype):
+    return t.cpu().numpy().view(dtype)
+
+
+def _keys(kind, n, seed, bits):
+    k = synth.make(kind, n, seed)
+    if bits == 32:
+        k = (k >> np.uint64(32)).astype(np.uint32) if kind in ("uniform64", "UNIF") else k.astype(np.uint32)
+    return k
+
+
+CASES = [
+    # kind, n, p, eps, seed, bits, payload
+    ("uniform64", 1 << 20, 16, 0.05, 1, 64, False),      # the small configuration
+    ("uniform64", 1 << 16, 16, 0.05, 7, 64, True),
+    ("uniform64", 100_003, 37, 0.02, 2, 64, True),       # ragged segments, several tiles
+    ("uniform32", 300_001, 64, 0.1, 3, 32, True),
+    ("uniform32", 65_536, 8, 0.05, 4, 32, False),
+    ("SKEW1", 200_000, 32, 0.05, 4, 64, False),
+    ("SKEW2", 200_000, 32, 0.05, 5, 64, True),           # 101 distinct keys
+    ("SKEW3", 120_000, 20, 0.05, 6, 64, False),
+    ("GAUSS", 120_000, 20, 0.05, 7, 64, False),
+    ("ALLZEROS", 100_000, 25, 0.05, 8, 64, True),
+    ("zipf_morton", 400_000, 128, 0.05, 9, 64, True),
+    ("uniform64", 5000, 1, 0.05, 10, 64, True),          # p = 1
+    ("uniform64", 300, 300, 0.5, 11, 64, True),          # p = N
+    ("uniform64", 40_000, 9, 1e-6, 12, 64, False),       # tol = 0
+    ("SKEW2", 33_333, 10, 0.003, 13, 64, True),          # tol = 0 with duplicates
+    ("uniform64", 1 << 22, 256, 0.02, 14, 64, False),    # medium, k = 7
+    ("uniform64", 1, 1, 0.5, 15, 64, True),              # a single key
+    ("uniform64", 4097, 4096, 0.9, 16, 64, False),       # many tiny segments
+]
+
+
+def _compare_trace(plan, ref, p):
+    tr = plan.trace()
+    assert len(tr) == len(ref.rounds), (len(tr), len(ref.rounds))
+    for j, (a, b) in enumerate(zip(tr, ref.rounds)):
+        assert (a.domain, a.m, a.thresh, a.all) == (b.domain, b.m, b.thresh, b.all), j
+        assert np.array_equal(a.probe_key, b.probe_key), j
+        assert np.array_equal(a.probe_tag, b.probe_tag), j
+        assert np.array_equal(a.probe_rank, b.probe_rank), j
+        assert np.array_equal(a.settled, b.settled), j
+        assert np.array_equal(a.chi, b.chi), j
+        assert np.array_equal(a.lo_rank, b.lo_rank), j
+        assert np.array_equal(a.hi_rank, b.hi_rank), j
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-{c[1]}-p{c[2]}-b{c[5]}" for c in CASES])
+def test_partition_and_sort_match_oracle(hss, case):
+    kind, n, p, eps, seed, bits, payload = case
+    _say(f"[parity] {kind} n={n} p={p} eps={eps} seed={seed} bits={bits} payload={payload}")
+    keys = _keys(kind, n, seed, bits)
+    vals = (np.arange(n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)) if payload else None
+    kd = _dev(keys)
+    vd = None if vals is None else _dev(vals)
+    kt = keys.dtype
+    with hss.Plan(n, p, eps, key_bytes=keys.itemsize, payload=payload, trace_level=1) as plan:
+        # constants
+        tol, k, a, th, al = plan.constants(40)
+        oc = oracle.constants(n, p, eps, max_j=40)
+        assert (tol, k, a) == (oc.tol, oc.k, oc.a)
+        assert np.array_equal(th, oc.thresh) and np.array_equal(al, oc.all)
+        # local sort
+        lk, lv = plan.local_sort(kd, vd)
+        ok_, ov_ = oracle.local_sort(keys, p, vals)
+        assert np.array_equal(_host(lk, kt), ok_)
+        if payload:
+            assert np.array_equal(_host(lv, np.uint64), ov_)
+        # partition
+        ko, vo, off = plan.partition(kd, seed, vd)
+        ref = oracle.hss(keys, p, eps, seed, vals=vals, mode="partition")
+        assert ref.status == 0
+        assert np.array_equal(_host(off, np.uint64), ref.offsets)
+        assert np.array_equal(_host(ko, kt), ref.keys)
+        if payload:
+            assert np.array_equal(_host(vo, np.uint64), ref.vals)
+        _compare_trace(plan, ref, p)
+        chi, sk, stg, pieces = plan.splitters()
+        assert np.array_equal(chi, ref.chi)
+        assert np.array_equal(sk[1:p], ref.s_key[1:p])
+        assert np.array_equal(stg[1:p], ref.s_tag[1:p])
+        assert np.array_equal(pieces, ref.pieces)
+        # sort
+        ks, vs, off2 = plan.sort(kd, seed, vd)
+        order = np.argsort(keys, kind="stable")
+        assert np.array_equal(_host(ks, kt), keys[order])
+        if payload:
+            assert np.array_equal(_host(vs, np.uint64), vals[order])
+        assert np.array_equal(_host(off2, np.uint64), ref.offsets)
+
+
+def test_force_full_sample_exact_splitters(hss):
+    n, p = 50_000, 13
+    _say(f"[parity] force_full_sample n={n} p={p}")
+    keys = synth.make("SKEW2", n, 3)
+    with hss.Plan(n, p, 0.05, trace_level=1, force_full_sample=True) as plan:
+        ko, _, off = plan.partition(_dev(keys), 1)
+        assert [int(x) for x in _host(off, np.uint64)] == list(R.ideal(n, p))
+        ref = oracle.hss(keys, p, 0.05, 1, force_full_sample=True)
+        assert np.array_equal(_host(ko, np.uint64), ref.keys)
+        _compare_trace(plan, ref, p)
+
+
+def test_round_cap_reports_not_converged(hss):
+    n, p = 1 << 16, 64
+    _say(f"[parity] max_rounds=1 n={n} p={p}")
+    keys = synth.make("uniform64", n, 3)
+    with hss.Plan(n, p, 0.01, max_rounds=1) as plan:
+        with pytest.raises(hss.HssError) as ei:
+            plan.partition(_dev(keys), 3)
+        assert ei.value.status == -5
+    assert oracle.hss(keys, p, 0.01, 3, max_rounds=1).status == -5
+
+
+def test_rejects_misaligned_and_overlapping_pointers(hss):
+    n, p = 4096, 4
+    _say("[parity] argument checks")
+    keys = _dev(synth.make("uniform64", n + 2, 3))
+    with hss.Plan(n, p, 0.1) as plan:
+        with pytest.raises(hss.HssError):      # outputs overlap the input
+            hss._check(hss._lib.hss_partition(plan._h, 1, keys.data_ptr(), None,
+                                              keys.data_ptr(), None,
+                                              torch.empty(p + 1, dtype=torch.int64,
+                                                          device="cuda").data_ptr(), None),
+                       "overlap")
+        out = torch.empty(n + 2, dtype=torch.int64, device="cuda")
+        with pytest.raises(hss.HssError):      # misaligned output
+            hss._check(hss._lib.hss_partition(plan._h, 1, keys.data_ptr(), None,
+                                              out.data_ptr() + 8, None,
+                                              torch.empty(p + 1, dtype=torch.int64,
+                                                          device="cuda").data_ptr(), None),
+                       "misaligned")
+
+
+def test_plan_reuse_and_seeds(hss):
+    """One plan, several seeds and inputs in a row: each call equals a fresh oracle run."""
+    n, p, eps = 200_000, 50, 0.03
+    with hss.Plan(n, p, eps, payload=True, trace_level=0) as plan:
+        for seed in (1, 2, 3):
+            _say(f"[parity] reuse seed={seed}")
+            keys = synth.make("uniform64", n, 40 + seed)
+            vals = np.arange(n, dtype=np.uint64)
+            ko, vo, off = plan.partition(_dev(keys), seed, _dev(vals))
+            ref = oracle.hss(keys, p, eps, seed, vals=vals, trace_level=0)
+            assert np.array_equal(_host(off, np.uint64), ref.offsets)
+            assert np.array_equal(_host(ko, np.uint64), ref.keys)
+            assert np.array_equal(_host(vo, np.uint64), ref.vals)
+            assert len(plan.trace()) == len(ref.rounds)
