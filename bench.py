@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Benchmark of the HSS hot path on one MI355X.
+
+One step = one hss_partition (local sort of every segment, the splitter
+rounds, the bucketed exchange) of N = 2^28 uniform uint64 keys in p = 1024
+segments with eps = 0.02, inputs resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+The line carries the throughput, the roofline of the dominant kernel (its
+algorithmic bytes per launch over its average launch time, HIP events on its
+stream over the timed region) and the CPU oracle timed on a bounded sample of
+the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Gkeys/s sort+partition, 2^28 u64 p=1024; % HBM peak; batched vs plain"
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, GB/s
+WORKLOADS = {
+    # name: (n, p, eps, data seed, hss seed, generator, payload)
+    "uniform_u64_2^28_p1024": (1 << 28, 1024, 0.02, 2, 2, "uniform64", False),
+    "zipf_morton_u64+payload_2^28_p4096": (1 << 28, 4096, 0.05, 3, 3, "zipf_morton", True),
+    "uniform_u64_2^20_p16": (1 << 20, 16, 0.05, 1, 1, "uniform64", False),
+}
+# traffic factors from the FETCH_SIZE / WRITE_SIZE counters of the dominant
+# kernel, each divided by what the same counter reads for a plain copy kernel
+# of known size; None until taken for the current kernel
+TRAFFIC = None
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(kind, n_sample, p, eps, dseed, hseed, payload):
+    import oracle
+    import synth
+    keys = synth.make(kind, n_sample, dseed)
+    vals = np.arange(n_sample, dtype=np.uint64) if payload else None
+    t0 = time.perf_counter()
+    r = oracle.hss(keys, p, eps, hseed, vals=vals, mode="partition", trace_level=0)
+    dt = time.perf_counter() - t0
+    assert r.status == 0
+    return {"value": n_sample / dt / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+            "sample": f"hss_partition of the first {n_sample} keys of the same generator "
+                      f"(seed {dseed}), p={p}, eps={eps}, single-threaded C++ oracle, "
+                      f"{dt:.2f} s",
+            "seconds": round(dt, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uniform_u64_2^28_p1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-sample", type=int, default=1 << 25,
+                    help="keys in the CPU oracle sample (0 to skip)")
+    ap.add_argument("--sort-steps", type=int, default=3, help="hss_sort steps timed for context")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1803_01237_amd as hss
+    import synth
+
+    n, p, eps, dseed, hseed, kind, payload = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    log(f"[bench] generating {args.workload}: n={n} p={p} eps={eps}")
+    keys_np = synth.make(kind, n, dseed)
+    keys = torch.from_numpy(keys_np.view(np.int64)).to(dev)
+    vals = torch.arange(n, dtype=torch.int64, device=dev) if payload else None
+    del keys_np
+    kout = torch.empty_like(keys)
+    vout = torch.empty_like(vals) if payload else None
+    off = torch.empty(p + 1, dtype=torch.int64, device=dev)
+
+    plan = hss.Plan(n, p, eps, key_bytes=8, payload=payload)
+    log(f"[bench] workspace {plan.workspace_bytes / 2**30:.2f} GiB; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        plan.partition(keys, hseed, vals, kout, vout, off)
+    torch.cuda.synchronize()
+
+    plan.profile(True)
+    plan.profile_reset()
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.partition(keys, hseed, vals, kout, vout, off)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = plan.profile_read()
+    plan.profile(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = n / (ms_step * 1e-3) / 1e9
+    rounds = len(plan.trace())
+    ms_m = [r.m for r in plan.trace()]
+
+    # check the benched result: every splitter inside its target range
+    tol = plan.constants(1)[0]
+    o = off.cpu().numpy()
+    ideal = (np.arange(p + 1, dtype=object) * n) // p
+    bad = [i for i in range(1, p) if abs(int(o[i]) - int(ideal[i])) > tol]
+    if bad or o[0] != 0 or o[p] != n:
+        log(f"[bench] BALANCE CHECK FAILED at {bad[:5]}")
+        sys.exit(1)
+
+    # hss_sort for context (not the headline)
+    sort_ms = None
+    if args.sort_steps > 0:
+        plan.sort(keys, hseed, vals, kout, vout, off)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for _ in range(args.sort_steps):
+            plan.sort(keys, hseed, vals, kout, vout, off)
+        torch.cuda.synchronize()
+        sort_ms = (time.perf_counter() - s0) * 1e3 / args.sort_steps
+
+    # roofline of the dominant kernel family (largest share of the step)
+    fam = max((f for f in prof if f != "rounds" and prof[f][1] > 0), key=lambda f: prof[f][0])
+    f_ms, f_n, f_bytes = prof[fam]
+    achieved = (f_bytes / f_n) / (f_ms / f_n * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": TRAFFIC, "avg_launch_ms": round(f_ms / f_n, 4),
+            "bytes_per_launch": f_bytes // f_n}
+    stages = {f: {"ms_per_step": round(prof[f][0] / args.steps, 4),
+                  "launches_per_step": prof[f][1] // args.steps,
+                  "GB_per_s": (round(prof[f][2] / (prof[f][0] * 1e-3) / 1e9, 1)
+                               if prof[f][0] > 0 and prof[f][2] else None)}
+              for f in prof}
+
+    cpu = None
+    if args.cpu_sample > 0:
+        log(f"[bench] CPU oracle on {args.cpu_sample} keys")
+        cpu = cpu_baseline(kind, min(args.cpu_sample, n), p, eps, dseed, hseed, payload)
+
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gkeys/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "p": p, "eps": eps,
+                   "payload": payload, "op": "hss_partition", "seed": hseed},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "stages": stages,
+        "rounds": rounds, "probes_per_round": ms_m,
+        "hss_sort_ms": None if sort_ms is None else round(sort_ms, 4),
+        "hss_sort_gkeys_s": None if sort_ms is None else round(n / (sort_ms * 1e-3) / 1e9, 3),
+    }
+    print(json.dumps(line), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -16,7 +16,9 @@
  *     All work is enqueued on `stream`.  The splitter rounds read a few words
  *     back to the host once per round, and hss_partition / hss_sort read the
  *     device consistency word once more at the end, so both return after
- *     their work on `stream` has completed.  hss_local_sort is asynchronous.
+ *     their work on `stream` has completed.  Every segment sort also reads
+ *     back how many of its sub-buckets overflow on-chip memory, so
+ *     hss_local_sort returns after its work has completed too.
  *   - Keys are unsigned integers (32 or 64 bit) compared as unsigned.  Equal
  *     keys are ordered by (source segment, position in the segment), the
  *     implicit tags of section 6.1, which makes every result equal to what a
@@ -57,7 +59,10 @@ typedef struct {
     uint32_t force_full_sample; /* 1: every key is a probe in round 1 (one round) */
     uint32_t trace_level;       /* 0: per-round counts only; 1: also probes, ranks
                                    and splitter state per round (host copies)    */
-    uint32_t reserved[4];       /* must be zero */
+    uint32_t lsd_only;          /* 1: sort segments and buckets by plain 8-bit LSD
+                                   passes instead of the MSD pass + on-chip finish
+                                   (same results; for comparison)               */
+    uint32_t reserved[3];       /* must be zero */
 } hss_tuning;
 
 /*
@@ -153,6 +158,23 @@ hss_status hss_trace_round_state(hss_plan_t plan, uint32_t j, uint64_t* lo_rank,
  * keys preceding S(b)).  Any pointer may be NULL. */
 hss_status hss_trace_splitters(hss_plan_t plan, uint64_t* chi, uint64_t* s_key, uint64_t* s_tag,
                                uint64_t* pieces);
+
+/*
+ * Measurement.  hss_profile(plan, 1) makes later calls on the plan bracket
+ * every launch of a kernel family with HIP events recorded on the call's
+ * stream; hss_profile_read waits for those events and returns, for one
+ * family, the summed milliseconds, the number of launches and the
+ * algorithmic bytes the launches move (keys, payload and tables read plus
+ * written).  Families:
+ *   0 radix count   1 radix scan   2 radix scatter
+ *   3 splitter rounds (the whole phase, host read-backs included; bytes 0)
+ *   4 exchange offsets   5 exchange copy   6 on-chip sub-bucket sort
+ * hss_profile(plan, 0) stops timing; hss_profile_reset zeroes the totals.
+ */
+hss_status hss_profile(hss_plan_t plan, int enable);
+hss_status hss_profile_reset(hss_plan_t plan);
+hss_status hss_profile_read(hss_plan_t plan, uint32_t family, double* ms, uint64_t* launches,
+                            uint64_t* bytes);
 
 const char* hss_status_string(hss_status status);
 

@@ -26,6 +26,10 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it first (__graft_entry__.build() or "
                       f"python -m paper_1803_01237_amd.build)")
 
+# PyTorch ships its own HIP runtime under the same soname as the system one;
+# load it first so that libhss.so and PyTorch share one runtime.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 HSS_U32, HSS_U64 = 0, 1
@@ -37,8 +41,12 @@ EXPORTS = [
     "hss_plan", "hss_plan_destroy", "hss_workspace_bytes", "hss_partition", "hss_sort",
     "hss_local_sort", "hss_get_constants", "hss_trace_rounds", "hss_trace_round_info",
     "hss_trace_round_probes", "hss_trace_round_state", "hss_trace_splitters",
+    "hss_profile", "hss_profile_reset", "hss_profile_read",
     "hss_status_string", "hss_last_error",
 ]
+
+PROFILE_FAMILIES = ["radix_count", "radix_scan", "radix_scatter", "rounds",
+                    "exchange_offsets", "exchange_copy", "small_sort"]
 
 
 class HssError(RuntimeError):
@@ -51,7 +59,7 @@ class HssError(RuntimeError):
 class _Tuning(C.Structure):
     _fields_ = [("max_rounds", C.c_uint32), ("k_override", C.c_uint32),
                 ("force_full_sample", C.c_uint32), ("trace_level", C.c_uint32),
-                ("reserved", C.c_uint32 * 4)]
+                ("lsd_only", C.c_uint32), ("reserved", C.c_uint32 * 3)]
 
 
 _vp, _u64, _u32, _dbl = C.c_void_p, C.c_uint64, C.c_uint32, C.c_double
@@ -78,6 +86,12 @@ _lib.hss_trace_round_state.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp]
 _lib.hss_trace_round_state.restype = C.c_int
 _lib.hss_trace_splitters.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.hss_trace_splitters.restype = C.c_int
+_lib.hss_profile.argtypes = [_vp, C.c_int]
+_lib.hss_profile.restype = C.c_int
+_lib.hss_profile_reset.argtypes = [_vp]
+_lib.hss_profile_reset.restype = C.c_int
+_lib.hss_profile_read.argtypes = [_vp, _u32, _vp, _vp, _vp]
+_lib.hss_profile_read.restype = C.c_int
 _lib.hss_status_string.argtypes = [C.c_int]
 _lib.hss_status_string.restype = C.c_char_p
 _lib.hss_last_error.argtypes = []
@@ -131,8 +145,9 @@ class Plan:
 
     def __init__(self, n: int, p: int, eps: float, key_bytes: int = 8, payload: bool = False,
                  max_rounds: int = 0, k_override: int = 0, force_full_sample: bool = False,
-                 trace_level: int = 0):
-        tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, trace_level)
+                 trace_level: int = 0, lsd_only: bool = False):
+        tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, trace_level,
+                      1 if lsd_only else 0)
         h = _vp()
         kt = HSS_U64 if key_bytes == 8 else HSS_U32
         _check(_lib.hss_plan(C.byref(h), n, p, eps, kt, 1 if payload else 0, C.byref(tun)),
@@ -246,6 +261,22 @@ class Plan:
                                                   _np_ptr(r.hi_rank), _np_ptr(r.settled),
                                                   _np_ptr(r.chi)), "hss_trace_round_state")
             out.append(r)
+        return out
+
+    def profile(self, enable: bool = True):
+        _check(_lib.hss_profile(self._h, 1 if enable else 0), "hss_profile")
+
+    def profile_reset(self):
+        _check(_lib.hss_profile_reset(self._h), "hss_profile_reset")
+
+    def profile_read(self) -> dict:
+        """{family: (ms, launches, algorithmic bytes)} summed since the last reset."""
+        out = {}
+        for i, name in enumerate(PROFILE_FAMILIES):
+            ms, n, b = C.c_double(), C.c_uint64(), C.c_uint64()
+            _check(_lib.hss_profile_read(self._h, i, C.byref(ms), C.byref(n), C.byref(b)),
+                   "hss_profile_read")
+            out[name] = (float(ms.value), int(n.value), int(b.value))
         return out
 
     def splitters(self):

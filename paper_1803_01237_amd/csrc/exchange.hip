@@ -61,9 +61,12 @@ __device__ __forceinline__ uint32_t last_le_u32(const uint32_t* v, uint32_t lo, 
 }
 
 template <typename K, bool kPayload>
-__global__ __launch_bounds__(kT) void exchange_copy_kernel(ExchangeArgs a, uint32_t chunks) {
-    __shared__ uint32_t w_off[kWindow];     // piece start inside the bucket
-    __shared__ uint64_t w_src[kWindow];     // source position of the piece start
+__global__ __launch_bounds__(kT) void exchange_copy_kernel(ExchangeArgs a, uint32_t chunks,
+                                                           uint32_t window) {
+    // window entries: piece start inside the bucket, source position of the piece
+    extern __shared__ uint64_t smem[];
+    uint64_t* w_src = smem;
+    uint32_t* w_off = (uint32_t*)(smem + window);
     __shared__ uint32_t sh_first, sh_count;
     const uint32_t b = blockIdx.x / chunks;
     const uint32_t c = blockIdx.x % chunks;
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(kT) void exchange_copy_kernel(ExchangeArgs a, uint3
     const uint32_t first = sh_first, cnt = sh_count;
     const K* B = (const K*)a.B;
     K* out = (K*)a.out;
-    if (cnt > kWindow) {
+    if (cnt > window) {
         // many empty pieces in the window: search the bucket's row directly
         for (uint32_t r = (uint32_t)r0 + threadIdx.x; r < r1; r += kT) {
             const uint32_t s = last_le_u32(row, first, first + cnt, r);
@@ -111,21 +114,51 @@ __global__ __launch_bounds__(kT) void exchange_copy_kernel(ExchangeArgs a, uint3
     }
 }
 
+__global__ void bucket_shift_kernel(uint32_t p, int key_bits, const uint64_t* __restrict__ s_key,
+                                    uint8_t* __restrict__ shift) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= p) return;
+    const uint64_t top = key_bits == 64 ? ~0ull : 0xFFFFFFFFull;
+    const uint64_t lo = b == 0 ? 0 : s_key[b];
+    const uint64_t hi = b + 1 == p ? top : s_key[b + 1];
+    const uint64_t x = lo ^ hi;
+    const int h = x ? 63 - __clzll((long long)x) : 0;   // highest differing bit
+    shift[b] = (uint8_t)(h >= 7 ? h - 7 : 0);
+}
+
 }  // namespace
 
+hipError_t launch_bucket_shift(uint32_t p, int key_bits, const uint64_t* s_key, uint8_t* shift,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(bucket_shift_kernel, dim3((p + 255) / 256), dim3(256), 0, s, p, key_bits,
+                       s_key, shift);
+    return hipGetLastError();
+}
+
 hipError_t launch_exchange(const ExchangeArgs& a, hipStream_t s) {
+    Profiler dummy;
+    Profiler& prof = a.prof ? *a.prof : dummy;
+    const uint64_t pp = (uint64_t)a.p * a.p;
+    prof.begin(s);
     hipLaunchKernelGGL(piece_offsets_kernel, dim3(a.p), dim3(kT), 0, s, a);
+    prof.end(kProfExchangeOffsets, s, pp * 4 * 3);
     const uint32_t chunks = (uint32_t)((a.max_bucket + kChunk - 1) / kChunk);
     if (chunks == 0) return hipGetLastError();
     const dim3 grid((unsigned)((uint64_t)a.p * chunks));
     const bool pay = a.Bv != nullptr;
+    // LDS window: the pieces meeting one chunk, at most p and at most kWindow
+    const uint32_t window = a.p < (uint32_t)kWindow ? a.p : (uint32_t)kWindow;
+    const size_t lds = (size_t)window * (8 + 4);
+    // algorithmic bytes: every key (and payload word) read once and written once
+    prof.begin(s);
     if (a.key_bytes == 4) {
-        if (pay) hipLaunchKernelGGL((exchange_copy_kernel<uint32_t, true>), grid, dim3(kT), 0, s, a, chunks);
-        else hipLaunchKernelGGL((exchange_copy_kernel<uint32_t, false>), grid, dim3(kT), 0, s, a, chunks);
+        if (pay) hipLaunchKernelGGL((exchange_copy_kernel<uint32_t, true>), grid, dim3(kT), lds, s, a, chunks, window);
+        else hipLaunchKernelGGL((exchange_copy_kernel<uint32_t, false>), grid, dim3(kT), lds, s, a, chunks, window);
     } else {
-        if (pay) hipLaunchKernelGGL((exchange_copy_kernel<uint64_t, true>), grid, dim3(kT), 0, s, a, chunks);
-        else hipLaunchKernelGGL((exchange_copy_kernel<uint64_t, false>), grid, dim3(kT), 0, s, a, chunks);
+        if (pay) hipLaunchKernelGGL((exchange_copy_kernel<uint64_t, true>), grid, dim3(kT), lds, s, a, chunks, window);
+        else hipLaunchKernelGGL((exchange_copy_kernel<uint64_t, false>), grid, dim3(kT), lds, s, a, chunks, window);
     }
+    prof.end(kProfExchangeCopy, s, a.n * 2 * (a.key_bytes + (pay ? 8 : 0)));
     return hipGetLastError();
 }
 

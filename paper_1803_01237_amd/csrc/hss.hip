@@ -36,6 +36,9 @@ hss_status fail(hss_status st, const std::string& msg) {
 
 typedef unsigned __int128 u128;
 
+// largest per-round probe x segment count matrix kept on the device (words)
+constexpr uint64_t kCountMatrixBudget = 1ull << 27;
+
 struct RoundRecord {
     uint64_t domain = 0, m = 0;
     uint32_t thresh = 0, all = 0;
@@ -95,6 +98,18 @@ struct hss_plan_s {
     size_t sort_scratch_bytes = 0;
 
     std::vector<RoundRecord> trace;
+    Profiler prof;
+
+    // per-probe segment counts of the current round (grown on demand)
+    uint32_t* cmat = nullptr;
+    uint64_t cmat_words = 0;
+    uint8_t* bucket_shift = nullptr;
+
+    // hybrid sort state
+    uint64_t* sb_start = nullptr;
+    uint32_t* sb_len = nullptr;
+    OversizeList ov;
+    HybridHost hh;
 };
 
 namespace {
@@ -154,6 +169,16 @@ size_t layout(hss_plan_s& P, char* base) {
     r.req_kind = ar.take<uint32_t>(2 * p);
     r.ctr = ar.take<RoundCounters>(1);
     P.dst = r.ivl_blk;   // the exchange runs after the last round
+    P.bucket_shift = ar.take<uint8_t>(p);
+    P.sb_start = ar.take<uint64_t>(p * 256);
+    P.sb_len = ar.take<uint32_t>(p * 256);
+    const uint64_t ovc = oversize_capacity((uint32_t)p, n);
+    P.ov.count = ar.take<uint32_t>(1);
+    P.ov.tiles = ar.take<uint32_t>(1);
+    P.ov.beg = ar.take<uint64_t>(ovc);
+    P.ov.end = ar.take<uint64_t>(ovc);
+    P.ov.tile0 = ar.take<uint32_t>(ovc + 1);
+    P.ov.tile_seg = ar.take<uint32_t>(oversize_tile_capacity((uint32_t)p, n));
     return ar.used;
 }
 
@@ -234,24 +259,56 @@ hss_status d2h(std::vector<T>& v, const T* d, size_t count, hipStream_t s) {
     return HSS_OK;
 }
 
+// Stable sort of the segments [seg_off[s], seg_off[s+1]) (the p input
+// segments, or the p buckets after the exchange).
+hss_status segment_sort(hss_plan_s& P, const void* kin, const uint64_t* vin, void* kout,
+                        uint64_t* vout, void* ktmp, uint64_t* vtmp, const uint64_t* seg_off,
+                        uint64_t max_len, const uint8_t* seg_shift, hipStream_t s) {
+    if (P.tune.lsd_only) {
+        SegSort ss;
+        ss.key_bytes = P.key_bytes;
+        ss.keys_in = kin;
+        ss.vals_in = vin;
+        ss.keys_out = kout;
+        ss.vals_out = vout;
+        ss.keys_tmp = ktmp;
+        ss.vals_tmp = vtmp;
+        ss.seg_off = seg_off;
+        ss.num_segs = P.p;
+        ss.max_seg_len = max_len;
+        ss.total_len = P.n;
+        ss.counts = P.counts;
+        ss.begin_bit = 0;
+        ss.end_bit = P.key_bytes * 8;
+        ss.prof = &P.prof;
+        HIP_TRY(segmented_radix_sort(ss, s));
+        return HSS_OK;
+    }
+    HybridSort hs;
+    hs.key_bytes = P.key_bytes;
+    hs.keys_in = kin;
+    hs.vals_in = vin;
+    hs.keys_out = kout;
+    hs.vals_out = vout;
+    hs.keys_tmp = ktmp;
+    hs.vals_tmp = vtmp;
+    hs.seg_off = seg_off;
+    hs.num_segs = P.p;
+    hs.max_seg_len = max_len;
+    hs.total_len = P.n;
+    hs.counts = P.counts;
+    hs.sb_start = P.sb_start;
+    hs.sb_len = P.sb_len;
+    hs.seg_shift = seg_shift;
+    hs.ov = P.ov;
+    hs.prof = &P.prof;
+    HIP_TRY(hybrid_sort(hs, s, P.hh));
+    return HSS_OK;
+}
+
 hss_status local_sort(hss_plan_s& P, const void* kin, const uint64_t* vin, void* kout,
                       uint64_t* vout, void* ktmp, uint64_t* vtmp, hipStream_t s) {
-    SegSort ss;
-    ss.key_bytes = P.key_bytes;
-    ss.keys_in = kin;
-    ss.vals_in = vin;
-    ss.keys_out = kout;
-    ss.vals_out = vout;
-    ss.keys_tmp = ktmp;
-    ss.vals_tmp = vtmp;
-    ss.seg_off = P.seg_off;
-    ss.num_segs = P.p;
-    ss.max_seg_len = P.max_seg;
-    ss.counts = P.counts;
-    ss.begin_bit = 0;
-    ss.end_bit = P.key_bytes * 8;
-    HIP_TRY(segmented_radix_sort(ss, s));
-    return HSS_OK;
+    return segment_sort(P, kin, vin, kout, vout, ktmp, vtmp, P.seg_off, P.max_seg, nullptr, s);
 }
 
 // Splitter rounds on the locally sorted buffer P.B; leaves chi in d_offsets.
@@ -285,9 +342,26 @@ hss_status determine_splitters(hss_plan_s& P, uint64_t seed, uint64_t* d_offsets
         st = ensure_sort_scratch(P, m);
         if (st != HSS_OK) return st;
         HIP_TRY(launch_probe_sort(r, m, P.sort_scratch, P.sort_scratch_bytes, P.counts, s));
-        HIP_TRY(launch_rank(r, m, s));
+        // keep every probe's segment counts when they fit the budget, so the
+        // locate step copies instead of searching again
+        uint32_t* cmat = nullptr;
+        const uint64_t words = m * (uint64_t)P.p;
+        if (words <= kCountMatrixBudget) {
+            if (words > P.cmat_words) {
+                if (P.cmat) HIP_TRY(hipFree(P.cmat));
+                P.cmat = nullptr;
+                P.cmat_words = 0;
+                uint64_t want = 1ull << 20;
+                while (want < words) want *= 2;
+                if (want > kCountMatrixBudget) want = kCountMatrixBudget;
+                if (hipMalloc((void**)&P.cmat, want * 4) == hipSuccess) P.cmat_words = want;
+                else P.cmat = nullptr;
+            }
+            if (P.cmat) cmat = P.cmat;
+        }
+        HIP_TRY(launch_rank(r, m, cmat, s));
         HIP_TRY(launch_settle(r, m, s));
-        HIP_TRY(launch_locate(r, s));
+        HIP_TRY(launch_locate(r, cmat, s));
         RoundRecord rec;
         rec.domain = c.domain;
         rec.m = m;
@@ -334,8 +408,10 @@ hss_status run(hss_plan_s* P, uint64_t seed, const void* kin, const uint64_t* vi
         HIP_TRY(hipMemcpyAsync(d_offsets, off, sizeof(off), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
     } else {
+        P->prof.begin(s);
         st = determine_splitters(*P, seed, d_offsets, s);
         if (st != HSS_OK) return st;
+        P->prof.end(kProfRounds, s, 0);
     }
     // phase 3: exchange into the output (or into A before the bucket sort)
     ExchangeArgs ex;
@@ -352,24 +428,18 @@ hss_status run(hss_plan_s* P, uint64_t seed, const void* kin, const uint64_t* vi
     ex.dst = P->dst;
     ex.max_bucket = P->max_bucket;
     ex.err = &P->ra.ctr->err;
+    ex.prof = &P->prof;
     HIP_TRY(launch_exchange(ex, s));
     // phase 4 (sort only): stable sort of every bucket
     if (sort_buckets) {
-        SegSort ss;
-        ss.key_bytes = P->key_bytes;
-        ss.keys_in = P->A;
-        ss.vals_in = P->Av;
-        ss.keys_out = kout;
-        ss.vals_out = vout;
-        ss.keys_tmp = P->B;
-        ss.vals_tmp = P->Bv;
-        ss.seg_off = d_offsets;
-        ss.num_segs = P->p;
-        ss.max_seg_len = P->max_bucket;
-        ss.counts = P->counts;
-        ss.begin_bit = 0;
-        ss.end_bit = P->key_bytes * 8;
-        HIP_TRY(segmented_radix_sort(ss, s));
+        const uint8_t* shifts = nullptr;
+        if (P->p > 1) {
+            HIP_TRY(launch_bucket_shift(P->p, P->key_bytes * 8, P->ra.s_key, P->bucket_shift, s));
+            shifts = P->bucket_shift;
+        }
+        st = segment_sort(*P, P->A, P->Av, kout, vout, P->B, P->Bv, d_offsets, P->max_bucket,
+                          shifts, s);
+        if (st != HSS_OK) return st;
     }
     // the exchange checks that every bucket's pieces add up to its size
     st = read_counters(*P, s);
@@ -422,7 +492,8 @@ hss_status hss_plan(hss_plan_t* out, uint64_t n, uint32_t p, double eps, hss_key
             return fail(HSS_ERR_OUT_OF_MEMORY, std::string("hipMalloc workspace: ") + hipGetErrorString(e));
         }
         layout(*P, (char*)P->arena);
-        e = hipHostMalloc((void**)&P->h_ctr, sizeof(RoundCounters), hipHostMallocDefault);
+        e = hipHostMalloc((void**)&P->h_ctr, sizeof(RoundCounters) + 16, hipHostMallocDefault);
+        if (e == hipSuccess) P->hh.pinned = (uint32_t*)((char*)P->h_ctr + sizeof(RoundCounters));
         if (e != hipSuccess) {
             (void)hipFree(P->arena);
             delete P;
@@ -474,6 +545,8 @@ void hss_plan_destroy(hss_plan_t P) {
         (void)hipDeviceSynchronize();
         if (P->probe_mem) (void)hipFree(P->probe_mem);
         if (P->sort_scratch) (void)hipFree(P->sort_scratch);
+        if (P->hh.fb_counts) (void)hipFree(P->hh.fb_counts);
+        if (P->cmat) (void)hipFree(P->cmat);
         if (P->arena) (void)hipFree(P->arena);
         if (P->h_ctr) (void)hipHostFree(P->h_ctr);
         delete P;
@@ -601,6 +674,29 @@ hss_status hss_trace_splitters(hss_plan_t P, uint64_t* chi, uint64_t* s_key, uin
     } catch (...) {
         return fail(HSS_ERR_DEVICE, "unexpected exception");
     }
+}
+
+hss_status hss_profile(hss_plan_t P, int enable) {
+    if (!P) return fail(HSS_ERR_INVALID_ARG, "null plan");
+    P->prof.collect();
+    P->prof.on = enable != 0;
+    return HSS_OK;
+}
+
+hss_status hss_profile_reset(hss_plan_t P) {
+    if (!P) return fail(HSS_ERR_INVALID_ARG, "null plan");
+    P->prof.reset();
+    return HSS_OK;
+}
+
+hss_status hss_profile_read(hss_plan_t P, uint32_t family, double* ms, uint64_t* launches,
+                            uint64_t* bytes) {
+    if (!P || family >= (uint32_t)kProfSlots) return fail(HSS_ERR_INVALID_ARG, "bad plan or family");
+    P->prof.collect();
+    if (ms) *ms = P->prof.ms[family];
+    if (launches) *launches = P->prof.launches[family];
+    if (bytes) *bytes = P->prof.bytes[family];
+    return HSS_OK;
 }
 
 const char* hss_status_string(hss_status s) {

@@ -4,9 +4,87 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace hss {
 
 constexpr uint64_t kNone = ~0ull;
+
+// ------------------------------------------------------------ profiling ----
+// Kernel families timed with HIP events on the launching stream when a plan
+// has profiling switched on.  `bytes` accumulates the algorithmic bytes the
+// launches move (reads + writes of keys, payload and tables).
+enum ProfSlot : int {
+    kProfRadixCount = 0,
+    kProfRadixScan,
+    kProfRadixScatter,
+    kProfRounds,
+    kProfExchangeOffsets,
+    kProfExchangeCopy,
+    kProfSmallSort,
+    kProfSlots
+};
+
+struct Profiler {
+    bool on = false;
+    struct Pending {
+        int slot;
+        hipEvent_t a, b;
+        uint64_t bytes;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> spare;
+    double ms[kProfSlots] = {};
+    uint64_t launches[kProfSlots] = {};
+    uint64_t bytes[kProfSlots] = {};
+    hipEvent_t open_a = nullptr;
+
+    hipEvent_t take() {
+        hipEvent_t e = nullptr;
+        if (!spare.empty()) {
+            e = spare.back();
+            spare.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+        }
+        return e;
+    }
+    void begin(hipStream_t s) {
+        if (!on) return;
+        open_a = take();
+        if (open_a) (void)hipEventRecord(open_a, s);
+    }
+    void end(int slot, hipStream_t s, uint64_t nbytes) {
+        if (!on || !open_a) return;
+        hipEvent_t b = take();
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        pending.push_back({slot, open_a, b, nbytes});
+        open_a = nullptr;
+    }
+    // Waits for the recorded events and folds them into the totals.
+    void collect() {
+        for (const Pending& q : pending) {
+            float t = 0;
+            if (hipEventSynchronize(q.b) == hipSuccess && hipEventElapsedTime(&t, q.a, q.b) == hipSuccess) {
+                ms[q.slot] += t;
+                launches[q.slot] += 1;
+                bytes[q.slot] += q.bytes;
+            }
+            spare.push_back(q.a);
+            spare.push_back(q.b);
+        }
+        pending.clear();
+    }
+    void reset() {
+        collect();
+        for (int i = 0; i < kProfSlots; ++i) { ms[i] = 0; launches[i] = 0; bytes[i] = 0; }
+    }
+    ~Profiler() {
+        for (const Pending& q : pending) { (void)hipEventDestroy(q.a); (void)hipEventDestroy(q.b); }
+        for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+    }
+};
 
 // ----------------------------------------------------------- radix sort ----
 // Stable sort of every segment [seg_off[s], seg_off[s+1]) of a key array by
@@ -25,17 +103,100 @@ struct SegSort {
     const uint64_t* seg_off = nullptr; // device, S+1 entries
     uint32_t num_segs = 0;
     uint64_t max_seg_len = 0;          // upper bound of every segment length
+    uint64_t total_len = 0;            // sum of the segment lengths (for byte counts)
     uint32_t* counts = nullptr;        // device, >= radix_count_words(S, max_seg_len)
     int begin_bit = 0;
     int end_bit = 64;
+    Profiler* prof = nullptr;          // optional
 };
 
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;   // keys per workgroup tile
 
+// Which key range a workgroup tile covers.  Fixed mode (tile_seg == nullptr):
+// segment s owns tiles [s*tps, (s+1)*tps).  List mode: tile i belongs to
+// segment tile_seg[i], whose tiles are [tile0[s], tile0[s+1]).  Segment s
+// spans [beg[s], end[s]).
+struct TileMap {
+    const uint64_t* beg = nullptr;
+    const uint64_t* end = nullptr;
+    const uint32_t* tile_seg = nullptr;
+    const uint32_t* tile0 = nullptr;
+    uint32_t tps = 0;
+};
+
+// One stable counting pass on digit [shift, shift+8) of every segment.
+struct RadixPass {
+    int key_bytes = 8;
+    const void* keys_in = nullptr;
+    const uint64_t* vals_in = nullptr;
+    void* keys_out = nullptr;
+    uint64_t* vals_out = nullptr;
+    TileMap map;
+    uint32_t num_segs = 0;
+    uint32_t num_tiles = 0;
+    int shift = 0;
+    const uint8_t* seg_shift = nullptr;  // optional: per-segment digit shift (fixed mode)
+    uint32_t* counts = nullptr;        // num_tiles * 256 words
+    uint64_t* sb_start = nullptr;      // optional: per (segment, digit) run start
+    uint32_t* sb_len = nullptr;        // optional: per (segment, digit) run length
+    uint64_t total_len = 0;            // keys covered (for byte counts)
+    Profiler* prof = nullptr;
+};
+
 uint64_t radix_count_words(uint32_t num_segs, uint64_t max_seg_len);
+hipError_t radix_pass(const RadixPass& a, hipStream_t stream);
 hipError_t segmented_radix_sort(const SegSort& a, hipStream_t stream);
+
+// ---------------------------------------------------------- hybrid sort ----
+// Sub-buckets too large for LDS, collected on the device.
+struct OversizeList {
+    uint32_t* count = nullptr;         // entries
+    uint32_t* tiles = nullptr;         // total tiles
+    uint64_t* beg = nullptr;           // capacity oversize_capacity()
+    uint64_t* end = nullptr;
+    uint32_t* tile0 = nullptr;         // capacity + 1
+    uint32_t* tile_seg = nullptr;      // oversize_tile_capacity()
+};
+
+// Stable sort of contiguous segments [seg_off[s], seg_off[s+1]): an MSD pass
+// into keys_tmp, then every sub-bucket finished into keys_out.  keys_in must
+// differ from keys_tmp and keys_out.
+struct HybridSort {
+    int key_bytes = 8;
+    const void* keys_in = nullptr;
+    const uint64_t* vals_in = nullptr;
+    void* keys_out = nullptr;
+    uint64_t* vals_out = nullptr;
+    void* keys_tmp = nullptr;
+    uint64_t* vals_tmp = nullptr;
+    const uint64_t* seg_off = nullptr;
+    uint32_t num_segs = 0;
+    uint64_t max_seg_len = 0;
+    uint64_t total_len = 0;
+    uint32_t* counts = nullptr;        // >= radix_count_words(num_segs, max_seg_len)
+    uint64_t* sb_start = nullptr;      // num_segs * 256
+    uint32_t* sb_len = nullptr;        // num_segs * 256
+    // optional per-segment MSD digit shift: all keys of segment s must agree
+    // on the bits above seg_shift[s] + 8 (nullptr: the top digit)
+    const uint8_t* seg_shift = nullptr;
+    OversizeList ov;
+    Profiler* prof = nullptr;
+};
+
+// Host-side state of the hybrid sort: pinned read-back words and the count
+// table of the oversize passes, grown on demand.
+struct HybridHost {
+    uint32_t* pinned = nullptr;        // 2 words
+    uint32_t* fb_counts = nullptr;
+    uint64_t fb_words = 0;
+    uint32_t last_oversize = 0;
+};
+
+hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host);
+uint64_t oversize_capacity(uint32_t num_segs, uint64_t total_len);
+uint64_t oversize_tile_capacity(uint32_t num_segs, uint64_t total_len);
 
 // --------------------------------------------------------------- rounds ----
 // Device counters read back once per round.
@@ -104,9 +265,10 @@ hipError_t launch_sample(const RoundArgs& a, uint64_t seed, uint32_t round, uint
 hipError_t launch_probe_sort(const RoundArgs& a, uint64_t m, void* scratch, size_t scratch_bytes,
                              uint32_t* counts, hipStream_t s);
 size_t probe_sort_scratch_bytes(uint64_t m);
-hipError_t launch_rank(const RoundArgs& a, uint64_t m, hipStream_t s);
+// cmat (optional, m x p words): per-probe segment counts kept for locate.
+hipError_t launch_rank(const RoundArgs& a, uint64_t m, uint32_t* cmat, hipStream_t s);
 hipError_t launch_settle(const RoundArgs& a, uint64_t m, hipStream_t s);
-hipError_t launch_locate(const RoundArgs& a, hipStream_t s);
+hipError_t launch_locate(const RoundArgs& a, const uint32_t* cmat, hipStream_t s);
 hipError_t launch_finalize(const RoundArgs& a, uint64_t* d_offsets, hipStream_t s);
 
 // ------------------------------------------------------------- exchange ----
@@ -124,8 +286,14 @@ struct ExchangeArgs {
     uint32_t* dst;                 // p x p, offset of piece (b, s) inside bucket b
     uint64_t max_bucket;
     unsigned int* err;
+    Profiler* prof = nullptr;      // optional
 };
 
 hipError_t launch_exchange(const ExchangeArgs& a, hipStream_t s);
+// Per-bucket MSD digit shift for the bucket sort: all keys of bucket b lie in
+// [key(S(b)), key(S(b+1))], so they agree on the bits above the highest bit
+// where those two keys differ.
+hipError_t launch_bucket_shift(uint32_t p, int key_bits, const uint64_t* s_key, uint8_t* shift,
+                               hipStream_t s);
 
 }  // namespace hss

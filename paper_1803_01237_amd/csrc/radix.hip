@@ -29,18 +29,36 @@ __device__ __forceinline__ uint32_t digit_of(K k, int shift) {
     return (uint32_t)(k >> shift) & 0xFFu;
 }
 
+// Key range [base, stop) of workgroup tile `bid`; false when it is empty.
+__device__ __forceinline__ bool tile_range(const TileMap& m, uint32_t bid, uint64_t* base,
+                                           uint64_t* stop, uint32_t* seg) {
+    uint32_t s, t;
+    if (m.tile_seg) {
+        s = m.tile_seg[bid];
+        t = bid - m.tile0[s];
+    } else {
+        s = bid / m.tps;
+        t = bid % m.tps;
+    }
+    const uint64_t b = m.beg[s], e = m.end[s];
+    *seg = s;
+    *base = b + (uint64_t)t * kSortTile;
+    *stop = e;
+    return *base < e;
+}
+
 template <typename K>
-__global__ __launch_bounds__(kSortThreads) void radix_count_kernel(
-    const K* __restrict__ keys, const uint64_t* __restrict__ seg_off, uint32_t tiles_per_seg,
-    int shift, uint32_t* __restrict__ counts) {
+__global__ __launch_bounds__(kSortThreads) void radix_count_kernel(const K* __restrict__ keys,
+                                                                   TileMap m, int shift,
+                                                                   const uint8_t* __restrict__ seg_shift,
+                                                                   uint32_t* __restrict__ counts) {
     __shared__ uint32_t hist[256];
-    const uint32_t seg = blockIdx.x / tiles_per_seg;
-    const uint32_t tile = blockIdx.x % tiles_per_seg;
     hist[threadIdx.x] = 0;
     __syncthreads();
-    const uint64_t b = seg_off[seg], e = seg_off[seg + 1];
-    const uint64_t base = b + (uint64_t)tile * kSortTile;
-    if (base < e) {
+    uint64_t base, e;
+    uint32_t seg;
+    if (tile_range(m, blockIdx.x, &base, &e, &seg)) {
+        if (seg_shift) shift = seg_shift[seg];
         const uint32_t n_tile = (uint32_t)min((uint64_t)kSortTile, e - base);
         const uint32_t w = threadIdx.x / kWave;
         const uint32_t lane = lane_id();
@@ -51,25 +69,41 @@ __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(
             const uint32_t d = valid ? digit_of(keys[base + li], shift) : 0u;
             const uint64_t live = __ballot(valid);
             if (live == 0) break;
-            const uint64_t m = match_byte(d, live);
-            if (valid && (m & lanes_below_mask()) == 0) atomicAdd(&hist[d], (uint32_t)__popcll(m));
+            const uint64_t mm = match_byte(d, live);
+            if (valid && (mm & lanes_below_mask()) == 0) atomicAdd(&hist[d], (uint32_t)__popcll(mm));
         }
     }
     __syncthreads();
     counts[(uint64_t)blockIdx.x * 256 + threadIdx.x] = hist[threadIdx.x];
 }
 
-// counts[s][t][d] -> offset of the run of digit d from tile t inside segment s.
-__global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ counts,
-                                                         uint32_t tiles_per_seg) {
+// counts[tile][d] of one segment's tiles -> offset of the run of digit d from
+// that tile inside the segment.  Optionally records, per (segment, digit), the
+// start and length of the digit's run: the sub-buckets of an MSD pass.
+__global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ counts, TileMap m,
+                                                         uint64_t* __restrict__ sb_start,
+                                                         uint32_t* __restrict__ sb_len) {
     __shared__ uint32_t scratch[256 / kWave];
-    uint32_t* c = counts + (uint64_t)blockIdx.x * tiles_per_seg * 256;
+    const uint32_t s = blockIdx.x;
+    uint32_t t0, nt;
+    if (m.tile_seg) {
+        t0 = m.tile0[s];
+        nt = m.tile0[s + 1] - t0;
+    } else {
+        t0 = s * m.tps;
+        nt = m.tps;
+    }
+    uint32_t* c = counts + (uint64_t)t0 * 256;
     const uint32_t d = threadIdx.x;
     uint32_t tot = 0;
-    for (uint32_t t = 0; t < tiles_per_seg; ++t) tot += c[t * 256 + d];
+    for (uint32_t t = 0; t < nt; ++t) tot += c[t * 256 + d];
     uint32_t all;
     uint32_t run = block_exclusive_scan<uint32_t, 256>(tot, scratch, &all);
-    for (uint32_t t = 0; t < tiles_per_seg; ++t) {
+    if (sb_start) {
+        sb_start[(uint64_t)s * 256 + d] = m.beg[s] + run;
+        sb_len[(uint64_t)s * 256 + d] = tot;
+    }
+    for (uint32_t t = 0; t < nt; ++t) {
         const uint32_t x = c[t * 256 + d];
         c[t * 256 + d] = run;
         run += x;
@@ -79,8 +113,8 @@ __global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ 
 template <typename K, bool kPayload>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const K* __restrict__ kin, const uint64_t* __restrict__ vin, K* __restrict__ kout,
-    uint64_t* __restrict__ vout, const uint64_t* __restrict__ seg_off, uint32_t tiles_per_seg,
-    int shift, const uint32_t* __restrict__ counts) {
+    uint64_t* __restrict__ vout, TileMap m, int shift, const uint8_t* __restrict__ seg_shift,
+    const uint32_t* __restrict__ counts) {
     __shared__ uint32_t whist[kWavesPerTile][256];
     __shared__ uint32_t tstart[256];
     __shared__ uint32_t gofs[256];
@@ -88,11 +122,11 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     __shared__ uint64_t stage[kSortTile];
     __shared__ uint8_t dstage[kSortTile];
 
-    const uint32_t seg = blockIdx.x / tiles_per_seg;
-    const uint32_t tile = blockIdx.x % tiles_per_seg;
-    const uint64_t b = seg_off[seg], e = seg_off[seg + 1];
-    const uint64_t base = b + (uint64_t)tile * kSortTile;
-    if (base >= e) return;   // uniform over the workgroup
+    uint64_t base, e;
+    uint32_t seg;
+    if (!tile_range(m, blockIdx.x, &base, &e, &seg)) return;   // uniform over the workgroup
+    if (seg_shift) shift = seg_shift[seg];
+    const uint64_t b = m.beg[seg];
     const uint32_t n_tile = (uint32_t)min((uint64_t)kSortTile, e - base);
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
@@ -110,15 +144,15 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         key[r] = valid ? kin[base + li] : (K)0;
         const uint32_t d = digit_of(key[r], shift);
         const uint64_t live = __ballot(valid);
-        const uint64_t m = match_byte(d, live);
-        const int leader = valid ? (int)(__ffsll((unsigned long long)m) - 1) : (int)lane;
+        const uint64_t mm = match_byte(d, live);
+        const int leader = valid ? (int)(__ffsll((unsigned long long)mm) - 1) : (int)lane;
         uint32_t old = 0;
         if (valid && (int)lane == leader) {
             old = whist[w][d];
-            whist[w][d] = old + (uint32_t)__popcll(m);
+            whist[w][d] = old + (uint32_t)__popcll(mm);
         }
         old = __shfl(old, leader);
-        rank[r] = old + (uint32_t)__popcll(m & lanes_below_mask());
+        rank[r] = old + (uint32_t)__popcll(mm & lanes_below_mask());
     }
     __syncthreads();
     {
@@ -166,48 +200,81 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 }
 
 template <typename K>
-hipError_t run_sort(const SegSort& a, hipStream_t stream) {
-    const uint32_t tps = (uint32_t)((a.max_seg_len + kSortTile - 1) / kSortTile);
-    if (a.num_segs == 0 || tps == 0) return hipSuccess;
-    const uint64_t grid = (uint64_t)a.num_segs * tps;
-    const int passes = (a.end_bit - a.begin_bit + 7) / 8;
-    const K* src = (const K*)a.keys_in;
-    const uint64_t* vsrc = a.vals_in;
+hipError_t pass_impl(const RadixPass& a, hipStream_t stream) {
+    if (a.num_segs == 0 || a.num_tiles == 0) return hipSuccess;
+    Profiler dummy;
+    Profiler& prof = a.prof ? *a.prof : dummy;
     const bool pay = a.vals_in != nullptr;
-    for (int i = 0; i < passes; ++i) {
-        const bool to_out = ((passes - 1 - i) % 2) == 0;
-        K* dst = (K*)(to_out ? a.keys_out : a.keys_tmp);
-        uint64_t* vdst = to_out ? a.vals_out : a.vals_tmp;
-        const int shift = a.begin_bit + 8 * i;
-        hipLaunchKernelGGL(radix_count_kernel<K>, dim3((unsigned)grid), dim3(kSortThreads), 0,
-                           stream, src, a.seg_off, tps, shift, a.counts);
-        hipLaunchKernelGGL(radix_scan_kernel, dim3(a.num_segs), dim3(256), 0, stream, a.counts,
-                           tps);
-        if (pay) {
-            hipLaunchKernelGGL((radix_scatter_kernel<K, true>), dim3((unsigned)grid),
-                               dim3(kSortThreads), 0, stream, src, vsrc, dst, vdst, a.seg_off, tps,
-                               shift, a.counts);
-        } else {
-            hipLaunchKernelGGL((radix_scatter_kernel<K, false>), dim3((unsigned)grid),
-                               dim3(kSortThreads), 0, stream, src, nullptr, dst, nullptr,
-                               a.seg_off, tps, shift, a.counts);
-        }
-        src = dst;
-        vsrc = vdst;
-    }
+    // algorithmic bytes: the keys (and payload) are read by the count pass,
+    // read and written by the scatter pass; the count table is written by the
+    // count pass, read and written by the scan, read by the scatter pass
+    const uint64_t table = (uint64_t)a.num_tiles * 256ull * 4ull;
+    const dim3 grid(a.num_tiles), block(kSortThreads);
+    prof.begin(stream);
+    hipLaunchKernelGGL(radix_count_kernel<K>, grid, block, 0, stream, (const K*)a.keys_in, a.map,
+                       a.shift, a.seg_shift, a.counts);
+    prof.end(kProfRadixCount, stream, a.total_len * sizeof(K) + table);
+    prof.begin(stream);
+    hipLaunchKernelGGL(radix_scan_kernel, dim3(a.num_segs), dim3(256), 0, stream, a.counts, a.map,
+                       a.sb_start, a.sb_len);
+    prof.end(kProfRadixScan, stream, 2 * table);
+    prof.begin(stream);
+    if (pay)
+        hipLaunchKernelGGL((radix_scatter_kernel<K, true>), grid, block, 0, stream,
+                           (const K*)a.keys_in, a.vals_in, (K*)a.keys_out, a.vals_out, a.map,
+                           a.shift, a.seg_shift, a.counts);
+    else
+        hipLaunchKernelGGL((radix_scatter_kernel<K, false>), grid, block, 0, stream,
+                           (const K*)a.keys_in, nullptr, (K*)a.keys_out, nullptr, a.map, a.shift,
+                           a.seg_shift, a.counts);
+    prof.end(kProfRadixScatter, stream,
+             a.total_len * 2 * (sizeof(K) + (pay ? 8 : 0)) + table);
     return hipGetLastError();
 }
 
 }  // namespace
+
+hipError_t radix_pass(const RadixPass& a, hipStream_t stream) {
+    if (a.key_bytes == 4) return pass_impl<uint32_t>(a, stream);
+    return pass_impl<uint64_t>(a, stream);
+}
 
 uint64_t radix_count_words(uint32_t num_segs, uint64_t max_seg_len) {
     const uint64_t tps = (max_seg_len + kSortTile - 1) / kSortTile;
     return (uint64_t)num_segs * tps * 256;
 }
 
+// Plain LSD over contiguous segments: ceil((end_bit - begin_bit) / 8) passes,
+// the last one into keys_out.
 hipError_t segmented_radix_sort(const SegSort& a, hipStream_t stream) {
-    if (a.key_bytes == 4) return run_sort<uint32_t>(a, stream);
-    return run_sort<uint64_t>(a, stream);
+    const uint32_t tps = (uint32_t)((a.max_seg_len + kSortTile - 1) / kSortTile);
+    if (a.num_segs == 0 || tps == 0) return hipSuccess;
+    const int passes = (a.end_bit - a.begin_bit + 7) / 8;
+    RadixPass ps;
+    ps.key_bytes = a.key_bytes;
+    ps.map.beg = a.seg_off;
+    ps.map.end = a.seg_off + 1;
+    ps.map.tps = tps;
+    ps.num_segs = a.num_segs;
+    ps.num_tiles = a.num_segs * tps;
+    ps.counts = a.counts;
+    ps.total_len = a.total_len;
+    ps.prof = a.prof;
+    const void* src = a.keys_in;
+    const uint64_t* vsrc = a.vals_in;
+    for (int i = 0; i < passes; ++i) {
+        const bool to_out = ((passes - 1 - i) % 2) == 0;
+        ps.keys_in = src;
+        ps.vals_in = vsrc;
+        ps.keys_out = to_out ? a.keys_out : a.keys_tmp;
+        ps.vals_out = to_out ? a.vals_out : a.vals_tmp;
+        ps.shift = a.begin_bit + 8 * i;
+        hipError_t e = radix_pass(ps, stream);
+        if (e != hipSuccess) return e;
+        src = ps.keys_out;
+        vsrc = ps.vals_out;
+    }
+    return hipSuccess;
 }
 
 }  // namespace hss

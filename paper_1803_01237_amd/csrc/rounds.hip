@@ -298,10 +298,12 @@ __device__ __forceinline__ uint32_t segment_of(const uint64_t* seg_off, uint32_t
 }
 
 // Workgroup per sorted probe: c_s for every segment s inside the slice of the
-// probe's own interval, summed -> R(e).
-template <typename K>
-__global__ __launch_bounds__(kT) void rank_kernel(RoundArgs a) {
-    __shared__ uint64_t scratch[kT / kWave];
+// probe's own interval, summed -> R(e).  One segment per thread (kThreads =
+// 1024 when p is large, so that many dependent searches are in flight per CU).
+// With a count matrix, c_s(e) is also stored at cmat[e * p + s] for locate.
+template <typename K, int kThreads>
+__global__ __launch_bounds__(kThreads) void rank_kernel(RoundArgs a, uint32_t* __restrict__ cmat) {
+    __shared__ uint64_t scratch[kThreads / kWave];
     __shared__ uint32_t sh_t;
     const uint64_t e = blockIdx.x;
     const K key = (K)a.ps_key[e];
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(kT) void rank_kernel(RoundArgs a) {
     const bool unone = a.urank[row] == kNone;
     const K* B = (const K*)a.B;
     uint64_t sum = 0;
-    for (uint32_t s = threadIdx.x; s < a.p; s += kT) {
+    for (uint32_t s = threadIdx.x; s < a.p; s += kThreads) {
         const uint64_t sb = a.seg_off[s];
         const uint64_t slen = a.seg_off[s + 1] - sb;
         const uint64_t lo = lnone ? 0 : a.lpos[(uint64_t)row * a.p + s];
@@ -328,8 +330,9 @@ __global__ __launch_bounds__(kT) void rank_kernel(RoundArgs a) {
             c = count_before<K>(B + sb, lo, hi, key, s < t);
         }
         sum += c;
+        if (cmat) cmat[e * a.p + s] = (uint32_t)c;
     }
-    sum = block_sum<uint64_t, kT>(sum, scratch);
+    sum = block_sum<uint64_t, kThreads>(sum, scratch);
     if (threadIdx.x == 0) a.pr_rank[e] = sum;
 }
 
@@ -382,9 +385,11 @@ __global__ __launch_bounds__(kT) void settle_kernel(RoundArgs a, uint64_t m) {
     }
 }
 
-// Workgroup per request: per-segment counts of a new bound / splitter probe.
-template <typename K>
-__global__ __launch_bounds__(kT) void locate_kernel(RoundArgs a) {
+// Workgroup per request: per-segment counts of a new bound / splitter probe,
+// copied from the rank step's count matrix or found by searching each segment.
+template <typename K, int kThreads>
+__global__ __launch_bounds__(kThreads) void locate_kernel(RoundArgs a,
+                                                          const uint32_t* __restrict__ cmat) {
     __shared__ uint32_t sh_t;
     const uint32_t r = blockIdx.x;
     if (r >= a.ctr->n_req) return;
@@ -398,13 +403,17 @@ __global__ __launch_bounds__(kT) void locate_kernel(RoundArgs a) {
     const uint32_t t = sh_t;
     const K* B = (const K*)a.B;
     uint32_t* dst = kind == 0 ? a.lpos : (kind == 1 ? a.upos : a.prow);
-    for (uint32_t s = threadIdx.x; s < a.p; s += kT) {
-        const uint64_t sb = a.seg_off[s];
-        const uint64_t slen = a.seg_off[s + 1] - sb;
+    const uint32_t own = kind == 0 ? 1u : 0u;   // the L probe itself is excluded
+    const uint32_t* col = cmat ? cmat + (uint64_t)e * a.p : nullptr;
+    for (uint32_t s = threadIdx.x; s < a.p; s += kThreads) {
         uint64_t c;
-        if (s == t) c = g - sb + (kind == 0 ? 1 : 0);   // the L probe itself is excluded
-        else c = count_before<K>(B + sb, 0, slen, key, s < t);
-        dst[row * a.p + s] = (uint32_t)c;
+        if (col) {
+            c = col[s];
+        } else {
+            const uint64_t sb = a.seg_off[s];
+            c = s == t ? g - sb : count_before<K>(B + sb, 0, a.seg_off[s + 1] - sb, key, s < t);
+        }
+        dst[row * a.p + s] = (uint32_t)c + (s == t ? own : 0u);
     }
 }
 
@@ -505,12 +514,16 @@ hipError_t launch_probe_sort(const RoundArgs& a, uint64_t m, void* scratch, size
     return hipGetLastError();
 }
 
-hipError_t launch_rank(const RoundArgs& a, uint64_t m, hipStream_t s) {
+hipError_t launch_rank(const RoundArgs& a, uint64_t m, uint32_t* cmat, hipStream_t s) {
     if (m == 0) return hipSuccess;
-    if (a.key_bytes == 4)
-        hipLaunchKernelGGL(rank_kernel<uint32_t>, dim3((unsigned)m), dim3(kT), 0, s, a);
-    else
-        hipLaunchKernelGGL(rank_kernel<uint64_t>, dim3((unsigned)m), dim3(kT), 0, s, a);
+    const dim3 grid((unsigned)m);
+    if (a.p > 256) {
+        if (a.key_bytes == 4) hipLaunchKernelGGL((rank_kernel<uint32_t, 1024>), grid, dim3(1024), 0, s, a, cmat);
+        else hipLaunchKernelGGL((rank_kernel<uint64_t, 1024>), grid, dim3(1024), 0, s, a, cmat);
+    } else {
+        if (a.key_bytes == 4) hipLaunchKernelGGL((rank_kernel<uint32_t, 256>), grid, dim3(256), 0, s, a, cmat);
+        else hipLaunchKernelGGL((rank_kernel<uint64_t, 256>), grid, dim3(256), 0, s, a, cmat);
+    }
     return hipGetLastError();
 }
 
@@ -519,12 +532,15 @@ hipError_t launch_settle(const RoundArgs& a, uint64_t m, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_locate(const RoundArgs& a, hipStream_t s) {
-    const unsigned grid = 2u * (a.p > 1 ? a.p - 1 : 1);
-    if (a.key_bytes == 4)
-        hipLaunchKernelGGL(locate_kernel<uint32_t>, dim3(grid), dim3(kT), 0, s, a);
-    else
-        hipLaunchKernelGGL(locate_kernel<uint64_t>, dim3(grid), dim3(kT), 0, s, a);
+hipError_t launch_locate(const RoundArgs& a, const uint32_t* cmat, hipStream_t s) {
+    const dim3 grid(2u * (a.p > 1 ? a.p - 1 : 1));
+    if (a.p > 256) {
+        if (a.key_bytes == 4) hipLaunchKernelGGL((locate_kernel<uint32_t, 1024>), grid, dim3(1024), 0, s, a, cmat);
+        else hipLaunchKernelGGL((locate_kernel<uint64_t, 1024>), grid, dim3(1024), 0, s, a, cmat);
+    } else {
+        if (a.key_bytes == 4) hipLaunchKernelGGL((locate_kernel<uint32_t, 256>), grid, dim3(256), 0, s, a, cmat);
+        else hipLaunchKernelGGL((locate_kernel<uint64_t, 256>), grid, dim3(256), 0, s, a, cmat);
+    }
     return hipGetLastError();
 }
 

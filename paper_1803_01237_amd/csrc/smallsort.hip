@@ -1,0 +1,368 @@
+// Segmented stable sort by MSD splitting plus on-chip finishing.
+//
+//   1. one counting pass on the top 8 bits of the key (count / scan / scatter
+//      of radix.hip) moves every segment into 256 sub-buckets, in the
+//      temporary buffer; the scan records each sub-bucket's start and length
+//   2. one workgroup per sub-bucket of at most kCap keys loads it into LDS
+//      and sorts it there by the remaining bits, then writes it to the output:
+//        - a stable counting pass on the next 8 bits splits it into groups;
+//        - when no group exceeds kGroupMax keys, each key's place inside its
+//          group is counted directly (keys smaller, or equal and earlier);
+//        - otherwise LSD counting passes over the remaining digits run in LDS,
+//          skipping digits on which all keys of the sub-bucket agree
+//   3. sub-buckets larger than kCap are collected into a compact list and go
+//      through LSD counting passes in HBM (radix.hip, list mode)
+// Every step is stable, so equal keys keep their input order.
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace hss {
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kW = kT / kWave;               // waves per workgroup
+constexpr int kCap = 2048;                   // largest sub-bucket sorted in LDS
+constexpr int kRows = kCap / kT;             // rows of 64 keys per wave at kCap
+constexpr uint32_t kGroupMax = 32;           // largest group ranked by direct counting
+
+template <typename K>
+__device__ __forceinline__ uint32_t dig(K k, int shift) {
+    return (uint32_t)(k >> shift) & 0xFFu;
+}
+
+// Stable counting pass in LDS: the n keys of `sk` (with indices `si`, or the
+// identity when null) are placed by their digit at `shift` into `dk` / `di`.
+// Leaves the digit starts in start[0..256] and the largest digit count in
+// *max_count.  Wave w handles the keys [w*cw, (w+1)*cw) in rows of 64.
+template <typename K>
+__device__ void lds_pass(const K* sk, const uint16_t* si, K* dk, uint16_t* di, uint32_t n,
+                         int shift, uint32_t (*whist)[256], uint32_t* start, uint32_t* scratch,
+                         uint32_t* max_count) {
+    const uint32_t cw = ((n + kW * kWave - 1) / (kW * kWave)) * kWave;
+    const uint32_t rows = cw / kWave;
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    for (int i = threadIdx.x; i < kW * 256; i += kT) (&whist[0][0])[i] = 0;
+    if (threadIdx.x == 0) *max_count = 0;
+    __syncthreads();
+    uint32_t rank[kRows];
+    uint32_t dg[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        rank[r] = 0;
+        dg[r] = 0;
+        if ((uint32_t)r < rows) {      // uniform over the wave
+            const uint32_t idx = w * cw + r * kWave + lane;
+            const bool valid = idx < n;
+            const uint32_t d = valid ? dig(sk[idx], shift) : 0u;
+            const uint64_t live = __ballot(valid);
+            const uint64_t m = match_byte(d, live);
+            const int leader = valid ? (int)(__ffsll((unsigned long long)m) - 1) : (int)lane;
+            uint32_t old = 0;
+            if (valid && (int)lane == leader) {
+                old = whist[w][d];
+                whist[w][d] = old + (uint32_t)__popcll(m);
+            }
+            old = __shfl(old, leader);
+            rank[r] = old + (uint32_t)__popcll(m & lanes_below_mask());
+            dg[r] = d;
+        }
+    }
+    __syncthreads();
+    {
+        const uint32_t d = threadIdx.x;
+        uint32_t c = 0;
+#pragma unroll
+        for (int ww = 0; ww < kW; ++ww) {
+            const uint32_t t = whist[ww][d];
+            whist[ww][d] = c;
+            c += t;
+        }
+        uint32_t all;
+        start[d] = block_exclusive_scan<uint32_t, kT>(c, scratch, &all);
+        if (d == 0) start[256] = all;
+        if (c) atomicMax(max_count, c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        if ((uint32_t)r < rows) {
+            const uint32_t idx = w * cw + r * kWave + lane;
+            if (idx < n) {
+                const uint32_t pos = start[dg[r]] + whist[w][dg[r]] + rank[r];
+                dk[pos] = sk[idx];
+                di[pos] = si ? si[idx] : (uint16_t)idx;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <typename K, bool kPayload>
+__global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ kin,
+                                                        const uint64_t* __restrict__ vin,
+                                                        K* __restrict__ kout,
+                                                        uint64_t* __restrict__ vout,
+                                                        const uint64_t* __restrict__ sb_start,
+                                                        const uint32_t* __restrict__ sb_len,
+                                                        int uniform_bits,
+                                                        const uint8_t* __restrict__ seg_shift,
+                                                        OversizeList ov) {
+    __shared__ K A[kCap];
+    __shared__ K Bk[kCap];
+    __shared__ uint16_t Ai[kCap];
+    __shared__ uint16_t Bi[kCap];
+    __shared__ uint32_t whist[kW][256];
+    __shared__ uint32_t start[257];
+    __shared__ uint32_t scratch[kW];
+    __shared__ uint32_t max_count;
+    __shared__ uint32_t diff_lo, diff_hi;
+
+    const uint64_t base = sb_start[blockIdx.x];
+    const uint32_t n = sb_len[blockIdx.x];
+    // keys of this sub-bucket agree on every bit at or above `bits`
+    const int bits = seg_shift ? (int)seg_shift[blockIdx.x / 256] : uniform_bits;
+    if (n == 0) return;
+    if (n > (uint32_t)kCap) {
+        if (threadIdx.x == 0) {
+            const uint32_t e = atomicAdd(ov.count, 1u);
+            ov.beg[e] = base;
+            ov.end[e] = base + n;
+        }
+        return;
+    }
+    if (n == 1) {
+        if (threadIdx.x == 0) {
+            kout[base] = kin[base];
+            if constexpr (kPayload) vout[base] = vin[base];
+        }
+        return;
+    }
+    // groups by the 8 bits below `bits` (or the lowest 8 bits)
+    const int shift2 = bits >= 8 ? bits - 8 : 0;
+    uint32_t* hist = &whist[0][0];
+    uint32_t* cursor = &whist[1][0];
+    hist[threadIdx.x] = 0;
+    if (threadIdx.x == 0) max_count = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += kT) {
+        const K k = kin[base + i];
+        A[i] = k;
+        atomicAdd(&hist[dig(k, shift2)], 1u);
+    }
+    __syncthreads();
+    {
+        const uint32_t c = hist[threadIdx.x];
+        uint32_t all;
+        const uint32_t st = block_exclusive_scan<uint32_t, kT>(c, scratch, &all);
+        start[threadIdx.x] = st;
+        cursor[threadIdx.x] = st;
+        if (threadIdx.x == 0) start[256] = all;
+        if (c) atomicMax(&max_count, c);
+    }
+    __syncthreads();
+    const K* fk = A;
+    const uint16_t* fi = Ai;
+    if (max_count <= kGroupMax) {
+        // place keys in their group in any order, then count each key's rank
+        // inside the group by (key, input index): stable by construction
+        for (uint32_t i = threadIdx.x; i < n; i += kT) {
+            const K k = A[i];
+            const uint32_t pos = atomicAdd(&cursor[dig(k, shift2)], 1u);
+            Bk[pos] = k;
+            Bi[pos] = (uint16_t)i;
+        }
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < n; e += kT) {
+            const K k = Bk[e];
+            const uint16_t ie = Bi[e];
+            const uint32_t d = dig(k, shift2);
+            const uint32_t g0 = start[d], g1 = start[d + 1];
+            uint32_t r = 0;
+            for (uint32_t j = g0; j < g1; ++j) {
+                const K x = Bk[j];
+                r += (x < k || (x == k && Bi[j] < ie)) ? 1u : 0u;
+            }
+            A[g0 + r] = k;
+            Ai[g0 + r] = ie;
+        }
+        __syncthreads();
+    } else {
+        // LSD in LDS over the digits below the top one that actually vary
+        if (threadIdx.x == 0) { diff_lo = 0; diff_hi = 0; }
+        __syncthreads();
+        {
+            const uint64_t k0 = (uint64_t)A[0];
+            uint64_t acc = 0;
+            for (uint32_t i = threadIdx.x; i < n; i += kT) acc |= (uint64_t)A[i] ^ k0;
+            if (acc) {
+                atomicOr(&diff_lo, (uint32_t)acc);
+                atomicOr(&diff_hi, (uint32_t)(acc >> 32));
+            }
+        }
+        __syncthreads();
+        const uint64_t diff = ((uint64_t)diff_hi << 32) | diff_lo;
+        const K* sk = A;
+        const uint16_t* si = nullptr;
+        K* dk = Bk;
+        uint16_t* di = Bi;
+        for (int sh = 0; sh < bits; sh += 8) {
+            if (((diff >> sh) & 0xFFu) == 0) continue;   // uniform digit: order unchanged
+            lds_pass<K>(sk, si, dk, di, n, sh, whist, start, scratch, &max_count);
+            // the pass output becomes the next input; the buffer pair (keys,
+            // indices) it read from becomes the next output
+            K* old = (K*)sk;
+            sk = dk;
+            si = di;
+            dk = old;
+            di = old == A ? Ai : Bi;
+        }
+        if (si == nullptr) {   // every digit uniform: input order is sorted
+            for (uint32_t i = threadIdx.x; i < n; i += kT) Ai[i] = (uint16_t)i;
+            __syncthreads();
+            si = Ai;
+        }
+        fk = sk;
+        fi = si;
+    }
+    for (uint32_t i = threadIdx.x; i < n; i += kT) {
+        kout[base + i] = fk[i];
+        if constexpr (kPayload) vout[base + i] = vin[base + fi[i]];
+    }
+}
+
+// One workgroup: tile offsets of the oversize list.
+__global__ __launch_bounds__(1024) void ov_tiles_kernel(OversizeList ov) {
+    __shared__ uint32_t scratch[1024 / kWave];
+    const uint32_t E = *ov.count;
+    uint32_t run = 0;
+    for (uint32_t c = 0; c < E; c += 1024) {
+        const uint32_t e = c + threadIdx.x;
+        const uint32_t nt = e < E ? (uint32_t)((ov.end[e] - ov.beg[e] + kSortTile - 1) / kSortTile) : 0u;
+        uint32_t tot;
+        const uint32_t pre = block_exclusive_scan<uint32_t, 1024>(nt, scratch, &tot);
+        if (e < E) ov.tile0[e] = run + pre;
+        run += tot;
+    }
+    if (threadIdx.x == 0) {
+        ov.tile0[E] = run;
+        *ov.tiles = run;
+    }
+}
+
+__global__ void ov_fill_kernel(OversizeList ov) {
+    const uint32_t E = *ov.count;
+    for (uint32_t e = blockIdx.x; e < E; e += gridDim.x) {
+        const uint32_t t0 = ov.tile0[e], t1 = ov.tile0[e + 1];
+        for (uint32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) ov.tile_seg[t] = e;
+    }
+}
+
+__global__ void ov_reset_kernel(OversizeList ov) {
+    *ov.count = 0;
+    *ov.tiles = 0;
+}
+
+}  // namespace
+
+hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
+    const uint32_t tps = (uint32_t)((a.max_seg_len + kSortTile - 1) / kSortTile);
+    if (a.num_segs == 0 || tps == 0) return hipSuccess;
+    const int kb = a.key_bytes * 8;
+    const int bits = kb - 8;             // bits below the top digit
+    Profiler dummy;
+    Profiler& prof = a.prof ? *a.prof : dummy;
+    const bool pay = a.vals_in != nullptr;
+
+    hipLaunchKernelGGL(ov_reset_kernel, dim3(1), dim3(1), 0, s, a.ov);
+    // 1. MSD pass into the temporary buffer
+    RadixPass ps;
+    ps.key_bytes = a.key_bytes;
+    ps.keys_in = a.keys_in;
+    ps.vals_in = a.vals_in;
+    ps.keys_out = a.keys_tmp;
+    ps.vals_out = a.vals_tmp;
+    ps.map.beg = a.seg_off;
+    ps.map.end = a.seg_off + 1;
+    ps.map.tps = tps;
+    ps.num_segs = a.num_segs;
+    ps.num_tiles = a.num_segs * tps;
+    ps.shift = bits;
+    ps.seg_shift = a.seg_shift;
+    ps.counts = a.counts;
+    ps.sb_start = a.sb_start;
+    ps.sb_len = a.sb_len;
+    ps.total_len = a.total_len;
+    ps.prof = a.prof;
+    hipError_t e = radix_pass(ps, s);
+    if (e != hipSuccess) return e;
+    // 2. sub-buckets in LDS
+    const dim3 grid(a.num_segs * 256u);
+    prof.begin(s);
+    if (a.key_bytes == 4) {
+        if (pay) hipLaunchKernelGGL((small_sort_kernel<uint32_t, true>), grid, dim3(kT), 0, s, (const uint32_t*)a.keys_tmp, a.vals_tmp, (uint32_t*)a.keys_out, a.vals_out, a.sb_start, a.sb_len, bits, a.seg_shift, a.ov);
+        else hipLaunchKernelGGL((small_sort_kernel<uint32_t, false>), grid, dim3(kT), 0, s, (const uint32_t*)a.keys_tmp, nullptr, (uint32_t*)a.keys_out, nullptr, a.sb_start, a.sb_len, bits, a.seg_shift, a.ov);
+    } else {
+        if (pay) hipLaunchKernelGGL((small_sort_kernel<uint64_t, true>), grid, dim3(kT), 0, s, (const uint64_t*)a.keys_tmp, a.vals_tmp, (uint64_t*)a.keys_out, a.vals_out, a.sb_start, a.sb_len, bits, a.seg_shift, a.ov);
+        else hipLaunchKernelGGL((small_sort_kernel<uint64_t, false>), grid, dim3(kT), 0, s, (const uint64_t*)a.keys_tmp, nullptr, (uint64_t*)a.keys_out, nullptr, a.sb_start, a.sb_len, bits, a.seg_shift, a.ov);
+    }
+    prof.end(kProfSmallSort, s, a.total_len * 2 * (a.key_bytes + (pay ? 8 : 0)));
+    // 3. oversize sub-buckets: LSD passes in HBM over a compact list
+    hipLaunchKernelGGL(ov_tiles_kernel, dim3(1), dim3(1024), 0, s, a.ov);
+    hipLaunchKernelGGL(ov_fill_kernel, dim3(1024), dim3(256), 0, s, a.ov);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(host.pinned, a.ov.count, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host.pinned + 1, a.ov.tiles, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    const uint32_t E = host.pinned[0], T = host.pinned[1];
+    host.last_oversize = E;
+    if (E == 0) return hipSuccess;
+    const uint64_t words = (uint64_t)T * 256;
+    if (words > host.fb_words) {
+        if (host.fb_counts) (void)hipFree(host.fb_counts);
+        host.fb_counts = nullptr;
+        host.fb_words = 0;
+        e = hipMalloc((void**)&host.fb_counts, words * 4);
+        if (e != hipSuccess) return e;
+        host.fb_words = words;
+    }
+    RadixPass fb;
+    fb.key_bytes = a.key_bytes;
+    fb.map.beg = a.ov.beg;
+    fb.map.end = a.ov.end;
+    fb.map.tile_seg = a.ov.tile_seg;
+    fb.map.tile0 = a.ov.tile0;
+    fb.num_segs = E;
+    fb.num_tiles = T;
+    fb.counts = host.fb_counts;
+    fb.total_len = 0;
+    fb.prof = a.prof;
+    const int passes = (bits + 7) / 8;   // odd for 32- and 64-bit keys: ends in keys_out
+    for (int i = 0; i < passes; ++i) {
+        const bool from_tmp = (i % 2) == 0;
+        fb.keys_in = from_tmp ? a.keys_tmp : a.keys_out;
+        fb.vals_in = from_tmp ? a.vals_tmp : a.vals_out;
+        fb.keys_out = from_tmp ? a.keys_out : a.keys_tmp;
+        fb.vals_out = from_tmp ? a.vals_out : a.vals_tmp;
+        if (!pay) { fb.vals_in = nullptr; fb.vals_out = nullptr; }
+        fb.shift = 8 * i;
+        e = radix_pass(fb, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+uint64_t oversize_capacity(uint32_t num_segs, uint64_t total_len) {
+    const uint64_t by_count = (uint64_t)num_segs * 256;
+    const uint64_t by_size = total_len / (kCap + 1) + 1;
+    return by_count < by_size ? by_count : by_size;
+}
+
+uint64_t oversize_tile_capacity(uint32_t num_segs, uint64_t total_len) {
+    return total_len / kSortTile + oversize_capacity(num_segs, total_len) + 1;
+}
+
+}  // namespace hss

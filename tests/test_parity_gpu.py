@@ -189,3 +189,85 @@ def test_plan_reuse_and_seeds(hss):
             assert np.array_equal(_host(ko, np.uint64), ref.keys)
             assert np.array_equal(_host(vo, np.uint64), ref.vals)
             assert len(plan.trace()) == len(ref.rounds)
+
+
+SORT_CASES = [
+    # kind, n, p, note
+    ("uniform64", 1 << 20, 64, "on-chip fast path"),
+    ("SKEW2", 100_000, 64, "segments <= cap, one big group: LDS slow path"),
+    ("SKEW2", 300_000, 16, "top byte constant: HBM fallback"),
+    ("ALLZEROS", 50_000, 7, "all equal"),
+    ("GAUSS", 60_000, 40, "few top bytes"),
+    ("SKEW3", 90_000, 30, "biased bits"),
+    ("zipf_morton", 500_000, 64, "mixed"),
+    ("uniform32", 1 << 18, 32, "32-bit keys"),
+]
+
+
+@pytest.mark.parametrize("lsd_only", [False, True])
+@pytest.mark.parametrize("case", SORT_CASES, ids=[c[3] for c in SORT_CASES])
+def test_local_sort_paths(hss, case, lsd_only):
+    kind, n, p, _ = case
+    _say(f"[local sort] {kind} n={n} p={p} lsd_only={lsd_only}")
+    keys = synth.make(kind, n, 21)
+    if kind == "uniform32":
+        keys = keys.astype(np.uint32)
+    vals = np.arange(n, dtype=np.uint64)
+    with hss.Plan(n, p, 0.05, key_bytes=keys.itemsize, payload=True, lsd_only=lsd_only) as plan:
+        lk, lv = plan.local_sort(_dev(keys), _dev(vals))
+        ok_, ov_ = oracle.local_sort(keys, p, vals)
+        assert np.array_equal(_host(lk, keys.dtype), ok_)
+        assert np.array_equal(_host(lv, np.uint64), ov_)
+        ks, vs, _ = plan.sort(_dev(keys), 5, _dev(vals))
+        order = np.argsort(keys, kind="stable")
+        assert np.array_equal(_host(ks, keys.dtype), keys[order])
+        assert np.array_equal(_host(vs, np.uint64), vals[order])
+
+
+@pytest.mark.parametrize("size", [2047, 2048, 2049, 4096, 33, 32])
+def test_local_sort_sub_bucket_boundaries(hss, size):
+    """One segment whose top byte puts exactly `size` keys in one sub-bucket,
+    with the rest spread out; duplicates inside the sub-bucket."""
+    rng = np.random.default_rng(size)
+    n, p = 1 << 15, 4
+    keys = rng.integers(0, 2**64, size=n, dtype=np.uint64)
+    seg = n // p
+    # no other key of segment 0 in the hot sub-bucket
+    top = keys[:seg] >> np.uint64(56)
+    keys[:seg][top == np.uint64(0xAB)] ^= np.uint64(1 << 56)
+    idx = rng.choice(seg, size=size, replace=False)
+    # hot keys share the top two bytes: one sub-bucket, one group, duplicates
+    hot = (np.uint64(0xAB) << np.uint64(56)) | rng.integers(0, 1 << 10, size=size, dtype=np.uint64)
+    keys[idx] = hot
+    vals = np.arange(n, dtype=np.uint64)
+    _say(f"[local sort] sub-bucket of {size} keys")
+    with hss.Plan(n, p, 0.05, payload=True) as plan:
+        lk, lv = plan.local_sort(_dev(keys), _dev(vals))
+        ok_, ov_ = oracle.local_sort(keys, p, vals)
+        assert np.array_equal(_host(lk, np.uint64), ok_)
+        assert np.array_equal(_host(lv, np.uint64), ov_)
+
+
+@pytest.mark.parametrize("n,p", [(1 << 22, 16), (1 << 21, 8), (1 << 23, 1024)])
+def test_local_sort_large_segments(hss, n, p):
+    """Segments of 2^18 keys: sub-buckets of about 1024 keys, as at full size."""
+    _say(f"[local sort] uniform n={n} p={p}")
+    keys = synth.uniform64(n, 77)
+    with hss.Plan(n, p, 0.02) as plan:
+        lk, _ = plan.local_sort(_dev(keys))
+        ok_, _ = oracle.local_sort(keys, p)
+        got = _host(lk, np.uint64)
+        bad = np.nonzero(got != ok_)[0]
+        assert len(bad) == 0, (len(bad), bad[:10])
+
+
+@pytest.mark.parametrize("n,p,eps", [(1 << 22, 16, 0.02), (1 << 23, 1024, 0.02)])
+def test_partition_large_segments(hss, n, p, eps):
+    _say(f"[parity] uniform n={n} p={p} eps={eps}")
+    keys = synth.uniform64(n, 78)
+    with hss.Plan(n, p, eps, trace_level=1) as plan:
+        ko, _, off = plan.partition(_dev(keys), 5)
+        ref = oracle.hss(keys, p, eps, 5)
+        _compare_trace(plan, ref, p)
+        assert np.array_equal(_host(off, np.uint64), ref.offsets)
+        assert np.array_equal(_host(ko, np.uint64), ref.keys)
