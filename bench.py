@@ -69,7 +69,23 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 25,
                     help="keys in the CPU oracle sample (0 to skip)")
     ap.add_argument("--sort-steps", type=int, default=3, help="hss_sort steps timed for context")
+    ap.add_argument("--op", default="partition", choices=["partition", "sort"],
+                    help="operation timed as the step (the headline is partition)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device-to-device copy of 2 GiB (HBM counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        src = torch.empty(1 << 28, dtype=torch.int64, device="cuda:0")
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": src.numel() * 8,
+                          "dispatches": 3}), flush=True)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -93,8 +109,9 @@ def main():
 
     plan = hss.Plan(n, p, eps, key_bytes=8, payload=payload)
     log(f"[bench] workspace {plan.workspace_bytes / 2**30:.2f} GiB; warmup {args.warmup}")
+    step = plan.partition if args.op == "partition" else plan.sort
     for _ in range(args.warmup):
-        plan.partition(keys, hseed, vals, kout, vout, off)
+        step(keys, hseed, vals, kout, vout, off)
     torch.cuda.synchronize()
 
     plan.profile(True)
@@ -103,7 +120,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        plan.partition(keys, hseed, vals, kout, vout, off)
+        step(keys, hseed, vals, kout, vout, off)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = plan.profile_read()
@@ -158,7 +175,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "p": p, "eps": eps,
-                   "payload": payload, "op": "hss_partition", "seed": hseed},
+                   "payload": payload, "op": "hss_" + args.op, "seed": hseed},
         "roofline": roof,
         "cpu_baseline": cpu,
         "stages": stages,

@@ -115,23 +115,24 @@ __global__ __launch_bounds__(kT) void exchange_copy_kernel(ExchangeArgs a, uint3
 }
 
 __global__ void bucket_shift_kernel(uint32_t p, int key_bits, const uint64_t* __restrict__ s_key,
-                                    uint8_t* __restrict__ shift) {
+                                    uint8_t* __restrict__ shift, uint64_t* __restrict__ base) {
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= p) return;
     const uint64_t top = key_bits == 64 ? ~0ull : 0xFFFFFFFFull;
     const uint64_t lo = b == 0 ? 0 : s_key[b];
     const uint64_t hi = b + 1 == p ? top : s_key[b + 1];
-    const uint64_t x = lo ^ hi;
-    const int h = x ? 63 - __clzll((long long)x) : 0;   // highest differing bit
-    shift[b] = (uint8_t)(h >= 7 ? h - 7 : 0);
+    const uint64_t w = hi - lo;                           // offsets lie in [0, w]
+    const int len = w ? 64 - __clzll((long long)w) : 0;   // bits of w
+    shift[b] = (uint8_t)(len > 8 ? len - 8 : 0);
+    base[b] = lo;
 }
 
 }  // namespace
 
 hipError_t launch_bucket_shift(uint32_t p, int key_bits, const uint64_t* s_key, uint8_t* shift,
-                               hipStream_t s) {
+                               uint64_t* base, hipStream_t s) {
     hipLaunchKernelGGL(bucket_shift_kernel, dim3((p + 255) / 256), dim3(256), 0, s, p, key_bits,
-                       s_key, shift);
+                       s_key, shift, base);
     return hipGetLastError();
 }
 

@@ -104,11 +104,14 @@ struct hss_plan_s {
     uint32_t* cmat = nullptr;
     uint64_t cmat_words = 0;
     uint8_t* bucket_shift = nullptr;
+    uint64_t* bucket_base = nullptr;
+    Fences fences;                    // of B, written by the local sort of hss_partition/hss_sort
 
     // hybrid sort state
     uint64_t* sb_start = nullptr;
     uint32_t* sb_len = nullptr;
     OversizeList ov;
+    SlowList sl;
     HybridHost hh;
 };
 
@@ -169,7 +172,10 @@ size_t layout(hss_plan_s& P, char* base) {
     r.req_kind = ar.take<uint32_t>(2 * p);
     r.ctr = ar.take<RoundCounters>(1);
     P.dst = r.ivl_blk;   // the exchange runs after the last round
+    P.fences.per_seg = (P.max_seg + kFenceStride - 1) / kFenceStride;
+    P.fences.key = ar.take<uint64_t>(p * P.fences.per_seg);
     P.bucket_shift = ar.take<uint8_t>(p);
+    P.bucket_base = ar.take<uint64_t>(p);
     P.sb_start = ar.take<uint64_t>(p * 256);
     P.sb_len = ar.take<uint32_t>(p * 256);
     const uint64_t ovc = oversize_capacity((uint32_t)p, n);
@@ -177,8 +183,17 @@ size_t layout(hss_plan_s& P, char* base) {
     P.ov.tiles = ar.take<uint32_t>(1);
     P.ov.beg = ar.take<uint64_t>(ovc);
     P.ov.end = ar.take<uint64_t>(ovc);
+    P.ov.base = ar.take<uint64_t>(ovc);
+    P.ov.seg = ar.take<uint32_t>(ovc);
     P.ov.tile0 = ar.take<uint32_t>(ovc + 1);
     P.ov.tile_seg = ar.take<uint32_t>(oversize_tile_capacity((uint32_t)p, n));
+    const uint64_t slc = slow_capacity((uint32_t)p, n);
+    P.sl.count = ar.take<uint32_t>(1);
+    P.sl.beg = ar.take<uint64_t>(slc);
+    P.sl.len = ar.take<uint32_t>(slc);
+    P.sl.bits = ar.take<uint8_t>(slc);
+    P.sl.base = ar.take<uint64_t>(slc);
+    P.sl.seg = ar.take<uint32_t>(slc);
     return ar.used;
 }
 
@@ -192,7 +207,7 @@ hss_status grow_probes(hss_plan_s& P, uint64_t need) {
     ar.base = nullptr;
     ar.take<uint64_t>(cap); ar.take<uint64_t>(cap); ar.take<uint32_t>(cap);
     ar.take<uint64_t>(cap); ar.take<uint64_t>(cap); ar.take<uint32_t>(cap);
-    ar.take<uint64_t>(cap); ar.take<uint32_t>(cap);
+    ar.take<uint64_t>(cap); ar.take<uint32_t>(cap); ar.take<uint32_t>(cap);
     P.probe_bytes = ar.used + 256;
     HIP_TRY(hipMalloc(&P.probe_mem, P.probe_bytes));
     ar.base = (char*)P.probe_mem;
@@ -206,6 +221,7 @@ hss_status grow_probes(hss_plan_s& P, uint64_t need) {
     r.ps_ivl = ar.take<uint32_t>(cap);
     r.pr_rank = ar.take<uint64_t>(cap);
     r.pr_pos = ar.take<uint32_t>(cap);
+    r.ps_seg = ar.take<uint32_t>(cap);
     r.cap = cap;
     P.cap = cap;
     return HSS_OK;
@@ -263,7 +279,8 @@ hss_status d2h(std::vector<T>& v, const T* d, size_t count, hipStream_t s) {
 // segments, or the p buckets after the exchange).
 hss_status segment_sort(hss_plan_s& P, const void* kin, const uint64_t* vin, void* kout,
                         uint64_t* vout, void* ktmp, uint64_t* vtmp, const uint64_t* seg_off,
-                        uint64_t max_len, const uint8_t* seg_shift, hipStream_t s) {
+                        uint64_t max_len, const uint8_t* seg_shift, const uint64_t* seg_base,
+                        const Fences* fences, hipStream_t s) {
     if (P.tune.lsd_only) {
         SegSort ss;
         ss.key_bytes = P.key_bytes;
@@ -300,7 +317,10 @@ hss_status segment_sort(hss_plan_s& P, const void* kin, const uint64_t* vin, voi
     hs.sb_start = P.sb_start;
     hs.sb_len = P.sb_len;
     hs.seg_shift = seg_shift;
+    hs.seg_base = seg_base;
+    if (fences) hs.fences = *fences;
     hs.ov = P.ov;
+    hs.sl = P.sl;
     hs.prof = &P.prof;
     HIP_TRY(hybrid_sort(hs, s, P.hh));
     return HSS_OK;
@@ -308,7 +328,8 @@ hss_status segment_sort(hss_plan_s& P, const void* kin, const uint64_t* vin, voi
 
 hss_status local_sort(hss_plan_s& P, const void* kin, const uint64_t* vin, void* kout,
                       uint64_t* vout, void* ktmp, uint64_t* vtmp, hipStream_t s) {
-    return segment_sort(P, kin, vin, kout, vout, ktmp, vtmp, P.seg_off, P.max_seg, nullptr, s);
+    return segment_sort(P, kin, vin, kout, vout, ktmp, vtmp, P.seg_off, P.max_seg, nullptr,
+                        nullptr, nullptr, s);
 }
 
 // Splitter rounds on the locally sorted buffer P.B; leaves chi in d_offsets.
@@ -359,9 +380,10 @@ hss_status determine_splitters(hss_plan_s& P, uint64_t seed, uint64_t* d_offsets
             }
             if (P.cmat) cmat = P.cmat;
         }
-        HIP_TRY(launch_rank(r, m, cmat, s));
+        const Fences none;
+        HIP_TRY(launch_rank(r, m, cmat, P.tune.lsd_only ? none : P.fences, P.max_seg, s));
         HIP_TRY(launch_settle(r, m, s));
-        HIP_TRY(launch_locate(r, cmat, s));
+        HIP_TRY(launch_locate(r, cmat, m, s));
         RoundRecord rec;
         rec.domain = c.domain;
         rec.m = m;
@@ -398,8 +420,9 @@ hss_status run(hss_plan_s* P, uint64_t seed, const void* kin, const uint64_t* vi
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(P->device));
     HIP_TRY(hipMemsetAsync(P->ra.ctr, 0, sizeof(RoundCounters), s));
-    // phase 1: local sort of every segment into B
-    st = local_sort(*P, kin, vin, P->B, P->Bv, P->A, P->Av, s);
+    // phase 1: local sort of every segment into B, with its fences
+    st = segment_sort(*P, kin, vin, P->B, P->Bv, P->A, P->Av, P->seg_off, P->max_seg, nullptr,
+                      nullptr, P->tune.lsd_only ? nullptr : &P->fences, s);
     if (st != HSS_OK) return st;
     // phase 2: splitter rounds
     if (P->p == 1) {
@@ -433,12 +456,15 @@ hss_status run(hss_plan_s* P, uint64_t seed, const void* kin, const uint64_t* vi
     // phase 4 (sort only): stable sort of every bucket
     if (sort_buckets) {
         const uint8_t* shifts = nullptr;
+        const uint64_t* bases = nullptr;
         if (P->p > 1) {
-            HIP_TRY(launch_bucket_shift(P->p, P->key_bytes * 8, P->ra.s_key, P->bucket_shift, s));
+            HIP_TRY(launch_bucket_shift(P->p, P->key_bytes * 8, P->ra.s_key, P->bucket_shift,
+                                        P->bucket_base, s));
             shifts = P->bucket_shift;
+            bases = P->bucket_base;
         }
         st = segment_sort(*P, P->A, P->Av, kout, vout, P->B, P->Bv, d_offsets, P->max_bucket,
-                          shifts, s);
+                          shifts, bases, nullptr, s);
         if (st != HSS_OK) return st;
     }
     // the exchange checks that every bucket's pieces add up to its size

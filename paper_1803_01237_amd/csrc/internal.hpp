@@ -121,6 +121,8 @@ constexpr int kSortTile = kSortThreads * kSortItems;   // keys per workgroup til
 struct TileMap {
     const uint64_t* beg = nullptr;
     const uint64_t* end = nullptr;
+    // optional per-segment key offset: digits are taken from key - base[s]
+    const uint64_t* base = nullptr;
     const uint32_t* tile_seg = nullptr;
     const uint32_t* tile0 = nullptr;
     uint32_t tps = 0;
@@ -149,6 +151,18 @@ uint64_t radix_count_words(uint32_t num_segs, uint64_t max_seg_len);
 hipError_t radix_pass(const RadixPass& a, hipStream_t stream);
 hipError_t segmented_radix_sort(const SegSort& a, hipStream_t stream);
 
+// --------------------------------------------------------------- fences ----
+// Every kFenceStride-th key of each locally sorted segment, kept so that a
+// search inside a segment can start from on-chip fences and finish inside
+// one cache line: key[s * per_seg + f] = key at position f * kFenceStride of
+// segment s (widened to 64 bits).
+constexpr int kFenceStride = 16;
+
+struct Fences {
+    uint64_t* key = nullptr;
+    uint64_t per_seg = 0;              // ceil(max segment length / kFenceStride)
+};
+
 // ---------------------------------------------------------- hybrid sort ----
 // Sub-buckets too large for LDS, collected on the device.
 struct OversizeList {
@@ -156,8 +170,21 @@ struct OversizeList {
     uint32_t* tiles = nullptr;         // total tiles
     uint64_t* beg = nullptr;           // capacity oversize_capacity()
     uint64_t* end = nullptr;
+    uint64_t* base = nullptr;          // key offset of the entry's segment
+    uint32_t* seg = nullptr;           // segment of the entry
     uint32_t* tile0 = nullptr;         // capacity + 1
     uint32_t* tile_seg = nullptr;      // oversize_tile_capacity()
+};
+
+// Sub-buckets that fit LDS but hold a large group of keys equal in their
+// next 8 bits, collected on the device for the LDS-LSD kernel.
+struct SlowList {
+    uint32_t* count = nullptr;
+    uint64_t* beg = nullptr;           // capacity slow_capacity()
+    uint32_t* len = nullptr;
+    uint8_t* bits = nullptr;           // bits of key - base below which keys still differ
+    uint64_t* base = nullptr;          // key offset of the entry's segment
+    uint32_t* seg = nullptr;           // segment of the entry
 };
 
 // Stable sort of contiguous segments [seg_off[s], seg_off[s+1]): an MSD pass
@@ -178,25 +205,31 @@ struct HybridSort {
     uint32_t* counts = nullptr;        // >= radix_count_words(num_segs, max_seg_len)
     uint64_t* sb_start = nullptr;      // num_segs * 256
     uint32_t* sb_len = nullptr;        // num_segs * 256
-    // optional per-segment MSD digit shift: all keys of segment s must agree
-    // on the bits above seg_shift[s] + 8 (nullptr: the top digit)
+    // optional per-segment MSD digit: every key k of segment s must satisfy
+    // 0 <= k - seg_base[s] < 2^(seg_shift[s] + 8); the MSD digit is then
+    // (k - seg_base[s]) >> seg_shift[s].  nullptr: base 0, the top digit.
     const uint8_t* seg_shift = nullptr;
+    const uint64_t* seg_base = nullptr;
     OversizeList ov;
+    SlowList sl;
+    Fences fences;                     // optional: written for the sorted output
     Profiler* prof = nullptr;
 };
 
 // Host-side state of the hybrid sort: pinned read-back words and the count
 // table of the oversize passes, grown on demand.
 struct HybridHost {
-    uint32_t* pinned = nullptr;        // 2 words
+    uint32_t* pinned = nullptr;        // 3 words
     uint32_t* fb_counts = nullptr;
     uint64_t fb_words = 0;
     uint32_t last_oversize = 0;
+    uint32_t last_slow = 0;
 };
 
 hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host);
 uint64_t oversize_capacity(uint32_t num_segs, uint64_t total_len);
 uint64_t oversize_tile_capacity(uint32_t num_segs, uint64_t total_len);
+uint64_t slow_capacity(uint32_t num_segs, uint64_t total_len);
 
 // --------------------------------------------------------------- rounds ----
 // Device counters read back once per round.
@@ -249,6 +282,7 @@ struct RoundArgs {
     uint32_t* ps_ivl;
     uint64_t* pr_rank;             // rank R of sorted probe e
     uint32_t* pr_pos;              // sorted position of emitted probe
+    uint32_t* ps_seg;              // segment of sorted probe e
     // requests
     uint32_t* req_probe;
     uint32_t* req_row;
@@ -265,10 +299,14 @@ hipError_t launch_sample(const RoundArgs& a, uint64_t seed, uint32_t round, uint
 hipError_t launch_probe_sort(const RoundArgs& a, uint64_t m, void* scratch, size_t scratch_bytes,
                              uint32_t* counts, hipStream_t s);
 size_t probe_sort_scratch_bytes(uint64_t m);
-// cmat (optional, m x p words): per-probe segment counts kept for locate.
-hipError_t launch_rank(const RoundArgs& a, uint64_t m, uint32_t* cmat, hipStream_t s);
+// cmat (optional, p x m words, segment-major): c_s(e) at cmat[s * m + e],
+// kept for locate.  With fences (and cmat), the counts are found per
+// (segment, chunk) from on-chip fences; otherwise per probe by searching
+// every segment's slice.
+hipError_t launch_rank(const RoundArgs& a, uint64_t m, uint32_t* cmat, const Fences& fences,
+                       uint64_t max_seg, hipStream_t s);
 hipError_t launch_settle(const RoundArgs& a, uint64_t m, hipStream_t s);
-hipError_t launch_locate(const RoundArgs& a, const uint32_t* cmat, hipStream_t s);
+hipError_t launch_locate(const RoundArgs& a, const uint32_t* cmat, uint64_t m, hipStream_t s);
 hipError_t launch_finalize(const RoundArgs& a, uint64_t* d_offsets, hipStream_t s);
 
 // ------------------------------------------------------------- exchange ----
@@ -290,10 +328,11 @@ struct ExchangeArgs {
 };
 
 hipError_t launch_exchange(const ExchangeArgs& a, hipStream_t s);
-// Per-bucket MSD digit shift for the bucket sort: all keys of bucket b lie in
-// [key(S(b)), key(S(b+1))], so they agree on the bits above the highest bit
-// where those two keys differ.
+// Per-bucket MSD digit for the bucket sort: all keys of bucket b lie in
+// [lo, hi] = [key(S(b)), key(S(b+1))] (0 and the largest key at the ends), so
+// with base = lo the offsets key - lo fit below 2^(shift + 8) for the
+// smallest shift with hi - lo < 2^(shift + 8).
 hipError_t launch_bucket_shift(uint32_t p, int key_bits, const uint64_t* s_key, uint8_t* shift,
-                               hipStream_t s);
+                               uint64_t* base, hipStream_t s);
 
 }  // namespace hss

@@ -59,14 +59,22 @@ __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(const K* __re
     uint32_t seg;
     if (tile_range(m, blockIdx.x, &base, &e, &seg)) {
         if (seg_shift) shift = seg_shift[seg];
+        const K kb = m.base ? (K)m.base[seg] : (K)0;
         const uint32_t n_tile = (uint32_t)min((uint64_t)kSortTile, e - base);
         const uint32_t w = threadIdx.x / kWave;
         const uint32_t lane = lane_id();
-#pragma unroll 4
+        // all loads of the tile in flight before any ranking work
+        K kr[kSortItems];
+#pragma unroll
+        for (int r = 0; r < kSortItems; ++r) {
+            const uint32_t li = w * kKeysPerWave + r * kWave + lane;
+            kr[r] = li < n_tile ? keys[base + li] : (K)0;
+        }
+#pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
             const uint32_t li = w * kKeysPerWave + r * kWave + lane;
             const bool valid = li < n_tile;
-            const uint32_t d = valid ? digit_of(keys[base + li], shift) : 0u;
+            const uint32_t d = digit_of((K)(kr[r] - kb), shift);
             const uint64_t live = __ballot(valid);
             if (live == 0) break;
             const uint64_t mm = match_byte(d, live);
@@ -126,6 +134,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     uint32_t seg;
     if (!tile_range(m, blockIdx.x, &base, &e, &seg)) return;   // uniform over the workgroup
     if (seg_shift) shift = seg_shift[seg];
+    const K kb = m.base ? (K)m.base[seg] : (K)0;
     const uint64_t b = m.beg[seg];
     const uint32_t n_tile = (uint32_t)min((uint64_t)kSortTile, e - base);
     const uint32_t w = threadIdx.x / kWave;
@@ -142,7 +151,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         const uint32_t li = w * kKeysPerWave + r * kWave + lane;
         const bool valid = li < n_tile;
         key[r] = valid ? kin[base + li] : (K)0;
-        const uint32_t d = digit_of(key[r], shift);
+        const uint32_t d = digit_of((K)(key[r] - kb), shift);
         const uint64_t live = __ballot(valid);
         const uint64_t mm = match_byte(d, live);
         const int leader = valid ? (int)(__ffsll((unsigned long long)mm) - 1) : (int)lane;
@@ -172,7 +181,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
 #pragma unroll
     for (int r = 0; r < kSortItems; ++r) {
         const uint32_t li = w * kKeysPerWave + r * kWave + lane;
-        const uint32_t d = digit_of(key[r], shift);
+        const uint32_t d = digit_of((K)(key[r] - kb), shift);
         pos[r] = tstart[d] + whist[w][d] + rank[r];
         if (li < n_tile) {
             stage[pos[r]] = (uint64_t)key[r];

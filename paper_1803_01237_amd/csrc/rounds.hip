@@ -31,7 +31,7 @@ constexpr int kT = 256;           // threads of most round kernels
 constexpr int kRun = 8;           // consecutive Philox blocks per lane in the sampler
 constexpr int kSampleGrid = 4096; // workgroups of the grid-stride sampler
 constexpr uint64_t kCountSortMax = 32768;   // probe sort by pairwise counting up to here
-constexpr int kCountTile = 1024;
+constexpr int kCountTile = 256;
 
 __global__ void round_init_kernel(uint32_t p, uint32_t* settled, uint64_t* chi, uint64_t* lrank,
                                   uint64_t* urank, RoundCounters* ctr) {
@@ -263,15 +263,19 @@ __global__ __launch_bounds__(kT) void probe_count_kernel(const uint64_t* __restr
     if (c) atomicAdd(&pos[i], c);
 }
 
+__device__ __forceinline__ uint32_t segment_of(const uint64_t* seg_off, uint32_t p, uint64_t g);
+
 __global__ void probe_permute_kernel(RoundArgs a, uint64_t m, const uint64_t* order) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
          i += (uint64_t)gridDim.x * blockDim.x) {
         uint64_t src, dst;
         if (order) { src = order[i]; dst = i; }      // order[i] = emitted index of sorted i
         else { src = i; dst = a.pr_pos[i]; }          // pr_pos[i] = sorted index of emitted i
+        const uint64_t g = a.pr_tag[src];
         a.ps_key[dst] = a.pr_key[src];
-        a.ps_tag[dst] = a.pr_tag[src];
+        a.ps_tag[dst] = g;
         a.ps_ivl[dst] = a.pr_ivl[src];
+        a.ps_seg[dst] = segment_of(a.seg_off, a.p, g);
     }
 }
 
@@ -330,10 +334,98 @@ __global__ __launch_bounds__(kThreads) void rank_kernel(RoundArgs a, uint32_t* _
             c = count_before<K>(B + sb, lo, hi, key, s < t);
         }
         sum += c;
-        if (cmat) cmat[e * a.p + s] = (uint32_t)c;
+        if (cmat) cmat[(uint64_t)s * gridDim.x + e] = (uint32_t)c;
     }
     sum = block_sum<uint64_t, kThreads>(sum, scratch);
     if (threadIdx.x == 0) a.pr_rank[e] = sum;
+}
+
+constexpr uint32_t kRankChunk = 1u << 15;                  // keys of a segment per workgroup
+constexpr uint32_t kRankFences = kRankChunk / kFenceStride;  // their fences, held in LDS
+
+// (key_e, g_e) after (kx, gx) in the order (key, tag)?
+template <typename K>
+__device__ __forceinline__ bool after(K ke, uint64_t ge, K kx, uint64_t gx) {
+    return ke > kx || (ke == kx && ge > gx);
+}
+
+// Workgroup per (segment s, chunk c): the probes e whose count c_s(e) falls
+// in the chunk are the sorted run [e0, e1); each finds its place among the
+// chunk's fences in LDS, then inside one kFenceStride-key block of B.
+// Result: cmat[s * m + e] = c_s(e).
+template <typename K>
+__global__ __launch_bounds__(256) void rank_seg_kernel(RoundArgs a, uint64_t m,
+                                                       uint32_t chunks_per_seg, Fences fn,
+                                                       uint32_t* __restrict__ cmat) {
+    __shared__ uint64_t F[kRankFences];
+    __shared__ uint64_t sh_e[2];
+    const uint32_t s = blockIdx.x / chunks_per_seg;
+    const uint32_t c = blockIdx.x % chunks_per_seg;
+    const uint64_t sb = a.seg_off[s];
+    const uint64_t ns = a.seg_off[s + 1] - sb;
+    const uint32_t nchunks = ns == 0 ? 1u : (uint32_t)((ns + kRankChunk - 1) / kRankChunk);
+    if (c >= nchunks) return;
+    const bool last = c + 1 == nchunks;
+    const uint64_t lo_pos = (uint64_t)c * kRankChunk;
+    const uint64_t chunk_end = min(lo_pos + kRankChunk, ns);   // last element + 1 in the chunk
+    const K* B = (const K*)a.B + sb;
+    if (threadIdx.x < 2) {
+        // first probe with c_s(e) >= x; for x >= 1 that is the first probe
+        // after the element at position x - 1 of the segment
+        const uint64_t x = threadIdx.x == 0 ? lo_pos : chunk_end;
+        uint64_t r;
+        if (x == 0) {
+            r = 0;
+        } else if (threadIdx.x == 1 && last) {
+            r = m;
+        } else {
+            const K kx = B[x - 1];
+            const uint64_t gx = sb + x - 1;
+            uint64_t lo = 0, hi = m;
+            while (lo < hi) {
+                const uint64_t mid = (lo + hi) >> 1;
+                if (after<K>((K)a.ps_key[mid], a.ps_tag[mid], kx, gx)) hi = mid; else lo = mid + 1;
+            }
+            r = lo;
+        }
+        sh_e[threadIdx.x] = r;
+    }
+    __syncthreads();
+    const uint64_t e0 = sh_e[0], e1 = sh_e[1];
+    if (e0 >= e1) return;   // no probe counts into this chunk (uniform over the workgroup)
+    const uint32_t nf = (uint32_t)((chunk_end - lo_pos + kFenceStride - 1) / kFenceStride);
+    const uint64_t* fsrc = fn.key + (uint64_t)s * fn.per_seg + lo_pos / kFenceStride;
+    for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) F[i] = fsrc[i];
+    __syncthreads();
+    for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const K key = (K)a.ps_key[e];
+        const uint64_t g = a.ps_tag[e];
+        const uint32_t t = a.ps_seg[e];
+        uint64_t cnt;
+        if (t == s) {
+            cnt = g - sb;
+        } else {
+            // equal keys of earlier segments precede the probe, of later ones follow
+            const bool eqb = s < t;
+            uint32_t f0 = 0, f1 = nf;   // first fence that does not precede the probe
+            while (f0 < f1) {
+                const uint32_t mid = (f0 + f1) >> 1;
+                const K x = (K)F[mid];
+                if (eqb ? (x <= key) : (x < key)) f0 = mid + 1; else f1 = mid;
+            }
+            if (f0 == 0) {
+                cnt = lo_pos;
+            } else {
+                const uint64_t lo = lo_pos + (uint64_t)(f0 - 1) * kFenceStride + 1;
+                const uint64_t hi = f0 < nf ? lo_pos + (uint64_t)f0 * kFenceStride : chunk_end;
+                cnt = count_before<K>(B, lo, hi, key, eqb);
+            }
+        }
+        cmat[(uint64_t)s * m + e] = (uint32_t)cnt;
+        // the reduction of section 5.2: integer sums, so the order of the
+        // atomic additions does not change R(e)
+        atomicAdd((unsigned long long*)&a.pr_rank[e], (unsigned long long)cnt);
+    }
 }
 
 __device__ __forceinline__ void emit_request(const RoundArgs& a, uint32_t e, uint32_t row,
@@ -389,7 +481,8 @@ __global__ __launch_bounds__(kT) void settle_kernel(RoundArgs a, uint64_t m) {
 // copied from the rank step's count matrix or found by searching each segment.
 template <typename K, int kThreads>
 __global__ __launch_bounds__(kThreads) void locate_kernel(RoundArgs a,
-                                                          const uint32_t* __restrict__ cmat) {
+                                                          const uint32_t* __restrict__ cmat,
+                                                          uint64_t m) {
     __shared__ uint32_t sh_t;
     const uint32_t r = blockIdx.x;
     if (r >= a.ctr->n_req) return;
@@ -404,11 +497,10 @@ __global__ __launch_bounds__(kThreads) void locate_kernel(RoundArgs a,
     const K* B = (const K*)a.B;
     uint32_t* dst = kind == 0 ? a.lpos : (kind == 1 ? a.upos : a.prow);
     const uint32_t own = kind == 0 ? 1u : 0u;   // the L probe itself is excluded
-    const uint32_t* col = cmat ? cmat + (uint64_t)e * a.p : nullptr;
     for (uint32_t s = threadIdx.x; s < a.p; s += kThreads) {
         uint64_t c;
-        if (col) {
-            c = col[s];
+        if (cmat) {
+            c = cmat[(uint64_t)s * m + e];
         } else {
             const uint64_t sb = a.seg_off[s];
             c = s == t ? g - sb : count_before<K>(B + sb, 0, a.seg_off[s + 1] - sb, key, s < t);
@@ -514,8 +606,18 @@ hipError_t launch_probe_sort(const RoundArgs& a, uint64_t m, void* scratch, size
     return hipGetLastError();
 }
 
-hipError_t launch_rank(const RoundArgs& a, uint64_t m, uint32_t* cmat, hipStream_t s) {
+hipError_t launch_rank(const RoundArgs& a, uint64_t m, uint32_t* cmat, const Fences& fences,
+                       uint64_t max_seg, hipStream_t s) {
     if (m == 0) return hipSuccess;
+    if (cmat && fences.key) {
+        const uint32_t cps = max_seg == 0 ? 1u : (uint32_t)((max_seg + kRankChunk - 1) / kRankChunk);
+        const dim3 grid((unsigned)((uint64_t)a.p * cps));
+        hipError_t err = hipMemsetAsync(a.pr_rank, 0, m * sizeof(uint64_t), s);
+        if (err != hipSuccess) return err;
+        if (a.key_bytes == 4) hipLaunchKernelGGL(rank_seg_kernel<uint32_t>, grid, dim3(256), 0, s, a, m, cps, fences, cmat);
+        else hipLaunchKernelGGL(rank_seg_kernel<uint64_t>, grid, dim3(256), 0, s, a, m, cps, fences, cmat);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)m);
     if (a.p > 256) {
         if (a.key_bytes == 4) hipLaunchKernelGGL((rank_kernel<uint32_t, 1024>), grid, dim3(1024), 0, s, a, cmat);
@@ -532,14 +634,14 @@ hipError_t launch_settle(const RoundArgs& a, uint64_t m, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_locate(const RoundArgs& a, const uint32_t* cmat, hipStream_t s) {
+hipError_t launch_locate(const RoundArgs& a, const uint32_t* cmat, uint64_t m, hipStream_t s) {
     const dim3 grid(2u * (a.p > 1 ? a.p - 1 : 1));
     if (a.p > 256) {
-        if (a.key_bytes == 4) hipLaunchKernelGGL((locate_kernel<uint32_t, 1024>), grid, dim3(1024), 0, s, a, cmat);
-        else hipLaunchKernelGGL((locate_kernel<uint64_t, 1024>), grid, dim3(1024), 0, s, a, cmat);
+        if (a.key_bytes == 4) hipLaunchKernelGGL((locate_kernel<uint32_t, 1024>), grid, dim3(1024), 0, s, a, cmat, m);
+        else hipLaunchKernelGGL((locate_kernel<uint64_t, 1024>), grid, dim3(1024), 0, s, a, cmat, m);
     } else {
-        if (a.key_bytes == 4) hipLaunchKernelGGL((locate_kernel<uint32_t, 256>), grid, dim3(256), 0, s, a, cmat);
-        else hipLaunchKernelGGL((locate_kernel<uint64_t, 256>), grid, dim3(256), 0, s, a, cmat);
+        if (a.key_bytes == 4) hipLaunchKernelGGL((locate_kernel<uint32_t, 256>), grid, dim3(256), 0, s, a, cmat, m);
+        else hipLaunchKernelGGL((locate_kernel<uint64_t, 256>), grid, dim3(256), 0, s, a, cmat, m);
     }
     return hipGetLastError();
 }

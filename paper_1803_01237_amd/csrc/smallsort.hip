@@ -3,13 +3,14 @@
 //   1. one counting pass on the top 8 bits of the key (count / scan / scatter
 //      of radix.hip) moves every segment into 256 sub-buckets, in the
 //      temporary buffer; the scan records each sub-bucket's start and length
-//   2. one workgroup per sub-bucket of at most kCap keys loads it into LDS
-//      and sorts it there by the remaining bits, then writes it to the output:
-//        - a stable counting pass on the next 8 bits splits it into groups;
-//        - when no group exceeds kGroupMax keys, each key's place inside its
+//   2. one workgroup per sub-bucket of at most kCap keys sorts it on chip by
+//      the remaining bits and writes it to the output:
+//        - the keys are dropped into groups by the next 8 bits in LDS, and
+//          when no group exceeds kGroupMax keys, each key's place inside its
 //          group is counted directly (keys smaller, or equal and earlier);
-//        - otherwise LSD counting passes over the remaining digits run in LDS,
-//          skipping digits on which all keys of the sub-bucket agree
+//        - otherwise the sub-bucket is listed for a second kernel that runs
+//          LSD counting passes in LDS over the remaining digits, skipping
+//          digits on which all its keys agree
 //   3. sub-buckets larger than kCap are collected into a compact list and go
 //      through LSD counting passes in HBM (radix.hip, list mode)
 // Every step is stable, so equal keys keep their input order.
@@ -23,7 +24,9 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kW = kT / kWave;               // waves per workgroup
-constexpr int kCap = 2048;                   // largest sub-bucket sorted in LDS
+constexpr int kCapSmall = 2048;              // largest sub-bucket sorted in LDS (local sort)
+constexpr int kCapLarge = 4096;              // same for the bucket sort
+constexpr int kCap = kCapLarge;              // the LDS-LSD kernel handles any of them
 constexpr int kRows = kCap / kT;             // rows of 64 keys per wave at kCap
 constexpr uint32_t kGroupMax = 32;           // largest group ranked by direct counting
 
@@ -32,14 +35,23 @@ __device__ __forceinline__ uint32_t dig(K k, int shift) {
     return (uint32_t)(k >> shift) & 0xFFu;
 }
 
+// Records the key written at output position o of segment seg when o falls
+// on a fence position of that segment.
+__device__ __forceinline__ void put_fence(const Fences& f, const uint64_t* seg_off, uint32_t seg,
+                                          uint64_t o, uint64_t key) {
+    const uint64_t rel = o - seg_off[seg];
+    if ((rel & (kFenceStride - 1)) == 0) f.key[seg * f.per_seg + rel / kFenceStride] = key;
+}
+
 // Stable counting pass in LDS: the n keys of `sk` (with indices `si`, or the
-// identity when null) are placed by their digit at `shift` into `dk` / `di`.
+// identity when null) are placed by the digit of key - kbase at `shift` into
+// `dk` / `di`.
 // Leaves the digit starts in start[0..256] and the largest digit count in
 // *max_count.  Wave w handles the keys [w*cw, (w+1)*cw) in rows of 64.
 template <typename K>
 __device__ void lds_pass(const K* sk, const uint16_t* si, K* dk, uint16_t* di, uint32_t n,
-                         int shift, uint32_t (*whist)[256], uint32_t* start, uint32_t* scratch,
-                         uint32_t* max_count) {
+                         int shift, K kbase, uint32_t (*whist)[256], uint32_t* start,
+                         uint32_t* scratch, uint32_t* max_count) {
     const uint32_t cw = ((n + kW * kWave - 1) / (kW * kWave)) * kWave;
     const uint32_t rows = cw / kWave;
     const uint32_t w = threadIdx.x / kWave, lane = lane_id();
@@ -55,7 +67,7 @@ __device__ void lds_pass(const K* sk, const uint16_t* si, K* dk, uint16_t* di, u
         if ((uint32_t)r < rows) {      // uniform over the wave
             const uint32_t idx = w * cw + r * kWave + lane;
             const bool valid = idx < n;
-            const uint32_t d = valid ? dig(sk[idx], shift) : 0u;
+            const uint32_t d = valid ? dig((K)(sk[idx] - kbase), shift) : 0u;
             const uint64_t live = __ballot(valid);
             const uint64_t m = match_byte(d, live);
             const int leader = valid ? (int)(__ffsll((unsigned long long)m) - 1) : (int)lane;
@@ -99,7 +111,12 @@ __device__ void lds_pass(const K* sk, const uint16_t* si, K* dk, uint16_t* di, u
     __syncthreads();
 }
 
-template <typename K, bool kPayload>
+// Fast path, one workgroup per sub-bucket of at most kCap keys: keys stay in
+// registers, are dropped into their group (next 8 bits) in LDS in any order,
+// and each key's rank inside its group is counted by (key, input index).
+// Sub-buckets with a group larger than kGroupMax go to the LDS-LSD list,
+// larger than kCap to the oversize list.
+template <typename K, bool kPayload, int kCapT>
 __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ kin,
                                                         const uint64_t* __restrict__ vin,
                                                         K* __restrict__ kout,
@@ -108,7 +125,126 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
                                                         const uint32_t* __restrict__ sb_len,
                                                         int uniform_bits,
                                                         const uint8_t* __restrict__ seg_shift,
-                                                        OversizeList ov) {
+                                                        const uint64_t* __restrict__ seg_base,
+                                                        OversizeList ov, SlowList sl,
+                                                        const uint64_t* __restrict__ seg_off,
+                                                        Fences fences) {
+    constexpr int kRowsT = kCapT / kT;
+    __shared__ K Bk[kCapT];
+    __shared__ uint16_t Bi[kCapT];
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t cursor[256];
+    __shared__ uint32_t start[257];
+    __shared__ uint32_t scratch[kW];
+    __shared__ uint32_t max_count;
+
+    const uint64_t base = sb_start[blockIdx.x];
+    const uint32_t n = sb_len[blockIdx.x];
+    if (n == 0) return;
+    const uint32_t seg = blockIdx.x / 256;
+    const K kbase = seg_base ? (K)seg_base[seg] : (K)0;
+    if (n > (uint32_t)kCapT) {
+        if (threadIdx.x == 0) {
+            const uint32_t e = atomicAdd(ov.count, 1u);
+            ov.beg[e] = base;
+            ov.end[e] = base + n;
+            ov.base[e] = (uint64_t)kbase;
+            ov.seg[e] = seg;
+        }
+        return;
+    }
+    if (n == 1) {
+        if (threadIdx.x == 0) {
+            const K k = kin[base];
+            kout[base] = k;
+            if constexpr (kPayload) vout[base] = vin[base];
+            if (fences.key) put_fence(fences, seg_off, seg, base, (uint64_t)k);
+        }
+        return;
+    }
+    // the offsets key - kbase of this sub-bucket agree on every bit at or
+    // above `bits`
+    const int bits = seg_shift ? (int)seg_shift[seg] : uniform_bits;
+    const int shift2 = bits >= 8 ? bits - 8 : 0;
+    hist[threadIdx.x] = 0;
+    if (threadIdx.x == 0) max_count = 0;
+    __syncthreads();
+    K kr[kRowsT];
+    uint32_t dr[kRowsT];
+#pragma unroll
+    for (int r = 0; r < kRowsT; ++r) {
+        const uint32_t i = r * kT + threadIdx.x;
+        kr[r] = 0;
+        dr[r] = 0;
+        if (i < n) kr[r] = kin[base + i];
+    }
+#pragma unroll
+    for (int r = 0; r < kRowsT; ++r) {
+        const uint32_t i = r * kT + threadIdx.x;
+        if (i < n) {
+            dr[r] = dig((K)(kr[r] - kbase), shift2);
+            atomicAdd(&hist[dr[r]], 1u);
+        }
+    }
+    __syncthreads();
+    {
+        const uint32_t c = hist[threadIdx.x];
+        uint32_t all;
+        const uint32_t st = block_exclusive_scan<uint32_t, kT>(c, scratch, &all);
+        start[threadIdx.x] = st;
+        cursor[threadIdx.x] = st;
+        if (threadIdx.x == 0) start[256] = all;
+        if (c > kGroupMax) atomicMax(&max_count, c);
+    }
+    __syncthreads();
+    if (max_count > kGroupMax) {
+        if (threadIdx.x == 0) {
+            const uint32_t e = atomicAdd(sl.count, 1u);
+            sl.beg[e] = base;
+            sl.len[e] = n;
+            sl.bits[e] = (uint8_t)bits;
+            sl.base[e] = (uint64_t)kbase;
+            sl.seg[e] = seg;
+        }
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < kRowsT; ++r) {
+        const uint32_t i = r * kT + threadIdx.x;
+        if (i < n) {
+            const uint32_t pos = atomicAdd(&cursor[dr[r]], 1u);
+            Bk[pos] = kr[r];
+            Bi[pos] = (uint16_t)i;
+        }
+    }
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < n; e += kT) {
+        const K k = Bk[e];
+        const uint16_t ie = Bi[e];
+        const uint32_t d = dig((K)(k - kbase), shift2);
+        const uint32_t g0 = start[d], g1 = start[d + 1];
+        uint32_t rk = 0;
+        for (uint32_t j = g0; j < g1; ++j) {
+            const K x = Bk[j];
+            rk += (x < k || (x == k && Bi[j] < ie)) ? 1u : 0u;
+        }
+        const uint64_t o = base + g0 + rk;
+        kout[o] = k;
+        if constexpr (kPayload) vout[o] = vin[base + ie];
+        if (fences.key) put_fence(fences, seg_off, seg, o, (uint64_t)k);
+    }
+}
+
+// Sub-buckets of at most kCap keys with a large group (duplicates or
+// clustered keys): LSD counting passes in LDS over the digits below `bits`
+// that vary, from the input order.
+template <typename K, bool kPayload>
+__global__ __launch_bounds__(kT) void lds_lsd_kernel(const K* __restrict__ kin,
+                                                     const uint64_t* __restrict__ vin,
+                                                     K* __restrict__ kout,
+                                                     uint64_t* __restrict__ vout, SlowList sl,
+                                                     const uint64_t* __restrict__ seg_off,
+                                                     Fences fences) {
     __shared__ K A[kCap];
     __shared__ K Bk[kCap];
     __shared__ uint16_t Ai[kCap];
@@ -119,116 +255,59 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     __shared__ uint32_t max_count;
     __shared__ uint32_t diff_lo, diff_hi;
 
-    const uint64_t base = sb_start[blockIdx.x];
-    const uint32_t n = sb_len[blockIdx.x];
-    // keys of this sub-bucket agree on every bit at or above `bits`
-    const int bits = seg_shift ? (int)seg_shift[blockIdx.x / 256] : uniform_bits;
-    if (n == 0) return;
-    if (n > (uint32_t)kCap) {
-        if (threadIdx.x == 0) {
-            const uint32_t e = atomicAdd(ov.count, 1u);
-            ov.beg[e] = base;
-            ov.end[e] = base + n;
-        }
-        return;
-    }
-    if (n == 1) {
-        if (threadIdx.x == 0) {
-            kout[base] = kin[base];
-            if constexpr (kPayload) vout[base] = vin[base];
-        }
-        return;
-    }
-    // groups by the 8 bits below `bits` (or the lowest 8 bits)
-    const int shift2 = bits >= 8 ? bits - 8 : 0;
-    uint32_t* hist = &whist[0][0];
-    uint32_t* cursor = &whist[1][0];
-    hist[threadIdx.x] = 0;
-    if (threadIdx.x == 0) max_count = 0;
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n; i += kT) {
-        const K k = kin[base + i];
-        A[i] = k;
-        atomicAdd(&hist[dig(k, shift2)], 1u);
-    }
+    const uint64_t base = sl.beg[blockIdx.x];
+    const uint32_t n = sl.len[blockIdx.x];
+    const int bits = sl.bits[blockIdx.x];
+    const K kbase = (K)sl.base[blockIdx.x];
+    if (threadIdx.x == 0) { diff_lo = 0; diff_hi = 0; }
+    for (uint32_t i = threadIdx.x; i < n; i += kT) A[i] = kin[base + i];
     __syncthreads();
     {
-        const uint32_t c = hist[threadIdx.x];
-        uint32_t all;
-        const uint32_t st = block_exclusive_scan<uint32_t, kT>(c, scratch, &all);
-        start[threadIdx.x] = st;
-        cursor[threadIdx.x] = st;
-        if (threadIdx.x == 0) start[256] = all;
-        if (c) atomicMax(&max_count, c);
+        const uint64_t k0 = (uint64_t)(K)(A[0] - kbase);
+        uint64_t acc = 0;
+        for (uint32_t i = threadIdx.x; i < n; i += kT) acc |= (uint64_t)(K)(A[i] - kbase) ^ k0;
+        if (acc) {
+            atomicOr(&diff_lo, (uint32_t)acc);
+            atomicOr(&diff_hi, (uint32_t)(acc >> 32));
+        }
     }
     __syncthreads();
-    const K* fk = A;
-    const uint16_t* fi = Ai;
-    if (max_count <= kGroupMax) {
-        // place keys in their group in any order, then count each key's rank
-        // inside the group by (key, input index): stable by construction
-        for (uint32_t i = threadIdx.x; i < n; i += kT) {
-            const K k = A[i];
-            const uint32_t pos = atomicAdd(&cursor[dig(k, shift2)], 1u);
-            Bk[pos] = k;
-            Bi[pos] = (uint16_t)i;
-        }
-        __syncthreads();
-        for (uint32_t e = threadIdx.x; e < n; e += kT) {
-            const K k = Bk[e];
-            const uint16_t ie = Bi[e];
-            const uint32_t d = dig(k, shift2);
-            const uint32_t g0 = start[d], g1 = start[d + 1];
-            uint32_t r = 0;
-            for (uint32_t j = g0; j < g1; ++j) {
-                const K x = Bk[j];
-                r += (x < k || (x == k && Bi[j] < ie)) ? 1u : 0u;
-            }
-            A[g0 + r] = k;
-            Ai[g0 + r] = ie;
-        }
-        __syncthreads();
-    } else {
-        // LSD in LDS over the digits below the top one that actually vary
-        if (threadIdx.x == 0) { diff_lo = 0; diff_hi = 0; }
-        __syncthreads();
-        {
-            const uint64_t k0 = (uint64_t)A[0];
-            uint64_t acc = 0;
-            for (uint32_t i = threadIdx.x; i < n; i += kT) acc |= (uint64_t)A[i] ^ k0;
-            if (acc) {
-                atomicOr(&diff_lo, (uint32_t)acc);
-                atomicOr(&diff_hi, (uint32_t)(acc >> 32));
-            }
-        }
-        __syncthreads();
-        const uint64_t diff = ((uint64_t)diff_hi << 32) | diff_lo;
-        const K* sk = A;
-        const uint16_t* si = nullptr;
-        K* dk = Bk;
-        uint16_t* di = Bi;
-        for (int sh = 0; sh < bits; sh += 8) {
-            if (((diff >> sh) & 0xFFu) == 0) continue;   // uniform digit: order unchanged
-            lds_pass<K>(sk, si, dk, di, n, sh, whist, start, scratch, &max_count);
-            // the pass output becomes the next input; the buffer pair (keys,
-            // indices) it read from becomes the next output
-            K* old = (K*)sk;
-            sk = dk;
-            si = di;
-            dk = old;
-            di = old == A ? Ai : Bi;
-        }
-        if (si == nullptr) {   // every digit uniform: input order is sorted
-            for (uint32_t i = threadIdx.x; i < n; i += kT) Ai[i] = (uint16_t)i;
-            __syncthreads();
-            si = Ai;
-        }
-        fk = sk;
-        fi = si;
+    const uint64_t diff = ((uint64_t)diff_hi << 32) | diff_lo;
+    const K* sk = A;
+    const uint16_t* si = nullptr;
+    K* dk = Bk;
+    uint16_t* di = Bi;
+    for (int sh = 0; sh < bits; sh += 8) {
+        if (((diff >> sh) & 0xFFu) == 0) continue;   // uniform digit: order unchanged
+        lds_pass<K>(sk, si, dk, di, n, sh, kbase, whist, start, scratch, &max_count);
+        // the pass output becomes the next input; the buffer pair (keys,
+        // indices) it read from becomes the next output
+        K* old = (K*)sk;
+        sk = dk;
+        si = di;
+        dk = old;
+        di = old == A ? Ai : Bi;
     }
+    const uint32_t seg = sl.seg[blockIdx.x];
     for (uint32_t i = threadIdx.x; i < n; i += kT) {
-        kout[base + i] = fk[i];
-        if constexpr (kPayload) vout[base + i] = vin[base + fi[i]];
+        kout[base + i] = sk[i];
+        if constexpr (kPayload) vout[base + i] = vin[base + (si ? si[i] : i)];
+        if (fences.key) put_fence(fences, seg_off, seg, base + i, (uint64_t)sk[i]);
+    }
+}
+
+// Fences of the oversize sub-buckets, read back from the sorted output.
+template <typename K>
+__global__ void ov_fence_kernel(const K* __restrict__ kout, OversizeList ov,
+                                const uint64_t* __restrict__ seg_off, Fences fences) {
+    const uint32_t E = *ov.count;
+    for (uint32_t e = blockIdx.x; e < E; e += gridDim.x) {
+        const uint32_t seg = ov.seg[e];
+        const uint64_t sb = seg_off[seg];
+        const uint64_t first = sb + ((ov.beg[e] - sb + kFenceStride - 1) / kFenceStride) * kFenceStride;
+        for (uint64_t o = first + (uint64_t)threadIdx.x * kFenceStride; o < ov.end[e];
+             o += (uint64_t)blockDim.x * kFenceStride)
+            fences.key[seg * fences.per_seg + (o - sb) / kFenceStride] = (uint64_t)kout[o];
     }
 }
 
@@ -259,9 +338,10 @@ __global__ void ov_fill_kernel(OversizeList ov) {
     }
 }
 
-__global__ void ov_reset_kernel(OversizeList ov) {
+__global__ void ov_reset_kernel(OversizeList ov, SlowList sl) {
     *ov.count = 0;
     *ov.tiles = 0;
+    *sl.count = 0;
 }
 
 }  // namespace
@@ -275,7 +355,7 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     Profiler& prof = a.prof ? *a.prof : dummy;
     const bool pay = a.vals_in != nullptr;
 
-    hipLaunchKernelGGL(ov_reset_kernel, dim3(1), dim3(1), 0, s, a.ov);
+    hipLaunchKernelGGL(ov_reset_kernel, dim3(1), dim3(1), 0, s, a.ov, a.sl);
     // 1. MSD pass into the temporary buffer
     RadixPass ps;
     ps.key_bytes = a.key_bytes;
@@ -285,6 +365,7 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     ps.vals_out = a.vals_tmp;
     ps.map.beg = a.seg_off;
     ps.map.end = a.seg_off + 1;
+    ps.map.base = a.seg_base;
     ps.map.tps = tps;
     ps.num_segs = a.num_segs;
     ps.num_tiles = a.num_segs * tps;
@@ -300,13 +381,22 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     // 2. sub-buckets in LDS
     const dim3 grid(a.num_segs * 256u);
     prof.begin(s);
+    // sub-buckets of the p input segments split by their top byte average
+    // N/(256 p) keys; bucket key ranges may use only half of the digit values
+    const bool large = a.seg_base != nullptr;
+#define HSS_SMALL(KT, PAY, CAP)                                                                  \
+    hipLaunchKernelGGL((small_sort_kernel<KT, PAY, CAP>), grid, dim3(kT), 0, s,                  \
+                       (const KT*)a.keys_tmp, PAY ? a.vals_tmp : nullptr, (KT*)a.keys_out,         \
+                       PAY ? a.vals_out : nullptr, a.sb_start, a.sb_len, bits, a.seg_shift,        \
+                       a.seg_base, a.ov, a.sl, a.seg_off, a.fences)
     if (a.key_bytes == 4) {
-        if (pay) hipLaunchKernelGGL((small_sort_kernel<uint32_t, true>), grid, dim3(kT), 0, s, (const uint32_t*)a.keys_tmp, a.vals_tmp, (uint32_t*)a.keys_out, a.vals_out, a.sb_start, a.sb_len, bits, a.seg_shift, a.ov);
-        else hipLaunchKernelGGL((small_sort_kernel<uint32_t, false>), grid, dim3(kT), 0, s, (const uint32_t*)a.keys_tmp, nullptr, (uint32_t*)a.keys_out, nullptr, a.sb_start, a.sb_len, bits, a.seg_shift, a.ov);
+        if (pay) { if (large) HSS_SMALL(uint32_t, true, kCapLarge); else HSS_SMALL(uint32_t, true, kCapSmall); }
+        else { if (large) HSS_SMALL(uint32_t, false, kCapLarge); else HSS_SMALL(uint32_t, false, kCapSmall); }
     } else {
-        if (pay) hipLaunchKernelGGL((small_sort_kernel<uint64_t, true>), grid, dim3(kT), 0, s, (const uint64_t*)a.keys_tmp, a.vals_tmp, (uint64_t*)a.keys_out, a.vals_out, a.sb_start, a.sb_len, bits, a.seg_shift, a.ov);
-        else hipLaunchKernelGGL((small_sort_kernel<uint64_t, false>), grid, dim3(kT), 0, s, (const uint64_t*)a.keys_tmp, nullptr, (uint64_t*)a.keys_out, nullptr, a.sb_start, a.sb_len, bits, a.seg_shift, a.ov);
+        if (pay) { if (large) HSS_SMALL(uint64_t, true, kCapLarge); else HSS_SMALL(uint64_t, true, kCapSmall); }
+        else { if (large) HSS_SMALL(uint64_t, false, kCapLarge); else HSS_SMALL(uint64_t, false, kCapSmall); }
     }
+#undef HSS_SMALL
     prof.end(kProfSmallSort, s, a.total_len * 2 * (a.key_bytes + (pay ? 8 : 0)));
     // 3. oversize sub-buckets: LSD passes in HBM over a compact list
     hipLaunchKernelGGL(ov_tiles_kernel, dim3(1), dim3(1024), 0, s, a.ov);
@@ -315,10 +405,24 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(host.pinned, a.ov.count, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(host.pinned + 1, a.ov.tiles, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host.pinned + 2, a.sl.count, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
-    const uint32_t E = host.pinned[0], T = host.pinned[1];
+    const uint32_t E = host.pinned[0], T = host.pinned[1], SL = host.pinned[2];
     host.last_oversize = E;
+    host.last_slow = SL;
+    if (SL > 0) {
+        const dim3 g(SL);
+        if (a.key_bytes == 4) {
+            if (pay) hipLaunchKernelGGL((lds_lsd_kernel<uint32_t, true>), g, dim3(kT), 0, s, (const uint32_t*)a.keys_tmp, a.vals_tmp, (uint32_t*)a.keys_out, a.vals_out, a.sl, a.seg_off, a.fences);
+            else hipLaunchKernelGGL((lds_lsd_kernel<uint32_t, false>), g, dim3(kT), 0, s, (const uint32_t*)a.keys_tmp, nullptr, (uint32_t*)a.keys_out, nullptr, a.sl, a.seg_off, a.fences);
+        } else {
+            if (pay) hipLaunchKernelGGL((lds_lsd_kernel<uint64_t, true>), g, dim3(kT), 0, s, (const uint64_t*)a.keys_tmp, a.vals_tmp, (uint64_t*)a.keys_out, a.vals_out, a.sl, a.seg_off, a.fences);
+            else hipLaunchKernelGGL((lds_lsd_kernel<uint64_t, false>), g, dim3(kT), 0, s, (const uint64_t*)a.keys_tmp, nullptr, (uint64_t*)a.keys_out, nullptr, a.sl, a.seg_off, a.fences);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (E == 0) return hipSuccess;
     const uint64_t words = (uint64_t)T * 256;
     if (words > host.fb_words) {
@@ -335,6 +439,7 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     fb.map.end = a.ov.end;
     fb.map.tile_seg = a.ov.tile_seg;
     fb.map.tile0 = a.ov.tile0;
+    fb.map.base = a.ov.base;
     fb.num_segs = E;
     fb.num_tiles = T;
     fb.counts = host.fb_counts;
@@ -352,12 +457,25 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         e = radix_pass(fb, s);
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    if (a.fences.key) {
+        if (a.key_bytes == 4)
+            hipLaunchKernelGGL(ov_fence_kernel<uint32_t>, dim3(1024), dim3(256), 0, s, (const uint32_t*)a.keys_out, a.ov, a.seg_off, a.fences);
+        else
+            hipLaunchKernelGGL(ov_fence_kernel<uint64_t>, dim3(1024), dim3(256), 0, s, (const uint64_t*)a.keys_out, a.ov, a.seg_off, a.fences);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 uint64_t oversize_capacity(uint32_t num_segs, uint64_t total_len) {
     const uint64_t by_count = (uint64_t)num_segs * 256;
-    const uint64_t by_size = total_len / (kCap + 1) + 1;
+    const uint64_t by_size = total_len / (kCapSmall + 1) + 1;
+    return by_count < by_size ? by_count : by_size;
+}
+
+uint64_t slow_capacity(uint32_t num_segs, uint64_t total_len) {
+    const uint64_t by_count = (uint64_t)num_segs * 256;
+    const uint64_t by_size = total_len / (kGroupMax + 1) + 1;
     return by_count < by_size ? by_count : by_size;
 }
 

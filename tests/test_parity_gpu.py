@@ -224,7 +224,7 @@ def test_local_sort_paths(hss, case, lsd_only):
         assert np.array_equal(_host(vs, np.uint64), vals[order])
 
 
-@pytest.mark.parametrize("size", [2047, 2048, 2049, 4096, 33, 32])
+@pytest.mark.parametrize("size", [2047, 2048, 2049, 3071, 3072, 3073, 4096, 33, 32])
 def test_local_sort_sub_bucket_boundaries(hss, size):
     """One segment whose top byte puts exactly `size` keys in one sub-bucket,
     with the rest spread out; duplicates inside the sub-bucket."""
@@ -271,3 +271,24 @@ def test_partition_large_segments(hss, n, p, eps):
         _compare_trace(plan, ref, p)
         assert np.array_equal(_host(off, np.uint64), ref.offsets)
         assert np.array_equal(_host(ko, np.uint64), ref.keys)
+
+
+@pytest.mark.parametrize("centre_bit", [56, 63, 40, 8])
+def test_sort_buckets_straddling_power_of_two(hss, centre_bit):
+    """Keys packed around 2^centre_bit: bucket key ranges cross a power of two,
+    so the bucket sort must take digits of key - bucket base, not raw bits."""
+    n, p = 300_000, 8
+    rng = np.random.default_rng(centre_bit)
+    c = np.uint64(1) << np.uint64(centre_bit)
+    half = np.uint64(min(1 << 20, (1 << centre_bit) - 1))
+    keys = c - half + rng.integers(0, 2 * int(half), size=n, dtype=np.uint64)
+    keys[::7] = keys[::7] & ~np.uint64(0xFF)           # duplicates
+    vals = np.arange(n, dtype=np.uint64)
+    _say(f"[sort] keys around 2^{centre_bit}")
+    with hss.Plan(n, p, 0.05, payload=True) as plan:
+        ks, vs, off = plan.sort(_dev(keys), 9, _dev(vals))
+        order = np.argsort(keys, kind="stable")
+        assert np.array_equal(_host(ks, np.uint64), keys[order])
+        assert np.array_equal(_host(vs, np.uint64), vals[order])
+        ref = oracle.hss(keys, p, 0.05, 9, vals=vals, mode="sort")
+        assert np.array_equal(_host(off, np.uint64), ref.offsets)
