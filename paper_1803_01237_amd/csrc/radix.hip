@@ -23,6 +23,7 @@ namespace {
 
 constexpr int kWavesPerTile = kSortThreads / kWave;           // 4
 constexpr int kKeysPerWave = kSortItems * kWave;              // 1024
+constexpr uint32_t kScatterTilesPerGroup = 1;                 // consecutive tiles per scatter workgroup
 
 template <typename K>
 __device__ __forceinline__ uint32_t digit_of(K k, int shift) {
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(const K* __re
         const uint32_t n_tile = (uint32_t)min((uint64_t)kSortTile, e - base);
         const uint32_t w = threadIdx.x / kWave;
         const uint32_t lane = lane_id();
-        // all loads of the tile in flight before any ranking work
+        // all loads of the tile in flight before any counting
         K kr[kSortItems];
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
@@ -75,10 +76,14 @@ __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(const K* __re
             const uint32_t li = w * kKeysPerWave + r * kWave + lane;
             const bool valid = li < n_tile;
             const uint32_t d = digit_of((K)(kr[r] - kb), shift);
+            // a row whose keys all share one digit adds once (skewed inputs)
+            const uint32_t d0 = __shfl(d, 0);
             const uint64_t live = __ballot(valid);
-            if (live == 0) break;
-            const uint64_t mm = match_byte(d, live);
-            if (valid && (mm & lanes_below_mask()) == 0) atomicAdd(&hist[d], (uint32_t)__popcll(mm));
+            if (__ballot(valid && d != d0) == 0) {
+                if (lane == 0 && live) atomicAdd(&hist[d0], (uint32_t)__popcll(live));
+            } else if (valid) {
+                atomicAdd(&hist[d], 1u);
+            }
         }
     }
     __syncthreads();
@@ -118,92 +123,94 @@ __global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ 
     }
 }
 
+// Stable placement of one tile by digit: each wave ranks its keys among equal
+// digits with ballots (a wave owns a contiguous quarter of the tile, rows of
+// 64 keys in order), per-wave digit counts give the offsets, the tile is
+// staged in LDS in digit order and written out digit run by digit run.
 template <typename K, bool kPayload>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const K* __restrict__ kin, const uint64_t* __restrict__ vin, K* __restrict__ kout,
-    uint64_t* __restrict__ vout, TileMap m, int shift, const uint8_t* __restrict__ seg_shift,
-    const uint32_t* __restrict__ counts) {
-    __shared__ uint32_t whist[kWavesPerTile][256];
+    uint64_t* __restrict__ vout, TileMap m, int shift0, const uint8_t* __restrict__ seg_shift,
+    const uint32_t* __restrict__ counts, uint32_t num_tiles) {
     __shared__ uint32_t tstart[256];
     __shared__ uint32_t gofs[256];
+    __shared__ uint32_t whist[kWavesPerTile][256];
     __shared__ uint32_t scratch[kSortThreads / kWave];
     __shared__ uint64_t stage[kSortTile];
-    __shared__ uint8_t dstage[kSortTile];
+    __shared__ uint16_t sidx[kPayload ? kSortTile : 1];   // input index of each staged key
 
-    uint64_t base, e;
-    uint32_t seg;
-    if (!tile_range(m, blockIdx.x, &base, &e, &seg)) return;   // uniform over the workgroup
-    if (seg_shift) shift = seg_shift[seg];
-    const K kb = m.base ? (K)m.base[seg] : (K)0;
-    const uint64_t b = m.beg[seg];
-    const uint32_t n_tile = (uint32_t)min((uint64_t)kSortTile, e - base);
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
+    for (uint32_t sub = 0; sub < kScatterTilesPerGroup; ++sub) {
+        const uint32_t tile = blockIdx.x * kScatterTilesPerGroup + sub;
+        if (tile >= num_tiles) break;   // uniform over the workgroup
+        uint64_t base, e;
+        uint32_t seg;
+        if (!tile_range(m, tile, &base, &e, &seg)) continue;   // uniform
+        const int shift = seg_shift ? (int)seg_shift[seg] : shift0;
+        const K kb = m.base ? (K)m.base[seg] : (K)0;
+        const uint64_t b = m.beg[seg];
+        const uint32_t n_tile = (uint32_t)min((uint64_t)kSortTile, e - base);
 
-    for (int i = threadIdx.x; i < kWavesPerTile * 256; i += kSortThreads) (&whist[0][0])[i] = 0;
-    gofs[threadIdx.x] = counts[(uint64_t)blockIdx.x * 256 + threadIdx.x];
-    __syncthreads();
+        if (sub) __syncthreads();   // the previous tile is done with the LDS
+        for (int i = threadIdx.x; i < kWavesPerTile * 256; i += kSortThreads) (&whist[0][0])[i] = 0;
+        gofs[threadIdx.x] = counts[(uint64_t)tile * 256 + threadIdx.x];
+        __syncthreads();
 
-    K key[kSortItems];
-    uint32_t rank[kSortItems];
+        K key[kSortItems];
+        uint32_t rank[kSortItems];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint32_t li = w * kKeysPerWave + r * kWave + lane;
-        const bool valid = li < n_tile;
-        key[r] = valid ? kin[base + li] : (K)0;
-        const uint32_t d = digit_of((K)(key[r] - kb), shift);
-        const uint64_t live = __ballot(valid);
-        const uint64_t mm = match_byte(d, live);
-        const int leader = valid ? (int)(__ffsll((unsigned long long)mm) - 1) : (int)lane;
-        uint32_t old = 0;
-        if (valid && (int)lane == leader) {
-            old = whist[w][d];
-            whist[w][d] = old + (uint32_t)__popcll(mm);
+        for (int r = 0; r < kSortItems; ++r) {
+            const uint32_t li = w * kKeysPerWave + r * kWave + lane;
+            key[r] = li < n_tile ? kin[base + li] : (K)0;
         }
-        old = __shfl(old, leader);
-        rank[r] = old + (uint32_t)__popcll(mm & lanes_below_mask());
-    }
-    __syncthreads();
-    {
-        const uint32_t d = threadIdx.x;
-        uint32_t c = 0;
 #pragma unroll
-        for (int ww = 0; ww < kWavesPerTile; ++ww) {
-            const uint32_t t = whist[ww][d];
-            whist[ww][d] = c;
-            c += t;
+        for (int r = 0; r < kSortItems; ++r) {
+            const uint32_t li = w * kKeysPerWave + r * kWave + lane;
+            const bool valid = li < n_tile;
+            const uint32_t d = digit_of((K)(key[r] - kb), shift);
+            const uint64_t live = __ballot(valid);
+            const uint64_t mm = match_byte(d, live);
+            const int leader = valid ? (int)(__ffsll((unsigned long long)mm) - 1) : (int)lane;
+            uint32_t old = 0;
+            if (valid && (int)lane == leader) {
+                old = whist[w][d];
+                whist[w][d] = old + (uint32_t)__popcll(mm);
+            }
+            old = __shfl(old, leader);
+            rank[r] = old + (uint32_t)__popcll(mm & lanes_below_mask());
         }
-        uint32_t all;
-        tstart[d] = block_exclusive_scan<uint32_t, kSortThreads>(c, scratch, &all);
-    }
-    __syncthreads();
-    uint32_t pos[kSortItems];
+        __syncthreads();
+        {
+            const uint32_t d = threadIdx.x;
+            uint32_t c = 0;
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint32_t li = w * kKeysPerWave + r * kWave + lane;
-        const uint32_t d = digit_of((K)(key[r] - kb), shift);
-        pos[r] = tstart[d] + whist[w][d] + rank[r];
-        if (li < n_tile) {
-            stage[pos[r]] = (uint64_t)key[r];
-            dstage[pos[r]] = (uint8_t)d;
+            for (int ww = 0; ww < kWavesPerTile; ++ww) {
+                const uint32_t t = whist[ww][d];
+                whist[ww][d] = c;
+                c += t;
+            }
+            uint32_t all;
+            tstart[d] = block_exclusive_scan<uint32_t, kSortThreads>(c, scratch, &all);
         }
-    }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < n_tile; i += kSortThreads) {
-        const uint32_t d = dstage[i];
-        kout[b + gofs[d] + (i - tstart[d])] = (K)stage[i];
-    }
-    if constexpr (kPayload) {
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
             const uint32_t li = w * kKeysPerWave + r * kWave + lane;
-            if (li < n_tile) stage[pos[r]] = vin[base + li];
+            if (li < n_tile) {
+                const uint32_t d = digit_of((K)(key[r] - kb), shift);
+                const uint32_t pos = tstart[d] + whist[w][d] + rank[r];
+                stage[pos] = (uint64_t)key[r];
+                if constexpr (kPayload) sidx[pos] = (uint16_t)li;
+            }
         }
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < n_tile; i += kSortThreads) {
-            const uint32_t d = dstage[i];
-            vout[b + gofs[d] + (i - tstart[d])] = stage[i];
+            const K k = (K)stage[i];
+            const uint32_t d = digit_of((K)(k - kb), shift);
+            const uint64_t dst = b + gofs[d] + (i - tstart[d]);
+            kout[dst] = k;
+            if constexpr (kPayload) vout[dst] = vin[base + sidx[i]];
         }
     }
 }
@@ -228,14 +235,15 @@ hipError_t pass_impl(const RadixPass& a, hipStream_t stream) {
                        a.sb_start, a.sb_len);
     prof.end(kProfRadixScan, stream, 2 * table);
     prof.begin(stream);
+    const dim3 sgrid((a.num_tiles + kScatterTilesPerGroup - 1) / kScatterTilesPerGroup);
     if (pay)
-        hipLaunchKernelGGL((radix_scatter_kernel<K, true>), grid, block, 0, stream,
+        hipLaunchKernelGGL((radix_scatter_kernel<K, true>), sgrid, block, 0, stream,
                            (const K*)a.keys_in, a.vals_in, (K*)a.keys_out, a.vals_out, a.map,
-                           a.shift, a.seg_shift, a.counts);
+                           a.shift, a.seg_shift, a.counts, a.num_tiles);
     else
-        hipLaunchKernelGGL((radix_scatter_kernel<K, false>), grid, block, 0, stream,
+        hipLaunchKernelGGL((radix_scatter_kernel<K, false>), sgrid, block, 0, stream,
                            (const K*)a.keys_in, nullptr, (K*)a.keys_out, nullptr, a.map, a.shift,
-                           a.seg_shift, a.counts);
+                           a.seg_shift, a.counts, a.num_tiles);
     prof.end(kProfRadixScatter, stream,
              a.total_len * 2 * (sizeof(K) + (pay ? 8 : 0)) + table);
     return hipGetLastError();
