@@ -21,14 +21,13 @@ __device__ __forceinline__ Philox4 philox10(uint32_t c0, uint32_t c1, uint32_t c
                                            uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo_a = 0xD2511F53u * c0;
-        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t lo_b = 0xCD9E8D57u * c2;
-        c0 = hi_b ^ c1 ^ k0;
-        c2 = hi_a ^ c3 ^ k1;
-        c1 = lo_b;
-        c3 = lo_a;
+        // one 32x32->64 multiply gives both halves of each product
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+        c0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        c2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }

@@ -144,6 +144,9 @@ struct RadixPass {
     uint64_t* sb_start = nullptr;      // optional: per (segment, digit) run start
     uint32_t* sb_len = nullptr;        // optional: per (segment, digit) run length
     uint64_t total_len = 0;            // keys covered (for byte counts)
+    // keys only and the order of equal digits within a run is free (a pass
+    // whose runs are fully sorted afterwards): rank by LDS atomics
+    bool any_order = false;
     Profiler* prof = nullptr;
 };
 

@@ -8,8 +8,9 @@
 //   count   -- workgroup (segment s, tile t) histograms the digit of its tile
 //   scan    -- workgroup per segment turns the (tile, digit) counts into the
 //              offset of every (digit, tile) run inside the segment
-//   scatter -- workgroup (s, t) ranks its keys stably per digit with wave
-//              ballots, stages the tile in LDS in digit order and writes each
+//   scatter -- workgroup (s, t) ranks its keys per digit (stably with wave
+//              ballots, or with LDS atomics when the order inside a run is
+//              free), stages the tile in LDS in digit order and writes each
 //              digit run contiguously
 // Tiles are kSortTile = 4096 keys; wave w of a tile owns the 1024 consecutive
 // keys [w*1024, (w+1)*1024), read as 16 coalesced rows of 64 lanes.
@@ -123,15 +124,29 @@ __global__ __launch_bounds__(256) void radix_scan_kernel(uint32_t* __restrict__ 
     }
 }
 
-// Stable placement of one tile by digit: each wave ranks its keys among equal
-// digits with ballots (a wave owns a contiguous quarter of the tile, rows of
-// 64 keys in order), per-wave digit counts give the offsets, the tile is
-// staged in LDS in digit order and written out digit run by digit run.
-template <typename K, bool kPayload>
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.  The
+// tile of workgroup b is chosen so that every XCD walks one contiguous range
+// of tiles in order: neighbouring tiles of a segment then write the two parts
+// of a shared cache line through the same L2.  A bijection on [0, n).
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n) {
+    constexpr uint32_t kXcds = 8;
+    const uint32_t q = n / kXcds, r = n % kXcds;
+    const uint32_t x = b % kXcds, l = b / kXcds;
+    return x * q + min(x, r) + l;
+}
+
+// Placement of one tile by digit; the tile is staged in LDS in digit order and
+// written out digit run by digit run.  kStable: each wave ranks its keys among
+// equal digits with ballots (a wave owns a contiguous quarter of the tile,
+// rows of 64 keys in order) and per-wave digit counts give the offsets, so
+// equal digits keep their input order.  Otherwise one LDS atomic per key
+// hands out the slots of its digit in arbitrary order.
+template <typename K, bool kPayload, bool kStable>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const K* __restrict__ kin, const uint64_t* __restrict__ vin, K* __restrict__ kout,
     uint64_t* __restrict__ vout, TileMap m, int shift0, const uint8_t* __restrict__ seg_shift,
     const uint32_t* __restrict__ counts, uint32_t num_tiles) {
+    static_assert(kStable || !kPayload, "a payload needs the stable placement");
     __shared__ uint32_t tstart[256];
     __shared__ uint32_t gofs[256];
     __shared__ uint32_t whist[kWavesPerTile][256];
@@ -142,7 +157,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
     for (uint32_t sub = 0; sub < kScatterTilesPerGroup; ++sub) {
-        const uint32_t tile = blockIdx.x * kScatterTilesPerGroup + sub;
+        const uint32_t tile = xcd_contiguous(blockIdx.x, gridDim.x) * kScatterTilesPerGroup + sub;
         if (tile >= num_tiles) break;   // uniform over the workgroup
         uint64_t base, e;
         uint32_t seg;
@@ -164,44 +179,63 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
             const uint32_t li = w * kKeysPerWave + r * kWave + lane;
             key[r] = li < n_tile ? kin[base + li] : (K)0;
         }
+        if constexpr (kStable) {
 #pragma unroll
-        for (int r = 0; r < kSortItems; ++r) {
-            const uint32_t li = w * kKeysPerWave + r * kWave + lane;
-            const bool valid = li < n_tile;
-            const uint32_t d = digit_of((K)(key[r] - kb), shift);
-            const uint64_t live = __ballot(valid);
-            const uint64_t mm = match_byte(d, live);
-            const int leader = valid ? (int)(__ffsll((unsigned long long)mm) - 1) : (int)lane;
-            uint32_t old = 0;
-            if (valid && (int)lane == leader) {
-                old = whist[w][d];
-                whist[w][d] = old + (uint32_t)__popcll(mm);
-            }
-            old = __shfl(old, leader);
-            rank[r] = old + (uint32_t)__popcll(mm & lanes_below_mask());
-        }
-        __syncthreads();
-        {
-            const uint32_t d = threadIdx.x;
-            uint32_t c = 0;
-#pragma unroll
-            for (int ww = 0; ww < kWavesPerTile; ++ww) {
-                const uint32_t t = whist[ww][d];
-                whist[ww][d] = c;
-                c += t;
-            }
-            uint32_t all;
-            tstart[d] = block_exclusive_scan<uint32_t, kSortThreads>(c, scratch, &all);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < kSortItems; ++r) {
-            const uint32_t li = w * kKeysPerWave + r * kWave + lane;
-            if (li < n_tile) {
+            for (int r = 0; r < kSortItems; ++r) {
+                const uint32_t li = w * kKeysPerWave + r * kWave + lane;
+                const bool valid = li < n_tile;
                 const uint32_t d = digit_of((K)(key[r] - kb), shift);
-                const uint32_t pos = tstart[d] + whist[w][d] + rank[r];
-                stage[pos] = (uint64_t)key[r];
-                if constexpr (kPayload) sidx[pos] = (uint16_t)li;
+                const uint64_t live = __ballot(valid);
+                const uint64_t mm = match_byte(d, live);
+                const int leader = valid ? (int)(__ffsll((unsigned long long)mm) - 1) : (int)lane;
+                uint32_t old = 0;
+                if (valid && (int)lane == leader) {
+                    old = whist[w][d];
+                    whist[w][d] = old + (uint32_t)__popcll(mm);
+                }
+                old = __shfl(old, leader);
+                rank[r] = old + (uint32_t)__popcll(mm & lanes_below_mask());
+            }
+            __syncthreads();
+            {
+                const uint32_t d = threadIdx.x;
+                uint32_t c = 0;
+#pragma unroll
+                for (int ww = 0; ww < kWavesPerTile; ++ww) {
+                    const uint32_t t = whist[ww][d];
+                    whist[ww][d] = c;
+                    c += t;
+                }
+                uint32_t all;
+                tstart[d] = block_exclusive_scan<uint32_t, kSortThreads>(c, scratch, &all);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kSortItems; ++r) {
+                const uint32_t li = w * kKeysPerWave + r * kWave + lane;
+                if (li < n_tile) {
+                    const uint32_t d = digit_of((K)(key[r] - kb), shift);
+                    const uint32_t pos = tstart[d] + whist[w][d] + rank[r];
+                    stage[pos] = (uint64_t)key[r];
+                    if constexpr (kPayload) sidx[pos] = (uint16_t)li;
+                }
+            }
+        } else {
+            uint32_t* hist = &whist[0][0];   // one tile-wide count per digit
+#pragma unroll
+            for (int r = 0; r < kSortItems; ++r) {
+                const uint32_t li = w * kKeysPerWave + r * kWave + lane;
+                if (li < n_tile) rank[r] = atomicAdd(&hist[digit_of((K)(key[r] - kb), shift)], 1u);
+            }
+            __syncthreads();
+            uint32_t all;
+            tstart[threadIdx.x] =
+                block_exclusive_scan<uint32_t, kSortThreads>(hist[threadIdx.x], scratch, &all);
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kSortItems; ++r) {
+                const uint32_t li = w * kKeysPerWave + r * kWave + lane;
+                if (li < n_tile) stage[tstart[digit_of((K)(key[r] - kb), shift)] + rank[r]] = (uint64_t)key[r];
             }
         }
         __syncthreads();
@@ -237,11 +271,15 @@ hipError_t pass_impl(const RadixPass& a, hipStream_t stream) {
     prof.begin(stream);
     const dim3 sgrid((a.num_tiles + kScatterTilesPerGroup - 1) / kScatterTilesPerGroup);
     if (pay)
-        hipLaunchKernelGGL((radix_scatter_kernel<K, true>), sgrid, block, 0, stream,
+        hipLaunchKernelGGL((radix_scatter_kernel<K, true, true>), sgrid, block, 0, stream,
                            (const K*)a.keys_in, a.vals_in, (K*)a.keys_out, a.vals_out, a.map,
                            a.shift, a.seg_shift, a.counts, a.num_tiles);
+    else if (a.any_order)
+        hipLaunchKernelGGL((radix_scatter_kernel<K, false, false>), sgrid, block, 0, stream,
+                           (const K*)a.keys_in, nullptr, (K*)a.keys_out, nullptr, a.map, a.shift,
+                           a.seg_shift, a.counts, a.num_tiles);
     else
-        hipLaunchKernelGGL((radix_scatter_kernel<K, false>), sgrid, block, 0, stream,
+        hipLaunchKernelGGL((radix_scatter_kernel<K, false, true>), sgrid, block, 0, stream,
                            (const K*)a.keys_in, nullptr, (K*)a.keys_out, nullptr, a.map, a.shift,
                            a.seg_shift, a.counts, a.num_tiles);
     prof.end(kProfRadixScatter, stream,

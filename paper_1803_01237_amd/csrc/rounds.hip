@@ -359,6 +359,7 @@ __global__ __launch_bounds__(256) void rank_seg_kernel(RoundArgs a, uint64_t m,
                                                        uint32_t* __restrict__ cmat) {
     __shared__ uint64_t F[kRankFences];
     __shared__ uint64_t sh_e[2];
+    __shared__ uint32_t sh_cnt[2];
     const uint32_t s = blockIdx.x / chunks_per_seg;
     const uint32_t c = blockIdx.x % chunks_per_seg;
     const uint64_t sb = a.seg_off[s];
@@ -369,26 +370,46 @@ __global__ __launch_bounds__(256) void rank_seg_kernel(RoundArgs a, uint64_t m,
     const uint64_t lo_pos = (uint64_t)c * kRankChunk;
     const uint64_t chunk_end = min(lo_pos + kRankChunk, ns);   // last element + 1 in the chunk
     const K* B = (const K*)a.B + sb;
-    if (threadIdx.x < 2) {
-        // first probe with c_s(e) >= x; for x >= 1 that is the first probe
-        // after the element at position x - 1 of the segment
-        const uint64_t x = threadIdx.x == 0 ? lo_pos : chunk_end;
-        uint64_t r;
-        if (x == 0) {
-            r = 0;
-        } else if (threadIdx.x == 1 && last) {
-            r = m;
-        } else {
-            const K kx = B[x - 1];
-            const uint64_t gx = sb + x - 1;
-            uint64_t lo = 0, hi = m;
-            while (lo < hi) {
-                const uint64_t mid = (lo + hi) >> 1;
-                if (after<K>((K)a.ps_key[mid], a.ps_tag[mid], kx, gx)) hi = mid; else lo = mid + 1;
-            }
-            r = lo;
+    // [e0, e1): the probes with c_s(e) in the chunk.  The first probe with
+    // c_s(e) >= x (x >= 1) is the first probe after the element at position
+    // x - 1 of the segment.  Two parallel steps: 256 evenly spaced probes
+    // bracket the answer, then every probe of the bracket is tested.
+    const bool need0 = lo_pos != 0, need1 = !last;
+    // no probe after the boundary element: m; no boundary (first chunk): 0
+    if (threadIdx.x < 2) sh_e[threadIdx.x] = (threadIdx.x == 0 && !need0) ? 0 : m;
+    if (threadIdx.x == 0) sh_cnt[0] = sh_cnt[1] = 0;
+    __syncthreads();
+    const uint64_t step = (m + 255) / 256;
+    K bx[2];
+    uint64_t bg[2];
+    bx[0] = need0 ? B[lo_pos - 1] : (K)0;
+    bg[0] = sb + lo_pos - 1;
+    bx[1] = need1 ? B[chunk_end - 1] : (K)0;
+    bg[1] = sb + chunk_end - 1;
+    {
+        // probes j*step before or at each boundary element (j = 0..255)
+        const uint64_t j = (uint64_t)threadIdx.x * step;
+        if (j < m) {
+            const K kj = (K)a.ps_key[j];
+            const uint64_t gj = a.ps_tag[j];
+            if (need0 && !after<K>(kj, gj, bx[0], bg[0])) atomicAdd(&sh_cnt[0], 1u);
+            if (need1 && !after<K>(kj, gj, bx[1], bg[1])) atomicAdd(&sh_cnt[1], 1u);
         }
-        sh_e[threadIdx.x] = r;
+    }
+    __syncthreads();
+    for (int q = 0; q < 2; ++q) {
+        if (!(q == 0 ? need0 : need1)) continue;   // uniform
+        // c samples are not after the boundary (the predicate is monotone over
+        // the sorted probes), so the answer lies in [(c-1)*step + 1, c*step],
+        // or is m when no probe of that range is after it
+        const uint64_t c = sh_cnt[q];
+        const uint64_t lo = c == 0 ? 0 : (c - 1) * step + 1;
+        const uint64_t hi = min(c * step + 1, m);   // exclusive
+        for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+            if (after<K>((K)a.ps_key[e], a.ps_tag[e], bx[q], bg[q]) &&
+                (e == 0 || !after<K>((K)a.ps_key[e - 1], a.ps_tag[e - 1], bx[q], bg[q])))
+                sh_e[q] = e;   // exactly one e qualifies
+        }
     }
     __syncthreads();
     const uint64_t e0 = sh_e[0], e1 = sh_e[1];

@@ -376,6 +376,9 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     ps.sb_len = a.sb_len;
     ps.total_len = a.total_len;
     ps.prof = a.prof;
+    // every sub-bucket is sorted completely afterwards; with keys only, equal
+    // keys are interchangeable, so the order inside a run does not matter
+    ps.any_order = !pay;
     hipError_t e = radix_pass(ps, s);
     if (e != hipSuccess) return e;
     // 2. sub-buckets in LDS
