@@ -13,7 +13,8 @@
 //          digits on which all its keys agree
 //   3. sub-buckets larger than kCap are collected into a compact list and go
 //      through LSD counting passes in HBM (radix.hip, list mode)
-// Every step is stable, so equal keys keep their input order.
+// With a payload every step is stable, so equal keys keep their input order;
+// keys alone may swap places with equal keys, which leaves the output the same.
 
 #include "device.hpp"
 #include "internal.hpp"
@@ -113,7 +114,8 @@ __device__ void lds_pass(const K* sk, const uint16_t* si, K* dk, uint16_t* di, u
 
 // Fast path, one workgroup per sub-bucket of at most kCap keys: keys stay in
 // registers, are dropped into their group (next 8 bits) in LDS in any order,
-// and each key's rank inside its group is counted by (key, input index).
+// and each key's rank inside its group is counted by (key, input index), or
+// by (key, place in the group) for keys without payload.
 // Sub-buckets with a group larger than kGroupMax go to the LDS-LSD list,
 // larger than kCap to the oversize list.
 template <typename K, bool kPayload, int kCapT>
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
                                                         Fences fences) {
     constexpr int kRowsT = kCapT / kT;
     __shared__ K Bk[kCapT];
-    __shared__ uint16_t Bi[kCapT];
+    __shared__ uint16_t Bi[kPayload ? kCapT : 1];   // input index of each placed key
     __shared__ uint32_t hist[256];
     __shared__ uint32_t cursor[256];
     __shared__ uint32_t start[257];
@@ -214,24 +216,35 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
         if (i < n) {
             const uint32_t pos = atomicAdd(&cursor[dr[r]], 1u);
             Bk[pos] = kr[r];
-            Bi[pos] = (uint16_t)i;
+            if constexpr (kPayload) Bi[pos] = (uint16_t)i;
         }
     }
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < n; e += kT) {
         const K k = Bk[e];
-        const uint16_t ie = Bi[e];
         const uint32_t d = dig((K)(k - kbase), shift2);
         const uint32_t g0 = start[d], g1 = start[d + 1];
         uint32_t rk = 0;
-        for (uint32_t j = g0; j < g1; ++j) {
-            const K x = Bk[j];
-            rk += (x < k || (x == k && Bi[j] < ie)) ? 1u : 0u;
+        if constexpr (kPayload) {
+            // equal keys keep their input order
+            const uint16_t ie = Bi[e];
+            for (uint32_t j = g0; j < g1; ++j) {
+                const K x = Bk[j];
+                rk += (x < k || (x == k && Bi[j] < ie)) ? 1u : 0u;
+            }
+            const uint64_t o = base + g0 + rk;
+            kout[o] = k;
+            vout[o] = vin[base + ie];
+            if (fences.key) put_fence(fences, seg_off, seg, o, (uint64_t)k);
+        } else {
+            // keys only: equal keys are interchangeable, so the ones placed
+            // before this one in the group go first
+            for (uint32_t j = g0; j < e; ++j) rk += Bk[j] <= k ? 1u : 0u;
+            for (uint32_t j = e + 1; j < g1; ++j) rk += Bk[j] < k ? 1u : 0u;
+            const uint64_t o = base + g0 + rk;
+            kout[o] = k;
+            if (fences.key) put_fence(fences, seg_off, seg, o, (uint64_t)k);
         }
-        const uint64_t o = base + g0 + rk;
-        kout[o] = k;
-        if constexpr (kPayload) vout[o] = vin[base + ie];
-        if (fences.key) put_fence(fences, seg_off, seg, o, (uint64_t)k);
     }
 }
 
