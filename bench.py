@@ -127,8 +127,10 @@ def main():
     plan.profile(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = n / (ms_step * 1e-3) / 1e9
-    rounds = len(plan.trace())
-    ms_m = [r.m for r in plan.trace()]
+    tr = plan.trace()
+    rounds = len(tr)
+    ms_m = [r.m for r in tr]
+    domains = [r.domain for r in tr]
 
     # check the benched result: every splitter inside its target range
     tol = plan.constants(1)[0]
@@ -179,7 +181,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "stages": stages,
-        "rounds": rounds, "probes_per_round": ms_m,
+        "rounds": rounds, "probes_per_round": ms_m, "domain_per_round": domains,
         "hss_sort_ms": None if sort_ms is None else round(sort_ms, 4),
         "hss_sort_gkeys_s": None if sort_ms is None else round(n / (sort_ms * 1e-3) / 1e9, 3),
     }

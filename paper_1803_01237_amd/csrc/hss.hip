@@ -164,14 +164,15 @@ size_t layout(hss_plan_s& P, char* base) {
     r.upos = ar.take<uint32_t>((p + 1) * p);
     r.prow = ar.take<uint32_t>((p + 1) * p);
     r.ivl_row = ar.take<uint32_t>(p);
-    r.ivl_blk = ar.take<uint32_t>(p * p);
+    r.slices = ar.take<uint4>(p * p);
+    r.ivl_nz = ar.take<uint32_t>(p + 1);
     r.ivl_tot = ar.take<uint64_t>(p + 1);
     r.ivl_dom = ar.take<uint64_t>(p);
     r.req_probe = ar.take<uint32_t>(2 * p);
     r.req_row = ar.take<uint32_t>(2 * p);
     r.req_kind = ar.take<uint32_t>(2 * p);
     r.ctr = ar.take<RoundCounters>(1);
-    P.dst = r.ivl_blk;   // the exchange runs after the last round
+    P.dst = (uint32_t*)r.slices;   // p x p words; the exchange runs after the last round
     P.fences.per_seg = (P.max_seg + kFenceStride - 1) / kFenceStride;
     P.fences.key = ar.take<uint64_t>(p * P.fences.per_seg);
     P.bucket_shift = ar.take<uint8_t>(p);
@@ -181,6 +182,7 @@ size_t layout(hss_plan_s& P, char* base) {
     const uint64_t ovc = oversize_capacity((uint32_t)p, n);
     P.ov.count = ar.take<uint32_t>(1);
     P.ov.tiles = ar.take<uint32_t>(1);
+    P.ov.summary = ar.take<uint32_t>(4);
     P.ov.beg = ar.take<uint64_t>(ovc);
     P.ov.end = ar.take<uint64_t>(ovc);
     P.ov.base = ar.take<uint64_t>(ovc);
@@ -419,7 +421,7 @@ hss_status run(hss_plan_s* P, uint64_t seed, const void* kin, const uint64_t* vi
     if (!d_offsets) return fail(HSS_ERR_INVALID_ARG, "null offsets pointer");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(P->device));
-    HIP_TRY(hipMemsetAsync(P->ra.ctr, 0, sizeof(RoundCounters), s));
+    HIP_TRY(launch_counters_reset(P->ra.ctr, s));
     // phase 1: local sort of every segment into B, with its fences
     st = segment_sort(*P, kin, vin, P->B, P->Bv, P->A, P->Av, P->seg_off, P->max_seg, nullptr,
                       nullptr, P->tune.lsd_only ? nullptr : &P->fences, s);

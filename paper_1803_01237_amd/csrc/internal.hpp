@@ -177,6 +177,7 @@ struct OversizeList {
     uint32_t* seg = nullptr;           // segment of the entry
     uint32_t* tile0 = nullptr;         // capacity + 1
     uint32_t* tile_seg = nullptr;      // oversize_tile_capacity()
+    uint32_t* summary = nullptr;       // 4 words for the host: entries, tiles, slow-list entries
 };
 
 // Sub-buckets that fit LDS but hold a large group of keys equal in their
@@ -222,7 +223,7 @@ struct HybridSort {
 // Host-side state of the hybrid sort: pinned read-back words and the count
 // table of the oversize passes, grown on demand.
 struct HybridHost {
-    uint32_t* pinned = nullptr;        // 3 words
+    uint32_t* pinned = nullptr;        // 4 words
     uint32_t* fb_counts = nullptr;
     uint64_t fb_words = 0;
     uint32_t last_oversize = 0;
@@ -241,6 +242,7 @@ struct RoundCounters {
     unsigned long long domain;     // keys in the sampled domain
     unsigned long long blocks;     // Philox blocks in the flattened domain
     unsigned int n_ivl;            // distinct unsettled intervals
+    unsigned int n_slices;         // non-empty (interval, segment) slices
     unsigned int n_unsettled;      // unsettled splitters before the round
     unsigned int n_req;            // locate requests emitted by the settle step
     unsigned int err;              // device consistency failures (bit set)
@@ -272,7 +274,8 @@ struct RoundArgs {
     uint32_t* prow;                // (p+1) x p
     // intervals
     uint32_t* ivl_row;             // p
-    uint32_t* ivl_blk;             // p x p, exclusive block offset of slice (k, s) in interval k
+    uint4* slices;                 // p x p: non-empty slices {first block, first tag, end tag, interval}
+    uint32_t* ivl_nz;              // p+1: non-empty slice counts, then exclusive offsets
     uint64_t* ivl_tot;             // p+1: block totals, then exclusive offsets
     uint64_t* ivl_dom;             // p
     // probes
@@ -294,6 +297,8 @@ struct RoundArgs {
 };
 
 hipError_t launch_round_init(const RoundArgs& a, hipStream_t s);
+// Zero the round counters (the device error word included).
+hipError_t launch_counters_reset(RoundCounters* ctr, hipStream_t s);
 hipError_t launch_intervals(const RoundArgs& a, hipStream_t s);
 hipError_t launch_sample(const RoundArgs& a, uint64_t seed, uint32_t round, uint32_t thresh,
                          int take_all, hipStream_t s);

@@ -6,7 +6,8 @@
 //                or identical, section 4.2.2)
 //   slices    -- per (interval, segment) the slice of the locally sorted
 //                segment strictly inside the interval, as a run of 4-tag
-//                Philox blocks in one flattened block space
+//                Philox blocks in one flattened block space; the non-empty
+//                slices are listed in (interval, segment) order
 //   sample    -- every tag of the domain draws its Philox word and becomes a
 //                probe when the word is below the round threshold
 //                (section 4.2.1: independent Bernoulli with rate p s_j / N)
@@ -28,7 +29,6 @@ namespace hss {
 namespace {
 
 constexpr int kT = 256;           // threads of most round kernels
-constexpr int kRun = 8;           // consecutive Philox blocks per lane in the sampler
 constexpr int kSampleGrid = 4096; // workgroups of the grid-stride sampler
 constexpr uint64_t kCountSortMax = 32768;   // probe sort by pairwise counting up to here
 constexpr int kCountTile = 256;
@@ -46,10 +46,15 @@ __global__ void round_init_kernel(uint32_t p, uint32_t* settled, uint64_t* chi, 
         ctr->domain = 0;
         ctr->blocks = 0;
         ctr->n_ivl = 0;
+        ctr->n_slices = 0;
         ctr->n_unsettled = 0;
         ctr->n_req = 0;
         ctr->err = 0;
     }
+}
+
+__global__ void counters_reset_kernel(RoundCounters* ctr) {
+    *ctr = RoundCounters{};
 }
 
 // One workgroup: leaders of runs of identical unsettled intervals, in
@@ -94,58 +99,6 @@ __device__ __forceinline__ uint64_t blocks_of(uint64_t ga, uint64_t gb) {
     return gb > ga ? ((gb - 1) >> 2) - (ga >> 2) + 1 : 0;
 }
 
-// Workgroup per interval k: block counts of its p slices, scanned.
-__global__ __launch_bounds__(kT) void slices_kernel(RoundArgs a) {
-    __shared__ uint64_t scratch[kT / kWave];
-    const uint32_t k = blockIdx.x;
-    if (k >= a.ctr->n_ivl) return;
-    const uint32_t row = a.ivl_row[k];
-    const bool lnone = a.lrank[row] == kNone;
-    const bool unone = a.urank[row] == kNone;
-    uint64_t run = 0, dom = 0;
-    for (uint32_t s0 = 0; s0 < a.p; s0 += kT) {
-        const uint32_t s = s0 + threadIdx.x;
-        uint64_t nb = 0, len = 0;
-        if (s < a.p) {
-            uint64_t ga, gb;
-            slice_bounds(a, row, s, lnone, unone, &ga, &gb);
-            nb = blocks_of(ga, gb);
-            len = gb - ga;
-        }
-        uint64_t tot;
-        const uint64_t pre = block_exclusive_scan<uint64_t, kT>(nb, scratch, &tot);
-        if (s < a.p) a.ivl_blk[(uint64_t)k * a.p + s] = (uint32_t)(run + pre);
-        run += tot;
-        dom += block_sum<uint64_t, kT>(len, scratch);
-    }
-    if (threadIdx.x == 0) {
-        a.ivl_tot[k] = run;
-        a.ivl_dom[k] = dom;
-    }
-}
-
-// One workgroup: exclusive scan of the interval block totals.
-__global__ __launch_bounds__(1024) void ivl_scan_kernel(RoundArgs a) {
-    __shared__ uint64_t scratch[1024 / kWave];
-    const uint32_t n = a.ctr->n_ivl;
-    uint64_t run = 0, dom = 0;
-    for (uint32_t c = 0; c < n; c += 1024) {
-        const uint32_t k = c + threadIdx.x;
-        const uint64_t v = k < n ? a.ivl_tot[k] : 0;
-        const uint64_t d = k < n ? a.ivl_dom[k] : 0;
-        uint64_t tot;
-        const uint64_t pre = block_exclusive_scan<uint64_t, 1024>(v, scratch, &tot);
-        if (k < n) a.ivl_tot[k] = run + pre;
-        run += tot;
-        dom += block_sum<uint64_t, 1024>(d, scratch);
-    }
-    if (threadIdx.x == 0) {
-        a.ivl_tot[n] = run;
-        a.ctr->blocks = run;
-        a.ctr->domain = dom;
-    }
-}
-
 // Last index i in [0, n) with v[i] <= x (v non-decreasing, v[0] <= x).
 template <typename T>
 __device__ __forceinline__ uint32_t last_le(const T* v, uint32_t n, uint64_t x) {
@@ -157,83 +110,191 @@ __device__ __forceinline__ uint32_t last_le(const T* v, uint32_t n, uint64_t x) 
     return lo;
 }
 
+// Workgroup per interval k: Philox blocks, non-empty slices and tags of its
+// p slices.
+__global__ __launch_bounds__(kT) void slices_kernel(RoundArgs a) {
+    __shared__ uint64_t scratch[kT / kWave];
+    const uint32_t k = blockIdx.x;
+    if (k >= a.ctr->n_ivl) return;
+    const uint32_t row = a.ivl_row[k];
+    const bool lnone = a.lrank[row] == kNone;
+    const bool unone = a.urank[row] == kNone;
+    uint64_t nb_sum = 0, nz_sum = 0, dom = 0;
+    for (uint32_t s0 = 0; s0 < a.p; s0 += kT) {
+        const uint32_t s = s0 + threadIdx.x;
+        uint64_t nb = 0, len = 0;
+        if (s < a.p) {
+            uint64_t ga, gb;
+            slice_bounds(a, row, s, lnone, unone, &ga, &gb);
+            nb = blocks_of(ga, gb);
+            len = gb - ga;
+        }
+        nb_sum += nb;
+        nz_sum += nb ? 1 : 0;
+        dom += len;
+    }
+    nb_sum = block_sum<uint64_t, kT>(nb_sum, scratch);
+    nz_sum = block_sum<uint64_t, kT>(nz_sum, scratch);
+    dom = block_sum<uint64_t, kT>(dom, scratch);
+    if (threadIdx.x == 0) {
+        a.ivl_tot[k] = nb_sum;
+        a.ivl_nz[k] = (uint32_t)nz_sum;
+        a.ivl_dom[k] = dom;
+    }
+}
+
+// One workgroup: exclusive scans of the interval block and slice totals.
+__global__ __launch_bounds__(1024) void ivl_scan_kernel(RoundArgs a) {
+    __shared__ uint64_t scratch[1024 / kWave];
+    const uint32_t n = a.ctr->n_ivl;
+    uint64_t run = 0, run_nz = 0, dom = 0;
+    for (uint32_t c = 0; c < n; c += 1024) {
+        const uint32_t k = c + threadIdx.x;
+        const uint64_t v = k < n ? a.ivl_tot[k] : 0;
+        const uint64_t z = k < n ? a.ivl_nz[k] : 0;
+        const uint64_t d = k < n ? a.ivl_dom[k] : 0;
+        uint64_t tot, tot_nz;
+        const uint64_t pre = block_exclusive_scan<uint64_t, 1024>(v, scratch, &tot);
+        const uint64_t pre_nz = block_exclusive_scan<uint64_t, 1024>(z, scratch, &tot_nz);
+        if (k < n) {
+            a.ivl_tot[k] = run + pre;
+            a.ivl_nz[k] = (uint32_t)(run_nz + pre_nz);
+        }
+        run += tot;
+        run_nz += tot_nz;
+        dom += block_sum<uint64_t, 1024>(d, scratch);
+    }
+    if (threadIdx.x == 0) {
+        a.ivl_tot[n] = run;
+        a.ivl_nz[n] = (uint32_t)run_nz;
+        a.ctr->blocks = run;
+        a.ctr->n_slices = (uint32_t)run_nz;
+        a.ctr->domain = dom;
+    }
+}
+
+// Workgroup per interval k: its non-empty slices, in segment order, into the
+// slice list {first block in the flattened block space, first tag, end tag,
+// interval}.  Blocks and slices of interval k start at the scanned offsets.
+__global__ __launch_bounds__(kT) void compact_kernel(RoundArgs a) {
+    __shared__ uint64_t scratch[kT / kWave];
+    const uint32_t k = blockIdx.x;
+    if (k >= a.ctr->n_ivl) return;
+    const uint32_t row = a.ivl_row[k];
+    const bool lnone = a.lrank[row] == kNone;
+    const bool unone = a.urank[row] == kNone;
+    uint64_t run = a.ivl_tot[k], run_nz = a.ivl_nz[k];
+    for (uint32_t s0 = 0; s0 < a.p; s0 += kT) {
+        const uint32_t s = s0 + threadIdx.x;
+        uint64_t nb = 0, ga = 0, gb = 0;
+        if (s < a.p) {
+            slice_bounds(a, row, s, lnone, unone, &ga, &gb);
+            nb = blocks_of(ga, gb);
+        }
+        uint64_t tot, tot_nz;
+        const uint64_t pre = block_exclusive_scan<uint64_t, kT>(nb, scratch, &tot);
+        const uint64_t pre_nz = block_exclusive_scan<uint64_t, kT>(nb ? 1 : 0, scratch, &tot_nz);
+        if (nb) a.slices[run_nz + pre_nz] = make_uint4((uint32_t)(run + pre), (uint32_t)ga, (uint32_t)gb, k);
+        run += tot;
+        run_nz += tot_nz;
+    }
+}
+
+// Wave-per-range sampler.  Wave w of W takes the blocks [w T / W, (w+1) T / W)
+// of the flattened block space (T blocks), one block per lane per step.  The
+// slice list is walked with a window of 64 consecutive entries, one per lane:
+// slices are non-empty, so the 64 blocks of a step lie in the 64 slices that
+// start with the slice of the step's first block, and the next step's first
+// block lies at most one slice past the window.
 template <typename K>
 __global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint64_t seed, uint32_t round,
                                                     uint32_t thresh, int take_all) {
-    const uint64_t total = a.ctr->blocks;
-    const uint32_t n_ivl = a.ctr->n_ivl;
+    constexpr uint32_t kNoBlock = 0xFFFFFFFFu;   // start of the entries past the list
+    const uint32_t total = (uint32_t)a.ctr->blocks;
+    const uint32_t nsl = a.ctr->n_slices;
     const K* B = (const K*)a.B;
+    const uint4* sl = a.slices;
     const uint32_t lane = lane_id();
-    const uint64_t wave_global = ((uint64_t)blockIdx.x * kT + threadIdx.x) / kWave;
-    const uint64_t n_waves = (uint64_t)gridDim.x * kT / kWave;
-    const uint64_t p = a.p;
+    const uint32_t W = gridDim.x * (kT / kWave);
+    const uint32_t w = blockIdx.x * (kT / kWave) + threadIdx.x / kWave;
+    const uint32_t b_lo = (uint32_t)((uint64_t)total * w / W);
+    const uint32_t b_hi = (uint32_t)((uint64_t)total * (w + 1) / W);
+    if (b_lo >= b_hi) return;   // uniform over the wave
 
-    for (uint64_t w0 = wave_global * kWave * kRun; w0 < total; w0 += n_waves * kWave * kRun) {
-        uint64_t bi = w0 + (uint64_t)lane * kRun;
-        const uint64_t bend = min(bi + kRun, total);
-        // current slice of this lane
-        uint32_t k = 0, s = 0, row = 0;
-        uint64_t ga = 0, gb = 0, sstart = 0, send = 0;
-        bool lnone = false, unone = false;
-        if (bi < bend) {
-            k = last_le(a.ivl_tot, n_ivl, bi);
-            const uint64_t kbase = a.ivl_tot[k];
-            s = last_le(a.ivl_blk + (uint64_t)k * p, a.p, bi - kbase);
-            row = a.ivl_row[k];
-            lnone = a.lrank[row] == kNone;
-            unone = a.urank[row] == kNone;
-            slice_bounds(a, row, s, lnone, unone, &ga, &gb);
-            sstart = kbase + a.ivl_blk[(uint64_t)k * p + s];
-            send = sstart + blocks_of(ga, gb);
+    // slice of block b_lo: the last entry starting at or before it, by a
+    // 64-way search (entry 0 starts at block 0)
+    uint32_t lo = 0, hi = nsl;   // answer in [lo, hi)
+    while (hi - lo > (uint32_t)kWave) {
+        const uint32_t step = (hi - lo + kWave - 1) / kWave;
+        const uint32_t q = lo + lane * step;
+        const uint32_t c = (uint32_t)__popcll(__ballot(q < hi && sl[q].x <= b_lo));
+        lo += (c - 1) * step;
+        hi = min(lo + step, hi);
+    }
+    uint32_t jq = lo + (uint32_t)__popcll(__ballot(lo + lane < hi && sl[lo + lane].x <= b_lo)) - 1;
+
+    uint4 e = jq + lane < nsl ? sl[jq + lane] : make_uint4(kNoBlock, 0, 0, 0);
+    uint32_t nxt = jq + kWave < nsl ? sl[jq + kWave].x : kNoBlock;
+    for (uint32_t b0 = b_lo; b0 < b_hi; b0 += kWave) {
+        // the window of the next step, loaded while this one draws
+        const uint32_t bn = b0 + kWave;
+        const uint32_t jn = jq + (uint32_t)__popcll(__ballot(e.x <= bn)) + (nxt <= bn ? 1u : 0u) - 1;
+        uint4 en = make_uint4(kNoBlock, 0, 0, 0);
+        uint32_t nxtn = kNoBlock;
+        if (bn < b_hi) {   // uniform
+            if (jn + lane < nsl) en = sl[jn + lane];
+            if (jn + kWave < nsl) nxtn = sl[jn + kWave].x;
         }
-        for (int r = 0; r < kRun; ++r) {
-            uint32_t hits = 0;     // bit w: tag 4*blk + w is a probe
-            uint64_t blk = 0;
-            const bool act = bi < bend;
-            if (act) {
-                while (bi >= send) {   // move to the slice holding block bi
-                    ++s;
-                    if (s == a.p) {
-                        s = 0;
-                        ++k;
-                        row = a.ivl_row[k];
-                        lnone = a.lrank[row] == kNone;
-                        unone = a.urank[row] == kNone;
-                    }
-                    slice_bounds(a, row, s, lnone, unone, &ga, &gb);
-                    sstart = a.ivl_tot[k] + a.ivl_blk[(uint64_t)k * p + s];
-                    send = sstart + blocks_of(ga, gb);
-                }
-                blk = (ga >> 2) + (bi - sstart);
-                const Philox4 w = sample_block(seed, blk, round);
+        // slice of this lane's block: the last window entry starting at or
+        // before it (entry starts increase across the lanes)
+        const uint32_t b = b0 + lane;
+        uint32_t pos = 0;
+        if (__builtin_amdgcn_readlane(e.x, 1) > b0 + (kWave - 1)) {
+            pos = 0;   // the first slice holds the whole step
+        } else {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint64_t g = blk * 4 + q;
-                    if (g >= ga && g < gb && (take_all || w.v[q] < thresh)) hits |= 1u << q;
+            for (uint32_t st = kWave / 2; st > 0; st >>= 1)
+                if ((uint32_t)__shfl(e.x, (int)(pos + st)) <= b) pos += st;
+        }
+        const uint32_t s_first = __shfl(e.x, (int)pos);
+        const uint32_t ga = __shfl(e.y, (int)pos);
+        const uint32_t gb = __shfl(e.z, (int)pos);
+        const uint32_t k = __shfl(e.w, (int)pos);
+        uint32_t hits = 0;   // bit q: tag 4 blk + q is a probe
+        uint64_t blk = 0;
+        if (b < b_hi) {
+            blk = (uint64_t)(ga >> 2) + (b - s_first);
+            const Philox4 r = sample_block(seed, blk, round);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t g = blk * 4 + q;
+                if (g >= ga && g < gb && (take_all || r.v[q] < thresh)) hits |= 1u << q;
+            }
+        }
+        if (__ballot(hits != 0)) {
+            const uint32_t c = __popc(hits);
+            const uint32_t inc = wave_inclusive_scan<uint32_t>(c);
+            unsigned long long base = 0;
+            if (lane == kWave - 1) base = atomicAdd(&a.ctr->m, (unsigned long long)inc);
+            base = shfl_u64(base, kWave - 1);
+            uint64_t o = base + inc - c;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (hits & (1u << q)) {
+                    if (o < a.cap) {
+                        const uint64_t g = blk * 4 + q;
+                        a.pr_key[o] = (uint64_t)B[g];
+                        a.pr_tag[o] = g;
+                        a.pr_ivl[o] = k;
+                        a.pr_pos[o] = 0;   // the probe sort counts into it
+                    }
+                    ++o;
                 }
             }
-            if (__ballot(hits != 0)) {
-                const uint32_t c = __popc(hits);
-                const uint32_t inc = wave_inclusive_scan<uint32_t>(c);
-                unsigned long long base = 0;
-                if (lane == kWave - 1) base = atomicAdd(&a.ctr->m, (unsigned long long)inc);
-                base = shfl_u64(base, kWave - 1);
-                uint64_t o = base + inc - c;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (hits & (1u << q)) {
-                        if (o < a.cap) {
-                            const uint64_t g = blk * 4 + q;
-                            a.pr_key[o] = (uint64_t)B[g];
-                            a.pr_tag[o] = g;
-                            a.pr_ivl[o] = k;
-                        }
-                        ++o;
-                    }
-                }
-            }
-            ++bi;
         }
+        e = en;
+        nxt = nxtn;
+        jq = jn;
     }
 }
 
@@ -276,6 +337,7 @@ __global__ void probe_permute_kernel(RoundArgs a, uint64_t m, const uint64_t* or
         a.ps_tag[dst] = g;
         a.ps_ivl[dst] = a.pr_ivl[src];
         a.ps_seg[dst] = segment_of(a.seg_off, a.p, g);
+        a.pr_rank[dst] = 0;   // the rank reduction adds into it
     }
 }
 
@@ -443,10 +505,26 @@ __global__ __launch_bounds__(256) void rank_seg_kernel(RoundArgs a, uint64_t m,
             }
         }
         cmat[(uint64_t)s * m + e] = (uint32_t)cnt;
-        // the reduction of section 5.2: integer sums, so the order of the
-        // atomic additions does not change R(e)
-        atomicAdd((unsigned long long*)&a.pr_rank[e], (unsigned long long)cnt);
     }
+}
+
+constexpr uint32_t kReduceRows = 16;   // segments summed per workgroup of the reduction
+
+// The reduction of section 5.2: R(e) is the sum over segments of c_s(e), the
+// column sums of the count matrix.  Tiles of 256 probes x kReduceRows
+// segments; the partial sums are integers, so the order of the atomic
+// additions does not change R(e).
+__global__ __launch_bounds__(256) void rank_reduce_kernel(const uint32_t* __restrict__ cmat,
+                                                          uint64_t m, uint32_t p,
+                                                          uint64_t* __restrict__ pr_rank) {
+    const uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= m) return;
+    const uint32_t s0 = blockIdx.y * kReduceRows;
+    const uint32_t s1 = min(s0 + kReduceRows, p);
+    uint64_t sum = 0;
+#pragma unroll
+    for (uint32_t s = s0; s < s1; ++s) sum += cmat[(uint64_t)s * m + e];
+    atomicAdd((unsigned long long*)&pr_rank[e], (unsigned long long)sum);
 }
 
 __device__ __forceinline__ void emit_request(const RoundArgs& a, uint32_t e, uint32_t row,
@@ -548,10 +626,16 @@ hipError_t launch_round_init(const RoundArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_counters_reset(RoundCounters* ctr, hipStream_t s) {
+    hipLaunchKernelGGL(counters_reset_kernel, dim3(1), dim3(1), 0, s, ctr);
+    return hipGetLastError();
+}
+
 hipError_t launch_intervals(const RoundArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(leaders_kernel, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(slices_kernel, dim3(a.p > 1 ? a.p - 1 : 1), dim3(kT), 0, s, a);
     hipLaunchKernelGGL(ivl_scan_kernel, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(compact_kernel, dim3(a.p > 1 ? a.p - 1 : 1), dim3(kT), 0, s, a);
     return hipGetLastError();
 }
 
@@ -576,8 +660,6 @@ hipError_t launch_probe_sort(const RoundArgs& a, uint64_t m, void* scratch, size
                              uint32_t* counts, hipStream_t s) {
     if (m == 0) return hipSuccess;
     if (m <= kCountSortMax) {
-        hipError_t err = hipMemsetAsync(a.pr_pos, 0, m * sizeof(uint32_t), s);
-        if (err != hipSuccess) return err;
         dim3 grid((unsigned)((m + kT - 1) / kT), (unsigned)((m + kCountTile - 1) / kCountTile));
         hipLaunchKernelGGL(probe_count_kernel, grid, dim3(kT), 0, s, a.pr_key, a.pr_tag, m,
                            a.pr_pos);
@@ -633,10 +715,10 @@ hipError_t launch_rank(const RoundArgs& a, uint64_t m, uint32_t* cmat, const Fen
     if (cmat && fences.key) {
         const uint32_t cps = max_seg == 0 ? 1u : (uint32_t)((max_seg + kRankChunk - 1) / kRankChunk);
         const dim3 grid((unsigned)((uint64_t)a.p * cps));
-        hipError_t err = hipMemsetAsync(a.pr_rank, 0, m * sizeof(uint64_t), s);
-        if (err != hipSuccess) return err;
         if (a.key_bytes == 4) hipLaunchKernelGGL(rank_seg_kernel<uint32_t>, grid, dim3(256), 0, s, a, m, cps, fences, cmat);
         else hipLaunchKernelGGL(rank_seg_kernel<uint64_t>, grid, dim3(256), 0, s, a, m, cps, fences, cmat);
+        const dim3 rgrid((unsigned)((m + 255) / 256), (a.p + kReduceRows - 1) / kReduceRows);
+        hipLaunchKernelGGL(rank_reduce_kernel, rgrid, dim3(256), 0, s, (const uint32_t*)cmat, m, a.p, a.pr_rank);
         return hipGetLastError();
     }
     const dim3 grid((unsigned)m);

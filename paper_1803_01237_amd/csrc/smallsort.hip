@@ -30,6 +30,7 @@ constexpr int kCapLarge = 4096;              // same for the bucket sort
 constexpr int kCap = kCapLarge;              // the LDS-LSD kernel handles any of them
 constexpr int kRows = kCap / kT;             // rows of 64 keys per wave at kCap
 constexpr uint32_t kGroupMax = 32;           // largest group ranked by direct counting
+constexpr int kGroupBits = 9;                // bits of the second-level groups of the fast path
 
 template <typename K>
 __device__ __forceinline__ uint32_t dig(K k, int shift) {
@@ -113,12 +114,12 @@ __device__ void lds_pass(const K* sk, const uint16_t* si, K* dk, uint16_t* di, u
 }
 
 // Fast path, one workgroup per sub-bucket of at most kCap keys: keys stay in
-// registers, are dropped into their group (next 8 bits) in LDS in any order,
+// registers, are dropped into their group (next kGB bits) in LDS in any order,
 // and each key's rank inside its group is counted by (key, input index), or
 // by (key, place in the group) for keys without payload.
 // Sub-buckets with a group larger than kGroupMax go to the LDS-LSD list,
 // larger than kCap to the oversize list.
-template <typename K, bool kPayload, int kCapT>
+template <typename K, bool kPayload, int kCapT, int kGB>
 __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ kin,
                                                         const uint64_t* __restrict__ vin,
                                                         K* __restrict__ kout,
@@ -132,11 +133,13 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
                                                         const uint64_t* __restrict__ seg_off,
                                                         Fences fences) {
     constexpr int kRowsT = kCapT / kT;
+    constexpr uint32_t kG = 1u << kGB;           // groups
+    constexpr int kGR = (int)kG / kT;            // groups per thread in the scan
+    static_assert(kGR >= 1 && kGR * kT == (int)kG, "group count");
     __shared__ K Bk[kCapT];
     __shared__ uint16_t Bi[kPayload ? kCapT : 1];   // input index of each placed key
-    __shared__ uint32_t hist[256];
-    __shared__ uint32_t cursor[256];
-    __shared__ uint32_t start[257];
+    __shared__ uint32_t hist[kG];                 // group sizes
+    __shared__ uint32_t cursor[kG];               // group starts, then ends after placement
     __shared__ uint32_t scratch[kW];
     __shared__ uint32_t max_count;
 
@@ -167,8 +170,8 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     // the offsets key - kbase of this sub-bucket agree on every bit at or
     // above `bits`
     const int bits = seg_shift ? (int)seg_shift[seg] : uniform_bits;
-    const int shift2 = bits >= 8 ? bits - 8 : 0;
-    hist[threadIdx.x] = 0;
+    const int shift2 = bits >= kGB ? bits - kGB : 0;
+    for (uint32_t i = threadIdx.x; i < kG; i += kT) hist[i] = 0;
     if (threadIdx.x == 0) max_count = 0;
     __syncthreads();
     K kr[kRowsT];
@@ -184,19 +187,28 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     for (int r = 0; r < kRowsT; ++r) {
         const uint32_t i = r * kT + threadIdx.x;
         if (i < n) {
-            dr[r] = dig((K)(kr[r] - kbase), shift2);
+            dr[r] = (uint32_t)((K)(kr[r] - kbase) >> shift2) & (kG - 1);
             atomicAdd(&hist[dr[r]], 1u);
         }
     }
     __syncthreads();
     {
-        const uint32_t c = hist[threadIdx.x];
+        // thread t scans the groups [t kGR, (t+1) kGR)
+        uint32_t c[kGR], local = 0, mx = 0;
+#pragma unroll
+        for (int j = 0; j < kGR; ++j) {
+            c[j] = hist[threadIdx.x * kGR + j];
+            local += c[j];
+            mx = max(mx, c[j]);
+        }
         uint32_t all;
-        const uint32_t st = block_exclusive_scan<uint32_t, kT>(c, scratch, &all);
-        start[threadIdx.x] = st;
-        cursor[threadIdx.x] = st;
-        if (threadIdx.x == 0) start[256] = all;
-        if (c > kGroupMax) atomicMax(&max_count, c);
+        uint32_t st = block_exclusive_scan<uint32_t, kT>(local, scratch, &all);
+#pragma unroll
+        for (int j = 0; j < kGR; ++j) {
+            cursor[threadIdx.x * kGR + j] = st;
+            st += c[j];
+        }
+        if (mx > kGroupMax) atomicMax(&max_count, mx);
     }
     __syncthreads();
     if (max_count > kGroupMax) {
@@ -222,8 +234,8 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < n; e += kT) {
         const K k = Bk[e];
-        const uint32_t d = dig((K)(k - kbase), shift2);
-        const uint32_t g0 = start[d], g1 = start[d + 1];
+        const uint32_t d = (uint32_t)((K)(k - kbase) >> shift2) & (kG - 1);
+        const uint32_t g1 = cursor[d], g0 = g1 - hist[d];
         uint32_t rk = 0;
         if constexpr (kPayload) {
             // equal keys keep their input order
@@ -324,8 +336,9 @@ __global__ void ov_fence_kernel(const K* __restrict__ kout, OversizeList ov,
     }
 }
 
-// One workgroup: tile offsets of the oversize list.
-__global__ __launch_bounds__(1024) void ov_tiles_kernel(OversizeList ov) {
+// One workgroup: tile offsets of the oversize list, and the list sizes the
+// host reads back in one copy.
+__global__ __launch_bounds__(1024) void ov_tiles_kernel(OversizeList ov, SlowList sl) {
     __shared__ uint32_t scratch[1024 / kWave];
     const uint32_t E = *ov.count;
     uint32_t run = 0;
@@ -340,6 +353,10 @@ __global__ __launch_bounds__(1024) void ov_tiles_kernel(OversizeList ov) {
     if (threadIdx.x == 0) {
         ov.tile0[E] = run;
         *ov.tiles = run;
+        ov.summary[0] = E;
+        ov.summary[1] = run;
+        ov.summary[2] = *sl.count;
+        ov.summary[3] = 0;
     }
 }
 
@@ -401,7 +418,7 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     // N/(256 p) keys; bucket key ranges may use only half of the digit values
     const bool large = a.seg_base != nullptr;
 #define HSS_SMALL(KT, PAY, CAP)                                                                  \
-    hipLaunchKernelGGL((small_sort_kernel<KT, PAY, CAP>), grid, dim3(kT), 0, s,                  \
+    hipLaunchKernelGGL((small_sort_kernel<KT, PAY, CAP, kGroupBits>), grid, dim3(kT), 0, s,      \
                        (const KT*)a.keys_tmp, PAY ? a.vals_tmp : nullptr, (KT*)a.keys_out,         \
                        PAY ? a.vals_out : nullptr, a.sb_start, a.sb_len, bits, a.seg_shift,        \
                        a.seg_base, a.ov, a.sl, a.seg_off, a.fences)
@@ -415,13 +432,11 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
 #undef HSS_SMALL
     prof.end(kProfSmallSort, s, a.total_len * 2 * (a.key_bytes + (pay ? 8 : 0)));
     // 3. oversize sub-buckets: LSD passes in HBM over a compact list
-    hipLaunchKernelGGL(ov_tiles_kernel, dim3(1), dim3(1024), 0, s, a.ov);
+    hipLaunchKernelGGL(ov_tiles_kernel, dim3(1), dim3(1024), 0, s, a.ov, a.sl);
     hipLaunchKernelGGL(ov_fill_kernel, dim3(1024), dim3(256), 0, s, a.ov);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(host.pinned, a.ov.count, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(host.pinned + 1, a.ov.tiles, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(host.pinned + 2, a.sl.count, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(host.pinned, a.ov.summary, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
     const uint32_t E = host.pinned[0], T = host.pinned[1], SL = host.pinned[2];
