@@ -83,8 +83,17 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / 10
         print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": src.numel() * 8,
-                          "dispatches": 3}), flush=True)
+                          "dispatches": 13, "copy_ms": round(ms, 4),
+                          "copy_GB_per_s": round(2 * src.numel() * 8 / (ms * 1e-3) / 1e9, 1)}),
+              flush=True)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

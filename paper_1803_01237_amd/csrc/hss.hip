@@ -335,6 +335,10 @@ hss_status local_sort(hss_plan_s& P, const void* kin, const uint64_t* vin, void*
 }
 
 // Splitter rounds on the locally sorted buffer P.B; leaves chi in d_offsets.
+// Average keys per (interval, segment) slice below which the ranks are found
+// by searching the slices instead of the fences.
+constexpr uint64_t kNarrowSliceKeys = 8;
+
 hss_status determine_splitters(hss_plan_s& P, uint64_t seed, uint64_t* d_offsets, hipStream_t s) {
     RoundArgs& r = P.ra;
     P.trace.clear();
@@ -382,8 +386,13 @@ hss_status determine_splitters(hss_plan_s& P, uint64_t seed, uint64_t* d_offsets
             }
             if (P.cmat) cmat = P.cmat;
         }
+        // Once the open intervals hold few keys per segment, a search inside
+        // each probe's own interval slice reads fewer bytes than the fences
+        // of every segment chunk.
         const Fences none;
-        HIP_TRY(launch_rank(r, m, cmat, P.tune.lsd_only ? none : P.fences, P.max_seg, s));
+        const bool narrow = j > 1 && c.n_ivl > 0 &&
+                            c.domain <= kNarrowSliceKeys * (uint64_t)c.n_ivl * P.p;
+        HIP_TRY(launch_rank(r, m, cmat, (P.tune.lsd_only || narrow) ? none : P.fences, P.max_seg, s));
         HIP_TRY(launch_settle(r, m, s));
         HIP_TRY(launch_locate(r, cmat, m, s));
         RoundRecord rec;

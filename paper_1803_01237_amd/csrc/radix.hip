@@ -22,9 +22,9 @@ namespace hss {
 
 namespace {
 
-constexpr int kWavesPerTile = kSortThreads / kWave;           // 4
 constexpr int kKeysPerWave = kSortItems * kWave;              // 1024
 constexpr uint32_t kScatterTilesPerGroup = 1;                 // consecutive tiles per scatter workgroup
+constexpr int kScatterThreads = 256;                           // threads of a scatter workgroup
 
 template <typename K>
 __device__ __forceinline__ uint32_t digit_of(K k, int shift) {
@@ -142,20 +142,25 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n) {
 // equal digits keep their input order.  Otherwise one LDS atomic per key
 // hands out the slots of its digit in arbitrary order.
 template <typename K, bool kPayload, bool kStable>
-__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
+__global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
     const K* __restrict__ kin, const uint64_t* __restrict__ vin, K* __restrict__ kout,
     uint64_t* __restrict__ vout, TileMap m, int shift0, const uint8_t* __restrict__ seg_shift,
     const uint32_t* __restrict__ counts, uint32_t num_tiles) {
     static_assert(kStable || !kPayload, "a payload needs the stable placement");
+    constexpr int kWv = kScatterThreads / kWave;          // waves per tile
+    constexpr int kIt = kSortTile / kScatterThreads;      // keys per thread
+    constexpr int kKpw = kIt * kWave;                     // keys per wave
+    static_assert(kScatterThreads >= 256 && kIt * kScatterThreads == kSortTile, "tile shape");
     __shared__ uint32_t tstart[256];
     __shared__ uint32_t gofs[256];
-    __shared__ uint32_t whist[kWavesPerTile][256];
-    __shared__ uint32_t scratch[kSortThreads / kWave];
+    __shared__ uint32_t whist[kStable ? kWv : 1][256];
+    __shared__ uint32_t scratch[kScatterThreads / kWave];
     __shared__ uint64_t stage[kSortTile];
     __shared__ uint16_t sidx[kPayload ? kSortTile : 1];   // input index of each staged key
 
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
+    const bool digit_thread = threadIdx.x < 256;   // one thread per digit for the tables
     for (uint32_t sub = 0; sub < kScatterTilesPerGroup; ++sub) {
         const uint32_t tile = xcd_contiguous(blockIdx.x, gridDim.x) * kScatterTilesPerGroup + sub;
         if (tile >= num_tiles) break;   // uniform over the workgroup
@@ -168,21 +173,21 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         const uint32_t n_tile = (uint32_t)min((uint64_t)kSortTile, e - base);
 
         if (sub) __syncthreads();   // the previous tile is done with the LDS
-        for (int i = threadIdx.x; i < kWavesPerTile * 256; i += kSortThreads) (&whist[0][0])[i] = 0;
-        gofs[threadIdx.x] = counts[(uint64_t)tile * 256 + threadIdx.x];
+        for (int i = threadIdx.x; i < (kStable ? kWv : 1) * 256; i += kScatterThreads) (&whist[0][0])[i] = 0;
+        if (digit_thread) gofs[threadIdx.x] = counts[(uint64_t)tile * 256 + threadIdx.x];
         __syncthreads();
 
-        K key[kSortItems];
-        uint32_t rank[kSortItems];
+        K key[kIt];
+        uint32_t rank[kIt];
 #pragma unroll
-        for (int r = 0; r < kSortItems; ++r) {
-            const uint32_t li = w * kKeysPerWave + r * kWave + lane;
+        for (int r = 0; r < kIt; ++r) {
+            const uint32_t li = w * kKpw + r * kWave + lane;
             key[r] = li < n_tile ? kin[base + li] : (K)0;
         }
         if constexpr (kStable) {
 #pragma unroll
-            for (int r = 0; r < kSortItems; ++r) {
-                const uint32_t li = w * kKeysPerWave + r * kWave + lane;
+            for (int r = 0; r < kIt; ++r) {
+                const uint32_t li = w * kKpw + r * kWave + lane;
                 const bool valid = li < n_tile;
                 const uint32_t d = digit_of((K)(key[r] - kb), shift);
                 const uint64_t live = __ballot(valid);
@@ -200,19 +205,22 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
             {
                 const uint32_t d = threadIdx.x;
                 uint32_t c = 0;
+                if (digit_thread) {
 #pragma unroll
-                for (int ww = 0; ww < kWavesPerTile; ++ww) {
-                    const uint32_t t = whist[ww][d];
-                    whist[ww][d] = c;
-                    c += t;
+                    for (int ww = 0; ww < kWv; ++ww) {
+                        const uint32_t t = whist[ww][d];
+                        whist[ww][d] = c;
+                        c += t;
+                    }
                 }
                 uint32_t all;
-                tstart[d] = block_exclusive_scan<uint32_t, kSortThreads>(c, scratch, &all);
+                const uint32_t st = block_exclusive_scan<uint32_t, kScatterThreads>(c, scratch, &all);
+                if (digit_thread) tstart[d] = st;
             }
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < kSortItems; ++r) {
-                const uint32_t li = w * kKeysPerWave + r * kWave + lane;
+            for (int r = 0; r < kIt; ++r) {
+                const uint32_t li = w * kKpw + r * kWave + lane;
                 if (li < n_tile) {
                     const uint32_t d = digit_of((K)(key[r] - kb), shift);
                     const uint32_t pos = tstart[d] + whist[w][d] + rank[r];
@@ -223,23 +231,24 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(
         } else {
             uint32_t* hist = &whist[0][0];   // one tile-wide count per digit
 #pragma unroll
-            for (int r = 0; r < kSortItems; ++r) {
-                const uint32_t li = w * kKeysPerWave + r * kWave + lane;
+            for (int r = 0; r < kIt; ++r) {
+                const uint32_t li = w * kKpw + r * kWave + lane;
                 if (li < n_tile) rank[r] = atomicAdd(&hist[digit_of((K)(key[r] - kb), shift)], 1u);
             }
             __syncthreads();
             uint32_t all;
-            tstart[threadIdx.x] =
-                block_exclusive_scan<uint32_t, kSortThreads>(hist[threadIdx.x], scratch, &all);
+            const uint32_t st = block_exclusive_scan<uint32_t, kScatterThreads>(
+                digit_thread ? hist[threadIdx.x] : 0u, scratch, &all);
+            if (digit_thread) tstart[threadIdx.x] = st;
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < kSortItems; ++r) {
-                const uint32_t li = w * kKeysPerWave + r * kWave + lane;
+            for (int r = 0; r < kIt; ++r) {
+                const uint32_t li = w * kKpw + r * kWave + lane;
                 if (li < n_tile) stage[tstart[digit_of((K)(key[r] - kb), shift)] + rank[r]] = (uint64_t)key[r];
             }
         }
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < n_tile; i += kSortThreads) {
+        for (uint32_t i = threadIdx.x; i < n_tile; i += kScatterThreads) {
             const K k = (K)stage[i];
             const uint32_t d = digit_of((K)(k - kb), shift);
             const uint64_t dst = b + gofs[d] + (i - tstart[d]);
@@ -270,16 +279,17 @@ hipError_t pass_impl(const RadixPass& a, hipStream_t stream) {
     prof.end(kProfRadixScan, stream, 2 * table);
     prof.begin(stream);
     const dim3 sgrid((a.num_tiles + kScatterTilesPerGroup - 1) / kScatterTilesPerGroup);
+    const dim3 sblock(kScatterThreads);
     if (pay)
-        hipLaunchKernelGGL((radix_scatter_kernel<K, true, true>), sgrid, block, 0, stream,
+        hipLaunchKernelGGL((radix_scatter_kernel<K, true, true>), sgrid, sblock, 0, stream,
                            (const K*)a.keys_in, a.vals_in, (K*)a.keys_out, a.vals_out, a.map,
                            a.shift, a.seg_shift, a.counts, a.num_tiles);
     else if (a.any_order)
-        hipLaunchKernelGGL((radix_scatter_kernel<K, false, false>), sgrid, block, 0, stream,
+        hipLaunchKernelGGL((radix_scatter_kernel<K, false, false>), sgrid, sblock, 0, stream,
                            (const K*)a.keys_in, nullptr, (K*)a.keys_out, nullptr, a.map, a.shift,
                            a.seg_shift, a.counts, a.num_tiles);
     else
-        hipLaunchKernelGGL((radix_scatter_kernel<K, false, true>), sgrid, block, 0, stream,
+        hipLaunchKernelGGL((radix_scatter_kernel<K, false, true>), sgrid, sblock, 0, stream,
                            (const K*)a.keys_in, nullptr, (K*)a.keys_out, nullptr, a.map, a.shift,
                            a.seg_shift, a.counts, a.num_tiles);
     prof.end(kProfRadixScatter, stream,

@@ -263,12 +263,19 @@ __global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint64_t seed, 
         uint32_t hits = 0;   // bit q: tag 4 blk + q is a probe
         uint64_t blk = 0;
         if (b < b_hi) {
-            blk = (uint64_t)(ga >> 2) + (b - s_first);
+            // tags are below 2^32 (N < 2^32), so block and tag fit 32 bits
+            const uint32_t blk32 = (ga >> 2) + (b - s_first);
+            blk = blk32;
             const Philox4 r = sample_block(seed, blk, round);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint64_t g = blk * 4 + q;
-                if (g >= ga && g < gb && (take_all || r.v[q] < thresh)) hits |= 1u << q;
+            for (int q = 0; q < 4; ++q)
+                if (take_all || r.v[q] < thresh) hits |= 1u << q;
+            // the first and last block of a slice may hold tags outside it
+            const uint32_t g0 = blk32 * 4;
+            if (g0 < ga || (uint64_t)g0 + 4 > gb) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (g0 + q < ga || g0 + q >= gb) hits &= ~(1u << q);
             }
         }
         if (__ballot(hits != 0)) {
