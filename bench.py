@@ -34,10 +34,41 @@ WORKLOADS = {
     "zipf_morton_u64+payload_2^28_p4096": (1 << 28, 4096, 0.05, 3, 3, "zipf_morton", True),
     "uniform_u64_2^20_p16": (1 << 20, 16, 0.05, 1, 1, "uniform64", False),
 }
-# traffic factors from the FETCH_SIZE / WRITE_SIZE counters of the dominant
-# kernel, each divided by what the same counter reads for a plain copy kernel
-# of known size; None until taken for the current kernel
-TRAFFIC = None
+# Measured HBM bytes per launch of each kernel family on the uniform 2^28,
+# p=1024 partition: rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1 (KiB per
+# dispatch x 1024).  The factors are what the two counters read for a plain
+# 2 GiB device copy: FETCH_SIZE 1 GiB (x 2), WRITE_SIZE 2 GiB (x 1).  The
+# figures hold for the kernel sources with the hash below; after any change
+# to them the traffic is reported as null until the counters are taken again.
+TRAFFIC_WORKLOAD = "uniform_u64_2^28_p1024"
+TRAFFIC_SRC_SHA = "d32e61566dc0ff17"
+TRAFFIC = {   # family: (fetch bytes, write bytes) per launch
+    "radix_count": (2147704627, 67108864),
+    "radix_scan": (134383206, 70254592),
+    "radix_scatter": (2214709862, 2535529574),
+    "exchange_copy": (2344404787, 2153100185),
+    "small_sort": (2229389312, 2294237798),
+}
+
+
+def kernel_source_sha() -> str:
+    import glob
+    import hashlib
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1803_01237_amd", "csrc", "*.hip")) +
+                   glob.glob(os.path.join(ROOT, "paper_1803_01237_amd", "csrc", "*.hpp")) +
+                   [os.path.join(ROOT, "include", "hss.h")])
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, fam):
+    if workload != TRAFFIC_WORKLOAD or fam not in TRAFFIC or kernel_source_sha() != TRAFFIC_SRC_SHA:
+        return None
+    return sum(TRAFFIC[fam])
 
 
 def log(msg):
@@ -167,7 +198,8 @@ def main():
     achieved = (f_bytes / f_n) / (f_ms / f_n * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": TRAFFIC, "avg_launch_ms": round(f_ms / f_n, 4),
+            "traffic": measured_traffic(args.workload, fam), "traffic_unit": "bytes/launch",
+            "avg_launch_ms": round(f_ms / f_n, 4),
             "bytes_per_launch": f_bytes // f_n}
     stages = {f: {"ms_per_step": round(prof[f][0] / args.steps, 4),
                   "launches_per_step": prof[f][1] // args.steps,
