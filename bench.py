@@ -91,6 +91,57 @@ def cpu_baseline(kind, n_sample, p, eps, dseed, hseed, payload):
             "seconds": round(dt, 3)}
 
 
+def batched_bench(steps, count):
+    """The batched workload: `count` instances of uneven N and p (half u32,
+    half u64 keys) partitioned by one hss_batch_partition, against the same
+    instances as sequential hss_partition calls on one plan each."""
+    import torch
+    import paper_1803_01237_amd as hss
+    import synth
+    dev = torch.device("cuda:0")
+    shapes = synth.batched_shapes(count)
+    log(f"[bench] batched: {count} instances, {sum(s[0] for s in shapes)} keys")
+    keys = []
+    for sh in shapes:
+        k = synth.batched_keys(sh)
+        keys.append(torch.from_numpy(k.view(np.int64 if sh[3] == 8 else np.int32)).to(dev))
+    seeds = [sh[5] for sh in shapes]
+    kout = [torch.empty_like(k) for k in keys]
+    offs = [torch.empty(sh[1] + 1, dtype=torch.int64, device=dev) for sh in shapes]
+    total = sum(sh[0] for sh in shapes)
+    with hss.BatchPlan([(sh[0], sh[1], sh[2], sh[3]) for sh in shapes]) as bp:
+        bp.partition(keys, seeds, keys_out=kout, offsets=offs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            bp.partition(keys, seeds, keys_out=kout, offsets=offs)
+        torch.cuda.synchronize()
+        b_ms = (time.perf_counter() - t0) * 1e3 / steps
+        b_offs = [o.cpu().numpy() for o in offs]
+        ws = bp.workspace_bytes
+    plans = [hss.Plan(sh[0], sh[1], sh[2], key_bytes=sh[3]) for sh in shapes]
+    try:
+        for pl, k, sd, ko, of in zip(plans, keys, seeds, kout, offs):
+            pl.partition(k, sd, keys_out=ko, offsets=of)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for pl, k, sd, ko, of in zip(plans, keys, seeds, kout, offs):
+            pl.partition(k, sd, keys_out=ko, offsets=of)
+        torch.cuda.synchronize()
+        p_ms = (time.perf_counter() - t0) * 1e3
+        same = all(np.array_equal(a, o.cpu().numpy()) for a, o in zip(b_offs, offs))
+    finally:
+        for pl in plans:
+            pl.close()
+    return {"instances": count, "keys": total, "batched_ms": round(b_ms, 3),
+            "batched_gkeys_per_s": round(total / (b_ms * 1e-3) / 1e9, 3),
+            "plain_ms": round(p_ms, 3), "plain_gkeys_per_s": round(total / (p_ms * 1e-3) / 1e9, 3),
+            "speedup": round(p_ms / b_ms, 2), "offsets_equal": bool(same),
+            "workspace_gib": round(ws / 2**30, 2),
+            "shape": "N log-uniform on [2^12, 2^22], p log-uniform on [8, 256], eps 0.05, "
+                     "first half u32 keys, second half u64"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +153,9 @@ def main():
     ap.add_argument("--sort-steps", type=int, default=3, help="hss_sort steps timed for context")
     ap.add_argument("--op", default="partition", choices=["partition", "sort"],
                     help="operation timed as the step (the headline is partition)")
+    ap.add_argument("--batch-count", type=int, default=512,
+                    help="instances of the batched comparison (0 to skip)")
+    ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 2 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -207,6 +261,9 @@ def main():
                                if prof[f][0] > 0 and prof[f][2] else None)}
               for f in prof}
 
+    plan.close()
+    batched = batched_bench(args.batch_steps, args.batch_count) if args.batch_count > 0 else None
+
     cpu = None
     if args.cpu_sample > 0:
         log(f"[bench] CPU oracle on {args.cpu_sample} keys")
@@ -225,9 +282,9 @@ def main():
         "rounds": rounds, "probes_per_round": ms_m, "domain_per_round": domains,
         "hss_sort_ms": None if sort_ms is None else round(sort_ms, 4),
         "hss_sort_gkeys_s": None if sort_ms is None else round(n / (sort_ms * 1e-3) / 1e9, 3),
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":

@@ -13,12 +13,14 @@
  *     aligned.  Violations return HSS_ERR_INVALID_ARG before any work is
  *     enqueued.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
- *     All work is enqueued on `stream`.  The splitter rounds read a few words
- *     back to the host once per round, and hss_partition / hss_sort read the
- *     device consistency word once more at the end, so both return after
- *     their work on `stream` has completed.  Every segment sort also reads
- *     back how many of its sub-buckets overflow on-chip memory, so
- *     hss_local_sort returns after its work has completed too.
+ *     All work is enqueued on `stream`.  The splitter rounds are queued k at
+ *     a time (k of section 4.2) and read a few counter words back to the
+ *     host after them (and after every further round, if one is needed),
+ *     and hss_partition / hss_sort read the device consistency word once
+ *     more at the end, so both return after their work on `stream` has
+ *     completed.  Every segment sort also reads back how many of its
+ *     sub-buckets overflow on-chip memory, so hss_local_sort returns after
+ *     its work has completed too.
  *   - Keys are unsigned integers (32 or 64 bit) compared as unsigned.  Equal
  *     keys are ordered by (source segment, position in the segment), the
  *     implicit tags of section 6.1, which makes every result equal to what a
@@ -175,6 +177,63 @@ hss_status hss_profile(hss_plan_t plan, int enable);
 hss_status hss_profile_reset(hss_plan_t plan);
 hss_status hss_profile_read(hss_plan_t plan, uint32_t family, double* ms, uint64_t* launches,
                             uint64_t* bytes);
+
+/*
+ * Batches: many independent instances (each its own N, p, eps, key type and
+ * seed) partitioned together.  Every phase -- local sort, splitter rounds,
+ * exchange -- processes all instances of one key type in the same launches,
+ * so the per-launch and per-round costs are paid once per batch instead of
+ * once per instance.  Each instance's result is exactly what hss_partition
+ * of a plan with the same (N, p, eps, key type, payload) returns for its
+ * seed and input.
+ */
+typedef struct hss_batch_s* hss_batch_t;
+
+typedef struct {
+    uint64_t n;                 /* keys N of the instance, 1 <= p <= N      */
+    uint32_t p;                 /* segments and buckets                     */
+    hss_key_type key_type;      /* HSS_U32 or HSS_U64                       */
+    double eps;                 /* 0 < eps < 1, as in hss_plan              */
+} hss_instance_shape;
+
+typedef struct {
+    uint64_t seed;              /* Philox stream of the instance's rounds   */
+    const void* keys_in;        /* N keys                                   */
+    const uint64_t* vals_in;    /* N payload words, or NULL without payload */
+    void* keys_out;             /* N keys, bucket order as hss_partition    */
+    uint64_t* vals_out;         /* N payload words, or NULL                 */
+    uint64_t* offsets;          /* p+1 words: chi                           */
+} hss_instance_io;
+
+/*
+ * hss_batch_plan -- validate `count` instance shapes and prepare a batch:
+ * one workspace per key type present, sized for the sum of the instances.
+ * The sum of N per key type must stay below 2^32.  tuning: NULL, or knobs
+ * as for hss_plan except lsd_only and trace_level, which must be zero
+ * (HSS_ERR_UNSUPPORTED otherwise).  Errors name the failing instance.
+ */
+hss_status hss_batch_plan(hss_batch_t* out, const hss_instance_shape* shapes, uint32_t count,
+                          int with_payload, const hss_tuning* tuning);
+
+/* Release a batch and its device memory (synchronises the device). NULL is ok. */
+void hss_batch_destroy(hss_batch_t batch);
+
+/* Bytes of device memory held by the batch. */
+size_t hss_batch_workspace_bytes(hss_batch_t batch);
+
+/*
+ * hss_batch_partition -- hss_partition of every instance: io[i] holds the
+ * buffers of shape i (same conventions and checks as hss_partition, per
+ * instance).  Returns after the work on `stream` has completed.
+ */
+hss_status hss_batch_partition(hss_batch_t batch, const hss_instance_io* io, void* stream);
+
+/* Measurement of a batch, summed over its key types; families as for
+ * hss_profile_read. */
+hss_status hss_batch_profile(hss_batch_t batch, int enable);
+hss_status hss_batch_profile_reset(hss_batch_t batch);
+hss_status hss_batch_profile_read(hss_batch_t batch, uint32_t family, double* ms,
+                                  uint64_t* launches, uint64_t* bytes);
 
 const char* hss_status_string(hss_status status);
 

@@ -42,6 +42,8 @@ EXPORTS = [
     "hss_local_sort", "hss_get_constants", "hss_trace_rounds", "hss_trace_round_info",
     "hss_trace_round_probes", "hss_trace_round_state", "hss_trace_splitters",
     "hss_profile", "hss_profile_reset", "hss_profile_read",
+    "hss_batch_plan", "hss_batch_destroy", "hss_batch_workspace_bytes", "hss_batch_partition",
+    "hss_batch_profile", "hss_batch_profile_reset", "hss_batch_profile_read",
     "hss_status_string", "hss_last_error",
 ]
 
@@ -92,6 +94,31 @@ _lib.hss_profile_reset.argtypes = [_vp]
 _lib.hss_profile_reset.restype = C.c_int
 _lib.hss_profile_read.argtypes = [_vp, _u32, _vp, _vp, _vp]
 _lib.hss_profile_read.restype = C.c_int
+
+
+class _Shape(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("p", C.c_uint32), ("key_type", C.c_int), ("eps", C.c_double)]
+
+
+class _IO(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("keys_in", C.c_void_p), ("vals_in", C.c_void_p),
+                ("keys_out", C.c_void_p), ("vals_out", C.c_void_p), ("offsets", C.c_void_p)]
+
+
+_lib.hss_batch_plan.argtypes = [C.POINTER(_vp), C.POINTER(_Shape), _u32, C.c_int, C.POINTER(_Tuning)]
+_lib.hss_batch_plan.restype = C.c_int
+_lib.hss_batch_destroy.argtypes = [_vp]
+_lib.hss_batch_destroy.restype = None
+_lib.hss_batch_workspace_bytes.argtypes = [_vp]
+_lib.hss_batch_workspace_bytes.restype = C.c_size_t
+_lib.hss_batch_partition.argtypes = [_vp, C.POINTER(_IO), _vp]
+_lib.hss_batch_partition.restype = C.c_int
+_lib.hss_batch_profile.argtypes = [_vp, C.c_int]
+_lib.hss_batch_profile.restype = C.c_int
+_lib.hss_batch_profile_reset.argtypes = [_vp]
+_lib.hss_batch_profile_reset.restype = C.c_int
+_lib.hss_batch_profile_read.argtypes = [_vp, _u32, _vp, _vp, _vp]
+_lib.hss_batch_profile_read.restype = C.c_int
 _lib.hss_status_string.argtypes = [C.c_int]
 _lib.hss_status_string.restype = C.c_char_p
 _lib.hss_last_error.argtypes = []
@@ -288,6 +315,89 @@ class Plan:
         _check(_lib.hss_trace_splitters(self._h, _np_ptr(chi), _np_ptr(sk), _np_ptr(stg),
                                         _np_ptr(pieces)), "hss_trace_splitters")
         return chi, sk, stg, pieces.reshape(p + 1, p)
+
+
+class BatchPlan:
+    """Many independent instances partitioned in the same launches.
+
+    shapes: list of (n, p, eps, key_bytes).  Every call passes one
+    (keys, seed[, vals]) per instance, in the same order."""
+
+    def __init__(self, shapes, payload: bool = False, max_rounds: int = 0, k_override: int = 0,
+                 force_full_sample: bool = False):
+        self.shapes = [(int(n), int(p), float(e), int(kb)) for (n, p, e, kb) in shapes]
+        arr = (_Shape * len(self.shapes))()
+        for i, (n, p, e, kb) in enumerate(self.shapes):
+            arr[i] = _Shape(n, p, HSS_U64 if kb == 8 else HSS_U32, e)
+        tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, 0, 0)
+        h = _vp()
+        _check(_lib.hss_batch_plan(C.byref(h), arr, len(self.shapes), 1 if payload else 0,
+                                   C.byref(tun)), "hss_batch_plan")
+        self._h = h
+        self.payload = payload
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hss_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(_lib.hss_batch_workspace_bytes(self._h))
+
+    def partition(self, keys, seeds, vals=None, keys_out=None, vals_out=None, offsets=None):
+        """keys: list of device tensors (one per instance); seeds: list of ints.
+        Returns (keys_out, vals_out, offsets), lists in instance order."""
+        torch = _torch()
+        B = len(self.shapes)
+        if len(keys) != B or len(seeds) != B:
+            raise ValueError("one key tensor and one seed per instance")
+        if (vals is not None) != self.payload:
+            raise ValueError("payload presence does not match the batch")
+        keys_out = keys_out or [torch.empty_like(k) for k in keys]
+        vals_out = vals_out or ([torch.empty_like(v) for v in vals] if vals is not None else None)
+        offsets = offsets or [torch.empty(s[1] + 1, dtype=torch.int64, device=keys[0].device)
+                              for s in self.shapes]
+        io = (_IO * B)()
+        for i, (n, p, _, kb) in enumerate(self.shapes):
+            k = keys[i]
+            if (not k.is_cuda or not k.is_contiguous() or k.numel() != n
+                    or k.element_size() != kb):
+                raise ValueError(f"keys of instance {i} do not match its shape")
+            io[i] = _IO(seeds[i] & NONE, k.data_ptr(),
+                        vals[i].data_ptr() if vals is not None else None,
+                        keys_out[i].data_ptr(),
+                        vals_out[i].data_ptr() if vals_out is not None else None,
+                        offsets[i].data_ptr())
+        _check(_lib.hss_batch_partition(self._h, io, _stream_handle()), "hss_batch_partition")
+        return keys_out, vals_out, offsets
+
+    def profile(self, enable: bool = True):
+        _check(_lib.hss_batch_profile(self._h, 1 if enable else 0), "hss_batch_profile")
+
+    def profile_reset(self):
+        _check(_lib.hss_batch_profile_reset(self._h), "hss_batch_profile_reset")
+
+    def profile_read(self) -> dict:
+        out = {}
+        for i, name in enumerate(PROFILE_FAMILIES):
+            ms, n, b = C.c_double(), C.c_uint64(), C.c_uint64()
+            _check(_lib.hss_batch_profile_read(self._h, i, C.byref(ms), C.byref(n), C.byref(b)),
+                   "hss_batch_profile_read")
+            out[name] = (float(ms.value), int(n.value), int(b.value))
+        return out
 
 
 def _plan_for(keys, p, eps, vals, tuning):

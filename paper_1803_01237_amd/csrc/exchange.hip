@@ -1,15 +1,18 @@
 // Data exchange of HSS on one device (section 3.1 step 3, section 5: the
-// all-to-all becomes one bucketed scatter).
+// all-to-all becomes one bucketed scatter), for every instance of a plan.
 //
-// Piece (b, s) is the run [P(b, s), P(b+1, s)) of locally sorted segment s,
-// with P(b, s) = c_s(S(b)), P(0, s) = 0 and P(p, s) = |segment s|.  Bucket b
-// receives its pieces in ascending s, starting at chi(b).
+// Piece (b, s) of an instance is the run [P(b, s), P(b+1, s)) of its locally
+// sorted segment s, with P(b, s) = c_s(S(b)), P(0, s) = 0 and P(p, s) =
+// |segment s|.  Bucket b receives its pieces in ascending s, starting at
+// chi(b).  Buckets are numbered like segments (instance I's bucket b is
+// seg0 + b).
 //   offsets -- workgroup per bucket: exclusive scan of piece lengths over s,
-//              checked against chi(b+1) - chi(b)
-//   copy    -- workgroup per (bucket, chunk of 4096 outputs): the pieces that
-//              cover the chunk are staged in LDS; every output element finds
-//              its piece by binary search there and copies one key (and
-//              payload); consecutive lanes write consecutive outputs.
+//              checked against chi(b+1) - chi(b); copy workgroups per bucket
+//   scan    -- one workgroup: first copy workgroup of every bucket
+//   copy    -- workgroup per 4096 outputs of a bucket: the pieces that cover
+//              them are staged in LDS; every output element finds its piece
+//              by binary search there and copies one key (and payload);
+//              consecutive lanes write consecutive outputs.
 
 #include "device.hpp"
 #include "internal.hpp"
@@ -19,35 +22,59 @@ namespace hss {
 namespace {
 
 constexpr int kT = 256;
+constexpr int kScanT = 1024;
 constexpr int kChunk = 4096;
 constexpr int kWindow = kChunk + 1;    // at most kChunk non-empty pieces meet a chunk
 
-__device__ __forceinline__ uint64_t piece_start(const ExchangeArgs& a, uint32_t b, uint32_t s) {
+__device__ __forceinline__ uint64_t piece_start(const ExchangeArgs& a, const InstDesc& D,
+                                                uint32_t b, uint32_t s) {
     if (b == 0) return 0;
-    if (b == a.p) return a.seg_off[s + 1] - a.seg_off[s];
-    return a.prow[(uint64_t)b * a.p + s];
+    if (b == D.p) return a.seg_off[D.seg0 + s + 1] - a.seg_off[D.seg0 + s];
+    return a.prow[D.tab0 + (uint64_t)b * D.p + s];
 }
 
 __global__ __launch_bounds__(kT) void piece_offsets_kernel(ExchangeArgs a) {
     __shared__ uint64_t scratch[kT / kWave];
-    const uint32_t b = blockIdx.x;
+    const uint32_t u = blockIdx.x;
+    const InstDesc D = a.inst[a.seg_inst[u]];
+    const uint32_t b = u - D.seg0;
     uint64_t run = 0;
     bool bad = false;
-    for (uint32_t s0 = 0; s0 < a.p; s0 += kT) {
+    for (uint32_t s0 = 0; s0 < D.p; s0 += kT) {
         const uint32_t s = s0 + threadIdx.x;
         uint64_t len = 0;
-        if (s < a.p) {
-            const uint64_t x0 = piece_start(a, b, s), x1 = piece_start(a, b + 1, s);
+        if (s < D.p) {
+            const uint64_t x0 = piece_start(a, D, b, s), x1 = piece_start(a, D, b + 1, s);
             if (x1 < x0) bad = true; else len = x1 - x0;
         }
         uint64_t tot;
         const uint64_t pre = block_exclusive_scan<uint64_t, kT>(len, scratch, &tot);
-        if (s < a.p) a.dst[(uint64_t)b * a.p + s] = (uint32_t)(run + pre);
+        if (s < D.p) a.dst[D.tab0 + (uint64_t)b * D.p + s] = (uint32_t)(run + pre);
         run += tot;
     }
-    const uint64_t blen = a.chi[b + 1] - a.chi[b];
-    if (bad || (threadIdx.x == 0 && (run != blen || blen > a.max_bucket)))
+    const uint64_t blen = a.chi_all[D.row0 + b + 1] - a.chi_all[D.row0 + b];
+    const uint64_t max_bucket = (D.n + D.p - 1) / D.p + 2 * D.tol;
+    if (bad || (threadIdx.x == 0 && (run != blen || blen > max_bucket)))
         atomicOr(a.err, kErrPieceSum);
+    if (threadIdx.x == 0) a.chunk0[u] = (uint32_t)((min(blen, max_bucket) + kChunk - 1) / kChunk);
+}
+
+// One workgroup: exclusive scan of the copy workgroups per bucket.
+__global__ __launch_bounds__(kScanT) void chunk_scan_kernel(ExchangeArgs a) {
+    __shared__ uint64_t scratch[kScanT / kWave];
+    const uint32_t n = a.n_segs;
+    const uint32_t per = (n + kScanT - 1) / kScanT;
+    const uint32_t r0 = min(threadIdx.x * per, n), r1 = min(r0 + per, n);
+    uint64_t local = 0;
+    for (uint32_t i = r0; i < r1; ++i) local += a.chunk0[i];
+    uint64_t tot;
+    uint64_t run = block_exclusive_scan<uint64_t, kScanT>(local, scratch, &tot);
+    for (uint32_t i = r0; i < r1; ++i) {
+        const uint64_t x = a.chunk0[i];
+        a.chunk0[i] = (uint32_t)run;
+        run += x;
+    }
+    if (threadIdx.x == 0) a.chunk0[n] = (uint32_t)tot;
 }
 
 // Last index in [lo, hi) of v with v[i] <= x (v[lo] <= x).
@@ -61,56 +88,68 @@ __device__ __forceinline__ uint32_t last_le_u32(const uint32_t* v, uint32_t lo, 
 }
 
 template <typename K, bool kPayload>
-__global__ __launch_bounds__(kT) void exchange_copy_kernel(ExchangeArgs a, uint32_t chunks,
-                                                           uint32_t window) {
+__global__ __launch_bounds__(kT) void exchange_copy_kernel(ExchangeArgs a, uint32_t window) {
     // window entries: piece start inside the bucket, source position of the piece
     extern __shared__ uint64_t smem[];
     uint64_t* w_src = smem;
     uint32_t* w_off = (uint32_t*)(smem + window);
     __shared__ uint32_t sh_first, sh_count;
-    const uint32_t b = blockIdx.x / chunks;
-    const uint32_t c = blockIdx.x % chunks;
-    const uint64_t bstart = a.chi[b];
-    const uint64_t blen = a.chi[b + 1] - bstart;
-    const uint64_t r0 = (uint64_t)c * kChunk;
-    if (r0 >= blen) return;
-    const uint32_t r1 = (uint32_t)min(blen, r0 + kChunk);
-    const uint32_t* row = a.dst + (uint64_t)b * a.p;
+    const uint32_t t = blockIdx.x;
+    if (t >= a.chunk0[a.n_segs]) return;
+    const uint32_t u = last_le_u32(a.chunk0, 0, a.n_segs, t);
+    const InstDesc D = a.inst[a.seg_inst[u]];
+    const uint32_t b = u - D.seg0;
+    const uint64_t bstart = a.chi_all[D.row0 + b];
+    const uint64_t blen = a.chi_all[D.row0 + b + 1] - bstart;
+    const uint64_t r0 = (uint64_t)(t - a.chunk0[u]) * kChunk;
+    // a consistent state has bstart + blen <= n; the bounds only keep an
+    // inconsistent one (reported through err) inside the instance
+    if (r0 >= blen || bstart + r0 >= D.n) return;
+    const uint32_t r1 = (uint32_t)min(min(blen, r0 + kChunk), D.n - bstart);
+    const uint32_t* row = a.dst + D.tab0 + (uint64_t)b * D.p;
     if (threadIdx.x == 0) {
-        const uint32_t first = last_le_u32(row, 0, a.p, (uint32_t)r0);
-        const uint32_t last = last_le_u32(row, first, a.p, r1 - 1);
+        const uint32_t first = last_le_u32(row, 0, D.p, (uint32_t)r0);
+        const uint32_t last = last_le_u32(row, first, D.p, r1 - 1);
         sh_first = first;
         sh_count = last - first + 1;
     }
     __syncthreads();
     const uint32_t first = sh_first, cnt = sh_count;
     const K* B = (const K*)a.B;
-    K* out = (K*)a.out;
+    K* out;
+    uint64_t* vout;
+    if (a.out) {
+        out = (K*)a.out + D.pos0 + bstart;
+        vout = kPayload ? a.vout + D.pos0 + bstart : nullptr;
+    } else {
+        const InstRun& R = a.run[a.seg_inst[u]];
+        out = (K*)R.kout + bstart;
+        vout = kPayload ? R.vout + bstart : nullptr;
+    }
+    // a consistent state keeps every source inside its segment; the clamp only
+    // keeps an inconsistent one (reported through err) inside the instance
+    const uint64_t src_max = D.pos0 + D.n - 1;
     if (cnt > window) {
         // many empty pieces in the window: search the bucket's row directly
         for (uint32_t r = (uint32_t)r0 + threadIdx.x; r < r1; r += kT) {
             const uint32_t s = last_le_u32(row, first, first + cnt, r);
-            const uint64_t src = min(a.seg_off[s] + piece_start(a, b, s) + (r - row[s]), a.n - 1);
-            if (bstart + r >= a.n) break;
-            out[bstart + r] = B[src];
-            if constexpr (kPayload) a.vout[bstart + r] = a.Bv[src];
+            const uint64_t src = min(a.seg_off[D.seg0 + s] + piece_start(a, D, b, s) + (r - row[s]), src_max);
+            out[r] = B[src];
+            if constexpr (kPayload) vout[r] = a.Bv[src];
         }
         return;
     }
     for (uint32_t i = threadIdx.x; i < cnt; i += kT) {
         const uint32_t s = first + i;
         w_off[i] = row[s];
-        w_src[i] = a.seg_off[s] + piece_start(a, b, s);
+        w_src[i] = a.seg_off[D.seg0 + s] + piece_start(a, D, b, s);
     }
     __syncthreads();
     for (uint32_t r = (uint32_t)r0 + threadIdx.x; r < r1; r += kT) {
         const uint32_t j = last_le_u32(w_off, 0, cnt, r);
-        // a consistent state keeps src inside segment s; the clamps only keep an
-        // inconsistent one (reported through err) inside the buffers
-        const uint64_t src = min(w_src[j] + (r - w_off[j]), a.n - 1);
-        if (bstart + r >= a.n) break;
-        out[bstart + r] = B[src];
-        if constexpr (kPayload) a.vout[bstart + r] = a.Bv[src];
+        const uint64_t src = min(w_src[j] + (r - w_off[j]), src_max);
+        out[r] = B[src];
+        if constexpr (kPayload) vout[r] = a.Bv[src];
     }
 }
 
@@ -136,30 +175,33 @@ hipError_t launch_bucket_shift(uint32_t p, int key_bits, const uint64_t* s_key, 
     return hipGetLastError();
 }
 
+uint64_t exchange_chunk_bound(uint64_t total, uint32_t buckets) {
+    return total / kChunk + buckets + 1;
+}
+
 hipError_t launch_exchange(const ExchangeArgs& a, hipStream_t s) {
     Profiler dummy;
     Profiler& prof = a.prof ? *a.prof : dummy;
-    const uint64_t pp = (uint64_t)a.p * a.p;
+    if (a.n_segs == 0) return hipSuccess;
     prof.begin(s);
-    hipLaunchKernelGGL(piece_offsets_kernel, dim3(a.p), dim3(kT), 0, s, a);
-    prof.end(kProfExchangeOffsets, s, pp * 4 * 3);
-    const uint32_t chunks = (uint32_t)((a.max_bucket + kChunk - 1) / kChunk);
-    if (chunks == 0) return hipGetLastError();
-    const dim3 grid((unsigned)((uint64_t)a.p * chunks));
+    hipLaunchKernelGGL(piece_offsets_kernel, dim3(a.n_segs), dim3(kT), 0, s, a);
+    hipLaunchKernelGGL(chunk_scan_kernel, dim3(1), dim3(kScanT), 0, s, a);
+    prof.end(kProfExchangeOffsets, s, 0);
+    const dim3 grid((unsigned)a.max_chunks);
     const bool pay = a.Bv != nullptr;
     // LDS window: the pieces meeting one chunk, at most p and at most kWindow
-    const uint32_t window = a.p < (uint32_t)kWindow ? a.p : (uint32_t)kWindow;
+    const uint32_t window = a.p_max < (uint32_t)kWindow ? a.p_max : (uint32_t)kWindow;
     const size_t lds = (size_t)window * (8 + 4);
     // algorithmic bytes: every key (and payload word) read once and written once
     prof.begin(s);
     if (a.key_bytes == 4) {
-        if (pay) hipLaunchKernelGGL((exchange_copy_kernel<uint32_t, true>), grid, dim3(kT), lds, s, a, chunks, window);
-        else hipLaunchKernelGGL((exchange_copy_kernel<uint32_t, false>), grid, dim3(kT), lds, s, a, chunks, window);
+        if (pay) hipLaunchKernelGGL((exchange_copy_kernel<uint32_t, true>), grid, dim3(kT), lds, s, a, window);
+        else hipLaunchKernelGGL((exchange_copy_kernel<uint32_t, false>), grid, dim3(kT), lds, s, a, window);
     } else {
-        if (pay) hipLaunchKernelGGL((exchange_copy_kernel<uint64_t, true>), grid, dim3(kT), lds, s, a, chunks, window);
-        else hipLaunchKernelGGL((exchange_copy_kernel<uint64_t, false>), grid, dim3(kT), lds, s, a, chunks, window);
+        if (pay) hipLaunchKernelGGL((exchange_copy_kernel<uint64_t, true>), grid, dim3(kT), lds, s, a, window);
+        else hipLaunchKernelGGL((exchange_copy_kernel<uint64_t, false>), grid, dim3(kT), lds, s, a, window);
     }
-    prof.end(kProfExchangeCopy, s, a.n * 2 * (a.key_bytes + (pay ? 8 : 0)));
+    prof.end(kProfExchangeCopy, s, a.total * 2 * (a.key_bytes + (pay ? 8 : 0)));
     return hipGetLastError();
 }
 

@@ -1,10 +1,15 @@
-// libhss: plan, executor and C ABI of Histogram Sort with Sampling on one
-// device.  The host drives the splitter rounds (one small read-back per
-// round); every step on the data runs in the kernels of radix.hip,
-// rounds.hip and exchange.hip.
+// libhss: plans, executor and C ABI of Histogram Sort with Sampling on one
+// device.  An engine holds one or more independent instances with the same
+// key type; every phase (local sort, splitter rounds, exchange) runs all of
+// them in the same launches.  hss_plan is an engine of one instance;
+// hss_batch_plan groups a list of instances into one engine per key type.
+// The splitter rounds are queued without waiting: the host reads the round
+// counters back once after the expected number of rounds (and once per
+// further round in the rare case that more are needed).
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -36,8 +41,8 @@ hss_status fail(hss_status st, const std::string& msg) {
 
 typedef unsigned __int128 u128;
 
-// largest per-round probe x segment count matrix kept on the device (words)
-constexpr uint64_t kCountMatrixBudget = 1ull << 27;
+constexpr uint32_t kMaxRestarts = 8;     // capacity growths per call
+constexpr uint32_t kMaxRateRounds = 64;  // rounds kept in the rate table
 
 struct RoundRecord {
     uint64_t domain = 0, m = 0;
@@ -60,183 +65,43 @@ struct Arena {
     }
 };
 
-}  // namespace
-
-struct hss_plan_s {
+// Host view of one instance.
+struct InstHost {
     uint64_t n = 0;
     uint32_t p = 0;
     double eps = 0;
-    int key_bytes = 8;
-    bool payload = false;
-    hss_tuning tune{};
-    int device = 0;
-
-    // constants (section 2 and section 4.2)
-    uint64_t tol = 0;
-    uint32_t k = 1;
-    double a = 0;
-    uint64_t max_seg = 0;      // ceil(N / p)
-    uint64_t max_bucket = 0;   // ceil(N / p) + 2 tol
-
-    // device memory
-    void* arena = nullptr;
-    size_t arena_bytes = 0;
-    void* B = nullptr;  uint64_t* Bv = nullptr;
-    void* A = nullptr;  uint64_t* Av = nullptr;
-    uint64_t* seg_off = nullptr;
-    uint64_t* ideal = nullptr;
-    uint32_t* counts = nullptr;
-    RoundArgs ra{};
-    uint32_t* dst = nullptr;
-    RoundCounters* h_ctr = nullptr;   // pinned host copy
-
-    // growable probe storage
-    void* probe_mem = nullptr;
-    size_t probe_bytes = 0;
-    uint64_t cap = 0;
-    void* sort_scratch = nullptr;
-    size_t sort_scratch_bytes = 0;
-
-    std::vector<RoundRecord> trace;
-    Profiler prof;
-
-    // per-probe segment counts of the current round (grown on demand)
-    uint32_t* cmat = nullptr;
-    uint64_t cmat_words = 0;
-    uint8_t* bucket_shift = nullptr;
-    uint64_t* bucket_base = nullptr;
-    Fences fences;                    // of B, written by the local sort of hss_partition/hss_sort
-
-    // hybrid sort state
-    uint64_t* sb_start = nullptr;
-    uint32_t* sb_len = nullptr;
-    OversizeList ov;
-    SlowList sl;
-    HybridHost hh;
+    uint64_t tol = 0;     // section 2: the target range is N i/p +- tol
+    uint32_t k = 1;       // rounds of the rate schedule (section 4.2)
+    double a = 0;         // s_k = 2 ln p / eps
+    uint64_t pos0 = 0, tab0 = 0;
+    uint32_t seg0 = 0, row0 = 0;
+    uint64_t max_seg = 0, max_bucket = 0;
 };
 
-namespace {
-
-void compute_constants(hss_plan_s& P) {
-    const double nd = (double)P.n, pd = (double)P.p;
-    P.tol = (uint64_t)std::floor((nd * P.eps) / (2.0 * pd));
-    P.a = (2.0 * std::log(pd)) / P.eps;
-    const double kk = std::ceil(std::log(P.a));
-    P.k = (kk >= 1.0) ? (uint32_t)kk : 1u;
-    if (P.tune.k_override) P.k = P.tune.k_override;
-    P.max_seg = (P.n + P.p - 1) / P.p;
-    P.max_bucket = P.max_seg + 2 * P.tol;
+void instance_constants(InstHost& h, const hss_tuning& t) {
+    const double nd = (double)h.n, pd = (double)h.p;
+    h.tol = (uint64_t)std::floor((nd * h.eps) / (2.0 * pd));
+    h.a = (2.0 * std::log(pd)) / h.eps;
+    const double kk = std::ceil(std::log(h.a));
+    h.k = (kk >= 1.0) ? (uint32_t)kk : 1u;
+    if (t.k_override) h.k = t.k_override;
+    h.max_seg = (h.n + h.p - 1) / h.p;
+    h.max_bucket = h.max_seg + 2 * h.tol;
 }
 
 // Acceptance rule of round j: rate q_j = p s_j / N with s_j = a^(j/k),
 // clamped at 1 ("take all").
-void round_rate(const hss_plan_s& P, uint32_t j, bool forced, uint32_t* thresh, int* all) {
-    const double s_j = std::pow(P.a, (double)j / (double)P.k);
-    const double q = ((double)P.p * s_j) / (double)P.n;
-    if (q >= 1.0 || (forced && j == 1 && P.tune.force_full_sample)) {
+void round_rate(const InstHost& h, const hss_tuning& t, uint32_t j, bool forced, uint32_t* thresh,
+                int* all) {
+    const double s_j = std::pow(h.a, (double)j / (double)h.k);
+    const double q = ((double)h.p * s_j) / (double)h.n;
+    if (q >= 1.0 || (forced && j == 1 && t.force_full_sample)) {
         *thresh = 0xFFFFFFFFu;
         *all = 1;
     } else {
         *thresh = (uint32_t)std::floor(q * 4294967296.0);
         *all = 0;
     }
-}
-
-size_t layout(hss_plan_s& P, char* base) {
-    Arena ar;
-    ar.base = base;
-    const uint64_t n = P.n, p = P.p;
-    P.B = ar.take<char>(n * P.key_bytes);
-    P.A = ar.take<char>(n * P.key_bytes);
-    P.Bv = P.payload ? ar.take<uint64_t>(n) : nullptr;
-    P.Av = P.payload ? ar.take<uint64_t>(n) : nullptr;
-    P.seg_off = ar.take<uint64_t>(p + 1);
-    P.ideal = ar.take<uint64_t>(p + 1);
-    P.counts = ar.take<uint32_t>(radix_count_words((uint32_t)p, P.max_bucket > P.max_seg ? P.max_bucket : P.max_seg));
-    RoundArgs& r = P.ra;
-    r.settled = ar.take<uint32_t>(p + 1);
-    r.chi = ar.take<uint64_t>(p + 1);
-    r.lrank = ar.take<uint64_t>(p + 1);
-    r.urank = ar.take<uint64_t>(p + 1);
-    r.s_key = ar.take<uint64_t>(p + 1);
-    r.s_tag = ar.take<uint64_t>(p + 1);
-    r.lpos = ar.take<uint32_t>((p + 1) * p);
-    r.upos = ar.take<uint32_t>((p + 1) * p);
-    r.prow = ar.take<uint32_t>((p + 1) * p);
-    r.ivl_row = ar.take<uint32_t>(p);
-    r.slices = ar.take<uint4>(p * p);
-    r.ivl_nz = ar.take<uint32_t>(p + 1);
-    r.ivl_tot = ar.take<uint64_t>(p + 1);
-    r.ivl_dom = ar.take<uint64_t>(p);
-    r.req_probe = ar.take<uint32_t>(2 * p);
-    r.req_row = ar.take<uint32_t>(2 * p);
-    r.req_kind = ar.take<uint32_t>(2 * p);
-    r.ctr = ar.take<RoundCounters>(1);
-    P.dst = (uint32_t*)r.slices;   // p x p words; the exchange runs after the last round
-    P.fences.per_seg = (P.max_seg + kFenceStride - 1) / kFenceStride;
-    P.fences.key = ar.take<uint64_t>(p * P.fences.per_seg);
-    P.bucket_shift = ar.take<uint8_t>(p);
-    P.bucket_base = ar.take<uint64_t>(p);
-    P.sb_start = ar.take<uint64_t>(p * 256);
-    P.sb_len = ar.take<uint32_t>(p * 256);
-    const uint64_t ovc = oversize_capacity((uint32_t)p, n);
-    P.ov.count = ar.take<uint32_t>(1);
-    P.ov.tiles = ar.take<uint32_t>(1);
-    P.ov.summary = ar.take<uint32_t>(4);
-    P.ov.beg = ar.take<uint64_t>(ovc);
-    P.ov.end = ar.take<uint64_t>(ovc);
-    P.ov.base = ar.take<uint64_t>(ovc);
-    P.ov.seg = ar.take<uint32_t>(ovc);
-    P.ov.tile0 = ar.take<uint32_t>(ovc + 1);
-    P.ov.tile_seg = ar.take<uint32_t>(oversize_tile_capacity((uint32_t)p, n));
-    const uint64_t slc = slow_capacity((uint32_t)p, n);
-    P.sl.count = ar.take<uint32_t>(1);
-    P.sl.beg = ar.take<uint64_t>(slc);
-    P.sl.len = ar.take<uint32_t>(slc);
-    P.sl.bits = ar.take<uint8_t>(slc);
-    P.sl.base = ar.take<uint64_t>(slc);
-    P.sl.seg = ar.take<uint32_t>(slc);
-    return ar.used;
-}
-
-hss_status grow_probes(hss_plan_s& P, uint64_t need) {
-    if (need <= P.cap && P.probe_mem) return HSS_OK;
-    uint64_t cap = P.cap ? P.cap : 4096;
-    while (cap < need) cap *= 2;
-    if (P.probe_mem) HIP_TRY(hipFree(P.probe_mem));
-    P.probe_mem = nullptr;
-    Arena ar;
-    ar.base = nullptr;
-    ar.take<uint64_t>(cap); ar.take<uint64_t>(cap); ar.take<uint32_t>(cap);
-    ar.take<uint64_t>(cap); ar.take<uint64_t>(cap); ar.take<uint32_t>(cap);
-    ar.take<uint64_t>(cap); ar.take<uint32_t>(cap); ar.take<uint32_t>(cap);
-    P.probe_bytes = ar.used + 256;
-    HIP_TRY(hipMalloc(&P.probe_mem, P.probe_bytes));
-    ar.base = (char*)P.probe_mem;
-    ar.used = 0;
-    RoundArgs& r = P.ra;
-    r.pr_key = ar.take<uint64_t>(cap);
-    r.pr_tag = ar.take<uint64_t>(cap);
-    r.pr_ivl = ar.take<uint32_t>(cap);
-    r.ps_key = ar.take<uint64_t>(cap);
-    r.ps_tag = ar.take<uint64_t>(cap);
-    r.ps_ivl = ar.take<uint32_t>(cap);
-    r.pr_rank = ar.take<uint64_t>(cap);
-    r.pr_pos = ar.take<uint32_t>(cap);
-    r.ps_seg = ar.take<uint32_t>(cap);
-    r.cap = cap;
-    P.cap = cap;
-    return HSS_OK;
-}
-
-hss_status ensure_sort_scratch(hss_plan_s& P, uint64_t m) {
-    const size_t need = probe_sort_scratch_bytes(m);
-    if (need <= P.sort_scratch_bytes) return HSS_OK;
-    if (P.sort_scratch) HIP_TRY(hipFree(P.sort_scratch));
-    P.sort_scratch = nullptr;
-    HIP_TRY(hipMalloc(&P.sort_scratch, need));
-    P.sort_scratch_bytes = need;
-    return HSS_OK;
 }
 
 bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15u) == 0; }
@@ -247,25 +112,452 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
     return x < y + nb && y < x + na;
 }
 
-hss_status check_io(const hss_plan_s* P, const void* kin, const uint64_t* vin, const void* kout,
-                    const uint64_t* vout, const uint64_t* offsets) {
-    if (!P) return fail(HSS_ERR_INVALID_ARG, "null plan");
-    if (!kin || !kout) return fail(HSS_ERR_INVALID_ARG, "null key pointer");
-    if (P->payload != (vin != nullptr) || P->payload != (vout != nullptr))
-        return fail(HSS_ERR_INVALID_ARG, "payload pointers must be given iff the plan has a payload");
-    const void* ptrs[] = {kin, vin, kout, vout, offsets};
-    for (const void* q : ptrs)
-        if (q && !aligned16(q)) return fail(HSS_ERR_INVALID_ARG, "device pointers must be 16-byte aligned");
-    const size_t kb = P->n * P->key_bytes, vb = P->n * 8, ob = (P->p + 1) * 8;
-    if (overlap(kin, kb, kout, kb) || overlap(kin, kb, vout, vb) || overlap(vin, vb, kout, kb) ||
-        overlap(vin, vb, vout, vb) || overlap(offsets, ob, kin, kb) || overlap(offsets, ob, kout, kb) ||
-        overlap(offsets, ob, vin, vb) || overlap(offsets, ob, vout, vb) || overlap(kout, kb, vout, vb))
-        return fail(HSS_ERR_INVALID_ARG, "outputs overlap inputs or each other");
+}  // namespace
+
+// ------------------------------------------------------------- engine ----
+struct Engine {
+    int key_bytes = 8;
+    bool payload = false;
+    hss_tuning tune{};
+    int device = 0;
+    std::vector<InstHost> ih;
+    uint64_t n_tot = 0;
+    uint32_t S = 0, Q = 0;    // segments, splitter rows
+    uint64_t T = 0;           // entries of the (p+1) x p tables
+    uint32_t p_max = 0, J = 1, k_max = 1;
+    uint64_t max_seg = 0, max_bucket = 0;
+    // engines of a batch read their inputs through per-segment source
+    // addresses; segments above kDirectSegMax take the MSD pass from a list,
+    // the others are sorted whole
+    bool batch = false;
+    bool listed = false;
+    uint32_t n_msd = 0, msd_tiles = 0, n_direct = 0, n_chunks = 0;
+    uint64_t n_fences = 0;
+
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    void* B = nullptr;  uint64_t* Bv = nullptr;
+    void* A = nullptr;  uint64_t* Av = nullptr;
+    uint64_t* seg_off = nullptr;
+    uint32_t* seg_inst = nullptr;
+    uint32_t* row_inst = nullptr;
+    uint64_t* ideal = nullptr;
+    InstDesc* inst_d = nullptr;
+    InstRun* run_d = nullptr;
+    uint32_t* thresh_d = nullptr;
+    uint8_t* all_d = nullptr;
+    uint32_t* counts = nullptr;
+    RoundArgs ra{};
+    uint64_t* chi_all = nullptr;
+    uint32_t* dst = nullptr;
+    uint32_t* chunk0 = nullptr;
+    Fences fences;
+    uint64_t* fence_base = nullptr;
+    uint32_t* chunk_seg = nullptr;
+    uint32_t* chunk_lo = nullptr;
+    uint8_t* bucket_shift = nullptr;
+    uint64_t* bucket_base = nullptr;
+    uint64_t* sb_start = nullptr;
+    uint32_t* sb_len = nullptr;
+    OversizeList ov;
+    SlowList sl;
+    HybridHost hh;
+    uint32_t* msd_seg = nullptr;
+    uint64_t* msd_beg = nullptr;
+    uint64_t* msd_end = nullptr;
+    uint32_t* msd_tile_seg = nullptr;
+    uint32_t* msd_tile0 = nullptr;
+    uint32_t* direct_seg = nullptr;
+    uint64_t* msd_src = nullptr;
+    uint64_t* msd_vsrc = nullptr;
+    uint64_t* direct_src = nullptr;
+    uint64_t* direct_vsrc = nullptr;
+
+    // probes and count matrix, grown on demand
+    void* probe_mem = nullptr;
+    size_t probe_bytes = 0;
+    uint64_t cap = 0;
+    uint32_t* cmat = nullptr;
+    uint64_t cm_cap = 0;
+
+    RoundCounters* h_ctr = nullptr;   // pinned; 16 more bytes for the sort's read-back
+    InstRun* h_run = nullptr;         // pinned
+    RoundHist* h_hist = nullptr;      // pinned, J entries
+    std::vector<RoundRecord> trace;
+    Profiler prof;
+
+    ~Engine() {
+        (void)hipSetDevice(device);
+        (void)hipDeviceSynchronize();
+        if (probe_mem) (void)hipFree(probe_mem);
+        if (cmat) (void)hipFree(cmat);
+        if (hh.fb_counts) (void)hipFree(hh.fb_counts);
+        if (arena) (void)hipFree(arena);
+        if (h_ctr) (void)hipHostFree(h_ctr);
+        if (h_run) (void)hipHostFree(h_run);
+        if (h_hist) (void)hipHostFree(h_hist);
+    }
+};
+
+struct hss_plan_s {
+    Engine e;
+};
+
+struct hss_batch_s {
+    Engine* eng[2] = {nullptr, nullptr};   // u32 instances, u64 instances
+    std::vector<std::pair<int, uint32_t>> where;   // instance -> (engine, index in it)
+    ~hss_batch_s() {
+        delete eng[0];
+        delete eng[1];
+    }
+};
+
+namespace {
+
+// Host tables of the instance layout (positions, segments, rows, lists).
+struct Layout {
+    std::vector<uint64_t> seg_off, ideal, fence_base, msd_beg, msd_end;
+    std::vector<uint32_t> seg_inst, row_inst, chunk_seg, chunk_lo, msd_seg, msd_tile_seg, msd_tile0,
+        direct_seg, thresh;
+    std::vector<uint8_t> all;
+    std::vector<InstDesc> inst;
+};
+
+void build_layout(Engine& E, Layout& L) {
+    const uint32_t B = (uint32_t)E.ih.size();
+    uint64_t pos = 0, tab = 0;
+    uint32_t seg = 0, row = 0;
+    E.p_max = 0;
+    E.k_max = 1;
+    E.max_seg = 0;
+    E.max_bucket = 0;
+    for (InstHost& h : E.ih) {
+        h.pos0 = pos;
+        h.seg0 = seg;
+        h.row0 = row;
+        h.tab0 = tab;
+        pos += h.n;
+        seg += h.p;
+        row += h.p + 1;
+        tab += (uint64_t)(h.p + 1) * h.p;
+        E.p_max = std::max(E.p_max, h.p);
+        E.k_max = std::max(E.k_max, h.k);
+        E.max_seg = std::max(E.max_seg, h.max_seg);
+        E.max_bucket = std::max(E.max_bucket, h.max_bucket);
+    }
+    E.n_tot = pos;
+    E.S = seg;
+    E.Q = row;
+    E.T = tab;
+    E.listed = E.batch;
+    L.seg_off.assign(E.S + 1, 0);
+    L.seg_inst.assign(E.S, 0);
+    L.row_inst.assign(E.Q, 0);
+    L.ideal.assign(E.Q, 0);
+    L.inst.assign(B, InstDesc{});
+    for (uint32_t I = 0; I < B; ++I) {
+        const InstHost& h = E.ih[I];
+        // segment boundaries floor(s N / p) and ideal ranks floor(i N / p):
+        // the same integers (section 2)
+        for (uint32_t s = 0; s < h.p; ++s) {
+            L.seg_off[h.seg0 + s] = h.pos0 + (uint64_t)(((u128)s * h.n) / h.p);
+            L.seg_inst[h.seg0 + s] = I;
+        }
+        for (uint32_t i = 0; i <= h.p; ++i) {
+            L.row_inst[h.row0 + i] = I;
+            L.ideal[h.row0 + i] = (uint64_t)(((u128)i * h.n) / h.p);
+        }
+        InstDesc& d = L.inst[I];
+        d.n = h.n;
+        d.pos0 = h.pos0;
+        d.tol = h.tol;
+        d.tab0 = h.tab0;
+        d.p = h.p;
+        d.seg0 = h.seg0;
+        d.row0 = h.row0;
+        d.pad = 0;
+    }
+    L.seg_off[E.S] = E.n_tot;
+    // fences and rank chunks of every segment
+    L.fence_base.assign(E.S + 1, 0);
+    L.chunk_seg.clear();
+    L.chunk_lo.clear();
+    for (uint32_t s = 0; s < E.S; ++s) {
+        const uint64_t len = L.seg_off[s + 1] - L.seg_off[s];
+        L.fence_base[s + 1] = L.fence_base[s] + (len + kFenceStride - 1) / kFenceStride;
+        for (uint64_t lo = 0; lo < len; lo += kRankChunk) {
+            L.chunk_seg.push_back(s);
+            L.chunk_lo.push_back((uint32_t)lo);
+        }
+    }
+    E.n_fences = L.fence_base[E.S];
+    E.n_chunks = (uint32_t)L.chunk_seg.size();
+    // segment lists of the local sort
+    E.n_msd = E.n_direct = E.msd_tiles = 0;
+    L.msd_seg.clear();
+    L.msd_beg.clear();
+    L.msd_end.clear();
+    L.msd_tile_seg.clear();
+    L.msd_tile0.assign(1, 0);
+    L.direct_seg.clear();
+    if (E.listed) {
+        for (uint32_t s = 0; s < E.S; ++s) {
+            const uint64_t len = L.seg_off[s + 1] - L.seg_off[s];
+            if (len <= kDirectSegMax) {
+                L.direct_seg.push_back(s);
+                continue;
+            }
+            const uint32_t li = (uint32_t)L.msd_seg.size();
+            L.msd_seg.push_back(s);
+            L.msd_beg.push_back(L.seg_off[s]);
+            L.msd_end.push_back(L.seg_off[s + 1]);
+            const uint32_t nt = (uint32_t)((len + kSortTile - 1) / kSortTile);
+            for (uint32_t t = 0; t < nt; ++t) L.msd_tile_seg.push_back(li);
+            L.msd_tile0.push_back(L.msd_tile0.back() + nt);
+        }
+        E.n_msd = (uint32_t)L.msd_seg.size();
+        E.n_direct = (uint32_t)L.direct_seg.size();
+        E.msd_tiles = L.msd_tile0.back();
+    }
+    // rate table: rounds until every instance takes all keys of its domain
+    E.J = 1;
+    for (const InstHost& h : E.ih) {
+        uint32_t j = 1;
+        for (; j < kMaxRateRounds; ++j) {
+            uint32_t t;
+            int al;
+            round_rate(h, E.tune, j, true, &t, &al);
+            if (al) break;
+        }
+        E.J = std::max(E.J, j);
+    }
+    L.thresh.assign((size_t)B * E.J, 0);
+    L.all.assign((size_t)B * E.J, 0);
+    for (uint32_t I = 0; I < B; ++I)
+        for (uint32_t j = 1; j <= E.J; ++j) {
+            uint32_t t;
+            int al;
+            round_rate(E.ih[I], E.tune, j, true, &t, &al);
+            L.thresh[(size_t)I * E.J + j - 1] = t;
+            L.all[(size_t)I * E.J + j - 1] = (uint8_t)al;
+        }
+}
+
+uint64_t tiles_of(uint64_t len) { return (len + kSortTile - 1) / kSortTile; }
+
+size_t layout(Engine& E, char* base) {
+    Arena ar;
+    ar.base = base;
+    const uint64_t n = E.n_tot;
+    const uint32_t S = E.S, Q = E.Q, B = (uint32_t)E.ih.size();
+    E.B = ar.take<char>(n * E.key_bytes);
+    E.A = ar.take<char>(n * E.key_bytes);
+    E.Bv = E.payload ? ar.take<uint64_t>(n) : nullptr;
+    E.Av = E.payload ? ar.take<uint64_t>(n) : nullptr;
+    E.seg_off = ar.take<uint64_t>(S + 1);
+    E.seg_inst = ar.take<uint32_t>(S);
+    E.row_inst = ar.take<uint32_t>(Q);
+    E.ideal = ar.take<uint64_t>(Q);
+    E.inst_d = ar.take<InstDesc>(B);
+    E.run_d = ar.take<InstRun>(B);
+    E.thresh_d = ar.take<uint32_t>((size_t)B * E.J);
+    E.all_d = ar.take<uint8_t>((size_t)B * E.J);
+    // count table: the MSD pass of the local sort, and of the bucket sort
+    // (one instance only)
+    uint64_t tiles = E.listed ? E.msd_tiles : (uint64_t)S * tiles_of(E.max_seg);
+    if (!E.listed) tiles = std::max(tiles, (uint64_t)S * tiles_of(E.max_bucket));
+    E.counts = ar.take<uint32_t>(tiles * 256 + 256);
+    RoundArgs& r = E.ra;
+    r.settled = ar.take<uint32_t>(Q);
+    r.chi = ar.take<uint64_t>(Q);
+    r.lrank = ar.take<uint64_t>(Q);
+    r.urank = ar.take<uint64_t>(Q);
+    r.s_key = ar.take<uint64_t>(Q);
+    r.s_tag = ar.take<uint64_t>(Q);
+    r.lpos = ar.take<uint32_t>(E.T);
+    r.upos = ar.take<uint32_t>(E.T);
+    r.prow = ar.take<uint32_t>(E.T);
+    r.ivl_row = ar.take<uint32_t>(Q);
+    r.ivl_inst = ar.take<uint32_t>(Q);
+    r.ivl_tot = ar.take<uint64_t>(Q + 1);
+    r.ivl_nz = ar.take<uint32_t>(Q + 1);
+    r.ivl_dom = ar.take<uint64_t>(Q);
+    r.ivl_pcnt = ar.take<uint32_t>(Q);
+    r.ivl_poff = ar.take<uint32_t>(Q + 1);
+    r.ivl_cursor = ar.take<uint32_t>(Q);
+    r.ivl_tile0 = ar.take<uint32_t>(Q + 1);
+    r.slices = ar.take<uint4>(E.T > 0 ? E.T : 1);
+    r.inst_plo = ar.take<uint32_t>(B);
+    r.inst_pm = ar.take<uint32_t>(B);
+    r.cm_off = ar.take<uint64_t>(B);
+    r.ctr = ar.take<RoundCounters>(1);
+    r.hist = ar.take<RoundHist>(E.J);
+    E.chi_all = ar.take<uint64_t>(Q);
+    E.dst = ar.take<uint32_t>(E.T > 0 ? E.T : 1);
+    E.chunk0 = ar.take<uint32_t>(S + 1);
+    E.fence_base = ar.take<uint64_t>(S + 1);
+    E.fences.key = ar.take<uint64_t>(E.n_fences + 1);
+    E.chunk_seg = ar.take<uint32_t>(E.n_chunks + 1);
+    E.chunk_lo = ar.take<uint32_t>(E.n_chunks + 1);
+    E.bucket_shift = ar.take<uint8_t>(S);
+    E.bucket_base = ar.take<uint64_t>(S);
+    const uint32_t msd_segs = E.listed ? E.n_msd : S;
+    E.sb_start = ar.take<uint64_t>((size_t)msd_segs * 256 + 1);
+    E.sb_len = ar.take<uint32_t>((size_t)msd_segs * 256 + 1);
+    // the lists hold sub-buckets (256 per MSD segment) and whole segments
+    const uint32_t list_segs = msd_segs + (E.n_direct + 255) / 256;
+    const uint64_t ovc = oversize_capacity(list_segs, n);
+    E.ov.count = ar.take<uint32_t>(1);
+    E.ov.tiles = ar.take<uint32_t>(1);
+    E.ov.summary = ar.take<uint32_t>(4);
+    E.ov.beg = ar.take<uint64_t>(ovc);
+    E.ov.end = ar.take<uint64_t>(ovc);
+    E.ov.base = ar.take<uint64_t>(ovc);
+    E.ov.seg = ar.take<uint32_t>(ovc);
+    E.ov.tile0 = ar.take<uint32_t>(ovc + 1);
+    E.ov.tile_seg = ar.take<uint32_t>(oversize_tile_capacity(list_segs, n));
+    const uint64_t slc = slow_capacity(list_segs, n);
+    E.sl.count = ar.take<uint32_t>(1);
+    E.sl.beg = ar.take<uint64_t>(slc);
+    E.sl.len = ar.take<uint32_t>(slc);
+    E.sl.bits = ar.take<uint8_t>(slc);
+    E.sl.base = ar.take<uint64_t>(slc);
+    E.sl.seg = ar.take<uint32_t>(slc);
+    if (E.listed) {
+        E.msd_seg = ar.take<uint32_t>(E.n_msd + 1);
+        E.msd_beg = ar.take<uint64_t>(E.n_msd + 1);
+        E.msd_end = ar.take<uint64_t>(E.n_msd + 1);
+        E.msd_tile_seg = ar.take<uint32_t>(E.msd_tiles + 1);
+        E.msd_tile0 = ar.take<uint32_t>(E.n_msd + 1);
+        E.direct_seg = ar.take<uint32_t>(E.n_direct + 1);
+        E.msd_src = ar.take<uint64_t>(E.n_msd + 1);
+        E.msd_vsrc = ar.take<uint64_t>(E.n_msd + 1);
+        E.direct_src = ar.take<uint64_t>(E.n_direct + 1);
+        E.direct_vsrc = ar.take<uint64_t>(E.n_direct + 1);
+    }
+    return ar.used;
+}
+
+// Probe buffers for `need` probes and a count matrix of `cm_need` words.
+hss_status grow(Engine& E, uint64_t need, uint64_t cm_need) {
+    RoundArgs& r = E.ra;
+    if (need > E.cap || !E.probe_mem) {
+        uint64_t cap = E.cap ? E.cap : 4096;
+        while (cap < need) cap *= 2;
+        if (E.probe_mem) HIP_TRY(hipFree(E.probe_mem));
+        E.probe_mem = nullptr;
+        E.cap = 0;
+        Arena ar;
+        for (int pass = 0; pass < 2; ++pass) {
+            ar.used = 0;
+            r.pr_key = ar.take<uint64_t>(cap);
+            r.pr_tag = ar.take<uint64_t>(cap);
+            r.pr_ivl = ar.take<uint32_t>(cap);
+            r.g_key = ar.take<uint64_t>(cap);
+            r.g_tag = ar.take<uint64_t>(cap);
+            r.ps_key = ar.take<uint64_t>(cap);
+            r.ps_tag = ar.take<uint64_t>(cap);
+            r.ps_ivl = ar.take<uint32_t>(cap);
+            r.ps_seg = ar.take<uint32_t>(cap);
+            r.pr_rank = ar.take<uint64_t>(cap);
+            if (pass == 0) {
+                E.probe_bytes = ar.used + 256;
+                HIP_TRY(hipMalloc(&E.probe_mem, E.probe_bytes));
+                ar.base = (char*)E.probe_mem;
+            }
+        }
+        E.cap = cap;
+        r.cap = cap;
+    }
+    if (cm_need > E.cm_cap || !E.cmat) {
+        uint64_t want = E.cm_cap ? E.cm_cap : (1ull << 20);
+        while (want < cm_need) want *= 2;
+        if (E.cmat) HIP_TRY(hipFree(E.cmat));
+        E.cmat = nullptr;
+        E.cm_cap = 0;
+        HIP_TRY(hipMalloc((void**)&E.cmat, want * 4));
+        E.cm_cap = want;
+        r.cmat = E.cmat;
+        r.cm_cap = want;
+    }
     return HSS_OK;
 }
 
-hss_status read_counters(hss_plan_s& P, hipStream_t s) {
-    HIP_TRY(hipMemcpyAsync(P.h_ctr, P.ra.ctr, sizeof(RoundCounters), hipMemcpyDeviceToHost, s));
+template <typename T>
+hipError_t h2d(T* d, const std::vector<T>& v) {
+    if (v.empty()) return hipSuccess;
+    return hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Allocates the engine for its instances (E.ih filled, constants computed).
+hss_status engine_init(Engine& E) {
+    HIP_TRY(hipGetDevice(&E.device));
+    Layout L;
+    build_layout(E, L);
+    if (E.n_tot >= (1ull << 32)) return fail(HSS_ERR_UNSUPPORTED, "more than 2^32 - 1 keys in one plan");
+    if (E.max_bucket >= (1ull << 32)) return fail(HSS_ERR_UNSUPPORTED, "bucket bound >= 2^32");
+    E.arena_bytes = layout(E, nullptr) + 256;
+    HIP_TRY(hipMalloc(&E.arena, E.arena_bytes));
+    layout(E, (char*)E.arena);
+    HIP_TRY(hipHostMalloc((void**)&E.h_ctr, sizeof(RoundCounters) + 16, hipHostMallocDefault));
+    E.hh.pinned = (uint32_t*)((char*)E.h_ctr + sizeof(RoundCounters));
+    HIP_TRY(hipHostMalloc((void**)&E.h_run, E.ih.size() * sizeof(InstRun), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&E.h_hist, E.J * sizeof(RoundHist), hipHostMallocDefault));
+    HIP_TRY(h2d(E.seg_off, L.seg_off));
+    HIP_TRY(h2d(E.seg_inst, L.seg_inst));
+    HIP_TRY(h2d(E.row_inst, L.row_inst));
+    HIP_TRY(h2d(E.ideal, L.ideal));
+    HIP_TRY(h2d(E.inst_d, L.inst));
+    HIP_TRY(h2d(E.thresh_d, L.thresh));
+    HIP_TRY(h2d(E.all_d, L.all));
+    HIP_TRY(h2d(E.fence_base, L.fence_base));
+    HIP_TRY(h2d(E.chunk_seg, L.chunk_seg));
+    HIP_TRY(h2d(E.chunk_lo, L.chunk_lo));
+    if (E.listed) {
+        HIP_TRY(h2d(E.msd_seg, L.msd_seg));
+        HIP_TRY(h2d(E.msd_beg, L.msd_beg));
+        HIP_TRY(h2d(E.msd_end, L.msd_end));
+        HIP_TRY(h2d(E.msd_tile_seg, L.msd_tile_seg));
+        HIP_TRY(h2d(E.msd_tile0, L.msd_tile0));
+        HIP_TRY(h2d(E.direct_seg, L.direct_seg));
+    }
+    E.fences.base = E.fence_base;
+    E.fences.seg_off = E.seg_off;
+    RoundArgs& r = E.ra;
+    r.key_bytes = E.key_bytes;
+    r.B = E.B;
+    r.n_inst = (uint32_t)E.ih.size();
+    r.n_rows = E.Q;
+    r.n_segs = E.S;
+    r.p_max = E.p_max;
+    r.J = E.J;
+    r.inst = E.inst_d;
+    r.run = E.run_d;
+    r.thresh = E.thresh_d;
+    r.all = E.all_d;
+    r.seg_off = E.seg_off;
+    r.seg_inst = E.seg_inst;
+    r.row_inst = E.row_inst;
+    r.ideal = E.ideal;
+    r.chunk_seg = E.chunk_seg;
+    r.chunk_lo = E.chunk_lo;
+    r.n_chunks = E.n_chunks;
+    r.fences = E.fences;
+    // probes: a generous multiple of the expected sample p s_j / s_{j-1} per
+    // round and instance; the count matrix holds each instance's probes x p
+    uint64_t want = 0, cm = 0;
+    for (const InstHost& h : E.ih) {
+        const uint64_t m = std::min<uint64_t>(h.n, 8ull * h.p + 256);
+        want += m;
+        cm += m * h.p;
+    }
+    return grow(E, want, cm);
+}
+
+hss_status read_counters(Engine& E, hipStream_t s, uint32_t rounds = 0) {
+    HIP_TRY(hipMemcpyAsync(E.h_ctr, E.ra.ctr, sizeof(RoundCounters), hipMemcpyDeviceToHost, s));
+    if (rounds)
+        HIP_TRY(hipMemcpyAsync(E.h_hist, E.ra.hist, rounds * sizeof(RoundHist), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return HSS_OK;
 }
@@ -277,15 +569,17 @@ hss_status d2h(std::vector<T>& v, const T* d, size_t count, hipStream_t s) {
     return HSS_OK;
 }
 
-// Stable sort of the segments [seg_off[s], seg_off[s+1]) (the p input
-// segments, or the p buckets after the exchange).
-hss_status segment_sort(hss_plan_s& P, const void* kin, const uint64_t* vin, void* kout,
+// Local sort of every segment (first=true: of the callers' inputs) or of
+// every bucket of the one instance (first=false).
+hss_status segment_sort(Engine& E, bool first, const void* kin, const uint64_t* vin, void* kout,
                         uint64_t* vout, void* ktmp, uint64_t* vtmp, const uint64_t* seg_off,
                         uint64_t max_len, const uint8_t* seg_shift, const uint64_t* seg_base,
-                        const Fences* fences, hipStream_t s) {
-    if (P.tune.lsd_only) {
+                        bool with_fences, hipStream_t s) {
+    if (E.tune.lsd_only) {
+        if (E.listed) return fail(HSS_ERR_UNSUPPORTED, "lsd_only in a batch");
+        if (!kin || (E.payload && !vin)) return fail(HSS_ERR_INVALID_ARG, "segment sort without an input buffer");
         SegSort ss;
-        ss.key_bytes = P.key_bytes;
+        ss.key_bytes = E.key_bytes;
         ss.keys_in = kin;
         ss.vals_in = vin;
         ss.keys_out = kout;
@@ -293,18 +587,23 @@ hss_status segment_sort(hss_plan_s& P, const void* kin, const uint64_t* vin, voi
         ss.keys_tmp = ktmp;
         ss.vals_tmp = vtmp;
         ss.seg_off = seg_off;
-        ss.num_segs = P.p;
+        ss.num_segs = E.S;
         ss.max_seg_len = max_len;
-        ss.total_len = P.n;
-        ss.counts = P.counts;
+        ss.total_len = E.n_tot;
+        ss.counts = E.counts;
         ss.begin_bit = 0;
-        ss.end_bit = P.key_bytes * 8;
-        ss.prof = &P.prof;
+        ss.end_bit = E.key_bytes * 8;
+        ss.prof = &E.prof;
         HIP_TRY(segmented_radix_sort(ss, s));
+        if (with_fences) HIP_TRY(write_fences(kout, E.key_bytes, E.S, E.fences, s));
         return HSS_OK;
     }
+    // a batch reads its inputs through the segment sources; anything else
+    // needs the input buffer itself
+    if (!(first && E.listed) && (!kin || (E.payload && !vin)))
+        return fail(HSS_ERR_INVALID_ARG, "segment sort without an input buffer");
     HybridSort hs;
-    hs.key_bytes = P.key_bytes;
+    hs.key_bytes = E.key_bytes;
     hs.keys_in = kin;
     hs.vals_in = vin;
     hs.keys_out = kout;
@@ -312,177 +611,247 @@ hss_status segment_sort(hss_plan_s& P, const void* kin, const uint64_t* vin, voi
     hs.keys_tmp = ktmp;
     hs.vals_tmp = vtmp;
     hs.seg_off = seg_off;
-    hs.num_segs = P.p;
+    hs.num_segs = E.S;
     hs.max_seg_len = max_len;
-    hs.total_len = P.n;
-    hs.counts = P.counts;
-    hs.sb_start = P.sb_start;
-    hs.sb_len = P.sb_len;
+    hs.total_len = E.n_tot;
+    hs.counts = E.counts;
+    hs.sb_start = E.sb_start;
+    hs.sb_len = E.sb_len;
     hs.seg_shift = seg_shift;
     hs.seg_base = seg_base;
-    if (fences) hs.fences = *fences;
-    hs.ov = P.ov;
-    hs.sl = P.sl;
-    hs.prof = &P.prof;
-    HIP_TRY(hybrid_sort(hs, s, P.hh));
-    return HSS_OK;
-}
-
-hss_status local_sort(hss_plan_s& P, const void* kin, const uint64_t* vin, void* kout,
-                      uint64_t* vout, void* ktmp, uint64_t* vtmp, hipStream_t s) {
-    return segment_sort(P, kin, vin, kout, vout, ktmp, vtmp, P.seg_off, P.max_seg, nullptr,
-                        nullptr, nullptr, s);
-}
-
-// Splitter rounds on the locally sorted buffer P.B; leaves chi in d_offsets.
-// Average keys per (interval, segment) slice below which the ranks are found
-// by searching the slices instead of the fences.
-constexpr uint64_t kNarrowSliceKeys = 8;
-
-hss_status determine_splitters(hss_plan_s& P, uint64_t seed, uint64_t* d_offsets, hipStream_t s) {
-    RoundArgs& r = P.ra;
-    P.trace.clear();
-    HIP_TRY(launch_round_init(r, s));
-    for (uint32_t j = 1;; ++j) {
-        uint32_t thresh;
-        int all;
-        round_rate(P, j, true, &thresh, &all);
-        HIP_TRY(launch_intervals(r, s));
-        HIP_TRY(launch_sample(r, seed, j, thresh, all, s));
-        hss_status st = read_counters(P, s);
-        if (st != HSS_OK) return st;
-        const RoundCounters c = *P.h_ctr;
-        if (c.err) return fail(HSS_ERR_DEVICE, "device consistency check failed (code " + std::to_string(c.err) + ")");
-        if (c.n_unsettled == 0) break;
-        if (P.tune.max_rounds && j > P.tune.max_rounds)
-            return fail(HSS_ERR_NOT_CONVERGED, "round cap reached with " + std::to_string(c.n_unsettled) + " splitters unsettled");
-        uint64_t m = c.m;
-        if (m > P.cap) {   // resample into a larger buffer; the draw is a pure function of (seed, tag, round)
-            st = grow_probes(P, m);
-            if (st != HSS_OK) return st;
-            HIP_TRY(launch_intervals(r, s));
-            HIP_TRY(launch_sample(r, seed, j, thresh, all, s));
-            st = read_counters(P, s);
-            if (st != HSS_OK) return st;
-            if (P.h_ctr->m != m) return fail(HSS_ERR_DEVICE, "probe count changed on resampling");
-        }
-        st = ensure_sort_scratch(P, m);
-        if (st != HSS_OK) return st;
-        HIP_TRY(launch_probe_sort(r, m, P.sort_scratch, P.sort_scratch_bytes, P.counts, s));
-        // keep every probe's segment counts when they fit the budget, so the
-        // locate step copies instead of searching again
-        uint32_t* cmat = nullptr;
-        const uint64_t words = m * (uint64_t)P.p;
-        if (words <= kCountMatrixBudget) {
-            if (words > P.cmat_words) {
-                if (P.cmat) HIP_TRY(hipFree(P.cmat));
-                P.cmat = nullptr;
-                P.cmat_words = 0;
-                uint64_t want = 1ull << 20;
-                while (want < words) want *= 2;
-                if (want > kCountMatrixBudget) want = kCountMatrixBudget;
-                if (hipMalloc((void**)&P.cmat, want * 4) == hipSuccess) P.cmat_words = want;
-                else P.cmat = nullptr;
-            }
-            if (P.cmat) cmat = P.cmat;
-        }
-        // Once the open intervals hold few keys per segment, a search inside
-        // each probe's own interval slice reads fewer bytes than the fences
-        // of every segment chunk.
-        const Fences none;
-        const bool narrow = j > 1 && c.n_ivl > 0 &&
-                            c.domain <= kNarrowSliceKeys * (uint64_t)c.n_ivl * P.p;
-        HIP_TRY(launch_rank(r, m, cmat, (P.tune.lsd_only || narrow) ? none : P.fences, P.max_seg, s));
-        HIP_TRY(launch_settle(r, m, s));
-        HIP_TRY(launch_locate(r, cmat, m, s));
-        RoundRecord rec;
-        rec.domain = c.domain;
-        rec.m = m;
-        rec.thresh = thresh;
-        rec.all = (uint32_t)all;
-        if (P.tune.trace_level >= 1) {
-            const uint32_t q = P.p - 1;
-            std::vector<uint32_t> settled;
-            if ((st = d2h(rec.key, r.ps_key, m, s)) != HSS_OK) return st;
-            if ((st = d2h(rec.tag, r.ps_tag, m, s)) != HSS_OK) return st;
-            if ((st = d2h(rec.rank, r.pr_rank, m, s)) != HSS_OK) return st;
-            if ((st = d2h(rec.lo, r.lrank + 1, q, s)) != HSS_OK) return st;
-            if ((st = d2h(rec.hi, r.urank + 1, q, s)) != HSS_OK) return st;
-            if ((st = d2h(rec.chi, r.chi + 1, q, s)) != HSS_OK) return st;
-            if ((st = d2h(settled, r.settled + 1, q, s)) != HSS_OK) return st;
-            HIP_TRY(hipStreamSynchronize(s));
-            rec.settled.resize(q);
-            for (uint32_t i = 0; i < q; ++i) {
-                rec.settled[i] = settled[i] ? 1 : 0;
-                if (settled[i]) { rec.lo[i] = kNone; rec.hi[i] = kNone; }
-            }
-        }
-        P.trace.push_back(std::move(rec));
+    if (with_fences) hs.fences = E.fences;
+    hs.ov = E.ov;
+    hs.sl = E.sl;
+    hs.prof = &E.prof;
+    if (first && E.listed) {
+        hs.num_segs = E.n_msd;
+        hs.msd_seg = E.msd_seg;
+        hs.msd_beg = E.msd_beg;
+        hs.msd_end = E.msd_end;
+        hs.msd_tile_seg = E.msd_tile_seg;
+        hs.msd_tile0 = E.msd_tile0;
+        hs.msd_tiles = E.msd_tiles;
+        hs.msd_src = E.msd_src;
+        hs.msd_vsrc = E.payload ? E.msd_vsrc : nullptr;
+        hs.direct_seg = E.direct_seg;
+        hs.n_direct = E.n_direct;
+        hs.direct_src = E.direct_src;
+        hs.direct_vsrc = E.payload ? E.direct_vsrc : nullptr;
+        hs.has_payload = E.payload;
     }
-    HIP_TRY(launch_finalize(r, d_offsets, s));
+    HIP_TRY(hybrid_sort(hs, s, E.hh));
     return HSS_OK;
 }
 
-hss_status run(hss_plan_s* P, uint64_t seed, const void* kin, const uint64_t* vin, void* kout,
-               uint64_t* vout, uint64_t* d_offsets, void* stream, bool sort_buckets) {
-    hss_status st = check_io(P, kin, vin, kout, vout, d_offsets);
+void record_round(Engine& E, RoundRecord& rec, uint32_t j) {
+    rec.domain = E.h_ctr->domain;
+    rec.m = E.h_ctr->m;
+    uint32_t t;
+    int al;
+    round_rate(E.ih[0], E.tune, j, true, &t, &al);
+    rec.thresh = t;
+    rec.all = (uint32_t)al;
+}
+
+// Splitter rounds of every instance on the locally sorted buffer B; leaves
+// chi in chi_all and in every instance's offsets.
+hss_status determine_splitters(Engine& E, hipStream_t s) {
+    RoundArgs& r = E.ra;
+    E.trace.clear();
+    const bool tracing = E.tune.trace_level >= 1;
+    if (E.Q > 2 * (uint32_t)E.ih.size()) {
+        uint32_t restarts = 0;
+        HIP_TRY(launch_round_init(r, s));
+        uint32_t j = 0;
+        // the rounds that usually settle every splitter (k - 1 of them at the
+        // configurations measured), queued in one go; each further round is
+        // queued and read back on its own
+        const uint32_t first_chunk = std::min(std::max(E.k_max, 2u) - 1, E.J);
+        uint32_t chunk = tracing ? 1u : first_chunk;
+        for (;;) {
+            uint32_t stop = E.J;
+            if (E.tune.max_rounds) stop = std::min(stop, E.tune.max_rounds);
+            const uint32_t upto = std::min(j + chunk, stop);
+            while (j < upto) {
+                ++j;
+                HIP_TRY(launch_round(r, j, s, &E.prof));
+            }
+            hss_status st = read_counters(E, s, tracing ? 0u : j);
+            if (st != HSS_OK) return st;
+            const RoundCounters c = *E.h_ctr;
+            if (c.overflow) {
+                if (++restarts > kMaxRestarts) return fail(HSS_ERR_DEVICE, "probe buffers keep overflowing");
+                // the recorded needs, and at least twice what overflowed
+                const bool probes_short = c.m_max > E.cap || c.cm_max <= E.cm_cap;
+                const uint64_t need = probes_short ? std::max<uint64_t>(c.m_max + c.m_max / 4 + 1024, 2 * E.cap) : E.cap;
+                const uint64_t cm_need = c.cm_max > E.cm_cap ? std::max<uint64_t>(c.cm_max + c.cm_max / 4, 2 * E.cm_cap) : E.cm_cap;
+                st = grow(E, need, cm_need);
+                if (st != HSS_OK) return st;
+                E.trace.clear();
+                HIP_TRY(launch_round_init(r, s));
+                j = 0;
+                chunk = tracing ? 1u : first_chunk;
+                continue;
+            }
+            if (c.err) return fail(HSS_ERR_DEVICE, "device consistency check failed (code " + std::to_string(c.err) + ")");
+            if (tracing && c.n_unsettled > 0) {
+                RoundRecord rec;
+                record_round(E, rec, j);
+                const uint64_t m = c.m_stored;
+                const uint32_t q = E.ih[0].p - 1;
+                std::vector<uint32_t> settled;
+                if ((st = d2h(rec.key, r.ps_key, m, s)) != HSS_OK) return st;
+                if ((st = d2h(rec.tag, r.ps_tag, m, s)) != HSS_OK) return st;
+                if ((st = d2h(rec.rank, r.pr_rank, m, s)) != HSS_OK) return st;
+                if ((st = d2h(rec.lo, r.lrank + 1, q, s)) != HSS_OK) return st;
+                if ((st = d2h(rec.hi, r.urank + 1, q, s)) != HSS_OK) return st;
+                if ((st = d2h(rec.chi, r.chi + 1, q, s)) != HSS_OK) return st;
+                if ((st = d2h(settled, r.settled + 1, q, s)) != HSS_OK) return st;
+                HIP_TRY(hipStreamSynchronize(s));
+                rec.settled.resize(q);
+                for (uint32_t i = 0; i < q; ++i) {
+                    rec.settled[i] = settled[i] ? 1 : 0;
+                    if (settled[i]) { rec.lo[i] = kNone; rec.hi[i] = kNone; }
+                }
+                E.trace.push_back(std::move(rec));
+            }
+            if (c.n_after == 0) {
+                if (!tracing) {
+                    // counts of every round that had unsettled splitters
+                    for (uint32_t q = 0; q < j; ++q) {
+                        const RoundHist& h = E.h_hist[q];
+                        if (h.unsettled == 0) break;
+                        RoundRecord rec;
+                        record_round(E, rec, q + 1);
+                        rec.domain = h.domain;
+                        rec.m = h.m;
+                        E.trace.push_back(std::move(rec));
+                    }
+                }
+                break;
+            }
+            if (j >= stop) {
+                if (E.tune.max_rounds && j >= E.tune.max_rounds)
+                    return fail(HSS_ERR_NOT_CONVERGED, "round cap reached with " + std::to_string(c.n_after) + " splitters unsettled");
+                return fail(HSS_ERR_DEVICE, "splitters unsettled after the rate reached 1");
+            }
+            chunk = 1;
+        }
+    }
+    HIP_TRY(launch_finalize(r, E.chi_all, s));
+    return HSS_OK;
+}
+
+// One call on an engine: local sort, rounds, exchange (and, for one
+// instance, the bucket sort).  The per-call records are already queued.
+hss_status engine_run(Engine& E, const void* kin, const uint64_t* vin, void* kout, uint64_t* vout,
+                      hipStream_t s, bool sort_buckets) {
+    if (E.listed) {
+        HIP_TRY(launch_segment_sources(E.ra, E.msd_seg, E.n_msd, E.msd_src,
+                                       E.payload ? E.msd_vsrc : nullptr, E.key_bytes, s));
+        HIP_TRY(launch_segment_sources(E.ra, E.direct_seg, E.n_direct, E.direct_src,
+                                       E.payload ? E.direct_vsrc : nullptr, E.key_bytes, s));
+    }
+    // phase 1: local sort of every segment into B, with its fences
+    hss_status st = segment_sort(E, true, kin, vin, E.B, E.Bv, E.A, E.Av, E.seg_off, E.max_seg,
+                                 nullptr, nullptr, true, s);
+    if (st != HSS_OK) return st;
+    // phase 2: splitter rounds
+    E.prof.begin(s);
+    st = determine_splitters(E, s);
+    if (st != HSS_OK) return st;
+    E.prof.end(kProfRounds, s, 0);
+    // phase 3: exchange into the outputs (or into A before the bucket sort)
+    ExchangeArgs ex;
+    ex.key_bytes = E.key_bytes;
+    ex.B = E.B;
+    ex.Bv = E.payload ? E.Bv : nullptr;
+    ex.n_inst = (uint32_t)E.ih.size();
+    ex.n_segs = E.S;
+    ex.p_max = E.p_max;
+    ex.inst = E.inst_d;
+    ex.run = E.run_d;
+    ex.seg_off = E.seg_off;
+    ex.seg_inst = E.seg_inst;
+    ex.prow = E.ra.prow;
+    ex.chi_all = E.chi_all;
+    ex.dst = E.dst;
+    ex.chunk0 = E.chunk0;
+    ex.max_chunks = exchange_chunk_bound(E.n_tot, E.S);
+    ex.total = E.n_tot;
+    ex.out = sort_buckets ? E.A : nullptr;
+    ex.vout = sort_buckets ? E.Av : nullptr;
+    ex.err = &E.ra.ctr->err;
+    ex.prof = &E.prof;
+    HIP_TRY(launch_exchange(ex, s));
+    // phase 4 (sort, one instance): stable sort of every bucket
+    if (sort_buckets) {
+        const uint32_t p = E.ih[0].p;
+        const uint8_t* shifts = nullptr;
+        const uint64_t* bases = nullptr;
+        if (p > 1) {
+            HIP_TRY(launch_bucket_shift(p, E.key_bytes * 8, E.ra.s_key, E.bucket_shift, E.bucket_base, s));
+            shifts = E.bucket_shift;
+            bases = E.bucket_base;
+        }
+        st = segment_sort(E, false, E.A, E.Av, kout, vout, E.B, E.Bv, E.chi_all, E.max_bucket,
+                          shifts, bases, false, s);
+        if (st != HSS_OK) return st;
+    }
+    return HSS_OK;
+}
+
+hss_status check_io(const Engine& E, const InstHost& h, const void* kin, const uint64_t* vin,
+                    const void* kout, const uint64_t* vout, const uint64_t* offsets) {
+    if (!kin || !kout) return fail(HSS_ERR_INVALID_ARG, "null key pointer");
+    if (E.payload != (vin != nullptr) || E.payload != (vout != nullptr))
+        return fail(HSS_ERR_INVALID_ARG, "payload pointers must be given iff the plan has a payload");
+    const void* ptrs[] = {kin, vin, kout, vout, offsets};
+    for (const void* q : ptrs)
+        if (q && !aligned16(q)) return fail(HSS_ERR_INVALID_ARG, "device pointers must be 16-byte aligned");
+    const size_t kb = h.n * E.key_bytes, vb = h.n * 8, ob = (h.p + 1) * 8;
+    if (overlap(kin, kb, kout, kb) || overlap(kin, kb, vout, vb) || overlap(vin, vb, kout, kb) ||
+        overlap(vin, vb, vout, vb) || overlap(offsets, ob, kin, kb) || overlap(offsets, ob, kout, kb) ||
+        overlap(offsets, ob, vin, vb) || overlap(offsets, ob, vout, vb) || overlap(kout, kb, vout, vb))
+        return fail(HSS_ERR_INVALID_ARG, "outputs overlap inputs or each other");
+    return HSS_OK;
+}
+
+hss_status finish(Engine& E, hipStream_t s) {
+    // the exchange checks that every bucket's pieces add up to its size
+    hss_status st = read_counters(E, s);
+    if (st != HSS_OK) return st;
+    if (E.h_ctr->err)
+        return fail(HSS_ERR_DEVICE, "device consistency check failed (code " + std::to_string(E.h_ctr->err) + ")");
+    return HSS_OK;
+}
+
+hss_status run_plain(hss_plan_s* P, uint64_t seed, const void* kin, const uint64_t* vin, void* kout,
+                     uint64_t* vout, uint64_t* d_offsets, void* stream, bool sort_buckets) {
+    if (!P) return fail(HSS_ERR_INVALID_ARG, "null plan");
+    Engine& E = P->e;
+    hss_status st = check_io(E, E.ih[0], kin, vin, kout, vout, d_offsets);
     if (st != HSS_OK) return st;
     if (!d_offsets) return fail(HSS_ERR_INVALID_ARG, "null offsets pointer");
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(hipSetDevice(P->device));
-    HIP_TRY(launch_counters_reset(P->ra.ctr, s));
-    // phase 1: local sort of every segment into B, with its fences
-    st = segment_sort(*P, kin, vin, P->B, P->Bv, P->A, P->Av, P->seg_off, P->max_seg, nullptr,
-                      nullptr, P->tune.lsd_only ? nullptr : &P->fences, s);
+    HIP_TRY(hipSetDevice(E.device));
+    InstRun run{seed, kin, vin, kout, vout, d_offsets};
+    HIP_TRY(launch_set_run(run, E.run_d, s));
+    HIP_TRY(launch_counters_reset(E.ra.ctr, s));
+    st = engine_run(E, kin, vin, kout, vout, s, sort_buckets);
     if (st != HSS_OK) return st;
-    // phase 2: splitter rounds
-    if (P->p == 1) {
-        P->trace.clear();
-        const uint64_t off[2] = {0, P->n};
-        HIP_TRY(hipMemcpyAsync(d_offsets, off, sizeof(off), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));
-    } else {
-        P->prof.begin(s);
-        st = determine_splitters(*P, seed, d_offsets, s);
-        if (st != HSS_OK) return st;
-        P->prof.end(kProfRounds, s, 0);
-    }
-    // phase 3: exchange into the output (or into A before the bucket sort)
-    ExchangeArgs ex;
-    ex.key_bytes = P->key_bytes;
-    ex.B = P->B;
-    ex.Bv = P->Bv;
-    ex.out = sort_buckets ? P->A : kout;
-    ex.vout = sort_buckets ? P->Av : vout;
-    ex.n = P->n;
-    ex.p = P->p;
-    ex.seg_off = P->seg_off;
-    ex.prow = P->ra.prow;
-    ex.chi = d_offsets;
-    ex.dst = P->dst;
-    ex.max_bucket = P->max_bucket;
-    ex.err = &P->ra.ctr->err;
-    ex.prof = &P->prof;
-    HIP_TRY(launch_exchange(ex, s));
-    // phase 4 (sort only): stable sort of every bucket
-    if (sort_buckets) {
-        const uint8_t* shifts = nullptr;
-        const uint64_t* bases = nullptr;
-        if (P->p > 1) {
-            HIP_TRY(launch_bucket_shift(P->p, P->key_bytes * 8, P->ra.s_key, P->bucket_shift,
-                                        P->bucket_base, s));
-            shifts = P->bucket_shift;
-            bases = P->bucket_base;
-        }
-        st = segment_sort(*P, P->A, P->Av, kout, vout, P->B, P->Bv, d_offsets, P->max_bucket,
-                          shifts, bases, nullptr, s);
-        if (st != HSS_OK) return st;
-    }
-    // the exchange checks that every bucket's pieces add up to its size
-    st = read_counters(*P, s);
-    if (st != HSS_OK) return st;
-    if (P->h_ctr->err)
-        return fail(HSS_ERR_DEVICE, "device consistency check failed (code " + std::to_string(P->h_ctr->err) + ")");
+    return finish(E, s);
+}
+
+hss_status new_engine_instance(Engine& E, uint64_t n, uint32_t p, double eps) {
+    if (n == 0 || p == 0 || (uint64_t)p > n) return fail(HSS_ERR_INVALID_ARG, "need 1 <= p <= N");
+    if (!(eps > 0.0 && eps < 1.0)) return fail(HSS_ERR_INVALID_ARG, "need 0 < eps < 1");
+    InstHost h;
+    h.n = n;
+    h.p = p;
+    h.eps = eps;
+    instance_constants(h, E.tune);
+    E.ih.push_back(h);
     return HSS_OK;
 }
 
@@ -495,8 +864,7 @@ hss_status hss_plan(hss_plan_t* out, uint64_t n, uint32_t p, double eps, hss_key
     try {
         if (!out) return fail(HSS_ERR_INVALID_ARG, "null plan pointer");
         *out = nullptr;
-        if (n == 0 || p == 0 || (uint64_t)p > n)
-            return fail(HSS_ERR_INVALID_ARG, "need 1 <= p <= N");
+        if (n == 0 || p == 0 || (uint64_t)p > n) return fail(HSS_ERR_INVALID_ARG, "need 1 <= p <= N");
         if (!(eps > 0.0 && eps < 1.0)) return fail(HSS_ERR_INVALID_ARG, "need 0 < eps < 1");
         if (kt != HSS_U32 && kt != HSS_U64) return fail(HSS_ERR_INVALID_ARG, "bad key type");
         if (tuning) {
@@ -506,65 +874,13 @@ hss_status hss_plan(hss_plan_t* out, uint64_t n, uint32_t p, double eps, hss_key
         if (n >= (1ull << 32)) return fail(HSS_ERR_UNSUPPORTED, "N >= 2^32 is not supported");
         hss_plan_s* P = new (std::nothrow) hss_plan_s();
         if (!P) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
-        P->n = n;
-        P->p = p;
-        P->eps = eps;
-        P->key_bytes = kt == HSS_U32 ? 4 : 8;
-        P->payload = with_payload != 0;
-        if (tuning) P->tune = *tuning;
-        compute_constants(*P);
-        if (P->max_bucket >= (1ull << 32)) {
-            delete P;
-            return fail(HSS_ERR_UNSUPPORTED, "bucket bound >= 2^32");
-        }
-        hipError_t e = hipGetDevice(&P->device);
-        if (e != hipSuccess) {
-            delete P;
-            return fail(HSS_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
-        }
-        P->arena_bytes = layout(*P, nullptr) + 256;
-        e = hipMalloc(&P->arena, P->arena_bytes);
-        if (e != hipSuccess) {
-            delete P;
-            return fail(HSS_ERR_OUT_OF_MEMORY, std::string("hipMalloc workspace: ") + hipGetErrorString(e));
-        }
-        layout(*P, (char*)P->arena);
-        e = hipHostMalloc((void**)&P->h_ctr, sizeof(RoundCounters) + 16, hipHostMallocDefault);
-        if (e == hipSuccess) P->hh.pinned = (uint32_t*)((char*)P->h_ctr + sizeof(RoundCounters));
-        if (e != hipSuccess) {
-            (void)hipFree(P->arena);
-            delete P;
-            return fail(HSS_ERR_OUT_OF_MEMORY, "pinned host allocation failed");
-        }
-        // segment boundaries floor(s N / p) and ideal ranks floor(i N / p): the
-        // same integers (section 2)
-        std::vector<uint64_t> sb(p + 1);
-        for (uint64_t i = 0; i <= p; ++i) sb[i] = (uint64_t)(((u128)i * n) / p);
-        RoundArgs& r = P->ra;
-        r.key_bytes = P->key_bytes;
-        r.B = P->B;
-        r.n = n;
-        r.p = p;
-        r.seg_off = P->seg_off;
-        r.ideal = P->ideal;
-        r.tol = P->tol;
-        e = hipMemcpy(P->seg_off, sb.data(), sb.size() * 8, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(P->ideal, sb.data(), sb.size() * 8, hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            (void)hipHostFree(P->h_ctr);
-            (void)hipFree(P->arena);
-            delete P;
-            return fail(HSS_ERR_DEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
-        }
-        // initial probe capacity: a generous multiple of the expected sample
-        // p * s_j / s_{j-1} per round, grown on demand
-        const double ratio = std::pow(P->a, 1.0 / P->k);
-        uint64_t want = (uint64_t)(16.0 * p * (ratio > 1 ? ratio : 1)) + 65536;
-        if (want > n) want = n;
-        hss_status st = grow_probes(*P, want);
+        Engine& E = P->e;
+        E.key_bytes = kt == HSS_U32 ? 4 : 8;
+        E.payload = with_payload != 0;
+        if (tuning) E.tune = *tuning;
+        hss_status st = new_engine_instance(E, n, p, eps);
+        if (st == HSS_OK) st = engine_init(E);
         if (st != HSS_OK) {
-            (void)hipHostFree(P->h_ctr);
-            (void)hipFree(P->arena);
             delete P;
             return st;
         }
@@ -578,27 +894,19 @@ hss_status hss_plan(hss_plan_t* out, uint64_t n, uint32_t p, double eps, hss_key
 void hss_plan_destroy(hss_plan_t P) {
     if (!P) return;
     try {
-        (void)hipSetDevice(P->device);
-        (void)hipDeviceSynchronize();
-        if (P->probe_mem) (void)hipFree(P->probe_mem);
-        if (P->sort_scratch) (void)hipFree(P->sort_scratch);
-        if (P->hh.fb_counts) (void)hipFree(P->hh.fb_counts);
-        if (P->cmat) (void)hipFree(P->cmat);
-        if (P->arena) (void)hipFree(P->arena);
-        if (P->h_ctr) (void)hipHostFree(P->h_ctr);
         delete P;
     } catch (...) {
     }
 }
 
 size_t hss_workspace_bytes(hss_plan_t P) {
-    return P ? P->arena_bytes + P->probe_bytes + P->sort_scratch_bytes : 0;
+    return P ? P->e.arena_bytes + P->e.probe_bytes + P->e.cm_cap * 4 : 0;
 }
 
 hss_status hss_partition(hss_plan_t P, uint64_t seed, const void* kin, const uint64_t* vin,
                          void* kout, uint64_t* vout, uint64_t* d_offsets, void* stream) {
     try {
-        return run(P, seed, kin, vin, kout, vout, d_offsets, stream, false);
+        return run_plain(P, seed, kin, vin, kout, vout, d_offsets, stream, false);
     } catch (...) {
         return fail(HSS_ERR_DEVICE, "unexpected exception");
     }
@@ -607,7 +915,7 @@ hss_status hss_partition(hss_plan_t P, uint64_t seed, const void* kin, const uin
 hss_status hss_sort(hss_plan_t P, uint64_t seed, const void* kin, const uint64_t* vin,
                     void* kout, uint64_t* vout, uint64_t* d_offsets, void* stream) {
     try {
-        return run(P, seed, kin, vin, kout, vout, d_offsets, stream, true);
+        return run_plain(P, seed, kin, vin, kout, vout, d_offsets, stream, true);
     } catch (...) {
         return fail(HSS_ERR_DEVICE, "unexpected exception");
     }
@@ -616,10 +924,13 @@ hss_status hss_sort(hss_plan_t P, uint64_t seed, const void* kin, const uint64_t
 hss_status hss_local_sort(hss_plan_t P, const void* kin, const uint64_t* vin, void* kout,
                           uint64_t* vout, void* stream) {
     try {
-        hss_status st = check_io(P, kin, vin, kout, vout, nullptr);
+        if (!P) return fail(HSS_ERR_INVALID_ARG, "null plan");
+        Engine& E = P->e;
+        hss_status st = check_io(E, E.ih[0], kin, vin, kout, vout, nullptr);
         if (st != HSS_OK) return st;
-        HIP_TRY(hipSetDevice(P->device));
-        return local_sort(*P, kin, vin, kout, vout, P->A, P->Av, (hipStream_t)stream);
+        HIP_TRY(hipSetDevice(E.device));
+        return segment_sort(E, true, kin, vin, kout, vout, E.A, E.Av, E.seg_off, E.max_seg, nullptr,
+                            nullptr, false, (hipStream_t)stream);
     } catch (...) {
         return fail(HSS_ERR_DEVICE, "unexpected exception");
     }
@@ -628,25 +939,26 @@ hss_status hss_local_sort(hss_plan_t P, const void* kin, const uint64_t* vin, vo
 hss_status hss_get_constants(hss_plan_t P, uint64_t* tol, uint32_t* k, double* a, uint32_t max_j,
                              uint32_t* thresh, uint32_t* all) {
     if (!P) return fail(HSS_ERR_INVALID_ARG, "null plan");
-    if (tol) *tol = P->tol;
-    if (k) *k = P->k;
-    if (a) *a = P->a;
+    const InstHost& h = P->e.ih[0];
+    if (tol) *tol = h.tol;
+    if (k) *k = h.k;
+    if (a) *a = h.a;
     for (uint32_t j = 1; j <= max_j; ++j) {
         uint32_t t;
         int al;
-        round_rate(*P, j, false, &t, &al);   // the schedule itself, without forcing
+        round_rate(h, P->e.tune, j, false, &t, &al);   // the schedule itself, without forcing
         if (thresh) thresh[j - 1] = t;
         if (all) all[j - 1] = (uint32_t)al;
     }
     return HSS_OK;
 }
 
-uint32_t hss_trace_rounds(hss_plan_t P) { return P ? (uint32_t)P->trace.size() : 0; }
+uint32_t hss_trace_rounds(hss_plan_t P) { return P ? (uint32_t)P->e.trace.size() : 0; }
 
 hss_status hss_trace_round_info(hss_plan_t P, uint32_t j, uint64_t* domain, uint64_t* m,
                                 uint32_t* thresh, uint32_t* all) {
-    if (!P || j >= P->trace.size()) return fail(HSS_ERR_INVALID_ARG, "no such round");
-    const RoundRecord& r = P->trace[j];
+    if (!P || j >= P->e.trace.size()) return fail(HSS_ERR_INVALID_ARG, "no such round");
+    const RoundRecord& r = P->e.trace[j];
     if (domain) *domain = r.domain;
     if (m) *m = r.m;
     if (thresh) *thresh = r.thresh;
@@ -656,8 +968,8 @@ hss_status hss_trace_round_info(hss_plan_t P, uint32_t j, uint64_t* domain, uint
 
 hss_status hss_trace_round_probes(hss_plan_t P, uint32_t j, uint64_t* keys, uint64_t* tags,
                                   uint64_t* ranks) {
-    if (!P || j >= P->trace.size()) return fail(HSS_ERR_INVALID_ARG, "no such round");
-    const RoundRecord& r = P->trace[j];
+    if (!P || j >= P->e.trace.size()) return fail(HSS_ERR_INVALID_ARG, "no such round");
+    const RoundRecord& r = P->e.trace[j];
     if (r.key.size() != r.m) return fail(HSS_ERR_INVALID_ARG, "round probes need trace_level >= 1");
     if (keys) std::memcpy(keys, r.key.data(), r.m * 8);
     if (tags) std::memcpy(tags, r.tag.data(), r.m * 8);
@@ -667,9 +979,9 @@ hss_status hss_trace_round_probes(hss_plan_t P, uint32_t j, uint64_t* keys, uint
 
 hss_status hss_trace_round_state(hss_plan_t P, uint32_t j, uint64_t* lo_rank, uint64_t* hi_rank,
                                  uint8_t* settled, uint64_t* chi) {
-    if (!P || j >= P->trace.size()) return fail(HSS_ERR_INVALID_ARG, "no such round");
-    const RoundRecord& r = P->trace[j];
-    const size_t q = P->p - 1;
+    if (!P || j >= P->e.trace.size()) return fail(HSS_ERR_INVALID_ARG, "no such round");
+    const RoundRecord& r = P->e.trace[j];
+    const size_t q = P->e.ih[0].p - 1;
     if (r.settled.size() != q) return fail(HSS_ERR_INVALID_ARG, "round state needs trace_level >= 1");
     if (lo_rank) std::memcpy(lo_rank, r.lo.data(), q * 8);
     if (hi_rank) std::memcpy(hi_rank, r.hi.data(), q * 8);
@@ -682,23 +994,24 @@ hss_status hss_trace_splitters(hss_plan_t P, uint64_t* chi, uint64_t* s_key, uin
                                uint64_t* pieces) {
     if (!P) return fail(HSS_ERR_INVALID_ARG, "null plan");
     try {
-        HIP_TRY(hipSetDevice(P->device));
+        Engine& E = P->e;
+        HIP_TRY(hipSetDevice(E.device));
         HIP_TRY(hipDeviceSynchronize());
-        const uint64_t p = P->p;
+        const uint64_t p = E.ih[0].p, n = E.ih[0].n;
         std::vector<uint64_t> c(p + 1, 0), sk(p + 1, 0), st(p + 1, kNone);
         std::vector<uint32_t> pr((p + 1) * p, 0);
         if (p > 1) {
-            HIP_TRY(hipMemcpy(c.data(), P->ra.chi, (p + 1) * 8, hipMemcpyDeviceToHost));
-            HIP_TRY(hipMemcpy(sk.data(), P->ra.s_key, (p + 1) * 8, hipMemcpyDeviceToHost));
-            HIP_TRY(hipMemcpy(st.data(), P->ra.s_tag, (p + 1) * 8, hipMemcpyDeviceToHost));
-            HIP_TRY(hipMemcpy(pr.data(), P->ra.prow, (p + 1) * p * 4, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(c.data(), E.ra.chi, (p + 1) * 8, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(sk.data(), E.ra.s_key, (p + 1) * 8, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(st.data(), E.ra.s_tag, (p + 1) * 8, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(pr.data(), E.ra.prow, (p + 1) * p * 4, hipMemcpyDeviceToHost));
         }
         c[0] = 0;
-        c[p] = P->n;
+        c[p] = n;
         sk[0] = sk[p] = 0;
         st[0] = st[p] = kNone;
         std::vector<uint64_t> sb(p + 1);
-        for (uint64_t i = 0; i <= p; ++i) sb[i] = (uint64_t)(((u128)i * P->n) / p);
+        for (uint64_t i = 0; i <= p; ++i) sb[i] = (uint64_t)(((u128)i * n) / p);
         if (chi) std::memcpy(chi, c.data(), (p + 1) * 8);
         if (s_key) std::memcpy(s_key, sk.data(), (p + 1) * 8);
         if (s_tag) std::memcpy(s_tag, st.data(), (p + 1) * 8);
@@ -715,24 +1028,171 @@ hss_status hss_trace_splitters(hss_plan_t P, uint64_t* chi, uint64_t* s_key, uin
 
 hss_status hss_profile(hss_plan_t P, int enable) {
     if (!P) return fail(HSS_ERR_INVALID_ARG, "null plan");
-    P->prof.collect();
-    P->prof.on = enable != 0;
+    P->e.prof.collect();
+    P->e.prof.on = enable != 0;
     return HSS_OK;
 }
 
 hss_status hss_profile_reset(hss_plan_t P) {
     if (!P) return fail(HSS_ERR_INVALID_ARG, "null plan");
-    P->prof.reset();
+    P->e.prof.reset();
     return HSS_OK;
 }
 
 hss_status hss_profile_read(hss_plan_t P, uint32_t family, double* ms, uint64_t* launches,
                             uint64_t* bytes) {
     if (!P || family >= (uint32_t)kProfSlots) return fail(HSS_ERR_INVALID_ARG, "bad plan or family");
-    P->prof.collect();
-    if (ms) *ms = P->prof.ms[family];
-    if (launches) *launches = P->prof.launches[family];
-    if (bytes) *bytes = P->prof.bytes[family];
+    Profiler& pr = P->e.prof;
+    pr.collect();
+    if (ms) *ms = pr.ms[family];
+    if (launches) *launches = pr.launches[family];
+    if (bytes) *bytes = pr.bytes[family];
+    return HSS_OK;
+}
+
+// ------------------------------------------------------------- batches ----
+
+hss_status hss_batch_plan(hss_batch_t* out, const hss_instance_shape* shapes, uint32_t count,
+                          int with_payload, const hss_tuning* tuning) {
+    try {
+        if (!out) return fail(HSS_ERR_INVALID_ARG, "null batch pointer");
+        *out = nullptr;
+        if (!shapes || count == 0) return fail(HSS_ERR_INVALID_ARG, "need at least one instance");
+        if (tuning) {
+            for (uint32_t x : tuning->reserved)
+                if (x) return fail(HSS_ERR_INVALID_ARG, "reserved tuning fields must be zero");
+            if (tuning->lsd_only) return fail(HSS_ERR_UNSUPPORTED, "lsd_only is for single plans");
+            if (tuning->trace_level) return fail(HSS_ERR_UNSUPPORTED, "traces are for single plans");
+        }
+        hss_batch_s* Bt = new (std::nothrow) hss_batch_s();
+        if (!Bt) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
+        Bt->where.resize(count);
+        for (uint32_t i = 0; i < count; ++i) {
+            const hss_instance_shape& sh = shapes[i];
+            if (sh.key_type != HSS_U32 && sh.key_type != HSS_U64) {
+                delete Bt;
+                return fail(HSS_ERR_INVALID_ARG, "bad key type of instance " + std::to_string(i));
+            }
+            const int g = sh.key_type == HSS_U32 ? 0 : 1;
+            if (!Bt->eng[g]) {
+                Bt->eng[g] = new (std::nothrow) Engine();
+                if (!Bt->eng[g]) {
+                    delete Bt;
+                    return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
+                }
+                Bt->eng[g]->batch = true;
+                Bt->eng[g]->key_bytes = g == 0 ? 4 : 8;
+                Bt->eng[g]->payload = with_payload != 0;
+                if (tuning) Bt->eng[g]->tune = *tuning;
+            }
+            Engine& E = *Bt->eng[g];
+            Bt->where[i] = {g, (uint32_t)E.ih.size()};
+            hss_status st = new_engine_instance(E, sh.n, sh.p, sh.eps);
+            if (st != HSS_OK) {
+                const std::string msg = "instance " + std::to_string(i) + ": " + g_last_error;
+                delete Bt;
+                return fail(st, msg);
+            }
+        }
+        for (int g = 0; g < 2; ++g) {
+            if (!Bt->eng[g]) continue;
+            hss_status st = engine_init(*Bt->eng[g]);
+            if (st != HSS_OK) {
+                delete Bt;
+                return st;
+            }
+        }
+        *out = Bt;
+        return HSS_OK;
+    } catch (...) {
+        return fail(HSS_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+void hss_batch_destroy(hss_batch_t Bt) {
+    if (!Bt) return;
+    try {
+        delete Bt;
+    } catch (...) {
+    }
+}
+
+size_t hss_batch_workspace_bytes(hss_batch_t Bt) {
+    if (!Bt) return 0;
+    size_t b = 0;
+    for (Engine* E : Bt->eng)
+        if (E) b += E->arena_bytes + E->probe_bytes + E->cm_cap * 4;
+    return b;
+}
+
+hss_status hss_batch_partition(hss_batch_t Bt, const hss_instance_io* io, void* stream) {
+    try {
+        if (!Bt || !io) return fail(HSS_ERR_INVALID_ARG, "null batch or io");
+        for (uint32_t i = 0; i < Bt->where.size(); ++i) {
+            const Engine& E = *Bt->eng[Bt->where[i].first];
+            const InstHost& h = E.ih[Bt->where[i].second];
+            const hss_instance_io& x = io[i];
+            if (!x.offsets) return fail(HSS_ERR_INVALID_ARG, "null offsets of instance " + std::to_string(i));
+            hss_status st = check_io(E, h, x.keys_in, x.vals_in, x.keys_out, x.vals_out, x.offsets);
+            if (st != HSS_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_last_error);
+        }
+        hipStream_t s = (hipStream_t)stream;
+        for (int g = 0; g < 2; ++g) {
+            Engine* E = Bt->eng[g];
+            if (!E) continue;
+            HIP_TRY(hipSetDevice(E->device));
+            for (uint32_t i = 0; i < Bt->where.size(); ++i) {
+                if (Bt->where[i].first != g) continue;
+                const hss_instance_io& x = io[i];
+                E->h_run[Bt->where[i].second] = InstRun{x.seed, x.keys_in, x.vals_in, x.keys_out,
+                                                        x.vals_out, x.offsets};
+            }
+            HIP_TRY(hipMemcpyAsync(E->run_d, E->h_run, E->ih.size() * sizeof(InstRun),
+                                   hipMemcpyHostToDevice, s));
+            HIP_TRY(launch_counters_reset(E->ra.ctr, s));
+            hss_status st = engine_run(*E, nullptr, nullptr, nullptr, nullptr, s, false);
+            if (st != HSS_OK) return st;
+            st = finish(*E, s);
+            if (st != HSS_OK) return st;
+        }
+        return HSS_OK;
+    } catch (...) {
+        return fail(HSS_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+hss_status hss_batch_profile(hss_batch_t Bt, int enable) {
+    if (!Bt) return fail(HSS_ERR_INVALID_ARG, "null batch");
+    for (Engine* E : Bt->eng)
+        if (E) {
+            E->prof.collect();
+            E->prof.on = enable != 0;
+        }
+    return HSS_OK;
+}
+
+hss_status hss_batch_profile_reset(hss_batch_t Bt) {
+    if (!Bt) return fail(HSS_ERR_INVALID_ARG, "null batch");
+    for (Engine* E : Bt->eng)
+        if (E) E->prof.reset();
+    return HSS_OK;
+}
+
+hss_status hss_batch_profile_read(hss_batch_t Bt, uint32_t family, double* ms, uint64_t* launches,
+                                  uint64_t* bytes) {
+    if (!Bt || family >= (uint32_t)kProfSlots) return fail(HSS_ERR_INVALID_ARG, "bad batch or family");
+    double t = 0;
+    uint64_t l = 0, b = 0;
+    for (Engine* E : Bt->eng)
+        if (E) {
+            E->prof.collect();
+            t += E->prof.ms[family];
+            l += E->prof.launches[family];
+            b += E->prof.bytes[family];
+        }
+    if (ms) *ms = t;
+    if (launches) *launches = l;
+    if (bytes) *bytes = b;
     return HSS_OK;
 }
 

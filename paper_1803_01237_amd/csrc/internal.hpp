@@ -126,6 +126,10 @@ struct TileMap {
     const uint32_t* tile_seg = nullptr;
     const uint32_t* tile0 = nullptr;
     uint32_t tps = 0;
+    // optional per-segment source: device addresses of the segment's first
+    // key (and payload word); otherwise the pass input at position beg[s]
+    const uint64_t* src = nullptr;
+    const uint64_t* vsrc = nullptr;
 };
 
 // One stable counting pass on digit [shift, shift+8) of every segment.
@@ -147,6 +151,7 @@ struct RadixPass {
     // keys only and the order of equal digits within a run is free (a pass
     // whose runs are fully sorted afterwards): rank by LDS atomics
     bool any_order = false;
+    bool has_payload = false;          // payload read through map.vsrc (vals_in may be null)
     Profiler* prof = nullptr;
 };
 
@@ -157,14 +162,20 @@ hipError_t segmented_radix_sort(const SegSort& a, hipStream_t stream);
 // --------------------------------------------------------------- fences ----
 // Every kFenceStride-th key of each locally sorted segment, kept so that a
 // search inside a segment can start from on-chip fences and finish inside
-// one cache line: key[s * per_seg + f] = key at position f * kFenceStride of
-// segment s (widened to 64 bits).
+// one cache line: key[base[s] + f] = key at position f * kFenceStride of
+// segment s (widened to 64 bits); base[s] = sum over earlier segments of
+// ceil(length / kFenceStride).
 constexpr int kFenceStride = 16;
 
 struct Fences {
     uint64_t* key = nullptr;
-    uint64_t per_seg = 0;              // ceil(max segment length / kFenceStride)
+    const uint64_t* base = nullptr;    // S+1 entries
+    const uint64_t* seg_off = nullptr; // S+1 entries, positions of the sorted buffer
 };
+
+// Fences of segments sorted by another path (the LSD-only mode).
+hipError_t write_fences(const void* keys, int key_bytes, uint32_t num_segs, const Fences& f,
+                        hipStream_t s);
 
 // ---------------------------------------------------------- hybrid sort ----
 // Sub-buckets too large for LDS, collected on the device.
@@ -218,7 +229,31 @@ struct HybridSort {
     SlowList sl;
     Fences fences;                     // optional: written for the sorted output
     Profiler* prof = nullptr;
+    // Segment selection (all optional).  By default every segment s of
+    // seg_off takes the MSD pass.  With msd_seg, only the listed segments do
+    // (num_segs of them, spanning [msd_beg[i], msd_end[i]) with the tile list
+    // msd_tile_seg / msd_tile0 of msd_tiles tiles), and the n_direct
+    // segments of direct_seg (at most the small-sort capacity each) are
+    // sorted in one step.  msd_src / direct_src give per-segment device
+    // addresses of the input keys (payload: *_vsrc); otherwise keys_in at
+    // the segment's position.
+    bool has_payload = false;          // payload read through the *_vsrc sources
+    const uint32_t* msd_seg = nullptr;
+    const uint64_t* msd_beg = nullptr;
+    const uint64_t* msd_end = nullptr;
+    const uint32_t* msd_tile_seg = nullptr;
+    const uint32_t* msd_tile0 = nullptr;
+    uint32_t msd_tiles = 0;
+    const uint64_t* msd_src = nullptr;
+    const uint64_t* msd_vsrc = nullptr;
+    const uint32_t* direct_seg = nullptr;
+    uint32_t n_direct = 0;
+    const uint64_t* direct_src = nullptr;
+    const uint64_t* direct_vsrc = nullptr;
 };
+
+// Largest segment the small sort takes in one step (direct segments).
+constexpr uint32_t kDirectSegMax = 2048;
 
 // Host-side state of the hybrid sort: pinned read-back words and the count
 // table of the oversize passes, grown on demand.
@@ -236,101 +271,170 @@ uint64_t oversize_tile_capacity(uint32_t num_segs, uint64_t total_len);
 uint64_t slow_capacity(uint32_t num_segs, uint64_t total_len);
 
 // --------------------------------------------------------------- rounds ----
-// Device counters read back once per round.
+// The splitter rounds of any number of independent instances at once.  Index
+// spaces (all global over the instances of a plan):
+//   positions  instance I owns [pos0, pos0 + n) of the sorted buffer B; its
+//              tags g (section 6.1) are positions relative to pos0
+//   segments   instance I owns segments [seg0, seg0 + p)
+//   rows       instance I owns splitter rows [row0, row0 + p]; row row0 + i
+//              holds splitter i (rows i = 0 and i = p are the fixed ends)
+//   tables     per-segment counts of instance I's row i live at
+//              tab0 + i * p + s, s < p (lpos, upos, prow)
+struct InstDesc {
+    uint64_t n;
+    uint64_t pos0;
+    uint64_t tol;
+    uint64_t tab0;
+    uint32_t p;
+    uint32_t seg0;
+    uint32_t row0;
+    uint32_t pad;
+};
+
+// Per call: seed and the caller's buffers of every instance.
+struct InstRun {
+    uint64_t seed;
+    const void* kin;
+    const uint64_t* vin;
+    void* kout;
+    uint64_t* vout;
+    uint64_t* offsets;             // p + 1 entries: chi
+};
+
+// Device counters of the current round and of the call.
 struct RoundCounters {
     unsigned long long m;          // probes emitted this round (may exceed capacity)
-    unsigned long long domain;     // keys in the sampled domain
+    unsigned long long domain;     // tags in the sampled domain
     unsigned long long blocks;     // Philox blocks in the flattened domain
+    unsigned long long m_stored;   // probes kept (m unless over capacity)
+    unsigned long long cm_need;    // count-matrix words of this round
+    unsigned long long m_max;      // largest m of the call (capacity growth)
+    unsigned long long cm_max;     // largest cm_need of the call
     unsigned int n_ivl;            // distinct unsettled intervals
     unsigned int n_slices;         // non-empty (interval, segment) slices
     unsigned int n_unsettled;      // unsettled splitters before the round
-    unsigned int n_req;            // locate requests emitted by the settle step
+    unsigned int n_after;          // unsettled splitters after the round
+    unsigned int tiles;            // workgroups of the probe ranking
     unsigned int err;              // device consistency failures (bit set)
+    unsigned int overflow;         // a capacity was exceeded: the call's later work is skipped
+};
+
+// Counts of round j, kept for the host to read once after the rounds.
+struct RoundHist {
+    unsigned long long domain;     // tags sampled from
+    unsigned long long m;          // probes
+    unsigned int unsettled;        // unsettled splitters before the round
+    unsigned int pad;
 };
 
 enum DeviceErr : unsigned int {
     kErrProbeOutside = 1u,         // a probe outside its own interval slice
     kErrRankOrder = 2u,            // ranks not strictly increasing in probe order
-    kErrPieceSum = 4u,             // bucket pieces do not add up to the bucket size
+    kErrPieceSum = 4u,             // a bucket's pieces do not add up to chi(b+1) - chi(b)
 };
 
 struct RoundArgs {
     int key_bytes;
-    const void* B;                 // locally sorted keys
-    uint64_t n;
-    uint32_t p;
-    const uint64_t* seg_off;       // p+1
-    const uint64_t* ideal;         // p+1, floor(i N / p)
-    uint64_t tol;
-    // splitter state, indexed 0..p (1..p-1 used)
+    const void* B;                 // locally sorted keys of all instances
+    uint32_t n_inst, n_rows, n_segs, p_max;
+    uint32_t J;                    // rounds in the rate table
+    const InstDesc* inst;
+    const InstRun* run;
+    const uint32_t* thresh;        // n_inst x J: acceptance threshold of round j at [I J + j - 1]
+    const uint8_t* all;            // n_inst x J: 1 = every tag of the domain is a probe
+    const uint64_t* seg_off;       // S+1 positions
+    const uint32_t* seg_inst;      // S
+    const uint32_t* row_inst;      // Q
+    const uint64_t* ideal;         // Q: floor(i n / p) of row i
+    // splitter state, Q rows
     uint32_t* settled;
     uint64_t* chi;
     uint64_t* lrank;
     uint64_t* urank;
     uint64_t* s_key;
     uint64_t* s_tag;
-    uint32_t* lpos;                // (p+1) x p
-    uint32_t* upos;                // (p+1) x p
-    uint32_t* prow;                // (p+1) x p
-    // intervals
-    uint32_t* ivl_row;             // p
-    uint4* slices;                 // p x p: non-empty slices {first block, first tag, end tag, interval}
-    uint32_t* ivl_nz;              // p+1: non-empty slice counts, then exclusive offsets
-    uint64_t* ivl_tot;             // p+1: block totals, then exclusive offsets
-    uint64_t* ivl_dom;             // p
-    // probes
-    uint64_t cap;                  // probe capacity
+    uint32_t* lpos;                // sum over instances of (p+1) p
+    uint32_t* upos;
+    uint32_t* prow;
+    // intervals (at most Q)
+    uint32_t* ivl_row;
+    uint32_t* ivl_inst;
+    uint64_t* ivl_tot;             // Philox blocks, then exclusive offsets
+    uint32_t* ivl_nz;              // non-empty slices, then exclusive offsets
+    uint64_t* ivl_dom;
+    uint32_t* ivl_pcnt;            // probes of the interval
+    uint32_t* ivl_poff;            // their first sorted index
+    uint32_t* ivl_cursor;
+    uint32_t* ivl_tile0;           // first ranking workgroup of the interval
+    uint4* slices;                 // {first block, first tag, end tag, interval}
+    // per instance, per round
+    uint32_t* inst_plo;            // first sorted probe of the instance
+    uint32_t* inst_pm;             // its probes
+    uint64_t* cm_off;              // its count-matrix block
+    // probes (capacity cap)
+    uint64_t cap;
     uint64_t* pr_key;
     uint64_t* pr_tag;
     uint32_t* pr_ivl;
-    uint64_t* ps_key;              // sorted
+    uint64_t* g_key;               // grouped by interval
+    uint64_t* g_tag;
+    uint64_t* ps_key;              // sorted by (instance, key, tag)
     uint64_t* ps_tag;
     uint32_t* ps_ivl;
-    uint64_t* pr_rank;             // rank R of sorted probe e
-    uint32_t* pr_pos;              // sorted position of emitted probe
-    uint32_t* ps_seg;              // segment of sorted probe e
-    // requests
-    uint32_t* req_probe;
-    uint32_t* req_row;
-    uint32_t* req_kind;
+    uint32_t* ps_seg;
+    uint64_t* pr_rank;
+    uint32_t* cmat;                // count matrix, capacity cm_cap words
+    uint64_t cm_cap;
+    // rank work list: chunk c covers keys [chunk_lo[c], +kRankChunk) of segment chunk_seg[c]
+    const uint32_t* chunk_seg;
+    const uint32_t* chunk_lo;
+    uint32_t n_chunks;
+    Fences fences;                 // of B
     RoundCounters* ctr;
+    RoundHist* hist;               // J entries
 };
 
-hipError_t launch_round_init(const RoundArgs& a, hipStream_t s);
-// Zero the round counters (the device error word included).
+constexpr uint32_t kRankChunk = 1u << 15;   // keys of a segment per rank workgroup
+
 hipError_t launch_counters_reset(RoundCounters* ctr, hipStream_t s);
-hipError_t launch_intervals(const RoundArgs& a, hipStream_t s);
-hipError_t launch_sample(const RoundArgs& a, uint64_t seed, uint32_t round, uint32_t thresh,
-                         int take_all, hipStream_t s);
-// Sort the m emitted probes by (key, tag) into ps_*; uses sort scratch for
-// large m.
-hipError_t launch_probe_sort(const RoundArgs& a, uint64_t m, void* scratch, size_t scratch_bytes,
-                             uint32_t* counts, hipStream_t s);
-size_t probe_sort_scratch_bytes(uint64_t m);
-// cmat (optional, p x m words, segment-major): c_s(e) at cmat[s * m + e],
-// kept for locate.  With fences (and cmat), the counts are found per
-// (segment, chunk) from on-chip fences; otherwise per probe by searching
-// every segment's slice.
-hipError_t launch_rank(const RoundArgs& a, uint64_t m, uint32_t* cmat, const Fences& fences,
-                       uint64_t max_seg, hipStream_t s);
-hipError_t launch_settle(const RoundArgs& a, uint64_t m, hipStream_t s);
-hipError_t launch_locate(const RoundArgs& a, const uint32_t* cmat, uint64_t m, hipStream_t s);
-hipError_t launch_finalize(const RoundArgs& a, uint64_t* d_offsets, hipStream_t s);
+// Start of a call's rounds: every splitter unsettled with open bounds.
+hipError_t launch_round_init(const RoundArgs& a, hipStream_t s);
+// One whole round j (section 4.2.2 steps 1-5) for every instance; sizes are
+// read on the device, so nothing here waits for the host.
+hipError_t launch_round(const RoundArgs& a, uint32_t j, hipStream_t s, Profiler* prof);
+// chi of every instance into its offsets array and into chi_all (Q entries).
+hipError_t launch_finalize(const RoundArgs& a, uint64_t* chi_all, hipStream_t s);
+// The per-call record of one instance, written on the stream (no host copy).
+hipError_t launch_set_run(const InstRun& r, InstRun* dst, hipStream_t s);
+// Caller buffers per segment: device addresses of the input keys (and
+// payload) of the segments list[x] (x < count; nullptr: segment x) for the
+// first sort pass.
+hipError_t launch_segment_sources(const RoundArgs& a, const uint32_t* list, uint32_t count,
+                                  uint64_t* key_src, uint64_t* val_src, int key_bytes,
+                                  hipStream_t s);
 
 // ------------------------------------------------------------- exchange ----
 struct ExchangeArgs {
     int key_bytes;
-    const void* B;
+    const void* B;                 // locally sorted keys of all instances
     const uint64_t* Bv;            // nullptr: keys only
-    void* out;
-    uint64_t* vout;
-    uint64_t n;
-    uint32_t p;
-    const uint64_t* seg_off;       // p+1
-    const uint32_t* prow;          // (p+1) x p, rows 1..p-1 used
-    const uint64_t* chi;           // p+1 (the offsets array)
-    uint32_t* dst;                 // p x p, offset of piece (b, s) inside bucket b
-    uint64_t max_bucket;
+    uint32_t n_inst;
+    uint32_t n_segs;               // = number of buckets
+    uint32_t p_max;                // largest p of the instances
+    const InstDesc* inst;
+    const InstRun* run;
+    const uint64_t* seg_off;
+    const uint32_t* seg_inst;
+    const uint32_t* prow;
+    const uint64_t* chi_all;       // Q rows
+    uint32_t* dst;                 // table-shaped: offset of piece (b, s) inside bucket b
+    uint32_t* chunk0;              // S+1: first copy workgroup of every bucket
+    uint64_t max_chunks;           // bound on the copy workgroups
+    uint64_t total;                // keys of all instances
+    // output: the caller's buffers of every instance, or (when out is set)
+    // one buffer at the instance positions
+    void* out = nullptr;
+    uint64_t* vout = nullptr;
     unsigned int* err;
     Profiler* prof = nullptr;      // optional
 };
@@ -342,5 +446,7 @@ hipError_t launch_exchange(const ExchangeArgs& a, hipStream_t s);
 // smallest shift with hi - lo < 2^(shift + 8).
 hipError_t launch_bucket_shift(uint32_t p, int key_bits, const uint64_t* s_key, uint8_t* shift,
                                uint64_t* base, hipStream_t s);
+// Upper bound of the copy workgroups for buckets of at most `total` keys.
+uint64_t exchange_chunk_bound(uint64_t total, uint32_t buckets);
 
 }  // namespace hss

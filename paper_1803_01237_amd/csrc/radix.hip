@@ -49,6 +49,20 @@ __device__ __forceinline__ bool tile_range(const TileMap& m, uint32_t bid, uint6
     return *base < e;
 }
 
+// First key of the tile starting at position `base` of segment `seg`.
+template <typename K>
+__device__ __forceinline__ const K* tile_source(const TileMap& m, const K* in, uint32_t seg,
+                                                uint64_t base) {
+    if (m.src) return (const K*)(uintptr_t)m.src[seg] + (base - m.beg[seg]);
+    return in + base;
+}
+
+__device__ __forceinline__ const uint64_t* tile_vsource(const TileMap& m, const uint64_t* in,
+                                                        uint32_t seg, uint64_t base) {
+    if (m.vsrc) return (const uint64_t*)(uintptr_t)m.vsrc[seg] + (base - m.beg[seg]);
+    return in + base;
+}
+
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(const K* __restrict__ keys,
                                                                    TileMap m, int shift,
@@ -65,12 +79,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(const K* __re
         const uint32_t n_tile = (uint32_t)min((uint64_t)kSortTile, e - base);
         const uint32_t w = threadIdx.x / kWave;
         const uint32_t lane = lane_id();
+        const K* src = tile_source(m, keys, seg, base);
         // all loads of the tile in flight before any counting
         K kr[kSortItems];
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
             const uint32_t li = w * kKeysPerWave + r * kWave + lane;
-            kr[r] = li < n_tile ? keys[base + li] : (K)0;
+            kr[r] = li < n_tile ? src[li] : (K)0;
         }
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
@@ -177,12 +192,13 @@ __global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
         if (digit_thread) gofs[threadIdx.x] = counts[(uint64_t)tile * 256 + threadIdx.x];
         __syncthreads();
 
+        const K* src = tile_source(m, kin, seg, base);
         K key[kIt];
         uint32_t rank[kIt];
 #pragma unroll
         for (int r = 0; r < kIt; ++r) {
             const uint32_t li = w * kKpw + r * kWave + lane;
-            key[r] = li < n_tile ? kin[base + li] : (K)0;
+            key[r] = li < n_tile ? src[li] : (K)0;
         }
         if constexpr (kStable) {
 #pragma unroll
@@ -248,12 +264,13 @@ __global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
             }
         }
         __syncthreads();
+        const uint64_t* vsrc = kPayload ? tile_vsource(m, vin, seg, base) : nullptr;
         for (uint32_t i = threadIdx.x; i < n_tile; i += kScatterThreads) {
             const K k = (K)stage[i];
             const uint32_t d = digit_of((K)(k - kb), shift);
             const uint64_t dst = b + gofs[d] + (i - tstart[d]);
             kout[dst] = k;
-            if constexpr (kPayload) vout[dst] = vin[base + sidx[i]];
+            if constexpr (kPayload) vout[dst] = vsrc[sidx[i]];
         }
     }
 }
@@ -263,7 +280,7 @@ hipError_t pass_impl(const RadixPass& a, hipStream_t stream) {
     if (a.num_segs == 0 || a.num_tiles == 0) return hipSuccess;
     Profiler dummy;
     Profiler& prof = a.prof ? *a.prof : dummy;
-    const bool pay = a.vals_in != nullptr;
+    const bool pay = a.vals_in != nullptr || a.has_payload;
     // algorithmic bytes: the keys (and payload) are read by the count pass,
     // read and written by the scatter pass; the count table is written by the
     // count pass, read and written by the scan, read by the scatter pass

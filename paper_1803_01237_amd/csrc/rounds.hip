@@ -1,25 +1,34 @@
-// Splitter rounds of HSS (section 4.2.2, steps 1-5), all on the device.
+// Splitter rounds of HSS (section 4.2.2, steps 1-5) on the device, for any
+// number of independent instances in the same launches.
 //
-// Round j, given the splitter state after round j-1:
-//   intervals -- the distinct open intervals (L_i, U_i) of unsettled splitters
-//                (identical intervals are taken once: they are either disjoint
-//                or identical, section 4.2.2)
-//   slices    -- per (interval, segment) the slice of the locally sorted
-//                segment strictly inside the interval, as a run of 4-tag
-//                Philox blocks in one flattened block space; the non-empty
-//                slices are listed in (interval, segment) order
-//   sample    -- every tag of the domain draws its Philox word and becomes a
-//                probe when the word is below the round threshold
-//                (section 4.2.1: independent Bernoulli with rate p s_j / N)
-//   probe sort-- probes ordered by (key, tag), the strict order of section 6.1
-//   rank      -- per probe, the number of keys of every segment that precede
-//                it (the local histograms), summed over segments in the same
-//                workgroup (the reduction of section 5.2)
-//   settle    -- per unsettled splitter, a probe in its target range settles
-//                it (closest to N i/p, lower rank on a tie); otherwise L and U
-//                move to the closest probe ranks below and above N i/p
-//   locate    -- per-segment counts of every new bound / splitter probe, which
-//                become the next round's slice ends and the piece boundaries
+// Round j, given the splitter state after round j-1, for every instance:
+//   leaders  -- the distinct open intervals (L_i, U_i) of unsettled splitters
+//               (identical intervals are taken once: they are either disjoint
+//               or identical, section 4.2.2)
+//   slices   -- per (interval, segment) the slice of the locally sorted
+//               segment strictly inside the interval, as a run of 4-tag
+//               Philox blocks of one flattened block space; the non-empty
+//               slices are listed in (interval, segment) order
+//   sample   -- every tag of the domain draws its Philox word and becomes a
+//               probe when the word is below the instance's round threshold
+//               (section 4.2.1: independent Bernoulli trials at rate p s_j/N)
+//   group,   -- probes by interval; the intervals of an instance are disjoint
+//   order       and in key order, so ranking (key, tag) inside each interval
+//               sorts every instance's probes (the strict order of section 6.1)
+//   rank     -- per probe and segment of its instance, the keys below it (the
+//               local histograms), found from the segment's fences in LDS
+//   reduce   -- R(e), the sum over the instance's segments (section 5.2)
+//   settle   -- a probe in the target range settles splitter i (closest to
+//               N i/p, lower rank on a tie); otherwise L and U move to the
+//               closest probe ranks below and above N i/p
+//               and the per-segment counts of every new bound or splitter
+//               probe become the next round's slice ends and the piece
+//               boundaries
+// Every size (intervals, probes, work items) is read on the device, so a
+// whole round is queued without waiting for the host, and a round with
+// nothing left to do does nothing.  A capacity overrun sets a flag that turns
+// the rest of the call into no-ops; the host then grows the buffers and runs
+// the rounds again (the draws depend only on seed, tag and round).
 
 #include "device.hpp"
 #include "internal.hpp"
@@ -28,75 +37,32 @@ namespace hss {
 
 namespace {
 
-constexpr int kT = 256;           // threads of most round kernels
-constexpr int kSampleGrid = 4096; // workgroups of the grid-stride sampler
-constexpr uint64_t kCountSortMax = 32768;   // probe sort by pairwise counting up to here
-constexpr int kCountTile = 256;
+constexpr int kT = 256;
+constexpr int kScanT = 1024;            // threads of the one-workgroup scans
+constexpr int kSampleGrid = 4096;       // workgroups of the sampler
+constexpr uint32_t kRankFences = kRankChunk / kFenceStride;
+constexpr uint32_t kReduceRows = 16;    // segments summed per reduction workgroup
+constexpr uint32_t kOrderLanes = 64;    // probes per ordering workgroup
+constexpr uint32_t kOrderThreads = 512; // their comparisons split over 8 waves
 
-__global__ void round_init_kernel(uint32_t p, uint32_t* settled, uint64_t* chi, uint64_t* lrank,
-                                  uint64_t* urank, RoundCounters* ctr) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= p; i += gridDim.x * blockDim.x) {
-        settled[i] = 0;
-        chi[i] = 0;
-        lrank[i] = kNone;
-        urank[i] = kNone;
+__device__ __forceinline__ bool halted(const RoundArgs& a) { return a.ctr->overflow != 0; }
+
+// Exclusive scan of v[0, n) in place by one workgroup of kScanT threads
+// (thread t scans a contiguous run serially); returns the total.
+template <typename T>
+__device__ uint64_t wg_scan_inplace(T* v, uint32_t n, uint64_t* scratch) {
+    const uint32_t per = (n + kScanT - 1) / kScanT;
+    const uint32_t r0 = min(threadIdx.x * per, n), r1 = min(r0 + per, n);
+    uint64_t local = 0;
+    for (uint32_t i = r0; i < r1; ++i) local += v[i];
+    uint64_t tot;
+    uint64_t run = block_exclusive_scan<uint64_t, kScanT>(local, scratch, &tot);
+    for (uint32_t i = r0; i < r1; ++i) {
+        const uint64_t x = v[i];
+        v[i] = (T)run;
+        run += x;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctr->m = 0;
-        ctr->domain = 0;
-        ctr->blocks = 0;
-        ctr->n_ivl = 0;
-        ctr->n_slices = 0;
-        ctr->n_unsettled = 0;
-        ctr->n_req = 0;
-        ctr->err = 0;
-    }
-}
-
-__global__ void counters_reset_kernel(RoundCounters* ctr) {
-    *ctr = RoundCounters{};
-}
-
-// One workgroup: leaders of runs of identical unsettled intervals, in
-// splitter order, compacted into ivl_row.
-__global__ __launch_bounds__(1024) void leaders_kernel(RoundArgs a) {
-    __shared__ uint32_t scratch[1024 / kWave];
-    uint32_t base = 0, unsettled = 0;
-    for (uint32_t c = 1; c < a.p; c += 1024) {
-        const uint32_t i = c + threadIdx.x;
-        const bool u = i < a.p && a.settled[i] == 0;
-        bool lead = u;
-        if (u && i > 1 && a.settled[i - 1] == 0 && a.lrank[i - 1] == a.lrank[i] &&
-            a.urank[i - 1] == a.urank[i])
-            lead = false;
-        uint32_t tot;
-        const uint32_t pre = block_exclusive_scan<uint32_t, 1024>(lead ? 1u : 0u, scratch, &tot);
-        if (lead) a.ivl_row[base + pre] = i;
-        base += tot;
-        uint32_t ut;
-        block_exclusive_scan<uint32_t, 1024>(u ? 1u : 0u, scratch, &ut);
-        unsettled += ut;
-    }
-    if (threadIdx.x == 0) {
-        a.ctr->n_ivl = base;
-        a.ctr->n_unsettled = unsettled;
-        a.ctr->m = 0;
-        a.ctr->n_req = 0;
-    }
-}
-
-__device__ __forceinline__ void slice_bounds(const RoundArgs& a, uint32_t row, uint32_t s,
-                                             bool lnone, bool unone, uint64_t* ga, uint64_t* gb) {
-    const uint64_t sb = a.seg_off[s];
-    const uint64_t slen = a.seg_off[s + 1] - sb;
-    const uint64_t lo = lnone ? 0 : a.lpos[(uint64_t)row * a.p + s];
-    const uint64_t hi = unone ? slen : a.upos[(uint64_t)row * a.p + s];
-    *ga = sb + lo;
-    *gb = sb + (hi > lo ? hi : lo);
-}
-
-__device__ __forceinline__ uint64_t blocks_of(uint64_t ga, uint64_t gb) {
-    return gb > ga ? ((gb - 1) >> 2) - (ga >> 2) + 1 : 0;
+    return tot;
 }
 
 // Last index i in [0, n) with v[i] <= x (v non-decreasing, v[0] <= x).
@@ -110,28 +76,106 @@ __device__ __forceinline__ uint32_t last_le(const T* v, uint32_t n, uint64_t x) 
     return lo;
 }
 
+__global__ void counters_reset_kernel(RoundCounters* ctr) { *ctr = RoundCounters{}; }
+
+__global__ void round_init_kernel(RoundArgs a) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < a.n_rows; r += gridDim.x * blockDim.x) {
+        const InstDesc& D = a.inst[a.row_inst[r]];
+        const uint32_t i = r - D.row0;
+        a.settled[r] = (i == 0 || i == D.p) ? 1u : 0u;   // the ends are fixed
+        a.chi[r] = 0;                                       // until the splitter settles
+        a.lrank[r] = kNone;
+        a.urank[r] = kNone;
+        a.s_key[r] = 0;
+        a.s_tag[r] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.ctr = RoundCounters{};
+}
+
+// One workgroup: leaders of runs of identical unsettled intervals, in row
+// order (instance by instance, splitter by splitter).
+__global__ __launch_bounds__(kScanT) void leaders_kernel(RoundArgs a, uint32_t round) {
+    __shared__ uint32_t scratch[kScanT / kWave];
+    if (halted(a)) {
+        if (threadIdx.x == 0) { a.ctr->n_ivl = 0; a.ctr->n_unsettled = 0; }
+        return;
+    }
+    const uint32_t Q = a.n_rows;
+    const uint32_t per = (Q + kScanT - 1) / kScanT;
+    const uint32_t r0 = min(threadIdx.x * per, Q), r1 = min(r0 + per, Q);
+    // row 0 of every instance is a settled end, so an unsettled row r has r >= 1
+    auto lead = [&](uint32_t r) {
+        return a.settled[r] == 0 &&
+               !(a.settled[r - 1] == 0 && a.lrank[r - 1] == a.lrank[r] && a.urank[r - 1] == a.urank[r]);
+    };
+    uint32_t nl = 0, nu = 0;
+    for (uint32_t r = r0; r < r1; ++r) {
+        nl += lead(r) ? 1u : 0u;
+        nu += a.settled[r] == 0 ? 1u : 0u;
+    }
+    uint32_t tot;
+    uint32_t o = block_exclusive_scan<uint32_t, kScanT>(nl, scratch, &tot);
+    const uint32_t unsettled = block_sum<uint32_t, kScanT>(nu, scratch);
+    for (uint32_t r = r0; r < r1; ++r) {
+        if (lead(r)) {
+            a.ivl_row[o] = r;
+            a.ivl_inst[o] = a.row_inst[r];
+            ++o;
+        }
+    }
+    if (threadIdx.x == 0) {
+        RoundCounters* c = a.ctr;
+        a.hist[round - 1] = RoundHist{0, 0, unsettled, 0};
+        c->n_ivl = tot;
+        c->n_unsettled = unsettled;
+        c->n_after = 0;
+        c->m = 0;
+        c->m_stored = 0;
+        c->blocks = 0;
+        c->domain = 0;
+        c->n_slices = 0;
+        c->tiles = 0;
+        c->cm_need = 0;
+    }
+}
+
+// Slice of segment s of instance D strictly inside the interval of its row i,
+// as instance tags [ga, gb).
+__device__ __forceinline__ void slice_bounds(const RoundArgs& a, const InstDesc& D, uint32_t i,
+                                             uint32_t s, bool lnone, bool unone, uint64_t* ga,
+                                             uint64_t* gb) {
+    const uint32_t seg = D.seg0 + s;
+    const uint64_t sb = a.seg_off[seg] - D.pos0;
+    const uint64_t slen = a.seg_off[seg + 1] - a.seg_off[seg];
+    const uint64_t lo = lnone ? 0 : a.lpos[D.tab0 + (uint64_t)i * D.p + s];
+    const uint64_t hi = unone ? slen : a.upos[D.tab0 + (uint64_t)i * D.p + s];
+    *ga = sb + lo;
+    *gb = sb + (hi > lo ? hi : lo);
+}
+
+__device__ __forceinline__ uint64_t blocks_of(uint64_t ga, uint64_t gb) {
+    return gb > ga ? ((gb - 1) >> 2) - (ga >> 2) + 1 : 0;
+}
+
 // Workgroup per interval k: Philox blocks, non-empty slices and tags of its
-// p slices.
+// slices; clears its probe counters.
 __global__ __launch_bounds__(kT) void slices_kernel(RoundArgs a) {
     __shared__ uint64_t scratch[kT / kWave];
     const uint32_t k = blockIdx.x;
     if (k >= a.ctr->n_ivl) return;
     const uint32_t row = a.ivl_row[k];
+    const InstDesc D = a.inst[a.ivl_inst[k]];
+    const uint32_t i = row - D.row0;
     const bool lnone = a.lrank[row] == kNone;
     const bool unone = a.urank[row] == kNone;
     uint64_t nb_sum = 0, nz_sum = 0, dom = 0;
-    for (uint32_t s0 = 0; s0 < a.p; s0 += kT) {
-        const uint32_t s = s0 + threadIdx.x;
-        uint64_t nb = 0, len = 0;
-        if (s < a.p) {
-            uint64_t ga, gb;
-            slice_bounds(a, row, s, lnone, unone, &ga, &gb);
-            nb = blocks_of(ga, gb);
-            len = gb - ga;
-        }
+    for (uint32_t s = threadIdx.x; s < D.p; s += kT) {
+        uint64_t ga, gb;
+        slice_bounds(a, D, i, s, lnone, unone, &ga, &gb);
+        const uint64_t nb = blocks_of(ga, gb);
         nb_sum += nb;
         nz_sum += nb ? 1 : 0;
-        dom += len;
+        dom += gb - ga;
     }
     nb_sum = block_sum<uint64_t, kT>(nb_sum, scratch);
     nz_sum = block_sum<uint64_t, kT>(nz_sum, scratch);
@@ -140,36 +184,28 @@ __global__ __launch_bounds__(kT) void slices_kernel(RoundArgs a) {
         a.ivl_tot[k] = nb_sum;
         a.ivl_nz[k] = (uint32_t)nz_sum;
         a.ivl_dom[k] = dom;
+        a.ivl_pcnt[k] = 0;
+        a.ivl_cursor[k] = 0;
     }
 }
 
 // One workgroup: exclusive scans of the interval block and slice totals.
-__global__ __launch_bounds__(1024) void ivl_scan_kernel(RoundArgs a) {
-    __shared__ uint64_t scratch[1024 / kWave];
+__global__ __launch_bounds__(kScanT) void ivl_scan_kernel(RoundArgs a) {
+    __shared__ uint64_t scratch[kScanT / kWave];
     const uint32_t n = a.ctr->n_ivl;
-    uint64_t run = 0, run_nz = 0, dom = 0;
-    for (uint32_t c = 0; c < n; c += 1024) {
-        const uint32_t k = c + threadIdx.x;
-        const uint64_t v = k < n ? a.ivl_tot[k] : 0;
-        const uint64_t z = k < n ? a.ivl_nz[k] : 0;
-        const uint64_t d = k < n ? a.ivl_dom[k] : 0;
-        uint64_t tot, tot_nz;
-        const uint64_t pre = block_exclusive_scan<uint64_t, 1024>(v, scratch, &tot);
-        const uint64_t pre_nz = block_exclusive_scan<uint64_t, 1024>(z, scratch, &tot_nz);
-        if (k < n) {
-            a.ivl_tot[k] = run + pre;
-            a.ivl_nz[k] = (uint32_t)(run_nz + pre_nz);
-        }
-        run += tot;
-        run_nz += tot_nz;
-        dom += block_sum<uint64_t, 1024>(d, scratch);
-    }
+    const uint64_t blocks = wg_scan_inplace(a.ivl_tot, n, scratch);
+    const uint64_t slices = wg_scan_inplace(a.ivl_nz, n, scratch);
+    const uint32_t per = (n + kScanT - 1) / kScanT;
+    const uint32_t r0 = min(threadIdx.x * per, n), r1 = min(r0 + per, n);
+    uint64_t d = 0;
+    for (uint32_t k = r0; k < r1; ++k) d += a.ivl_dom[k];
+    d = block_sum<uint64_t, kScanT>(d, scratch);
     if (threadIdx.x == 0) {
-        a.ivl_tot[n] = run;
-        a.ivl_nz[n] = (uint32_t)run_nz;
-        a.ctr->blocks = run;
-        a.ctr->n_slices = (uint32_t)run_nz;
-        a.ctr->domain = dom;
+        a.ivl_tot[n] = blocks;
+        a.ivl_nz[n] = (uint32_t)slices;
+        a.ctr->blocks = blocks;
+        a.ctr->n_slices = (uint32_t)slices;
+        a.ctr->domain = d;
     }
 }
 
@@ -181,14 +217,16 @@ __global__ __launch_bounds__(kT) void compact_kernel(RoundArgs a) {
     const uint32_t k = blockIdx.x;
     if (k >= a.ctr->n_ivl) return;
     const uint32_t row = a.ivl_row[k];
+    const InstDesc D = a.inst[a.ivl_inst[k]];
+    const uint32_t i = row - D.row0;
     const bool lnone = a.lrank[row] == kNone;
     const bool unone = a.urank[row] == kNone;
     uint64_t run = a.ivl_tot[k], run_nz = a.ivl_nz[k];
-    for (uint32_t s0 = 0; s0 < a.p; s0 += kT) {
+    for (uint32_t s0 = 0; s0 < D.p; s0 += kT) {
         const uint32_t s = s0 + threadIdx.x;
         uint64_t nb = 0, ga = 0, gb = 0;
-        if (s < a.p) {
-            slice_bounds(a, row, s, lnone, unone, &ga, &gb);
+        if (s < D.p) {
+            slice_bounds(a, D, i, s, lnone, unone, &ga, &gb);
             nb = blocks_of(ga, gb);
         }
         uint64_t tot, tot_nz;
@@ -206,9 +244,8 @@ __global__ __launch_bounds__(kT) void compact_kernel(RoundArgs a) {
 // slices are non-empty, so the 64 blocks of a step lie in the 64 slices that
 // start with the slice of the step's first block, and the next step's first
 // block lies at most one slice past the window.
-template <typename K>
-__global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint64_t seed, uint32_t round,
-                                                    uint32_t thresh, int take_all) {
+template <typename K, bool kSingle>
+__global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint32_t round) {
     constexpr uint32_t kNoBlock = 0xFFFFFFFFu;   // start of the entries past the list
     const uint32_t total = (uint32_t)a.ctr->blocks;
     const uint32_t nsl = a.ctr->n_slices;
@@ -232,6 +269,19 @@ __global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint64_t seed, 
         hi = min(lo + step, hi);
     }
     uint32_t jq = lo + (uint32_t)__popcll(__ballot(lo + lane < hi && sl[lo + lane].x <= b_lo)) - 1;
+
+    // parameters of the lane's current interval (instance seed, rate, base);
+    // the same for every lane when the engine holds one instance
+    constexpr bool single = kSingle;
+    uint32_t cur_k = kNoBlock, th = 0;
+    bool take_all = false;
+    uint64_t seed = 0, pos0 = 0;
+    if (single) {
+        seed = a.run[0].seed;
+        pos0 = a.inst[0].pos0;
+        th = a.thresh[round - 1];
+        take_all = a.all[round - 1] != 0;
+    }
 
     uint4 e = jq + lane < nsl ? sl[jq + lane] : make_uint4(kNoBlock, 0, 0, 0);
     uint32_t nxt = jq + kWave < nsl ? sl[jq + kWave].x : kNoBlock;
@@ -263,13 +313,21 @@ __global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint64_t seed, 
         uint32_t hits = 0;   // bit q: tag 4 blk + q is a probe
         uint64_t blk = 0;
         if (b < b_hi) {
-            // tags are below 2^32 (N < 2^32), so block and tag fit 32 bits
+            if (!single && k != cur_k) {
+                cur_k = k;
+                const uint32_t I = a.ivl_inst[k];
+                seed = a.run[I].seed;
+                pos0 = a.inst[I].pos0;
+                th = a.thresh[(uint64_t)I * a.J + (round - 1)];
+                take_all = a.all[(uint64_t)I * a.J + (round - 1)] != 0;
+            }
+            // tags are below 2^32, so block and tag fit 32 bits
             const uint32_t blk32 = (ga >> 2) + (b - s_first);
             blk = blk32;
             const Philox4 r = sample_block(seed, blk, round);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                if (take_all || r.v[q] < thresh) hits |= 1u << q;
+                if (take_all || r.v[q] < th) hits |= 1u << q;
             // the first and last block of a slice may hold tags outside it
             const uint32_t g0 = blk32 * 4;
             if (g0 < ga || (uint64_t)g0 + 4 > gb) {
@@ -288,12 +346,14 @@ __global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint64_t seed, 
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if (hits & (1u << q)) {
+                    const uint64_t g = blk * 4 + q;
                     if (o < a.cap) {
-                        const uint64_t g = blk * 4 + q;
-                        a.pr_key[o] = (uint64_t)B[g];
+                        a.pr_key[o] = (uint64_t)B[pos0 + g];
                         a.pr_tag[o] = g;
                         a.pr_ivl[o] = k;
-                        a.pr_pos[o] = 0;   // the probe sort counts into it
+                        atomicAdd(&a.ivl_pcnt[k], 1u);
+                    } else {
+                        atomicOr(&a.ctr->overflow, 1u);
                     }
                     ++o;
                 }
@@ -305,140 +365,208 @@ __global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint64_t seed, 
     }
 }
 
-// Sorted position of every probe: the number of probes before it in the
-// order (key, tag), counted against one tile of kCountTile probes per
-// workgroup row.
-__global__ __launch_bounds__(kT) void probe_count_kernel(const uint64_t* __restrict__ key,
-                                                         const uint64_t* __restrict__ tag,
-                                                         uint64_t m, uint32_t* __restrict__ pos) {
-    __shared__ uint64_t sk[kCountTile];
-    __shared__ uint64_t st[kCountTile];
-    const uint64_t j0 = (uint64_t)blockIdx.y * kCountTile;
-    const uint32_t nj = (uint32_t)min((uint64_t)kCountTile, m - j0);
-    for (uint32_t j = threadIdx.x; j < nj; j += kT) {
-        sk[j] = key[j0 + j];
-        st[j] = tag[j0 + j];
+// One workgroup: where every interval's probes go in sorted order, how many
+// ordering workgroups it takes, every instance's probe range and count-matrix
+// block; flags a capacity overrun.
+__global__ __launch_bounds__(kScanT) void probe_scan_kernel(RoundArgs a, uint32_t round) {
+    __shared__ uint64_t scratch[kScanT / kWave];
+    RoundCounters* c = a.ctr;
+    const uint64_t m = c->m;
+    // the sampler may already have flagged an overrun: record how many probes
+    // the round needs before anything else
+    if (threadIdx.x == 0 && m > c->m_max) c->m_max = m;
+    if (halted(a)) return;
+    if (threadIdx.x == 0) {
+        a.hist[round - 1].domain = c->domain;
+        a.hist[round - 1].m = m;
+    }
+    if (m > a.cap) {
+        if (threadIdx.x == 0) c->overflow = 1u;
+        return;
+    }
+    const uint32_t n = c->n_ivl;
+    const uint32_t per = (n + kScanT - 1) / kScanT;
+    const uint32_t r0 = min(threadIdx.x * per, n), r1 = min(r0 + per, n);
+    uint64_t lp = 0, lt = 0;
+    for (uint32_t k = r0; k < r1; ++k) {
+        const uint32_t pc = a.ivl_pcnt[k];
+        lp += pc;
+        lt += (pc + kOrderLanes - 1) / kOrderLanes;
+    }
+    uint64_t tp, tt;
+    uint64_t rp = block_exclusive_scan<uint64_t, kScanT>(lp, scratch, &tp);
+    uint64_t rt = block_exclusive_scan<uint64_t, kScanT>(lt, scratch, &tt);
+    for (uint32_t I = threadIdx.x; I < a.n_inst; I += kScanT) {
+        a.inst_plo[I] = 0;
+        a.inst_pm[I] = 0;
     }
     __syncthreads();
-    const uint64_t i = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    if (i >= m) return;
-    const uint64_t k = key[i], t = tag[i];
-    uint32_t c = 0;
-    for (uint32_t j = 0; j < nj; ++j) {
-        const uint64_t kj = sk[j];
-        c += (kj < k || (kj == k && st[j] < t)) ? 1u : 0u;
+    for (uint32_t k = r0; k < r1; ++k) {
+        const uint32_t pc = a.ivl_pcnt[k];
+        const uint32_t I = a.ivl_inst[k];
+        a.ivl_poff[k] = (uint32_t)rp;
+        a.ivl_tile0[k] = (uint32_t)rt;
+        if (k == 0 || a.ivl_inst[k - 1] != I) a.inst_plo[I] = (uint32_t)rp;
+        if (k + 1 == n || a.ivl_inst[k + 1] != I) a.inst_pm[I] = (uint32_t)(rp + pc);   // end, for now
+        rp += pc;
+        rt += (pc + kOrderLanes - 1) / kOrderLanes;
     }
-    if (c) atomicAdd(&pos[i], c);
-}
-
-__device__ __forceinline__ uint32_t segment_of(const uint64_t* seg_off, uint32_t p, uint64_t g);
-
-__global__ void probe_permute_kernel(RoundArgs a, uint64_t m, const uint64_t* order) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t src, dst;
-        if (order) { src = order[i]; dst = i; }      // order[i] = emitted index of sorted i
-        else { src = i; dst = a.pr_pos[i]; }          // pr_pos[i] = sorted index of emitted i
-        const uint64_t g = a.pr_tag[src];
-        a.ps_key[dst] = a.pr_key[src];
-        a.ps_tag[dst] = g;
-        a.ps_ivl[dst] = a.pr_ivl[src];
-        a.ps_seg[dst] = segment_of(a.seg_off, a.p, g);
-        a.pr_rank[dst] = 0;   // the rank reduction adds into it
-    }
-}
-
-__global__ void iota_kernel(uint64_t* v, uint64_t m) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        v[i] = i;
-}
-
-__global__ void gather_kernel(const uint64_t* __restrict__ src, const uint64_t* __restrict__ idx,
-                              uint64_t* __restrict__ dst, uint64_t m) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        dst[i] = src[idx[i]];
-}
-
-__global__ void one_segment_kernel(uint64_t* seg, uint64_t m) {
-    seg[0] = 0;
-    seg[1] = m;
-}
-
-__device__ __forceinline__ uint32_t segment_of(const uint64_t* seg_off, uint32_t p, uint64_t g) {
-    return last_le(seg_off, p + 1, g);
-}
-
-// Workgroup per sorted probe: c_s for every segment s inside the slice of the
-// probe's own interval, summed -> R(e).  One segment per thread (kThreads =
-// 1024 when p is large, so that many dependent searches are in flight per CU).
-// With a count matrix, c_s(e) is also stored at cmat[e * p + s] for locate.
-template <typename K, int kThreads>
-__global__ __launch_bounds__(kThreads) void rank_kernel(RoundArgs a, uint32_t* __restrict__ cmat) {
-    __shared__ uint64_t scratch[kThreads / kWave];
-    __shared__ uint32_t sh_t;
-    const uint64_t e = blockIdx.x;
-    const K key = (K)a.ps_key[e];
-    const uint64_t g = a.ps_tag[e];
-    const uint32_t row = a.ivl_row[a.ps_ivl[e]];
-    if (threadIdx.x == 0) sh_t = segment_of(a.seg_off, a.p, g);
     __syncthreads();
-    const uint32_t t = sh_t;
-    const bool lnone = a.lrank[row] == kNone;
-    const bool unone = a.urank[row] == kNone;
-    const K* B = (const K*)a.B;
-    uint64_t sum = 0;
-    for (uint32_t s = threadIdx.x; s < a.p; s += kThreads) {
-        const uint64_t sb = a.seg_off[s];
-        const uint64_t slen = a.seg_off[s + 1] - sb;
-        const uint64_t lo = lnone ? 0 : a.lpos[(uint64_t)row * a.p + s];
-        const uint64_t hi = unone ? slen : a.upos[(uint64_t)row * a.p + s];
-        uint64_t c;
-        if (s == t) {
-            c = g - sb;
-            if (c < lo || c >= hi) atomicOr(&a.ctr->err, kErrProbeOutside);
-        } else {
-            // equal keys of earlier segments precede the probe, of later ones follow
-            c = count_before<K>(B + sb, lo, hi, key, s < t);
+    // probe counts and count-matrix blocks of the instances
+    const uint32_t ni = a.n_inst;
+    const uint32_t pi = (ni + kScanT - 1) / kScanT;
+    const uint32_t i0 = min(threadIdx.x * pi, ni), i1 = min(i0 + pi, ni);
+    uint64_t lc = 0;
+    for (uint32_t I = i0; I < i1; ++I) {
+        const uint32_t end = a.inst_pm[I];
+        const uint32_t mI = end ? end - a.inst_plo[I] : 0u;
+        lc += (uint64_t)mI * a.inst[I].p;
+    }
+    uint64_t tc;
+    uint64_t rc = block_exclusive_scan<uint64_t, kScanT>(lc, scratch, &tc);
+    for (uint32_t I = i0; I < i1; ++I) {
+        const uint32_t end = a.inst_pm[I];
+        const uint32_t mI = end ? end - a.inst_plo[I] : 0u;
+        a.inst_pm[I] = mI;
+        a.cm_off[I] = rc;
+        rc += (uint64_t)mI * a.inst[I].p;
+    }
+    if (threadIdx.x == 0) {
+        a.ivl_poff[n] = (uint32_t)tp;
+        a.ivl_tile0[n] = (uint32_t)tt;
+        c->m_stored = tp;
+        c->tiles = (uint32_t)tt;
+        c->cm_need = tc;
+        if (tc > c->cm_max) c->cm_max = tc;
+        if (tc > a.cm_cap || tp != m) c->overflow = 1u;
+    }
+}
+
+// Thread per emitted probe: into its interval's range (any order inside).
+// Lanes of a wave with the same interval take their slots with one atomic.
+__global__ void group_kernel(RoundArgs a) {
+    if (halted(a)) return;
+    const uint64_t m = a.ctr->m_stored;
+    const uint32_t lane = lane_id();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t o0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; o0 < m; o0 += stride) {
+        const uint64_t o = o0 + lane;
+        const bool valid = o < m;
+        const uint32_t k = valid ? a.pr_ivl[o] : 0u;
+        uint32_t slot = 0;
+        const uint64_t live = __ballot(valid);
+        const uint32_t k0 = __shfl(k, __ffsll((unsigned long long)live) - 1);
+        if (__ballot(valid && k != k0) == 0) {
+            // one interval for the whole wave (round 1 has a single one): one atomic
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&a.ivl_cursor[k0], (uint32_t)__popcll(live));
+            base = __shfl(base, 0);
+            slot = base + (uint32_t)__popcll(live & lanes_below_mask());
+        } else if (valid) {
+            slot = atomicAdd(&a.ivl_cursor[k], 1u);
         }
-        sum += c;
-        if (cmat) cmat[(uint64_t)s * gridDim.x + e] = (uint32_t)c;
+        if (valid) {
+            const uint64_t gi = (uint64_t)a.ivl_poff[k] + slot;
+            a.g_key[gi] = a.pr_key[o];
+            a.g_tag[gi] = a.pr_tag[o];
+        }
     }
-    sum = block_sum<uint64_t, kThreads>(sum, scratch);
-    if (threadIdx.x == 0) a.pr_rank[e] = sum;
 }
 
-constexpr uint32_t kRankChunk = 1u << 15;                  // keys of a segment per workgroup
-constexpr uint32_t kRankFences = kRankChunk / kFenceStride;  // their fences, held in LDS
+// Workgroup per kOrderLanes probes of one interval: each probe's place among
+// the interval's probes in the order (key, tag), counted against tiles of
+// the interval staged in LDS, a quarter of every tile per wave; the probe
+// goes to that place of the sorted arrays, with its segment, and its rank
+// sum is cleared.
+__global__ __launch_bounds__(kOrderThreads) void order_kernel(RoundArgs a) {
+    constexpr uint32_t kTile = 1024;
+    constexpr uint32_t kParts = kOrderThreads / kOrderLanes;
+    __shared__ uint64_t tk[kTile];
+    __shared__ uint64_t tt[kTile];
+    __shared__ uint32_t part[kParts][kOrderLanes];
+    if (halted(a)) return;
+    const uint32_t t = blockIdx.x;
+    if (t >= a.ctr->tiles) return;
+    const uint32_t n_ivl = a.ctr->n_ivl;
+    const uint32_t k = last_le(a.ivl_tile0, n_ivl, t);
+    const uint32_t base = a.ivl_poff[k];
+    const uint32_t nk = a.ivl_poff[k + 1] - base;
+    const uint32_t lane = threadIdx.x % kOrderLanes, w = threadIdx.x / kOrderLanes;
+    const uint32_t i = (t - a.ivl_tile0[k]) * kOrderLanes + lane;
+    const bool valid = i < nk;
+    const uint64_t key = valid ? a.g_key[base + i] : 0;
+    const uint64_t tag = valid ? a.g_tag[base + i] : 0;
+    uint32_t c = 0;
+    for (uint32_t c0 = 0; c0 < nk; c0 += kTile) {
+        const uint32_t nc = min(kTile, nk - c0);
+        __syncthreads();   // the previous tile is no longer read
+        for (uint32_t x = threadIdx.x; x < nc; x += kOrderThreads) {
+            tk[x] = a.g_key[base + c0 + x];
+            tt[x] = a.g_tag[base + c0 + x];
+        }
+        __syncthreads();
+        const uint32_t q = (nc + kParts - 1) / kParts;
+        const uint32_t j0 = min(w * q, nc), j1 = min(j0 + q, nc);
+#pragma unroll 8
+        for (uint32_t j = j0; j < j1; ++j) {
+            const uint64_t kj = tk[j], tj = tt[j];
+            c += (kj < key || (kj == key && tj < tag)) ? 1u : 0u;
+        }
+    }
+    part[w][lane] = c;
+    __syncthreads();
+    if (w != 0 || !valid) return;
+    uint32_t rank = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kParts; ++q) rank += part[q][lane];
+    const uint64_t pos = base + rank;
+    const InstDesc& D = a.inst[a.ivl_inst[k]];
+    // segment of the probe: the last segment of the instance starting at or before it
+    uint32_t lo = 0, hi = D.p;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.seg_off[D.seg0 + mid] - D.pos0 <= tag) lo = mid; else hi = mid;
+    }
+    a.ps_key[pos] = key;
+    a.ps_tag[pos] = tag;
+    a.ps_ivl[pos] = k;
+    a.ps_seg[pos] = D.seg0 + lo;
+    a.pr_rank[pos] = 0;   // the rank reduction adds into it
+}
 
 // (key_e, g_e) after (kx, gx) in the order (key, tag)?
-template <typename K>
-__device__ __forceinline__ bool after(K ke, uint64_t ge, K kx, uint64_t gx) {
+__device__ __forceinline__ bool after(uint64_t ke, uint64_t ge, uint64_t kx, uint64_t gx) {
     return ke > kx || (ke == kx && ge > gx);
 }
 
-// Workgroup per (segment s, chunk c): the probes e whose count c_s(e) falls
-// in the chunk are the sorted run [e0, e1); each finds its place among the
-// chunk's fences in LDS, then inside one kFenceStride-key block of B.
-// Result: cmat[s * m + e] = c_s(e).
+// Workgroup per (segment s, chunk of kRankChunk keys): the probes of the
+// segment's instance whose count c_s(e) falls in the chunk are the sorted run
+// [e0, e1); each finds its place among the chunk's fences in LDS, then inside
+// one kFenceStride-key block of B.  c_s(e) goes to the instance's count matrix
+// (segment-major).
 template <typename K>
-__global__ __launch_bounds__(256) void rank_seg_kernel(RoundArgs a, uint64_t m,
-                                                       uint32_t chunks_per_seg, Fences fn,
-                                                       uint32_t* __restrict__ cmat) {
+__global__ __launch_bounds__(256) void rank_kernel(RoundArgs a) {
     __shared__ uint64_t F[kRankFences];
-    __shared__ uint64_t sh_e[2];
+    __shared__ uint32_t sh_e[2];
     __shared__ uint32_t sh_cnt[2];
-    const uint32_t s = blockIdx.x / chunks_per_seg;
-    const uint32_t c = blockIdx.x % chunks_per_seg;
+    const uint32_t c = blockIdx.x;
+    if (c >= a.n_chunks || halted(a)) return;
+    const uint32_t s = a.chunk_seg[c];
+    const uint32_t I = a.seg_inst[s];
+    const uint32_t m = a.inst_pm[I];
+    if (m == 0) return;
+    const uint32_t plo = a.inst_plo[I];
+    const InstDesc& D = a.inst[I];
+    const uint32_t s_local = s - D.seg0;
     const uint64_t sb = a.seg_off[s];
     const uint64_t ns = a.seg_off[s + 1] - sb;
-    const uint32_t nchunks = ns == 0 ? 1u : (uint32_t)((ns + kRankChunk - 1) / kRankChunk);
-    if (c >= nchunks) return;
-    const bool last = c + 1 == nchunks;
-    const uint64_t lo_pos = (uint64_t)c * kRankChunk;
-    const uint64_t chunk_end = min(lo_pos + kRankChunk, ns);   // last element + 1 in the chunk
+    const uint64_t g_sb = sb - D.pos0;   // tag of the segment's first key
+    const uint64_t lo_pos = a.chunk_lo[c];
+    const uint64_t chunk_end = min(lo_pos + kRankChunk, ns);
+    const bool last = chunk_end == ns;
     const K* B = (const K*)a.B + sb;
+    const uint64_t* pk = a.ps_key + plo;
+    const uint64_t* pt = a.ps_tag + plo;
     // [e0, e1): the probes with c_s(e) in the chunk.  The first probe with
     // c_s(e) >= x (x >= 1) is the first probe after the element at position
     // x - 1 of the segment.  Two parallel steps: 256 evenly spaced probes
@@ -448,52 +576,49 @@ __global__ __launch_bounds__(256) void rank_seg_kernel(RoundArgs a, uint64_t m,
     if (threadIdx.x < 2) sh_e[threadIdx.x] = (threadIdx.x == 0 && !need0) ? 0 : m;
     if (threadIdx.x == 0) sh_cnt[0] = sh_cnt[1] = 0;
     __syncthreads();
-    const uint64_t step = (m + 255) / 256;
-    K bx[2];
-    uint64_t bg[2];
-    bx[0] = need0 ? B[lo_pos - 1] : (K)0;
-    bg[0] = sb + lo_pos - 1;
-    bx[1] = need1 ? B[chunk_end - 1] : (K)0;
-    bg[1] = sb + chunk_end - 1;
+    const uint32_t step = (m + 255) / 256;
+    uint64_t bx[2], bg[2];
+    bx[0] = need0 ? (uint64_t)B[lo_pos - 1] : 0;
+    bg[0] = g_sb + lo_pos - 1;
+    bx[1] = need1 ? (uint64_t)B[chunk_end - 1] : 0;
+    bg[1] = g_sb + chunk_end - 1;
     {
-        // probes j*step before or at each boundary element (j = 0..255)
         const uint64_t j = (uint64_t)threadIdx.x * step;
         if (j < m) {
-            const K kj = (K)a.ps_key[j];
-            const uint64_t gj = a.ps_tag[j];
-            if (need0 && !after<K>(kj, gj, bx[0], bg[0])) atomicAdd(&sh_cnt[0], 1u);
-            if (need1 && !after<K>(kj, gj, bx[1], bg[1])) atomicAdd(&sh_cnt[1], 1u);
+            const uint64_t kj = pk[j], gj = pt[j];
+            if (need0 && !after(kj, gj, bx[0], bg[0])) atomicAdd(&sh_cnt[0], 1u);
+            if (need1 && !after(kj, gj, bx[1], bg[1])) atomicAdd(&sh_cnt[1], 1u);
         }
     }
     __syncthreads();
     for (int q = 0; q < 2; ++q) {
         if (!(q == 0 ? need0 : need1)) continue;   // uniform
-        // c samples are not after the boundary (the predicate is monotone over
-        // the sorted probes), so the answer lies in [(c-1)*step + 1, c*step],
+        // cn samples are not after the boundary (the predicate is monotone over
+        // the sorted probes), so the answer lies in [(cn-1)*step + 1, cn*step],
         // or is m when no probe of that range is after it
-        const uint64_t c = sh_cnt[q];
-        const uint64_t lo = c == 0 ? 0 : (c - 1) * step + 1;
-        const uint64_t hi = min(c * step + 1, m);   // exclusive
-        for (uint64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-            if (after<K>((K)a.ps_key[e], a.ps_tag[e], bx[q], bg[q]) &&
-                (e == 0 || !after<K>((K)a.ps_key[e - 1], a.ps_tag[e - 1], bx[q], bg[q])))
+        const uint32_t cn = sh_cnt[q];
+        const uint32_t lo = cn == 0 ? 0 : (cn - 1) * step + 1;
+        const uint32_t hi = (uint32_t)min((uint64_t)cn * step + 1, (uint64_t)m);   // exclusive
+        for (uint32_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+            if (after(pk[e], pt[e], bx[q], bg[q]) && (e == 0 || !after(pk[e - 1], pt[e - 1], bx[q], bg[q])))
                 sh_e[q] = e;   // exactly one e qualifies
         }
     }
     __syncthreads();
-    const uint64_t e0 = sh_e[0], e1 = sh_e[1];
+    const uint32_t e0 = sh_e[0], e1 = sh_e[1];
     if (e0 >= e1) return;   // no probe counts into this chunk (uniform over the workgroup)
     const uint32_t nf = (uint32_t)((chunk_end - lo_pos + kFenceStride - 1) / kFenceStride);
-    const uint64_t* fsrc = fn.key + (uint64_t)s * fn.per_seg + lo_pos / kFenceStride;
+    const uint64_t* fsrc = a.fences.key + a.fences.base[s] + lo_pos / kFenceStride;
     for (uint32_t i = threadIdx.x; i < nf; i += blockDim.x) F[i] = fsrc[i];
     __syncthreads();
-    for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        const K key = (K)a.ps_key[e];
-        const uint64_t g = a.ps_tag[e];
-        const uint32_t t = a.ps_seg[e];
+    uint32_t* out = a.cmat + a.cm_off[I] + (uint64_t)s_local * m;
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const K key = (K)pk[e];
+        const uint64_t g = pt[e];
+        const uint32_t t = a.ps_seg[plo + e];
         uint64_t cnt;
         if (t == s) {
-            cnt = g - sb;
+            cnt = g - g_sb;
         } else {
             // equal keys of earlier segments precede the probe, of later ones follow
             const bool eqb = s < t;
@@ -511,253 +636,217 @@ __global__ __launch_bounds__(256) void rank_seg_kernel(RoundArgs a, uint64_t m,
                 cnt = count_before<K>(B, lo, hi, key, eqb);
             }
         }
-        cmat[(uint64_t)s * m + e] = (uint32_t)cnt;
+        out[e] = (uint32_t)cnt;
     }
 }
 
-constexpr uint32_t kReduceRows = 16;   // segments summed per workgroup of the reduction
-
-// The reduction of section 5.2: R(e) is the sum over segments of c_s(e), the
-// column sums of the count matrix.  Tiles of 256 probes x kReduceRows
-// segments; the partial sums are integers, so the order of the atomic
-// additions does not change R(e).
-__global__ __launch_bounds__(256) void rank_reduce_kernel(const uint32_t* __restrict__ cmat,
-                                                          uint64_t m, uint32_t p,
-                                                          uint64_t* __restrict__ pr_rank) {
+// The reduction of section 5.2: R(e) is the sum over the instance's segments
+// of c_s(e), the column sums of its count matrix.  Tiles of 256 sorted probes
+// x kReduceRows segments; the partial sums are integers, so the order of the
+// atomic additions does not change R(e).
+__global__ __launch_bounds__(256) void reduce_kernel(RoundArgs a) {
+    if (halted(a)) return;
     const uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= m) return;
+    if (e >= a.ctr->m_stored) return;
+    const uint32_t I = a.ivl_inst[a.ps_ivl[e]];
+    const uint32_t p = a.inst[I].p;
     const uint32_t s0 = blockIdx.y * kReduceRows;
+    if (s0 >= p) return;
     const uint32_t s1 = min(s0 + kReduceRows, p);
+    const uint32_t m = a.inst_pm[I];
+    const uint32_t* col = a.cmat + a.cm_off[I] + (e - a.inst_plo[I]);
     uint64_t sum = 0;
 #pragma unroll
-    for (uint32_t s = s0; s < s1; ++s) sum += cmat[(uint64_t)s * m + e];
-    atomicAdd((unsigned long long*)&pr_rank[e], (unsigned long long)sum);
+    for (uint32_t q = 0; q < kReduceRows; ++q)
+        if (s0 + q < s1) sum += col[(uint64_t)(s0 + q) * m];
+    atomicAdd((unsigned long long*)&a.pr_rank[e], (unsigned long long)sum);
 }
 
-__device__ __forceinline__ void emit_request(const RoundArgs& a, uint32_t e, uint32_t row,
-                                             uint32_t kind) {
-    const uint32_t r = atomicAdd(&a.ctr->n_req, 1u);
-    a.req_probe[r] = e;
-    a.req_row[r] = row;
-    a.req_kind[r] = kind;
-}
-
-// Thread per splitter i = 1..p-1.
-__global__ __launch_bounds__(kT) void settle_kernel(RoundArgs a, uint64_t m) {
-    const uint64_t gid = (uint64_t)blockIdx.x * kT + threadIdx.x;
-    for (uint64_t e = gid; e + 1 < m; e += (uint64_t)gridDim.x * kT)
-        if (a.pr_rank[e] >= a.pr_rank[e + 1]) atomicOr(&a.ctr->err, kErrRankOrder);
-    const uint64_t i = gid + 1;
-    if (i >= a.p || a.settled[i]) return;
-    const uint64_t target = a.ideal[i];
-    // first probe with R >= N i / p
-    uint64_t lo = 0, hi = m;
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi) >> 1;
-        if (a.pr_rank[mid] < target) lo = mid + 1; else hi = mid;
-    }
-    const bool has_above = lo < m;
-    const bool has_below = lo > 0;
-    const uint64_t r_above = has_above ? a.pr_rank[lo] : 0;
-    const uint64_t r_below = has_below ? a.pr_rank[lo - 1] : 0;
-    const uint64_t d_above = r_above - target;
-    const uint64_t d_below = target - r_below;
-    int64_t pick = -1;
-    if (has_below && d_below <= a.tol) pick = (int64_t)lo - 1;
-    if (has_above && d_above <= a.tol && (pick < 0 || d_above < d_below)) pick = (int64_t)lo;
-    if (pick >= 0) {
-        a.settled[i] = 1;
-        a.chi[i] = a.pr_rank[pick];
-        a.s_key[i] = a.ps_key[pick];
-        a.s_tag[i] = a.ps_tag[pick];
-        emit_request(a, (uint32_t)pick, (uint32_t)i, 2u);
-        return;
-    }
-    if (has_below && (a.lrank[i] == kNone || r_below > a.lrank[i])) {
-        a.lrank[i] = r_below;
-        emit_request(a, (uint32_t)(lo - 1), (uint32_t)i, 0u);
-    }
-    if (has_above && r_above < a.urank[i]) {
-        a.urank[i] = r_above;
-        emit_request(a, (uint32_t)lo, (uint32_t)i, 1u);
-    }
-}
-
-// Workgroup per request: per-segment counts of a new bound / splitter probe,
-// copied from the rank step's count matrix or found by searching each segment.
-template <typename K, int kThreads>
-__global__ __launch_bounds__(kThreads) void locate_kernel(RoundArgs a,
-                                                          const uint32_t* __restrict__ cmat,
-                                                          uint64_t m) {
-    __shared__ uint32_t sh_t;
+// Workgroup per splitter row (section 4.2.2 steps 3 and 5).  A probe whose
+// rank lies in the target range settles the splitter (closest to N i/p, the
+// lower rank on a tie); otherwise L and U move to the closest probe ranks
+// below and above N i/p.  The per-segment counts of each new bound or
+// splitter probe (its column of the count matrix) then become row i of lpos
+// (L; the probe itself is excluded in its own segment), upos (U) or prow
+// (the splitter).  The grid also checks that ranks increase along every
+// instance's sorted probes.
+template <int kThreads>
+__global__ __launch_bounds__(kThreads) void settle_kernel(RoundArgs a) {
+    __shared__ uint32_t sh_n, sh_e[2], sh_kind[2], sh_cnt, sh_first;
+    if (halted(a)) return;
+    const uint64_t m_all = a.ctr->m_stored;
+    for (uint64_t e = (uint64_t)blockIdx.x * kThreads + threadIdx.x; e + 1 < m_all;
+         e += (uint64_t)gridDim.x * kThreads)
+        if (a.ivl_inst[a.ps_ivl[e]] == a.ivl_inst[a.ps_ivl[e + 1]] && a.pr_rank[e] >= a.pr_rank[e + 1])
+            atomicOr(&a.ctr->err, kErrRankOrder);
     const uint32_t r = blockIdx.x;
-    if (r >= a.ctr->n_req) return;
-    const uint32_t e = a.req_probe[r];
-    const uint64_t row = a.req_row[r];
-    const uint32_t kind = a.req_kind[r];
-    const K key = (K)a.ps_key[e];
-    const uint64_t g = a.ps_tag[e];
-    if (threadIdx.x == 0) sh_t = segment_of(a.seg_off, a.p, g);
+    if (r >= a.n_rows || a.settled[r]) return;   // uniform over the workgroup
+    const uint32_t I = a.row_inst[r];
+    const uint32_t mI = a.inst_pm[I];
+    const uint64_t plo = a.inst_plo[I];
+    const uint64_t* R = a.pr_rank + plo;
+    const uint64_t target = a.ideal[r];
+    // first probe with R >= N i / p, in two parallel steps: kThreads evenly
+    // spaced probes bracket it, then every probe of the bracket is tested
+    if (threadIdx.x == 0) { sh_cnt = 0; sh_first = mI; }
     __syncthreads();
-    const uint32_t t = sh_t;
-    const K* B = (const K*)a.B;
-    uint32_t* dst = kind == 0 ? a.lpos : (kind == 1 ? a.upos : a.prow);
-    const uint32_t own = kind == 0 ? 1u : 0u;   // the L probe itself is excluded
-    for (uint32_t s = threadIdx.x; s < a.p; s += kThreads) {
-        uint64_t c;
-        if (cmat) {
-            c = cmat[(uint64_t)s * m + e];
+    const uint32_t step = (mI + kThreads - 1) / kThreads;
+    {
+        const uint64_t j = (uint64_t)threadIdx.x * step;
+        if (j < mI && R[j] < target) atomicAdd(&sh_cnt, 1u);
+    }
+    __syncthreads();
+    {
+        const uint32_t cn = sh_cnt;   // samples below the target
+        const uint32_t blo = cn == 0 ? 0 : (cn - 1) * step + 1;
+        const uint32_t bhi = (uint32_t)min((uint64_t)cn * step + 1, (uint64_t)mI);
+        for (uint32_t e = blo + threadIdx.x; e < bhi; e += kThreads)
+            if (R[e] >= target && (e == 0 || R[e - 1] < target)) sh_first = e;   // one e qualifies
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t n = 0;
+        if (mI == 0) {   // no probe of this instance this round
+            atomicAdd(&a.ctr->n_after, 1u);
         } else {
-            const uint64_t sb = a.seg_off[s];
-            c = s == t ? g - sb : count_before<K>(B + sb, 0, a.seg_off[s + 1] - sb, key, s < t);
+            const uint64_t tol = a.inst[I].tol;
+            const uint64_t lo = sh_first;
+            const bool has_above = lo < mI;
+            const bool has_below = lo > 0;
+            const uint64_t r_above = has_above ? R[lo] : 0;
+            const uint64_t r_below = has_below ? R[lo - 1] : 0;
+            const uint64_t d_above = r_above - target;
+            const uint64_t d_below = target - r_below;
+            int64_t pick = -1;
+            if (has_below && d_below <= tol) pick = (int64_t)lo - 1;
+            if (has_above && d_above <= tol && (pick < 0 || d_above < d_below)) pick = (int64_t)lo;
+            if (pick >= 0) {
+                const uint64_t e = plo + (uint64_t)pick;
+                a.settled[r] = 1;
+                a.chi[r] = R[pick];
+                a.s_key[r] = a.ps_key[e];
+                a.s_tag[r] = a.ps_tag[e];
+                sh_e[n] = (uint32_t)e;
+                sh_kind[n++] = 2u;
+            } else {
+                atomicAdd(&a.ctr->n_after, 1u);
+                if (has_below && (a.lrank[r] == kNone || r_below > a.lrank[r])) {
+                    a.lrank[r] = r_below;
+                    sh_e[n] = (uint32_t)(plo + lo - 1);
+                    sh_kind[n++] = 0u;
+                }
+                if (has_above && r_above < a.urank[r]) {
+                    a.urank[r] = r_above;
+                    sh_e[n] = (uint32_t)(plo + lo);
+                    sh_kind[n++] = 1u;
+                }
+            }
         }
-        dst[row * a.p + s] = (uint32_t)c + (s == t ? own : 0u);
+        sh_n = n;
+    }
+    __syncthreads();
+    const uint32_t n = sh_n;
+    if (n == 0) return;
+    const InstDesc& D = a.inst[I];
+    const uint32_t i = r - D.row0;
+    for (uint32_t q = 0; q < n; ++q) {
+        const uint32_t e = sh_e[q], kind = sh_kind[q];
+        const uint32_t* col = a.cmat + a.cm_off[I] + (e - plo);
+        const uint32_t t = a.ps_seg[e] - D.seg0;
+        uint32_t* dst = (kind == 0 ? a.lpos : (kind == 1 ? a.upos : a.prow)) + D.tab0 + (uint64_t)i * D.p;
+        const uint32_t own = kind == 0 ? 1u : 0u;
+        for (uint32_t s = threadIdx.x; s < D.p; s += kThreads)
+            dst[s] = col[(uint64_t)s * mI] + (s == t ? own : 0u);
     }
 }
 
-__global__ void finalize_kernel(RoundArgs a, uint64_t* offsets) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= a.p; i += gridDim.x * blockDim.x)
-        offsets[i] = i == 0 ? 0 : (i == a.p ? a.n : a.chi[i]);
+__global__ void finalize_kernel(RoundArgs a, uint64_t* chi_all) {
+    for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < a.n_rows; r += gridDim.x * blockDim.x) {
+        const uint32_t I = a.row_inst[r];
+        const InstDesc& D = a.inst[I];
+        const uint32_t i = r - D.row0;
+        const uint64_t v = i == 0 ? 0 : (i == D.p ? D.n : a.chi[r]);
+        chi_all[r] = v;
+        a.run[I].offsets[i] = v;
+    }
 }
 
-unsigned grid_for(uint64_t n, unsigned threads, unsigned cap = 65535u) {
+__global__ void segment_sources_kernel(RoundArgs a, const uint32_t* list, uint32_t count,
+                                       uint64_t* key_src, uint64_t* val_src, int key_bytes) {
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < count; x += gridDim.x * blockDim.x) {
+        const uint32_t s = list ? list[x] : x;
+        const uint32_t I = a.seg_inst[s];
+        const uint64_t rel = a.seg_off[s] - a.inst[I].pos0;
+        key_src[x] = (uint64_t)(uintptr_t)a.run[I].kin + rel * (uint64_t)key_bytes;
+        if (val_src) val_src[x] = a.run[I].vin ? (uint64_t)(uintptr_t)a.run[I].vin + rel * 8 : 0;
+    }
+}
+
+__global__ void set_run_kernel(InstRun r, InstRun* dst) { *dst = r; }
+
+unsigned grid_for(uint64_t n, unsigned threads, unsigned cap = 1u << 20) {
     const uint64_t g = (n + threads - 1) / threads;
     return (unsigned)(g == 0 ? 1 : (g > cap ? cap : g));
 }
 
 }  // namespace
 
-hipError_t launch_round_init(const RoundArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(round_init_kernel, dim3(grid_for(a.p + 1, kT)), dim3(kT), 0, s, a.p,
-                       a.settled, a.chi, a.lrank, a.urank, a.ctr);
-    return hipGetLastError();
-}
-
 hipError_t launch_counters_reset(RoundCounters* ctr, hipStream_t s) {
     hipLaunchKernelGGL(counters_reset_kernel, dim3(1), dim3(1), 0, s, ctr);
     return hipGetLastError();
 }
 
-hipError_t launch_intervals(const RoundArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(leaders_kernel, dim3(1), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(slices_kernel, dim3(a.p > 1 ? a.p - 1 : 1), dim3(kT), 0, s, a);
-    hipLaunchKernelGGL(ivl_scan_kernel, dim3(1), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(compact_kernel, dim3(a.p > 1 ? a.p - 1 : 1), dim3(kT), 0, s, a);
+hipError_t launch_round_init(const RoundArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(round_init_kernel, dim3(grid_for(a.n_rows, kT)), dim3(kT), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_sample(const RoundArgs& a, uint64_t seed, uint32_t round, uint32_t thresh,
-                         int take_all, hipStream_t s) {
-    if (a.key_bytes == 4)
-        hipLaunchKernelGGL(sample_kernel<uint32_t>, dim3(kSampleGrid), dim3(kT), 0, s, a, seed,
-                           round, thresh, take_all);
-    else
-        hipLaunchKernelGGL(sample_kernel<uint64_t>, dim3(kSampleGrid), dim3(kT), 0, s, a, seed,
-                           round, thresh, take_all);
-    return hipGetLastError();
-}
-
-size_t probe_sort_scratch_bytes(uint64_t m) {
-    if (m <= kCountSortMax) return 0;
-    // seg(2) + idx + idx_tmp + key_a + key_b, 8 bytes each
-    return 16 + 4 * m * 8 + 256;
-}
-
-hipError_t launch_probe_sort(const RoundArgs& a, uint64_t m, void* scratch, size_t scratch_bytes,
-                             uint32_t* counts, hipStream_t s) {
-    if (m == 0) return hipSuccess;
-    if (m <= kCountSortMax) {
-        dim3 grid((unsigned)((m + kT - 1) / kT), (unsigned)((m + kCountTile - 1) / kCountTile));
-        hipLaunchKernelGGL(probe_count_kernel, grid, dim3(kT), 0, s, a.pr_key, a.pr_tag, m,
-                           a.pr_pos);
-        hipLaunchKernelGGL(probe_permute_kernel, dim3(grid_for(m, kT)), dim3(kT), 0, s, a, m,
-                           (const uint64_t*)nullptr);
-        return hipGetLastError();
-    }
-    if (scratch_bytes < probe_sort_scratch_bytes(m)) return hipErrorInvalidValue;
-    // Two stable LSD sorts: by tag, then by key -> order (key, tag).
-    uint64_t* seg = (uint64_t*)scratch;
-    uint64_t* idx = seg + 2;
-    uint64_t* idx_tmp = idx + m;
-    uint64_t* ka = idx_tmp + m;
-    uint64_t* kb = ka + m;
-    hipLaunchKernelGGL(one_segment_kernel, dim3(1), dim3(1), 0, s, seg, m);
-    hipLaunchKernelGGL(iota_kernel, dim3(grid_for(m, kT)), dim3(kT), 0, s, ka, m);
-    SegSort ss;
-    ss.key_bytes = 8;
-    ss.seg_off = seg;
-    ss.num_segs = 1;
-    ss.max_seg_len = m;
-    ss.counts = counts;
-    // by tag: keys = tags, payload = emitted index
-    ss.keys_in = a.pr_tag;
-    ss.vals_in = ka;
-    ss.keys_out = kb;
-    ss.vals_out = idx;
-    ss.keys_tmp = a.ps_tag;          // free until the permute below
-    ss.vals_tmp = idx_tmp;
-    ss.begin_bit = 0;
-    ss.end_bit = 64;
-    hipError_t err = segmented_radix_sort(ss, s);
-    if (err != hipSuccess) return err;
-    // by key, stably: keys = key of each index in tag order
-    hipLaunchKernelGGL(gather_kernel, dim3(grid_for(m, kT)), dim3(kT), 0, s, a.pr_key, idx, ka, m);
-    ss.keys_in = ka;
-    ss.vals_in = idx;
-    ss.keys_out = kb;
-    ss.vals_out = idx_tmp;
-    ss.keys_tmp = a.ps_key;
-    ss.vals_tmp = a.ps_tag;
-    ss.end_bit = a.key_bytes * 8;
-    err = segmented_radix_sort(ss, s);
-    if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(probe_permute_kernel, dim3(grid_for(m, kT)), dim3(kT), 0, s, a, m,
-                       (const uint64_t*)idx_tmp);
-    return hipGetLastError();
-}
-
-hipError_t launch_rank(const RoundArgs& a, uint64_t m, uint32_t* cmat, const Fences& fences,
-                       uint64_t max_seg, hipStream_t s) {
-    if (m == 0) return hipSuccess;
-    if (cmat && fences.key) {
-        const uint32_t cps = max_seg == 0 ? 1u : (uint32_t)((max_seg + kRankChunk - 1) / kRankChunk);
-        const dim3 grid((unsigned)((uint64_t)a.p * cps));
-        if (a.key_bytes == 4) hipLaunchKernelGGL(rank_seg_kernel<uint32_t>, grid, dim3(256), 0, s, a, m, cps, fences, cmat);
-        else hipLaunchKernelGGL(rank_seg_kernel<uint64_t>, grid, dim3(256), 0, s, a, m, cps, fences, cmat);
-        const dim3 rgrid((unsigned)((m + 255) / 256), (a.p + kReduceRows - 1) / kReduceRows);
-        hipLaunchKernelGGL(rank_reduce_kernel, rgrid, dim3(256), 0, s, (const uint32_t*)cmat, m, a.p, a.pr_rank);
-        return hipGetLastError();
-    }
-    const dim3 grid((unsigned)m);
-    if (a.p > 256) {
-        if (a.key_bytes == 4) hipLaunchKernelGGL((rank_kernel<uint32_t, 1024>), grid, dim3(1024), 0, s, a, cmat);
-        else hipLaunchKernelGGL((rank_kernel<uint64_t, 1024>), grid, dim3(1024), 0, s, a, cmat);
+hipError_t launch_round(const RoundArgs& a, uint32_t j, hipStream_t s, Profiler* prof) {
+    (void)prof;
+    // at most one interval per splitter (rows minus the two ends of every instance)
+    const uint32_t ivl_bound = a.n_rows > 2 * a.n_inst ? a.n_rows - 2 * a.n_inst : 1u;
+    hipLaunchKernelGGL(leaders_kernel, dim3(1), dim3(kScanT), 0, s, a, j);
+    hipLaunchKernelGGL(slices_kernel, dim3(ivl_bound), dim3(kT), 0, s, a);
+    hipLaunchKernelGGL(ivl_scan_kernel, dim3(1), dim3(kScanT), 0, s, a);
+    hipLaunchKernelGGL(compact_kernel, dim3(ivl_bound), dim3(kT), 0, s, a);
+    if (a.n_inst == 1) {
+        if (a.key_bytes == 4) hipLaunchKernelGGL((sample_kernel<uint32_t, true>), dim3(kSampleGrid), dim3(kT), 0, s, a, j);
+        else hipLaunchKernelGGL((sample_kernel<uint64_t, true>), dim3(kSampleGrid), dim3(kT), 0, s, a, j);
     } else {
-        if (a.key_bytes == 4) hipLaunchKernelGGL((rank_kernel<uint32_t, 256>), grid, dim3(256), 0, s, a, cmat);
-        else hipLaunchKernelGGL((rank_kernel<uint64_t, 256>), grid, dim3(256), 0, s, a, cmat);
+        if (a.key_bytes == 4) hipLaunchKernelGGL((sample_kernel<uint32_t, false>), dim3(kSampleGrid), dim3(kT), 0, s, a, j);
+        else hipLaunchKernelGGL((sample_kernel<uint64_t, false>), dim3(kSampleGrid), dim3(kT), 0, s, a, j);
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_settle(const RoundArgs& a, uint64_t m, hipStream_t s) {
-    hipLaunchKernelGGL(settle_kernel, dim3(grid_for(a.p, kT)), dim3(kT), 0, s, a, m);
-    return hipGetLastError();
-}
-
-hipError_t launch_locate(const RoundArgs& a, const uint32_t* cmat, uint64_t m, hipStream_t s) {
-    const dim3 grid(2u * (a.p > 1 ? a.p - 1 : 1));
-    if (a.p > 256) {
-        if (a.key_bytes == 4) hipLaunchKernelGGL((locate_kernel<uint32_t, 1024>), grid, dim3(1024), 0, s, a, cmat, m);
-        else hipLaunchKernelGGL((locate_kernel<uint64_t, 1024>), grid, dim3(1024), 0, s, a, cmat, m);
-    } else {
-        if (a.key_bytes == 4) hipLaunchKernelGGL((locate_kernel<uint32_t, 256>), grid, dim3(256), 0, s, a, cmat, m);
-        else hipLaunchKernelGGL((locate_kernel<uint64_t, 256>), grid, dim3(256), 0, s, a, cmat, m);
+    hipLaunchKernelGGL(probe_scan_kernel, dim3(1), dim3(kScanT), 0, s, a, j);
+    hipLaunchKernelGGL(group_kernel, dim3(grid_for(a.cap, kT, 4096)), dim3(kT), 0, s, a);
+    const uint64_t tiles_bound = (a.cap + kOrderLanes - 1) / kOrderLanes + ivl_bound;
+    hipLaunchKernelGGL(order_kernel, dim3((unsigned)tiles_bound), dim3(kOrderThreads), 0, s, a);
+    if (a.n_chunks > 0) {
+        if (a.key_bytes == 4) hipLaunchKernelGGL(rank_kernel<uint32_t>, dim3(a.n_chunks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(rank_kernel<uint64_t>, dim3(a.n_chunks), dim3(256), 0, s, a);
     }
+    const dim3 rgrid((unsigned)((a.cap + 255) / 256), (a.p_max + kReduceRows - 1) / kReduceRows);
+    hipLaunchKernelGGL(reduce_kernel, rgrid, dim3(256), 0, s, a);
+    if (a.p_max > 256) hipLaunchKernelGGL(settle_kernel<1024>, dim3(a.n_rows), dim3(1024), 0, s, a);
+    else hipLaunchKernelGGL(settle_kernel<256>, dim3(a.n_rows), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const RoundArgs& a, uint64_t* d_offsets, hipStream_t s) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(grid_for(a.p + 1, kT)), dim3(kT), 0, s, a, d_offsets);
+hipError_t launch_finalize(const RoundArgs& a, uint64_t* chi_all, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(grid_for(a.n_rows, kT)), dim3(kT), 0, s, a, chi_all);
+    return hipGetLastError();
+}
+
+hipError_t launch_segment_sources(const RoundArgs& a, const uint32_t* list, uint32_t count,
+                                  uint64_t* key_src, uint64_t* val_src, int key_bytes,
+                                  hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(segment_sources_kernel, dim3(grid_for(count, kT)), dim3(kT), 0, s, a, list,
+                       count, key_src, val_src, key_bytes);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_run(const InstRun& r, InstRun* dst, hipStream_t s) {
+    hipLaunchKernelGGL(set_run_kernel, dim3(1), dim3(1), 0, s, r, dst);
     return hipGetLastError();
 }
 

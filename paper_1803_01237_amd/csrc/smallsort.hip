@@ -26,6 +26,7 @@ namespace {
 constexpr int kT = 256;
 constexpr int kW = kT / kWave;               // waves per workgroup
 constexpr int kCapSmall = 2048;              // largest sub-bucket sorted in LDS (local sort)
+static_assert(kDirectSegMax <= (uint32_t)kCapSmall, "direct segments fit the small sort");
 constexpr int kCapLarge = 4096;              // same for the bucket sort
 constexpr int kCap = kCapLarge;              // the LDS-LSD kernel handles any of them
 constexpr int kRows = kCap / kT;             // rows of 64 keys per wave at kCap
@@ -39,10 +40,21 @@ __device__ __forceinline__ uint32_t dig(K k, int shift) {
 
 // Records the key written at output position o of segment seg when o falls
 // on a fence position of that segment.
-__device__ __forceinline__ void put_fence(const Fences& f, const uint64_t* seg_off, uint32_t seg,
-                                          uint64_t o, uint64_t key) {
-    const uint64_t rel = o - seg_off[seg];
-    if ((rel & (kFenceStride - 1)) == 0) f.key[seg * f.per_seg + rel / kFenceStride] = key;
+// Where the fences of one segment go: fence f of the segment is the key at
+// position org + f * kFenceStride; dst is null when no fences are kept.
+struct FenceSink {
+    uint64_t* dst;
+    uint64_t org;
+};
+
+__device__ __forceinline__ FenceSink fence_sink(const Fences& f, uint32_t seg) {
+    if (!f.key) return FenceSink{nullptr, 0};
+    return FenceSink{f.key + f.base[seg], f.seg_off[seg]};
+}
+
+__device__ __forceinline__ void put_fence(const FenceSink& fs, uint64_t o, uint64_t key) {
+    const uint64_t rel = o - fs.org;
+    if ((rel & (kFenceStride - 1)) == 0) fs.dst[rel / kFenceStride] = key;
 }
 
 // Stable counting pass in LDS: the n keys of `sk` (with indices `si`, or the
@@ -119,6 +131,24 @@ __device__ void lds_pass(const K* sk, const uint16_t* si, K* dk, uint16_t* di, u
 // by (key, place in the group) for keys without payload.
 // Sub-buckets with a group larger than kGroupMax go to the LDS-LSD list,
 // larger than kCap to the oversize list.
+// Work of the small sort: entries [0, n_msd) are the sub-buckets of the MSD
+// pass (entry = 256 * pass segment + digit), entries [n_msd, n_msd +
+// n_direct) whole segments taken straight from their input.
+template <typename K>
+struct SmallJobs {
+    uint32_t n_msd = 0;
+    const uint32_t* msd_seg = nullptr;     // pass segment -> segment (nullptr: the same)
+    const uint32_t* direct_seg = nullptr;
+    const uint64_t* direct_src = nullptr;  // device addresses (nullptr: keys_in + position)
+    const uint64_t* direct_vsrc = nullptr;
+    const K* keys_in = nullptr;
+    const uint64_t* vals_in = nullptr;
+    K* stash = nullptr;                    // the MSD buffer: direct segments put on the slow list
+    uint64_t* vstash = nullptr;
+    const uint64_t* seg_off = nullptr;     // positions of every segment
+    int key_bits = 64;
+};
+
 template <typename K, bool kPayload, int kCapT, int kGB>
 __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ kin,
                                                         const uint64_t* __restrict__ vin,
@@ -130,8 +160,7 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
                                                         const uint8_t* __restrict__ seg_shift,
                                                         const uint64_t* __restrict__ seg_base,
                                                         OversizeList ov, SlowList sl,
-                                                        const uint64_t* __restrict__ seg_off,
-                                                        Fences fences) {
+                                                        SmallJobs<K> jobs, Fences fences) {
     constexpr int kRowsT = kCapT / kT;
     constexpr uint32_t kG = 1u << kGB;           // groups
     constexpr int kGR = (int)kG / kT;            // groups per thread in the scan
@@ -143,12 +172,36 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     __shared__ uint32_t scratch[kW];
     __shared__ uint32_t max_count;
 
-    const uint64_t base = sb_start[blockIdx.x];
-    const uint32_t n = sb_len[blockIdx.x];
+    uint64_t base;
+    uint32_t n, seg;
+    K kbase;
+    int bits;
+    const K* src;
+    const uint64_t* vsrc;
+    const bool direct = blockIdx.x >= jobs.n_msd;
+    if (!direct) {
+        base = sb_start[blockIdx.x];
+        n = sb_len[blockIdx.x];
+        const uint32_t li = blockIdx.x / 256;
+        seg = jobs.msd_seg ? jobs.msd_seg[li] : li;
+        kbase = seg_base ? (K)seg_base[seg] : (K)0;
+        bits = seg_shift ? (int)seg_shift[seg] : uniform_bits;
+        src = kin + base;
+        vsrc = kPayload ? vin + base : nullptr;
+    } else {
+        const uint32_t dj = blockIdx.x - jobs.n_msd;
+        seg = jobs.direct_seg[dj];
+        base = jobs.seg_off[seg];
+        n = (uint32_t)(jobs.seg_off[seg + 1] - base);
+        kbase = (K)0;
+        bits = jobs.key_bits;
+        src = jobs.direct_src ? (const K*)(uintptr_t)jobs.direct_src[dj] : jobs.keys_in + base;
+        vsrc = kPayload ? (jobs.direct_vsrc ? (const uint64_t*)(uintptr_t)jobs.direct_vsrc[dj]
+                                            : jobs.vals_in + base)
+                        : nullptr;
+    }
     if (n == 0) return;
-    const uint32_t seg = blockIdx.x / 256;
-    const K kbase = seg_base ? (K)seg_base[seg] : (K)0;
-    if (n > (uint32_t)kCapT) {
+    if (n > (uint32_t)kCapT) {   // sub-buckets of the MSD pass only
         if (threadIdx.x == 0) {
             const uint32_t e = atomicAdd(ov.count, 1u);
             ov.beg[e] = base;
@@ -160,16 +213,16 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     }
     if (n == 1) {
         if (threadIdx.x == 0) {
-            const K k = kin[base];
+            const K k = src[0];
             kout[base] = k;
-            if constexpr (kPayload) vout[base] = vin[base];
-            if (fences.key) put_fence(fences, seg_off, seg, base, (uint64_t)k);
+            if constexpr (kPayload) vout[base] = vsrc[0];
+            const FenceSink fs = fence_sink(fences, seg);
+            if (fs.dst) put_fence(fs, base, (uint64_t)k);
         }
         return;
     }
     // the offsets key - kbase of this sub-bucket agree on every bit at or
     // above `bits`
-    const int bits = seg_shift ? (int)seg_shift[seg] : uniform_bits;
     const int shift2 = bits >= kGB ? bits - kGB : 0;
     for (uint32_t i = threadIdx.x; i < kG; i += kT) hist[i] = 0;
     if (threadIdx.x == 0) max_count = 0;
@@ -181,7 +234,7 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
         const uint32_t i = r * kT + threadIdx.x;
         kr[r] = 0;
         dr[r] = 0;
-        if (i < n) kr[r] = kin[base + i];
+        if (i < n) kr[r] = src[i];
     }
 #pragma unroll
     for (int r = 0; r < kRowsT; ++r) {
@@ -212,6 +265,17 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     }
     __syncthreads();
     if (max_count > kGroupMax) {
+        if (direct) {
+            // the slow path reads the MSD buffer: move the segment there
+#pragma unroll
+            for (int r = 0; r < kRowsT; ++r) {
+                const uint32_t i = r * kT + threadIdx.x;
+                if (i < n) {
+                    jobs.stash[base + i] = kr[r];
+                    if constexpr (kPayload) jobs.vstash[base + i] = vsrc[i];
+                }
+            }
+        }
         if (threadIdx.x == 0) {
             const uint32_t e = atomicAdd(sl.count, 1u);
             sl.beg[e] = base;
@@ -232,6 +296,7 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
         }
     }
     __syncthreads();
+    const FenceSink fs = fence_sink(fences, seg);
     for (uint32_t e = threadIdx.x; e < n; e += kT) {
         const K k = Bk[e];
         const uint32_t d = (uint32_t)((K)(k - kbase) >> shift2) & (kG - 1);
@@ -246,8 +311,8 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
             }
             const uint64_t o = base + g0 + rk;
             kout[o] = k;
-            vout[o] = vin[base + ie];
-            if (fences.key) put_fence(fences, seg_off, seg, o, (uint64_t)k);
+            vout[o] = vsrc[ie];
+            if (fs.dst) put_fence(fs, o, (uint64_t)k);
         } else {
             // keys only: equal keys are interchangeable, so the ones placed
             // before this one in the group go first
@@ -255,7 +320,7 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
             for (uint32_t j = e + 1; j < g1; ++j) rk += Bk[j] < k ? 1u : 0u;
             const uint64_t o = base + g0 + rk;
             kout[o] = k;
-            if (fences.key) put_fence(fences, seg_off, seg, o, (uint64_t)k);
+            if (fs.dst) put_fence(fs, o, (uint64_t)k);
         }
     }
 }
@@ -268,7 +333,6 @@ __global__ __launch_bounds__(kT) void lds_lsd_kernel(const K* __restrict__ kin,
                                                      const uint64_t* __restrict__ vin,
                                                      K* __restrict__ kout,
                                                      uint64_t* __restrict__ vout, SlowList sl,
-                                                     const uint64_t* __restrict__ seg_off,
                                                      Fences fences) {
     __shared__ K A[kCap];
     __shared__ K Bk[kCap];
@@ -314,26 +378,37 @@ __global__ __launch_bounds__(kT) void lds_lsd_kernel(const K* __restrict__ kin,
         di = old == A ? Ai : Bi;
     }
     const uint32_t seg = sl.seg[blockIdx.x];
+    const FenceSink fs = fence_sink(fences, seg);
     for (uint32_t i = threadIdx.x; i < n; i += kT) {
         kout[base + i] = sk[i];
         if constexpr (kPayload) vout[base + i] = vin[base + (si ? si[i] : i)];
-        if (fences.key) put_fence(fences, seg_off, seg, base + i, (uint64_t)sk[i]);
+        if (fs.dst) put_fence(fs, base + i, (uint64_t)sk[i]);
     }
 }
 
 // Fences of the oversize sub-buckets, read back from the sorted output.
 template <typename K>
-__global__ void ov_fence_kernel(const K* __restrict__ kout, OversizeList ov,
-                                const uint64_t* __restrict__ seg_off, Fences fences) {
+__global__ void ov_fence_kernel(const K* __restrict__ kout, OversizeList ov, Fences fences) {
     const uint32_t E = *ov.count;
     for (uint32_t e = blockIdx.x; e < E; e += gridDim.x) {
         const uint32_t seg = ov.seg[e];
-        const uint64_t sb = seg_off[seg];
+        const uint64_t sb = fences.seg_off[seg];
         const uint64_t first = sb + ((ov.beg[e] - sb + kFenceStride - 1) / kFenceStride) * kFenceStride;
         for (uint64_t o = first + (uint64_t)threadIdx.x * kFenceStride; o < ov.end[e];
              o += (uint64_t)blockDim.x * kFenceStride)
-            fences.key[seg * fences.per_seg + (o - sb) / kFenceStride] = (uint64_t)kout[o];
+            fences.key[fences.base[seg] + (o - sb) / kFenceStride] = (uint64_t)kout[o];
     }
+}
+
+// Workgroup per segment: every kFenceStride-th key of the sorted segment.
+template <typename K>
+__global__ void fence_fill_kernel(const K* __restrict__ keys, Fences fences) {
+    const uint32_t seg = blockIdx.x;
+    const uint64_t sb = fences.seg_off[seg];
+    const uint64_t len = fences.seg_off[seg + 1] - sb;
+    const uint64_t nf = (len + kFenceStride - 1) / kFenceStride;
+    for (uint64_t f = threadIdx.x; f < nf; f += blockDim.x)
+        fences.key[fences.base[seg] + f] = (uint64_t)keys[sb + f * kFenceStride];
 }
 
 // One workgroup: tile offsets of the oversize list, and the list sizes the
@@ -377,51 +452,77 @@ __global__ void ov_reset_kernel(OversizeList ov, SlowList sl) {
 }  // namespace
 
 hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
-    const uint32_t tps = (uint32_t)((a.max_seg_len + kSortTile - 1) / kSortTile);
-    if (a.num_segs == 0 || tps == 0) return hipSuccess;
+    const bool listed = a.msd_seg != nullptr;
+    const uint32_t tps = listed ? 0u : (uint32_t)((a.max_seg_len + kSortTile - 1) / kSortTile);
+    const uint32_t msd_segs = (listed || tps > 0) ? a.num_segs : 0u;
+    const uint32_t msd_tiles = listed ? a.msd_tiles : msd_segs * tps;
+    if (msd_segs == 0 && a.n_direct == 0) return hipSuccess;
+    if (listed && (a.seg_shift || a.seg_base)) return hipErrorInvalidValue;
     const int kb = a.key_bytes * 8;
     const int bits = kb - 8;             // bits below the top digit
     Profiler dummy;
     Profiler& prof = a.prof ? *a.prof : dummy;
-    const bool pay = a.vals_in != nullptr;
+    const bool pay = a.vals_in != nullptr || a.has_payload;
+    hipError_t e = hipSuccess;
 
     hipLaunchKernelGGL(ov_reset_kernel, dim3(1), dim3(1), 0, s, a.ov, a.sl);
-    // 1. MSD pass into the temporary buffer
-    RadixPass ps;
-    ps.key_bytes = a.key_bytes;
-    ps.keys_in = a.keys_in;
-    ps.vals_in = a.vals_in;
-    ps.keys_out = a.keys_tmp;
-    ps.vals_out = a.vals_tmp;
-    ps.map.beg = a.seg_off;
-    ps.map.end = a.seg_off + 1;
-    ps.map.base = a.seg_base;
-    ps.map.tps = tps;
-    ps.num_segs = a.num_segs;
-    ps.num_tiles = a.num_segs * tps;
-    ps.shift = bits;
-    ps.seg_shift = a.seg_shift;
-    ps.counts = a.counts;
-    ps.sb_start = a.sb_start;
-    ps.sb_len = a.sb_len;
-    ps.total_len = a.total_len;
-    ps.prof = a.prof;
-    // every sub-bucket is sorted completely afterwards; with keys only, equal
-    // keys are interchangeable, so the order inside a run does not matter
-    ps.any_order = !pay;
-    hipError_t e = radix_pass(ps, s);
-    if (e != hipSuccess) return e;
-    // 2. sub-buckets in LDS
-    const dim3 grid(a.num_segs * 256u);
+    // 1. MSD pass of the large segments into the temporary buffer
+    if (msd_segs > 0 && msd_tiles > 0) {
+        RadixPass ps;
+        ps.key_bytes = a.key_bytes;
+        ps.keys_in = a.keys_in;
+        ps.vals_in = a.vals_in;
+        ps.keys_out = a.keys_tmp;
+        ps.vals_out = a.vals_tmp;
+        ps.map.beg = listed ? a.msd_beg : a.seg_off;
+        ps.map.end = listed ? a.msd_end : a.seg_off + 1;
+        ps.map.base = a.seg_base;
+        ps.map.tile_seg = listed ? a.msd_tile_seg : nullptr;
+        ps.map.tile0 = listed ? a.msd_tile0 : nullptr;
+        ps.map.tps = tps;
+        ps.map.src = a.msd_src;
+        ps.map.vsrc = a.msd_vsrc;
+        ps.num_segs = msd_segs;
+        ps.num_tiles = msd_tiles;
+        ps.shift = bits;
+        ps.seg_shift = a.seg_shift;
+        ps.counts = a.counts;
+        ps.sb_start = a.sb_start;
+        ps.sb_len = a.sb_len;
+        ps.total_len = a.total_len;
+        ps.prof = a.prof;
+        // every sub-bucket is sorted completely afterwards; with keys only, equal
+        // keys are interchangeable, so the order inside a run does not matter
+        ps.any_order = !pay;
+        ps.has_payload = pay;
+        e = radix_pass(ps, s);
+        if (e != hipSuccess) return e;
+    }
+    // 2. sub-buckets, and the segments small enough to take whole, in LDS
+    const dim3 grid(msd_segs * 256u + a.n_direct);
     prof.begin(s);
     // sub-buckets of the p input segments split by their top byte average
     // N/(256 p) keys; bucket key ranges may use only half of the digit values
     const bool large = a.seg_base != nullptr;
 #define HSS_SMALL(KT, PAY, CAP)                                                                  \
-    hipLaunchKernelGGL((small_sort_kernel<KT, PAY, CAP, kGroupBits>), grid, dim3(kT), 0, s,      \
-                       (const KT*)a.keys_tmp, PAY ? a.vals_tmp : nullptr, (KT*)a.keys_out,         \
-                       PAY ? a.vals_out : nullptr, a.sb_start, a.sb_len, bits, a.seg_shift,        \
-                       a.seg_base, a.ov, a.sl, a.seg_off, a.fences)
+    do {                                                                                         \
+        SmallJobs<KT> jobs;                                                                      \
+        jobs.n_msd = msd_segs * 256u;                                                            \
+        jobs.msd_seg = a.msd_seg;                                                                \
+        jobs.direct_seg = a.direct_seg;                                                          \
+        jobs.direct_src = a.direct_src;                                                          \
+        jobs.direct_vsrc = a.direct_vsrc;                                                        \
+        jobs.keys_in = (const KT*)a.keys_in;                                                     \
+        jobs.vals_in = a.vals_in;                                                                \
+        jobs.stash = (KT*)a.keys_tmp;                                                            \
+        jobs.vstash = a.vals_tmp;                                                                \
+        jobs.seg_off = a.seg_off;                                                                \
+        jobs.key_bits = kb;                                                                      \
+        hipLaunchKernelGGL((small_sort_kernel<KT, PAY, CAP, kGroupBits>), grid, dim3(kT), 0, s,  \
+                           (const KT*)a.keys_tmp, PAY ? a.vals_tmp : nullptr, (KT*)a.keys_out,     \
+                           PAY ? a.vals_out : nullptr, a.sb_start, a.sb_len, bits, a.seg_shift,    \
+                           a.seg_base, a.ov, a.sl, jobs, a.fences);                                \
+    } while (0)
     if (a.key_bytes == 4) {
         if (pay) { if (large) HSS_SMALL(uint32_t, true, kCapLarge); else HSS_SMALL(uint32_t, true, kCapSmall); }
         else { if (large) HSS_SMALL(uint32_t, false, kCapLarge); else HSS_SMALL(uint32_t, false, kCapSmall); }
@@ -445,11 +546,11 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     if (SL > 0) {
         const dim3 g(SL);
         if (a.key_bytes == 4) {
-            if (pay) hipLaunchKernelGGL((lds_lsd_kernel<uint32_t, true>), g, dim3(kT), 0, s, (const uint32_t*)a.keys_tmp, a.vals_tmp, (uint32_t*)a.keys_out, a.vals_out, a.sl, a.seg_off, a.fences);
-            else hipLaunchKernelGGL((lds_lsd_kernel<uint32_t, false>), g, dim3(kT), 0, s, (const uint32_t*)a.keys_tmp, nullptr, (uint32_t*)a.keys_out, nullptr, a.sl, a.seg_off, a.fences);
+            if (pay) hipLaunchKernelGGL((lds_lsd_kernel<uint32_t, true>), g, dim3(kT), 0, s, (const uint32_t*)a.keys_tmp, a.vals_tmp, (uint32_t*)a.keys_out, a.vals_out, a.sl, a.fences);
+            else hipLaunchKernelGGL((lds_lsd_kernel<uint32_t, false>), g, dim3(kT), 0, s, (const uint32_t*)a.keys_tmp, nullptr, (uint32_t*)a.keys_out, nullptr, a.sl, a.fences);
         } else {
-            if (pay) hipLaunchKernelGGL((lds_lsd_kernel<uint64_t, true>), g, dim3(kT), 0, s, (const uint64_t*)a.keys_tmp, a.vals_tmp, (uint64_t*)a.keys_out, a.vals_out, a.sl, a.seg_off, a.fences);
-            else hipLaunchKernelGGL((lds_lsd_kernel<uint64_t, false>), g, dim3(kT), 0, s, (const uint64_t*)a.keys_tmp, nullptr, (uint64_t*)a.keys_out, nullptr, a.sl, a.seg_off, a.fences);
+            if (pay) hipLaunchKernelGGL((lds_lsd_kernel<uint64_t, true>), g, dim3(kT), 0, s, (const uint64_t*)a.keys_tmp, a.vals_tmp, (uint64_t*)a.keys_out, a.vals_out, a.sl, a.fences);
+            else hipLaunchKernelGGL((lds_lsd_kernel<uint64_t, false>), g, dim3(kT), 0, s, (const uint64_t*)a.keys_tmp, nullptr, (uint64_t*)a.keys_out, nullptr, a.sl, a.fences);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -490,12 +591,22 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     }
     if (a.fences.key) {
         if (a.key_bytes == 4)
-            hipLaunchKernelGGL(ov_fence_kernel<uint32_t>, dim3(1024), dim3(256), 0, s, (const uint32_t*)a.keys_out, a.ov, a.seg_off, a.fences);
+            hipLaunchKernelGGL(ov_fence_kernel<uint32_t>, dim3(1024), dim3(256), 0, s, (const uint32_t*)a.keys_out, a.ov, a.fences);
         else
-            hipLaunchKernelGGL(ov_fence_kernel<uint64_t>, dim3(1024), dim3(256), 0, s, (const uint64_t*)a.keys_out, a.ov, a.seg_off, a.fences);
+            hipLaunchKernelGGL(ov_fence_kernel<uint64_t>, dim3(1024), dim3(256), 0, s, (const uint64_t*)a.keys_out, a.ov, a.fences);
         e = hipGetLastError();
     }
     return e;
+}
+
+hipError_t write_fences(const void* keys, int key_bytes, uint32_t num_segs, const Fences& f,
+                        hipStream_t s) {
+    if (num_segs == 0 || !f.key) return hipSuccess;
+    if (key_bytes == 4)
+        hipLaunchKernelGGL(fence_fill_kernel<uint32_t>, dim3(num_segs), dim3(256), 0, s, (const uint32_t*)keys, f);
+    else
+        hipLaunchKernelGGL(fence_fill_kernel<uint64_t>, dim3(num_segs), dim3(256), 0, s, (const uint64_t*)keys, f);
+    return hipGetLastError();
 }
 
 uint64_t oversize_capacity(uint32_t num_segs, uint64_t total_len) {

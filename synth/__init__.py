@@ -122,3 +122,26 @@ def config(name: str, n_override: int | None = None):
     keys = make(kind, n, dseed)
     vals = np.arange(n, dtype=np.uint64) if payload else None
     return keys, vals, p, eps, hseed
+
+
+def batched_shapes(count: int = 512, seed: int = 4, lo_bits: float = 12.0, hi_bits: float = 22.0):
+    """Instance shapes of the batched workload: N log-uniform on
+    [2^lo_bits, 2^hi_bits], p = clamp(floor(e^U(ln 8, ln 257)), 8, 256),
+    eps = 0.05; the first half of the instances has 32-bit keys, the rest
+    64-bit.  Returns [(n, p, eps, key_bytes, data_seed, hss_seed)]."""
+    rng = _rng(seed)
+    out = []
+    for i in range(count):
+        n = int(np.floor(2.0 ** rng.uniform(lo_bits, hi_bits)))
+        p = int(np.clip(np.floor(np.exp(rng.uniform(np.log(8.0), np.log(257.0)))), 8, 256))
+        p = min(p, n)
+        kb = 4 if i < count // 2 else 8
+        out.append((n, p, 0.05, kb, seed * 100_000 + i, 1000 + i))
+    return out
+
+
+def batched_keys(shape) -> np.ndarray:
+    """Uniform keys of one batched instance (32-bit: the top half of a 64-bit draw)."""
+    n, _p, _eps, kb, dseed, _hseed = shape
+    k = uniform64(n, dseed)
+    return (k >> np.uint64(32)).astype(np.uint32) if kb == 4 else k
