@@ -443,7 +443,8 @@ __global__ __launch_bounds__(kScanT) void probe_scan_kernel(RoundArgs a, uint32_
 }
 
 // Thread per emitted probe: into its interval's range (any order inside).
-// Lanes of a wave with the same interval take their slots with one atomic.
+// A wave whose probes all belong to one interval takes its slots with one
+// atomic; otherwise every probe takes its own.
 __global__ void group_kernel(RoundArgs a) {
     if (halted(a)) return;
     const uint64_t m = a.ctr->m_stored;
@@ -475,7 +476,7 @@ __global__ void group_kernel(RoundArgs a) {
 
 // Workgroup per kOrderLanes probes of one interval: each probe's place among
 // the interval's probes in the order (key, tag), counted against tiles of
-// the interval staged in LDS, a quarter of every tile per wave; the probe
+// the interval staged in LDS, an eighth of every tile per wave; the probe
 // goes to that place of the sorted arrays, with its segment, and its rank
 // sum is cleared.
 __global__ __launch_bounds__(kOrderThreads) void order_kernel(RoundArgs a) {
