@@ -142,6 +142,76 @@ def batched_bench(steps, count):
                      "first half u32 keys, second half u64"}
 
 
+SWEEP = ["UNIF", "SKEW1", "SKEW2", "SKEW3", "GAUSS", "ALLZEROS"]
+
+
+def _timed(fn, steps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def options_bench(keys, n, p, eps, hseed, steps):
+    """The plan options of the same kernels at the headline size: HSS with one
+    round (k = 1, section 4.1) and exact splitting (eps = p / N, tol = 0)."""
+    import torch
+    import paper_1803_01237_amd as hss
+    out = {}
+    kout = torch.empty_like(keys)
+    off = torch.empty(p + 1, dtype=torch.int64, device=keys.device)
+    ideal = (np.arange(p + 1, dtype=object) * n) // p
+    for name, e, k in [("one_round", eps, 1), ("exact", p / n, 0)]:
+        log(f"[bench] option {name}: eps={e} k_override={k}")
+        with hss.Plan(n, p, e, k_override=k) as plan:
+            ms = _timed(lambda: plan.partition(keys, hseed, keys_out=kout, offsets=off), steps)
+            tr = plan.trace()
+            tol, kk = plan.constants(1)[:2]
+            o = off.cpu().numpy()
+            dev = max(abs(int(o[i]) - int(ideal[i])) for i in range(p + 1))
+            if dev > tol:
+                raise RuntimeError(f"option {name}: splitter {dev} from its ideal rank, tol {tol}")
+            out[name] = {"eps": e, "k": int(kk), "tol": int(tol), "ms_per_step": round(ms, 4),
+                         "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3), "rounds": len(tr),
+                         "probes_per_round": [r.m for r in tr], "max_splitter_deviation": dev}
+    return out
+
+
+def sweep_bench(plan, keys, n, p, eps, hseed, steps):
+    """The distributions of section 7.5 through the headline plan: one input
+    buffer refilled per distribution, per-stage times from the HIP events."""
+    import torch
+    import synth
+    kout = torch.empty_like(keys)
+    off = torch.empty(p + 1, dtype=torch.int64, device=keys.device)
+    tol = plan.constants(1)[0]
+    ideal = (np.arange(p + 1, dtype=object) * n) // p
+    out = {}
+    for kind in SWEEP:
+        log(f"[bench] sweep {kind}")
+        keys.copy_(torch.from_numpy(synth.make(kind, n, 70).view(np.int64)))
+        plan.partition(keys, hseed, keys_out=kout, offsets=off)
+        torch.cuda.synchronize()
+        plan.profile(True)
+        plan.profile_reset()
+        ms = _timed(lambda: plan.partition(keys, hseed, keys_out=kout, offsets=off), steps)
+        prof = plan.profile_read()
+        plan.profile(False)
+        o = off.cpu().numpy()
+        dev = max(abs(int(o[i]) - int(ideal[i])) for i in range(p + 1))
+        if dev > tol:
+            raise RuntimeError(f"sweep {kind}: splitter {dev} from its ideal rank, tol {tol}")
+        st = {f: round(prof[f][0] / (steps + 1), 4) for f in prof if prof[f][1] > 0}
+        tr = plan.trace()
+        out[kind] = {"ms_per_step": round(ms, 4), "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3),
+                     "rounds": len(tr), "probes": sum(r.m for r in tr), "stage_ms": st}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +226,10 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512,
                     help="instances of the batched comparison (0 to skip)")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--option-steps", type=int, default=3,
+                    help="steps per plan option (one round, exact splitting); 0 to skip")
+    ap.add_argument("--sweep-steps", type=int, default=3,
+                    help="steps per distribution of the sweep; 0 to skip")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 2 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -261,7 +335,16 @@ def main():
                                if prof[f][0] > 0 and prof[f][2] else None)}
               for f in prof}
 
+    # both extra legs only at the headline workload; the options first, while
+    # the input buffer still holds the headline keys
+    headline = args.workload == "uniform_u64_2^28_p1024" and args.op == "partition"
+    options = (options_bench(keys, n, p, eps, hseed, args.option_steps)
+               if args.option_steps > 0 and headline else None)
+    sweep = (sweep_bench(plan, keys, n, p, eps, hseed, args.sweep_steps)
+             if args.sweep_steps > 0 and headline else None)
     plan.close()
+    del keys, kout, vout, vals
+    torch.cuda.empty_cache()
     batched = batched_bench(args.batch_steps, args.batch_count) if args.batch_count > 0 else None
 
     cpu = None
@@ -283,6 +366,8 @@ def main():
         "hss_sort_ms": None if sort_ms is None else round(sort_ms, 4),
         "hss_sort_gkeys_s": None if sort_ms is None else round(n / (sort_ms * 1e-3) / 1e9, 3),
         "batched": batched,
+        "plan_options": options,
+        "distributions": sweep,
     }
     print(json.dumps(line), flush=True)
 

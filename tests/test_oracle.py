@@ -364,3 +364,48 @@ def test_round_cap_reports_not_converged():
     keys = synth.make("uniform64", 1 << 16, 3)
     r = oracle.hss(keys, 64, 0.01, 3, max_rounds=1)
     assert r.status == -5
+
+
+def test_one_round_lemma():
+    """k = 1 is HSS with one round (section 4.1): at the rate 2 p ln p / (eps N)
+    each target range of N eps / p keys misses every probe with probability at
+    most 1/p^2, so all p - 1 splitters settle in the first round except with
+    probability below 1/p.  Over 60 seeds at p = 16 that bound allows about
+    3.5 runs with a second round; far more would mean a wrong rate, range or
+    settle rule."""
+    n, p, eps = 1 << 15, 16, 0.05
+    c = oracle.constants(n, p, eps, k_override=1)
+    assert c.k == 1
+    extra = 0
+    for seed in range(60):
+        keys = synth.make("uniform64", n, 500 + seed)
+        r = oracle.hss(keys, p, eps, seed, k_override=1, trace_level=0)
+        assert r.status == 0
+        off = r.offsets.astype(np.int64)
+        assert np.all(np.abs(off - np.array(R.ideal(n, p), dtype=np.int64)) <= r.tol)
+        extra += len(r.rounds) > 1
+    assert extra <= 12, extra
+
+
+@pytest.mark.parametrize("n,p,kind", [(20_000, 10, "uniform64"), (30_011, 7, "SKEW2"),
+                                      (8192, 64, "GAUSS")])
+def test_exact_splitting(n, p, kind):
+    """eps = p / N gives tol = 0 (section 4.2, exact splitting): every splitter
+    lands on rank floor(N i / p) and every bucket holds floor((i+1)N/p) -
+    floor(iN/p) keys.  The schedule reaches rate 1 after finitely many rounds,
+    which bounds the round count."""
+    eps = p / n
+    keys = synth.make(kind, n, 40 + p)
+    c = oracle.constants(n, p, eps, max_j=64)
+    assert c.tol == 0
+    j_full = 1 + int(np.argmax(c.all))
+    assert c.all[j_full - 1] and not any(c.all[:j_full - 1])
+    r = oracle.hss(keys, p, eps, 9, trace_level=0)
+    assert r.status == 0
+    assert [int(x) for x in r.offsets] == list(R.ideal(n, p))
+    assert 1 <= len(r.rounds) <= j_full
+    # every bucket holds exactly its slice of the sorted input
+    srt = np.sort(keys, kind="stable")
+    for b in range(p):
+        lo, hi = int(r.offsets[b]), int(r.offsets[b + 1])
+        assert np.array_equal(np.sort(r.keys[lo:hi]), srt[lo:hi]), b

@@ -132,6 +132,46 @@ def test_partition_and_sort_match_oracle(hss, case):
         assert np.array_equal(_host(off2, np.uint64), ref.offsets)
 
 
+OPTION_CASES = [
+    # kind, n, p, eps, seed, bits, payload, k_override
+    ("uniform64", 1 << 18, 64, 0.05, 21, 64, False, 1),   # one round (section 4.1)
+    ("SKEW2", 100_000, 16, 0.05, 22, 64, True, 1),        # one round, duplicates
+    ("uniform32", 50_000, 10, 10 / 50_000, 23, 32, False, 0),   # eps = p/N: exact
+    ("GAUSS", 8192, 64, 64 / 8192, 24, 64, True, 0),      # exact, 5 rounds
+    ("uniform64", 20_000, 10, 10 / 20_000, 25, 64, False, 1),   # exact with k = 1
+]
+
+
+@pytest.mark.parametrize("case", OPTION_CASES,
+                         ids=[f"{c[0]}-{c[1]}-p{c[2]}-k{c[7]}" for c in OPTION_CASES])
+def test_plan_options_match_oracle(hss, case):
+    """One-round HSS (k = 1) and exact splitting (eps = p / N, tol = 0) are plan
+    options on the same kernels; trace and outputs equal the oracle's."""
+    kind, n, p, eps, seed, bits, payload, k = case
+    _say(f"[parity] options {kind} n={n} p={p} eps={eps} k={k} payload={payload}")
+    keys = _keys(kind, n, seed, bits)
+    vals = (np.arange(n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)) if payload else None
+    kd = _dev(keys)
+    vd = None if vals is None else _dev(vals)
+    with hss.Plan(n, p, eps, key_bytes=keys.itemsize, payload=payload, trace_level=1,
+                  k_override=k) as plan:
+        tol, kk, a, th, al = plan.constants(40)
+        oc = oracle.constants(n, p, eps, k_override=k, max_j=40)
+        assert (tol, kk, a) == (oc.tol, oc.k, oc.a)
+        assert np.array_equal(th, oc.thresh) and np.array_equal(al, oc.all)
+        ko, vo, off = plan.partition(kd, seed, vd)
+        ref = oracle.hss(keys, p, eps, seed, vals=vals, mode="partition", k_override=k)
+        assert ref.status == 0
+        assert np.array_equal(_host(off, np.uint64), ref.offsets)
+        assert np.array_equal(_host(ko, keys.dtype), ref.keys)
+        if payload:
+            assert np.array_equal(_host(vo, np.uint64), ref.vals)
+        _compare_trace(plan, ref, p)
+        if tol == 0:
+            ideal = (np.arange(p + 1, dtype=np.uint64) * np.uint64(n)) // np.uint64(p)
+            assert np.array_equal(_host(off, np.uint64), ideal)
+
+
 def test_force_full_sample_exact_splitters(hss):
     n, p = 50_000, 13
     _say(f"[parity] force_full_sample n={n} p={p}")
