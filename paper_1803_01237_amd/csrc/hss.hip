@@ -159,7 +159,10 @@ struct Engine {
     uint64_t* bucket_base = nullptr;
     uint64_t* sb_start = nullptr;
     uint32_t* sb_len = nullptr;
-    OversizeList ov;
+    OversizeList ov, ov2;
+    EqualList eq;
+    LevelWork lw;
+    PackedJobs pj;
     SlowList sl;
     HybridHost hh;
     uint32_t* msd_seg = nullptr;
@@ -180,7 +183,7 @@ struct Engine {
     uint32_t* cmat = nullptr;
     uint64_t cm_cap = 0;
 
-    RoundCounters* h_ctr = nullptr;   // pinned; 16 more bytes for the sort's read-back
+    RoundCounters* h_ctr = nullptr;   // pinned; 32 more bytes for the sort's read-back
     InstRun* h_run = nullptr;         // pinned
     RoundHist* h_hist = nullptr;      // pinned, J entries
     std::vector<RoundRecord> trace;
@@ -192,6 +195,8 @@ struct Engine {
         if (probe_mem) (void)hipFree(probe_mem);
         if (cmat) (void)hipFree(cmat);
         if (hh.fb_counts) (void)hipFree(hh.fb_counts);
+        if (hh.fb_sb_start) (void)hipFree(hh.fb_sb_start);
+        if (hh.fb_sb_len) (void)hipFree(hh.fb_sb_len);
         if (arena) (void)hipFree(arena);
         if (h_ctr) (void)hipHostFree(h_ctr);
         if (h_run) (void)hipHostFree(h_run);
@@ -404,25 +409,59 @@ size_t layout(Engine& E, char* base) {
     const uint32_t msd_segs = E.listed ? E.n_msd : S;
     E.sb_start = ar.take<uint64_t>((size_t)msd_segs * 256 + 1);
     E.sb_len = ar.take<uint32_t>((size_t)msd_segs * 256 + 1);
-    // the lists hold sub-buckets (256 per MSD segment) and whole segments
-    const uint32_t list_segs = msd_segs + (E.n_direct + 255) / 256;
-    const uint64_t ovc = oversize_capacity(list_segs, n);
-    E.ov.count = ar.take<uint32_t>(1);
-    E.ov.tiles = ar.take<uint32_t>(1);
-    E.ov.summary = ar.take<uint32_t>(4);
-    E.ov.beg = ar.take<uint64_t>(ovc);
-    E.ov.end = ar.take<uint64_t>(ovc);
-    E.ov.base = ar.take<uint64_t>(ovc);
-    E.ov.seg = ar.take<uint32_t>(ovc);
-    E.ov.tile0 = ar.take<uint32_t>(ovc + 1);
-    E.ov.tile_seg = ar.take<uint32_t>(oversize_tile_capacity(list_segs, n));
-    const uint64_t slc = slow_capacity(list_segs, n);
+    // the lists of the hybrid sort (capacities from the key count alone)
+    const uint64_t ovc = oversize_capacity(n);
+    uint32_t* list_err = ar.take<uint32_t>(1);
+    for (OversizeList* o : {&E.ov, &E.ov2}) {
+        o->count = ar.take<uint32_t>(1);
+        o->tiles = ar.take<uint32_t>(1);
+        o->summary = ar.take<uint32_t>(8);
+        o->beg = ar.take<uint64_t>(ovc);
+        o->end = ar.take<uint64_t>(ovc);
+        o->base = ar.take<uint64_t>(ovc);
+        o->seg = ar.take<uint32_t>(ovc);
+        o->bits = ar.take<uint8_t>(ovc);
+        o->loc = ar.take<uint8_t>(ovc);
+        o->src = ar.take<uint64_t>(ovc);
+        o->vsrc = ar.take<uint64_t>(ovc);
+        o->tile0 = ar.take<uint32_t>(ovc + 1);
+        o->tile_seg = ar.take<uint32_t>(oversize_tile_capacity(n));
+        o->capacity = (uint32_t)ovc;
+        o->err = list_err;
+    }
+    E.eq.count = ar.take<uint32_t>(1);
+    E.eq.beg = ar.take<uint64_t>(ovc);
+    E.eq.end = ar.take<uint64_t>(ovc);
+    E.eq.seg = ar.take<uint32_t>(ovc);
+    E.eq.loc = ar.take<uint8_t>(ovc);
+    E.eq.src = ar.take<uint64_t>(ovc);
+    E.eq.vsrc = ar.take<uint64_t>(ovc);
+    E.eq.capacity = (uint32_t)ovc;
+    E.eq.err = list_err;
+    const uint64_t lwc = level_capacity(msd_segs, n);
+    E.lw.shift = ar.take<uint8_t>(lwc);
+    E.lw.skip = ar.take<uint8_t>(lwc);
+    E.lw.dst = ar.take<uint64_t>(lwc);
+    E.lw.vdst = ar.take<uint64_t>(lwc);
+    E.lw.and_mask = ar.take<uint64_t>(lwc);
+    E.lw.or_mask = ar.take<uint64_t>(lwc);
+    const uint64_t pjc = packed_capacity(n);
+    E.pj.count = ar.take<uint32_t>(1);
+    E.pj.start = ar.take<uint64_t>(pjc);
+    E.pj.len = ar.take<uint32_t>(pjc);
+    E.pj.entry = ar.take<uint32_t>(pjc);
+    E.pj.bits = ar.take<uint8_t>(pjc);
+    E.pj.capacity = (uint32_t)pjc;
+    E.pj.err = list_err;
+    const uint64_t slc = slow_capacity(n);
     E.sl.count = ar.take<uint32_t>(1);
     E.sl.beg = ar.take<uint64_t>(slc);
     E.sl.len = ar.take<uint32_t>(slc);
     E.sl.bits = ar.take<uint8_t>(slc);
     E.sl.base = ar.take<uint64_t>(slc);
     E.sl.seg = ar.take<uint32_t>(slc);
+    E.sl.capacity = (uint32_t)slc;
+    E.sl.err = list_err;
     if (E.listed) {
         E.msd_seg = ar.take<uint32_t>(E.n_msd + 1);
         E.msd_beg = ar.take<uint64_t>(E.n_msd + 1);
@@ -499,7 +538,7 @@ hss_status engine_init(Engine& E) {
     E.arena_bytes = layout(E, nullptr) + 256;
     HIP_TRY(hipMalloc(&E.arena, E.arena_bytes));
     layout(E, (char*)E.arena);
-    HIP_TRY(hipHostMalloc((void**)&E.h_ctr, sizeof(RoundCounters) + 16, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void**)&E.h_ctr, sizeof(RoundCounters) + 32, hipHostMallocDefault));
     E.hh.pinned = (uint32_t*)((char*)E.h_ctr + sizeof(RoundCounters));
     HIP_TRY(hipHostMalloc((void**)&E.h_run, E.ih.size() * sizeof(InstRun), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc((void**)&E.h_hist, E.J * sizeof(RoundHist), hipHostMallocDefault));
@@ -621,6 +660,10 @@ hss_status segment_sort(Engine& E, bool first, const void* kin, const uint64_t* 
     hs.seg_base = seg_base;
     if (with_fences) hs.fences = E.fences;
     hs.ov = E.ov;
+    hs.ov2 = E.ov2;
+    hs.eq = E.eq;
+    hs.lw = E.lw;
+    hs.pj = E.pj;
     hs.sl = E.sl;
     hs.prof = &E.prof;
     if (first && E.listed) {

@@ -130,6 +130,13 @@ struct TileMap {
     // key (and payload word); otherwise the pass input at position beg[s]
     const uint64_t* src = nullptr;
     const uint64_t* vsrc = nullptr;
+    // optional per-segment destination: device addresses where the
+    // segment's first key (and payload word) go; otherwise the pass output at
+    // position beg[s]
+    const uint64_t* dst = nullptr;
+    const uint64_t* vdst = nullptr;
+    // optional: segments flagged here are left alone by the scatter
+    const uint8_t* skip = nullptr;
 };
 
 // One stable counting pass on digit [shift, shift+8) of every segment.
@@ -152,11 +159,19 @@ struct RadixPass {
     // whose runs are fully sorted afterwards): rank by LDS atomics
     bool any_order = false;
     bool has_payload = false;          // payload read through map.vsrc (vals_in may be null)
+    // optional per-segment AND and OR of every key - base (the bits that
+    // vary inside the segment), accumulated by the count pass; both must be
+    // preset to all ones and zero
+    uint64_t* and_mask = nullptr;
+    uint64_t* or_mask = nullptr;
     Profiler* prof = nullptr;
 };
 
 uint64_t radix_count_words(uint32_t num_segs, uint64_t max_seg_len);
 hipError_t radix_pass(const RadixPass& a, hipStream_t stream);
+// The pass in two halves (count and scan; scatter), for work in between.
+hipError_t radix_count_scan(const RadixPass& a, hipStream_t stream);
+hipError_t radix_scatter(const RadixPass& a, hipStream_t stream);
 hipError_t segmented_radix_sort(const SegSort& a, hipStream_t stream);
 
 // --------------------------------------------------------------- fences ----
@@ -179,6 +194,14 @@ hipError_t write_fences(const void* keys, int key_bytes, uint32_t num_segs, cons
 
 // ---------------------------------------------------------- hybrid sort ----
 // Sub-buckets too large for LDS, collected on the device.
+// Where the keys of a pending range are: the MSD buffer, the output, or the
+// sort's input (a segment whose top digit held all its keys).
+enum : uint8_t { kLocTmp = 0, kLocOut = 1, kLocIn = 2 };
+
+// Key ranges still to sort after a level of MSD passes: sub-buckets above the
+// small-sort capacity, and ranges whose digit held every key (retried on the
+// highest bit that varies).  Every key k of an entry satisfies k - base <
+// 2^bits; its keys sit at src (payload vsrc) in buffer `loc`.
 struct OversizeList {
     uint32_t* count = nullptr;         // entries
     uint32_t* tiles = nullptr;         // total tiles
@@ -186,9 +209,54 @@ struct OversizeList {
     uint64_t* end = nullptr;
     uint64_t* base = nullptr;          // key offset of the entry's segment
     uint32_t* seg = nullptr;           // segment of the entry
+    uint8_t* bits = nullptr;
+    uint8_t* loc = nullptr;
+    uint64_t* src = nullptr;           // device address of the entry's first key
+    uint64_t* vsrc = nullptr;          // and payload word
     uint32_t* tile0 = nullptr;         // capacity + 1
     uint32_t* tile_seg = nullptr;      // oversize_tile_capacity()
-    uint32_t* summary = nullptr;       // 4 words for the host: entries, tiles, slow-list entries
+    uint32_t* summary = nullptr;       // 5 words for the host: entries, tiles, slow-list
+                                       // and equal-list entries, overrun flag
+    uint32_t capacity = 0;
+    uint32_t* err = nullptr;           // set when a push finds the list full
+};
+
+// Ranges whose keys are all equal: already sorted, copied to the output
+// (unless there) and given their fences at the end of the sort.
+struct EqualList {
+    uint32_t* count = nullptr;
+    uint64_t* beg = nullptr;           // capacity oversize_capacity()
+    uint64_t* end = nullptr;
+    uint32_t* seg = nullptr;
+    uint8_t* loc = nullptr;
+    uint64_t* src = nullptr;
+    uint64_t* vsrc = nullptr;
+    uint32_t capacity = 0;
+    uint32_t* err = nullptr;
+};
+
+// Small-sort jobs of a deeper level: runs of consecutive sub-buckets of one
+// entry packed up to the small-sort capacity (a sub-bucket above it is a job
+// of its own and goes on to the next level).  Capacity packed_capacity().
+struct PackedJobs {
+    uint32_t* count = nullptr;
+    uint64_t* start = nullptr;         // first position
+    uint32_t* len = nullptr;
+    uint32_t* entry = nullptr;         // entry of the level's list
+    uint8_t* bits = nullptr;           // free bits of key - base inside the job
+    uint32_t capacity = 0;
+    uint32_t* err = nullptr;
+};
+
+// Per-entry work arrays of one MSD level (level 1: the MSD segments; deeper:
+// the entries of an OversizeList), capacity level_capacity().
+struct LevelWork {
+    uint8_t* shift = nullptr;          // digit [shift, shift + 8) of key - base
+    uint8_t* skip = nullptr;           // 1: the digit held every key, no scatter
+    uint64_t* dst = nullptr;           // where the scatter writes the entry
+    uint64_t* vdst = nullptr;
+    uint64_t* and_mask = nullptr;
+    uint64_t* or_mask = nullptr;
 };
 
 // Sub-buckets that fit LDS but hold a large group of keys equal in their
@@ -200,6 +268,8 @@ struct SlowList {
     uint8_t* bits = nullptr;           // bits of key - base below which keys still differ
     uint64_t* base = nullptr;          // key offset of the entry's segment
     uint32_t* seg = nullptr;           // segment of the entry
+    uint32_t capacity = 0;
+    uint32_t* err = nullptr;
 };
 
 // Stable sort of contiguous segments [seg_off[s], seg_off[s+1]): an MSD pass
@@ -225,7 +295,11 @@ struct HybridSort {
     // (k - seg_base[s]) >> seg_shift[s].  nullptr: base 0, the top digit.
     const uint8_t* seg_shift = nullptr;
     const uint64_t* seg_base = nullptr;
-    OversizeList ov;
+    OversizeList ov;                   // two lists, alternating between levels
+    OversizeList ov2;
+    EqualList eq;
+    LevelWork lw;
+    PackedJobs pj;
     SlowList sl;
     Fences fences;                     // optional: written for the sorted output
     Profiler* prof = nullptr;
@@ -258,17 +332,25 @@ constexpr uint32_t kDirectSegMax = 2048;
 // Host-side state of the hybrid sort: pinned read-back words and the count
 // table of the oversize passes, grown on demand.
 struct HybridHost {
-    uint32_t* pinned = nullptr;        // 4 words
-    uint32_t* fb_counts = nullptr;
+    uint32_t* pinned = nullptr;        // 8 words
+    uint32_t* fb_counts = nullptr;     // count table of the deeper levels
     uint64_t fb_words = 0;
-    uint32_t last_oversize = 0;
+    uint64_t* fb_sb_start = nullptr;   // their sub-bucket tables
+    uint32_t* fb_sb_len = nullptr;
+    uint64_t fb_sb = 0;
+    uint32_t last_oversize = 0;        // entries of the first deeper level
     uint32_t last_slow = 0;
+    uint32_t last_levels = 0;          // deeper levels run
 };
 
 hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host);
-uint64_t oversize_capacity(uint32_t num_segs, uint64_t total_len);
-uint64_t oversize_tile_capacity(uint32_t num_segs, uint64_t total_len);
-uint64_t slow_capacity(uint32_t num_segs, uint64_t total_len);
+// List capacities: every list holds disjoint key ranges above a size, so the
+// bounds follow from the number of keys alone.
+uint64_t oversize_capacity(uint64_t total_len);
+uint64_t oversize_tile_capacity(uint64_t total_len);
+uint64_t level_capacity(uint32_t num_segs, uint64_t total_len);
+uint64_t packed_capacity(uint64_t total_len);
+uint64_t slow_capacity(uint64_t total_len);
 
 // --------------------------------------------------------------- rounds ----
 // The splitter rounds of any number of independent instances at once.  Index

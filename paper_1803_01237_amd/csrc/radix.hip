@@ -63,17 +63,32 @@ __device__ __forceinline__ const uint64_t* tile_vsource(const TileMap& m, const 
     return in + base;
 }
 
-template <typename K>
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// kMask: also the AND and OR of every key - base of the segment (which bits
+// vary inside it), one pair of atomics per tile.
+template <typename K, bool kMask>
 __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(const K* __restrict__ keys,
                                                                    TileMap m, int shift,
                                                                    const uint8_t* __restrict__ seg_shift,
-                                                                   uint32_t* __restrict__ counts) {
+                                                                   uint32_t* __restrict__ counts,
+                                                                   uint64_t* __restrict__ and_mask,
+                                                                   uint64_t* __restrict__ or_mask) {
     __shared__ uint32_t hist[256];
+    __shared__ uint64_t wmask[kMask ? kSortThreads / kWave : 1][2];
     hist[threadIdx.x] = 0;
     __syncthreads();
+    bool in_seg = false;
+    uint32_t mseg = 0;
     uint64_t base, e;
     uint32_t seg;
     if (tile_range(m, blockIdx.x, &base, &e, &seg)) {
+        in_seg = true;
+        mseg = seg;
         if (seg_shift) shift = seg_shift[seg];
         const K kb = m.base ? (K)m.base[seg] : (K)0;
         const uint32_t n_tile = (uint32_t)min((uint64_t)kSortTile, e - base);
@@ -101,9 +116,42 @@ __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(const K* __re
                 atomicAdd(&hist[d], 1u);
             }
         }
+        if constexpr (kMask) {
+            uint64_t am = ~0ull, om = 0;
+#pragma unroll
+            for (int r = 0; r < kSortItems; ++r) {
+                const uint32_t li = w * kKeysPerWave + r * kWave + lane;
+                if (li < n_tile) {
+                    const uint64_t x = (uint64_t)(K)(kr[r] - kb);
+                    am &= x;
+                    om |= x;
+                }
+            }
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                am &= shfl_xor_u64(am, o);
+                om |= shfl_xor_u64(om, o);
+            }
+            if (lane == 0) {
+                wmask[w][0] = am;
+                wmask[w][1] = om;
+            }
+        }
     }
     __syncthreads();
     counts[(uint64_t)blockIdx.x * 256 + threadIdx.x] = hist[threadIdx.x];
+    if constexpr (kMask) {
+        if (in_seg && threadIdx.x == 0) {
+            uint64_t am = ~0ull, om = 0;
+#pragma unroll
+            for (int q = 0; q < kSortThreads / kWave; ++q) {
+                am &= wmask[q][0];
+                om |= wmask[q][1];
+            }
+            atomicAnd((unsigned long long*)&and_mask[mseg], (unsigned long long)am);
+            atomicOr((unsigned long long*)&or_mask[mseg], (unsigned long long)om);
+        }
+    }
 }
 
 // counts[tile][d] of one segment's tiles -> offset of the run of digit d from
@@ -182,6 +230,7 @@ __global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
         uint64_t base, e;
         uint32_t seg;
         if (!tile_range(m, tile, &base, &e, &seg)) continue;   // uniform
+        if (m.skip && m.skip[seg]) continue;                   // uniform
         const int shift = seg_shift ? (int)seg_shift[seg] : shift0;
         const K kb = m.base ? (K)m.base[seg] : (K)0;
         const uint64_t b = m.beg[seg];
@@ -265,35 +314,52 @@ __global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
         }
         __syncthreads();
         const uint64_t* vsrc = kPayload ? tile_vsource(m, vin, seg, base) : nullptr;
+        // the segment's output: at its own position of the pass output, or
+        // at its listed destination
+        K* ko = m.dst ? (K*)(uintptr_t)m.dst[seg] : kout + b;
+        uint64_t* vo = kPayload ? (m.vdst ? (uint64_t*)(uintptr_t)m.vdst[seg] : vout + b) : nullptr;
         for (uint32_t i = threadIdx.x; i < n_tile; i += kScatterThreads) {
             const K k = (K)stage[i];
             const uint32_t d = digit_of((K)(k - kb), shift);
-            const uint64_t dst = b + gofs[d] + (i - tstart[d]);
-            kout[dst] = k;
-            if constexpr (kPayload) vout[dst] = vsrc[sidx[i]];
+            const uint64_t dst = gofs[d] + (i - tstart[d]);
+            ko[dst] = k;
+            if constexpr (kPayload) vo[dst] = vsrc[sidx[i]];
         }
     }
 }
 
+// algorithmic bytes: the keys (and payload) are read by the count pass, read
+// and written by the scatter pass; the count table is written by the count
+// pass, read and written by the scan, read by the scatter pass
 template <typename K>
-hipError_t pass_impl(const RadixPass& a, hipStream_t stream) {
+hipError_t count_scan_impl(const RadixPass& a, hipStream_t stream) {
     if (a.num_segs == 0 || a.num_tiles == 0) return hipSuccess;
     Profiler dummy;
     Profiler& prof = a.prof ? *a.prof : dummy;
-    const bool pay = a.vals_in != nullptr || a.has_payload;
-    // algorithmic bytes: the keys (and payload) are read by the count pass,
-    // read and written by the scatter pass; the count table is written by the
-    // count pass, read and written by the scan, read by the scatter pass
     const uint64_t table = (uint64_t)a.num_tiles * 256ull * 4ull;
     const dim3 grid(a.num_tiles), block(kSortThreads);
     prof.begin(stream);
-    hipLaunchKernelGGL(radix_count_kernel<K>, grid, block, 0, stream, (const K*)a.keys_in, a.map,
-                       a.shift, a.seg_shift, a.counts);
+    if (a.and_mask)
+        hipLaunchKernelGGL((radix_count_kernel<K, true>), grid, block, 0, stream, (const K*)a.keys_in,
+                           a.map, a.shift, a.seg_shift, a.counts, a.and_mask, a.or_mask);
+    else
+        hipLaunchKernelGGL((radix_count_kernel<K, false>), grid, block, 0, stream, (const K*)a.keys_in,
+                           a.map, a.shift, a.seg_shift, a.counts, nullptr, nullptr);
     prof.end(kProfRadixCount, stream, a.total_len * sizeof(K) + table);
     prof.begin(stream);
     hipLaunchKernelGGL(radix_scan_kernel, dim3(a.num_segs), dim3(256), 0, stream, a.counts, a.map,
                        a.sb_start, a.sb_len);
     prof.end(kProfRadixScan, stream, 2 * table);
+    return hipGetLastError();
+}
+
+template <typename K>
+hipError_t scatter_impl(const RadixPass& a, hipStream_t stream) {
+    if (a.num_segs == 0 || a.num_tiles == 0) return hipSuccess;
+    Profiler dummy;
+    Profiler& prof = a.prof ? *a.prof : dummy;
+    const bool pay = a.vals_in != nullptr || a.has_payload;
+    const uint64_t table = (uint64_t)a.num_tiles * 256ull * 4ull;
     prof.begin(stream);
     const dim3 sgrid((a.num_tiles + kScatterTilesPerGroup - 1) / kScatterTilesPerGroup);
     const dim3 sblock(kScatterThreads);
@@ -316,9 +382,20 @@ hipError_t pass_impl(const RadixPass& a, hipStream_t stream) {
 
 }  // namespace
 
+hipError_t radix_count_scan(const RadixPass& a, hipStream_t stream) {
+    if (a.key_bytes == 4) return count_scan_impl<uint32_t>(a, stream);
+    return count_scan_impl<uint64_t>(a, stream);
+}
+
+hipError_t radix_scatter(const RadixPass& a, hipStream_t stream) {
+    if (a.key_bytes == 4) return scatter_impl<uint32_t>(a, stream);
+    return scatter_impl<uint64_t>(a, stream);
+}
+
 hipError_t radix_pass(const RadixPass& a, hipStream_t stream) {
-    if (a.key_bytes == 4) return pass_impl<uint32_t>(a, stream);
-    return pass_impl<uint64_t>(a, stream);
+    const hipError_t e = radix_count_scan(a, stream);
+    if (e != hipSuccess) return e;
+    return radix_scatter(a, stream);
 }
 
 uint64_t radix_count_words(uint32_t num_segs, uint64_t max_seg_len) {

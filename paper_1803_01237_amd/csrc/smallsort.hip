@@ -2,17 +2,25 @@
 //
 //   1. one counting pass on the top 8 bits of the key (count / scan / scatter
 //      of radix.hip) moves every segment into 256 sub-buckets, in the
-//      temporary buffer; the scan records each sub-bucket's start and length
-//   2. one workgroup per sub-bucket of at most kCap keys sorts it on chip by
+//      temporary buffer; the scan records each sub-bucket's start and length.
+//      The count pass also takes the AND and OR of the segment's keys: a
+//      segment above the on-chip capacity whose top digit holds all its keys
+//      skips the scatter and goes on with the bits that still vary (or, when
+//      none does, is copied as it is)
+//   2. one workgroup per sub-bucket of at most kCapT keys sorts it on chip by
 //      the remaining bits and writes it to the output:
-//        - the keys are dropped into groups by the next 8 bits in LDS, and
-//          when no group exceeds kGroupMax keys, each key's place inside its
-//          group is counted directly (keys smaller, or equal and earlier);
-//        - otherwise the sub-bucket is listed for a second kernel that runs
-//          LSD counting passes in LDS over the remaining digits, skipping
-//          digits on which all its keys agree
-//   3. sub-buckets larger than kCap are collected into a compact list and go
-//      through LSD counting passes in HBM (radix.hip, list mode)
+//        - the keys are dropped into groups by the next 9 bits in LDS, and
+//          each key's place inside its group is counted directly (keys
+//          smaller, or equal and earlier) unless that costs more than
+//          kRankBudget comparisons per key;
+//        - then the sub-bucket is listed for a second kernel that runs LSD
+//          counting passes in LDS over the remaining digits, skipping digits
+//          on which all its keys agree
+//   3. sub-buckets above kCapT go through deeper levels of the same MSD pass
+//      on the 8 bits below their top, each range taking its own digit and
+//      alternating between the temporary buffer and the output, with the
+//      same skip rule; each level's sub-buckets are packed into on-chip jobs
+//      of at most kCapT keys.  Every level lowers the top by at least 8 bits.
 // With a payload every step is stable, so equal keys keep their input order;
 // keys alone may swap places with equal keys, which leaves the output the same.
 
@@ -28,9 +36,10 @@ constexpr int kW = kT / kWave;               // waves per workgroup
 constexpr int kCapSmall = 2048;              // largest sub-bucket sorted in LDS (local sort)
 static_assert(kDirectSegMax <= (uint32_t)kCapSmall, "direct segments fit the small sort");
 constexpr int kCapLarge = 4096;              // same for the bucket sort
-constexpr int kCap = kCapLarge;              // the LDS-LSD kernel handles any of them
-constexpr int kRows = kCap / kT;             // rows of 64 keys per wave at kCap
-constexpr uint32_t kGroupMax = 32;           // largest group ranked by direct counting
+constexpr uint32_t kGroupMax = 32;           // groups up to this size never leave the fast path
+// The fast path ranks each key against its group: sum over groups of size^2
+// comparisons.  Above kRankBudget per key the LDS-LSD passes are cheaper.
+constexpr uint32_t kRankBudget = 64;
 constexpr int kGroupBits = 9;                // bits of the second-level groups of the fast path
 
 template <typename K>
@@ -62,7 +71,7 @@ __device__ __forceinline__ void put_fence(const FenceSink& fs, uint64_t o, uint6
 // `dk` / `di`.
 // Leaves the digit starts in start[0..256] and the largest digit count in
 // *max_count.  Wave w handles the keys [w*cw, (w+1)*cw) in rows of 64.
-template <typename K>
+template <typename K, int kCapT>
 __device__ void lds_pass(const K* sk, const uint16_t* si, K* dk, uint16_t* di, uint32_t n,
                          int shift, K kbase, uint32_t (*whist)[256], uint32_t* start,
                          uint32_t* scratch, uint32_t* max_count) {
@@ -72,6 +81,7 @@ __device__ void lds_pass(const K* sk, const uint16_t* si, K* dk, uint16_t* di, u
     for (int i = threadIdx.x; i < kW * 256; i += kT) (&whist[0][0])[i] = 0;
     if (threadIdx.x == 0) *max_count = 0;
     __syncthreads();
+    constexpr int kRows = kCapT / kT;
     uint32_t rank[kRows];
     uint32_t dg[kRows];
 #pragma unroll
@@ -125,12 +135,13 @@ __device__ void lds_pass(const K* sk, const uint16_t* si, K* dk, uint16_t* di, u
     __syncthreads();
 }
 
-// Fast path, one workgroup per sub-bucket of at most kCap keys: keys stay in
+// Fast path, one workgroup per sub-bucket of at most kCapT keys: keys stay in
 // registers, are dropped into their group (next kGB bits) in LDS in any order,
 // and each key's rank inside its group is counted by (key, input index), or
 // by (key, place in the group) for keys without payload.
-// Sub-buckets with a group larger than kGroupMax go to the LDS-LSD list,
-// larger than kCap to the oversize list.
+// Sub-buckets whose large groups (above kGroupMax) would take more than
+// kRankBudget comparisons per key go to the LDS-LSD list, sub-buckets above
+// kCapT to the oversize list.
 // Work of the small sort: entries [0, n_msd) are the sub-buckets of the MSD
 // pass (entry = 256 * pass segment + digit), entries [n_msd, n_msd +
 // n_direct) whole segments taken straight from their input.
@@ -143,13 +154,24 @@ struct SmallJobs {
     const uint64_t* direct_vsrc = nullptr;
     const K* keys_in = nullptr;
     const uint64_t* vals_in = nullptr;
-    K* stash = nullptr;                    // the MSD buffer: direct segments put on the slow list
+    K* stash = nullptr;                    // the MSD buffer: slow-list entries are read from it
     uint64_t* vstash = nullptr;
     const uint64_t* seg_off = nullptr;     // positions of every segment
     int key_bits = 64;
+    // a deeper level: job j is packed job j of `pj`, a run of sub-buckets of
+    // entry li = pj.entry[j] of the level's list, whose keys were scattered
+    // into the output (loc kLocTmp) or into the MSD buffer (otherwise)
+    PackedJobs pj;
+    const uint64_t* lvl_base = nullptr;
+    const uint32_t* lvl_seg = nullptr;
+    const uint8_t* lvl_loc = nullptr;
+    EqualList eq;                          // all-equal sub-buckets above the capacity
 };
 
-template <typename K, bool kPayload, int kCapT, int kGB>
+// kStage: the payload is staged in LDS as well, so that a sub-bucket may be
+// sorted in place (deeper levels, whose sub-buckets may already sit in the
+// output).
+template <typename K, bool kPayload, int kCapT, int kGB, bool kStage>
 __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ kin,
                                                         const uint64_t* __restrict__ vin,
                                                         K* __restrict__ kout,
@@ -161,16 +183,19 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
                                                         const uint64_t* __restrict__ seg_base,
                                                         OversizeList ov, SlowList sl,
                                                         SmallJobs<K> jobs, Fences fences) {
+    static_assert(kPayload || !kStage, "staging is for the payload");
     constexpr int kRowsT = kCapT / kT;
     constexpr uint32_t kG = 1u << kGB;           // groups
     constexpr int kGR = (int)kG / kT;            // groups per thread in the scan
     static_assert(kGR >= 1 && kGR * kT == (int)kG, "group count");
     __shared__ K Bk[kCapT];
     __shared__ uint16_t Bi[kPayload ? kCapT : 1];   // input index of each placed key
+    __shared__ uint64_t Bv[kStage ? kCapT : 1];     // payload of each placed key
     __shared__ uint32_t hist[kG];                 // group sizes
     __shared__ uint32_t cursor[kG];               // group starts, then ends after placement
     __shared__ uint32_t scratch[kW];
     __shared__ uint32_t max_count;
+    __shared__ uint32_t rank_work;
 
     uint64_t base;
     uint32_t n, seg;
@@ -178,16 +203,31 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     int bits;
     const K* src;
     const uint64_t* vsrc;
+    bool in_out = false;   // the sub-bucket already sits in the output
     const bool direct = blockIdx.x >= jobs.n_msd;
     if (!direct) {
-        base = sb_start[blockIdx.x];
-        n = sb_len[blockIdx.x];
-        const uint32_t li = blockIdx.x / 256;
-        seg = jobs.msd_seg ? jobs.msd_seg[li] : li;
-        kbase = seg_base ? (K)seg_base[seg] : (K)0;
-        bits = seg_shift ? (int)seg_shift[seg] : uniform_bits;
-        src = kin + base;
-        vsrc = kPayload ? vin + base : nullptr;
+        if (jobs.pj.count) {
+            // the grid is a bound on the packed jobs
+            if (blockIdx.x >= min(*jobs.pj.count, jobs.pj.capacity)) return;
+            base = jobs.pj.start[blockIdx.x];
+            n = jobs.pj.len[blockIdx.x];
+            const uint32_t li = jobs.pj.entry[blockIdx.x];
+            seg = jobs.lvl_seg[li];
+            kbase = (K)jobs.lvl_base[li];
+            bits = jobs.pj.bits[blockIdx.x];
+            in_out = jobs.lvl_loc[li] == kLocTmp;
+            src = (in_out ? (const K*)kout : kin) + base;
+            vsrc = kPayload ? (in_out ? (const uint64_t*)vout : vin) + base : nullptr;
+        } else {
+            base = sb_start[blockIdx.x];
+            n = sb_len[blockIdx.x];
+            const uint32_t li = blockIdx.x / 256;
+            seg = jobs.msd_seg ? jobs.msd_seg[li] : li;
+            kbase = seg_base ? (K)seg_base[seg] : (K)0;
+            bits = seg_shift ? (int)seg_shift[seg] : uniform_bits;
+            src = kin + base;
+            vsrc = kPayload ? vin + base : nullptr;
+        }
     } else {
         const uint32_t dj = blockIdx.x - jobs.n_msd;
         seg = jobs.direct_seg[dj];
@@ -201,23 +241,45 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
                         : nullptr;
     }
     if (n == 0) return;
-    if (n > (uint32_t)kCapT) {   // sub-buckets of the MSD pass only
+    if (n > (uint32_t)kCapT) {   // sub-buckets of an MSD pass only
         if (threadIdx.x == 0) {
-            const uint32_t e = atomicAdd(ov.count, 1u);
-            ov.beg[e] = base;
-            ov.end[e] = base + n;
-            ov.base[e] = (uint64_t)kbase;
-            ov.seg[e] = seg;
+            if (bits == 0) {     // every key equal: nothing left to sort
+                const uint32_t e = atomicAdd(jobs.eq.count, 1u);
+                if (e >= jobs.eq.capacity) {
+                    atomicOr(jobs.eq.err, 1u);
+                    return;
+                }
+                jobs.eq.beg[e] = base;
+                jobs.eq.end[e] = base + n;
+                jobs.eq.seg[e] = seg;
+                jobs.eq.loc[e] = in_out ? kLocOut : kLocTmp;
+                jobs.eq.src[e] = (uint64_t)(uintptr_t)src;
+                jobs.eq.vsrc[e] = (uint64_t)(uintptr_t)vsrc;
+            } else {
+                const uint32_t e = atomicAdd(ov.count, 1u);
+                if (e >= ov.capacity) {
+                    atomicOr(ov.err, 1u);
+                    return;
+                }
+                ov.beg[e] = base;
+                ov.end[e] = base + n;
+                ov.base[e] = (uint64_t)kbase;
+                ov.seg[e] = seg;
+                ov.bits[e] = (uint8_t)bits;
+                ov.loc[e] = in_out ? kLocOut : kLocTmp;
+                ov.src[e] = (uint64_t)(uintptr_t)src;
+                ov.vsrc[e] = (uint64_t)(uintptr_t)vsrc;
+            }
         }
         return;
     }
-    if (n == 1) {
-        if (threadIdx.x == 0) {
-            const K k = src[0];
-            kout[base] = k;
-            if constexpr (kPayload) vout[base] = vsrc[0];
-            const FenceSink fs = fence_sink(fences, seg);
-            if (fs.dst) put_fence(fs, base, (uint64_t)k);
+    const FenceSink fs = fence_sink(fences, seg);
+    if (n == 1 || bits == 0) {   // already in order: every key equal
+        for (uint32_t i = threadIdx.x; i < n; i += kT) {
+            const K k = src[i];
+            kout[base + i] = k;
+            if constexpr (kPayload) vout[base + i] = vsrc[i];
+            if (fs.dst) put_fence(fs, base + i, (uint64_t)k);
         }
         return;
     }
@@ -225,16 +287,21 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     // above `bits`
     const int shift2 = bits >= kGB ? bits - kGB : 0;
     for (uint32_t i = threadIdx.x; i < kG; i += kT) hist[i] = 0;
-    if (threadIdx.x == 0) max_count = 0;
+    if (threadIdx.x == 0) {
+        max_count = 0;
+        rank_work = 0;
+    }
     __syncthreads();
     K kr[kRowsT];
     uint32_t dr[kRowsT];
+    uint64_t vr[kStage ? kRowsT : 1];
 #pragma unroll
     for (int r = 0; r < kRowsT; ++r) {
         const uint32_t i = r * kT + threadIdx.x;
         kr[r] = 0;
         dr[r] = 0;
         if (i < n) kr[r] = src[i];
+        if constexpr (kStage) vr[r] = i < n ? vsrc[i] : 0;
     }
 #pragma unroll
     for (int r = 0; r < kRowsT; ++r) {
@@ -247,13 +314,15 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     __syncthreads();
     {
         // thread t scans the groups [t kGR, (t+1) kGR)
-        uint32_t c[kGR], local = 0, mx = 0;
+        uint32_t c[kGR], local = 0, mx = 0, sq = 0;
 #pragma unroll
         for (int j = 0; j < kGR; ++j) {
             c[j] = hist[threadIdx.x * kGR + j];
             local += c[j];
             mx = max(mx, c[j]);
+            sq += c[j] * c[j];
         }
+        if (mx > kGroupMax) atomicAdd(&rank_work, sq);
         uint32_t all;
         uint32_t st = block_exclusive_scan<uint32_t, kT>(local, scratch, &all);
 #pragma unroll
@@ -264,20 +333,31 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
         if (mx > kGroupMax) atomicMax(&max_count, mx);
     }
     __syncthreads();
-    if (max_count > kGroupMax) {
-        if (direct) {
-            // the slow path reads the MSD buffer: move the segment there
+    // bits <= kGB: a group holds one key value, so with keys alone the
+    // placement below is already the sorted order
+    const bool exact = !kPayload && bits <= kGB;
+    // otherwise the groups above kGroupMax decide: their ranking work is
+    // counted against the budget (small groups cost at most kGroupMax each)
+    if (!exact && max_count > kGroupMax && rank_work > kRankBudget * n) {
+        if (direct || in_out) {
+            // the slow path reads the MSD buffer: move the keys there (its
+            // copy of this range is no longer needed)
 #pragma unroll
             for (int r = 0; r < kRowsT; ++r) {
                 const uint32_t i = r * kT + threadIdx.x;
                 if (i < n) {
                     jobs.stash[base + i] = kr[r];
-                    if constexpr (kPayload) jobs.vstash[base + i] = vsrc[i];
+                    if constexpr (kStage) jobs.vstash[base + i] = vr[r];
+                    else if constexpr (kPayload) jobs.vstash[base + i] = vsrc[i];
                 }
             }
         }
         if (threadIdx.x == 0) {
             const uint32_t e = atomicAdd(sl.count, 1u);
+            if (e >= sl.capacity) {
+                atomicOr(sl.err, 1u);
+                return;
+            }
             sl.beg[e] = base;
             sl.len[e] = n;
             sl.bits[e] = (uint8_t)bits;
@@ -293,10 +373,18 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
             const uint32_t pos = atomicAdd(&cursor[dr[r]], 1u);
             Bk[pos] = kr[r];
             if constexpr (kPayload) Bi[pos] = (uint16_t)i;
+            if constexpr (kStage) Bv[pos] = vr[r];
         }
     }
     __syncthreads();
-    const FenceSink fs = fence_sink(fences, seg);
+    if (exact) {
+        for (uint32_t e = threadIdx.x; e < n; e += kT) {
+            const K k = Bk[e];
+            kout[base + e] = k;
+            if (fs.dst) put_fence(fs, base + e, (uint64_t)k);
+        }
+        return;
+    }
     for (uint32_t e = threadIdx.x; e < n; e += kT) {
         const K k = Bk[e];
         const uint32_t d = (uint32_t)((K)(k - kbase) >> shift2) & (kG - 1);
@@ -311,7 +399,8 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
             }
             const uint64_t o = base + g0 + rk;
             kout[o] = k;
-            vout[o] = vsrc[ie];
+            if constexpr (kStage) vout[o] = Bv[e];
+            else vout[o] = vsrc[ie];
             if (fs.dst) put_fence(fs, o, (uint64_t)k);
         } else {
             // keys only: equal keys are interchangeable, so the ones placed
@@ -325,10 +414,10 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     }
 }
 
-// Sub-buckets of at most kCap keys with a large group (duplicates or
+// Sub-buckets of at most kCap keys with large groups (duplicates or
 // clustered keys): LSD counting passes in LDS over the digits below `bits`
 // that vary, from the input order.
-template <typename K, bool kPayload>
+template <typename K, bool kPayload, int kCap>
 __global__ __launch_bounds__(kT) void lds_lsd_kernel(const K* __restrict__ kin,
                                                      const uint64_t* __restrict__ vin,
                                                      K* __restrict__ kout,
@@ -368,7 +457,7 @@ __global__ __launch_bounds__(kT) void lds_lsd_kernel(const K* __restrict__ kin,
     uint16_t* di = Bi;
     for (int sh = 0; sh < bits; sh += 8) {
         if (((diff >> sh) & 0xFFu) == 0) continue;   // uniform digit: order unchanged
-        lds_pass<K>(sk, si, dk, di, n, sh, kbase, whist, start, scratch, &max_count);
+        lds_pass<K, kCap>(sk, si, dk, di, n, sh, kbase, whist, start, scratch, &max_count);
         // the pass output becomes the next input; the buffer pair (keys,
         // indices) it read from becomes the next output
         K* old = (K*)sk;
@@ -386,17 +475,27 @@ __global__ __launch_bounds__(kT) void lds_lsd_kernel(const K* __restrict__ kin,
     }
 }
 
-// Fences of the oversize sub-buckets, read back from the sorted output.
+// Ranges whose keys are all equal: copied to the output unless already
+// there, with their fences.  Workgroups stride over the entries.
 template <typename K>
-__global__ void ov_fence_kernel(const K* __restrict__ kout, OversizeList ov, Fences fences) {
-    const uint32_t E = *ov.count;
+__global__ void equal_copy_kernel(K* __restrict__ kout, uint64_t* __restrict__ vout, EqualList eq,
+                                  Fences fences) {
+    const uint32_t E = min(*eq.count, eq.capacity);
     for (uint32_t e = blockIdx.x; e < E; e += gridDim.x) {
-        const uint32_t seg = ov.seg[e];
-        const uint64_t sb = fences.seg_off[seg];
-        const uint64_t first = sb + ((ov.beg[e] - sb + kFenceStride - 1) / kFenceStride) * kFenceStride;
-        for (uint64_t o = first + (uint64_t)threadIdx.x * kFenceStride; o < ov.end[e];
-             o += (uint64_t)blockDim.x * kFenceStride)
-            fences.key[fences.base[seg] + (o - sb) / kFenceStride] = (uint64_t)kout[o];
+        const uint64_t b = eq.beg[e], n = eq.end[e] - b;
+        const uint32_t seg = eq.seg[e];
+        const FenceSink fs = fence_sink(fences, seg);
+        const K* src = (const K*)(uintptr_t)eq.src[e];
+        const uint64_t* vsrc = (const uint64_t*)(uintptr_t)eq.vsrc[e];
+        const bool copy = eq.loc[e] != kLocOut;
+        for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const K k = src[i];
+            if (copy) {
+                kout[b + i] = k;
+                if (vout) vout[b + i] = vsrc[i];
+            }
+            if (fs.dst) put_fence(fs, b + i, (uint64_t)k);
+        }
     }
 }
 
@@ -411,11 +510,14 @@ __global__ void fence_fill_kernel(const K* __restrict__ keys, Fences fences) {
         fences.key[fences.base[seg] + f] = (uint64_t)keys[sb + f * kFenceStride];
 }
 
-// One workgroup: tile offsets of the oversize list, and the list sizes the
-// host reads back in one copy.
-__global__ __launch_bounds__(1024) void ov_tiles_kernel(OversizeList ov, SlowList sl) {
+// One workgroup: tile offsets of an oversize list, and the list sizes the
+// host reads back in one copy (entries, tiles, slow-list and equal-list
+// entries).
+__global__ __launch_bounds__(1024) void ov_tiles_kernel(OversizeList ov, SlowList sl, EqualList eq) {
     __shared__ uint32_t scratch[1024 / kWave];
-    const uint32_t E = *ov.count;
+    // a full list stops the sort: the overrun flag is read with the sizes
+    const bool full = *ov.err != 0;
+    const uint32_t E = full ? 0u : min(*ov.count, ov.capacity);
     uint32_t run = 0;
     for (uint32_t c = 0; c < E; c += 1024) {
         const uint32_t e = c + threadIdx.x;
@@ -430,23 +532,299 @@ __global__ __launch_bounds__(1024) void ov_tiles_kernel(OversizeList ov, SlowLis
         *ov.tiles = run;
         ov.summary[0] = E;
         ov.summary[1] = run;
-        ov.summary[2] = *sl.count;
-        ov.summary[3] = 0;
+        ov.summary[2] = min(*sl.count, sl.capacity);
+        ov.summary[3] = min(*eq.count, eq.capacity);
+        ov.summary[4] = *ov.err;
+        if (full) *ov.count = 0;
     }
 }
 
 __global__ void ov_fill_kernel(OversizeList ov) {
-    const uint32_t E = *ov.count;
+    const uint32_t E = min(*ov.count, ov.capacity);
     for (uint32_t e = blockIdx.x; e < E; e += gridDim.x) {
         const uint32_t t0 = ov.tile0[e], t1 = ov.tile0[e + 1];
         for (uint32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) ov.tile_seg[t] = e;
     }
 }
 
-__global__ void ov_reset_kernel(OversizeList ov, SlowList sl) {
+// Empties a list; with the slow and equal lists given, also those and the
+// overrun flag (start of a sort).
+__global__ void ov_reset_kernel(OversizeList ov, SlowList sl, EqualList eq) {
     *ov.count = 0;
     *ov.tiles = 0;
-    *sl.count = 0;
+    if (sl.count) *sl.count = 0;
+    if (eq.count) {
+        *eq.count = 0;
+        *ov.err = 0;
+    }
+}
+
+__global__ void count_reset_kernel(uint32_t* c) { *c = 0; }
+
+// Level 1: the masks of every MSD segment start empty.
+__global__ void mask_reset_kernel(LevelWork w, uint32_t n) {
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        w.and_mask[e] = ~0ull;
+        w.or_mask[e] = 0;
+        w.skip[e] = 0;
+    }
+}
+
+// A deeper level over the entries of `ov`: each entry's digit is the 8 bits
+// below its top (the lowest 8 when fewer remain), and its scatter goes to the
+// other buffer (from the input, to the MSD buffer).
+__global__ void level_prep_kernel(OversizeList ov, LevelWork w, uint64_t tmp, uint64_t out,
+                                  uint64_t vtmp, uint64_t vout, int key_bytes) {
+    const uint32_t E = min(*ov.count, ov.capacity);
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < E; e += gridDim.x * blockDim.x) {
+        const int bits = ov.bits[e];
+        w.shift[e] = (uint8_t)(bits > 8 ? bits - 8 : 0);
+        const bool to_out = ov.loc[e] == kLocTmp;
+        w.dst[e] = (to_out ? out : tmp) + ov.beg[e] * (uint64_t)key_bytes;
+        w.vdst[e] = vtmp ? (to_out ? vout : vtmp) + ov.beg[e] * 8 : 0;
+        w.and_mask[e] = ~0ull;
+        w.or_mask[e] = 0;
+        w.skip[e] = 0;
+    }
+}
+
+// The entries a level decides on: level 1 takes them from the MSD pass map
+// (keys at the sort's input), deeper levels from their list.
+struct DecideView {
+    const uint64_t* beg = nullptr;
+    const uint64_t* end = nullptr;
+    const uint64_t* base = nullptr;    // null: 0
+    const uint32_t* seg = nullptr;     // null: the entry index
+    const uint8_t* loc = nullptr;      // null: kLocIn
+    const uint64_t* src = nullptr;     // null: keys_in at beg
+    const uint64_t* vsrc = nullptr;
+    uint64_t keys_in = 0;
+    uint64_t vals_in = 0;
+    int key_bytes = 8;
+    const uint32_t* count = nullptr;   // entries (null: n)
+    uint32_t capacity = 0;             // of the list behind count
+    uint32_t n = 0;
+    uint32_t min_len = 0;              // entries of at most this many keys stay
+};
+
+// Workgroup per entry, between scan and scatter.  When one digit holds all
+// of an entry's keys the scatter would only copy them: the entry skips it,
+// its sub-buckets are emptied, and it moves on with the bits that still vary
+// (AND and OR of the count pass) -- to the equal list when none does, else to
+// the next level's list with the highest varying bit as its new top.
+// Deeper levels (pj given) also pack the entry's sub-buckets into small-sort
+// jobs of at most `cap` keys, so that a level does not launch a workgroup per
+// (mostly tiny) sub-bucket.
+__global__ __launch_bounds__(256) void level_decide_kernel(DecideView v, LevelWork w,
+                                                           const uint64_t* __restrict__ sb_start,
+                                                           uint32_t* __restrict__ sb_len,
+                                                           OversizeList next, EqualList eq,
+                                                           PackedJobs pj, uint32_t cap) {
+    __shared__ uint32_t nz;
+    __shared__ uint32_t lens[256], starts[256];
+    __shared__ uint32_t job_d0[256], job_d1[256], job_len[256];
+    __shared__ uint32_t scan_tmp[256 / kWave];
+    __shared__ int last_ne[256 / kWave];
+    __shared__ uint32_t n_jobs, job0;
+    const uint32_t E = v.count ? min(*v.count, v.capacity) : v.n;
+    const uint32_t e = blockIdx.x;
+    if (e >= E) return;
+    const uint64_t b = v.beg[e], n = v.end[e] - b;
+    if (n <= v.min_len) return;   // uniform over the workgroup
+    if (threadIdx.x == 0) nz = 0;
+    __syncthreads();
+    const uint32_t len = sb_len[(uint64_t)e * 256 + threadIdx.x];
+    lens[threadIdx.x] = len;
+    if (len) atomicAdd(&nz, 1u);
+    __syncthreads();
+    if (nz != 1) {
+        if (!pj.count) return;
+        // packing by windows of C = cap / 2 keys: a sub-bucket above C is a
+        // job alone; the others form one job per run of sub-buckets whose
+        // starts fall in the same window (less than 2 C = cap keys in all)
+        const uint32_t C = cap / 2;
+        const uint32_t d = threadIdx.x, lane = lane_id(), wv = d / kWave;
+        uint32_t tot;
+        const uint32_t st = block_exclusive_scan<uint32_t, 256>(len, scan_tmp, &tot);
+        starts[d] = st;
+        const bool ne = len != 0;
+        const uint64_t mask = __ballot(ne);
+        if (lane == 0) last_ne[wv] = mask ? (int)(wv * kWave + 63 - __clzll((long long)mask)) : -1;
+        __syncthreads();
+        // the previous non-empty sub-bucket: in this wave, else the last of
+        // an earlier wave
+        int pd = -1;
+        const uint64_t below = mask & lanes_below_mask();
+        if (below) {
+            pd = (int)(wv * kWave + 63 - __clzll((long long)below));
+        } else {
+            for (int q = (int)wv - 1; q >= 0 && pd < 0; --q) pd = last_ne[q];
+        }
+        const bool big = len > C;
+        const bool first = ne && (pd < 0 || big || lens[pd] > C || st / C != starts[pd] / C);
+        // job index of every non-empty sub-bucket: inclusive count of firsts
+        const uint32_t fi = block_exclusive_scan<uint32_t, 256>(first ? 1u : 0u, scan_tmp, &tot);
+        const uint32_t jid = fi + (first ? 1u : 0u) - 1;   // valid where ne
+        if (d < tot) {
+            job_len[d] = 0;
+            job_d0[d] = 0;   // last non-empty digit of the job
+        }
+        if (d == 0) {
+            n_jobs = tot;
+            job0 = atomicAdd(pj.count, tot);
+            if (job0 + tot > pj.capacity) atomicOr(pj.err, 1u);
+        }
+        __syncthreads();
+        if (ne) {
+            atomicAdd(&job_len[jid], len);
+            atomicMax(&job_d0[jid], d);
+            if (first) job_d1[jid] = d;   // first sub-bucket of the job
+        }
+        __syncthreads();
+        const uint32_t nj = n_jobs, q0 = job0;
+        if (q0 + nj > pj.capacity) return;
+        const uint32_t shift = w.shift[e];
+        if (d < nj) {
+            pj.start[q0 + d] = sb_start[(uint64_t)e * 256 + job_d1[d]];
+            pj.len[q0 + d] = job_len[d];
+            pj.entry[q0 + d] = e;
+            // the job's digits lie in [first, last], so its keys agree above
+            // the highest bit in which first and last differ (one
+            // sub-bucket: the bits below its digit)
+            const uint32_t x = job_d1[d] ^ job_d0[d];
+            pj.bits[q0 + d] = (uint8_t)(shift + (x ? 32 - __clz(x) : 0));
+        }
+        return;
+    }
+    sb_len[(uint64_t)e * 256 + threadIdx.x] = 0;
+    if (threadIdx.x != 0) return;
+    w.skip[e] = 1;
+    const uint32_t seg = v.seg ? v.seg[e] : e;
+    const uint8_t loc = v.loc ? v.loc[e] : kLocIn;
+    const uint64_t src = v.src ? v.src[e] : v.keys_in + b * (uint64_t)v.key_bytes;
+    const uint64_t vsrc = v.vsrc ? v.vsrc[e] : (v.vals_in ? v.vals_in + b * 8 : 0);
+    const uint64_t vary = w.and_mask[e] ^ w.or_mask[e];
+    if (vary == 0) {
+        const uint32_t q = atomicAdd(eq.count, 1u);
+        if (q >= eq.capacity) {
+            atomicOr(eq.err, 1u);
+            return;
+        }
+        eq.beg[q] = b;
+        eq.end[q] = b + n;
+        eq.seg[q] = seg;
+        eq.loc[q] = loc;
+        eq.src[q] = src;
+        eq.vsrc[q] = vsrc;
+    } else {
+        const uint32_t q = atomicAdd(next.count, 1u);
+        if (q >= next.capacity) {
+            atomicOr(next.err, 1u);
+            return;
+        }
+        next.beg[q] = b;
+        next.end[q] = b + n;
+        next.base[q] = v.base ? v.base[e] : 0;
+        next.seg[q] = seg;
+        next.bits[q] = (uint8_t)(64 - __clzll((long long)vary));
+        next.loc[q] = loc;
+        next.src[q] = src;
+        next.vsrc[q] = vsrc;
+    }
+}
+
+template <typename K, bool kPay, int kCapT, bool kStage>
+void launch_small(dim3 grid, hipStream_t s, const HybridSort& a, const uint64_t* sb_start,
+                  const uint32_t* sb_len, int bits, const OversizeList& push, const SmallJobs<K>& jobs) {
+    hipLaunchKernelGGL((small_sort_kernel<K, kPay, kCapT, kGroupBits, kStage>), grid, dim3(kT), 0, s,
+                       (const K*)a.keys_tmp, kPay ? a.vals_tmp : nullptr, (K*)a.keys_out,
+                       kPay ? a.vals_out : nullptr, sb_start, sb_len, bits, a.seg_shift, a.seg_base,
+                       push, a.sl, jobs, a.fences);
+}
+
+// Level 1 (stage = false) reads sub-buckets from the MSD buffer; deeper
+// levels may sort in place and stage the payload.
+template <typename K>
+void launch_small_any(bool pay, bool large, bool stage, dim3 grid, hipStream_t s,
+                      const HybridSort& a, const uint64_t* sb_start, const uint32_t* sb_len,
+                      int bits, const OversizeList& push, const SmallJobs<K>& jobs) {
+    if (pay) {
+        if (stage) {
+            if (large) launch_small<K, true, kCapLarge, true>(grid, s, a, sb_start, sb_len, bits, push, jobs);
+            else launch_small<K, true, kCapSmall, true>(grid, s, a, sb_start, sb_len, bits, push, jobs);
+        } else {
+            if (large) launch_small<K, true, kCapLarge, false>(grid, s, a, sb_start, sb_len, bits, push, jobs);
+            else launch_small<K, true, kCapSmall, false>(grid, s, a, sb_start, sb_len, bits, push, jobs);
+        }
+    } else {
+        if (large) launch_small<K, false, kCapLarge, false>(grid, s, a, sb_start, sb_len, bits, push, jobs);
+        else launch_small<K, false, kCapSmall, false>(grid, s, a, sb_start, sb_len, bits, push, jobs);
+    }
+}
+
+template <typename K, int kCapT>
+void launch_lds_lsd(bool pay, dim3 g, hipStream_t s, const HybridSort& a) {
+    if (pay)
+        hipLaunchKernelGGL((lds_lsd_kernel<K, true, kCapT>), g, dim3(kT), 0, s, (const K*)a.keys_tmp,
+                           a.vals_tmp, (K*)a.keys_out, a.vals_out, a.sl, a.fences);
+    else
+        hipLaunchKernelGGL((lds_lsd_kernel<K, false, kCapT>), g, dim3(kT), 0, s, (const K*)a.keys_tmp,
+                           nullptr, (K*)a.keys_out, nullptr, a.sl, a.fences);
+}
+
+template <typename K>
+SmallJobs<K> level1_jobs(const HybridSort& a, uint32_t msd_segs, int kb) {
+    SmallJobs<K> jobs;
+    jobs.n_msd = msd_segs * 256u;
+    jobs.msd_seg = a.msd_seg;
+    jobs.direct_seg = a.direct_seg;
+    jobs.direct_src = a.direct_src;
+    jobs.direct_vsrc = a.direct_vsrc;
+    jobs.keys_in = (const K*)a.keys_in;
+    jobs.vals_in = a.vals_in;
+    jobs.stash = (K*)a.keys_tmp;
+    jobs.vstash = a.vals_tmp;
+    jobs.seg_off = a.seg_off;
+    jobs.key_bits = kb;
+    jobs.eq = a.eq;
+    return jobs;
+}
+
+template <typename K>
+SmallJobs<K> level_jobs(const HybridSort& a, const OversizeList& cur, uint32_t grid) {
+    SmallJobs<K> jobs;
+    jobs.n_msd = grid;
+    jobs.stash = (K*)a.keys_tmp;
+    jobs.vstash = a.vals_tmp;
+    jobs.seg_off = a.seg_off;
+    jobs.pj = a.pj;
+    jobs.lvl_base = cur.base;
+    jobs.lvl_seg = cur.seg;
+    jobs.lvl_loc = cur.loc;
+    jobs.eq = a.eq;
+    return jobs;
+}
+
+hipError_t read_summary(const OversizeList& ov, const SlowList& sl, const EqualList& eq,
+                        HybridHost& host, hipStream_t s) {
+    hipLaunchKernelGGL(ov_tiles_kernel, dim3(1), dim3(1024), 0, s, ov, sl, eq);
+    hipLaunchKernelGGL(ov_fill_kernel, dim3(1024), dim3(256), 0, s, ov);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(host.pinned, ov.summary, 5 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && host.pinned[4]) e = hipErrorOutOfMemory;   // a list overran
+    return e;
+}
+
+template <typename T>
+hipError_t grow(T** p, uint64_t* cap, uint64_t need) {
+    if (need <= *cap) return hipSuccess;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    hipError_t e = hipMalloc((void**)p, need * sizeof(T));
+    if (e == hipSuccess) *cap = need;
+    return e;
 }
 
 }  // namespace
@@ -463,10 +841,16 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     Profiler dummy;
     Profiler& prof = a.prof ? *a.prof : dummy;
     const bool pay = a.vals_in != nullptr || a.has_payload;
+    // sub-buckets of the p input segments split by their top byte average
+    // N/(256 p) keys; bucket key ranges may use only half of the digit values
+    const bool large = a.seg_base != nullptr;
+    const uint32_t cap = large ? kCapLarge : kCapSmall;
     hipError_t e = hipSuccess;
 
-    hipLaunchKernelGGL(ov_reset_kernel, dim3(1), dim3(1), 0, s, a.ov, a.sl);
-    // 1. MSD pass of the large segments into the temporary buffer
+    hipLaunchKernelGGL(ov_reset_kernel, dim3(1), dim3(1), 0, s, a.ov, a.sl, a.eq);
+    // 1. MSD pass of the large segments into the temporary buffer.  A segment
+    //    above the small-sort capacity whose top digit holds all its keys
+    //    skips the scatter and goes on to the deeper levels.
     if (msd_segs > 0 && msd_tiles > 0) {
         RadixPass ps;
         ps.key_bytes = a.key_bytes;
@@ -482,6 +866,7 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         ps.map.tps = tps;
         ps.map.src = a.msd_src;
         ps.map.vsrc = a.msd_vsrc;
+        ps.map.skip = a.lw.skip;
         ps.num_segs = msd_segs;
         ps.num_tiles = msd_tiles;
         ps.shift = bits;
@@ -495,105 +880,153 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         // keys are interchangeable, so the order inside a run does not matter
         ps.any_order = !pay;
         ps.has_payload = pay;
-        e = radix_pass(ps, s);
+        ps.and_mask = a.lw.and_mask;
+        ps.or_mask = a.lw.or_mask;
+        hipLaunchKernelGGL(mask_reset_kernel, dim3(min((msd_segs + 255) / 256, 1024u)), dim3(256), 0, s,
+                           a.lw, msd_segs);
+        e = radix_count_scan(ps, s);
+        if (e != hipSuccess) return e;
+        DecideView v;
+        v.beg = ps.map.beg;
+        v.end = ps.map.end;
+        v.base = a.seg_base;
+        v.seg = a.msd_seg;
+        v.src = a.msd_src;
+        v.vsrc = a.msd_vsrc;
+        v.keys_in = (uint64_t)(uintptr_t)a.keys_in;
+        v.vals_in = (uint64_t)(uintptr_t)a.vals_in;
+        v.key_bytes = a.key_bytes;
+        v.n = msd_segs;
+        v.min_len = cap;
+        hipLaunchKernelGGL(level_decide_kernel, dim3(msd_segs), dim3(256), 0, s, v, a.lw, a.sb_start,
+                           a.sb_len, a.ov, a.eq, PackedJobs{}, cap);
+        e = radix_scatter(ps, s);
         if (e != hipSuccess) return e;
     }
     // 2. sub-buckets, and the segments small enough to take whole, in LDS
-    const dim3 grid(msd_segs * 256u + a.n_direct);
-    prof.begin(s);
-    // sub-buckets of the p input segments split by their top byte average
-    // N/(256 p) keys; bucket key ranges may use only half of the digit values
-    const bool large = a.seg_base != nullptr;
-#define HSS_SMALL(KT, PAY, CAP)                                                                  \
-    do {                                                                                         \
-        SmallJobs<KT> jobs;                                                                      \
-        jobs.n_msd = msd_segs * 256u;                                                            \
-        jobs.msd_seg = a.msd_seg;                                                                \
-        jobs.direct_seg = a.direct_seg;                                                          \
-        jobs.direct_src = a.direct_src;                                                          \
-        jobs.direct_vsrc = a.direct_vsrc;                                                        \
-        jobs.keys_in = (const KT*)a.keys_in;                                                     \
-        jobs.vals_in = a.vals_in;                                                                \
-        jobs.stash = (KT*)a.keys_tmp;                                                            \
-        jobs.vstash = a.vals_tmp;                                                                \
-        jobs.seg_off = a.seg_off;                                                                \
-        jobs.key_bits = kb;                                                                      \
-        hipLaunchKernelGGL((small_sort_kernel<KT, PAY, CAP, kGroupBits>), grid, dim3(kT), 0, s,  \
-                           (const KT*)a.keys_tmp, PAY ? a.vals_tmp : nullptr, (KT*)a.keys_out,     \
-                           PAY ? a.vals_out : nullptr, a.sb_start, a.sb_len, bits, a.seg_shift,    \
-                           a.seg_base, a.ov, a.sl, jobs, a.fences);                                \
-    } while (0)
-    if (a.key_bytes == 4) {
-        if (pay) { if (large) HSS_SMALL(uint32_t, true, kCapLarge); else HSS_SMALL(uint32_t, true, kCapSmall); }
-        else { if (large) HSS_SMALL(uint32_t, false, kCapLarge); else HSS_SMALL(uint32_t, false, kCapSmall); }
-    } else {
-        if (pay) { if (large) HSS_SMALL(uint64_t, true, kCapLarge); else HSS_SMALL(uint64_t, true, kCapSmall); }
-        else { if (large) HSS_SMALL(uint64_t, false, kCapLarge); else HSS_SMALL(uint64_t, false, kCapSmall); }
+    {
+        const dim3 grid(msd_segs * 256u + a.n_direct);
+        prof.begin(s);
+        if (a.key_bytes == 4)
+            launch_small_any<uint32_t>(pay, large, false, grid, s, a, a.sb_start, a.sb_len, bits, a.ov,
+                                       level1_jobs<uint32_t>(a, msd_segs, kb));
+        else
+            launch_small_any<uint64_t>(pay, large, false, grid, s, a, a.sb_start, a.sb_len, bits, a.ov,
+                                       level1_jobs<uint64_t>(a, msd_segs, kb));
+        prof.end(kProfSmallSort, s, a.total_len * 2 * (a.key_bytes + (pay ? 8 : 0)));
     }
-#undef HSS_SMALL
-    prof.end(kProfSmallSort, s, a.total_len * 2 * (a.key_bytes + (pay ? 8 : 0)));
-    // 3. oversize sub-buckets: LSD passes in HBM over a compact list
-    hipLaunchKernelGGL(ov_tiles_kernel, dim3(1), dim3(1024), 0, s, a.ov, a.sl);
-    hipLaunchKernelGGL(ov_fill_kernel, dim3(1024), dim3(256), 0, s, a.ov);
-    e = hipGetLastError();
+    e = read_summary(a.ov, a.sl, a.eq, host, s);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(host.pinned, a.ov.summary, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return e;
-    const uint32_t E = host.pinned[0], T = host.pinned[1], SL = host.pinned[2];
+    uint32_t E = host.pinned[0], T = host.pinned[1];
     host.last_oversize = E;
+    host.last_levels = 0;
+    // 3. deeper levels: every entry above the capacity takes an MSD pass on
+    //    the 8 bits below its top, alternating between the MSD buffer and the
+    //    output; each level lowers the top by at least 8 bits, so at most
+    //    kb / 8 levels follow
+    OversizeList cur = a.ov, nxt = a.ov2;
+    while (E > 0) {
+        if (++host.last_levels > (uint32_t)kb / 8) return hipErrorUnknown;
+        e = grow(&host.fb_counts, &host.fb_words, (uint64_t)T * 256);
+        if (e == hipSuccess) {
+            uint64_t c0 = host.fb_sb;
+            e = grow(&host.fb_sb_start, &c0, (uint64_t)E * 256 + 1);
+            if (e == hipSuccess) e = grow(&host.fb_sb_len, &host.fb_sb, (uint64_t)E * 256 + 1);
+        }
+        if (e != hipSuccess) return e;
+        const uint64_t kt = (uint64_t)(uintptr_t)a.keys_tmp, ko = (uint64_t)(uintptr_t)a.keys_out;
+        const uint64_t vt = pay ? (uint64_t)(uintptr_t)a.vals_tmp : 0, vo = pay ? (uint64_t)(uintptr_t)a.vals_out : 0;
+        hipLaunchKernelGGL(level_prep_kernel, dim3(min((E + 255) / 256, 1024u)), dim3(256), 0, s, cur, a.lw,
+                           kt, ko, vt, vo, a.key_bytes);
+        RadixPass ps;
+        ps.key_bytes = a.key_bytes;
+        ps.keys_in = a.keys_tmp;        // unused: every entry has its source
+        ps.vals_in = pay ? a.vals_tmp : nullptr;
+        ps.keys_out = a.keys_out;       // unused: every entry has its destination
+        ps.vals_out = pay ? a.vals_out : nullptr;
+        ps.map.beg = cur.beg;
+        ps.map.end = cur.end;
+        ps.map.base = cur.base;
+        ps.map.tile_seg = cur.tile_seg;
+        ps.map.tile0 = cur.tile0;
+        ps.map.src = cur.src;
+        ps.map.vsrc = pay ? cur.vsrc : nullptr;
+        ps.map.dst = a.lw.dst;
+        ps.map.vdst = pay ? a.lw.vdst : nullptr;
+        ps.map.skip = a.lw.skip;
+        ps.num_segs = E;
+        ps.num_tiles = T;
+        ps.seg_shift = a.lw.shift;
+        ps.counts = host.fb_counts;
+        ps.sb_start = host.fb_sb_start;
+        ps.sb_len = host.fb_sb_len;
+        ps.total_len = (uint64_t)T * kSortTile;   // bound for the byte counts
+        ps.prof = a.prof;
+        ps.any_order = !pay;
+        ps.has_payload = pay;
+        ps.and_mask = a.lw.and_mask;
+        ps.or_mask = a.lw.or_mask;
+        e = radix_count_scan(ps, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(ov_reset_kernel, dim3(1), dim3(1), 0, s, nxt, SlowList{}, EqualList{});
+        hipLaunchKernelGGL(count_reset_kernel, dim3(1), dim3(1), 0, s, a.pj.count);
+        DecideView v;
+        v.beg = cur.beg;
+        v.end = cur.end;
+        v.base = cur.base;
+        v.seg = cur.seg;
+        v.loc = cur.loc;
+        v.src = cur.src;
+        v.vsrc = cur.vsrc;
+        v.key_bytes = a.key_bytes;
+        v.count = cur.count;
+        v.capacity = cur.capacity;
+        hipLaunchKernelGGL(level_decide_kernel, dim3(E), dim3(256), 0, s, v, a.lw, host.fb_sb_start,
+                           host.fb_sb_len, nxt, a.eq, a.pj, cap);
+        e = radix_scatter(ps, s);
+        if (e != hipSuccess) return e;
+        // packed jobs: an entry of n keys gives at most n / (cap/2) jobs of
+        // one large sub-bucket and n / (cap/2) + 1 windows
+        const uint64_t job_bound = 4 * ((uint64_t)T * kSortTile) / cap + E;
+        const dim3 grid((uint32_t)std::min<uint64_t>(job_bound, a.pj.capacity));
+        prof.begin(s);
+        if (a.key_bytes == 4)
+            launch_small_any<uint32_t>(pay, large, pay, grid, s, a, host.fb_sb_start, host.fb_sb_len, 0, nxt,
+                                       level_jobs<uint32_t>(a, cur, grid.x));
+        else
+            launch_small_any<uint64_t>(pay, large, pay, grid, s, a, host.fb_sb_start, host.fb_sb_len, 0, nxt,
+                                       level_jobs<uint64_t>(a, cur, grid.x));
+        prof.end(kProfSmallSort, s, ps.total_len * 2 * (a.key_bytes + (pay ? 8 : 0)));
+        e = read_summary(nxt, a.sl, a.eq, host, s);
+        if (e != hipSuccess) return e;
+        E = host.pinned[0];
+        T = host.pinned[1];
+        const OversizeList t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    const uint32_t SL = host.pinned[2], EQ = host.pinned[3];
     host.last_slow = SL;
+    // 4. sub-buckets with a large group: LSD passes in LDS (from the MSD buffer)
     if (SL > 0) {
         const dim3 g(SL);
         if (a.key_bytes == 4) {
-            if (pay) hipLaunchKernelGGL((lds_lsd_kernel<uint32_t, true>), g, dim3(kT), 0, s, (const uint32_t*)a.keys_tmp, a.vals_tmp, (uint32_t*)a.keys_out, a.vals_out, a.sl, a.fences);
-            else hipLaunchKernelGGL((lds_lsd_kernel<uint32_t, false>), g, dim3(kT), 0, s, (const uint32_t*)a.keys_tmp, nullptr, (uint32_t*)a.keys_out, nullptr, a.sl, a.fences);
+            if (large) launch_lds_lsd<uint32_t, kCapLarge>(pay, g, s, a);
+            else launch_lds_lsd<uint32_t, kCapSmall>(pay, g, s, a);
         } else {
-            if (pay) hipLaunchKernelGGL((lds_lsd_kernel<uint64_t, true>), g, dim3(kT), 0, s, (const uint64_t*)a.keys_tmp, a.vals_tmp, (uint64_t*)a.keys_out, a.vals_out, a.sl, a.fences);
-            else hipLaunchKernelGGL((lds_lsd_kernel<uint64_t, false>), g, dim3(kT), 0, s, (const uint64_t*)a.keys_tmp, nullptr, (uint64_t*)a.keys_out, nullptr, a.sl, a.fences);
+            if (large) launch_lds_lsd<uint64_t, kCapLarge>(pay, g, s, a);
+            else launch_lds_lsd<uint64_t, kCapSmall>(pay, g, s, a);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (E == 0) return hipSuccess;
-    const uint64_t words = (uint64_t)T * 256;
-    if (words > host.fb_words) {
-        if (host.fb_counts) (void)hipFree(host.fb_counts);
-        host.fb_counts = nullptr;
-        host.fb_words = 0;
-        e = hipMalloc((void**)&host.fb_counts, words * 4);
-        if (e != hipSuccess) return e;
-        host.fb_words = words;
-    }
-    RadixPass fb;
-    fb.key_bytes = a.key_bytes;
-    fb.map.beg = a.ov.beg;
-    fb.map.end = a.ov.end;
-    fb.map.tile_seg = a.ov.tile_seg;
-    fb.map.tile0 = a.ov.tile0;
-    fb.map.base = a.ov.base;
-    fb.num_segs = E;
-    fb.num_tiles = T;
-    fb.counts = host.fb_counts;
-    fb.total_len = 0;
-    fb.prof = a.prof;
-    const int passes = (bits + 7) / 8;   // odd for 32- and 64-bit keys: ends in keys_out
-    for (int i = 0; i < passes; ++i) {
-        const bool from_tmp = (i % 2) == 0;
-        fb.keys_in = from_tmp ? a.keys_tmp : a.keys_out;
-        fb.vals_in = from_tmp ? a.vals_tmp : a.vals_out;
-        fb.keys_out = from_tmp ? a.keys_out : a.keys_tmp;
-        fb.vals_out = from_tmp ? a.vals_out : a.vals_tmp;
-        if (!pay) { fb.vals_in = nullptr; fb.vals_out = nullptr; }
-        fb.shift = 8 * i;
-        e = radix_pass(fb, s);
-        if (e != hipSuccess) return e;
-    }
-    if (a.fences.key) {
+    // 5. ranges of equal keys: into the output, with their fences
+    if (EQ > 0) {
+        const dim3 g(min(EQ, 4096u));
         if (a.key_bytes == 4)
-            hipLaunchKernelGGL(ov_fence_kernel<uint32_t>, dim3(1024), dim3(256), 0, s, (const uint32_t*)a.keys_out, a.ov, a.fences);
+            hipLaunchKernelGGL(equal_copy_kernel<uint32_t>, g, dim3(256), 0, s, (uint32_t*)a.keys_out, pay ? a.vals_out : nullptr, a.eq, a.fences);
         else
-            hipLaunchKernelGGL(ov_fence_kernel<uint64_t>, dim3(1024), dim3(256), 0, s, (const uint64_t*)a.keys_out, a.ov, a.fences);
+            hipLaunchKernelGGL(equal_copy_kernel<uint64_t>, g, dim3(256), 0, s, (uint64_t*)a.keys_out, pay ? a.vals_out : nullptr, a.eq, a.fences);
         e = hipGetLastError();
     }
     return e;
@@ -609,20 +1042,26 @@ hipError_t write_fences(const void* keys, int key_bytes, uint32_t num_segs, cons
     return hipGetLastError();
 }
 
-uint64_t oversize_capacity(uint32_t num_segs, uint64_t total_len) {
-    const uint64_t by_count = (uint64_t)num_segs * 256;
-    const uint64_t by_size = total_len / (kCapSmall + 1) + 1;
-    return by_count < by_size ? by_count : by_size;
+// Entries of the oversize and equal lists are disjoint ranges of more than
+// kCapSmall keys; slow-list entries disjoint ranges of more than kGroupMax.
+uint64_t oversize_capacity(uint64_t total_len) { return total_len / (kCapSmall + 1) + 1; }
+
+uint64_t slow_capacity(uint64_t total_len) { return total_len / (kGroupMax + 1) + 1; }
+
+uint64_t oversize_tile_capacity(uint64_t total_len) {
+    return total_len / kSortTile + oversize_capacity(total_len) + 1;
 }
 
-uint64_t slow_capacity(uint32_t num_segs, uint64_t total_len) {
-    const uint64_t by_count = (uint64_t)num_segs * 256;
-    const uint64_t by_size = total_len / (kGroupMax + 1) + 1;
-    return by_count < by_size ? by_count : by_size;
+// Per-entry arrays serve level 1 (every MSD segment) and the deeper levels.
+// Packed jobs: per entry at most 4 n / kCapSmall + 1, and at most
+// oversize_capacity() entries.
+uint64_t packed_capacity(uint64_t total_len) {
+    return 4 * total_len / kCapSmall + oversize_capacity(total_len) + 1;
 }
 
-uint64_t oversize_tile_capacity(uint32_t num_segs, uint64_t total_len) {
-    return total_len / kSortTile + oversize_capacity(num_segs, total_len) + 1;
+uint64_t level_capacity(uint32_t num_segs, uint64_t total_len) {
+    const uint64_t o = oversize_capacity(total_len);
+    return num_segs > o ? num_segs : o;
 }
 
 }  // namespace hss
