@@ -43,6 +43,9 @@ typedef unsigned __int128 u128;
 
 constexpr uint32_t kMaxRestarts = 8;     // capacity growths per call
 constexpr uint32_t kMaxRateRounds = 64;  // rounds kept in the rate table
+// Expected first-round probes above which they are sorted by the segmented
+// sort rather than ranked pairwise inside their interval.
+constexpr uint64_t kBigRound = 16384;
 
 struct RoundRecord {
     uint64_t domain = 0, m = 0;
@@ -176,6 +179,15 @@ struct Engine {
     uint64_t* direct_src = nullptr;
     uint64_t* direct_vsrc = nullptr;
 
+    uint64_t counts_words = 0;
+
+    // round 1 of a plan whose first sample is large (one-round HSS, a full
+    // sample): its probes are sorted by the segmented sort, in scratch
+    // grown on demand
+    bool big_first = false;
+    void* psort_mem = nullptr;
+    uint64_t psort_cap = 0;
+
     // probes and count matrix, grown on demand
     void* probe_mem = nullptr;
     size_t probe_bytes = 0;
@@ -193,6 +205,7 @@ struct Engine {
         (void)hipSetDevice(device);
         (void)hipDeviceSynchronize();
         if (probe_mem) (void)hipFree(probe_mem);
+        if (psort_mem) (void)hipFree(psort_mem);
         if (cmat) (void)hipFree(cmat);
         if (hh.fb_counts) (void)hipFree(hh.fb_counts);
         if (hh.fb_sb_start) (void)hipFree(hh.fb_sb_start);
@@ -346,9 +359,16 @@ void build_layout(Engine& E, Layout& L) {
             L.thresh[(size_t)I * E.J + j - 1] = t;
             L.all[(size_t)I * E.J + j - 1] = (uint8_t)al;
         }
+    // the first round samples every key at the first rate: its expected
+    // probe count decides how its probes are put in order
+    if (B == 1 && E.J >= 1) {
+        const double m1 = L.all[0] ? (double)E.ih[0].n : (double)E.ih[0].n * (double)L.thresh[0] / 4294967296.0;
+        E.big_first = m1 > (double)kBigRound;
+    }
 }
 
 uint64_t tiles_of(uint64_t len) { return (len + kSortTile - 1) / kSortTile; }
+
 
 size_t layout(Engine& E, char* base) {
     Arena ar;
@@ -372,6 +392,7 @@ size_t layout(Engine& E, char* base) {
     uint64_t tiles = E.listed ? E.msd_tiles : (uint64_t)S * tiles_of(E.max_seg);
     if (!E.listed) tiles = std::max(tiles, (uint64_t)S * tiles_of(E.max_bucket));
     E.counts = ar.take<uint32_t>(tiles * 256 + 256);
+    E.counts_words = tiles * 256 + 256;
     RoundArgs& r = E.ra;
     r.settled = ar.take<uint32_t>(Q);
     r.chi = ar.take<uint64_t>(Q);
@@ -698,6 +719,76 @@ void record_round(Engine& E, RoundRecord& rec, uint32_t j) {
 
 // Splitter rounds of every instance on the locally sorted buffer B; leaves
 // chi in chi_all and in every instance's offsets.
+// Round 1 of a plan whose first sample is large (one-round HSS, a full
+// sample): the probes of its one interval are put in (key, tag) order by two
+// stable segmented sorts, by tag and then by key, instead of the pairwise
+// ranking inside the interval.
+hss_status big_first_round(Engine& E, hipStream_t s) {
+    RoundArgs& r = E.ra;
+    HIP_TRY(launch_round_head(r, 1, s));
+    hss_status st = read_counters(E, s, 0);
+    if (st != HSS_OK) return st;
+    const RoundCounters c = *E.h_ctr;
+    const uint64_t m = c.m_stored;
+    const uint32_t nivl = c.n_ivl;
+    const uint32_t msd_segs = E.listed ? E.n_msd : E.S;
+    const bool fits = !c.overflow && m > 0 && nivl >= 1 && m <= E.n_tot &&
+                      (uint64_t)nivl * tiles_of(m) * 256 + 256 <= E.counts_words &&
+                      nivl <= msd_segs;
+    if (!fits) {   // an overrun (the caller regrows) or an unexpected shape
+        HIP_TRY(launch_round_tail(r, s, false, &E.prof));
+        return HSS_OK;
+    }
+    const uint64_t need = 4 * m + nivl + 1;
+    if (need > E.psort_cap) {
+        if (E.psort_mem) HIP_TRY(hipFree(E.psort_mem));
+        E.psort_mem = nullptr;
+        E.psort_cap = 0;
+        const uint64_t want = need + need / 4;
+        HIP_TRY(hipMalloc(&E.psort_mem, want * sizeof(uint64_t)));
+        E.psort_cap = want;
+    }
+    uint64_t* x0 = (uint64_t*)E.psort_mem;
+    uint64_t* x1 = x0 + m;
+    uint64_t* y0 = x1 + m;
+    uint64_t* y1 = y0 + m;
+    uint64_t* off = y1 + m;
+    HIP_TRY(launch_probe_offsets(r, off, s));
+    HybridSort hs;
+    hs.key_bytes = 8;
+    hs.seg_off = off;
+    hs.num_segs = nivl;
+    hs.max_seg_len = m;
+    hs.total_len = m;
+    hs.counts = E.counts;
+    hs.sb_start = E.sb_start;
+    hs.sb_len = E.sb_len;
+    hs.ov = E.ov;
+    hs.ov2 = E.ov2;
+    hs.eq = E.eq;
+    hs.lw = E.lw;
+    hs.pj = E.pj;
+    hs.sl = E.sl;
+    hs.has_payload = true;
+    hs.keys_tmp = y0;
+    hs.vals_tmp = y1;
+    // by tag (tags are distinct) ...
+    hs.keys_in = r.g_tag;
+    hs.vals_in = r.g_key;
+    hs.keys_out = x0;
+    hs.vals_out = x1;
+    HIP_TRY(hybrid_sort(hs, s, E.hh));
+    // ... then stably by key: (key, tag) order
+    hs.keys_in = x1;
+    hs.vals_in = x0;
+    hs.keys_out = r.ps_key;
+    hs.vals_out = r.ps_tag;
+    HIP_TRY(hybrid_sort(hs, s, E.hh));
+    HIP_TRY(launch_probe_finish(r, s));
+    HIP_TRY(launch_round_tail(r, s, true, &E.prof));
+    return HSS_OK;
+}
+
 hss_status determine_splitters(Engine& E, hipStream_t s) {
     RoundArgs& r = E.ra;
     E.trace.clear();
@@ -717,7 +808,12 @@ hss_status determine_splitters(Engine& E, hipStream_t s) {
             const uint32_t upto = std::min(j + chunk, stop);
             while (j < upto) {
                 ++j;
-                HIP_TRY(launch_round(r, j, s, &E.prof));
+                if (j == 1 && E.big_first) {
+                    const hss_status sb = big_first_round(E, s);
+                    if (sb != HSS_OK) return sb;
+                } else {
+                    HIP_TRY(launch_round(r, j, s, &E.prof));
+                }
             }
             hss_status st = read_counters(E, s, tracing ? 0u : j);
             if (st != HSS_OK) return st;

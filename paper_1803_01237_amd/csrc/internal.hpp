@@ -486,6 +486,14 @@ hipError_t launch_round_init(const RoundArgs& a, hipStream_t s);
 hipError_t launch_round(const RoundArgs& a, uint32_t j, hipStream_t s, Profiler* prof);
 // chi of every instance into its offsets array and into chi_all (Q entries).
 hipError_t launch_finalize(const RoundArgs& a, uint64_t* chi_all, hipStream_t s);
+// A round in two halves: intervals, sampling, probe offsets and grouping by
+// interval (g_key, g_tag); then ordering (skipped when the caller has put
+// every interval's probes in (key, tag) order into ps_key / ps_tag and run
+// launch_probe_finish), ranks, reduction and settling.
+hipError_t launch_round_head(const RoundArgs& a, uint32_t j, hipStream_t s);
+hipError_t launch_round_tail(const RoundArgs& a, hipStream_t s, bool probes_sorted, Profiler* prof);
+hipError_t launch_probe_offsets(const RoundArgs& a, uint64_t* out, hipStream_t s);
+hipError_t launch_probe_finish(const RoundArgs& a, hipStream_t s);
 // The per-call record of one instance, written on the stream (no host copy).
 hipError_t launch_set_run(const InstRun& r, InstRun* dst, hipStream_t s);
 // Caller buffers per segment: device addresses of the input keys (and

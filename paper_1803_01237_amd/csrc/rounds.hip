@@ -641,6 +641,37 @@ __global__ __launch_bounds__(256) void rank_kernel(RoundArgs a) {
     }
 }
 
+// Sorted-probe path (large rounds sorted by the segmented sort): the
+// interval offsets as 64-bit segment bounds for the sort.
+__global__ void probe_offsets_kernel(RoundArgs a, uint64_t* __restrict__ out) {
+    const uint32_t n = a.ctr->n_ivl;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k <= n; k += gridDim.x * blockDim.x)
+        out[k] = a.ivl_poff[k];
+}
+
+// Sorted-probe path: the probes are in (key, tag) order inside their
+// interval's range; each gets its interval, its segment and a cleared rank
+// sum, as the ordering kernel would give them.
+__global__ void probe_finish_kernel(RoundArgs a) {
+    if (halted(a)) return;
+    const uint64_t m = a.ctr->m_stored;
+    const uint32_t n_ivl = a.ctr->n_ivl;
+    for (uint64_t pos = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; pos < m;
+         pos += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = last_le(a.ivl_poff, n_ivl, (uint32_t)pos);
+        const InstDesc& D = a.inst[a.ivl_inst[k]];
+        const uint64_t tag = a.ps_tag[pos];
+        uint32_t lo = 0, hi = D.p;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.seg_off[D.seg0 + mid] - D.pos0 <= tag) lo = mid; else hi = mid;
+        }
+        a.ps_ivl[pos] = k;
+        a.ps_seg[pos] = D.seg0 + lo;
+        a.pr_rank[pos] = 0;
+    }
+}
+
 // The reduction of section 5.2: R(e) is the sum over the instance's segments
 // of c_s(e), the column sums of its count matrix.  Tiles of 256 sorted probes
 // x kReduceRows segments; the partial sums are integers, so the order of the
@@ -802,10 +833,19 @@ hipError_t launch_round_init(const RoundArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// at most one interval per splitter (rows minus the two ends of every instance)
+static uint32_t interval_bound(const RoundArgs& a) {
+    return a.n_rows > 2 * a.n_inst ? a.n_rows - 2 * a.n_inst : 1u;
+}
+
 hipError_t launch_round(const RoundArgs& a, uint32_t j, hipStream_t s, Profiler* prof) {
-    (void)prof;
-    // at most one interval per splitter (rows minus the two ends of every instance)
-    const uint32_t ivl_bound = a.n_rows > 2 * a.n_inst ? a.n_rows - 2 * a.n_inst : 1u;
+    const hipError_t e = launch_round_head(a, j, s);
+    if (e != hipSuccess) return e;
+    return launch_round_tail(a, s, false, prof);
+}
+
+hipError_t launch_round_head(const RoundArgs& a, uint32_t j, hipStream_t s) {
+    const uint32_t ivl_bound = interval_bound(a);
     hipLaunchKernelGGL(leaders_kernel, dim3(1), dim3(kScanT), 0, s, a, j);
     hipLaunchKernelGGL(slices_kernel, dim3(ivl_bound), dim3(kT), 0, s, a);
     hipLaunchKernelGGL(ivl_scan_kernel, dim3(1), dim3(kScanT), 0, s, a);
@@ -819,8 +859,15 @@ hipError_t launch_round(const RoundArgs& a, uint32_t j, hipStream_t s, Profiler*
     }
     hipLaunchKernelGGL(probe_scan_kernel, dim3(1), dim3(kScanT), 0, s, a, j);
     hipLaunchKernelGGL(group_kernel, dim3(grid_for(a.cap, kT, 4096)), dim3(kT), 0, s, a);
-    const uint64_t tiles_bound = (a.cap + kOrderLanes - 1) / kOrderLanes + ivl_bound;
-    hipLaunchKernelGGL(order_kernel, dim3((unsigned)tiles_bound), dim3(kOrderThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_tail(const RoundArgs& a, hipStream_t s, bool probes_sorted, Profiler* prof) {
+    (void)prof;
+    if (!probes_sorted) {
+        const uint64_t tiles_bound = (a.cap + kOrderLanes - 1) / kOrderLanes + interval_bound(a);
+        hipLaunchKernelGGL(order_kernel, dim3((unsigned)tiles_bound), dim3(kOrderThreads), 0, s, a);
+    }
     if (a.n_chunks > 0) {
         if (a.key_bytes == 4) hipLaunchKernelGGL(rank_kernel<uint32_t>, dim3(a.n_chunks), dim3(256), 0, s, a);
         else hipLaunchKernelGGL(rank_kernel<uint64_t>, dim3(a.n_chunks), dim3(256), 0, s, a);
@@ -829,6 +876,16 @@ hipError_t launch_round(const RoundArgs& a, uint32_t j, hipStream_t s, Profiler*
     hipLaunchKernelGGL(reduce_kernel, rgrid, dim3(256), 0, s, a);
     if (a.p_max > 256) hipLaunchKernelGGL(settle_kernel<1024>, dim3(a.n_rows), dim3(1024), 0, s, a);
     else hipLaunchKernelGGL(settle_kernel<256>, dim3(a.n_rows), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_offsets(const RoundArgs& a, uint64_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(probe_offsets_kernel, dim3(grid_for(interval_bound(a) + 1, kT)), dim3(kT), 0, s, a, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_finish(const RoundArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(probe_finish_kernel, dim3(grid_for(a.cap, kT, 4096)), dim3(kT), 0, s, a);
     return hipGetLastError();
 }
 

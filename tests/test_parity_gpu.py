@@ -139,6 +139,10 @@ OPTION_CASES = [
     ("uniform32", 50_000, 10, 10 / 50_000, 23, 32, False, 0),   # eps = p/N: exact
     ("GAUSS", 8192, 64, 64 / 8192, 24, 64, True, 0),      # exact, 5 rounds
     ("uniform64", 20_000, 10, 10 / 20_000, 25, 64, False, 1),   # exact with k = 1
+    # first samples above 16384 probes: sorted by the segmented sort
+    ("uniform64", 1 << 20, 64, 0.02, 26, 64, True, 1),
+    ("SKEW2", 1 << 19, 128, 0.02, 27, 64, False, 1),
+    ("uniform32", 1 << 19, 128, 0.02, 28, 32, False, 1),
 ]
 
 
