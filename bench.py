@@ -212,6 +212,117 @@ def sweep_bench(plan, keys, n, p, eps, hseed, steps):
     return out
 
 
+def served_bench(count, mults, check_every):
+    """The served workload: u64 requests with a payload arriving as a Poisson
+    process, served by the library's request server.  The rate is set from
+    the plain-path capacity (keys per second of one plan per request: create,
+    partition, release) times each multiplier.  Latency is completion minus
+    the scheduled arrival; every check_every-th request is compared with its
+    solo run."""
+    import torch
+    import paper_1803_01237_amd as hss
+    import synth
+    dev = torch.device("cuda:0")
+    shapes = synth.served_shapes(count)
+    total = sum(sh[0] for sh in shapes)
+    mean_n = total / count
+
+    def inputs(sh):
+        return synth.device_keys(sh[0], sh[3], dev), torch.arange(sh[0], dtype=torch.int64, device=dev)
+
+    # plain-path capacity on the first requests
+    cap_keys, cap_s = 0, 0.0
+    for sh in shapes[:min(48, count)]:
+        keys, vals = inputs(sh)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with hss.Plan(sh[0], sh[1], sh[2], payload=True) as pl:
+            pl.partition(keys, sh[4], vals)
+            torch.cuda.synchronize()
+        cap_s += time.perf_counter() - t0
+        cap_keys += sh[0]
+    capacity = cap_keys / cap_s
+    log(f"[bench] served: {count} requests, {total} keys; plain capacity {capacity / 1e9:.2f} Gkeys/s")
+    runs = []
+    window = 32
+    inflight = 96
+    for mult in mults:
+        rate = mult * capacity / mean_n                 # requests per second
+        arrivals = np.cumsum(np.random.default_rng(5).exponential(1.0 / rate, count))
+        lat, lag, kept = [], [], []
+        with hss.Server() as srv:
+            t0 = srv.clock() + 0.05
+            pending = {}
+            t_last = 0.0
+
+            def drain(block):
+                nonlocal t_last
+                for t in list(pending):
+                    r = srv.wait(t) if block else srv.poll(t)
+                    if r is None:
+                        continue
+                    i, arr = pending.pop(t)
+                    lat.append(r.t_done - arr)
+                    t_last = max(t_last, r.t_done)
+                    if i % check_every == 0:
+                        kept.append((i, r))
+
+            for w0 in range(0, count, window):
+                # inputs of the next window, made before their arrival times
+                batch = [inputs(sh) for sh in shapes[w0:w0 + window]]
+                torch.cuda.synchronize()
+                for j, (keys, vals) in enumerate(batch):
+                    i = w0 + j
+                    sh = shapes[i]
+                    arr = t0 + arrivals[i]
+                    while srv.clock() < arr:
+                        drain(False)
+                    # a client with at most `inflight` requests outstanding:
+                    # above the server's capacity the arrivals fall behind
+                    while len(pending) >= inflight:
+                        oldest = next(iter(pending))
+                        r = srv.wait(oldest)
+                        i0, a0 = pending.pop(oldest)
+                        lat.append(r.t_done - a0)
+                        t_last = max(t_last, r.t_done)
+                        if i0 % check_every == 0:
+                            kept.append((i0, r))
+                    lag.append(max(0.0, srv.clock() - arr))
+                    t = srv.submit(keys, sh[1], sh[2], sh[4], vals, sync=False)
+                    pending[t] = (i, arr)
+                del batch
+            drain(True)
+            st = srv.stats()
+        makespan = t_last - (t0 + arrivals[0])
+        # each kept result against its solo run
+        same = True
+        for i, r in kept:
+            sh = shapes[i]
+            keys, vals = inputs(sh)
+            with hss.Plan(sh[0], sh[1], sh[2], payload=True) as pl:
+                ko, vo, off = pl.partition(keys, sh[4], vals)
+                torch.cuda.synchronize()
+                same = same and torch.equal(off, r.offsets) and torch.equal(ko, r.keys_out) \
+                    and torch.equal(vo, r.vals_out)
+        del kept
+        lat_ms = np.array(lat) * 1e3
+        runs.append({"rate_x_capacity": mult, "requests_per_s": round(rate, 1),
+                     "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                     "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+                     "throughput_gkeys_s": round(total / makespan / 1e9, 3),
+                     "makespan_s": round(makespan, 3), "batches": st["batches"],
+                     "mean_requests_per_batch": round(count / max(st["batches"], 1), 2),
+                     "submit_lag_p99_ms": round(float(np.percentile(np.array(lag) * 1e3, 99)), 3),
+                     "checked_against_solo": len(range(0, count, check_every)),
+                     "all_equal": bool(same)})
+        log(f"[bench] served x{mult}: p50 {runs[-1]['p50_ms']} ms, p99 {runs[-1]['p99_ms']} ms, "
+            f"{runs[-1]['throughput_gkeys_s']} Gkeys/s, {st['batches']} batches")
+    return {"requests": count, "keys": total, "plain_capacity_gkeys_s": round(capacity / 1e9, 3),
+            "shape": "N = floor(2^U(14,26)) u64 keys + u64 payload, p = clamp(floor(e^U(ln 64, ln 2049)), "
+                     "64, 2048), eps in {0.02, 0.05}, keys drawn on the device (torch generator per request), "
+                     "Poisson arrivals", "runs": runs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +341,11 @@ def main():
                     help="steps per plan option (one round, exact splitting); 0 to skip")
     ap.add_argument("--sweep-steps", type=int, default=3,
                     help="steps per distribution of the sweep; 0 to skip")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the served workload (0 to skip)")
+    ap.add_argument("--serve-rates", default="0.5,0.7,1.0,2.0,4.0",
+                    help="arrival rates as multiples of the plain-path capacity")
+    ap.add_argument("--serve-check-every", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 2 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -346,6 +462,8 @@ def main():
     del keys, kout, vout, vals
     torch.cuda.empty_cache()
     batched = batched_bench(args.batch_steps, args.batch_count) if args.batch_count > 0 else None
+    served = (served_bench(args.serve_requests, [float(x) for x in args.serve_rates.split(",")],
+                           args.serve_check_every) if args.serve_requests > 0 else None)
 
     cpu = None
     if args.cpu_sample > 0:
@@ -366,6 +484,7 @@ def main():
         "hss_sort_ms": None if sort_ms is None else round(sort_ms, 4),
         "hss_sort_gkeys_s": None if sort_ms is None else round(n / (sort_ms * 1e-3) / 1e9, 3),
         "batched": batched,
+        "served": served,
         "plan_options": options,
         "distributions": sweep,
     }

@@ -235,6 +235,76 @@ hss_status hss_batch_profile_reset(hss_batch_t batch);
 hss_status hss_batch_profile_read(hss_batch_t batch, uint32_t family, double* ms,
                                   uint64_t* launches, uint64_t* bytes);
 
+/*
+ * Server: requests of any shape arriving over time, each an hss_partition of
+ * its own input (the served workload of section 7's setting: independent
+ * sorts submitted by clients).  A worker thread of the server takes the
+ * requests queued when it becomes free -- in submission order, of one key
+ * type and payload choice, within the batch limits -- and runs them as one
+ * batch on a stream of its own, with device memory from a cache of blocks
+ * kept between batches (no allocation once the cache covers the load).
+ * Every request's outputs equal those of hss_partition of a plan with its
+ * (N, p, eps, key type, payload) for its seed and input.
+ */
+typedef struct hss_server_s* hss_server_t;
+
+typedef struct {
+    uint64_t n;                 /* keys N, 1 <= p <= N                      */
+    uint32_t p;                 /* buckets                                  */
+    hss_key_type key_type;      /* HSS_U32 or HSS_U64                       */
+    double eps;                 /* 0 < eps < 1                              */
+    uint64_t seed;              /* Philox stream of the request's rounds    */
+    const void* keys_in;        /* N keys on the device, fully written when */
+                                /* submitted (the server's stream does not  */
+                                /* wait on the writer's)                    */
+    const uint64_t* vals_in;    /* N payload words, or NULL                 */
+    void* keys_out;             /* N keys, bucket order as hss_partition    */
+    uint64_t* vals_out;         /* N payload words iff vals_in              */
+    uint64_t* offsets;          /* p+1 words: chi                           */
+} hss_request;
+
+/*
+ * hss_server_create -- start a server on the current device.
+ *   max_batch_keys      keys per batch (0: 2^30; at most 2^32 - 1); a single
+ *                       request larger than this still runs, alone
+ *   max_batch_requests  requests per batch (0: 1024)
+ */
+hss_status hss_server_create(hss_server_t* out, uint64_t max_batch_keys,
+                             uint32_t max_batch_requests);
+
+/* Finish every submitted request, stop the worker and release the server's
+ * memory.  NULL is ok. */
+void hss_server_destroy(hss_server_t server);
+
+/*
+ * hss_server_submit -- queue a request; *ticket names it.  The buffers stay
+ * owned by the caller and must remain valid until the request is done.
+ * Argument errors (shape, pointers, alignment, overlap) are returned here and
+ * nothing is queued; device errors come back as the request's result.
+ */
+hss_status hss_server_submit(hss_server_t server, const hss_request* req, uint64_t* ticket);
+
+/*
+ * hss_server_poll -- *done = 1 when the request has finished (its outputs are
+ * written and visible to any stream); then *result is its status and
+ * t_submit / t_done its submission and completion times on
+ * hss_server_clock, and the ticket is retired.  *done = 0: still queued or
+ * running.  Unknown tickets: HSS_ERR_INVALID_ARG.  Output pointers may be NULL.
+ */
+hss_status hss_server_poll(hss_server_t server, uint64_t ticket, int* done, hss_status* result,
+                           double* t_submit, double* t_done);
+
+/* hss_server_wait -- as hss_server_poll, blocking until the request is done. */
+hss_status hss_server_wait(hss_server_t server, uint64_t ticket, hss_status* result,
+                           double* t_submit, double* t_done);
+
+/* Seconds on the server's monotonic clock (the clock of t_submit, t_done). */
+double hss_server_clock(void);
+
+/* Batches run, requests finished and their keys, since creation. */
+hss_status hss_server_stats(hss_server_t server, uint64_t* batches, uint64_t* requests,
+                            uint64_t* keys);
+
 const char* hss_status_string(hss_status status);
 
 /* Message of the last failure on the calling thread ("" if none). */

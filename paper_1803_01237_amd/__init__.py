@@ -44,6 +44,8 @@ EXPORTS = [
     "hss_profile", "hss_profile_reset", "hss_profile_read",
     "hss_batch_plan", "hss_batch_destroy", "hss_batch_workspace_bytes", "hss_batch_partition",
     "hss_batch_profile", "hss_batch_profile_reset", "hss_batch_profile_read",
+    "hss_server_create", "hss_server_destroy", "hss_server_submit", "hss_server_poll",
+    "hss_server_wait", "hss_server_clock", "hss_server_stats",
     "hss_status_string", "hss_last_error",
 ]
 
@@ -119,6 +121,29 @@ _lib.hss_batch_profile_reset.argtypes = [_vp]
 _lib.hss_batch_profile_reset.restype = C.c_int
 _lib.hss_batch_profile_read.argtypes = [_vp, _u32, _vp, _vp, _vp]
 _lib.hss_batch_profile_read.restype = C.c_int
+
+
+class _Request(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("p", C.c_uint32), ("key_type", C.c_int), ("eps", C.c_double),
+                ("seed", C.c_uint64), ("keys_in", C.c_void_p), ("vals_in", C.c_void_p),
+                ("keys_out", C.c_void_p), ("vals_out", C.c_void_p), ("offsets", C.c_void_p)]
+
+
+_lib.hss_server_create.argtypes = [C.POINTER(_vp), _u64, _u32]
+_lib.hss_server_create.restype = C.c_int
+_lib.hss_server_destroy.argtypes = [_vp]
+_lib.hss_server_destroy.restype = None
+_lib.hss_server_submit.argtypes = [_vp, C.POINTER(_Request), C.POINTER(_u64)]
+_lib.hss_server_submit.restype = C.c_int
+_lib.hss_server_poll.argtypes = [_vp, _u64, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                 C.POINTER(_dbl), C.POINTER(_dbl)]
+_lib.hss_server_poll.restype = C.c_int
+_lib.hss_server_wait.argtypes = [_vp, _u64, C.POINTER(C.c_int), C.POINTER(_dbl), C.POINTER(_dbl)]
+_lib.hss_server_wait.restype = C.c_int
+_lib.hss_server_clock.argtypes = []
+_lib.hss_server_clock.restype = _dbl
+_lib.hss_server_stats.argtypes = [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64)]
+_lib.hss_server_stats.restype = C.c_int
 _lib.hss_status_string.argtypes = [C.c_int]
 _lib.hss_status_string.restype = C.c_char_p
 _lib.hss_last_error.argtypes = []
@@ -398,6 +423,100 @@ class BatchPlan:
                    "hss_batch_profile_read")
             out[name] = (float(ms.value), int(n.value), int(b.value))
         return out
+
+
+@dataclass
+class Served:
+    """A finished request: its outputs and its times on the server clock."""
+    keys_out: object
+    vals_out: object
+    offsets: object
+    t_submit: float
+    t_done: float
+
+
+class Server:
+    """Requests of any shape served as they arrive.  The library's worker
+    thread runs the queued requests (same key width and payload choice) as
+    batches on a stream of its own; each result equals the plain partition
+    of that request."""
+
+    def __init__(self, max_batch_keys: int = 0, max_batch_requests: int = 0):
+        h = _vp()
+        _check(_lib.hss_server_create(C.byref(h), max_batch_keys, max_batch_requests),
+               "hss_server_create")
+        self._h = h
+        self._live = {}
+
+    @staticmethod
+    def clock() -> float:
+        return float(_lib.hss_server_clock())
+
+    def submit(self, keys, p: int, eps: float, seed: int, vals=None, keys_out=None, vals_out=None,
+               offsets=None, sync: bool = True) -> int:
+        """Queue one request; returns its ticket.  With sync, the current
+        stream is synchronised first, so that the inputs are complete."""
+        torch = _torch()
+        if not keys.is_cuda or not keys.is_contiguous():
+            raise ValueError("keys must be a contiguous device tensor")
+        n = keys.numel()
+        keys_out = torch.empty_like(keys) if keys_out is None else keys_out
+        if vals is not None and vals_out is None:
+            vals_out = torch.empty_like(vals)
+        offsets = (torch.empty(p + 1, dtype=torch.int64, device=keys.device)
+                   if offsets is None else offsets)
+        if sync:
+            torch.cuda.current_stream().synchronize()
+        req = _Request(n, p, _key_type(keys), eps, seed & NONE, keys.data_ptr(),
+                       vals.data_ptr() if vals is not None else None, keys_out.data_ptr(),
+                       vals_out.data_ptr() if vals_out is not None else None, offsets.data_ptr())
+        t = _u64()
+        _check(_lib.hss_server_submit(self._h, C.byref(req), C.byref(t)), "hss_server_submit")
+        self._live[int(t.value)] = (keys, vals, keys_out, vals_out, offsets)
+        return int(t.value)
+
+    def _retire(self, ticket, st, ts, td) -> Served:
+        keys, vals, ko, vo, off = self._live.pop(ticket)
+        _check(st, f"request {ticket}")
+        return Served(ko, vo, off, ts, td)
+
+    def poll(self, ticket: int):
+        """None while the request runs, else its Served record."""
+        done, st, ts, td = C.c_int(), C.c_int(), _dbl(), _dbl()
+        _check(_lib.hss_server_poll(self._h, ticket, C.byref(done), C.byref(st), C.byref(ts),
+                                    C.byref(td)), "hss_server_poll")
+        if not done.value:
+            return None
+        return self._retire(ticket, st.value, ts.value, td.value)
+
+    def wait(self, ticket: int) -> Served:
+        st, ts, td = C.c_int(), _dbl(), _dbl()
+        _check(_lib.hss_server_wait(self._h, ticket, C.byref(st), C.byref(ts), C.byref(td)),
+               "hss_server_wait")
+        return self._retire(ticket, st.value, ts.value, td.value)
+
+    def stats(self) -> dict:
+        b, r, k = _u64(), _u64(), _u64()
+        _check(_lib.hss_server_stats(self._h, C.byref(b), C.byref(r), C.byref(k)), "hss_server_stats")
+        return {"batches": int(b.value), "requests": int(r.value), "keys": int(k.value)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hss_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def _plan_for(keys, p, eps, vals, tuning):

@@ -10,7 +10,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -21,6 +29,28 @@
 #include "internal.hpp"
 
 using namespace hss;
+
+namespace hss {
+
+hipError_t dev_alloc(MemSource* m, void** p, size_t bytes) {
+    return m ? m->dev_get(p, bytes) : hipMalloc(p, bytes);
+}
+
+void dev_release(MemSource* m, void* p) {
+    if (m) m->dev_put(p);
+    else (void)hipFree(p);
+}
+
+hipError_t host_alloc(MemSource* m, void** p, size_t bytes) {
+    return m ? m->host_get(p, bytes) : hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+
+void host_release(MemSource* m, void* p) {
+    if (m) m->host_put(p);
+    else (void)hipHostFree(p);
+}
+
+}  // namespace hss
 
 namespace {
 
@@ -201,19 +231,20 @@ struct Engine {
     std::vector<RoundRecord> trace;
     Profiler prof;
 
+    // where the memory comes from (null: hipMalloc), and the one stream a
+    // server engine runs on (null: plans and batches, any stream)
+    MemSource* mem = nullptr;
+    hipStream_t own_stream = nullptr;
+
     ~Engine() {
         (void)hipSetDevice(device);
-        (void)hipDeviceSynchronize();
-        if (probe_mem) (void)hipFree(probe_mem);
-        if (psort_mem) (void)hipFree(psort_mem);
-        if (cmat) (void)hipFree(cmat);
-        if (hh.fb_counts) (void)hipFree(hh.fb_counts);
-        if (hh.fb_sb_start) (void)hipFree(hh.fb_sb_start);
-        if (hh.fb_sb_len) (void)hipFree(hh.fb_sb_len);
-        if (arena) (void)hipFree(arena);
-        if (h_ctr) (void)hipHostFree(h_ctr);
-        if (h_run) (void)hipHostFree(h_run);
-        if (h_hist) (void)hipHostFree(h_hist);
+        if (own_stream) (void)hipStreamSynchronize(own_stream);
+        else (void)hipDeviceSynchronize();
+        for (void* q : {probe_mem, psort_mem, (void*)cmat, (void*)hh.fb_counts, (void*)hh.fb_sb_start,
+                        (void*)hh.fb_sb_len, arena})
+            if (q) dev_release(mem, q);
+        for (void* q : {(void*)h_ctr, (void*)h_run, (void*)h_hist})
+            if (q) host_release(mem, q);
     }
 };
 
@@ -504,7 +535,7 @@ hss_status grow(Engine& E, uint64_t need, uint64_t cm_need) {
     if (need > E.cap || !E.probe_mem) {
         uint64_t cap = E.cap ? E.cap : 4096;
         while (cap < need) cap *= 2;
-        if (E.probe_mem) HIP_TRY(hipFree(E.probe_mem));
+        if (E.probe_mem) dev_release(E.mem, E.probe_mem);
         E.probe_mem = nullptr;
         E.cap = 0;
         Arena ar;
@@ -522,7 +553,7 @@ hss_status grow(Engine& E, uint64_t need, uint64_t cm_need) {
             r.pr_rank = ar.take<uint64_t>(cap);
             if (pass == 0) {
                 E.probe_bytes = ar.used + 256;
-                HIP_TRY(hipMalloc(&E.probe_mem, E.probe_bytes));
+                HIP_TRY(dev_alloc(E.mem, &E.probe_mem, E.probe_bytes));
                 ar.base = (char*)E.probe_mem;
             }
         }
@@ -532,10 +563,10 @@ hss_status grow(Engine& E, uint64_t need, uint64_t cm_need) {
     if (cm_need > E.cm_cap || !E.cmat) {
         uint64_t want = E.cm_cap ? E.cm_cap : (1ull << 20);
         while (want < cm_need) want *= 2;
-        if (E.cmat) HIP_TRY(hipFree(E.cmat));
+        if (E.cmat) dev_release(E.mem, E.cmat);
         E.cmat = nullptr;
         E.cm_cap = 0;
-        HIP_TRY(hipMalloc((void**)&E.cmat, want * 4));
+        HIP_TRY(dev_alloc(E.mem, (void**)&E.cmat, want * 4));
         E.cm_cap = want;
         r.cmat = E.cmat;
         r.cm_cap = want;
@@ -543,9 +574,12 @@ hss_status grow(Engine& E, uint64_t need, uint64_t cm_need) {
     return HSS_OK;
 }
 
+// Host tables to the device: synchronously, or on the engine's own stream
+// (the vectors outlive the copies: the caller synchronises that stream).
 template <typename T>
-hipError_t h2d(T* d, const std::vector<T>& v) {
+hipError_t h2d(T* d, const std::vector<T>& v, hipStream_t s = nullptr) {
     if (v.empty()) return hipSuccess;
+    if (s) return hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
     return hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
@@ -557,30 +591,33 @@ hss_status engine_init(Engine& E) {
     if (E.n_tot >= (1ull << 32)) return fail(HSS_ERR_UNSUPPORTED, "more than 2^32 - 1 keys in one plan");
     if (E.max_bucket >= (1ull << 32)) return fail(HSS_ERR_UNSUPPORTED, "bucket bound >= 2^32");
     E.arena_bytes = layout(E, nullptr) + 256;
-    HIP_TRY(hipMalloc(&E.arena, E.arena_bytes));
+    E.hh.mem = E.mem;
+    HIP_TRY(dev_alloc(E.mem, &E.arena, E.arena_bytes));
     layout(E, (char*)E.arena);
-    HIP_TRY(hipHostMalloc((void**)&E.h_ctr, sizeof(RoundCounters) + 32, hipHostMallocDefault));
+    HIP_TRY(host_alloc(E.mem, (void**)&E.h_ctr, sizeof(RoundCounters) + 32));
     E.hh.pinned = (uint32_t*)((char*)E.h_ctr + sizeof(RoundCounters));
-    HIP_TRY(hipHostMalloc((void**)&E.h_run, E.ih.size() * sizeof(InstRun), hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc((void**)&E.h_hist, E.J * sizeof(RoundHist), hipHostMallocDefault));
-    HIP_TRY(h2d(E.seg_off, L.seg_off));
-    HIP_TRY(h2d(E.seg_inst, L.seg_inst));
-    HIP_TRY(h2d(E.row_inst, L.row_inst));
-    HIP_TRY(h2d(E.ideal, L.ideal));
-    HIP_TRY(h2d(E.inst_d, L.inst));
-    HIP_TRY(h2d(E.thresh_d, L.thresh));
-    HIP_TRY(h2d(E.all_d, L.all));
-    HIP_TRY(h2d(E.fence_base, L.fence_base));
-    HIP_TRY(h2d(E.chunk_seg, L.chunk_seg));
-    HIP_TRY(h2d(E.chunk_lo, L.chunk_lo));
+    HIP_TRY(host_alloc(E.mem, (void**)&E.h_run, E.ih.size() * sizeof(InstRun)));
+    HIP_TRY(host_alloc(E.mem, (void**)&E.h_hist, E.J * sizeof(RoundHist)));
+    hipStream_t cs = E.own_stream;
+    HIP_TRY(h2d(E.seg_off, L.seg_off, cs));
+    HIP_TRY(h2d(E.seg_inst, L.seg_inst, cs));
+    HIP_TRY(h2d(E.row_inst, L.row_inst, cs));
+    HIP_TRY(h2d(E.ideal, L.ideal, cs));
+    HIP_TRY(h2d(E.inst_d, L.inst, cs));
+    HIP_TRY(h2d(E.thresh_d, L.thresh, cs));
+    HIP_TRY(h2d(E.all_d, L.all, cs));
+    HIP_TRY(h2d(E.fence_base, L.fence_base, cs));
+    HIP_TRY(h2d(E.chunk_seg, L.chunk_seg, cs));
+    HIP_TRY(h2d(E.chunk_lo, L.chunk_lo, cs));
     if (E.listed) {
-        HIP_TRY(h2d(E.msd_seg, L.msd_seg));
-        HIP_TRY(h2d(E.msd_beg, L.msd_beg));
-        HIP_TRY(h2d(E.msd_end, L.msd_end));
-        HIP_TRY(h2d(E.msd_tile_seg, L.msd_tile_seg));
-        HIP_TRY(h2d(E.msd_tile0, L.msd_tile0));
-        HIP_TRY(h2d(E.direct_seg, L.direct_seg));
+        HIP_TRY(h2d(E.msd_seg, L.msd_seg, cs));
+        HIP_TRY(h2d(E.msd_beg, L.msd_beg, cs));
+        HIP_TRY(h2d(E.msd_end, L.msd_end, cs));
+        HIP_TRY(h2d(E.msd_tile_seg, L.msd_tile_seg, cs));
+        HIP_TRY(h2d(E.msd_tile0, L.msd_tile0, cs));
+        HIP_TRY(h2d(E.direct_seg, L.direct_seg, cs));
     }
+    if (cs) HIP_TRY(hipStreamSynchronize(cs));   // L goes out of scope
     E.fences.base = E.fence_base;
     E.fences.seg_off = E.seg_off;
     RoundArgs& r = E.ra;
@@ -741,11 +778,11 @@ hss_status big_first_round(Engine& E, hipStream_t s) {
     }
     const uint64_t need = 4 * m + nivl + 1;
     if (need > E.psort_cap) {
-        if (E.psort_mem) HIP_TRY(hipFree(E.psort_mem));
+        if (E.psort_mem) dev_release(E.mem, E.psort_mem);
         E.psort_mem = nullptr;
         E.psort_cap = 0;
         const uint64_t want = need + need / 4;
-        HIP_TRY(hipMalloc(&E.psort_mem, want * sizeof(uint64_t)));
+        HIP_TRY(dev_alloc(E.mem, &E.psort_mem, want * sizeof(uint64_t)));
         E.psort_cap = want;
     }
     uint64_t* x0 = (uint64_t*)E.psort_mem;
@@ -940,20 +977,26 @@ hss_status engine_run(Engine& E, const void* kin, const uint64_t* vin, void* kou
     return HSS_OK;
 }
 
-hss_status check_io(const Engine& E, const InstHost& h, const void* kin, const uint64_t* vin,
-                    const void* kout, const uint64_t* vout, const uint64_t* offsets) {
+hss_status check_io_raw(bool payload, int key_bytes, uint64_t n, uint32_t p, const void* kin,
+                        const uint64_t* vin, const void* kout, const uint64_t* vout,
+                        const uint64_t* offsets) {
     if (!kin || !kout) return fail(HSS_ERR_INVALID_ARG, "null key pointer");
-    if (E.payload != (vin != nullptr) || E.payload != (vout != nullptr))
+    if (payload != (vin != nullptr) || payload != (vout != nullptr))
         return fail(HSS_ERR_INVALID_ARG, "payload pointers must be given iff the plan has a payload");
     const void* ptrs[] = {kin, vin, kout, vout, offsets};
     for (const void* q : ptrs)
         if (q && !aligned16(q)) return fail(HSS_ERR_INVALID_ARG, "device pointers must be 16-byte aligned");
-    const size_t kb = h.n * E.key_bytes, vb = h.n * 8, ob = (h.p + 1) * 8;
+    const size_t kb = n * key_bytes, vb = n * 8, ob = ((size_t)p + 1) * 8;
     if (overlap(kin, kb, kout, kb) || overlap(kin, kb, vout, vb) || overlap(vin, vb, kout, kb) ||
         overlap(vin, vb, vout, vb) || overlap(offsets, ob, kin, kb) || overlap(offsets, ob, kout, kb) ||
         overlap(offsets, ob, vin, vb) || overlap(offsets, ob, vout, vb) || overlap(kout, kb, vout, vb))
         return fail(HSS_ERR_INVALID_ARG, "outputs overlap inputs or each other");
     return HSS_OK;
+}
+
+hss_status check_io(const Engine& E, const InstHost& h, const void* kin, const uint64_t* vin,
+                    const void* kout, const uint64_t* vout, const uint64_t* offsets) {
+    return check_io_raw(E.payload, E.key_bytes, h.n, h.p, kin, vin, kout, vout, offsets);
 }
 
 hss_status finish(Engine& E, hipStream_t s) {
@@ -991,6 +1034,186 @@ hss_status new_engine_instance(Engine& E, uint64_t n, uint32_t p, double eps) {
     h.eps = eps;
     instance_constants(h, E.tune);
     E.ih.push_back(h);
+    return HSS_OK;
+}
+
+}  // namespace
+
+
+// ------------------------------------------------------------- server ----
+
+namespace {
+
+double clock_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device and pinned blocks kept between batches: a released block is handed
+// out again to the smallest request it covers without wasting more than
+// half of it (plus 64 MiB); only a miss allocates.
+struct BlockCache : MemSource {
+    std::mutex mu;
+    std::multimap<size_t, void*> dev_free, host_free;
+    std::unordered_map<void*, size_t> dev_size, host_size;
+
+    static bool fits(size_t have, size_t want) { return have >= want && have <= 2 * want + (64u << 20); }
+
+    hipError_t dev_get(void** p, size_t bytes) override {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = dev_free.lower_bound(bytes);
+        if (it != dev_free.end() && fits(it->first, bytes)) {
+            *p = it->second;
+            dev_free.erase(it);
+            return hipSuccess;
+        }
+        hipError_t e = hipMalloc(p, bytes);
+        if (e == hipErrorOutOfMemory && !dev_free.empty()) {   // give back what is idle, then retry
+            for (auto& kv : dev_free) {
+                (void)hipFree(kv.second);
+                dev_size.erase(kv.second);
+            }
+            dev_free.clear();
+            (void)hipGetLastError();
+            e = hipMalloc(p, bytes);
+        }
+        if (e == hipSuccess) dev_size[*p] = bytes;
+        return e;
+    }
+    void dev_put(void* p) override {
+        std::lock_guard<std::mutex> g(mu);
+        dev_free.emplace(dev_size[p], p);
+    }
+    hipError_t host_get(void** p, size_t bytes) override {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = host_free.lower_bound(bytes);
+        if (it != host_free.end() && fits(it->first, bytes)) {
+            *p = it->second;
+            host_free.erase(it);
+            return hipSuccess;
+        }
+        hipError_t e = hipHostMalloc(p, bytes, hipHostMallocDefault);
+        if (e == hipSuccess) host_size[*p] = bytes;
+        return e;
+    }
+    void host_put(void* p) override {
+        std::lock_guard<std::mutex> g(mu);
+        host_free.emplace(host_size[p], p);
+    }
+    ~BlockCache() override {
+        for (auto& kv : dev_free) (void)hipFree(kv.second);
+        for (auto& kv : host_free) (void)hipHostFree(kv.second);
+    }
+};
+
+struct ServerReq {
+    hss_request r{};
+    double t_submit = 0, t_done = 0;
+    hss_status st = HSS_OK;
+    std::string msg;            // the worker's error message, for the caller's thread
+    bool done = false;
+};
+
+}  // namespace
+
+struct hss_server_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint64_t max_keys = 0;
+    uint32_t max_reqs = 0;
+    BlockCache cache;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, ServerReq> reqs;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+    uint64_t batches = 0, served = 0, keys = 0;
+};
+
+namespace {
+
+// One batch of queued requests (same key type and payload choice), run like
+// hss_batch_partition on the server's stream with memory from its cache.
+hss_status run_server_batch(hss_server_s* S, const std::vector<hss_request>& rq) {
+    std::unique_ptr<Engine> E(new (std::nothrow) Engine());
+    if (!E) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    E->batch = true;
+    E->key_bytes = rq[0].key_type == HSS_U32 ? 4 : 8;
+    E->payload = rq[0].vals_in != nullptr;
+    E->mem = &S->cache;
+    E->own_stream = S->stream;
+    for (const hss_request& r : rq) {
+        hss_status st = new_engine_instance(*E, r.n, r.p, r.eps);
+        if (st != HSS_OK) return st;
+    }
+    hss_status st = engine_init(*E);
+    if (st != HSS_OK) return st;
+    for (size_t i = 0; i < rq.size(); ++i)
+        E->h_run[i] = InstRun{rq[i].seed, rq[i].keys_in, rq[i].vals_in, rq[i].keys_out, rq[i].vals_out,
+                              rq[i].offsets};
+    HIP_TRY(hipMemcpyAsync(E->run_d, E->h_run, rq.size() * sizeof(InstRun), hipMemcpyHostToDevice, S->stream));
+    HIP_TRY(launch_counters_reset(E->ra.ctr, S->stream));
+    st = engine_run(*E, nullptr, nullptr, nullptr, nullptr, S->stream, false);
+    if (st != HSS_OK) return st;
+    return finish(*E, S->stream);   // synchronises the stream
+}
+
+void server_loop(hss_server_s* S) {
+    (void)hipSetDevice(S->device);
+    for (;;) {
+        std::vector<uint64_t> tickets;
+        std::vector<hss_request> rq;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_work.wait(lk, [S] { return S->stop || !S->queue.empty(); });
+            if (S->queue.empty()) return;   // stopping, nothing left
+            // in submission order: requests of the first one's class, within the limits
+            const hss_request& f = S->reqs[S->queue.front()].r;
+            const bool pay = f.vals_in != nullptr;
+            const hss_key_type kt = f.key_type;
+            uint64_t total = 0;
+            while (!S->queue.empty() && rq.size() < S->max_reqs) {
+                const hss_request& r = S->reqs[S->queue.front()].r;
+                if (r.key_type != kt || (r.vals_in != nullptr) != pay) break;
+                if (!rq.empty() && total + r.n > S->max_keys) break;
+                total += r.n;
+                rq.push_back(r);
+                tickets.push_back(S->queue.front());
+                S->queue.pop_front();
+            }
+        }
+        hss_status st;
+        try {
+            st = run_server_batch(S, rq);
+        } catch (...) {
+            st = fail(HSS_ERR_DEVICE, "unexpected exception");
+        }
+        const double t = clock_s();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (size_t i = 0; i < tickets.size(); ++i) {
+                ServerReq& q = S->reqs[tickets[i]];
+                q.st = st;
+                if (st != HSS_OK) q.msg = g_last_error;
+                q.t_done = t;
+                q.done = true;
+                S->keys += q.r.n;
+            }
+            S->batches += 1;
+            S->served += tickets.size();
+        }
+        S->cv_done.notify_all();
+    }
+}
+
+hss_status retire(hss_server_s* S, std::unordered_map<uint64_t, ServerReq>::iterator it,
+                  hss_status* result, double* t_submit, double* t_done) {
+    if (result) *result = it->second.st;
+    if (it->second.st != HSS_OK) g_last_error = it->second.msg;
+    if (t_submit) *t_submit = it->second.t_submit;
+    if (t_done) *t_done = it->second.t_done;
+    S->reqs.erase(it);
     return HSS_OK;
 }
 
@@ -1332,6 +1555,109 @@ hss_status hss_batch_profile_read(hss_batch_t Bt, uint32_t family, double* ms, u
     if (ms) *ms = t;
     if (launches) *launches = l;
     if (bytes) *bytes = b;
+    return HSS_OK;
+}
+
+// -------------------------------------------------------------- server ----
+
+hss_status hss_server_create(hss_server_t* out, uint64_t max_batch_keys, uint32_t max_batch_requests) {
+    try {
+        if (!out) return fail(HSS_ERR_INVALID_ARG, "null server pointer");
+        *out = nullptr;
+        if (max_batch_keys >= (1ull << 32)) return fail(HSS_ERR_INVALID_ARG, "max_batch_keys must be below 2^32");
+        std::unique_ptr<hss_server_s> S(new (std::nothrow) hss_server_s());
+        if (!S) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
+        S->max_keys = max_batch_keys ? max_batch_keys : (1ull << 30);
+        S->max_reqs = max_batch_requests ? max_batch_requests : 1024u;
+        HIP_TRY(hipGetDevice(&S->device));
+        // default priority; no implicit ordering with other streams
+        HIP_TRY(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
+        S->worker = std::thread(server_loop, S.get());
+        *out = S.release();
+        return HSS_OK;
+    } catch (...) {
+        return fail(HSS_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+void hss_server_destroy(hss_server_t S) {
+    if (!S) return;
+    try {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stop = true;
+        }
+        S->cv_work.notify_all();
+        if (S->worker.joinable()) S->worker.join();
+        (void)hipSetDevice(S->device);
+        if (S->stream) {
+            (void)hipStreamSynchronize(S->stream);
+            (void)hipStreamDestroy(S->stream);
+        }
+        delete S;
+    } catch (...) {
+    }
+}
+
+hss_status hss_server_submit(hss_server_t S, const hss_request* req, uint64_t* ticket) {
+    try {
+        if (!S || !req || !ticket) return fail(HSS_ERR_INVALID_ARG, "null server, request or ticket");
+        const hss_request& r = *req;
+        if (r.key_type != HSS_U32 && r.key_type != HSS_U64) return fail(HSS_ERR_INVALID_ARG, "bad key type");
+        if (r.n == 0 || r.p == 0 || (uint64_t)r.p > r.n) return fail(HSS_ERR_INVALID_ARG, "need 1 <= p <= N");
+        if (r.n >= (1ull << 32)) return fail(HSS_ERR_UNSUPPORTED, "N must be below 2^32");
+        if (!(r.eps > 0.0 && r.eps < 1.0)) return fail(HSS_ERR_INVALID_ARG, "need 0 < eps < 1");
+        if (!r.offsets) return fail(HSS_ERR_INVALID_ARG, "null offsets pointer");
+        hss_status st = check_io_raw(r.vals_in != nullptr, r.key_type == HSS_U32 ? 4 : 8, r.n, r.p,
+                                     r.keys_in, r.vals_in, r.keys_out, r.vals_out, r.offsets);
+        if (st != HSS_OK) return st;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (S->stop) return fail(HSS_ERR_INVALID_ARG, "server is stopping");
+            const uint64_t t = S->next_ticket++;
+            ServerReq q;
+            q.r = r;
+            q.t_submit = clock_s();
+            S->reqs.emplace(t, q);
+            S->queue.push_back(t);
+            *ticket = t;
+        }
+        S->cv_work.notify_one();
+        return HSS_OK;
+    } catch (...) {
+        return fail(HSS_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+hss_status hss_server_poll(hss_server_t S, uint64_t ticket, int* done, hss_status* result,
+                           double* t_submit, double* t_done) {
+    if (!S) return fail(HSS_ERR_INVALID_ARG, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(HSS_ERR_INVALID_ARG, "unknown ticket");
+    if (done) *done = it->second.done ? 1 : 0;
+    if (!it->second.done) return HSS_OK;
+    return retire(S, it, result, t_submit, t_done);
+}
+
+hss_status hss_server_wait(hss_server_t S, uint64_t ticket, hss_status* result, double* t_submit,
+                           double* t_done) {
+    if (!S) return fail(HSS_ERR_INVALID_ARG, "null server");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(HSS_ERR_INVALID_ARG, "unknown ticket");
+    S->cv_done.wait(lk, [&] { return it->second.done; });
+    return retire(S, it, result, t_submit, t_done);
+}
+
+double hss_server_clock(void) { return clock_s(); }
+
+hss_status hss_server_stats(hss_server_t S, uint64_t* batches, uint64_t* requests, uint64_t* keys) {
+    if (!S) return fail(HSS_ERR_INVALID_ARG, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (batches) *batches = S->batches;
+    if (requests) *requests = S->served;
+    if (keys) *keys = S->keys;
     return HSS_OK;
 }
 

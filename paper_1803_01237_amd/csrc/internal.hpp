@@ -329,6 +329,21 @@ struct HybridSort {
 // Largest segment the small sort takes in one step (direct segments).
 constexpr uint32_t kDirectSegMax = 2048;
 
+// Device and pinned host memory of an engine: hipMalloc / hipHostMalloc by
+// default, or a cache of blocks kept between the batches of a server.
+struct MemSource {
+    virtual hipError_t dev_get(void** p, size_t bytes) = 0;
+    virtual void dev_put(void* p) = 0;
+    virtual hipError_t host_get(void** p, size_t bytes) = 0;
+    virtual void host_put(void* p) = 0;
+    virtual ~MemSource() = default;
+};
+// With m null: hipMalloc / hipFree, hipHostMalloc / hipHostFree.
+hipError_t dev_alloc(MemSource* m, void** p, size_t bytes);
+void dev_release(MemSource* m, void* p);
+hipError_t host_alloc(MemSource* m, void** p, size_t bytes);
+void host_release(MemSource* m, void* p);
+
 // Host-side state of the hybrid sort: pinned read-back words and the count
 // table of the oversize passes, grown on demand.
 struct HybridHost {
@@ -338,6 +353,7 @@ struct HybridHost {
     uint64_t* fb_sb_start = nullptr;   // their sub-bucket tables
     uint32_t* fb_sb_len = nullptr;
     uint64_t fb_sb = 0;
+    MemSource* mem = nullptr;          // where the grown tables come from
     uint32_t last_oversize = 0;        // entries of the first deeper level
     uint32_t last_slow = 0;
     uint32_t last_levels = 0;          // deeper levels run

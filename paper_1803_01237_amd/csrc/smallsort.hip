@@ -817,12 +817,12 @@ hipError_t read_summary(const OversizeList& ov, const SlowList& sl, const EqualL
 }
 
 template <typename T>
-hipError_t grow(T** p, uint64_t* cap, uint64_t need) {
+hipError_t grow(MemSource* mem, T** p, uint64_t* cap, uint64_t need) {
     if (need <= *cap) return hipSuccess;
-    if (*p) (void)hipFree(*p);
+    if (*p) dev_release(mem, *p);
     *p = nullptr;
     *cap = 0;
-    hipError_t e = hipMalloc((void**)p, need * sizeof(T));
+    hipError_t e = dev_alloc(mem, (void**)p, need * sizeof(T));
     if (e == hipSuccess) *cap = need;
     return e;
 }
@@ -927,11 +927,11 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     OversizeList cur = a.ov, nxt = a.ov2;
     while (E > 0) {
         if (++host.last_levels > (uint32_t)kb / 8) return hipErrorUnknown;
-        e = grow(&host.fb_counts, &host.fb_words, (uint64_t)T * 256);
+        e = grow(host.mem, &host.fb_counts, &host.fb_words, (uint64_t)T * 256);
         if (e == hipSuccess) {
             uint64_t c0 = host.fb_sb;
-            e = grow(&host.fb_sb_start, &c0, (uint64_t)E * 256 + 1);
-            if (e == hipSuccess) e = grow(&host.fb_sb_len, &host.fb_sb, (uint64_t)E * 256 + 1);
+            e = grow(host.mem, &host.fb_sb_start, &c0, (uint64_t)E * 256 + 1);
+            if (e == hipSuccess) e = grow(host.mem, &host.fb_sb_len, &host.fb_sb, (uint64_t)E * 256 + 1);
         }
         if (e != hipSuccess) return e;
         const uint64_t kt = (uint64_t)(uintptr_t)a.keys_tmp, ko = (uint64_t)(uintptr_t)a.keys_out;

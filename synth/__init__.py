@@ -145,3 +145,28 @@ def batched_keys(shape) -> np.ndarray:
     n, _p, _eps, kb, dseed, _hseed = shape
     k = uniform64(n, dseed)
     return (k >> np.uint64(32)).astype(np.uint32) if kb == 4 else k
+
+
+def served_shapes(count: int = 20_000, seed: int = 5, lo_bits: float = 14.0, hi_bits: float = 26.0):
+    """Request shapes of the served workload: N log-uniform on
+    [2^lo_bits, 2^hi_bits], p = clamp(floor(e^U(ln 64, ln 2049)), 64, 2048)
+    (at most N), eps drawn from {0.02, 0.05}; 64-bit keys with a payload.
+    Returns [(n, p, eps, data_seed, hss_seed)]."""
+    rng = _rng(seed)
+    out = []
+    for i in range(count):
+        n = int(np.floor(2.0 ** rng.uniform(lo_bits, hi_bits)))
+        p = int(np.clip(np.floor(np.exp(rng.uniform(np.log(64.0), np.log(2049.0)))), 64, 2048))
+        eps = 0.02 if rng.integers(0, 2) == 0 else 0.05
+        out.append((n, min(p, n), eps, seed * 1_000_000 + i, 1_000_000 + i))
+    return out
+
+
+def device_keys(n: int, data_seed: int, device):
+    """Uniform 64-bit keys drawn on the device (the served workload's inputs,
+    too many to stage from the host): torch's generator seeded with
+    data_seed.  Returns an int64 tensor (keys compare as unsigned)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(data_seed)
+    return torch.randint(-(1 << 63), (1 << 63) - 1, (n,), dtype=torch.int64, device=device, generator=g)

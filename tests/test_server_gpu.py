@@ -1,0 +1,121 @@
+"""GPU tests of the request server: every served request equals the plain
+hss_partition of the same request bit for bit (keys, payload, offsets),
+whatever else was batched with it; a few small ones also equal the oracle."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def hss():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1803_01237_amd as lib
+    return lib
+
+
+def _requests(count, seed):
+    """Mixed small requests: u32 and u64 keys, with and without payload."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(2 ** rng.uniform(10, 17))
+        p = int(min(n, np.exp(rng.uniform(np.log(4), np.log(300)))))
+        eps = float(rng.choice([0.02, 0.05, 0.1]))
+        kb = 4 if rng.integers(0, 3) == 0 else 8
+        pay = bool(rng.integers(0, 2))
+        out.append((n, max(p, 1), eps, kb, pay, 7000 + i))
+    return out
+
+
+def _inputs(n, kb, pay, dseed):
+    keys = synth.make("uniform64", n, dseed)
+    if kb == 4:
+        keys = (keys >> np.uint64(32)).astype(np.uint32)
+    vals = (np.arange(n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)) if pay else None
+    return keys, vals
+
+
+def _dev(a):
+    return torch.from_numpy(a.view(np.int64 if a.dtype == np.uint64 else np.int32)).cuda()
+
+
+def test_served_requests_equal_plain_partitions(hss):
+    reqs = _requests(48, 3)
+    _say(f"[server] {len(reqs)} requests in bursts")
+    with hss.Server(max_batch_keys=1 << 20, max_batch_requests=16) as srv:
+        tickets, held = [], []
+        for i, (n, p, eps, kb, pay, dseed) in enumerate(reqs):
+            keys, vals = _inputs(n, kb, pay, dseed)
+            kd = _dev(keys)
+            vd = _dev(vals) if pay else None
+            tickets.append(srv.submit(kd, p, eps, dseed, vd))
+            held.append((keys, vals, kd, vd))
+            if i % 8 == 7:
+                time.sleep(0.002)
+        done = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+        assert st["requests"] == len(reqs)
+        assert 1 <= st["batches"] <= len(reqs)
+        _say(f"[server] {st['batches']} batches; comparing with plain partitions")
+        for i, ((n, p, eps, kb, pay, dseed), r) in enumerate(zip(reqs, done)):
+            keys, vals, kd, vd = held[i]
+            assert r.t_done >= r.t_submit
+            with hss.Plan(n, p, eps, key_bytes=kb, payload=pay) as plan:
+                ko, vo, off = plan.partition(kd, dseed, vd)
+                torch.cuda.synchronize()
+                assert torch.equal(off, r.offsets), i
+                assert torch.equal(ko, r.keys_out), i
+                if pay:
+                    assert torch.equal(vo, r.vals_out), i
+            if i < 6:
+                ref = oracle.hss(keys, p, eps, dseed, vals=vals, mode="partition", trace_level=0)
+                assert np.array_equal(r.offsets.cpu().numpy().view(np.uint64), ref.offsets), i
+                kt = np.uint64 if kb == 8 else np.uint32
+                assert np.array_equal(r.keys_out.cpu().numpy().view(kt), ref.keys), i
+
+
+def test_server_polls_and_reuses_memory(hss):
+    """Two waves of identical shapes: the second runs from the block cache;
+    poll reports a request only once."""
+    with hss.Server() as srv:
+        for wave in range(2):
+            tickets = []
+            for i in range(6):
+                keys, vals = _inputs(50_000 + 1000 * i, 8, True, 900 + i)
+                tickets.append((srv.submit(_dev(keys), 32, 0.05, 11 + i, _dev(vals)), keys, vals))
+            for i, (t, keys, vals) in enumerate(tickets):
+                r = None
+                while r is None:
+                    r = srv.poll(t)
+                    time.sleep(0.001)
+                with pytest.raises(hss.HssError):
+                    srv.poll(t)                       # retired
+                ref = oracle.hss(keys, 32, 0.05, 11 + i, vals=vals, mode="partition", trace_level=0)
+                assert np.array_equal(r.offsets.cpu().numpy().view(np.uint64), ref.offsets)
+                assert np.array_equal(r.vals_out.cpu().numpy().view(np.uint64), ref.vals)
+
+
+def test_server_rejects_bad_requests(hss):
+    with hss.Server() as srv:
+        k = torch.zeros(100, dtype=torch.int64, device="cuda")
+        with pytest.raises(hss.HssError):
+            srv.submit(k, 200, 0.05, 1)                # p > N
+        with pytest.raises(hss.HssError):
+            srv.submit(k, 4, 1.5, 1)                   # eps >= 1
+        with pytest.raises(hss.HssError):
+            srv.submit(k[1:], 4, 0.05, 1)              # misaligned keys
+        assert srv.stats()["requests"] == 0
