@@ -158,16 +158,20 @@ def _timed(fn, steps):
 
 def options_bench(keys, n, p, eps, hseed, steps):
     """The plan options of the same kernels at the headline size: HSS with one
-    round (k = 1, section 4.1) and exact splitting (eps = p / N, tol = 0)."""
+    round (k = 1, section 4.1), exact splitting (eps = p / N, tol = 0) and a
+    fixed budget of 5 p and of p probes per round (section 6); then the
+    rounds against p at eps = 2% (section 7.1) for the rate schedule and both
+    budgets, on the first 2^26 keys."""
     import torch
     import paper_1803_01237_amd as hss
     out = {}
     kout = torch.empty_like(keys)
     off = torch.empty(p + 1, dtype=torch.int64, device=keys.device)
     ideal = (np.arange(p + 1, dtype=object) * n) // p
-    for name, e, k in [("one_round", eps, 1), ("exact", p / n, 0)]:
-        log(f"[bench] option {name}: eps={e} k_override={k}")
-        with hss.Plan(n, p, e, k_override=k) as plan:
+    for name, e, k, c in [("one_round", eps, 1, 0), ("exact", p / n, 0, 0),
+                          ("budget_5p", eps, 0, 5), ("budget_1p", eps, 0, 1)]:
+        log(f"[bench] option {name}: eps={e} k_override={k} probes_per_round={c}")
+        with hss.Plan(n, p, e, k_override=k, probes_per_round=c) as plan:
             ms = _timed(lambda: plan.partition(keys, hseed, keys_out=kout, offsets=off), steps)
             tr = plan.trace()
             tol, kk = plan.constants(1)[:2]
@@ -178,6 +182,20 @@ def options_bench(keys, n, p, eps, hseed, steps):
             out[name] = {"eps": e, "k": int(kk), "tol": int(tol), "ms_per_step": round(ms, 4),
                          "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3), "rounds": len(tr),
                          "probes_per_round": [r.m for r in tr], "max_splitter_deviation": dev}
+    n2 = 1 << 26
+    sub = keys[:n2]
+    kout2 = torch.empty_like(sub)
+    curve = {}
+    for c in (0, 5, 1):
+        label = "schedule" if c == 0 else f"budget_{c}p"
+        curve[label] = {}
+        for pp in (64, 256, 1024, 4096):
+            off2 = torch.empty(pp + 1, dtype=torch.int64, device=keys.device)
+            with hss.Plan(n2, pp, 0.02, probes_per_round=c) as plan:
+                plan.partition(sub, hseed, keys_out=kout2, offsets=off2)
+                tr = plan.trace()
+                curve[label][str(pp)] = {"rounds": len(tr), "probes": sum(r.m for r in tr)}
+    out["rounds_vs_p"] = {"n": n2, "eps": 0.02, "curves": curve}
     return out
 
 

@@ -64,7 +64,13 @@ typedef struct {
     uint32_t lsd_only;          /* 1: sort segments and buckets by plain 8-bit LSD
                                    passes instead of the MSD pass + on-chip finish
                                    (same results; for comparison)               */
-    uint32_t reserved[3];       /* must be zero */
+    uint32_t probes_per_round;  /* c > 0: a fixed budget of c p probes per round
+                                   (the implementation of section 6 and the
+                                   theorem with O(p) samples per round): each key
+                                   of the round's domain gamma is a probe with
+                                   probability min(1, c p / |gamma|), in place of
+                                   the rate schedule; single plans only          */
+    uint32_t reserved[2];       /* must be zero */
 } hss_tuning;
 
 /*

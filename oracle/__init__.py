@@ -57,7 +57,7 @@ def lib():
         L.oracle_philox_word.argtypes = [u64, u64, u32]
         L.oracle_philox_word.restype = u32
         L.oracle_hss.argtypes = [u64, u32, dbl, C.c_int, vp, vp, u64, C.c_int, u32, u32,
-                                 C.c_int, C.c_int, vp, vp, vp]
+                                 C.c_int, u32, C.c_int, vp, vp, vp]
         L.oracle_hss.restype = vp
         L.oracle_local_sort.argtypes = [u64, u32, C.c_int, vp, vp, vp, vp]
         L.oracle_local_sort.restype = C.c_int
@@ -157,8 +157,11 @@ class Result:
 
 def hss(keys: np.ndarray, p: int, eps: float, seed: int, vals: np.ndarray | None = None,
         mode: str = "partition", k_override: int = 0, max_rounds: int = 0,
-        force_full_sample: bool = False, trace_level: int = 1) -> Result:
-    """Run the whole method on the host; returns outputs and the round trace."""
+        force_full_sample: bool = False, trace_level: int = 1,
+        probes_per_round: int = 0) -> Result:
+    """Run the whole method on the host; returns outputs and the round trace.
+    probes_per_round = c > 0: a fixed budget of c p probes per round (rate
+    c p / |gamma|) instead of the rate schedule."""
     keys = np.ascontiguousarray(keys)
     if keys.dtype not in (np.uint32, np.uint64):
         raise TypeError("keys must be uint32 or uint64")
@@ -172,7 +175,7 @@ def hss(keys: np.ndarray, p: int, eps: float, seed: int, vals: np.ndarray | None
     L = lib()
     h = L.oracle_hss(n, p, eps, bits, _ptr(kin), _ptr(vi), seed & NONE,
                      1 if mode == "sort" else 0, k_override, max_rounds,
-                     1 if force_full_sample else 0, trace_level,
+                     1 if force_full_sample else 0, probes_per_round, trace_level,
                      _ptr(ko), _ptr(vo), _ptr(off))
     try:
         st = L.oracle_status(h)

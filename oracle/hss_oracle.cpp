@@ -108,6 +108,18 @@ bool sampling_threshold(uint64_t n, uint32_t p, const Constants& c, uint32_t j,
     return false;
 }
 
+// Fixed probe budget (the implementation of section 6, and the theorem with
+// O(p) samples per round): c p probes per round in expectation.  READING:
+// each key of the domain gamma_{j-1} is a probe with probability
+// c p / |gamma_{j-1}|, clamped at 1, in place of the schedule p s_j / N; the
+// same acceptance threshold floor(q 2^32) as above.
+bool budget_threshold(uint64_t domain, uint32_t p, uint32_t c, uint32_t* thresh) {
+    double q = ((double)c * (double)p) / (double)domain;
+    if (q >= 1.0) { *thresh = 0xFFFFFFFFu; return true; }
+    *thresh = (uint32_t)std::floor(q * 4294967296.0);
+    return false;
+}
+
 // Ideal rank N i / p of splitter i, exact (section 2).
 uint64_t ideal_rank(uint64_t n, uint32_t p, uint64_t i) {
     return (uint64_t)(((u128)i * (u128)n) / (u128)p);
@@ -272,7 +284,7 @@ bool before(const Problem& P, uint64_t g1, uint64_t g2) {
 // probe in its target range).
 void determine_splitters(const Problem& P, double eps, uint64_t seed,
                          uint32_t k_override, uint32_t max_rounds, int force_full,
-                         int trace_level, Run& R) {
+                         uint32_t budget, int trace_level, Run& R) {
     const uint64_t n = P.n;
     const uint32_t p = P.p;
     R.c = make_constants(n, p, eps, k_override);
@@ -286,11 +298,6 @@ void determine_splitters(const Problem& P, double eps, uint64_t seed,
     for (uint32_t j = 1; unsettled > 0; ++j) {
         if (max_rounds && j > max_rounds) { R.status = -5; return; }
         RoundTrace tr;
-        uint32_t thresh;
-        bool all = sampling_threshold(n, p, R.c, j, &thresh);
-        if (force_full) all = true;
-        tr.thresh = all ? 0xFFFFFFFFu : thresh;
-        tr.all = all ? 1u : 0u;
 
         // Step 4 (sampling phase): the domain gamma_{j-1} is the union of the
         // open splitter intervals (L_i, U_i) of the splitters still unsettled
@@ -299,23 +306,32 @@ void determine_splitters(const Problem& P, double eps, uint64_t seed,
         std::map<std::pair<uint64_t, uint64_t>, bool> intervals;   // (L tag, U tag)
         for (uint32_t i = 1; i < p; ++i)
             if (!sp[i].settled) intervals[{sp[i].L, sp[i].U}] = true;
-
-        std::vector<uint64_t> probes;
+        // slice [lo, hi) of every segment inside every interval
+        std::vector<std::pair<uint64_t, uint64_t>> slices;
         for (auto& kv : intervals) {
             uint64_t Lg = kv.first.first, Ug = kv.first.second;
             for (uint32_t s = 0; s < p; ++s) {
                 uint64_t lo = 0, hi = P.seg_len(s);
                 if (Lg != NONE) lo = P.count_below(s, Lg) + (P.segment_of(Lg) == s ? 1 : 0);
                 if (Ug != NONE) hi = P.count_below(s, Ug);
-                for (uint64_t x = lo; x < hi; ++x) {
-                    uint64_t g = P.seg_start[s] + x;
-                    tr.domain += 1;
-                    // Section 4.2.1: each key of the domain is taken
-                    // independently with probability p s_j / N.
-                    if (all || philox_word(seed, g, j) < thresh) probes.push_back(g);
-                }
+                slices.push_back({P.seg_start[s] + lo, P.seg_start[s] + std::max(lo, hi)});
+                tr.domain += hi > lo ? hi - lo : 0;
             }
         }
+
+        uint32_t thresh;
+        bool all = budget ? budget_threshold(tr.domain, p, budget, &thresh)
+                          : sampling_threshold(n, p, R.c, j, &thresh);
+        if (force_full) all = true;
+        tr.thresh = all ? 0xFFFFFFFFu : thresh;
+        tr.all = all ? 1u : 0u;
+
+        // Section 4.2.1: each key of the domain is taken independently with
+        // the round's probability.
+        std::vector<uint64_t> probes;
+        for (auto& sl : slices)
+            for (uint64_t g = sl.first; g < sl.second; ++g)
+                if (all || philox_word(seed, g, j) < thresh) probes.push_back(g);
 
         // Gather and sort the probes (section 5.1), in the strict order.
         std::sort(probes.begin(), probes.end(),
@@ -410,8 +426,8 @@ extern "C" {
 oracle_run* oracle_hss(uint64_t n, uint32_t p, double eps, int key_bits,
                        const void* keys_in, const uint64_t* vals_in, uint64_t seed,
                        int mode, uint32_t k_override, uint32_t max_rounds, int force_full,
-                       int trace_level, void* keys_out, uint64_t* vals_out,
-                       uint64_t* offsets_out) {
+                       uint32_t probes_per_round, int trace_level, void* keys_out,
+                       uint64_t* vals_out, uint64_t* offsets_out) {
     Run* R = new Run();
     if (!valid_params(n, p, eps, key_bits) || !keys_in || !keys_out || !offsets_out) {
         R->status = -1;
@@ -419,7 +435,8 @@ oracle_run* oracle_hss(uint64_t n, uint32_t p, double eps, int key_bits,
     }
     Problem P;
     load_and_local_sort(P, n, p, key_bits, keys_in, vals_in);
-    determine_splitters(P, eps, seed, k_override, max_rounds, force_full, trace_level, *R);
+    determine_splitters(P, eps, seed, k_override, max_rounds, force_full, probes_per_round,
+                        trace_level, *R);
     if (R->status != 0) return (oracle_run*)R;
 
     // Data exchange (section 3.1 step 3): bucket b gathers, from every

@@ -124,10 +124,14 @@ void instance_constants(InstHost& h, const hss_tuning& t) {
 
 // Acceptance rule of round j: rate q_j = p s_j / N with s_j = a^(j/k),
 // clamped at 1 ("take all").
+// With a probe budget only round 1 is known here (its domain is all N keys);
+// the device sets the later rounds from their measured domains.
 void round_rate(const InstHost& h, const hss_tuning& t, uint32_t j, bool forced, uint32_t* thresh,
                 int* all) {
     const double s_j = std::pow(h.a, (double)j / (double)h.k);
-    const double q = ((double)h.p * s_j) / (double)h.n;
+    const double q = t.probes_per_round
+                         ? ((double)t.probes_per_round * (double)h.p) / (double)h.n
+                         : ((double)h.p * s_j) / (double)h.n;
     if (q >= 1.0 || (forced && j == 1 && t.force_full_sample)) {
         *thresh = 0xFFFFFFFFu;
         *all = 1;
@@ -378,7 +382,8 @@ void build_layout(Engine& E, Layout& L) {
             round_rate(h, E.tune, j, true, &t, &al);
             if (al) break;
         }
-        E.J = std::max(E.J, j);
+        // a probe budget has no schedule: any number of rounds up to the cap
+        E.J = std::max(E.J, E.tune.probes_per_round ? kMaxRateRounds : j);
     }
     L.thresh.assign((size_t)B * E.J, 0);
     L.all.assign((size_t)B * E.J, 0);
@@ -632,6 +637,7 @@ hss_status engine_init(Engine& E) {
     r.run = E.run_d;
     r.thresh = E.thresh_d;
     r.all = E.all_d;
+    r.budget = E.tune.probes_per_round;
     r.seg_off = E.seg_off;
     r.seg_inst = E.seg_inst;
     r.row_inst = E.row_inst;
@@ -744,18 +750,15 @@ hss_status segment_sort(Engine& E, bool first, const void* kin, const uint64_t* 
     return HSS_OK;
 }
 
+// Counts and rate of round j from its device history (read back).
 void record_round(Engine& E, RoundRecord& rec, uint32_t j) {
-    rec.domain = E.h_ctr->domain;
-    rec.m = E.h_ctr->m;
-    uint32_t t;
-    int al;
-    round_rate(E.ih[0], E.tune, j, true, &t, &al);
-    rec.thresh = t;
-    rec.all = (uint32_t)al;
+    const RoundHist& h = E.h_hist[j - 1];
+    rec.domain = h.domain;
+    rec.m = h.m;
+    rec.thresh = h.thresh;
+    rec.all = h.all;
 }
 
-// Splitter rounds of every instance on the locally sorted buffer B; leaves
-// chi in chi_all and in every instance's offsets.
 // Round 1 of a plan whose first sample is large (one-round HSS, a full
 // sample): the probes of its one interval are put in (key, tag) order by two
 // stable segmented sorts, by tag and then by key, instead of the pairwise
@@ -826,6 +829,8 @@ hss_status big_first_round(Engine& E, hipStream_t s) {
     return HSS_OK;
 }
 
+// Splitter rounds of every instance on the locally sorted buffer B; leaves
+// chi in chi_all and in every instance's offsets.
 hss_status determine_splitters(Engine& E, hipStream_t s) {
     RoundArgs& r = E.ra;
     E.trace.clear();
@@ -852,7 +857,7 @@ hss_status determine_splitters(Engine& E, hipStream_t s) {
                     HIP_TRY(launch_round(r, j, s, &E.prof));
                 }
             }
-            hss_status st = read_counters(E, s, tracing ? 0u : j);
+            hss_status st = read_counters(E, s, j);
             if (st != HSS_OK) return st;
             const RoundCounters c = *E.h_ctr;
             if (c.overflow) {
@@ -899,8 +904,6 @@ hss_status determine_splitters(Engine& E, hipStream_t s) {
                         if (h.unsettled == 0) break;
                         RoundRecord rec;
                         record_round(E, rec, q + 1);
-                        rec.domain = h.domain;
-                        rec.m = h.m;
                         E.trace.push_back(std::move(rec));
                     }
                 }
@@ -1425,6 +1428,8 @@ hss_status hss_batch_plan(hss_batch_t* out, const hss_instance_shape* shapes, ui
                 if (x) return fail(HSS_ERR_INVALID_ARG, "reserved tuning fields must be zero");
             if (tuning->lsd_only) return fail(HSS_ERR_UNSUPPORTED, "lsd_only is for single plans");
             if (tuning->trace_level) return fail(HSS_ERR_UNSUPPORTED, "traces are for single plans");
+            if (tuning->probes_per_round)
+                return fail(HSS_ERR_UNSUPPORTED, "a probe budget is for single plans");
         }
         hss_batch_s* Bt = new (std::nothrow) hss_batch_s();
         if (!Bt) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");

@@ -422,6 +422,8 @@ struct RoundHist {
     unsigned long long domain;     // tags sampled from
     unsigned long long m;          // probes
     unsigned int unsettled;        // unsettled splitters before the round
+    unsigned int thresh;           // acceptance threshold of instance 0
+    unsigned int all;              // 1: every tag of the domain was a probe
     unsigned int pad;
 };
 
@@ -438,8 +440,10 @@ struct RoundArgs {
     uint32_t J;                    // rounds in the rate table
     const InstDesc* inst;
     const InstRun* run;
-    const uint32_t* thresh;        // n_inst x J: acceptance threshold of round j at [I J + j - 1]
-    const uint8_t* all;            // n_inst x J: 1 = every tag of the domain is a probe
+    uint32_t* thresh;              // n_inst x J: acceptance threshold of round j at [I J + j - 1]
+    uint8_t* all;                  // n_inst x J: 1 = every tag of the domain is a probe
+    uint32_t budget;               // c > 0: rate c p / |gamma| set on the device each round
+                                   // (one instance)
     const uint64_t* seg_off;       // S+1 positions
     const uint32_t* seg_inst;      // S
     const uint32_t* row_inst;      // Q

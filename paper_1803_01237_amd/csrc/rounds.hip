@@ -365,6 +365,19 @@ __global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint32_t round)
     }
 }
 
+// Fixed probe budget (one instance): the round's acceptance threshold from
+// the domain just measured, floor(q 2^32) with q = c p / |gamma| in double,
+// or every tag when q >= 1.
+__global__ void budget_rate_kernel(RoundArgs a, uint32_t round) {
+    if (halted(a)) return;
+    const uint64_t dom = a.ctr->domain;
+    if (dom == 0) return;   // no interval left
+    const double q = ((double)a.budget * (double)a.inst[0].p) / (double)dom;
+    const bool all = q >= 1.0;
+    a.thresh[round - 1] = all ? 0xFFFFFFFFu : (uint32_t)floor(q * 4294967296.0);
+    a.all[round - 1] = all ? 1 : 0;
+}
+
 // One workgroup: where every interval's probes go in sorted order, how many
 // ordering workgroups it takes, every instance's probe range and count-matrix
 // block; flags a capacity overrun.
@@ -379,6 +392,8 @@ __global__ __launch_bounds__(kScanT) void probe_scan_kernel(RoundArgs a, uint32_
     if (threadIdx.x == 0) {
         a.hist[round - 1].domain = c->domain;
         a.hist[round - 1].m = m;
+        a.hist[round - 1].thresh = a.thresh[round - 1];
+        a.hist[round - 1].all = a.all[round - 1];
     }
     if (m > a.cap) {
         if (threadIdx.x == 0) c->overflow = 1u;
@@ -850,6 +865,7 @@ hipError_t launch_round_head(const RoundArgs& a, uint32_t j, hipStream_t s) {
     hipLaunchKernelGGL(slices_kernel, dim3(ivl_bound), dim3(kT), 0, s, a);
     hipLaunchKernelGGL(ivl_scan_kernel, dim3(1), dim3(kScanT), 0, s, a);
     hipLaunchKernelGGL(compact_kernel, dim3(ivl_bound), dim3(kT), 0, s, a);
+    if (a.budget) hipLaunchKernelGGL(budget_rate_kernel, dim3(1), dim3(1), 0, s, a, j);
     if (a.n_inst == 1) {
         if (a.key_bytes == 4) hipLaunchKernelGGL((sample_kernel<uint32_t, true>), dim3(kSampleGrid), dim3(kT), 0, s, a, j);
         else hipLaunchKernelGGL((sample_kernel<uint64_t, true>), dim3(kSampleGrid), dim3(kT), 0, s, a, j);

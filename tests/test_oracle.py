@@ -409,3 +409,40 @@ def test_exact_splitting(n, p, kind):
     for b in range(p):
         lo, hi = int(r.offsets[b]), int(r.offsets[b + 1])
         assert np.array_equal(np.sort(r.keys[lo:hi]), srt[lo:hi]), b
+
+
+def test_probe_budget_draws_cp_probes_per_round():
+    """A fixed budget of c p probes per round (section 6, the theorem with
+    O(p) samples per round): each key of the round's domain is a probe with
+    probability c p / |gamma|, so every round below rate 1 draws c p probes in
+    expectation whatever its domain.  Over 40 seeds the mean per round is
+    within 5 sigma of c p (Bernoulli counts: variance at most c p)."""
+    n, p, eps, c = 1 << 17, 64, 0.02, 5
+    counts = []
+    for seed in range(40):
+        keys = synth.make("uniform64", n, 300 + seed)
+        r = oracle.hss(keys, p, eps, seed, trace_level=0, probes_per_round=c)
+        assert r.status == 0
+        off = r.offsets.astype(np.int64)
+        assert np.all(np.abs(off - np.array(R.ideal(n, p), dtype=np.int64)) <= r.tol)
+        counts += [rd.m for rd in r.rounds if not rd.all]
+    mean = float(np.mean(counts))
+    assert abs(mean - c * p) <= 5 * math.sqrt(c * p / len(counts)), (mean, len(counts))
+
+
+def test_probe_budget_round_counts():
+    """With 5p probes per round at eps = 2% the splitters settle within the
+    6 rounds the paper reports (section 7.2, at p = 2048; the rank process
+    does not depend on p much); one probe per processor per round (the
+    iteration study of section 7.1) needs more rounds but stays bounded."""
+    n, p, eps = 1 << 21, 256, 0.02
+    r5, r1 = [], []
+    for seed in range(3):
+        keys = synth.make("uniform64", n, 600 + seed)
+        a = oracle.hss(keys, p, eps, seed, trace_level=0, probes_per_round=5)
+        b = oracle.hss(keys, p, eps, seed, trace_level=0, probes_per_round=1)
+        assert a.status == 0 and b.status == 0
+        r5.append(len(a.rounds))
+        r1.append(len(b.rounds))
+    assert all(3 <= x <= 6 for x in r5), r5
+    assert min(r1) > max(r5) and max(r1) <= 16, (r1, r5)

@@ -176,6 +176,39 @@ def test_plan_options_match_oracle(hss, case):
             assert np.array_equal(_host(off, np.uint64), ideal)
 
 
+BUDGET_CASES = [
+    # kind, n, p, eps, seed, bits, payload, probes per processor per round
+    ("uniform64", 1 << 18, 64, 0.02, 31, 64, False, 5),
+    ("SKEW2", 100_000, 16, 0.05, 32, 64, True, 1),
+    ("uniform32", 1 << 17, 32, 0.02, 33, 32, True, 3),
+    ("GAUSS", 1 << 16, 128, 0.05, 34, 64, False, 1),
+]
+
+
+@pytest.mark.parametrize("case", BUDGET_CASES,
+                         ids=[f"{c[0]}-{c[1]}-p{c[2]}-c{c[7]}" for c in BUDGET_CASES])
+def test_probe_budget_matches_oracle(hss, case):
+    """The fixed probe budget: each round's rate is set on the device from
+    the domain it measured; trace and outputs equal the oracle's."""
+    kind, n, p, eps, seed, bits, payload, c = case
+    _say(f"[parity] budget {kind} n={n} p={p} eps={eps} c={c} payload={payload}")
+    keys = _keys(kind, n, seed, bits)
+    vals = (np.arange(n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)) if payload else None
+    kd = _dev(keys)
+    vd = None if vals is None else _dev(vals)
+    with hss.Plan(n, p, eps, key_bytes=keys.itemsize, payload=payload, trace_level=1,
+                  probes_per_round=c) as plan:
+        ref = oracle.hss(keys, p, eps, seed, vals=vals, mode="partition", probes_per_round=c)
+        assert ref.status == 0
+        for call in range(2):   # the second call rewrites the device rates
+            ko, vo, off = plan.partition(kd, seed, vd)
+            assert np.array_equal(_host(off, np.uint64), ref.offsets), call
+            assert np.array_equal(_host(ko, keys.dtype), ref.keys), call
+            if payload:
+                assert np.array_equal(_host(vo, np.uint64), ref.vals), call
+            _compare_trace(plan, ref, p)
+
+
 def test_force_full_sample_exact_splitters(hss):
     n, p = 50_000, 13
     _say(f"[parity] force_full_sample n={n} p={p}")
