@@ -76,6 +76,9 @@ constexpr uint32_t kMaxRateRounds = 64;  // rounds kept in the rate table
 // Expected first-round probes above which they are sorted by the segmented
 // sort rather than ranked pairwise inside their interval.
 constexpr uint64_t kBigRound = 16384;
+// First round whose ranks are searched inside the probes' interval slices
+// (round 1 has one interval, the whole input: searched by segment chunks).
+constexpr uint32_t kPairRankFrom = 2;
 
 struct RoundRecord {
     uint64_t domain = 0, m = 0;
@@ -638,6 +641,7 @@ hss_status engine_init(Engine& E) {
     r.thresh = E.thresh_d;
     r.all = E.all_d;
     r.budget = E.tune.probes_per_round;
+    r.pair_rank_from = kPairRankFrom;
     r.seg_off = E.seg_off;
     r.seg_inst = E.seg_inst;
     r.row_inst = E.row_inst;
@@ -776,7 +780,7 @@ hss_status big_first_round(Engine& E, hipStream_t s) {
                       (uint64_t)nivl * tiles_of(m) * 256 + 256 <= E.counts_words &&
                       nivl <= msd_segs;
     if (!fits) {   // an overrun (the caller regrows) or an unexpected shape
-        HIP_TRY(launch_round_tail(r, s, false, &E.prof));
+        HIP_TRY(launch_round_tail(r, 1, s, false, &E.prof));
         return HSS_OK;
     }
     const uint64_t need = 4 * m + nivl + 1;
@@ -825,7 +829,7 @@ hss_status big_first_round(Engine& E, hipStream_t s) {
     hs.vals_out = r.ps_tag;
     HIP_TRY(hybrid_sort(hs, s, E.hh));
     HIP_TRY(launch_probe_finish(r, s));
-    HIP_TRY(launch_round_tail(r, s, true, &E.prof));
+    HIP_TRY(launch_round_tail(r, 1, s, true, &E.prof));
     return HSS_OK;
 }
 

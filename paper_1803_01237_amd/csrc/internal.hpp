@@ -444,6 +444,8 @@ struct RoundArgs {
     uint8_t* all;                  // n_inst x J: 1 = every tag of the domain is a probe
     uint32_t budget;               // c > 0: rate c p / |gamma| set on the device each round
                                    // (one instance)
+    uint32_t pair_rank_from;       // first round ranked per (probe, segment) pair inside
+                                   // the probe's interval slice (earlier: by segment chunks)
     const uint64_t* seg_off;       // S+1 positions
     const uint32_t* seg_inst;      // S
     const uint32_t* row_inst;      // Q
@@ -511,7 +513,8 @@ hipError_t launch_finalize(const RoundArgs& a, uint64_t* chi_all, hipStream_t s)
 // every interval's probes in (key, tag) order into ps_key / ps_tag and run
 // launch_probe_finish), ranks, reduction and settling.
 hipError_t launch_round_head(const RoundArgs& a, uint32_t j, hipStream_t s);
-hipError_t launch_round_tail(const RoundArgs& a, hipStream_t s, bool probes_sorted, Profiler* prof);
+hipError_t launch_round_tail(const RoundArgs& a, uint32_t j, hipStream_t s, bool probes_sorted,
+                             Profiler* prof);
 hipError_t launch_probe_offsets(const RoundArgs& a, uint64_t* out, hipStream_t s);
 hipError_t launch_probe_finish(const RoundArgs& a, hipStream_t s);
 // The per-call record of one instance, written on the stream (no host copy).

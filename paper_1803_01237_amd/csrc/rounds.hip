@@ -40,6 +40,7 @@ namespace {
 constexpr int kT = 256;
 constexpr int kScanT = 1024;            // threads of the one-workgroup scans
 constexpr int kSampleGrid = 4096;       // workgroups of the sampler
+constexpr int kPairGrid = 8192;         // workgroups of the per-pair rank search
 constexpr uint32_t kRankFences = kRankChunk / kFenceStride;
 constexpr uint32_t kReduceRows = 16;    // segments summed per reduction workgroup
 constexpr uint32_t kOrderLanes = 64;    // probes per ordering workgroup
@@ -656,6 +657,67 @@ __global__ __launch_bounds__(256) void rank_kernel(RoundArgs a) {
     }
 }
 
+// Rounds after the first: probe e lies strictly inside its interval, so its
+// count in segment s lies in the interval's slice [lo, hi) of s (section
+// 4.2.2: the search is confined to the splitter interval).  An empty slice
+// gives lo without a read; a short one is searched directly; a longer one
+// through its own fences first, then one kFenceStride-key block.  Thread per
+// (probe, segment) pair, in count-matrix order (probes of one segment on
+// consecutive threads).
+template <typename K>
+__global__ __launch_bounds__(256) void rank_pairs_kernel(RoundArgs a) {
+    if (halted(a)) return;
+    const uint64_t total = a.ctr->cm_need;
+    const K* B = (const K*)a.B;
+    for (uint64_t x = (uint64_t)blockIdx.x * 256 + threadIdx.x; x < total;
+         x += (uint64_t)gridDim.x * 256) {
+        const uint32_t I = a.n_inst > 1 ? last_le(a.cm_off, a.n_inst, x) : 0u;
+        const uint32_t m = a.inst_pm[I];
+        const uint64_t rem = x - a.cm_off[I];
+        const uint32_t sl = (uint32_t)(rem / m);
+        const uint64_t e = a.inst_plo[I] + rem % m;
+        const InstDesc& D = a.inst[I];
+        const uint32_t s = D.seg0 + sl;
+        const uint64_t s0 = a.seg_off[s];              // position of the segment
+        const uint32_t t = a.ps_seg[e];
+        uint64_t cnt;
+        if (t == s) {
+            cnt = a.ps_tag[e] - (s0 - D.pos0);         // its own place
+        } else {
+            const uint32_t row = a.ivl_row[a.ps_ivl[e]];
+            const uint64_t cell = D.tab0 + (uint64_t)(row - D.row0) * D.p + sl;
+            const uint64_t lo = a.lrank[row] == kNone ? 0 : a.lpos[cell];
+            const uint64_t hi = a.urank[row] == kNone ? a.seg_off[s + 1] - s0 : a.upos[cell];
+            if (hi <= lo) {
+                cnt = lo;
+            } else {
+                const K key = (K)a.ps_key[e];
+                const bool eqb = s < t;   // equal keys of earlier segments precede
+                const K* Bs = B + s0;
+                uint64_t q0 = lo, q1 = hi;
+                if (hi - lo > 2 * kFenceStride) {
+                    // fences f with f * kFenceStride in [lo, hi): the counted
+                    // ones form a prefix; the answer follows the last of them
+                    const uint64_t* F = a.fences.key + a.fences.base[s];
+                    uint64_t f0 = (lo + kFenceStride - 1) / kFenceStride;
+                    const uint64_t fl = f0;
+                    uint64_t f1 = (hi + kFenceStride - 1) / kFenceStride;
+                    const uint64_t fh = f1;
+                    while (f0 < f1) {
+                        const uint64_t mid = (f0 + f1) >> 1;
+                        const K fk = (K)F[mid];
+                        if (eqb ? (fk <= key) : (fk < key)) f0 = mid + 1; else f1 = mid;
+                    }
+                    if (f0 > fl) q0 = (f0 - 1) * kFenceStride + 1;
+                    if (f0 < fh) q1 = f0 * kFenceStride;
+                }
+                cnt = count_before<K>(Bs, q0, q1, key, eqb);
+            }
+        }
+        a.cmat[x] = (uint32_t)cnt;
+    }
+}
+
 // Sorted-probe path (large rounds sorted by the segmented sort): the
 // interval offsets as 64-bit segment bounds for the sort.
 __global__ void probe_offsets_kernel(RoundArgs a, uint64_t* __restrict__ out) {
@@ -856,7 +918,7 @@ static uint32_t interval_bound(const RoundArgs& a) {
 hipError_t launch_round(const RoundArgs& a, uint32_t j, hipStream_t s, Profiler* prof) {
     const hipError_t e = launch_round_head(a, j, s);
     if (e != hipSuccess) return e;
-    return launch_round_tail(a, s, false, prof);
+    return launch_round_tail(a, j, s, false, prof);
 }
 
 hipError_t launch_round_head(const RoundArgs& a, uint32_t j, hipStream_t s) {
@@ -878,13 +940,18 @@ hipError_t launch_round_head(const RoundArgs& a, uint32_t j, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_round_tail(const RoundArgs& a, hipStream_t s, bool probes_sorted, Profiler* prof) {
+hipError_t launch_round_tail(const RoundArgs& a, uint32_t j, hipStream_t s, bool probes_sorted,
+                             Profiler* prof) {
     (void)prof;
     if (!probes_sorted) {
         const uint64_t tiles_bound = (a.cap + kOrderLanes - 1) / kOrderLanes + interval_bound(a);
         hipLaunchKernelGGL(order_kernel, dim3((unsigned)tiles_bound), dim3(kOrderThreads), 0, s, a);
     }
-    if (a.n_chunks > 0) {
+    if (j >= a.pair_rank_from) {
+        // every probe searched inside its own interval slice
+        if (a.key_bytes == 4) hipLaunchKernelGGL(rank_pairs_kernel<uint32_t>, dim3(kPairGrid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(rank_pairs_kernel<uint64_t>, dim3(kPairGrid), dim3(256), 0, s, a);
+    } else if (a.n_chunks > 0) {
         if (a.key_bytes == 4) hipLaunchKernelGGL(rank_kernel<uint32_t>, dim3(a.n_chunks), dim3(256), 0, s, a);
         else hipLaunchKernelGGL(rank_kernel<uint64_t>, dim3(a.n_chunks), dim3(256), 0, s, a);
     }
