@@ -330,6 +330,8 @@ def served_bench(count, mults, check_every):
                      "throughput_gkeys_s": round(total / makespan / 1e9, 3),
                      "makespan_s": round(makespan, 3), "batches": st["batches"],
                      "mean_requests_per_batch": round(count / max(st["batches"], 1), 2),
+                     "max_concurrent_batches": st["max_concurrent_batches"],
+                     "max_admitted_gb": round(st["max_admitted_bytes"] / 1e9, 2),
                      "submit_lag_p99_ms": round(float(np.percentile(np.array(lag) * 1e3, 99)), 3),
                      "checked_against_solo": len(range(0, count, check_every)),
                      "all_equal": bool(same)})
@@ -338,7 +340,8 @@ def served_bench(count, mults, check_every):
     return {"requests": count, "keys": total, "plain_capacity_gkeys_s": round(capacity / 1e9, 3),
             "shape": "N = floor(2^U(14,26)) u64 keys + u64 payload, p = clamp(floor(e^U(ln 64, ln 2049)), "
                      "64, 2048), eps in {0.02, 0.05}, keys drawn on the device (torch generator per request), "
-                     "Poisson arrivals", "runs": runs}
+                     "Poisson arrivals", "server": "2 workers (streams), 64 GiB HBM budget",
+            "runs": runs}
 
 
 def main():

@@ -243,14 +243,19 @@ hss_status hss_batch_profile_read(hss_batch_t batch, uint32_t family, double* ms
 
 /*
  * Server: requests of any shape arriving over time, each an hss_partition of
- * its own input (the served workload of section 7's setting: independent
- * sorts submitted by clients).  A worker thread of the server takes the
- * requests queued when it becomes free -- in submission order, of one key
- * type and payload choice, within the batch limits -- and runs them as one
- * batch on a stream of its own, with device memory from a cache of blocks
- * kept between batches (no allocation once the cache covers the load).
- * Every request's outputs equal those of hss_partition of a plan with its
- * (N, p, eps, key type, payload) for its seed and input.
+ * its own input (the served workload: independent sorts submitted by
+ * clients), with continuous batching.  Worker threads of the server, each on
+ * a stream of its own, take the requests queued when they become free -- in
+ * submission order, of one key type and payload choice, within the batch
+ * limits -- and run them as one batch; requests that arrive while other
+ * batches are on the GPU start on a free worker as soon as the HBM budget
+ * admits them, so their work overlaps on the device.  A request is admitted
+ * when its footprint (inputs, outputs and its share of the workspace)
+ * fits the budget left by the batches running (a request above the whole
+ * budget runs when nothing else does).  Device memory comes from a cache of
+ * blocks kept between batches (no allocation once the cache covers the
+ * load).  Every request's outputs equal those of hss_partition of a plan
+ * with its (N, p, eps, key type, payload) for its seed and input.
  */
 typedef struct hss_server_s* hss_server_t;
 
@@ -261,7 +266,7 @@ typedef struct {
     double eps;                 /* 0 < eps < 1                              */
     uint64_t seed;              /* Philox stream of the request's rounds    */
     const void* keys_in;        /* N keys on the device, fully written when */
-                                /* submitted (the server's stream does not  */
+                                /* submitted (the server's streams do not   */
                                 /* wait on the writer's)                    */
     const uint64_t* vals_in;    /* N payload words, or NULL                 */
     void* keys_out;             /* N keys, bucket order as hss_partition    */
@@ -269,14 +274,22 @@ typedef struct {
     uint64_t* offsets;          /* p+1 words: chi                           */
 } hss_request;
 
-/*
- * hss_server_create -- start a server on the current device.
- *   max_batch_keys      keys per batch (0: 2^30; at most 2^32 - 1); a single
- *                       request larger than this still runs, alone
- *   max_batch_requests  requests per batch (0: 1024)
- */
-hss_status hss_server_create(hss_server_t* out, uint64_t max_batch_keys,
-                             uint32_t max_batch_requests);
+typedef struct {
+    uint64_t max_batch_keys;    /* keys per batch (0: 2^30; below 2^32); a  */
+                                /* single larger request still runs, alone  */
+    uint32_t max_batch_requests;/* requests per batch (0: 1024)             */
+    uint32_t workers;           /* batches on the GPU at once (0: 2)        */
+    uint64_t hbm_budget;        /* bytes of admitted requests' footprints   */
+                                /* at once (0: 64 GiB)                      */
+} hss_server_config;
+
+/* hss_server_create -- start a server on the current device; cfg NULL: the
+ * defaults above. */
+hss_status hss_server_create(hss_server_t* out, const hss_server_config* cfg);
+
+/* Bytes a request counts against the budget: its inputs and outputs and the
+ * workspace of its keys in a batch. */
+uint64_t hss_server_footprint(const hss_request* req);
 
 /* Finish every submitted request, stop the worker and release the server's
  * memory.  NULL is ok. */
@@ -307,9 +320,10 @@ hss_status hss_server_wait(hss_server_t server, uint64_t ticket, hss_status* res
 /* Seconds on the server's monotonic clock (the clock of t_submit, t_done). */
 double hss_server_clock(void);
 
-/* Batches run, requests finished and their keys, since creation. */
+/* Since creation: batches run, requests finished and their keys, the most
+ * batches on the GPU at once and the most budget bytes admitted at once. */
 hss_status hss_server_stats(hss_server_t server, uint64_t* batches, uint64_t* requests,
-                            uint64_t* keys);
+                            uint64_t* keys, uint32_t* max_concurrent, uint64_t* max_admitted);
 
 const char* hss_status_string(hss_status status);
 

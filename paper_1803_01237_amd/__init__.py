@@ -45,7 +45,7 @@ EXPORTS = [
     "hss_batch_plan", "hss_batch_destroy", "hss_batch_workspace_bytes", "hss_batch_partition",
     "hss_batch_profile", "hss_batch_profile_reset", "hss_batch_profile_read",
     "hss_server_create", "hss_server_destroy", "hss_server_submit", "hss_server_poll",
-    "hss_server_wait", "hss_server_clock", "hss_server_stats",
+    "hss_server_wait", "hss_server_clock", "hss_server_stats", "hss_server_footprint",
     "hss_status_string", "hss_last_error",
 ]
 
@@ -130,8 +130,15 @@ class _Request(C.Structure):
                 ("keys_out", C.c_void_p), ("vals_out", C.c_void_p), ("offsets", C.c_void_p)]
 
 
-_lib.hss_server_create.argtypes = [C.POINTER(_vp), _u64, _u32]
+class _ServerConfig(C.Structure):
+    _fields_ = [("max_batch_keys", C.c_uint64), ("max_batch_requests", C.c_uint32),
+                ("workers", C.c_uint32), ("hbm_budget", C.c_uint64)]
+
+
+_lib.hss_server_create.argtypes = [C.POINTER(_vp), C.POINTER(_ServerConfig)]
 _lib.hss_server_create.restype = C.c_int
+_lib.hss_server_footprint.argtypes = [C.POINTER(_Request)]
+_lib.hss_server_footprint.restype = _u64
 _lib.hss_server_destroy.argtypes = [_vp]
 _lib.hss_server_destroy.restype = None
 _lib.hss_server_submit.argtypes = [_vp, C.POINTER(_Request), C.POINTER(_u64)]
@@ -143,7 +150,8 @@ _lib.hss_server_wait.argtypes = [_vp, _u64, C.POINTER(C.c_int), C.POINTER(_dbl),
 _lib.hss_server_wait.restype = C.c_int
 _lib.hss_server_clock.argtypes = []
 _lib.hss_server_clock.restype = _dbl
-_lib.hss_server_stats.argtypes = [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64)]
+_lib.hss_server_stats.argtypes = [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64),
+                                  C.POINTER(_u32), C.POINTER(_u64)]
 _lib.hss_server_stats.restype = C.c_int
 _lib.hss_status_string.argtypes = [C.c_int]
 _lib.hss_status_string.restype = C.c_char_p
@@ -437,15 +445,17 @@ class Served:
 
 
 class Server:
-    """Requests of any shape served as they arrive.  The library's worker
-    thread runs the queued requests (same key width and payload choice) as
-    batches on a stream of its own; each result equals the plain partition
-    of that request."""
+    """Requests of any shape served as they arrive, with continuous batching:
+    the library's worker threads (each on its own stream) run the queued
+    requests (same key width and payload choice) as batches, admitted under
+    an HBM budget, so batches overlap on the device; each result equals the
+    plain partition of that request."""
 
-    def __init__(self, max_batch_keys: int = 0, max_batch_requests: int = 0):
+    def __init__(self, max_batch_keys: int = 0, max_batch_requests: int = 0, workers: int = 0,
+                 hbm_budget: int = 0):
         h = _vp()
-        _check(_lib.hss_server_create(C.byref(h), max_batch_keys, max_batch_requests),
-               "hss_server_create")
+        cfg = _ServerConfig(max_batch_keys, max_batch_requests, workers, hbm_budget)
+        _check(_lib.hss_server_create(C.byref(h), C.byref(cfg)), "hss_server_create")
         self._h = h
         self._live = {}
 
@@ -497,9 +507,18 @@ class Server:
         return self._retire(ticket, st.value, ts.value, td.value)
 
     def stats(self) -> dict:
-        b, r, k = _u64(), _u64(), _u64()
-        _check(_lib.hss_server_stats(self._h, C.byref(b), C.byref(r), C.byref(k)), "hss_server_stats")
-        return {"batches": int(b.value), "requests": int(r.value), "keys": int(k.value)}
+        b, r, k, mc, ma = _u64(), _u64(), _u64(), _u32(), _u64()
+        _check(_lib.hss_server_stats(self._h, C.byref(b), C.byref(r), C.byref(k), C.byref(mc),
+                                     C.byref(ma)), "hss_server_stats")
+        return {"batches": int(b.value), "requests": int(r.value), "keys": int(k.value),
+                "max_concurrent_batches": int(mc.value), "max_admitted_bytes": int(ma.value)}
+
+    @staticmethod
+    def footprint(n: int, p: int, key_bytes: int = 8, payload: bool = False) -> int:
+        """Budget bytes of a request of this shape."""
+        req = _Request(n, p, HSS_U64 if key_bytes == 8 else HSS_U32, 0.05, 0, None,
+                       1 if payload else None, None, None, None)
+        return int(_lib.hss_server_footprint(C.byref(req)))
 
     def close(self):
         if getattr(self, "_h", None):

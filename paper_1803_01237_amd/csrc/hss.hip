@@ -1124,9 +1124,9 @@ struct ServerReq {
 
 struct hss_server_s {
     int device = 0;
-    hipStream_t stream = nullptr;
     uint64_t max_keys = 0;
     uint32_t max_reqs = 0;
+    uint64_t budget = 0;
     BlockCache cache;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -1134,22 +1134,33 @@ struct hss_server_s {
     std::unordered_map<uint64_t, ServerReq> reqs;
     uint64_t next_ticket = 1;
     bool stop = false;
-    std::thread worker;
-    uint64_t batches = 0, served = 0, keys = 0;
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> streams;   // one per worker
+    uint64_t admitted = 0;              // footprint bytes of the batches running
+    uint32_t running = 0;
+    uint64_t batches = 0, served = 0, keys = 0, max_admitted = 0;
+    uint32_t max_running = 0;
 };
 
 namespace {
 
+// Budget bytes of a request: inputs and outputs, and the engine's share of its
+// keys (two key and payload buffers, fences, per-segment tables).
+uint64_t footprint(const hss_request& r) {
+    const uint64_t w = (r.key_type == HSS_U32 ? 4u : 8u) + (r.vals_in ? 8u : 0u);
+    return 4 * r.n * w + r.n / 2 + 12ull * ((uint64_t)r.p + 1) * r.p + (1ull << 20);
+}
+
 // One batch of queued requests (same key type and payload choice), run like
-// hss_batch_partition on the server's stream with memory from its cache.
-hss_status run_server_batch(hss_server_s* S, const std::vector<hss_request>& rq) {
+// hss_batch_partition on a worker's stream with memory from the cache.
+hss_status run_server_batch(hss_server_s* S, hipStream_t stream, const std::vector<hss_request>& rq) {
     std::unique_ptr<Engine> E(new (std::nothrow) Engine());
     if (!E) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
     E->batch = true;
     E->key_bytes = rq[0].key_type == HSS_U32 ? 4 : 8;
     E->payload = rq[0].vals_in != nullptr;
     E->mem = &S->cache;
-    E->own_stream = S->stream;
+    E->own_stream = stream;
     for (const hss_request& r : rq) {
         hss_status st = new_engine_instance(*E, r.n, r.p, r.eps);
         if (st != HSS_OK) return st;
@@ -1159,23 +1170,33 @@ hss_status run_server_batch(hss_server_s* S, const std::vector<hss_request>& rq)
     for (size_t i = 0; i < rq.size(); ++i)
         E->h_run[i] = InstRun{rq[i].seed, rq[i].keys_in, rq[i].vals_in, rq[i].keys_out, rq[i].vals_out,
                               rq[i].offsets};
-    HIP_TRY(hipMemcpyAsync(E->run_d, E->h_run, rq.size() * sizeof(InstRun), hipMemcpyHostToDevice, S->stream));
-    HIP_TRY(launch_counters_reset(E->ra.ctr, S->stream));
-    st = engine_run(*E, nullptr, nullptr, nullptr, nullptr, S->stream, false);
+    HIP_TRY(hipMemcpyAsync(E->run_d, E->h_run, rq.size() * sizeof(InstRun), hipMemcpyHostToDevice, stream));
+    HIP_TRY(launch_counters_reset(E->ra.ctr, stream));
+    st = engine_run(*E, nullptr, nullptr, nullptr, nullptr, stream, false);
     if (st != HSS_OK) return st;
-    return finish(*E, S->stream);   // synchronises the stream
+    return finish(*E, stream);   // synchronises the stream
 }
 
-void server_loop(hss_server_s* S) {
+// A worker: takes the requests at the head of the queue that the budget
+// admits (in submission order, of the head's class, within the batch limits)
+// and runs them as one batch on its stream; the head waits while the
+// batches already running leave it no room, unless none is running.
+void server_loop(hss_server_s* S, uint32_t wid) {
     (void)hipSetDevice(S->device);
+    const hipStream_t stream = S->streams[wid];
     for (;;) {
         std::vector<uint64_t> tickets;
         std::vector<hss_request> rq;
+        uint64_t fp_total = 0;
+        bool more = false;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv_work.wait(lk, [S] { return S->stop || !S->queue.empty(); });
+            S->cv_work.wait(lk, [S] {
+                if (S->queue.empty()) return S->stop;
+                const uint64_t fp = footprint(S->reqs[S->queue.front()].r);
+                return S->running == 0 || S->admitted + fp <= S->budget;
+            });
             if (S->queue.empty()) return;   // stopping, nothing left
-            // in submission order: requests of the first one's class, within the limits
             const hss_request& f = S->reqs[S->queue.front()].r;
             const bool pay = f.vals_in != nullptr;
             const hss_key_type kt = f.key_type;
@@ -1183,16 +1204,24 @@ void server_loop(hss_server_s* S) {
             while (!S->queue.empty() && rq.size() < S->max_reqs) {
                 const hss_request& r = S->reqs[S->queue.front()].r;
                 if (r.key_type != kt || (r.vals_in != nullptr) != pay) break;
-                if (!rq.empty() && total + r.n > S->max_keys) break;
+                const uint64_t fp = footprint(r);
+                if (!rq.empty() && (total + r.n > S->max_keys || S->admitted + fp_total + fp > S->budget)) break;
                 total += r.n;
+                fp_total += fp;
                 rq.push_back(r);
                 tickets.push_back(S->queue.front());
                 S->queue.pop_front();
             }
+            S->admitted += fp_total;
+            S->running += 1;
+            S->max_running = std::max(S->max_running, S->running);
+            S->max_admitted = std::max(S->max_admitted, S->admitted);
+            more = !S->queue.empty();
         }
+        if (more) S->cv_work.notify_one();   // another worker may take the rest
         hss_status st;
         try {
-            st = run_server_batch(S, rq);
+            st = run_server_batch(S, stream, rq);
         } catch (...) {
             st = fail(HSS_ERR_DEVICE, "unexpected exception");
         }
@@ -1209,8 +1238,11 @@ void server_loop(hss_server_s* S) {
             }
             S->batches += 1;
             S->served += tickets.size();
+            S->admitted -= fp_total;
+            S->running -= 1;
         }
         S->cv_done.notify_all();
+        S->cv_work.notify_all();   // budget freed
     }
 }
 
@@ -1569,25 +1601,36 @@ hss_status hss_batch_profile_read(hss_batch_t Bt, uint32_t family, double* ms, u
 
 // -------------------------------------------------------------- server ----
 
-hss_status hss_server_create(hss_server_t* out, uint64_t max_batch_keys, uint32_t max_batch_requests) {
+hss_status hss_server_create(hss_server_t* out, const hss_server_config* cfg) {
     try {
         if (!out) return fail(HSS_ERR_INVALID_ARG, "null server pointer");
         *out = nullptr;
-        if (max_batch_keys >= (1ull << 32)) return fail(HSS_ERR_INVALID_ARG, "max_batch_keys must be below 2^32");
+        hss_server_config c{};
+        if (cfg) c = *cfg;
+        if (c.max_batch_keys >= (1ull << 32)) return fail(HSS_ERR_INVALID_ARG, "max_batch_keys must be below 2^32");
+        if (c.workers > 16) return fail(HSS_ERR_INVALID_ARG, "at most 16 workers");
         std::unique_ptr<hss_server_s> S(new (std::nothrow) hss_server_s());
         if (!S) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
-        S->max_keys = max_batch_keys ? max_batch_keys : (1ull << 30);
-        S->max_reqs = max_batch_requests ? max_batch_requests : 1024u;
+        S->max_keys = c.max_batch_keys ? c.max_batch_keys : (1ull << 30);
+        S->max_reqs = c.max_batch_requests ? c.max_batch_requests : 1024u;
+        S->budget = c.hbm_budget ? c.hbm_budget : (64ull << 30);
+        const uint32_t nw = c.workers ? c.workers : 2u;
         HIP_TRY(hipGetDevice(&S->device));
-        // default priority; no implicit ordering with other streams
-        HIP_TRY(hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking));
-        S->worker = std::thread(server_loop, S.get());
+        for (uint32_t w = 0; w < nw; ++w) {
+            // default priority; no implicit ordering with other streams
+            hipStream_t st = nullptr;
+            HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            S->streams.push_back(st);
+        }
+        for (uint32_t w = 0; w < nw; ++w) S->workers.emplace_back(server_loop, S.get(), w);
         *out = S.release();
         return HSS_OK;
     } catch (...) {
         return fail(HSS_ERR_DEVICE, "unexpected exception");
     }
 }
+
+uint64_t hss_server_footprint(const hss_request* req) { return req ? footprint(*req) : 0; }
 
 void hss_server_destroy(hss_server_t S) {
     if (!S) return;
@@ -1597,11 +1640,12 @@ void hss_server_destroy(hss_server_t S) {
             S->stop = true;
         }
         S->cv_work.notify_all();
-        if (S->worker.joinable()) S->worker.join();
+        for (std::thread& w : S->workers)
+            if (w.joinable()) w.join();
         (void)hipSetDevice(S->device);
-        if (S->stream) {
-            (void)hipStreamSynchronize(S->stream);
-            (void)hipStreamDestroy(S->stream);
+        for (hipStream_t st : S->streams) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
         }
         delete S;
     } catch (...) {
@@ -1661,12 +1705,15 @@ hss_status hss_server_wait(hss_server_t S, uint64_t ticket, hss_status* result, 
 
 double hss_server_clock(void) { return clock_s(); }
 
-hss_status hss_server_stats(hss_server_t S, uint64_t* batches, uint64_t* requests, uint64_t* keys) {
+hss_status hss_server_stats(hss_server_t S, uint64_t* batches, uint64_t* requests, uint64_t* keys,
+                            uint32_t* max_concurrent, uint64_t* max_admitted) {
     if (!S) return fail(HSS_ERR_INVALID_ARG, "null server");
     std::lock_guard<std::mutex> lk(S->mu);
     if (batches) *batches = S->batches;
     if (requests) *requests = S->served;
     if (keys) *keys = S->keys;
+    if (max_concurrent) *max_concurrent = S->max_running;
+    if (max_admitted) *max_admitted = S->max_admitted;
     return HSS_OK;
 }
 

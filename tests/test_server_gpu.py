@@ -119,3 +119,50 @@ def test_server_rejects_bad_requests(hss):
         with pytest.raises(hss.HssError):
             srv.submit(k[1:], 4, 0.05, 1)              # misaligned keys
         assert srv.stats()["requests"] == 0
+
+
+def test_batches_overlap_and_match_alone(hss):
+    """Continuous batching: with several workers and a full queue, batches run
+    at once on their streams; each result is still the one the request gets
+    alone."""
+    reqs = [(int(2 ** (14 + (i % 5))), 16 + (i % 7) * 8, 0.05, 8, i % 2 == 0, 8100 + i)
+            for i in range(24)]
+    with hss.Server(max_batch_requests=4, workers=3) as srv:
+        tickets, held = [], []
+        for (n, p, eps, kb, pay, dseed) in reqs:
+            keys, vals = _inputs(n, kb, pay, dseed)
+            held.append((_dev(keys), _dev(vals) if pay else None))
+        torch.cuda.synchronize()
+        for (n, p, eps, kb, pay, dseed), (kd, vd) in zip(reqs, held):
+            tickets.append(srv.submit(kd, p, eps, dseed, vd, sync=False))
+        done = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    _say(f"[server] overlap: {st}")
+    assert st["requests"] == len(reqs)
+    assert st["max_concurrent_batches"] >= 2
+    for (n, p, eps, kb, pay, dseed), (kd, vd), r in zip(reqs, held, done):
+        with hss.Plan(n, p, eps, key_bytes=kb, payload=pay) as plan:
+            ko, vo, off = plan.partition(kd, dseed, vd)
+            torch.cuda.synchronize()
+            assert torch.equal(off, r.offsets) and torch.equal(ko, r.keys_out)
+            if pay:
+                assert torch.equal(vo, r.vals_out)
+
+
+def test_budget_bounds_admission(hss):
+    """The HBM budget bounds what runs at once: with room for two requests,
+    no more than two are admitted together, whatever the workers."""
+    n, p = 1 << 16, 32
+    fp = hss.Server.footprint(n, p, 8, True)
+    with hss.Server(workers=4, hbm_budget=2 * fp, max_batch_requests=1) as srv:
+        tickets = []
+        for i in range(12):
+            keys, vals = _inputs(n, 8, True, 8200 + i)
+            tickets.append((srv.submit(_dev(keys), p, 0.05, 40 + i, _dev(vals)), keys, vals, 40 + i))
+        for t, keys, vals, seed in tickets:
+            r = srv.wait(t)
+            ref = oracle.hss(keys, p, 0.05, seed, vals=vals, mode="partition", trace_level=0)
+            assert np.array_equal(r.vals_out.cpu().numpy().view(np.uint64), ref.vals)
+        st = srv.stats()
+    assert st["max_admitted_bytes"] <= 2 * fp
+    assert st["max_concurrent_batches"] <= 2
