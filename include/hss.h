@@ -70,7 +70,11 @@ typedef struct {
                                    of the round's domain gamma is a probe with
                                    probability min(1, c p / |gamma|), in place of
                                    the rate schedule; single plans only          */
-    uint32_t reserved[2];       /* must be zero */
+    uint32_t plain_launches;    /* 1: launch every round kernel; 0: the rounds
+                                   queued before the first read-back run from a
+                                   HIP graph captured once per plan (captured
+                                   again when the probe buffers grow)           */
+    uint32_t reserved[1];       /* must be zero */
 } hss_tuning;
 
 /*

@@ -64,7 +64,7 @@ class _Tuning(C.Structure):
     _fields_ = [("max_rounds", C.c_uint32), ("k_override", C.c_uint32),
                 ("force_full_sample", C.c_uint32), ("trace_level", C.c_uint32),
                 ("lsd_only", C.c_uint32), ("probes_per_round", C.c_uint32),
-                ("reserved", C.c_uint32 * 2)]
+                ("plain_launches", C.c_uint32), ("reserved", C.c_uint32 * 1)]
 
 
 _vp, _u64, _u32, _dbl = C.c_void_p, C.c_uint64, C.c_uint32, C.c_double
@@ -206,9 +206,10 @@ class Plan:
 
     def __init__(self, n: int, p: int, eps: float, key_bytes: int = 8, payload: bool = False,
                  max_rounds: int = 0, k_override: int = 0, force_full_sample: bool = False,
-                 trace_level: int = 0, lsd_only: bool = False, probes_per_round: int = 0):
+                 trace_level: int = 0, lsd_only: bool = False, probes_per_round: int = 0,
+                 plain_launches: bool = False):
         tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, trace_level,
-                      1 if lsd_only else 0, probes_per_round)
+                      1 if lsd_only else 0, probes_per_round, 1 if plain_launches else 0)
         h = _vp()
         kt = HSS_U64 if key_bytes == 8 else HSS_U32
         _check(_lib.hss_plan(C.byref(h), n, p, eps, kt, 1 if payload else 0, C.byref(tun)),

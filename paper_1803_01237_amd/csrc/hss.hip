@@ -243,10 +243,19 @@ struct Engine {
     MemSource* mem = nullptr;
     hipStream_t own_stream = nullptr;
 
+    // the first rounds of a call as a captured graph, for the probe and
+    // count-matrix buffers it was captured with
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t rounds_exec = nullptr;
+    uint32_t rounds_exec_n = 0;
+    uint64_t rounds_exec_cap = 0, rounds_exec_cm = 0;
+
     ~Engine() {
         (void)hipSetDevice(device);
         if (own_stream) (void)hipStreamSynchronize(own_stream);
         else (void)hipDeviceSynchronize();
+        if (rounds_exec) (void)hipGraphExecDestroy(rounds_exec);
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
         for (void* q : {probe_mem, psort_mem, (void*)cmat, (void*)hh.fb_counts, (void*)hh.fb_sb_start,
                         (void*)hh.fb_sb_len, arena})
             if (q) dev_release(mem, q);
@@ -833,6 +842,37 @@ hss_status big_first_round(Engine& E, hipStream_t s) {
     return HSS_OK;
 }
 
+// Rounds 1..n queued in one go: from a graph captured once for the engine's
+// current probe and count-matrix buffers (on a stream of its own, so that
+// the caller's stream may be any stream), replayed on the caller's stream.
+hss_status launch_first_rounds(Engine& E, uint32_t n, hipStream_t s) {
+    RoundArgs& r = E.ra;
+    if (E.tune.plain_launches || E.own_stream) {
+        for (uint32_t j = 1; j <= n; ++j) HIP_TRY(launch_round(r, j, s, &E.prof));
+        return HSS_OK;
+    }
+    if (!E.rounds_exec || E.rounds_exec_n != n || E.rounds_exec_cap != E.cap || E.rounds_exec_cm != E.cm_cap) {
+        if (E.rounds_exec) HIP_TRY(hipGraphExecDestroy(E.rounds_exec));
+        E.rounds_exec = nullptr;
+        if (!E.capture_stream) HIP_TRY(hipStreamCreateWithFlags(&E.capture_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(E.capture_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t le = hipSuccess;
+        for (uint32_t j = 1; j <= n && le == hipSuccess; ++j) le = launch_round(r, j, E.capture_stream, nullptr);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(E.capture_stream, &g);
+        HIP_TRY(le);
+        HIP_TRY(ce);
+        const hipError_t ie = hipGraphInstantiate(&E.rounds_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIP_TRY(ie);
+        E.rounds_exec_n = n;
+        E.rounds_exec_cap = E.cap;
+        E.rounds_exec_cm = E.cm_cap;
+    }
+    HIP_TRY(hipGraphLaunch(E.rounds_exec, s));
+    return HSS_OK;
+}
+
 // Splitter rounds of every instance on the locally sorted buffer B; leaves
 // chi in chi_all and in every instance's offsets.
 hss_status determine_splitters(Engine& E, hipStream_t s) {
@@ -852,6 +892,11 @@ hss_status determine_splitters(Engine& E, hipStream_t s) {
             uint32_t stop = E.J;
             if (E.tune.max_rounds) stop = std::min(stop, E.tune.max_rounds);
             const uint32_t upto = std::min(j + chunk, stop);
+            if (j == 0 && upto > 1 && !E.big_first) {
+                const hss_status sg = launch_first_rounds(E, upto, s);
+                if (sg != HSS_OK) return sg;
+                j = upto;
+            }
             while (j < upto) {
                 ++j;
                 if (j == 1 && E.big_first) {

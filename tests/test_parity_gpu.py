@@ -369,3 +369,26 @@ def test_sort_buckets_straddling_power_of_two(hss, centre_bit):
         assert np.array_equal(_host(vs, np.uint64), vals[order])
         ref = oracle.hss(keys, p, 0.05, 9, vals=vals, mode="sort")
         assert np.array_equal(_host(off, np.uint64), ref.offsets)
+
+
+def test_graph_replays_match_plain_launches(hss):
+    """The first rounds run from a captured graph; replayed call after call,
+    with other device work and synchronisations in between and after the
+    probe buffers grew, every call equals the same call with plain launches
+    (and the oracle)."""
+    n, p, eps = 1 << 18, 64, 0.02
+    _say("[parity] graph replays against plain launches")
+    with hss.Plan(n, p, eps) as g, hss.Plan(n, p, eps, plain_launches=True) as f:
+        for call in range(6):
+            keys = _keys("uniform64" if call % 3 else "SKEW1", n, 50 + call, 64)
+            kd = _dev(keys)
+            junk = torch.randn(1 << 20, device="cuda").cumsum(0)   # unrelated eager work
+            ko, _, off = g.partition(kd, 70 + call)
+            torch.cuda.synchronize()
+            ko2, _, off2 = f.partition(kd, 70 + call)
+            torch.cuda.synchronize()
+            assert torch.equal(off, off2) and torch.equal(ko, ko2), call
+            if call in (0, 5):
+                ref = oracle.hss(keys, p, eps, 70 + call, mode="partition", trace_level=0)
+                assert np.array_equal(_host(off, np.uint64), ref.offsets), call
+            del junk
