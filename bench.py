@@ -109,8 +109,8 @@ def batched_bench(steps, count):
     kout = [torch.empty_like(k) for k in keys]
     offs = [torch.empty(sh[1] + 1, dtype=torch.int64, device=dev) for sh in shapes]
     total = sum(sh[0] for sh in shapes)
-    with hss.BatchPlan([(sh[0], sh[1], sh[2], sh[3]) for sh in shapes]) as bp:
-        bp.partition(keys, seeds, keys_out=kout, offsets=offs)
+    with hss.BatchPlan([(sh[0], sh[1], sh[2], sh[3]) for sh in shapes], autotune=True) as bp:
+        bp.partition(keys, seeds, keys_out=kout, offsets=offs)   # warmup, autotunes
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -412,7 +412,9 @@ def main():
     vout = torch.empty_like(vals) if payload else None
     off = torch.empty(p + 1, dtype=torch.int64, device=dev)
 
-    plan = hss.Plan(n, p, eps, key_bytes=8, payload=payload)
+    # the first warmup call runs the autotuner on this input (no warmup: no
+    # autotuning, so that no timed step searches)
+    plan = hss.Plan(n, p, eps, key_bytes=8, payload=payload, autotune=args.warmup > 0)
     log(f"[bench] workspace {plan.workspace_bytes / 2**30:.2f} GiB; warmup {args.warmup}")
     step = plan.partition if args.op == "partition" else plan.sort
     for _ in range(args.warmup):
@@ -433,6 +435,7 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = n / (ms_step * 1e-3) / 1e9
     tr = plan.trace()
+    knobs = plan.knobs()
     rounds = len(tr)
     ms_m = [r.m for r in tr]
     domains = [r.domain for r in tr]
@@ -502,6 +505,7 @@ def main():
         "cpu_baseline": cpu,
         "stages": stages,
         "rounds": rounds, "probes_per_round": ms_m, "domain_per_round": domains,
+        "knobs": knobs,
         "hss_sort_ms": None if sort_ms is None else round(sort_ms, 4),
         "hss_sort_gkeys_s": None if sort_ms is None else round(n / (sort_ms * 1e-3) / 1e9, 3),
         "batched": batched,

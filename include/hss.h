@@ -74,8 +74,24 @@ typedef struct {
                                    queued before the first read-back run from a
                                    HIP graph captured once per plan (captured
                                    again when the probe buffers grow)           */
-    uint32_t reserved[1];       /* must be zero */
+    uint32_t autotune;          /* 1: the first call tries the launch knobs of
+                                   hss_knobs on its own input, one knob at a
+                                   time, and keeps the fastest setting (the
+                                   outputs do not depend on the knobs)          */
+    uint32_t reserved[2];       /* must be zero */
 } hss_tuning;
+
+/* Launch knobs of a plan (hss_plan_knobs); none changes any output. */
+typedef struct {
+    uint32_t small_sort_cap;    /* keys sorted on chip per job of the local
+                                   sort: 2048 or 4096                           */
+    uint32_t sample_workgroups; /* grid of the sampler                          */
+    uint32_t pair_rank_from;    /* first round whose ranks are searched per
+                                   (probe, segment) inside the probe's interval
+                                   slice; earlier rounds by segment chunks     */
+    uint32_t pair_rank_workgroups; /* grid of that search                       */
+    uint32_t tuned;             /* 1 once the autotuner has run                 */
+} hss_knobs;
 
 /*
  * hss_plan -- validate (N, p, eps, key type) and prepare a plan.
@@ -328,6 +344,15 @@ double hss_server_clock(void);
  * batches on the GPU at once and the most budget bytes admitted at once. */
 hss_status hss_server_stats(hss_server_t server, uint64_t* batches, uint64_t* requests,
                             uint64_t* keys, uint32_t* max_concurrent, uint64_t* max_admitted);
+
+/* The launch knobs a plan (or, for a batch, its instances of one key type)
+ * runs with: the defaults, or what the autotuner chose on the first call. */
+hss_status hss_plan_knobs(hss_plan_t plan, hss_knobs* out);
+/* Set a plan's launch knobs (small_sort_cap 2048 or 4096, grids in [1, 65536],
+ * pair_rank_from >= 1; `tuned` is kept as given).  HSS_ERR_INVALID_ARG on
+ * other values. */
+hss_status hss_plan_set_knobs(hss_plan_t plan, const hss_knobs* knobs);
+hss_status hss_batch_knobs(hss_batch_t batch, hss_key_type kt, hss_knobs* out);
 
 const char* hss_status_string(hss_status status);
 

@@ -46,6 +46,7 @@ EXPORTS = [
     "hss_batch_profile", "hss_batch_profile_reset", "hss_batch_profile_read",
     "hss_server_create", "hss_server_destroy", "hss_server_submit", "hss_server_poll",
     "hss_server_wait", "hss_server_clock", "hss_server_stats", "hss_server_footprint",
+    "hss_plan_knobs", "hss_plan_set_knobs", "hss_batch_knobs",
     "hss_status_string", "hss_last_error",
 ]
 
@@ -64,7 +65,17 @@ class _Tuning(C.Structure):
     _fields_ = [("max_rounds", C.c_uint32), ("k_override", C.c_uint32),
                 ("force_full_sample", C.c_uint32), ("trace_level", C.c_uint32),
                 ("lsd_only", C.c_uint32), ("probes_per_round", C.c_uint32),
-                ("plain_launches", C.c_uint32), ("reserved", C.c_uint32 * 1)]
+                ("plain_launches", C.c_uint32), ("autotune", C.c_uint32),
+                ("reserved", C.c_uint32 * 2)]
+
+
+class _Knobs(C.Structure):
+    _fields_ = [("small_sort_cap", C.c_uint32), ("sample_workgroups", C.c_uint32),
+                ("pair_rank_from", C.c_uint32), ("pair_rank_workgroups", C.c_uint32),
+                ("tuned", C.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 _vp, _u64, _u32, _dbl = C.c_void_p, C.c_uint64, C.c_uint32, C.c_double
@@ -153,6 +164,12 @@ _lib.hss_server_clock.restype = _dbl
 _lib.hss_server_stats.argtypes = [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64),
                                   C.POINTER(_u32), C.POINTER(_u64)]
 _lib.hss_server_stats.restype = C.c_int
+_lib.hss_plan_knobs.argtypes = [_vp, C.POINTER(_Knobs)]
+_lib.hss_plan_knobs.restype = C.c_int
+_lib.hss_plan_set_knobs.argtypes = [_vp, C.POINTER(_Knobs)]
+_lib.hss_plan_set_knobs.restype = C.c_int
+_lib.hss_batch_knobs.argtypes = [_vp, C.c_int, C.POINTER(_Knobs)]
+_lib.hss_batch_knobs.restype = C.c_int
 _lib.hss_status_string.argtypes = [C.c_int]
 _lib.hss_status_string.restype = C.c_char_p
 _lib.hss_last_error.argtypes = []
@@ -207,9 +224,10 @@ class Plan:
     def __init__(self, n: int, p: int, eps: float, key_bytes: int = 8, payload: bool = False,
                  max_rounds: int = 0, k_override: int = 0, force_full_sample: bool = False,
                  trace_level: int = 0, lsd_only: bool = False, probes_per_round: int = 0,
-                 plain_launches: bool = False):
+                 plain_launches: bool = False, autotune: bool = False):
         tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, trace_level,
-                      1 if lsd_only else 0, probes_per_round, 1 if plain_launches else 0)
+                      1 if lsd_only else 0, probes_per_round, 1 if plain_launches else 0,
+                      1 if autotune else 0)
         h = _vp()
         kt = HSS_U64 if key_bytes == 8 else HSS_U32
         _check(_lib.hss_plan(C.byref(h), n, p, eps, kt, 1 if payload else 0, C.byref(tun)),
@@ -239,6 +257,18 @@ class Plan:
     @property
     def workspace_bytes(self) -> int:
         return int(_lib.hss_workspace_bytes(self._h))
+
+    def knobs(self) -> dict:
+        k = _Knobs()
+        _check(_lib.hss_plan_knobs(self._h, C.byref(k)), "hss_plan_knobs")
+        return k.as_dict()
+
+    def set_knobs(self, **kw):
+        k = _Knobs()
+        _check(_lib.hss_plan_knobs(self._h, C.byref(k)), "hss_plan_knobs")
+        for f, v in kw.items():
+            setattr(k, f, v)
+        _check(_lib.hss_plan_set_knobs(self._h, C.byref(k)), "hss_plan_set_knobs")
 
     def _outputs(self, keys, vals, keys_out, vals_out, offsets):
         torch = _torch()
@@ -359,12 +389,13 @@ class BatchPlan:
     (keys, seed[, vals]) per instance, in the same order."""
 
     def __init__(self, shapes, payload: bool = False, max_rounds: int = 0, k_override: int = 0,
-                 force_full_sample: bool = False):
+                 force_full_sample: bool = False, autotune: bool = False):
         self.shapes = [(int(n), int(p), float(e), int(kb)) for (n, p, e, kb) in shapes]
         arr = (_Shape * len(self.shapes))()
         for i, (n, p, e, kb) in enumerate(self.shapes):
             arr[i] = _Shape(n, p, HSS_U64 if kb == 8 else HSS_U32, e)
-        tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, 0, 0)
+        tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, 0, 0, 0, 0,
+                      1 if autotune else 0)
         h = _vp()
         _check(_lib.hss_batch_plan(C.byref(h), arr, len(self.shapes), 1 if payload else 0,
                                    C.byref(tun)), "hss_batch_plan")
@@ -418,6 +449,12 @@ class BatchPlan:
                         offsets[i].data_ptr())
         _check(_lib.hss_batch_partition(self._h, io, _stream_handle()), "hss_batch_partition")
         return keys_out, vals_out, offsets
+
+    def knobs(self, key_bytes: int = 8) -> dict:
+        k = _Knobs()
+        _check(_lib.hss_batch_knobs(self._h, HSS_U64 if key_bytes == 8 else HSS_U32, C.byref(k)),
+               "hss_batch_knobs")
+        return k.as_dict()
 
     def profile(self, enable: bool = True):
         _check(_lib.hss_batch_profile(self._h, 1 if enable else 0), "hss_batch_profile")

@@ -79,6 +79,10 @@ constexpr uint64_t kBigRound = 16384;
 // First round whose ranks are searched inside the probes' interval slices
 // (round 1 has one interval, the whole input: searched by segment chunks).
 constexpr uint32_t kPairRankFrom = 2;
+constexpr uint32_t kDefaultSmallCap = 2048;
+constexpr uint32_t kDefaultSampleGrid = 4096;
+constexpr uint32_t kDefaultPairFrom = kPairRankFrom;
+constexpr uint32_t kDefaultPairGrid = 8192;
 
 struct RoundRecord {
     uint64_t domain = 0, m = 0;
@@ -244,11 +248,16 @@ struct Engine {
     hipStream_t own_stream = nullptr;
 
     // the first rounds of a call as a captured graph, for the probe and
-    // count-matrix buffers it was captured with
+    // count-matrix buffers and the knobs it was captured with
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t rounds_exec = nullptr;
     uint32_t rounds_exec_n = 0;
     uint64_t rounds_exec_cap = 0, rounds_exec_cm = 0;
+    uint32_t rounds_exec_knobs = 0;
+
+    // launch knobs (none changes an output); knob_gen counts changes
+    hss_knobs knobs{kDefaultSmallCap, kDefaultSampleGrid, kDefaultPairFrom, kDefaultPairGrid, 0};
+    uint32_t knob_gen = 0;
 
     ~Engine() {
         (void)hipSetDevice(device);
@@ -650,7 +659,9 @@ hss_status engine_init(Engine& E) {
     r.thresh = E.thresh_d;
     r.all = E.all_d;
     r.budget = E.tune.probes_per_round;
-    r.pair_rank_from = kPairRankFrom;
+    r.pair_rank_from = E.knobs.pair_rank_from;
+    r.sample_grid = E.knobs.sample_workgroups;
+    r.pair_grid = E.knobs.pair_rank_workgroups;
     r.seg_off = E.seg_off;
     r.seg_inst = E.seg_inst;
     r.row_inst = E.row_inst;
@@ -743,6 +754,7 @@ hss_status segment_sort(Engine& E, bool first, const void* kin, const uint64_t* 
     hs.pj = E.pj;
     hs.sl = E.sl;
     hs.prof = &E.prof;
+    hs.cap_large = first && E.knobs.small_sort_cap > 2048;
     if (first && E.listed) {
         hs.num_segs = E.n_msd;
         hs.msd_seg = E.msd_seg;
@@ -851,7 +863,8 @@ hss_status launch_first_rounds(Engine& E, uint32_t n, hipStream_t s) {
         for (uint32_t j = 1; j <= n; ++j) HIP_TRY(launch_round(r, j, s, &E.prof));
         return HSS_OK;
     }
-    if (!E.rounds_exec || E.rounds_exec_n != n || E.rounds_exec_cap != E.cap || E.rounds_exec_cm != E.cm_cap) {
+    if (!E.rounds_exec || E.rounds_exec_n != n || E.rounds_exec_cap != E.cap || E.rounds_exec_cm != E.cm_cap ||
+        E.rounds_exec_knobs != E.knob_gen) {
         if (E.rounds_exec) HIP_TRY(hipGraphExecDestroy(E.rounds_exec));
         E.rounds_exec = nullptr;
         if (!E.capture_stream) HIP_TRY(hipStreamCreateWithFlags(&E.capture_stream, hipStreamNonBlocking));
@@ -868,6 +881,7 @@ hss_status launch_first_rounds(Engine& E, uint32_t n, hipStream_t s) {
         E.rounds_exec_n = n;
         E.rounds_exec_cap = E.cap;
         E.rounds_exec_cm = E.cm_cap;
+        E.rounds_exec_knobs = E.knob_gen;
     }
     HIP_TRY(hipGraphLaunch(E.rounds_exec, s));
     return HSS_OK;
@@ -1060,6 +1074,60 @@ hss_status finish(Engine& E, hipStream_t s) {
     return HSS_OK;
 }
 
+void set_knobs(Engine& E, const hss_knobs& k) {
+    E.knobs = k;
+    E.ra.pair_rank_from = k.pair_rank_from;
+    E.ra.sample_grid = k.sample_workgroups;
+    E.ra.pair_grid = k.pair_rank_workgroups;
+    ++E.knob_gen;
+}
+
+// The autotuner: `call` runs one whole call of the engine on the caller's
+// input and returns after its work has completed.  Each knob in turn takes
+// each of its candidate values (the others at their best so far); each
+// setting is timed twice and the fastest kept.  Every run writes the same
+// outputs, so the call's result does not depend on the search.
+template <typename F>
+hss_status autotune(Engine& E, hipStream_t s, F call) {
+    using Clock = std::chrono::steady_clock;
+    auto time_once = [&](double* ms) -> hss_status {
+        HIP_TRY(hipStreamSynchronize(s));
+        const auto t0 = Clock::now();
+        const hss_status st = call();
+        if (st != HSS_OK) return st;
+        *ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+        return HSS_OK;
+    };
+    hss_knobs best = E.knobs;
+    const uint32_t cands[4][3] = {{2048, 4096, 0}, {2048, 4096, 8192}, {2, 3, 64}, {4096, 8192, 16384}};
+    for (int knob = 0; knob < 4; ++knob) {
+        double best_ms = 1e300;
+        hss_knobs pick = best;
+        for (int c = 0; c < 3; ++c) {
+            const uint32_t v = cands[knob][c];
+            if (v == 0) continue;
+            hss_knobs k = best;
+            if (knob == 0) k.small_sort_cap = v;
+            if (knob == 1) k.sample_workgroups = v;
+            if (knob == 2) k.pair_rank_from = v;
+            if (knob == 3) k.pair_rank_workgroups = v;
+            set_knobs(E, k);
+            double a = 0, b = 0;
+            hss_status st = time_once(&a);
+            if (st == HSS_OK) st = time_once(&b);
+            if (st != HSS_OK) return st;
+            if (std::min(a, b) < best_ms) {
+                best_ms = std::min(a, b);
+                pick = k;
+            }
+        }
+        best = pick;
+    }
+    best.tuned = 1;
+    set_knobs(E, best);
+    return call();   // the call's outputs, with the chosen knobs
+}
+
 hss_status run_plain(hss_plan_s* P, uint64_t seed, const void* kin, const uint64_t* vin, void* kout,
                      uint64_t* vout, uint64_t* d_offsets, void* stream, bool sort_buckets) {
     if (!P) return fail(HSS_ERR_INVALID_ARG, "null plan");
@@ -1070,11 +1138,15 @@ hss_status run_plain(hss_plan_s* P, uint64_t seed, const void* kin, const uint64
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(E.device));
     InstRun run{seed, kin, vin, kout, vout, d_offsets};
-    HIP_TRY(launch_set_run(run, E.run_d, s));
-    HIP_TRY(launch_counters_reset(E.ra.ctr, s));
-    st = engine_run(E, kin, vin, kout, vout, s, sort_buckets);
-    if (st != HSS_OK) return st;
-    return finish(E, s);
+    auto call = [&]() -> hss_status {
+        HIP_TRY(launch_set_run(run, E.run_d, s));
+        HIP_TRY(launch_counters_reset(E.ra.ctr, s));
+        const hss_status r = engine_run(E, kin, vin, kout, vout, s, sort_buckets);
+        if (r != HSS_OK) return r;
+        return finish(E, s);
+    };
+    if (E.tune.autotune && !E.knobs.tuned) return autotune(E, s, call);
+    return call();
 }
 
 hss_status new_engine_instance(Engine& E, uint64_t n, uint32_t p, double eps) {
@@ -1595,12 +1667,15 @@ hss_status hss_batch_partition(hss_batch_t Bt, const hss_instance_io* io, void* 
                 E->h_run[Bt->where[i].second] = InstRun{x.seed, x.keys_in, x.vals_in, x.keys_out,
                                                         x.vals_out, x.offsets};
             }
-            HIP_TRY(hipMemcpyAsync(E->run_d, E->h_run, E->ih.size() * sizeof(InstRun),
-                                   hipMemcpyHostToDevice, s));
-            HIP_TRY(launch_counters_reset(E->ra.ctr, s));
-            hss_status st = engine_run(*E, nullptr, nullptr, nullptr, nullptr, s, false);
-            if (st != HSS_OK) return st;
-            st = finish(*E, s);
+            auto call = [&]() -> hss_status {
+                HIP_TRY(hipMemcpyAsync(E->run_d, E->h_run, E->ih.size() * sizeof(InstRun),
+                                       hipMemcpyHostToDevice, s));
+                HIP_TRY(launch_counters_reset(E->ra.ctr, s));
+                const hss_status r = engine_run(*E, nullptr, nullptr, nullptr, nullptr, s, false);
+                if (r != HSS_OK) return r;
+                return finish(*E, s);
+            };
+            const hss_status st = (E->tune.autotune && !E->knobs.tuned) ? autotune(*E, s, call) : call();
             if (st != HSS_OK) return st;
         }
         return HSS_OK;
@@ -1759,6 +1834,30 @@ hss_status hss_server_stats(hss_server_t S, uint64_t* batches, uint64_t* request
     if (keys) *keys = S->keys;
     if (max_concurrent) *max_concurrent = S->max_running;
     if (max_admitted) *max_admitted = S->max_admitted;
+    return HSS_OK;
+}
+
+hss_status hss_plan_knobs(hss_plan_t P, hss_knobs* out) {
+    if (!P || !out) return fail(HSS_ERR_INVALID_ARG, "null plan or output");
+    *out = P->e.knobs;
+    return HSS_OK;
+}
+
+hss_status hss_plan_set_knobs(hss_plan_t P, const hss_knobs* k) {
+    if (!P || !k) return fail(HSS_ERR_INVALID_ARG, "null plan or knobs");
+    if ((k->small_sort_cap != 2048 && k->small_sort_cap != 4096) || k->sample_workgroups == 0 ||
+        k->sample_workgroups > 65536 || k->pair_rank_workgroups == 0 || k->pair_rank_workgroups > 65536 ||
+        k->pair_rank_from == 0)
+        return fail(HSS_ERR_INVALID_ARG, "knob out of range");
+    set_knobs(P->e, *k);
+    return HSS_OK;
+}
+
+hss_status hss_batch_knobs(hss_batch_t Bt, hss_key_type kt, hss_knobs* out) {
+    if (!Bt || !out) return fail(HSS_ERR_INVALID_ARG, "null batch or output");
+    const Engine* E = Bt->eng[kt == HSS_U32 ? 0 : 1];
+    if (!E) return fail(HSS_ERR_INVALID_ARG, "no instance of that key type");
+    *out = E->knobs;
     return HSS_OK;
 }
 

@@ -312,6 +312,8 @@ struct HybridSort {
     // addresses of the input keys (payload: *_vsrc); otherwise keys_in at
     // the segment's position.
     bool has_payload = false;          // payload read through the *_vsrc sources
+    bool cap_large = false;            // on-chip jobs of 4096 keys (else 2048; 4096 always
+                                       // with seg_base)
     const uint32_t* msd_seg = nullptr;
     const uint64_t* msd_beg = nullptr;
     const uint64_t* msd_end = nullptr;
@@ -446,6 +448,8 @@ struct RoundArgs {
                                    // (one instance)
     uint32_t pair_rank_from;       // first round ranked per (probe, segment) pair inside
                                    // the probe's interval slice (earlier: by segment chunks)
+    uint32_t sample_grid;          // workgroups of the sampler
+    uint32_t pair_grid;            // workgroups of the per-pair rank search
     const uint64_t* seg_off;       // S+1 positions
     const uint32_t* seg_inst;      // S
     const uint32_t* row_inst;      // Q

@@ -39,8 +39,6 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kScanT = 1024;            // threads of the one-workgroup scans
-constexpr int kSampleGrid = 4096;       // workgroups of the sampler
-constexpr int kPairGrid = 8192;         // workgroups of the per-pair rank search
 constexpr uint32_t kRankFences = kRankChunk / kFenceStride;
 constexpr uint32_t kReduceRows = 16;    // segments summed per reduction workgroup
 constexpr uint32_t kOrderLanes = 64;    // probes per ordering workgroup
@@ -929,11 +927,11 @@ hipError_t launch_round_head(const RoundArgs& a, uint32_t j, hipStream_t s) {
     hipLaunchKernelGGL(compact_kernel, dim3(ivl_bound), dim3(kT), 0, s, a);
     if (a.budget) hipLaunchKernelGGL(budget_rate_kernel, dim3(1), dim3(1), 0, s, a, j);
     if (a.n_inst == 1) {
-        if (a.key_bytes == 4) hipLaunchKernelGGL((sample_kernel<uint32_t, true>), dim3(kSampleGrid), dim3(kT), 0, s, a, j);
-        else hipLaunchKernelGGL((sample_kernel<uint64_t, true>), dim3(kSampleGrid), dim3(kT), 0, s, a, j);
+        if (a.key_bytes == 4) hipLaunchKernelGGL((sample_kernel<uint32_t, true>), dim3(a.sample_grid), dim3(kT), 0, s, a, j);
+        else hipLaunchKernelGGL((sample_kernel<uint64_t, true>), dim3(a.sample_grid), dim3(kT), 0, s, a, j);
     } else {
-        if (a.key_bytes == 4) hipLaunchKernelGGL((sample_kernel<uint32_t, false>), dim3(kSampleGrid), dim3(kT), 0, s, a, j);
-        else hipLaunchKernelGGL((sample_kernel<uint64_t, false>), dim3(kSampleGrid), dim3(kT), 0, s, a, j);
+        if (a.key_bytes == 4) hipLaunchKernelGGL((sample_kernel<uint32_t, false>), dim3(a.sample_grid), dim3(kT), 0, s, a, j);
+        else hipLaunchKernelGGL((sample_kernel<uint64_t, false>), dim3(a.sample_grid), dim3(kT), 0, s, a, j);
     }
     hipLaunchKernelGGL(probe_scan_kernel, dim3(1), dim3(kScanT), 0, s, a, j);
     hipLaunchKernelGGL(group_kernel, dim3(grid_for(a.cap, kT, 4096)), dim3(kT), 0, s, a);
@@ -949,8 +947,8 @@ hipError_t launch_round_tail(const RoundArgs& a, uint32_t j, hipStream_t s, bool
     }
     if (j >= a.pair_rank_from) {
         // every probe searched inside its own interval slice
-        if (a.key_bytes == 4) hipLaunchKernelGGL(rank_pairs_kernel<uint32_t>, dim3(kPairGrid), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL(rank_pairs_kernel<uint64_t>, dim3(kPairGrid), dim3(256), 0, s, a);
+        if (a.key_bytes == 4) hipLaunchKernelGGL(rank_pairs_kernel<uint32_t>, dim3(a.pair_grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(rank_pairs_kernel<uint64_t>, dim3(a.pair_grid), dim3(256), 0, s, a);
     } else if (a.n_chunks > 0) {
         if (a.key_bytes == 4) hipLaunchKernelGGL(rank_kernel<uint32_t>, dim3(a.n_chunks), dim3(256), 0, s, a);
         else hipLaunchKernelGGL(rank_kernel<uint64_t>, dim3(a.n_chunks), dim3(256), 0, s, a);

@@ -843,7 +843,7 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     const bool pay = a.vals_in != nullptr || a.has_payload;
     // sub-buckets of the p input segments split by their top byte average
     // N/(256 p) keys; bucket key ranges may use only half of the digit values
-    const bool large = a.seg_base != nullptr;
+    const bool large = a.seg_base != nullptr || a.cap_large;
     const uint32_t cap = large ? kCapLarge : kCapSmall;
     hipError_t e = hipSuccess;
 

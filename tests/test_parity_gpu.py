@@ -392,3 +392,65 @@ def test_graph_replays_match_plain_launches(hss):
                 ref = oracle.hss(keys, p, eps, 70 + call, mode="partition", trace_level=0)
                 assert np.array_equal(_host(off, np.uint64), ref.offsets), call
             del junk
+
+
+KNOB_SETTINGS = [
+    {},
+    {"small_sort_cap": 4096},
+    {"sample_workgroups": 1024},
+    {"pair_rank_from": 1},                 # round 1 searched per pair as well
+    {"pair_rank_from": 64},                # every round by segment chunks
+    {"pair_rank_workgroups": 2048, "sample_workgroups": 8192, "small_sort_cap": 4096},
+]
+
+
+@pytest.mark.parametrize("kind,n,p,bits,payload", [("uniform64", 1 << 20, 64, 64, False),
+                                                   ("SKEW1", 1 << 19, 16, 64, True),
+                                                   ("uniform32", 300_001, 37, 32, True)])
+def test_every_knob_setting_matches_oracle(hss, kind, n, p, bits, payload):
+    """The launch knobs change no output: every setting equals the oracle,
+    trace included."""
+    eps, seed = 0.02, 44
+    keys = _keys(kind, n, seed, bits)
+    vals = (np.arange(n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)) if payload else None
+    kd, vd = _dev(keys), (None if vals is None else _dev(vals))
+    ref = oracle.hss(keys, p, eps, seed, vals=vals, mode="partition")
+    with hss.Plan(n, p, eps, key_bytes=keys.itemsize, payload=payload, trace_level=1) as plan:
+        base = plan.knobs()
+        for k in KNOB_SETTINGS:
+            _say(f"[parity] knobs {kind} {k}")
+            plan.set_knobs(**{**base, **k})
+            ko, vo, off = plan.partition(kd, seed, vd)
+            assert np.array_equal(_host(off, np.uint64), ref.offsets), k
+            assert np.array_equal(_host(ko, keys.dtype), ref.keys), k
+            if payload:
+                assert np.array_equal(_host(vo, np.uint64), ref.vals), k
+            _compare_trace(plan, ref, p)
+        with pytest.raises(hss.HssError):
+            plan.set_knobs(small_sort_cap=3000)
+
+
+def test_autotuned_plan_and_batch(hss):
+    """The first call of an autotuned plan searches the knobs on its input
+    and still returns the oracle's result; later calls run with the choice."""
+    n, p, eps = 1 << 20, 128, 0.02
+    keys = _keys("uniform64", n, 45, 64)
+    ref = oracle.hss(keys, p, eps, 9, mode="partition", trace_level=0)
+    with hss.Plan(n, p, eps, autotune=True) as plan:
+        assert plan.knobs()["tuned"] == 0
+        for call in range(2):
+            ko, _, off = plan.partition(_dev(keys), 9)
+            assert np.array_equal(_host(off, np.uint64), ref.offsets), call
+            assert np.array_equal(_host(ko, np.uint64), ref.keys), call
+        k = plan.knobs()
+        _say(f"[parity] autotuned knobs {k}")
+        assert k["tuned"] == 1 and k["small_sort_cap"] in (2048, 4096)
+    shapes = [(70_000, 16, 0.05, 8), (123_457, 37, 0.05, 8), (5000, 8, 0.05, 8)]
+    ks = [_keys("uniform64", s[0], 60 + i, 64) for i, s in enumerate(shapes)]
+    with hss.BatchPlan(shapes, autotune=True) as bp:
+        ko, _, off = bp.partition([_dev(k) for k in ks], [3, 4, 5])
+        for i, (nn, pp, ee, _) in enumerate(shapes):
+            r = oracle.hss(ks[i], pp, ee, 3 + i, mode="partition", trace_level=0)
+            assert np.array_equal(_host(off[i], np.uint64), r.offsets), i
+            assert np.array_equal(_host(ko[i], np.uint64), r.keys), i
+        assert bp.knobs(8)["tuned"] == 1
