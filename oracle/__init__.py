@@ -16,6 +16,12 @@ Parity status of each entry point (what pins it, besides the GPU):
                     section 4.2.  The exact probe sets and which probe settles a
                     splitter depend on the random stream; beyond the Philox pin
                     and the definitions they are "parity unpinned".
+                    With q < p buckets (one stage of section 5.3): the same
+                    invariants, and q = 1 is the local sort.
+  hss_two_stage  -- pinned: r = 1 reduces to single-stage HSS of the locally
+                    sorted input, r = p to the single-stage sort; outputs
+                    against numpy's sort, group and bucket bounds of section 2
+                    for both stages.
 """
 from __future__ import annotations
 
@@ -56,7 +62,7 @@ def lib():
         L.oracle_constants.argtypes = [u64, u32, dbl, u32, vp, vp, vp, u32, vp, vp]
         L.oracle_philox_word.argtypes = [u64, u64, u32]
         L.oracle_philox_word.restype = u32
-        L.oracle_hss.argtypes = [u64, u32, dbl, C.c_int, vp, vp, u64, C.c_int, u32, u32,
+        L.oracle_hss.argtypes = [u64, u32, u32, dbl, C.c_int, vp, vp, u64, C.c_int, u32, u32,
                                  C.c_int, u32, C.c_int, vp, vp, vp]
         L.oracle_hss.restype = vp
         L.oracle_local_sort.argtypes = [u64, u32, C.c_int, vp, vp, vp, vp]
@@ -152,28 +158,34 @@ class Result:
     chi: np.ndarray | None = None
     s_key: np.ndarray | None = None
     s_tag: np.ndarray | None = None
-    pieces: np.ndarray | None = None     # (p+1, p)
+    pieces: np.ndarray | None = None     # (q+1, p)
 
 
 def hss(keys: np.ndarray, p: int, eps: float, seed: int, vals: np.ndarray | None = None,
         mode: str = "partition", k_override: int = 0, max_rounds: int = 0,
         force_full_sample: bool = False, trace_level: int = 1,
-        probes_per_round: int = 0) -> Result:
+        probes_per_round: int = 0, buckets: int | None = None) -> Result:
     """Run the whole method on the host; returns outputs and the round trace.
-    probes_per_round = c > 0: a fixed budget of c p probes per round (rate
-    c p / |gamma|) instead of the rate schedule."""
+    probes_per_round = c > 0: a fixed budget of c q probes per round (rate
+    c q / |gamma|) instead of the rate schedule.  buckets = q (default p):
+    the p segments are split into q <= p buckets, as in one stage of
+    multi-stage HSS (section 5.3); offsets, chi and the splitter state then
+    have q+1 (resp. q-1) entries."""
     keys = np.ascontiguousarray(keys)
     if keys.dtype not in (np.uint32, np.uint64):
         raise TypeError("keys must be uint32 or uint64")
     bits = 32 if keys.dtype == np.uint32 else 64
     n = len(keys)
+    q = p if buckets is None else int(buckets)
+    if q <= 0 or q > max(p, 0):
+        return Result(status=-1)
     ko = np.empty(max(n, 1), dtype=keys.dtype)
     vi = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint64)
     vo = None if vals is None else np.empty(max(n, 1), dtype=np.uint64)
-    off = np.zeros(max(p, 0) + 1, dtype=np.uint64)
+    off = np.zeros(q + 1, dtype=np.uint64)
     kin = keys if n else np.zeros(1, dtype=keys.dtype)
     L = lib()
-    h = L.oracle_hss(n, p, eps, bits, _ptr(kin), _ptr(vi), seed & NONE,
+    h = L.oracle_hss(n, p, q, eps, bits, _ptr(kin), _ptr(vi), seed & NONE,
                      1 if mode == "sort" else 0, k_override, max_rounds,
                      1 if force_full_sample else 0, probes_per_round, trace_level,
                      _ptr(ko), _ptr(vo), _ptr(off))
@@ -198,20 +210,81 @@ def hss(keys: np.ndarray, p: int, eps: float, seed: int, vals: np.ndarray | None
                                       _ptr(r.probe_rank), _ptr(cnt))
                 if cnt is not None:
                     r.counts = cnt.reshape(mm, p)
-                r.lo_rank = np.zeros(p - 1, dtype=np.uint64)
-                r.hi_rank = np.zeros(p - 1, dtype=np.uint64)
-                r.settled = np.zeros(p - 1, dtype=np.uint8)
-                r.chi = np.zeros(p - 1, dtype=np.uint64)
-                if p > 1:
+                r.lo_rank = np.zeros(q - 1, dtype=np.uint64)
+                r.hi_rank = np.zeros(q - 1, dtype=np.uint64)
+                r.settled = np.zeros(q - 1, dtype=np.uint8)
+                r.chi = np.zeros(q - 1, dtype=np.uint64)
+                if q > 1:
                     L.oracle_round_state(h, j, _ptr(r.lo_rank), _ptr(r.hi_rank),
                                          _ptr(r.settled), _ptr(r.chi))
             res.rounds.append(r)
-        res.chi = np.zeros(p + 1, dtype=np.uint64)
-        res.s_key = np.zeros(p + 1, dtype=np.uint64)
-        res.s_tag = np.zeros(p + 1, dtype=np.uint64)
-        res.pieces = np.zeros((p + 1) * p, dtype=np.uint64)
+        res.chi = np.zeros(q + 1, dtype=np.uint64)
+        res.s_key = np.zeros(q + 1, dtype=np.uint64)
+        res.s_tag = np.zeros(q + 1, dtype=np.uint64)
+        res.pieces = np.zeros((q + 1) * p, dtype=np.uint64)
         L.oracle_splitters(h, _ptr(res.chi), _ptr(res.s_key), _ptr(res.s_tag), _ptr(res.pieces))
-        res.pieces = res.pieces.reshape(p + 1, p)
+        res.pieces = res.pieces.reshape(q + 1, p)
         return res
     finally:
         L.oracle_free(h)
+
+
+@dataclass
+class TwoStage:
+    status: int
+    keys: np.ndarray | None = None
+    vals: np.ndarray | None = None
+    offsets: np.ndarray | None = None    # p+1 final bucket boundaries
+    groups: np.ndarray | None = None     # r+1 group boundaries of stage 1
+    stage1: Result | None = None
+    stage2: list = field(default_factory=list)
+
+
+def stage_seed(seed: int, g: int) -> int:
+    """Philox seed of group g in the second stage (READING: the paper leaves
+    the random streams of the groups open; each group gets its own, seed+1+g,
+    so that no two runs share one)."""
+    return (seed + 1 + g) & NONE
+
+
+def hss_two_stage(keys: np.ndarray, p: int, r: int, eps1: float, eps2: float, seed: int,
+                  vals: np.ndarray | None = None) -> TwoStage:
+    """Two-stage HSS (section 5.3), composed from single-stage runs.
+
+    Stage 1: the p segments are split into r buckets, one per group of p/r
+    processors (tolerance eps1); the exchange gives group g the keys ranked
+    [chi1(g), chi1(g+1)).  READING: the group's keys are then dealt out evenly
+    to its p/r processors in the order the exchange wrote them (segment s of
+    the group holds positions floor(s N_g r/p) ..).  Stage 2: every group runs
+    HSS on its own keys with p/r segments and buckets (tolerance eps2).  Final
+    bucket g p/r + i is bucket i of group g.  Requires r | p and N_g >= p/r.
+    """
+    keys = np.ascontiguousarray(keys)
+    if r <= 0 or p % r != 0:
+        return TwoStage(status=-1)
+    pg = p // r
+    st1 = hss(keys, p, eps1, seed, vals=vals, mode="partition", trace_level=0, buckets=r)
+    if st1.status != 0:
+        return TwoStage(status=st1.status)
+    ko = np.empty_like(keys)
+    vo = None if vals is None else np.empty(len(keys), dtype=np.uint64)
+    off = np.zeros(p + 1, dtype=np.uint64)
+    chi1 = st1.offsets.astype(np.uint64)
+    res = TwoStage(status=0, stage1=st1, groups=chi1)
+    for g in range(r):
+        lo, hi = int(chi1[g]), int(chi1[g + 1])
+        if hi - lo < pg:
+            return TwoStage(status=-1, stage1=st1, groups=chi1)
+        kg = st1.keys[lo:hi]
+        vg = None if vals is None else st1.vals[lo:hi]
+        st2 = hss(kg, pg, eps2, stage_seed(seed, g), vals=vg, mode="partition", trace_level=0)
+        if st2.status != 0:
+            return TwoStage(status=st2.status, stage1=st1, groups=chi1)
+        ko[lo:hi] = st2.keys
+        if vo is not None:
+            vo[lo:hi] = st2.vals
+        off[g * pg:(g + 1) * pg] = lo + st2.offsets[:pg]
+        res.stage2.append(st2)
+    off[p] = len(keys)
+    res.keys, res.vals, res.offsets = ko, vo, off
+    return res

@@ -191,9 +191,9 @@ struct Run {
     int status = 0;
     Constants c{};
     std::vector<RoundTrace> rounds;
-    std::vector<uint64_t> chi;           // p+1
-    std::vector<uint64_t> S_key, S_tag;  // p+1 (entries 0 and p unused)
-    std::vector<uint64_t> pieces;        // (p+1) x p, row b holds c_s(S(b))
+    std::vector<uint64_t> chi;           // q+1 (q buckets, q = p but in a stage)
+    std::vector<uint64_t> S_key, S_tag;  // q+1 (entries 0 and q unused)
+    std::vector<uint64_t> pieces;        // (q+1) x p, row b holds c_s(S(b))
     double t_local = 0, t_rounds = 0, t_exchange = 0, t_final = 0;
 };
 
@@ -282,19 +282,26 @@ bool before(const Problem& P, uint64_t g1, uint64_t g2) {
 // Splitter determination by k-round HSS (section 4.2.2, steps 1-5), with the
 // early stop of histogram sort (section 3.3: finish once every splitter has a
 // probe in its target range).
-void determine_splitters(const Problem& P, double eps, uint64_t seed,
+//
+// q is the number of buckets.  It equals p except in a stage of multi-stage
+// HSS (section 5.3), where q groups of processors take one bucket each: the
+// splitters are then i = 1..q-1 with ideal ranks N i/q, and every formula of
+// sections 2 and 4.2 that counts buckets uses q (READING: the tolerance
+// N eps/(2q), the final ratio 2 ln q / eps and the rate q s_j / N), while the
+// histogram still runs over the p segments.
+void determine_splitters(const Problem& P, uint32_t q, double eps, uint64_t seed,
                          uint32_t k_override, uint32_t max_rounds, int force_full,
                          uint32_t budget, int trace_level, Run& R) {
     const uint64_t n = P.n;
     const uint32_t p = P.p;
-    R.c = make_constants(n, p, eps, k_override);
+    R.c = make_constants(n, q, eps, k_override);
     const uint64_t tol = R.c.tol;
 
-    std::vector<Splitter> sp(p + 1);    // index 1..p-1
-    std::vector<uint64_t> ideal(p + 1);
-    for (uint32_t i = 0; i <= p; ++i) ideal[i] = ideal_rank(n, p, i);
+    std::vector<Splitter> sp(q + 1);    // index 1..q-1
+    std::vector<uint64_t> ideal(q + 1);
+    for (uint32_t i = 0; i <= q; ++i) ideal[i] = ideal_rank(n, q, i);
 
-    uint32_t unsettled = p - 1;
+    uint32_t unsettled = q - 1;
     for (uint32_t j = 1; unsettled > 0; ++j) {
         if (max_rounds && j > max_rounds) { R.status = -5; return; }
         RoundTrace tr;
@@ -304,7 +311,7 @@ void determine_splitters(const Problem& P, double eps, uint64_t seed,
         // (READING: settled splitters are frozen, the interval end points are
         // already probes).  Identical intervals are taken once.
         std::map<std::pair<uint64_t, uint64_t>, bool> intervals;   // (L tag, U tag)
-        for (uint32_t i = 1; i < p; ++i)
+        for (uint32_t i = 1; i < q; ++i)
             if (!sp[i].settled) intervals[{sp[i].L, sp[i].U}] = true;
         // slice [lo, hi) of every segment inside every interval
         std::vector<std::pair<uint64_t, uint64_t>> slices;
@@ -320,8 +327,8 @@ void determine_splitters(const Problem& P, double eps, uint64_t seed,
         }
 
         uint32_t thresh;
-        bool all = budget ? budget_threshold(tr.domain, p, budget, &thresh)
-                          : sampling_threshold(n, p, R.c, j, &thresh);
+        bool all = budget ? budget_threshold(tr.domain, q, budget, &thresh)
+                          : sampling_threshold(n, q, R.c, j, &thresh);
         if (force_full) all = true;
         tr.thresh = all ? 0xFFFFFFFFu : thresh;
         tr.all = all ? 1u : 0u;
@@ -354,7 +361,7 @@ void determine_splitters(const Problem& P, double eps, uint64_t seed,
         // lies in the target range settles it (READING: the closest to Ni/p,
         // the lower rank on a tie); otherwise the bounds L and U move to the
         // closest probe ranks below and above Ni/p.
-        for (uint32_t i = 1; i < p; ++i) {
+        for (uint32_t i = 1; i < q; ++i) {
             Splitter& S = sp[i];
             if (S.settled) continue;
             size_t best = SIZE_MAX;
@@ -386,9 +393,9 @@ void determine_splitters(const Problem& P, double eps, uint64_t seed,
             tr.probe_tag = probes;
             for (uint64_t g : probes) tr.probe_key.push_back(P.key[g]);
             tr.probe_rank = rk;
-            tr.lo_rank.resize(p - 1); tr.hi_rank.resize(p - 1);
-            tr.settled.resize(p - 1); tr.chi.resize(p - 1);
-            for (uint32_t i = 1; i < p; ++i) {
+            tr.lo_rank.resize(q - 1); tr.hi_rank.resize(q - 1);
+            tr.settled.resize(q - 1); tr.chi.resize(q - 1);
+            for (uint32_t i = 1; i < q; ++i) {
                 tr.lo_rank[i - 1] = sp[i].settled || sp[i].L == NONE ? NONE : sp[i].Lrank;
                 tr.hi_rank[i - 1] = sp[i].settled || sp[i].U == NONE ? NONE : sp[i].Urank;
                 tr.settled[i - 1] = sp[i].settled ? 1 : 0;
@@ -400,14 +407,14 @@ void determine_splitters(const Problem& P, double eps, uint64_t seed,
         R.rounds.push_back(std::move(tr));
     }
 
-    // Splitter ranks chi(0) = 0, chi(p) = N, and the piece boundaries c_s(S(b)).
-    R.chi.assign(p + 1, 0);
-    R.S_key.assign(p + 1, 0);
-    R.S_tag.assign(p + 1, NONE);
-    R.chi[p] = n;
-    R.pieces.assign((size_t)(p + 1) * p, 0);
-    for (uint32_t s = 0; s < p; ++s) R.pieces[(size_t)p * p + s] = P.seg_len(s);
-    for (uint32_t i = 1; i < p; ++i) {
+    // Splitter ranks chi(0) = 0, chi(q) = N, and the piece boundaries c_s(S(b)).
+    R.chi.assign(q + 1, 0);
+    R.S_key.assign(q + 1, 0);
+    R.S_tag.assign(q + 1, NONE);
+    R.chi[q] = n;
+    R.pieces.assign((size_t)(q + 1) * p, 0);
+    for (uint32_t s = 0; s < p; ++s) R.pieces[(size_t)q * p + s] = P.seg_len(s);
+    for (uint32_t i = 1; i < q; ++i) {
         R.chi[i] = sp[i].chi;
         R.S_tag[i] = sp[i].S;
         R.S_key[i] = P.key[sp[i].S];
@@ -422,20 +429,23 @@ extern "C" {
 // Full HSS on the host.  mode 0 = partition (bucket b holds the keys of ranks
 // [chi(b), chi(b+1)), pieces in ascending segment order, each in local sorted
 // order), mode 1 = sort (each bucket additionally sorted stably by key).
+// q = 0 means q = p buckets; 1 <= q <= p otherwise (one stage of multi-stage
+// HSS, section 5.3: offsets_out then holds q+1 words).
 // Returns a run handle (never NULL); oracle_status() tells the outcome.
-oracle_run* oracle_hss(uint64_t n, uint32_t p, double eps, int key_bits,
+oracle_run* oracle_hss(uint64_t n, uint32_t p, uint32_t q, double eps, int key_bits,
                        const void* keys_in, const uint64_t* vals_in, uint64_t seed,
                        int mode, uint32_t k_override, uint32_t max_rounds, int force_full,
                        uint32_t probes_per_round, int trace_level, void* keys_out,
                        uint64_t* vals_out, uint64_t* offsets_out) {
     Run* R = new Run();
-    if (!valid_params(n, p, eps, key_bits) || !keys_in || !keys_out || !offsets_out) {
+    if (q == 0) q = p;
+    if (!valid_params(n, p, eps, key_bits) || q > p || !keys_in || !keys_out || !offsets_out) {
         R->status = -1;
         return (oracle_run*)R;
     }
     Problem P;
     load_and_local_sort(P, n, p, key_bits, keys_in, vals_in);
-    determine_splitters(P, eps, seed, k_override, max_rounds, force_full, probes_per_round,
+    determine_splitters(P, q, eps, seed, k_override, max_rounds, force_full, probes_per_round,
                         trace_level, *R);
     if (R->status != 0) return (oracle_run*)R;
 
@@ -443,7 +453,7 @@ oracle_run* oracle_hss(uint64_t n, uint32_t p, double eps, int key_bits,
     // segment in turn, the keys ranked in [chi(b), chi(b+1)).
     std::vector<uint64_t> ok(n), ov(n);
     uint64_t o = 0;
-    for (uint32_t b = 0; b < p; ++b) {
+    for (uint32_t b = 0; b < q; ++b) {
         for (uint32_t s = 0; s < p; ++s) {
             uint64_t from = P.seg_start[s] + R->pieces[(size_t)b * p + s];
             uint64_t to = P.seg_start[s] + R->pieces[(size_t)(b + 1) * p + s];
@@ -453,7 +463,7 @@ oracle_run* oracle_hss(uint64_t n, uint32_t p, double eps, int key_bits,
     }
     // Local merge after the exchange (section 5): a stable sort of the bucket.
     if (mode == 1) {
-        for (uint32_t b = 0; b < p; ++b) {
+        for (uint32_t b = 0; b < q; ++b) {
             uint64_t lo = R->chi[b], hi = R->chi[b + 1];
             std::vector<uint64_t> idx(hi - lo);
             std::iota(idx.begin(), idx.end(), lo);
@@ -470,7 +480,7 @@ oracle_run* oracle_hss(uint64_t n, uint32_t p, double eps, int key_bits,
         else ((uint64_t*)keys_out)[i] = ok[i];
         if (vals_out) vals_out[i] = ov[i];
     }
-    for (uint32_t b = 0; b <= p; ++b) offsets_out[b] = R->chi[b];
+    for (uint32_t b = 0; b <= q; ++b) offsets_out[b] = R->chi[b];
     return (oracle_run*)R;
 }
 

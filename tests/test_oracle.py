@@ -446,3 +446,155 @@ def test_probe_budget_round_counts():
         r1.append(len(b.rounds))
     assert all(3 <= x <= 6 for x in r5), r5
     assert min(r1) > max(r5) and max(r1) <= 16, (r1, r5)
+
+
+# ------------------------------------------- fewer buckets, two stages ----
+
+BUCKET_CASES = [
+    # kind, n, p, q, eps, seed, bits, payload
+    ("uniform64", 40_000, 64, 8, 0.05, 3, 64, True),
+    ("SKEW2", 20_000, 32, 5, 0.05, 4, 64, False),
+    ("GAUSS", 30_000, 48, 12, 0.02, 5, 64, True),
+    ("uniform32", 10_007, 20, 3, 0.1, 6, 32, False),
+    ("ALLZEROS", 9_000, 16, 4, 0.05, 7, 64, True),
+    ("uniform64", 5_000, 10, 10, 0.05, 8, 64, False),     # q = p
+]
+
+
+@pytest.mark.parametrize("case", BUCKET_CASES, ids=[f"{c[0]}-{c[2]}-{c[3]}" for c in BUCKET_CASES])
+def test_buckets_partition_matches_definition(case):
+    """q < p buckets over p segments (one stage of section 5.3): splitters sit
+    within N eps/(2q) of N i/q, the output is the partition the splitter ranks
+    define (bucket, then source segment, then local order), and every row of
+    the piece matrix is the per-segment count of its splitter."""
+    kind, n, p, q, eps, seed, bits, payload = case
+    keys = _keys(kind, n, seed, bits)
+    vals = np.arange(n, dtype=np.uint64) * U64(7) if payload else None
+    r = oracle.hss(keys, p, eps, seed, vals=vals, buckets=q)
+    assert r.status == 0
+    assert r.tol == math.floor(n * eps / (2 * q))
+    assert r.k == max(1, math.ceil(math.log(2 * math.log(q) / eps))) if q > 1 else True
+    assert len(r.offsets) == q + 1 and r.pieces.shape == (q + 1, p)
+    R.check_balance(r.chi, n, q, r.tol)
+    assert np.array_equal(r.offsets, r.chi)
+    ek, ev = R.expected_partition(keys, vals, p, r.chi)
+    assert np.array_equal(r.keys, ek)
+    if payload:
+        assert np.array_equal(r.vals, ev)
+    tr = R.tag_rank(keys, p)
+    for i in range(1, q):
+        assert tr[int(r.s_tag[i])] == int(r.chi[i])
+        assert np.array_equal(r.pieces[i], R.brute_counts(keys, p, int(r.s_tag[i])))
+    assert np.array_equal(r.pieces[q], np.diff(R.seg_bounds(n, p)))
+
+
+def test_buckets_full_sample_settles_exactly():
+    for kind, n, p, q in [("uniform64", 3000, 13, 4), ("SKEW2", 2000, 16, 7), ("ALLZEROS", 999, 10, 2)]:
+        keys = synth.make(kind, n, 3)
+        r = oracle.hss(keys, p, 0.05, 1, force_full_sample=True, buckets=q)
+        assert r.status == 0
+        assert len(r.rounds) == 1 and r.rounds[0].m == n
+        assert [int(c) for c in r.chi] == list(R.ideal(n, q))
+
+
+def test_one_bucket_is_the_local_sort():
+    keys = synth.make("SKEW1", 7000, 2)
+    vals = np.arange(7000, dtype=np.uint64)
+    r = oracle.hss(keys, 9, 0.05, 1, vals=vals, buckets=1)
+    assert r.status == 0 and len(r.rounds) == 0
+    lo = R.local_order(keys, 9)
+    assert np.array_equal(r.keys, keys[lo]) and np.array_equal(r.vals, vals[lo])
+    assert [int(x) for x in r.offsets] == [0, 7000]
+
+
+def test_bucket_count_above_segments_is_invalid():
+    keys = synth.make("uniform64", 100, 1)
+    assert oracle.hss(keys, 4, 0.1, 1, buckets=5).status == -1
+    assert oracle.hss(keys, 4, 0.1, 1, buckets=0).status == -1
+
+
+TWO_STAGE_CASES = [
+    # kind, n, p, r, eps1, eps2, seed, payload
+    ("uniform64", 60_000, 64, 8, 0.05, 0.05, 11, True),
+    ("SKEW2", 30_000, 32, 4, 0.02, 0.05, 12, False),
+    ("GAUSS", 40_000, 36, 6, 0.05, 0.02, 13, True),
+    ("ALLZEROS", 8_000, 16, 4, 0.05, 0.05, 14, False),
+    ("zipf_morton", 50_000, 64, 16, 0.05, 0.05, 15, True),
+]
+
+
+@pytest.mark.parametrize("case", TWO_STAGE_CASES, ids=[f"{c[0]}-{c[2]}-{c[3]}" for c in TWO_STAGE_CASES])
+def test_two_stage_composition(case):
+    """Two-stage HSS (section 5.3): group boundaries within N eps1/(2r) of
+    N g/r; inside each group, bucket boundaries within N_g eps2 r/(2p) of
+    N_g i r/p; the output of each stage is the partition its splitter ranks
+    define, applied to the previous stage's output; and the whole is a
+    permutation whose buckets are in key order."""
+    kind, n, p, r, eps1, eps2, seed, payload = case
+    keys = synth.make(kind, n, seed)
+    vals = np.arange(n, dtype=np.uint64) ^ U64(0xABCDEF) if payload else None
+    t = oracle.hss_two_stage(keys, p, r, eps1, eps2, seed, vals=vals)
+    assert t.status == 0
+    pg = p // r
+    chi1 = [int(c) for c in t.groups]
+    R.check_balance(chi1, n, r, math.floor(n * eps1 / (2 * r)))
+    k1, v1 = R.expected_partition(keys, vals, p, chi1)
+    off = [int(x) for x in t.offsets]
+    assert off[0] == 0 and off[p] == n
+    for g in range(r):
+        lo, hi = chi1[g], chi1[g + 1]
+        ng = hi - lo
+        st2 = t.stage2[g]
+        tol2 = math.floor(ng * eps2 / (2 * pg))
+        assert st2.tol == tol2
+        loc = [x - lo for x in off[g * pg:(g + 1) * pg + 1]]
+        R.check_balance(loc, ng, pg, tol2)
+        ek, ev = R.expected_partition(k1[lo:hi], None if v1 is None else v1[lo:hi], pg, loc)
+        assert np.array_equal(t.keys[lo:hi], ek)
+        if payload:
+            assert np.array_equal(t.vals[lo:hi], ev)
+    # every final bucket lies between its neighbours in key order
+    srt = np.sort(keys)
+    for b in range(p):
+        seg = np.sort(t.keys[off[b]:off[b + 1]])
+        assert np.array_equal(seg, srt[off[b]:off[b + 1]]), b
+    if payload:
+        # the payload travels with its key
+        assert np.array_equal(np.sort(t.vals), np.sort(vals))
+        pos = {int(v): i for i, v in enumerate(vals)}
+        assert all(keys[pos[int(v)]] == k for v, k in zip(t.vals[:500], t.keys[:500]))
+
+
+def test_two_stage_with_one_group_is_single_stage():
+    """r = 1: the first stage only concatenates the locally sorted segments,
+    whose local sort the second stage leaves unchanged, so the result is the
+    single-stage run with the group's seed."""
+    keys = synth.make("SKEW3", 20_000, 21)
+    vals = np.arange(20_000, dtype=np.uint64)
+    p, eps, seed = 32, 0.03, 9
+    t = oracle.hss_two_stage(keys, p, 1, 0.05, eps, seed, vals=vals)
+    s = oracle.hss(keys, p, eps, oracle.stage_seed(seed, 0), vals=vals, trace_level=0)
+    assert t.status == 0 and s.status == 0
+    assert np.array_equal(t.keys, s.keys) and np.array_equal(t.vals, s.vals)
+    assert np.array_equal(t.offsets, s.offsets)
+
+
+def test_two_stage_with_p_groups_is_single_stage_sort():
+    """r = p: every group is one processor, whose second stage is a stable
+    sort of its bucket, which is the single-stage sort."""
+    keys = synth.make("GAUSS", 20_000, 22)
+    vals = np.arange(20_000, dtype=np.uint64)
+    p, eps, seed = 16, 0.05, 4
+    t = oracle.hss_two_stage(keys, p, p, eps, 0.05, seed, vals=vals)
+    s = oracle.hss(keys, p, eps, seed, vals=vals, mode="sort", trace_level=0)
+    assert t.status == 0 and s.status == 0
+    assert np.array_equal(t.keys, s.keys) and np.array_equal(t.vals, s.vals)
+    assert np.array_equal(t.offsets, s.offsets)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(t.keys, keys[order]) and np.array_equal(t.vals, vals[order])
+
+
+def test_two_stage_invalid_group_counts():
+    keys = synth.make("uniform64", 1000, 1)
+    assert oracle.hss_two_stage(keys, 16, 3, 0.05, 0.05, 1).status == -1
+    assert oracle.hss_two_stage(keys, 16, 0, 0.05, 0.05, 1).status == -1
