@@ -199,6 +199,44 @@ def options_bench(keys, n, p, eps, hseed, steps):
     return out
 
 
+def staged_bench(keys, n, hseed, steps, p=4096, r=64):
+    """Section 5.3 at the headline size: single-stage HSS with p = 4096
+    processors (eps = 2%) against two stages, r = sqrt(p) = 64 groups of 64
+    (eps = 1% per stage, as in the paper's two-stage runs, so that the final
+    imbalance stays within about 2%)."""
+    import torch
+    import paper_1803_01237_amd as hss
+    kout = torch.empty_like(keys)
+    off = torch.empty(p + 1, dtype=torch.int64, device=keys.device)
+    grp = torch.empty(r + 1, dtype=torch.int64, device=keys.device)
+    out = {"n": n, "p": p}
+    log(f"[bench] single stage p={p}")
+    with hss.Plan(n, p, 0.02, autotune=True) as plan:
+        ms = _timed(lambda: plan.partition(keys, hseed, keys_out=kout, offsets=off), steps)
+        tr = plan.trace()
+        o = off.cpu().numpy().astype(np.int64)
+        out["single"] = {"eps": 0.02, "ms_per_step": round(ms, 4),
+                         "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3), "rounds": len(tr),
+                         "probes": sum(x.m for x in tr), "max_bucket": int(np.diff(o).max())}
+    log(f"[bench] two stages p={p} r={r}")
+    with hss.StagedPlan(n, p, r, 0.01, 0.01, autotune=True) as plan:
+        ms = _timed(lambda: plan.partition(keys, hseed, keys_out=kout, offsets=off, groups_out=grp),
+                    steps)
+        t1, ts, t2 = plan.times()
+        o = off.cpu().numpy().astype(np.int64)
+        g = grp.cpu().numpy().astype(np.int64)
+        bound = int(n * 1.01 * 1.01 / p) + 2
+        if int(np.diff(o).max()) > bound or o[0] != 0 or o[p] != n or g[r] != n:
+            raise RuntimeError("two-stage balance check failed")
+        out["two_stage"] = {"groups": r, "eps1": 0.01, "eps2": 0.01, "ms_per_step": round(ms, 4),
+                            "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3),
+                            "last_call_ms": {"stage1": round(t1 * 1e3, 3), "stage2_layout": round(ts * 1e3, 3),
+                                             "stage2": round(t2 * 1e3, 3)},
+                            "max_bucket": int(np.diff(o).max()), "max_group": int(np.diff(g).max()),
+                            "workspace_gib": round(plan.workspace_bytes / 2**30, 2)}
+    return out
+
+
 def sweep_bench(plan, keys, n, p, eps, hseed, steps):
     """The distributions of section 7.5 through the headline plan: one input
     buffer refilled per distribution, per-stage times from the HIP events."""
@@ -360,6 +398,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--option-steps", type=int, default=3,
                     help="steps per plan option (one round, exact splitting); 0 to skip")
+    ap.add_argument("--staged-steps", type=int, default=3,
+                    help="single- vs two-stage partition at p = 4096 (0 to skip)")
     ap.add_argument("--sweep-steps", type=int, default=3,
                     help="steps per distribution of the sweep; 0 to skip")
     ap.add_argument("--serve-requests", type=int, default=2000,
@@ -480,6 +520,8 @@ def main():
     headline = args.workload == "uniform_u64_2^28_p1024" and args.op == "partition"
     options = (options_bench(keys, n, p, eps, hseed, args.option_steps)
                if args.option_steps > 0 and headline else None)
+    staged = (staged_bench(keys, n, hseed, args.staged_steps)
+              if args.staged_steps > 0 and headline else None)
     sweep = (sweep_bench(plan, keys, n, p, eps, hseed, args.sweep_steps)
              if args.sweep_steps > 0 and headline else None)
     plan.close()
@@ -511,6 +553,7 @@ def main():
         "batched": batched,
         "served": served,
         "plan_options": options,
+        "stages_p4096": staged,
         "distributions": sweep,
     }
     print(json.dumps(line), flush=True)

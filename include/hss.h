@@ -111,6 +111,20 @@ typedef struct {
 hss_status hss_plan(hss_plan_t* out, uint64_t n, uint32_t p, double eps, hss_key_type kt,
                     int with_payload, const hss_tuning* tuning);
 
+/*
+ * hss_plan_buckets -- as hss_plan, but the p segments are split into
+ * 1 <= q <= p buckets: one stage of HSS with several stages (section 5.3),
+ * where q groups of processors take one bucket each.  The splitters are
+ * i = 1..q-1 with ideal ranks N i/q; the tolerance floor(N eps / (2q)), the
+ * final sampling ratio 2 ln q / eps and the rate q s_j / N of section 4.2
+ * count buckets, the histograms still run over the p segments.  With such
+ * a plan hss_partition and hss_sort write q buckets and q+1 offsets, the
+ * trace calls report q-1 splitters and a (q+1) x p piece matrix.  q = p is
+ * hss_plan.  Errors as hss_plan; q outside 1..p is HSS_ERR_INVALID_ARG.
+ */
+hss_status hss_plan_buckets(hss_plan_t* out, uint64_t n, uint32_t p, uint32_t q, double eps,
+                            hss_key_type kt, int with_payload, const hss_tuning* tuning);
+
 /* Release a plan and its device memory (synchronises the device). NULL is ok. */
 void hss_plan_destroy(hss_plan_t plan);
 
@@ -353,6 +367,57 @@ hss_status hss_plan_knobs(hss_plan_t plan, hss_knobs* out);
  * other values. */
 hss_status hss_plan_set_knobs(hss_plan_t plan, const hss_knobs* knobs);
 hss_status hss_batch_knobs(hss_batch_t batch, hss_key_type kt, hss_knobs* out);
+
+/*
+ * ------------------------------------------------------------ two stages --
+ * HSS with two stages (section 5.3): the p processors form r groups of p/r.
+ * Stage 1 splits the N keys into r buckets, one per group (tolerance eps1,
+ * as hss_plan_buckets with q = r), and moves every bucket to its group.
+ * The group's keys are then dealt out evenly to its p/r processors in the
+ * order the exchange wrote them, and stage 2 runs HSS inside every group on
+ * its own (tolerance eps2, Philox seed `seed + 1 + g` for group g), all
+ * groups in the same launches.  Final bucket g p/r + i is bucket i of group
+ * g, so every bucket holds at most about N (1 + eps1)(1 + eps2) / p keys.
+ * The splitting of stage 1 ranks r-1 splitters against p segments and the
+ * rounds of stage 2 rank p/r - 1 splitters against p/r segments per group,
+ * in place of p-1 splitters against p segments.
+ */
+typedef struct hss_staged_s* hss_staged_t;
+
+/*
+ * hss_staged_plan -- validate and prepare.  groups = r must divide p;
+ * n, p, eps1, kt and tuning as for hss_plan (tuning: trace_level, lsd_only
+ * and probes_per_round must be zero, HSS_ERR_UNSUPPORTED otherwise; the
+ * autotuner, when asked for, tunes stage 1); 0 < eps2 < 1.  The plan holds
+ * the workspace of stage 1, a staging buffer of N keys (and payload words),
+ * and a cache of the device blocks of stage 2, whose layout depends on the
+ * group sizes of each call.
+ */
+hss_status hss_staged_plan(hss_staged_t* out, uint64_t n, uint32_t p, uint32_t groups, double eps1,
+                           double eps2, hss_key_type kt, int with_payload, const hss_tuning* tuning);
+
+/* Release the plan and its device memory (synchronises the device). NULL is ok. */
+void hss_staged_destroy(hss_staged_t plan);
+
+/* Bytes of device memory held by the plan, its cached blocks included. */
+size_t hss_staged_workspace_bytes(hss_staged_t plan);
+
+/*
+ * hss_staged_partition -- the two-stage partition.  Buffers as for
+ * hss_partition (N keys in and out, payload words or NULL, p+1 offsets);
+ * d_groups: NULL, or r+1 words that receive the group boundaries of stage
+ * 1.  The host reads the r+1 group boundaries between the stages (one
+ * synchronisation) to lay out stage 2.  A group with fewer than p/r keys
+ * (possible only when N is close to p) gives HSS_ERR_UNSUPPORTED.  Returns
+ * after the work on `stream` has completed.
+ */
+hss_status hss_staged_partition(hss_staged_t plan, uint64_t seed, const void* d_keys_in,
+                                const uint64_t* d_vals_in, void* d_keys_out, uint64_t* d_vals_out,
+                                uint64_t* d_offsets, uint64_t* d_groups, void* stream);
+
+/* Host wall time of the last call, in seconds: stage 1 (with the read of the
+ * group boundaries), the layout of stage 2, stage 2. */
+hss_status hss_staged_times(hss_staged_t plan, double* stage1_s, double* setup_s, double* stage2_s);
 
 const char* hss_status_string(hss_status status);
 

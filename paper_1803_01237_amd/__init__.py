@@ -46,8 +46,9 @@ EXPORTS = [
     "hss_batch_profile", "hss_batch_profile_reset", "hss_batch_profile_read",
     "hss_server_create", "hss_server_destroy", "hss_server_submit", "hss_server_poll",
     "hss_server_wait", "hss_server_clock", "hss_server_stats", "hss_server_footprint",
-    "hss_plan_knobs", "hss_plan_set_knobs", "hss_batch_knobs",
-    "hss_status_string", "hss_last_error",
+    "hss_plan_knobs", "hss_plan_set_knobs", "hss_batch_knobs", "hss_plan_buckets",
+    "hss_staged_plan", "hss_staged_destroy", "hss_staged_workspace_bytes", "hss_staged_partition",
+    "hss_staged_times", "hss_status_string", "hss_last_error",
 ]
 
 PROFILE_FAMILIES = ["radix_count", "radix_scan", "radix_scatter", "rounds",
@@ -81,6 +82,20 @@ class _Knobs(C.Structure):
 _vp, _u64, _u32, _dbl = C.c_void_p, C.c_uint64, C.c_uint32, C.c_double
 _lib.hss_plan.argtypes = [C.POINTER(_vp), _u64, _u32, _dbl, C.c_int, C.c_int, C.POINTER(_Tuning)]
 _lib.hss_plan.restype = C.c_int
+_lib.hss_plan_buckets.argtypes = [C.POINTER(_vp), _u64, _u32, _u32, _dbl, C.c_int, C.c_int,
+                                  C.POINTER(_Tuning)]
+_lib.hss_plan_buckets.restype = C.c_int
+_lib.hss_staged_plan.argtypes = [C.POINTER(_vp), _u64, _u32, _u32, _dbl, _dbl, C.c_int, C.c_int,
+                                 C.POINTER(_Tuning)]
+_lib.hss_staged_plan.restype = C.c_int
+_lib.hss_staged_destroy.argtypes = [_vp]
+_lib.hss_staged_destroy.restype = None
+_lib.hss_staged_workspace_bytes.argtypes = [_vp]
+_lib.hss_staged_workspace_bytes.restype = C.c_size_t
+_lib.hss_staged_partition.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.hss_staged_partition.restype = C.c_int
+_lib.hss_staged_times.argtypes = [_vp, C.POINTER(_dbl), C.POINTER(_dbl), C.POINTER(_dbl)]
+_lib.hss_staged_times.restype = C.c_int
 _lib.hss_plan_destroy.argtypes = [_vp]
 _lib.hss_plan_destroy.restype = None
 _lib.hss_workspace_bytes.argtypes = [_vp]
@@ -219,21 +234,28 @@ class RoundTrace:
 
 
 class Plan:
-    """A plan for (N, p, eps, key type, payload).  Owns its device workspace."""
+    """A plan for (N, p, eps, key type, payload).  Owns its device workspace.
+    buckets = q < p splits the p segments into q buckets (one stage of
+    multi-stage HSS); offsets and splitters then have q+1 entries."""
 
     def __init__(self, n: int, p: int, eps: float, key_bytes: int = 8, payload: bool = False,
                  max_rounds: int = 0, k_override: int = 0, force_full_sample: bool = False,
                  trace_level: int = 0, lsd_only: bool = False, probes_per_round: int = 0,
-                 plain_launches: bool = False, autotune: bool = False):
+                 plain_launches: bool = False, autotune: bool = False, buckets: int | None = None):
         tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, trace_level,
                       1 if lsd_only else 0, probes_per_round, 1 if plain_launches else 0,
                       1 if autotune else 0)
         h = _vp()
         kt = HSS_U64 if key_bytes == 8 else HSS_U32
-        _check(_lib.hss_plan(C.byref(h), n, p, eps, kt, 1 if payload else 0, C.byref(tun)),
-               "hss_plan")
+        if buckets is None:
+            _check(_lib.hss_plan(C.byref(h), n, p, eps, kt, 1 if payload else 0, C.byref(tun)),
+                   "hss_plan")
+        else:
+            _check(_lib.hss_plan_buckets(C.byref(h), n, p, buckets, eps, kt, 1 if payload else 0,
+                                         C.byref(tun)), "hss_plan_buckets")
         self._h = h
         self.n, self.p, self.eps = n, p, eps
+        self.q = p if buckets is None else int(buckets)
         self.key_bytes, self.payload = key_bytes, payload
         self.trace_level = trace_level
 
@@ -277,7 +299,7 @@ class Plan:
         if vals is not None and vals_out is None:
             vals_out = torch.empty_like(vals)
         if offsets is None:
-            offsets = torch.empty(self.p + 1, dtype=torch.int64, device=keys.device)
+            offsets = torch.empty(self.q + 1, dtype=torch.int64, device=keys.device)
         return keys_out, vals_out, offsets
 
     def _validate(self, keys, vals):
@@ -344,7 +366,7 @@ class Plan:
                 _check(_lib.hss_trace_round_probes(self._h, j, _np_ptr(r.probe_key),
                                                    _np_ptr(r.probe_tag), _np_ptr(r.probe_rank)),
                        "hss_trace_round_probes")
-                q = self.p - 1
+                q = self.q - 1
                 r.lo_rank = np.zeros(q, dtype=np.uint64)
                 r.hi_rank = np.zeros(q, dtype=np.uint64)
                 r.settled = np.zeros(q, dtype=np.uint8)
@@ -372,14 +394,89 @@ class Plan:
         return out
 
     def splitters(self):
-        p = self.p
-        chi = np.zeros(p + 1, dtype=np.uint64)
-        sk = np.zeros(p + 1, dtype=np.uint64)
-        stg = np.zeros(p + 1, dtype=np.uint64)
-        pieces = np.zeros((p + 1) * p, dtype=np.uint64)
+        p, q = self.p, self.q
+        chi = np.zeros(q + 1, dtype=np.uint64)
+        sk = np.zeros(q + 1, dtype=np.uint64)
+        stg = np.zeros(q + 1, dtype=np.uint64)
+        pieces = np.zeros((q + 1) * p, dtype=np.uint64)
         _check(_lib.hss_trace_splitters(self._h, _np_ptr(chi), _np_ptr(sk), _np_ptr(stg),
                                         _np_ptr(pieces)), "hss_trace_splitters")
-        return chi, sk, stg, pieces.reshape(p + 1, p)
+        return chi, sk, stg, pieces.reshape(q + 1, p)
+
+
+class StagedPlan:
+    """Two-stage HSS: r groups of p/r processors (r divides p).  Stage 1
+    splits into r group buckets (eps1), stage 2 partitions every group with
+    its p/r processors (eps2, seed + 1 + g for group g)."""
+
+    def __init__(self, n: int, p: int, groups: int, eps1: float, eps2: float, key_bytes: int = 8,
+                 payload: bool = False, max_rounds: int = 0, k_override: int = 0,
+                 force_full_sample: bool = False, plain_launches: bool = False,
+                 autotune: bool = False):
+        tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, 0, 0, 0,
+                      1 if plain_launches else 0, 1 if autotune else 0)
+        h = _vp()
+        kt = HSS_U64 if key_bytes == 8 else HSS_U32
+        _check(_lib.hss_staged_plan(C.byref(h), n, p, groups, eps1, eps2, kt, 1 if payload else 0,
+                                    C.byref(tun)), "hss_staged_plan")
+        self._h = h
+        self.n, self.p, self.r = n, p, groups
+        self.key_bytes, self.payload = key_bytes, payload
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hss_staged_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(_lib.hss_staged_workspace_bytes(self._h))
+
+    def times(self):
+        """Host seconds of the last call: (stage 1, stage-2 layout, stage 2)."""
+        a, b, c = _dbl(), _dbl(), _dbl()
+        _check(_lib.hss_staged_times(self._h, C.byref(a), C.byref(b), C.byref(c)), "hss_staged_times")
+        return float(a.value), float(b.value), float(c.value)
+
+    def partition(self, keys, seed: int, vals=None, keys_out=None, vals_out=None, offsets=None,
+                  groups_out=None):
+        torch = _torch()
+        if not keys.is_cuda or not keys.is_contiguous():
+            raise ValueError("keys must be a contiguous device tensor")
+        if keys.numel() != self.n or keys.element_size() != self.key_bytes:
+            raise ValueError("keys do not match the plan")
+        if (vals is not None) != self.payload:
+            raise ValueError("payload presence does not match the plan")
+        if vals is not None and (vals.numel() != self.n or vals.element_size() != 8
+                                 or not vals.is_contiguous() or not vals.is_cuda):
+            raise ValueError("payload must be a contiguous device tensor of N 8-byte words")
+        if keys_out is None:
+            keys_out = torch.empty_like(keys)
+        if vals is not None and vals_out is None:
+            vals_out = torch.empty_like(vals)
+        if offsets is None:
+            offsets = torch.empty(self.p + 1, dtype=torch.int64, device=keys.device)
+        if groups_out is None:
+            groups_out = torch.empty(self.r + 1, dtype=torch.int64, device=keys.device)
+        st = _lib.hss_staged_partition(self._h, seed & NONE, keys.data_ptr(),
+                                       None if vals is None else vals.data_ptr(),
+                                       keys_out.data_ptr(),
+                                       None if vals_out is None else vals_out.data_ptr(),
+                                       offsets.data_ptr(), groups_out.data_ptr(), _stream_handle())
+        _check(st, "hss_staged_partition")
+        return keys_out, vals_out, offsets, groups_out
 
 
 class BatchPlan:

@@ -29,15 +29,21 @@ constexpr int kWindow = kChunk + 1;    // at most kChunk non-empty pieces meet a
 __device__ __forceinline__ uint64_t piece_start(const ExchangeArgs& a, const InstDesc& D,
                                                 uint32_t b, uint32_t s) {
     if (b == 0) return 0;
-    if (b == D.p) return a.seg_off[D.seg0 + s + 1] - a.seg_off[D.seg0 + s];
+    if (b == D.q) return a.seg_off[D.seg0 + s + 1] - a.seg_off[D.seg0 + s];
     return a.prow[D.tab0 + (uint64_t)b * D.p + s];
 }
 
+// Workgroup per row u = bucket b of its instance (the last row of an
+// instance is none: no copy work).
 __global__ __launch_bounds__(kT) void piece_offsets_kernel(ExchangeArgs a) {
     __shared__ uint64_t scratch[kT / kWave];
     const uint32_t u = blockIdx.x;
-    const InstDesc D = a.inst[a.seg_inst[u]];
-    const uint32_t b = u - D.seg0;
+    const InstDesc D = a.inst[a.row_inst[u]];
+    const uint32_t b = u - D.row0;
+    if (b == D.q) {   // uniform over the workgroup
+        if (threadIdx.x == 0) a.chunk0[u] = 0;
+        return;
+    }
     uint64_t run = 0;
     bool bad = false;
     for (uint32_t s0 = 0; s0 < D.p; s0 += kT) {
@@ -53,7 +59,7 @@ __global__ __launch_bounds__(kT) void piece_offsets_kernel(ExchangeArgs a) {
         run += tot;
     }
     const uint64_t blen = a.chi_all[D.row0 + b + 1] - a.chi_all[D.row0 + b];
-    const uint64_t max_bucket = (D.n + D.p - 1) / D.p + 2 * D.tol;
+    const uint64_t max_bucket = (D.n + D.q - 1) / D.q + 2 * D.tol;
     if (bad || (threadIdx.x == 0 && (run != blen || blen > max_bucket)))
         atomicOr(a.err, kErrPieceSum);
     if (threadIdx.x == 0) a.chunk0[u] = (uint32_t)((min(blen, max_bucket) + kChunk - 1) / kChunk);
@@ -62,7 +68,7 @@ __global__ __launch_bounds__(kT) void piece_offsets_kernel(ExchangeArgs a) {
 // One workgroup: exclusive scan of the copy workgroups per bucket.
 __global__ __launch_bounds__(kScanT) void chunk_scan_kernel(ExchangeArgs a) {
     __shared__ uint64_t scratch[kScanT / kWave];
-    const uint32_t n = a.n_segs;
+    const uint32_t n = a.n_rows;
     const uint32_t per = (n + kScanT - 1) / kScanT;
     const uint32_t r0 = min(threadIdx.x * per, n), r1 = min(r0 + per, n);
     uint64_t local = 0;
@@ -95,10 +101,10 @@ __global__ __launch_bounds__(kT) void exchange_copy_kernel(ExchangeArgs a, uint3
     uint32_t* w_off = (uint32_t*)(smem + window);
     __shared__ uint32_t sh_first, sh_count;
     const uint32_t t = blockIdx.x;
-    if (t >= a.chunk0[a.n_segs]) return;
-    const uint32_t u = last_le_u32(a.chunk0, 0, a.n_segs, t);
-    const InstDesc D = a.inst[a.seg_inst[u]];
-    const uint32_t b = u - D.seg0;
+    if (t >= a.chunk0[a.n_rows]) return;
+    const uint32_t u = last_le_u32(a.chunk0, 0, a.n_rows, t);
+    const InstDesc D = a.inst[a.row_inst[u]];
+    const uint32_t b = u - D.row0;
     const uint64_t bstart = a.chi_all[D.row0 + b];
     const uint64_t blen = a.chi_all[D.row0 + b + 1] - bstart;
     const uint64_t r0 = (uint64_t)(t - a.chunk0[u]) * kChunk;
@@ -122,7 +128,7 @@ __global__ __launch_bounds__(kT) void exchange_copy_kernel(ExchangeArgs a, uint3
         out = (K*)a.out + D.pos0 + bstart;
         vout = kPayload ? a.vout + D.pos0 + bstart : nullptr;
     } else {
-        const InstRun& R = a.run[a.seg_inst[u]];
+        const InstRun& R = a.run[a.row_inst[u]];
         out = (K*)R.kout + bstart;
         vout = kPayload ? R.vout + bstart : nullptr;
     }
@@ -179,12 +185,36 @@ uint64_t exchange_chunk_bound(uint64_t total, uint32_t buckets) {
     return total / kChunk + buckets + 1;
 }
 
+// Offsets of two-stage HSS: final bucket g (p/r) + i starts where bucket i
+// of group g starts inside the group, shifted by the group's start.
+__global__ void stage_offsets_kernel(const uint64_t* chi1, const uint64_t* off2, uint32_t r,
+                                     uint32_t pg, uint64_t n, uint64_t* out) {
+    const uint64_t total = (uint64_t)r * pg;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= total;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        if (x == total) {
+            out[x] = n;
+            continue;
+        }
+        const uint64_t g = x / pg, i = x - g * pg;
+        out[x] = chi1[g] + off2[g * (pg + 1) + i];
+    }
+}
+
+hipError_t launch_stage_offsets(const uint64_t* chi1, const uint64_t* off2, uint32_t r, uint32_t pg,
+                                uint64_t n, uint64_t* out, hipStream_t s) {
+    const uint64_t total = (uint64_t)r * pg + 1;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((total + kT - 1) / kT, 1024);
+    hipLaunchKernelGGL(stage_offsets_kernel, dim3(grid), dim3(kT), 0, s, chi1, off2, r, pg, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_exchange(const ExchangeArgs& a, hipStream_t s) {
     Profiler dummy;
     Profiler& prof = a.prof ? *a.prof : dummy;
-    if (a.n_segs == 0) return hipSuccess;
+    if (a.n_rows == 0) return hipSuccess;
     prof.begin(s);
-    hipLaunchKernelGGL(piece_offsets_kernel, dim3(a.n_segs), dim3(kT), 0, s, a);
+    hipLaunchKernelGGL(piece_offsets_kernel, dim3(a.n_rows), dim3(kT), 0, s, a);
     hipLaunchKernelGGL(chunk_scan_kernel, dim3(1), dim3(kScanT), 0, s, a);
     prof.end(kProfExchangeOffsets, s, 0);
     const dim3 grid((unsigned)a.max_chunks);

@@ -108,28 +108,31 @@ struct Arena {
 // Host view of one instance.
 struct InstHost {
     uint64_t n = 0;
-    uint32_t p = 0;
+    uint32_t p = 0;       // segments
+    uint32_t q = 0;       // buckets: p, or fewer in a stage of section 5.3
     double eps = 0;
-    uint64_t tol = 0;     // section 2: the target range is N i/p +- tol
+    uint64_t tol = 0;     // section 2: the target range is N i/q +- tol
     uint32_t k = 1;       // rounds of the rate schedule (section 4.2)
-    double a = 0;         // s_k = 2 ln p / eps
+    double a = 0;         // s_k = 2 ln q / eps
     uint64_t pos0 = 0, tab0 = 0;
     uint32_t seg0 = 0, row0 = 0;
     uint64_t max_seg = 0, max_bucket = 0;
 };
 
+// Every formula that counts buckets takes q (the splitters are i = 1..q-1):
+// with q = p these are the constants of sections 2 and 4.2.
 void instance_constants(InstHost& h, const hss_tuning& t) {
-    const double nd = (double)h.n, pd = (double)h.p;
-    h.tol = (uint64_t)std::floor((nd * h.eps) / (2.0 * pd));
-    h.a = (2.0 * std::log(pd)) / h.eps;
+    const double nd = (double)h.n, qd = (double)h.q;
+    h.tol = (uint64_t)std::floor((nd * h.eps) / (2.0 * qd));
+    h.a = (2.0 * std::log(qd)) / h.eps;
     const double kk = std::ceil(std::log(h.a));
     h.k = (kk >= 1.0) ? (uint32_t)kk : 1u;
     if (t.k_override) h.k = t.k_override;
     h.max_seg = (h.n + h.p - 1) / h.p;
-    h.max_bucket = h.max_seg + 2 * h.tol;
+    h.max_bucket = (h.n + h.q - 1) / h.q + 2 * h.tol;
 }
 
-// Acceptance rule of round j: rate q_j = p s_j / N with s_j = a^(j/k),
+// Acceptance rule of round j: rate q_j = q s_j / N with s_j = a^(j/k),
 // clamped at 1 ("take all").
 // With a probe budget only round 1 is known here (its domain is all N keys);
 // the device sets the later rounds from their measured domains.
@@ -137,8 +140,8 @@ void round_rate(const InstHost& h, const hss_tuning& t, uint32_t j, bool forced,
                 int* all) {
     const double s_j = std::pow(h.a, (double)j / (double)h.k);
     const double q = t.probes_per_round
-                         ? ((double)t.probes_per_round * (double)h.p) / (double)h.n
-                         : ((double)h.p * s_j) / (double)h.n;
+                         ? ((double)t.probes_per_round * (double)h.q) / (double)h.n
+                         : ((double)h.q * s_j) / (double)h.n;
     if (q >= 1.0 || (forced && j == 1 && t.force_full_sample)) {
         *thresh = 0xFFFFFFFFu;
         *all = 1;
@@ -167,7 +170,7 @@ struct Engine {
     std::vector<InstHost> ih;
     uint64_t n_tot = 0;
     uint32_t S = 0, Q = 0;    // segments, splitter rows
-    uint64_t T = 0;           // entries of the (p+1) x p tables
+    uint64_t T = 0;           // entries of the (q+1) x p tables
     uint32_t p_max = 0, J = 1, k_max = 1;
     uint64_t max_seg = 0, max_bucket = 0;
     // engines of a batch read their inputs through per-segment source
@@ -312,8 +315,8 @@ void build_layout(Engine& E, Layout& L) {
         h.tab0 = tab;
         pos += h.n;
         seg += h.p;
-        row += h.p + 1;
-        tab += (uint64_t)(h.p + 1) * h.p;
+        row += h.q + 1;
+        tab += (uint64_t)(h.q + 1) * h.p;
         E.p_max = std::max(E.p_max, h.p);
         E.k_max = std::max(E.k_max, h.k);
         E.max_seg = std::max(E.max_seg, h.max_seg);
@@ -331,15 +334,15 @@ void build_layout(Engine& E, Layout& L) {
     L.inst.assign(B, InstDesc{});
     for (uint32_t I = 0; I < B; ++I) {
         const InstHost& h = E.ih[I];
-        // segment boundaries floor(s N / p) and ideal ranks floor(i N / p):
-        // the same integers (section 2)
+        // segment boundaries floor(s N / p) and ideal ranks floor(i N / q)
+        // (section 2; the same integers when q = p)
         for (uint32_t s = 0; s < h.p; ++s) {
             L.seg_off[h.seg0 + s] = h.pos0 + (uint64_t)(((u128)s * h.n) / h.p);
             L.seg_inst[h.seg0 + s] = I;
         }
-        for (uint32_t i = 0; i <= h.p; ++i) {
+        for (uint32_t i = 0; i <= h.q; ++i) {
             L.row_inst[h.row0 + i] = I;
-            L.ideal[h.row0 + i] = (uint64_t)(((u128)i * h.n) / h.p);
+            L.ideal[h.row0 + i] = (uint64_t)(((u128)i * h.n) / h.q);
         }
         InstDesc& d = L.inst[I];
         d.n = h.n;
@@ -349,7 +352,7 @@ void build_layout(Engine& E, Layout& L) {
         d.p = h.p;
         d.seg0 = h.seg0;
         d.row0 = h.row0;
-        d.pad = 0;
+        d.q = h.q;
     }
     L.seg_off[E.S] = E.n_tot;
     // fences and rank chunks of every segment
@@ -447,7 +450,7 @@ size_t layout(Engine& E, char* base) {
     // count table: the MSD pass of the local sort, and of the bucket sort
     // (one instance only)
     uint64_t tiles = E.listed ? E.msd_tiles : (uint64_t)S * tiles_of(E.max_seg);
-    if (!E.listed) tiles = std::max(tiles, (uint64_t)S * tiles_of(E.max_bucket));
+    if (!E.listed) tiles = std::max(tiles, (uint64_t)E.ih[0].q * tiles_of(E.max_bucket));
     E.counts = ar.take<uint32_t>(tiles * 256 + 256);
     E.counts_words = tiles * 256 + 256;
     RoundArgs& r = E.ra;
@@ -477,7 +480,7 @@ size_t layout(Engine& E, char* base) {
     r.hist = ar.take<RoundHist>(E.J);
     E.chi_all = ar.take<uint64_t>(Q);
     E.dst = ar.take<uint32_t>(E.T > 0 ? E.T : 1);
-    E.chunk0 = ar.take<uint32_t>(S + 1);
+    E.chunk0 = ar.take<uint32_t>(Q + 1);
     E.fence_base = ar.take<uint64_t>(S + 1);
     E.fences.key = ar.take<uint64_t>(E.n_fences + 1);
     E.chunk_seg = ar.take<uint32_t>(E.n_chunks + 1);
@@ -674,7 +677,7 @@ hss_status engine_init(Engine& E) {
     // round and instance; the count matrix holds each instance's probes x p
     uint64_t want = 0, cm = 0;
     for (const InstHost& h : E.ih) {
-        const uint64_t m = std::min<uint64_t>(h.n, 8ull * h.p + 256);
+        const uint64_t m = std::min<uint64_t>(h.n, 8ull * h.q + 256);
         want += m;
         cm += m * h.p;
     }
@@ -700,8 +703,8 @@ hss_status d2h(std::vector<T>& v, const T* d, size_t count, hipStream_t s) {
 // every bucket of the one instance (first=false).
 hss_status segment_sort(Engine& E, bool first, const void* kin, const uint64_t* vin, void* kout,
                         uint64_t* vout, void* ktmp, uint64_t* vtmp, const uint64_t* seg_off,
-                        uint64_t max_len, const uint8_t* seg_shift, const uint64_t* seg_base,
-                        bool with_fences, hipStream_t s) {
+                        uint32_t num_segs, uint64_t max_len, const uint8_t* seg_shift,
+                        const uint64_t* seg_base, bool with_fences, hipStream_t s) {
     if (E.tune.lsd_only) {
         if (E.listed) return fail(HSS_ERR_UNSUPPORTED, "lsd_only in a batch");
         if (!kin || (E.payload && !vin)) return fail(HSS_ERR_INVALID_ARG, "segment sort without an input buffer");
@@ -714,7 +717,7 @@ hss_status segment_sort(Engine& E, bool first, const void* kin, const uint64_t* 
         ss.keys_tmp = ktmp;
         ss.vals_tmp = vtmp;
         ss.seg_off = seg_off;
-        ss.num_segs = E.S;
+        ss.num_segs = num_segs;
         ss.max_seg_len = max_len;
         ss.total_len = E.n_tot;
         ss.counts = E.counts;
@@ -722,7 +725,7 @@ hss_status segment_sort(Engine& E, bool first, const void* kin, const uint64_t* 
         ss.end_bit = E.key_bytes * 8;
         ss.prof = &E.prof;
         HIP_TRY(segmented_radix_sort(ss, s));
-        if (with_fences) HIP_TRY(write_fences(kout, E.key_bytes, E.S, E.fences, s));
+        if (with_fences) HIP_TRY(write_fences(kout, E.key_bytes, num_segs, E.fences, s));
         return HSS_OK;
     }
     // a batch reads its inputs through the segment sources; anything else
@@ -738,7 +741,7 @@ hss_status segment_sort(Engine& E, bool first, const void* kin, const uint64_t* 
     hs.keys_tmp = ktmp;
     hs.vals_tmp = vtmp;
     hs.seg_off = seg_off;
-    hs.num_segs = E.S;
+    hs.num_segs = num_segs;
     hs.max_seg_len = max_len;
     hs.total_len = E.n_tot;
     hs.counts = E.counts;
@@ -942,7 +945,7 @@ hss_status determine_splitters(Engine& E, hipStream_t s) {
                 RoundRecord rec;
                 record_round(E, rec, j);
                 const uint64_t m = c.m_stored;
-                const uint32_t q = E.ih[0].p - 1;
+                const uint32_t q = E.ih[0].q - 1;
                 std::vector<uint32_t> settled;
                 if ((st = d2h(rec.key, r.ps_key, m, s)) != HSS_OK) return st;
                 if ((st = d2h(rec.tag, r.ps_tag, m, s)) != HSS_OK) return st;
@@ -995,7 +998,7 @@ hss_status engine_run(Engine& E, const void* kin, const uint64_t* vin, void* kou
                                        E.payload ? E.direct_vsrc : nullptr, E.key_bytes, s));
     }
     // phase 1: local sort of every segment into B, with its fences
-    hss_status st = segment_sort(E, true, kin, vin, E.B, E.Bv, E.A, E.Av, E.seg_off, E.max_seg,
+    hss_status st = segment_sort(E, true, kin, vin, E.B, E.Bv, E.A, E.Av, E.seg_off, E.S, E.max_seg,
                                  nullptr, nullptr, true, s);
     if (st != HSS_OK) return st;
     // phase 2: splitter rounds
@@ -1009,17 +1012,17 @@ hss_status engine_run(Engine& E, const void* kin, const uint64_t* vin, void* kou
     ex.B = E.B;
     ex.Bv = E.payload ? E.Bv : nullptr;
     ex.n_inst = (uint32_t)E.ih.size();
-    ex.n_segs = E.S;
+    ex.n_rows = E.Q;
     ex.p_max = E.p_max;
     ex.inst = E.inst_d;
     ex.run = E.run_d;
     ex.seg_off = E.seg_off;
-    ex.seg_inst = E.seg_inst;
+    ex.row_inst = E.row_inst;
     ex.prow = E.ra.prow;
     ex.chi_all = E.chi_all;
     ex.dst = E.dst;
     ex.chunk0 = E.chunk0;
-    ex.max_chunks = exchange_chunk_bound(E.n_tot, E.S);
+    ex.max_chunks = exchange_chunk_bound(E.n_tot, E.Q);
     ex.total = E.n_tot;
     ex.out = sort_buckets ? E.A : nullptr;
     ex.vout = sort_buckets ? E.Av : nullptr;
@@ -1028,15 +1031,15 @@ hss_status engine_run(Engine& E, const void* kin, const uint64_t* vin, void* kou
     HIP_TRY(launch_exchange(ex, s));
     // phase 4 (sort, one instance): stable sort of every bucket
     if (sort_buckets) {
-        const uint32_t p = E.ih[0].p;
+        const uint32_t q = E.ih[0].q;
         const uint8_t* shifts = nullptr;
         const uint64_t* bases = nullptr;
-        if (p > 1) {
-            HIP_TRY(launch_bucket_shift(p, E.key_bytes * 8, E.ra.s_key, E.bucket_shift, E.bucket_base, s));
+        if (q > 1) {
+            HIP_TRY(launch_bucket_shift(q, E.key_bytes * 8, E.ra.s_key, E.bucket_shift, E.bucket_base, s));
             shifts = E.bucket_shift;
             bases = E.bucket_base;
         }
-        st = segment_sort(E, false, E.A, E.Av, kout, vout, E.B, E.Bv, E.chi_all, E.max_bucket,
+        st = segment_sort(E, false, E.A, E.Av, kout, vout, E.B, E.Bv, E.chi_all, q, E.max_bucket,
                           shifts, bases, false, s);
         if (st != HSS_OK) return st;
     }
@@ -1062,7 +1065,7 @@ hss_status check_io_raw(bool payload, int key_bytes, uint64_t n, uint32_t p, con
 
 hss_status check_io(const Engine& E, const InstHost& h, const void* kin, const uint64_t* vin,
                     const void* kout, const uint64_t* vout, const uint64_t* offsets) {
-    return check_io_raw(E.payload, E.key_bytes, h.n, h.p, kin, vin, kout, vout, offsets);
+    return check_io_raw(E.payload, E.key_bytes, h.n, h.q, kin, vin, kout, vout, offsets);
 }
 
 hss_status finish(Engine& E, hipStream_t s) {
@@ -1149,12 +1152,15 @@ hss_status run_plain(hss_plan_s* P, uint64_t seed, const void* kin, const uint64
     return call();
 }
 
-hss_status new_engine_instance(Engine& E, uint64_t n, uint32_t p, double eps) {
+hss_status new_engine_instance(Engine& E, uint64_t n, uint32_t p, double eps, uint32_t q = 0) {
     if (n == 0 || p == 0 || (uint64_t)p > n) return fail(HSS_ERR_INVALID_ARG, "need 1 <= p <= N");
     if (!(eps > 0.0 && eps < 1.0)) return fail(HSS_ERR_INVALID_ARG, "need 0 < eps < 1");
+    if (q == 0) q = p;
+    if (q > p) return fail(HSS_ERR_INVALID_ARG, "need 1 <= q <= p");
     InstHost h;
     h.n = n;
     h.p = p;
+    h.q = q;
     h.eps = eps;
     instance_constants(h, E.tune);
     E.ih.push_back(h);
@@ -1375,28 +1381,40 @@ hss_status retire(hss_server_s* S, std::unordered_map<uint64_t, ServerReq>::iter
 
 }  // namespace
 
+namespace {
+
+hss_status plan_args(uint64_t n, uint32_t p, uint32_t q, double eps, hss_key_type kt,
+                     const hss_tuning* tuning) {
+    if (n == 0 || p == 0 || (uint64_t)p > n) return fail(HSS_ERR_INVALID_ARG, "need 1 <= p <= N");
+    if (q == 0 || q > p) return fail(HSS_ERR_INVALID_ARG, "need 1 <= q <= p");
+    if (!(eps > 0.0 && eps < 1.0)) return fail(HSS_ERR_INVALID_ARG, "need 0 < eps < 1");
+    if (kt != HSS_U32 && kt != HSS_U64) return fail(HSS_ERR_INVALID_ARG, "bad key type");
+    if (tuning) {
+        for (uint32_t x : tuning->reserved)
+            if (x) return fail(HSS_ERR_INVALID_ARG, "reserved tuning fields must be zero");
+    }
+    if (n >= (1ull << 32)) return fail(HSS_ERR_UNSUPPORTED, "N >= 2^32 is not supported");
+    return HSS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
-hss_status hss_plan(hss_plan_t* out, uint64_t n, uint32_t p, double eps, hss_key_type kt,
-                    int with_payload, const hss_tuning* tuning) {
+hss_status hss_plan_buckets(hss_plan_t* out, uint64_t n, uint32_t p, uint32_t q, double eps,
+                            hss_key_type kt, int with_payload, const hss_tuning* tuning) {
     try {
         if (!out) return fail(HSS_ERR_INVALID_ARG, "null plan pointer");
         *out = nullptr;
-        if (n == 0 || p == 0 || (uint64_t)p > n) return fail(HSS_ERR_INVALID_ARG, "need 1 <= p <= N");
-        if (!(eps > 0.0 && eps < 1.0)) return fail(HSS_ERR_INVALID_ARG, "need 0 < eps < 1");
-        if (kt != HSS_U32 && kt != HSS_U64) return fail(HSS_ERR_INVALID_ARG, "bad key type");
-        if (tuning) {
-            for (uint32_t x : tuning->reserved)
-                if (x) return fail(HSS_ERR_INVALID_ARG, "reserved tuning fields must be zero");
-        }
-        if (n >= (1ull << 32)) return fail(HSS_ERR_UNSUPPORTED, "N >= 2^32 is not supported");
+        const hss_status va = plan_args(n, p, q, eps, kt, tuning);
+        if (va != HSS_OK) return va;
         hss_plan_s* P = new (std::nothrow) hss_plan_s();
         if (!P) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
         Engine& E = P->e;
         E.key_bytes = kt == HSS_U32 ? 4 : 8;
         E.payload = with_payload != 0;
         if (tuning) E.tune = *tuning;
-        hss_status st = new_engine_instance(E, n, p, eps);
+        hss_status st = new_engine_instance(E, n, p, eps, q);
         if (st == HSS_OK) st = engine_init(E);
         if (st != HSS_OK) {
             delete P;
@@ -1407,6 +1425,13 @@ hss_status hss_plan(hss_plan_t* out, uint64_t n, uint32_t p, double eps, hss_key
     } catch (...) {
         return fail(HSS_ERR_DEVICE, "unexpected exception");
     }
+}
+
+hss_status hss_plan(hss_plan_t* out, uint64_t n, uint32_t p, double eps, hss_key_type kt,
+                    int with_payload, const hss_tuning* tuning) {
+    if (out) *out = nullptr;
+    if (p == 0) return fail(HSS_ERR_INVALID_ARG, "need 1 <= p <= N");
+    return hss_plan_buckets(out, n, p, p, eps, kt, with_payload, tuning);
 }
 
 void hss_plan_destroy(hss_plan_t P) {
@@ -1447,7 +1472,7 @@ hss_status hss_local_sort(hss_plan_t P, const void* kin, const uint64_t* vin, vo
         hss_status st = check_io(E, E.ih[0], kin, vin, kout, vout, nullptr);
         if (st != HSS_OK) return st;
         HIP_TRY(hipSetDevice(E.device));
-        return segment_sort(E, true, kin, vin, kout, vout, E.A, E.Av, E.seg_off, E.max_seg, nullptr,
+        return segment_sort(E, true, kin, vin, kout, vout, E.A, E.Av, E.seg_off, E.S, E.max_seg, nullptr,
                             nullptr, false, (hipStream_t)stream);
     } catch (...) {
         return fail(HSS_ERR_DEVICE, "unexpected exception");
@@ -1499,7 +1524,7 @@ hss_status hss_trace_round_state(hss_plan_t P, uint32_t j, uint64_t* lo_rank, ui
                                  uint8_t* settled, uint64_t* chi) {
     if (!P || j >= P->e.trace.size()) return fail(HSS_ERR_INVALID_ARG, "no such round");
     const RoundRecord& r = P->e.trace[j];
-    const size_t q = P->e.ih[0].p - 1;
+    const size_t q = P->e.ih[0].q - 1;
     if (r.settled.size() != q) return fail(HSS_ERR_INVALID_ARG, "round state needs trace_level >= 1");
     if (lo_rank) std::memcpy(lo_rank, r.lo.data(), q * 8);
     if (hi_rank) std::memcpy(hi_rank, r.hi.data(), q * 8);
@@ -1515,28 +1540,28 @@ hss_status hss_trace_splitters(hss_plan_t P, uint64_t* chi, uint64_t* s_key, uin
         Engine& E = P->e;
         HIP_TRY(hipSetDevice(E.device));
         HIP_TRY(hipDeviceSynchronize());
-        const uint64_t p = E.ih[0].p, n = E.ih[0].n;
-        std::vector<uint64_t> c(p + 1, 0), sk(p + 1, 0), st(p + 1, kNone);
-        std::vector<uint32_t> pr((p + 1) * p, 0);
-        if (p > 1) {
-            HIP_TRY(hipMemcpy(c.data(), E.ra.chi, (p + 1) * 8, hipMemcpyDeviceToHost));
-            HIP_TRY(hipMemcpy(sk.data(), E.ra.s_key, (p + 1) * 8, hipMemcpyDeviceToHost));
-            HIP_TRY(hipMemcpy(st.data(), E.ra.s_tag, (p + 1) * 8, hipMemcpyDeviceToHost));
-            HIP_TRY(hipMemcpy(pr.data(), E.ra.prow, (p + 1) * p * 4, hipMemcpyDeviceToHost));
+        const uint64_t p = E.ih[0].p, q = E.ih[0].q, n = E.ih[0].n;
+        std::vector<uint64_t> c(q + 1, 0), sk(q + 1, 0), st(q + 1, kNone);
+        std::vector<uint32_t> pr((q + 1) * p, 0);
+        if (q > 1) {
+            HIP_TRY(hipMemcpy(c.data(), E.ra.chi, (q + 1) * 8, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(sk.data(), E.ra.s_key, (q + 1) * 8, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(st.data(), E.ra.s_tag, (q + 1) * 8, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(pr.data(), E.ra.prow, (q + 1) * p * 4, hipMemcpyDeviceToHost));
         }
         c[0] = 0;
-        c[p] = n;
-        sk[0] = sk[p] = 0;
-        st[0] = st[p] = kNone;
+        c[q] = n;
+        sk[0] = sk[q] = 0;
+        st[0] = st[q] = kNone;
         std::vector<uint64_t> sb(p + 1);
         for (uint64_t i = 0; i <= p; ++i) sb[i] = (uint64_t)(((u128)i * n) / p);
-        if (chi) std::memcpy(chi, c.data(), (p + 1) * 8);
-        if (s_key) std::memcpy(s_key, sk.data(), (p + 1) * 8);
-        if (s_tag) std::memcpy(s_tag, st.data(), (p + 1) * 8);
+        if (chi) std::memcpy(chi, c.data(), (q + 1) * 8);
+        if (s_key) std::memcpy(s_key, sk.data(), (q + 1) * 8);
+        if (s_tag) std::memcpy(s_tag, st.data(), (q + 1) * 8);
         if (pieces) {
-            for (uint64_t b = 0; b <= p; ++b)
+            for (uint64_t b = 0; b <= q; ++b)
                 for (uint64_t s = 0; s < p; ++s)
-                    pieces[b * p + s] = b == 0 ? 0 : (b == p ? sb[s + 1] - sb[s] : pr[b * p + s]);
+                    pieces[b * p + s] = b == 0 ? 0 : (b == q ? sb[s + 1] - sb[s] : pr[b * p + s]);
         }
         return HSS_OK;
     } catch (...) {
@@ -1858,6 +1883,189 @@ hss_status hss_batch_knobs(hss_batch_t Bt, hss_key_type kt, hss_knobs* out) {
     const Engine* E = Bt->eng[kt == HSS_U32 ? 0 : 1];
     if (!E) return fail(HSS_ERR_INVALID_ARG, "no instance of that key type");
     *out = E->knobs;
+    return HSS_OK;
+}
+
+// ------------------------------------------------------ two stages ----
+// Section 5.3 with two stages: the p segments are first split into r
+// buckets, one per group of p/r processors; every group then runs HSS on its
+// bucket alone.  Stage 1 is a plan with q = r buckets writing into a staging
+// buffer; stage 2 is a batch of the r group instances built for the group
+// sizes of the call (its device blocks come from a cache kept by the plan),
+// reading each group where stage 1 wrote it and writing the caller's output.
+
+}  // extern "C"
+
+struct hss_staged_s {
+    hss_plan_s st1;                 // stage 1: N keys, p segments, r buckets
+    BlockCache cache;               // device and pinned blocks of stage 2
+    uint32_t p = 0, r = 0, pg = 0;
+    uint64_t n = 0;
+    double eps2 = 0;
+    hss_tuning tune2{};
+    void* T = nullptr;              // stage-1 output: N keys
+    uint64_t* Tv = nullptr;         // and payload
+    uint64_t* chi1 = nullptr;       // r+1 group boundaries (device)
+    uint64_t* off2 = nullptr;       // r x (p/r + 1): offsets of every group
+    uint64_t* h_chi1 = nullptr;     // pinned copy of chi1
+    size_t bytes = 0;
+    double t_stage[3] = {0, 0, 0};  // host clock of the last call: stage 1, set-up, stage 2
+    ~hss_staged_s() {
+        (void)hipSetDevice(st1.e.device);
+        (void)hipDeviceSynchronize();
+        for (void* q : {T, (void*)Tv, (void*)chi1, (void*)off2})
+            if (q) (void)hipFree(q);
+        if (h_chi1) (void)hipHostFree(h_chi1);
+    }
+};
+
+namespace {
+
+hss_status staged_stage2(hss_staged_s* P, uint64_t seed, void* kout, uint64_t* vout, hipStream_t s) {
+    Engine& E1 = P->st1.e;
+    std::unique_ptr<Engine> E(new (std::nothrow) Engine());
+    if (!E) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    E->batch = true;
+    E->key_bytes = E1.key_bytes;
+    E->payload = E1.payload;
+    E->tune = P->tune2;
+    E->device = E1.device;
+    E->mem = &P->cache;
+    E->own_stream = s;
+    const uint64_t* c = P->h_chi1;
+    for (uint32_t g = 0; g < P->r; ++g) {
+        const uint64_t ng = c[g + 1] - c[g];
+        if (c[g + 1] < c[g] || c[g + 1] > P->n) return fail(HSS_ERR_DEVICE, "stage 1 returned bad group offsets");
+        if (ng < P->pg)
+            return fail(HSS_ERR_UNSUPPORTED, "group " + std::to_string(g) + " holds " + std::to_string(ng) +
+                                                 " keys, fewer than its " + std::to_string(P->pg) + " processors");
+        hss_status st = new_engine_instance(*E, ng, P->pg, P->eps2);
+        if (st != HSS_OK) return st;
+    }
+    const double t0 = clock_s();
+    hss_status st = engine_init(*E);
+    if (st != HSS_OK) return st;
+    const size_t kb = (size_t)E1.key_bytes;
+    for (uint32_t g = 0; g < P->r; ++g) {
+        const uint64_t o = c[g];
+        E->h_run[g] = InstRun{(seed + 1 + g), (const char*)P->T + o * kb, P->Tv ? P->Tv + o : nullptr,
+                              (char*)kout + o * kb, vout ? vout + o : nullptr,
+                              P->off2 + (uint64_t)g * (P->pg + 1)};
+    }
+    HIP_TRY(hipMemcpyAsync(E->run_d, E->h_run, P->r * sizeof(InstRun), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_counters_reset(E->ra.ctr, s));
+    const double t1 = clock_s();
+    st = engine_run(*E, nullptr, nullptr, nullptr, nullptr, s, false);
+    if (st != HSS_OK) return st;
+    st = finish(*E, s);
+    P->t_stage[1] = t1 - t0;
+    P->t_stage[2] = clock_s() - t1;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+hss_status hss_staged_plan(hss_staged_t* out, uint64_t n, uint32_t p, uint32_t groups, double eps1,
+                           double eps2, hss_key_type kt, int with_payload, const hss_tuning* tuning) {
+    try {
+        if (!out) return fail(HSS_ERR_INVALID_ARG, "null plan pointer");
+        *out = nullptr;
+        if (groups == 0 || p == 0 || p % groups != 0)
+            return fail(HSS_ERR_INVALID_ARG, "need groups >= 1 dividing p");
+        if (!(eps2 > 0.0 && eps2 < 1.0)) return fail(HSS_ERR_INVALID_ARG, "need 0 < eps2 < 1");
+        if (tuning && (tuning->trace_level || tuning->lsd_only || tuning->probes_per_round))
+            return fail(HSS_ERR_UNSUPPORTED, "traces, lsd_only and a probe budget are for single plans");
+        hss_status st = plan_args(n, p, groups, eps1, kt, tuning);
+        if (st != HSS_OK) return st;
+        std::unique_ptr<hss_staged_s> P(new (std::nothrow) hss_staged_s());
+        if (!P) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
+        Engine& E = P->st1.e;
+        E.key_bytes = kt == HSS_U32 ? 4 : 8;
+        E.payload = with_payload != 0;
+        if (tuning) E.tune = *tuning;
+        st = new_engine_instance(E, n, p, eps1, groups);
+        if (st == HSS_OK) st = engine_init(E);
+        if (st != HSS_OK) return st;
+        P->p = p;
+        P->r = groups;
+        P->pg = p / groups;
+        P->n = n;
+        P->eps2 = eps2;
+        if (tuning) P->tune2 = *tuning;
+        P->tune2.autotune = 0;
+        const size_t kb = n * (size_t)E.key_bytes;
+        HIP_TRY(hipMalloc(&P->T, kb));
+        if (E.payload) HIP_TRY(hipMalloc((void**)&P->Tv, n * 8));
+        HIP_TRY(hipMalloc((void**)&P->chi1, ((size_t)groups + 1) * 8));
+        HIP_TRY(hipMalloc((void**)&P->off2, (size_t)groups * (P->pg + 1) * 8));
+        HIP_TRY(hipHostMalloc((void**)&P->h_chi1, ((size_t)groups + 1) * 8, hipHostMallocDefault));
+        P->bytes = kb + (E.payload ? n * 8 : 0) + ((size_t)groups + 1) * 8 + (size_t)groups * (P->pg + 1) * 8;
+        *out = P.release();
+        return HSS_OK;
+    } catch (...) {
+        return fail(HSS_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+void hss_staged_destroy(hss_staged_t P) {
+    if (!P) return;
+    try {
+        delete P;
+    } catch (...) {
+    }
+}
+
+size_t hss_staged_workspace_bytes(hss_staged_t P) {
+    if (!P) return 0;
+    size_t b = P->st1.e.arena_bytes + P->bytes;
+    std::lock_guard<std::mutex> g(P->cache.mu);
+    for (auto& kv : P->cache.dev_size) b += kv.second;
+    return b;
+}
+
+hss_status hss_staged_partition(hss_staged_t P, uint64_t seed, const void* d_keys_in,
+                                const uint64_t* d_vals_in, void* d_keys_out, uint64_t* d_vals_out,
+                                uint64_t* d_offsets, uint64_t* d_groups, void* stream) {
+    if (!P) return fail(HSS_ERR_INVALID_ARG, "null plan");
+    try {
+        Engine& E = P->st1.e;
+        hss_status st = check_io_raw(E.payload, E.key_bytes, P->n, P->p, d_keys_in, d_vals_in, d_keys_out,
+                                     d_vals_out, d_offsets);
+        if (st != HSS_OK) return st;
+        if (!d_offsets) return fail(HSS_ERR_INVALID_ARG, "null offsets pointer");
+        if (d_groups && !aligned16(d_groups)) return fail(HSS_ERR_INVALID_ARG, "device pointers must be 16-byte aligned");
+        const size_t kb = P->n * (size_t)E.key_bytes, vb = P->n * 8, gb = ((size_t)P->r + 1) * 8,
+                     ob = ((size_t)P->p + 1) * 8;
+        if (d_groups && (overlap(d_groups, gb, d_keys_in, kb) || overlap(d_groups, gb, d_keys_out, kb) ||
+                         overlap(d_groups, gb, d_vals_in, vb) || overlap(d_groups, gb, d_vals_out, vb) ||
+                         overlap(d_groups, gb, d_offsets, ob)))
+            return fail(HSS_ERR_INVALID_ARG, "outputs overlap inputs or each other");
+        hipStream_t s = (hipStream_t)stream;
+        HIP_TRY(hipSetDevice(E.device));
+        const double t0 = clock_s();
+        st = run_plain(&P->st1, seed, d_keys_in, d_vals_in, P->T, P->Tv, P->chi1, stream, false);
+        if (st != HSS_OK) return st;
+        HIP_TRY(hipMemcpyAsync(P->h_chi1, P->chi1, ((size_t)P->r + 1) * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        P->t_stage[0] = clock_s() - t0;
+        st = staged_stage2(P, seed, d_keys_out, d_vals_out, s);
+        if (st != HSS_OK) return st;
+        HIP_TRY(launch_stage_offsets(P->chi1, P->off2, P->r, P->pg, P->n, d_offsets, s));
+        if (d_groups) HIP_TRY(hipMemcpyAsync(d_groups, P->chi1, gb, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return HSS_OK;
+    } catch (...) {
+        return fail(HSS_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+hss_status hss_staged_times(hss_staged_t P, double* stage1_s, double* setup_s, double* stage2_s) {
+    if (!P) return fail(HSS_ERR_INVALID_ARG, "null plan");
+    if (stage1_s) *stage1_s = P->t_stage[0];
+    if (setup_s) *setup_s = P->t_stage[1];
+    if (stage2_s) *stage2_s = P->t_stage[2];
     return HSS_OK;
 }
 

@@ -385,10 +385,10 @@ struct InstDesc {
     uint64_t pos0;
     uint64_t tol;
     uint64_t tab0;
-    uint32_t p;
+    uint32_t p;                    // segments (virtual processors)
     uint32_t seg0;
-    uint32_t row0;
-    uint32_t pad;
+    uint32_t row0;                 // rows: splitters 0..q
+    uint32_t q;                    // buckets (= p, or fewer: a stage of multi-stage HSS)
 };
 
 // Per call: seed and the caller's buffers of every instance.
@@ -536,16 +536,17 @@ struct ExchangeArgs {
     const void* B;                 // locally sorted keys of all instances
     const uint64_t* Bv;            // nullptr: keys only
     uint32_t n_inst;
-    uint32_t n_segs;               // = number of buckets
+    uint32_t n_rows;               // rows of all instances: bucket b of instance I is row
+                                   // row0 + b (the last row of an instance is no bucket)
     uint32_t p_max;                // largest p of the instances
     const InstDesc* inst;
     const InstRun* run;
     const uint64_t* seg_off;
-    const uint32_t* seg_inst;
+    const uint32_t* row_inst;
     const uint32_t* prow;
     const uint64_t* chi_all;       // Q rows
     uint32_t* dst;                 // table-shaped: offset of piece (b, s) inside bucket b
-    uint32_t* chunk0;              // S+1: first copy workgroup of every bucket
+    uint32_t* chunk0;              // Q+1: first copy workgroup of every bucket (row)
     uint64_t max_chunks;           // bound on the copy workgroups
     uint64_t total;                // keys of all instances
     // output: the caller's buffers of every instance, or (when out is set)
@@ -557,6 +558,9 @@ struct ExchangeArgs {
 };
 
 hipError_t launch_exchange(const ExchangeArgs& a, hipStream_t s);
+// out[g pg + i] = chi1[g] + off2[g (pg+1) + i] for g < r, i < pg; out[r pg] = n.
+hipError_t launch_stage_offsets(const uint64_t* chi1, const uint64_t* off2, uint32_t r, uint32_t pg,
+                                uint64_t n, uint64_t* out, hipStream_t s);
 // Per-bucket MSD digit for the bucket sort: all keys of bucket b lie in
 // [lo, hi] = [key(S(b)), key(S(b+1))] (0 and the largest key at the ends), so
 // with base = lo the offsets key - lo fit below 2^(shift + 8) for the

@@ -81,7 +81,7 @@ __global__ void round_init_kernel(RoundArgs a) {
     for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < a.n_rows; r += gridDim.x * blockDim.x) {
         const InstDesc& D = a.inst[a.row_inst[r]];
         const uint32_t i = r - D.row0;
-        a.settled[r] = (i == 0 || i == D.p) ? 1u : 0u;   // the ends are fixed
+        a.settled[r] = (i == 0 || i == D.q) ? 1u : 0u;   // the ends are fixed
         a.chi[r] = 0;                                       // until the splitter settles
         a.lrank[r] = kNone;
         a.urank[r] = kNone;
@@ -371,7 +371,7 @@ __global__ void budget_rate_kernel(RoundArgs a, uint32_t round) {
     if (halted(a)) return;
     const uint64_t dom = a.ctr->domain;
     if (dom == 0) return;   // no interval left
-    const double q = ((double)a.budget * (double)a.inst[0].p) / (double)dom;
+    const double q = ((double)a.budget * (double)a.inst[0].q) / (double)dom;
     const bool all = q >= 1.0;
     a.thresh[round - 1] = all ? 0xFFFFFFFFu : (uint32_t)floor(q * 4294967296.0);
     a.all[round - 1] = all ? 1 : 0;
@@ -872,7 +872,7 @@ __global__ void finalize_kernel(RoundArgs a, uint64_t* chi_all) {
         const uint32_t I = a.row_inst[r];
         const InstDesc& D = a.inst[I];
         const uint32_t i = r - D.row0;
-        const uint64_t v = i == 0 ? 0 : (i == D.p ? D.n : a.chi[r]);
+        const uint64_t v = i == 0 ? 0 : (i == D.q ? D.n : a.chi[r]);
         chi_all[r] = v;
         a.run[I].offsets[i] = v;
     }
