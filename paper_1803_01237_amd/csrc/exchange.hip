@@ -24,7 +24,11 @@ namespace {
 constexpr int kT = 256;
 constexpr int kScanT = 1024;
 constexpr int kChunk = 4096;
-constexpr int kWindow = kChunk + 1;    // at most kChunk non-empty pieces meet a chunk
+// LDS window of piece starts: at most kChunk non-empty pieces meet a chunk,
+// but rarely more than a few hundred; a larger window would only cost
+// occupancy (12 bytes per entry), so chunks meeting more pieces search the
+// bucket's row in global memory instead
+constexpr int kWindow = 1024;
 
 __device__ __forceinline__ uint64_t piece_start(const ExchangeArgs& a, const InstDesc& D,
                                                 uint32_t b, uint32_t s) {
@@ -219,7 +223,7 @@ hipError_t launch_exchange(const ExchangeArgs& a, hipStream_t s) {
     prof.end(kProfExchangeOffsets, s, 0);
     const dim3 grid((unsigned)a.max_chunks);
     const bool pay = a.Bv != nullptr;
-    // LDS window: the pieces meeting one chunk, at most p and at most kWindow
+    // LDS window: the pieces meeting one chunk, at most p entries and at most kWindow
     const uint32_t window = a.p_max < (uint32_t)kWindow ? a.p_max : (uint32_t)kWindow;
     const size_t lds = (size_t)window * (8 + 4);
     // algorithmic bytes: every key (and payload word) read once and written once

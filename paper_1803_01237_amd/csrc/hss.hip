@@ -531,6 +531,7 @@ size_t layout(Engine& E, char* base) {
     E.pj.start = ar.take<uint64_t>(pjc);
     E.pj.len = ar.take<uint32_t>(pjc);
     E.pj.entry = ar.take<uint32_t>(pjc);
+    E.pj.base = ar.take<uint64_t>(pjc);
     E.pj.bits = ar.take<uint8_t>(pjc);
     E.pj.capacity = (uint32_t)pjc;
     E.pj.err = list_err;

@@ -243,6 +243,7 @@ struct PackedJobs {
     uint64_t* start = nullptr;         // first position
     uint32_t* len = nullptr;
     uint32_t* entry = nullptr;         // entry of the level's list
+    uint64_t* base = nullptr;          // key offset of the job: entry base + first digit
     uint8_t* bits = nullptr;           // free bits of key - base inside the job
     uint32_t capacity = 0;
     uint32_t* err = nullptr;

@@ -158,11 +158,11 @@ struct SmallJobs {
     uint64_t* vstash = nullptr;
     const uint64_t* seg_off = nullptr;     // positions of every segment
     int key_bits = 64;
-    // a deeper level: job j is packed job j of `pj`, a run of sub-buckets of
+    // packed jobs: job j is packed job j of `pj`, a run of sub-buckets of
     // entry li = pj.entry[j] of the level's list, whose keys were scattered
-    // into the output (loc kLocTmp) or into the MSD buffer (otherwise)
+    // into the output (loc kLocTmp) or into the MSD buffer (otherwise); at
+    // level 1 (lvl_seg null) of MSD pass segment li, in the MSD buffer
     PackedJobs pj;
-    const uint64_t* lvl_base = nullptr;
     const uint32_t* lvl_seg = nullptr;
     const uint8_t* lvl_loc = nullptr;
     EqualList eq;                          // all-equal sub-buckets above the capacity
@@ -212,10 +212,14 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
             base = jobs.pj.start[blockIdx.x];
             n = jobs.pj.len[blockIdx.x];
             const uint32_t li = jobs.pj.entry[blockIdx.x];
-            seg = jobs.lvl_seg[li];
-            kbase = (K)jobs.lvl_base[li];
+            if (jobs.lvl_seg) {
+                seg = jobs.lvl_seg[li];
+                in_out = jobs.lvl_loc[li] == kLocTmp;
+            } else {   // level 1: entry li is MSD pass segment li, scattered into kin
+                seg = jobs.msd_seg ? jobs.msd_seg[li] : li;
+            }
+            kbase = (K)jobs.pj.base[blockIdx.x];
             bits = jobs.pj.bits[blockIdx.x];
-            in_out = jobs.lvl_loc[li] == kLocTmp;
             src = (in_out ? (const K*)kout : kin) + base;
             vsrc = kPayload ? (in_out ? (const uint64_t*)vout : vin) + base : nullptr;
         } else {
@@ -605,13 +609,19 @@ struct DecideView {
     uint32_t capacity = 0;             // of the list behind count
     uint32_t n = 0;
     uint32_t min_len = 0;              // entries of at most this many keys stay
+    const uint8_t* shift = nullptr;    // digit of entry e at bits shift[e]..+7,
+    int shift_all = 0;                 // or at shift_all when null
 };
 
 // Workgroup per entry, between scan and scatter.  When one digit holds all
 // of an entry's keys the scatter would only copy them: the entry skips it,
 // its sub-buckets are emptied, and it moves on with the bits that still vary
 // (AND and OR of the count pass) -- to the equal list when none does, else to
-// the next level's list with the highest varying bit as its new top.
+// the next level's list with the highest varying bit as its new top.  The
+// same holds when the top bits of the digit do not vary and even evenly
+// filled sub-buckets would average more than twice the capacity: every one
+// of them would take another level, so the entry takes that level whole, on
+// the 8 bits below its highest varying bit (one scatter fewer).
 // Deeper levels (pj given) also pack the entry's sub-buckets into small-sort
 // jobs of at most `cap` keys, so that a level does not launch a workgroup per
 // (mostly tiny) sub-bucket.
@@ -630,14 +640,27 @@ __global__ __launch_bounds__(256) void level_decide_kernel(DecideView v, LevelWo
     const uint32_t e = blockIdx.x;
     if (e >= E) return;
     const uint64_t b = v.beg[e], n = v.end[e] - b;
-    if (n <= v.min_len) return;   // uniform over the workgroup
+    // entries of at most min_len keys are sorted as they are (packed into
+    // jobs when pj is given)
+    const bool small = n <= v.min_len;
+    if (small && !pj.count) return;   // uniform over the workgroup
     if (threadIdx.x == 0) nz = 0;
     __syncthreads();
     const uint32_t len = sb_len[(uint64_t)e * 256 + threadIdx.x];
     lens[threadIdx.x] = len;
     if (len) atomicAdd(&nz, 1u);
     __syncthreads();
-    if (nz != 1) {
+    bool narrow = false;
+    const int sh = v.shift ? (int)v.shift[e] : v.shift_all;
+    if (nz > 1 && !small) {   // uniform over the workgroup
+        const uint64_t vary = w.and_mask[e] ^ w.or_mask[e];
+        const int hb = 63 - __clzll((long long)vary);
+        // 2^(hb - sh + 1) digit values can occur; each sub-bucket would
+        // average n / 2^(hb - sh + 1) keys.  The next level's digit must lie
+        // lower (its shift max(hb - 7, 0) is below sh only when sh > 0).
+        narrow = vary != 0 && sh > 0 && hb >= sh && hb < sh + 7 && (n >> (hb - sh + 2)) > cap;
+    }
+    if (small || (nz != 1 && !narrow)) {
         if (!pj.count) return;
         // packing by windows of C = cap / 2 keys: a sub-bucket above C is a
         // job alone; the others form one job per run of sub-buckets whose
@@ -683,15 +706,17 @@ __global__ __launch_bounds__(256) void level_decide_kernel(DecideView v, LevelWo
         __syncthreads();
         const uint32_t nj = n_jobs, q0 = job0;
         if (q0 + nj > pj.capacity) return;
-        const uint32_t shift = w.shift[e];
+        const uint32_t shift = (uint32_t)sh;
         if (d < nj) {
             pj.start[q0 + d] = sb_start[(uint64_t)e * 256 + job_d1[d]];
             pj.len[q0 + d] = job_len[d];
             pj.entry[q0 + d] = e;
-            // the job's digits lie in [first, last], so its keys agree above
-            // the highest bit in which first and last differ (one
-            // sub-bucket: the bits below its digit)
-            const uint32_t x = job_d1[d] ^ job_d0[d];
+            // the job's digits lie in [first, last]: taken from the first
+            // digit on, key - base has digit (d - first) and the same bits
+            // above the digit, so only the bits of last - first and those
+            // below the digit vary (one sub-bucket: the bits below its digit)
+            const uint32_t x = job_d0[d] - job_d1[d];
+            pj.base[q0 + d] = (v.base ? v.base[e] : 0) + ((uint64_t)job_d1[d] << shift);
             pj.bits[q0 + d] = (uint8_t)(shift + (x ? 32 - __clz(x) : 0));
         }
         return;
@@ -798,7 +823,6 @@ SmallJobs<K> level_jobs(const HybridSort& a, const OversizeList& cur, uint32_t g
     jobs.vstash = a.vals_tmp;
     jobs.seg_off = a.seg_off;
     jobs.pj = a.pj;
-    jobs.lvl_base = cur.base;
     jobs.lvl_seg = cur.seg;
     jobs.lvl_loc = cur.loc;
     jobs.eq = a.eq;
@@ -848,6 +872,15 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     hipError_t e = hipSuccess;
 
     hipLaunchKernelGGL(ov_reset_kernel, dim3(1), dim3(1), 0, s, a.ov, a.sl, a.eq);
+    // Sub-buckets averaging under a quarter of the capacity (many segments
+    // of few keys) are packed into jobs of up to `cap` keys, as at the
+    // deeper levels, so that the small sort does not spend a workgroup on
+    // every few hundred keys.  An entry of n keys gives at most 4 n / cap + 1
+    // jobs.
+    const uint64_t msd_keys = listed ? (uint64_t)msd_tiles * kSortTile : a.total_len;
+    const uint64_t job_bound1 = 4 * msd_keys / cap + msd_segs;
+    const bool pack1 = msd_segs > 0 && msd_tiles > 0 && a.pj.count &&
+                       msd_keys < (uint64_t)msd_segs * 256 * (cap / 4) && job_bound1 <= a.pj.capacity;
     // 1. MSD pass of the large segments into the temporary buffer.  A segment
     //    above the small-sort capacity whose top digit holds all its keys
     //    skips the scatter and goes on to the deeper levels.
@@ -898,21 +931,35 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         v.key_bytes = a.key_bytes;
         v.n = msd_segs;
         v.min_len = cap;
+        v.shift = a.seg_shift;
+        v.shift_all = bits;
+        if (pack1) hipLaunchKernelGGL(count_reset_kernel, dim3(1), dim3(1), 0, s, a.pj.count);
         hipLaunchKernelGGL(level_decide_kernel, dim3(msd_segs), dim3(256), 0, s, v, a.lw, a.sb_start,
-                           a.sb_len, a.ov, a.eq, PackedJobs{}, cap);
+                           a.sb_len, a.ov, a.eq, pack1 ? a.pj : PackedJobs{}, cap);
         e = radix_scatter(ps, s);
         if (e != hipSuccess) return e;
     }
-    // 2. sub-buckets, and the segments small enough to take whole, in LDS
+    // 2. sub-buckets (or their packed jobs), and the segments small enough to
+    //    take whole, in LDS
     {
-        const dim3 grid(msd_segs * 256u + a.n_direct);
+        const uint32_t n_first = pack1 ? (uint32_t)job_bound1 : msd_segs * 256u;
+        const dim3 grid(n_first + a.n_direct);
         prof.begin(s);
-        if (a.key_bytes == 4)
-            launch_small_any<uint32_t>(pay, large, false, grid, s, a, a.sb_start, a.sb_len, bits, a.ov,
-                                       level1_jobs<uint32_t>(a, msd_segs, kb));
-        else
-            launch_small_any<uint64_t>(pay, large, false, grid, s, a, a.sb_start, a.sb_len, bits, a.ov,
-                                       level1_jobs<uint64_t>(a, msd_segs, kb));
+        if (a.key_bytes == 4) {
+            SmallJobs<uint32_t> jobs = level1_jobs<uint32_t>(a, msd_segs, kb);
+            if (pack1) {
+                jobs.n_msd = n_first;
+                jobs.pj = a.pj;
+            }
+            launch_small_any<uint32_t>(pay, large, false, grid, s, a, a.sb_start, a.sb_len, bits, a.ov, jobs);
+        } else {
+            SmallJobs<uint64_t> jobs = level1_jobs<uint64_t>(a, msd_segs, kb);
+            if (pack1) {
+                jobs.n_msd = n_first;
+                jobs.pj = a.pj;
+            }
+            launch_small_any<uint64_t>(pay, large, false, grid, s, a, a.sb_start, a.sb_len, bits, a.ov, jobs);
+        }
         prof.end(kProfSmallSort, s, a.total_len * 2 * (a.key_bytes + (pay ? 8 : 0)));
     }
     e = read_summary(a.ov, a.sl, a.eq, host, s);
@@ -922,11 +969,11 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     host.last_levels = 0;
     // 3. deeper levels: every entry above the capacity takes an MSD pass on
     //    the 8 bits below its top, alternating between the MSD buffer and the
-    //    output; each level lowers the top by at least 8 bits, so at most
-    //    kb / 8 levels follow
+    //    output; each level lowers the top of every entry it keeps, so at
+    //    most kb levels follow
     OversizeList cur = a.ov, nxt = a.ov2;
     while (E > 0) {
-        if (++host.last_levels > (uint32_t)kb / 8) return hipErrorUnknown;
+        if (++host.last_levels > (uint32_t)kb) return hipErrorUnknown;
         e = grow(host.mem, &host.fb_counts, &host.fb_words, (uint64_t)T * 256);
         if (e == hipSuccess) {
             uint64_t c0 = host.fb_sb;
@@ -981,6 +1028,7 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         v.key_bytes = a.key_bytes;
         v.count = cur.count;
         v.capacity = cur.capacity;
+        v.shift = a.lw.shift;
         hipLaunchKernelGGL(level_decide_kernel, dim3(E), dim3(256), 0, s, v, a.lw, host.fb_sb_start,
                            host.fb_sb_len, nxt, a.eq, a.pj, cap);
         e = radix_scatter(ps, s);
