@@ -205,6 +205,27 @@ __global__ void stage_offsets_kernel(const uint64_t* chi1, const uint64_t* off2,
     }
 }
 
+__global__ void entry_ranges_kernel(uint32_t n_msd, const uint32_t* __restrict__ msd_seg,
+                                    const uint32_t* __restrict__ seg_inst,
+                                    const uint8_t* __restrict__ ishift, const uint64_t* __restrict__ ibase,
+                                    uint8_t* __restrict__ shift, uint64_t* __restrict__ base) {
+    for (uint32_t li = blockIdx.x * blockDim.x + threadIdx.x; li < n_msd; li += gridDim.x * blockDim.x) {
+        const uint32_t I = seg_inst[msd_seg[li]];
+        shift[li] = ishift[I];
+        base[li] = ibase[I];
+    }
+}
+
+hipError_t launch_entry_ranges(uint32_t n_msd, const uint32_t* msd_seg, const uint32_t* seg_inst,
+                               const uint8_t* ishift, const uint64_t* ibase, uint8_t* shift,
+                               uint64_t* base, hipStream_t s) {
+    if (n_msd == 0) return hipSuccess;
+    const uint32_t grid = std::min<uint32_t>((n_msd + kT - 1) / kT, 1024);
+    hipLaunchKernelGGL(entry_ranges_kernel, dim3(grid), dim3(kT), 0, s, n_msd, msd_seg, seg_inst, ishift,
+                       ibase, shift, base);
+    return hipGetLastError();
+}
+
 hipError_t launch_stage_offsets(const uint64_t* chi1, const uint64_t* off2, uint32_t r, uint32_t pg,
                                 uint64_t n, uint64_t* out, hipStream_t s) {
     const uint64_t total = (uint64_t)r * pg + 1;

@@ -222,6 +222,12 @@ struct Engine {
     uint64_t* msd_vsrc = nullptr;
     uint64_t* direct_src = nullptr;
     uint64_t* direct_vsrc = nullptr;
+    // key range of every MSD list entry (listed engines): the first local
+    // sort takes its digit over it when first_shift is set
+    uint8_t* msd_shift = nullptr;
+    uint64_t* msd_base = nullptr;
+    const uint8_t* first_shift = nullptr;
+    const uint64_t* first_base = nullptr;
 
     uint64_t counts_words = 0;
 
@@ -553,6 +559,8 @@ size_t layout(Engine& E, char* base) {
         E.direct_seg = ar.take<uint32_t>(E.n_direct + 1);
         E.msd_src = ar.take<uint64_t>(E.n_msd + 1);
         E.msd_vsrc = ar.take<uint64_t>(E.n_msd + 1);
+        E.msd_shift = ar.take<uint8_t>(E.n_msd + 1);
+        E.msd_base = ar.take<uint64_t>(E.n_msd + 1);
         E.direct_src = ar.take<uint64_t>(E.n_direct + 1);
         E.direct_vsrc = ar.take<uint64_t>(E.n_direct + 1);
     }
@@ -1000,7 +1008,7 @@ hss_status engine_run(Engine& E, const void* kin, const uint64_t* vin, void* kou
     }
     // phase 1: local sort of every segment into B, with its fences
     hss_status st = segment_sort(E, true, kin, vin, E.B, E.Bv, E.A, E.Av, E.seg_off, E.S, E.max_seg,
-                                 nullptr, nullptr, true, s);
+                                 E.first_shift, E.first_base, true, s);
     if (st != HSS_OK) return st;
     // phase 2: splitter rounds
     E.prof.begin(s);
@@ -1955,6 +1963,16 @@ hss_status staged_stage2(hss_staged_s* P, uint64_t seed, void* kout, uint64_t* v
     }
     HIP_TRY(hipMemcpyAsync(E->run_d, E->h_run, P->r * sizeof(InstRun), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_counters_reset(E->ra.ctr, s));
+    // every key of group g lies between the stage-1 splitter keys g and g+1:
+    // the first local sort takes its MSD digit over that range, as the
+    // bucket sort of a plan does
+    if (E->listed && E->n_msd > 0) {
+        HIP_TRY(launch_bucket_shift(P->r, E1.key_bytes * 8, E1.ra.s_key, E1.bucket_shift, E1.bucket_base, s));
+        HIP_TRY(launch_entry_ranges(E->n_msd, E->msd_seg, E->seg_inst, E1.bucket_shift, E1.bucket_base,
+                                    E->msd_shift, E->msd_base, s));
+        E->first_shift = E->msd_shift;
+        E->first_base = E->msd_base;
+    }
     const double t1 = clock_s();
     st = engine_run(*E, nullptr, nullptr, nullptr, nullptr, s, false);
     if (st != HSS_OK) return st;

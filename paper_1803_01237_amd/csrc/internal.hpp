@@ -291,7 +291,8 @@ struct HybridSort {
     uint32_t* counts = nullptr;        // >= radix_count_words(num_segs, max_seg_len)
     uint64_t* sb_start = nullptr;      // num_segs * 256
     uint32_t* sb_len = nullptr;        // num_segs * 256
-    // optional per-segment MSD digit: every key k of segment s must satisfy
+    // optional MSD digit per entry of the MSD pass (segment s, or list entry
+    // s when msd_seg is given): every key k of the entry must satisfy
     // 0 <= k - seg_base[s] < 2^(seg_shift[s] + 8); the MSD digit is then
     // (k - seg_base[s]) >> seg_shift[s].  nullptr: base 0, the top digit.
     const uint8_t* seg_shift = nullptr;
@@ -560,6 +561,12 @@ struct ExchangeArgs {
 
 hipError_t launch_exchange(const ExchangeArgs& a, hipStream_t s);
 // out[g pg + i] = chi1[g] + off2[g (pg+1) + i] for g < r, i < pg; out[r pg] = n.
+// Key range of every MSD list entry of a multi-instance engine from the range
+// of its instance: shift[li] = ishift[I], base[li] = ibase[I] with
+// I = seg_inst[msd_seg[li]].
+hipError_t launch_entry_ranges(uint32_t n_msd, const uint32_t* msd_seg, const uint32_t* seg_inst,
+                               const uint8_t* ishift, const uint64_t* ibase, uint8_t* shift,
+                               uint64_t* base, hipStream_t s);
 hipError_t launch_stage_offsets(const uint64_t* chi1, const uint64_t* off2, uint32_t r, uint32_t pg,
                                 uint64_t n, uint64_t* out, hipStream_t s);
 // Per-bucket MSD digit for the bucket sort: all keys of bucket b lie in

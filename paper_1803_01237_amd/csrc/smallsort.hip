@@ -227,8 +227,8 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
             n = sb_len[blockIdx.x];
             const uint32_t li = blockIdx.x / 256;
             seg = jobs.msd_seg ? jobs.msd_seg[li] : li;
-            kbase = seg_base ? (K)seg_base[seg] : (K)0;
-            bits = seg_shift ? (int)seg_shift[seg] : uniform_bits;
+            kbase = seg_base ? (K)seg_base[li] : (K)0;
+            bits = seg_shift ? (int)seg_shift[li] : uniform_bits;
             src = kin + base;
             vsrc = kPayload ? vin + base : nullptr;
         }
@@ -859,7 +859,6 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     const uint32_t msd_segs = (listed || tps > 0) ? a.num_segs : 0u;
     const uint32_t msd_tiles = listed ? a.msd_tiles : msd_segs * tps;
     if (msd_segs == 0 && a.n_direct == 0) return hipSuccess;
-    if (listed && (a.seg_shift || a.seg_base)) return hipErrorInvalidValue;
     const int kb = a.key_bytes * 8;
     const int bits = kb - 8;             // bits below the top digit
     Profiler dummy;
