@@ -228,6 +228,10 @@ struct Engine {
     uint64_t* msd_base = nullptr;
     const uint8_t* first_shift = nullptr;
     const uint64_t* first_base = nullptr;
+    // when set, the splitter ranks (Q words) are copied here once the rounds
+    // end, and chi_ready is recorded after the copy (before the exchange)
+    uint64_t* chi_out_host = nullptr;
+    hipEvent_t chi_ready = nullptr;
 
     uint64_t counts_words = 0;
 
@@ -1015,6 +1019,10 @@ hss_status engine_run(Engine& E, const void* kin, const uint64_t* vin, void* kou
     st = determine_splitters(E, s);
     if (st != HSS_OK) return st;
     E.prof.end(kProfRounds, s, 0);
+    if (E.chi_out_host) {
+        HIP_TRY(hipMemcpyAsync(E.chi_out_host, E.chi_all, (size_t)E.Q * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipEventRecord(E.chi_ready, s));
+    }
     // phase 3: exchange into the outputs (or into A before the bucket sort)
     ExchangeArgs ex;
     ex.key_bytes = E.key_bytes;
@@ -1917,6 +1925,8 @@ struct hss_staged_s {
     uint64_t* chi1 = nullptr;       // r+1 group boundaries (device)
     uint64_t* off2 = nullptr;       // r x (p/r + 1): offsets of every group
     uint64_t* h_chi1 = nullptr;     // pinned copy of chi1
+    hipEvent_t chi_ready = nullptr; // h_chi1 holds stage 1's group boundaries
+    hipStream_t setup = nullptr;    // stage 2's table uploads, beside stage 1's exchange
     size_t bytes = 0;
     double t_stage[3] = {0, 0, 0};  // host clock of the last call: stage 1, set-up, stage 2
     ~hss_staged_s() {
@@ -1925,6 +1935,8 @@ struct hss_staged_s {
         for (void* q : {T, (void*)Tv, (void*)chi1, (void*)off2})
             if (q) (void)hipFree(q);
         if (h_chi1) (void)hipHostFree(h_chi1);
+        if (chi_ready) (void)hipEventDestroy(chi_ready);
+        if (setup) (void)hipStreamDestroy(setup);
     }
 };
 
@@ -1940,8 +1952,11 @@ hss_status staged_stage2(hss_staged_s* P, uint64_t seed, void* kout, uint64_t* v
     E->tune = P->tune2;
     E->device = E1.device;
     E->mem = &P->cache;
-    E->own_stream = s;
+    // the layout's uploads go through the plan's own stream (engine_init
+    // waits for them), so that they need not wait for stage 1's exchange
+    E->own_stream = P->setup;
     const uint64_t* c = P->h_chi1;
+    if (c[0] != 0 || c[P->r] != P->n) return fail(HSS_ERR_DEVICE, "stage 1 returned bad group offsets");
     for (uint32_t g = 0; g < P->r; ++g) {
         const uint64_t ng = c[g + 1] - c[g];
         if (c[g + 1] < c[g] || c[g + 1] > P->n) return fail(HSS_ERR_DEVICE, "stage 1 returned bad group offsets");
@@ -1953,6 +1968,7 @@ hss_status staged_stage2(hss_staged_s* P, uint64_t seed, void* kout, uint64_t* v
     }
     const double t0 = clock_s();
     hss_status st = engine_init(*E);
+    E->own_stream = s;
     if (st != HSS_OK) return st;
     const size_t kb = (size_t)E1.key_bytes;
     for (uint32_t g = 0; g < P->r; ++g) {
@@ -1961,7 +1977,7 @@ hss_status staged_stage2(hss_staged_s* P, uint64_t seed, void* kout, uint64_t* v
                               (char*)kout + o * kb, vout ? vout + o : nullptr,
                               P->off2 + (uint64_t)g * (P->pg + 1)};
     }
-    HIP_TRY(hipMemcpyAsync(E->run_d, E->h_run, P->r * sizeof(InstRun), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(E->run_d, E->h_run, (size_t)P->r * sizeof(InstRun), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_counters_reset(E->ra.ctr, s));
     // every key of group g lies between the stage-1 splitter keys g and g+1:
     // the first local sort takes its MSD digit over that range, as the
@@ -2020,6 +2036,8 @@ hss_status hss_staged_plan(hss_staged_t* out, uint64_t n, uint32_t p, uint32_t g
         HIP_TRY(hipMalloc((void**)&P->chi1, ((size_t)groups + 1) * 8));
         HIP_TRY(hipMalloc((void**)&P->off2, (size_t)groups * (P->pg + 1) * 8));
         HIP_TRY(hipHostMalloc((void**)&P->h_chi1, ((size_t)groups + 1) * 8, hipHostMallocDefault));
+        HIP_TRY(hipEventCreateWithFlags(&P->chi_ready, hipEventDisableTiming));
+        HIP_TRY(hipStreamCreateWithFlags(&P->setup, hipStreamNonBlocking));
         P->bytes = kb + (E.payload ? n * 8 : 0) + ((size_t)groups + 1) * 8 + (size_t)groups * (P->pg + 1) * 8;
         *out = P.release();
         return HSS_OK;
@@ -2064,12 +2082,34 @@ hss_status hss_staged_partition(hss_staged_t P, uint64_t seed, const void* d_key
         hipStream_t s = (hipStream_t)stream;
         HIP_TRY(hipSetDevice(E.device));
         const double t0 = clock_s();
-        st = run_plain(&P->st1, seed, d_keys_in, d_vals_in, P->T, P->Tv, P->chi1, stream, false);
-        if (st != HSS_OK) return st;
-        HIP_TRY(hipMemcpyAsync(P->h_chi1, P->chi1, ((size_t)P->r + 1) * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        bool stage1_done = false;
+        if (E.tune.autotune && !E.knobs.tuned) {
+            // the first call tunes stage 1 through whole plain calls
+            st = run_plain(&P->st1, seed, d_keys_in, d_vals_in, P->T, P->Tv, P->chi1, stream, false);
+            if (st != HSS_OK) return st;
+            HIP_TRY(hipMemcpyAsync(P->h_chi1, P->chi1, ((size_t)P->r + 1) * 8, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            stage1_done = true;
+        } else {
+            // the group boundaries come back as soon as the rounds end: stage
+            // 2 is laid out on the host while stage 1's exchange still runs
+            HIP_TRY(launch_set_run(InstRun{seed, d_keys_in, d_vals_in, P->T, P->Tv, P->chi1}, E.run_d, s));
+            HIP_TRY(launch_counters_reset(E.ra.ctr, s));
+            E.chi_out_host = P->h_chi1;
+            E.chi_ready = P->chi_ready;
+            st = engine_run(E, d_keys_in, d_vals_in, P->T, P->Tv, s, false);
+            E.chi_out_host = nullptr;
+            E.chi_ready = nullptr;
+            if (st != HSS_OK) return st;
+            HIP_TRY(hipEventSynchronize(P->chi_ready));
+        }
         P->t_stage[0] = clock_s() - t0;
         st = staged_stage2(P, seed, d_keys_out, d_vals_out, s);
+        // stage 1's own checks (its exchange ran before stage 2 on the stream)
+        if (!stage1_done) {
+            const hss_status s1 = finish(E, s);
+            if (s1 != HSS_OK) return s1;
+        }
         if (st != HSS_OK) return st;
         HIP_TRY(launch_stage_offsets(P->chi1, P->off2, P->r, P->pg, P->n, d_offsets, s));
         if (d_groups) HIP_TRY(hipMemcpyAsync(d_groups, P->chi1, gb, hipMemcpyDeviceToDevice, s));
