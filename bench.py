@@ -41,13 +41,13 @@ WORKLOADS = {
 # figures hold for the kernel sources with the hash below; after any change
 # to them the traffic is reported as null until the counters are taken again.
 TRAFFIC_WORKLOAD = "uniform_u64_2^28_p1024"
-TRAFFIC_SRC_SHA = "f44b9a6b5525e0cf"
+TRAFFIC_SRC_SHA = "abf5f96268818584"
 TRAFFIC = {   # family: (fetch bytes, write bytes) per launch
-    "radix_count": (2147733077, 71303168),
+    "radix_count": (2147722696, 71303168),
     "radix_scan": (134381568, 70254592),
-    "radix_scatter": (2214724181, 2313362400),
-    "exchange_copy": (2306406571, 2152673899),
-    "small_sort": (2229556053, 2294237141),
+    "radix_scatter": (2214722212, 2316126822),
+    "exchange_copy": (2306309550, 2152674938),
+    "small_sort": (2229541677, 2294237176),
 }
 
 
