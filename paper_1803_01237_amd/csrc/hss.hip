@@ -76,6 +76,8 @@ constexpr uint32_t kMaxRateRounds = 64;  // rounds kept in the rate table
 // Expected first-round probes above which they are sorted by the segmented
 // sort rather than ranked pairwise inside their interval.
 constexpr uint64_t kBigRound = 16384;
+constexpr uint64_t kPresampleMin = 1ull << 20;   // keys of a plan whose first draws go ahead
+constexpr uint64_t kPresampleCapMax = 1ull << 24; // longest list of draws taken ahead
 // First round whose ranks are searched inside the probes' interval slices
 // (round 1 has one interval, the whole input: searched by segment chunks).
 constexpr uint32_t kPairRankFrom = 2;
@@ -232,6 +234,16 @@ struct Engine {
     // end, and chi_ready is recorded after the copy (before the exchange)
     uint64_t* chi_out_host = nullptr;
     hipEvent_t chi_ready = nullptr;
+    // one large instance: the draws of the first rounds are taken on a side
+    // stream while the memory-bound local sort runs (they depend on the
+    // seed and the tags only)
+    uint32_t pre_rounds = 0;
+    uint32_t pre_thresh[kPreRounds] = {};
+    uint32_t pre_cap = 0;
+    uint32_t* pre_mem = nullptr;        // kPreRounds counts, then pre_rounds lists of pre_cap tags
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_start = nullptr, ev_pre = nullptr;
+    uint64_t cur_seed = 0;              // seed of the call in progress
 
     uint64_t counts_words = 0;
 
@@ -278,6 +290,13 @@ struct Engine {
         else (void)hipDeviceSynchronize();
         if (rounds_exec) (void)hipGraphExecDestroy(rounds_exec);
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
+        if (aux) {
+            (void)hipStreamSynchronize(aux);
+            (void)hipStreamDestroy(aux);
+        }
+        if (ev_start) (void)hipEventDestroy(ev_start);
+        if (ev_pre) (void)hipEventDestroy(ev_pre);
+        if (pre_mem) dev_release(mem, pre_mem);
         for (void* q : {probe_mem, psort_mem, (void*)cmat, (void*)hh.fb_counts, (void*)hh.fb_sb_start,
                         (void*)hh.fb_sb_len, arena})
             if (q) dev_release(mem, q);
@@ -686,6 +705,41 @@ hss_status engine_init(Engine& E) {
     r.chunk_lo = E.chunk_lo;
     r.n_chunks = E.n_chunks;
     r.fences = E.fences;
+    // draws taken ahead: the first rounds (up to kPreRounds) of one instance
+    // of at least kPresampleMin keys, while their rate is fixed and below 1
+    // (with a probe budget only round 1's is)
+    for (uint32_t j = 0; j < kPreRounds; ++j) {
+        r.pre_list[j] = nullptr;
+        r.pre_cnt[j] = nullptr;
+    }
+    r.pre_cap = 0;
+    E.pre_rounds = 0;
+    double expect = 0;   // largest expected number of draws below a threshold
+    if (!E.batch && E.ih.size() == 1 && E.n_tot >= kPresampleMin && !E.tune.lsd_only) {
+        for (uint32_t j = 1; j <= kPreRounds && j <= E.J; ++j) {
+            if (L.all[j - 1] || (j > 1 && E.tune.probes_per_round)) break;
+            E.pre_thresh[j - 1] = L.thresh[j - 1];
+            expect = std::max(expect, (double)E.n_tot * ((double)L.thresh[j - 1] / 4294967296.0));
+            E.pre_rounds = j;
+        }
+    }
+    // a list of twice the expected draws plus 4096 holds all of them except
+    // with negligible probability (binomial counts); a longer one is not
+    // used (the sampler draws itself)
+    if (E.pre_rounds && expect * 2 + 4096 > (double)kPresampleCapMax) E.pre_rounds = 0;
+    if (E.pre_rounds) {
+        E.pre_cap = (uint32_t)(expect * 2 + 4096);
+        HIP_TRY(dev_alloc(E.mem, (void**)&E.pre_mem,
+                          (kPreRounds + (uint64_t)E.pre_cap * E.pre_rounds) * sizeof(uint32_t)));
+        HIP_TRY(hipStreamCreateWithFlags(&E.aux, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&E.ev_start, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&E.ev_pre, hipEventDisableTiming));
+        r.pre_cap = E.pre_cap;
+        for (uint32_t j = 0; j < E.pre_rounds; ++j) {
+            r.pre_cnt[j] = E.pre_mem + j;
+            r.pre_list[j] = E.pre_mem + kPreRounds + (uint64_t)j * E.pre_cap;
+        }
+    }
     // probes: a generous multiple of the expected sample p s_j / s_{j-1} per
     // round and instance; the count matrix holds each instance's probes x p
     uint64_t want = 0, cm = 0;
@@ -1010,10 +1064,23 @@ hss_status engine_run(Engine& E, const void* kin, const uint64_t* vin, void* kou
         HIP_TRY(launch_segment_sources(E.ra, E.direct_seg, E.n_direct, E.direct_src,
                                        E.payload ? E.direct_vsrc : nullptr, E.key_bytes, s));
     }
+    if (E.pre_rounds) {
+        // after the work already on the caller's stream (the previous call's
+        // rounds read the masks)
+        HIP_TRY(hipEventRecord(E.ev_start, s));
+        HIP_TRY(hipStreamWaitEvent(E.aux, E.ev_start, 0));
+        HIP_TRY(launch_presample_reset(E.pre_mem, kPreRounds, E.aux));
+        for (uint32_t j = 1; j <= E.pre_rounds; ++j)
+            HIP_TRY(launch_presample(E.cur_seed, E.n_tot, j, E.pre_thresh[j - 1],
+                                     E.pre_mem + kPreRounds + (uint64_t)(j - 1) * E.pre_cap, E.pre_cap,
+                                     E.pre_mem + (j - 1), E.aux));
+        HIP_TRY(hipEventRecord(E.ev_pre, E.aux));
+    }
     // phase 1: local sort of every segment into B, with its fences
     hss_status st = segment_sort(E, true, kin, vin, E.B, E.Bv, E.A, E.Av, E.seg_off, E.S, E.max_seg,
                                  E.first_shift, E.first_base, true, s);
     if (st != HSS_OK) return st;
+    if (E.pre_rounds) HIP_TRY(hipStreamWaitEvent(s, E.ev_pre, 0));
     // phase 2: splitter rounds
     E.prof.begin(s);
     st = determine_splitters(E, s);
@@ -1158,6 +1225,7 @@ hss_status run_plain(hss_plan_s* P, uint64_t seed, const void* kin, const uint64
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(hipSetDevice(E.device));
     InstRun run{seed, kin, vin, kout, vout, d_offsets};
+    E.cur_seed = seed;
     auto call = [&]() -> hss_status {
         HIP_TRY(launch_set_run(run, E.run_d, s));
         HIP_TRY(launch_counters_reset(E.ra.ctr, s));
@@ -2097,6 +2165,7 @@ hss_status hss_staged_partition(hss_staged_t P, uint64_t seed, const void* d_key
             HIP_TRY(launch_counters_reset(E.ra.ctr, s));
             E.chi_out_host = P->h_chi1;
             E.chi_ready = P->chi_ready;
+            E.cur_seed = seed;
             st = engine_run(E, d_keys_in, d_vals_in, P->T, P->Tv, s, false);
             E.chi_out_host = nullptr;
             E.chi_ready = nullptr;

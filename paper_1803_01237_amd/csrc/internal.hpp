@@ -437,6 +437,11 @@ enum DeviceErr : unsigned int {
     kErrPieceSum = 4u,             // a bucket's pieces do not add up to chi(b+1) - chi(b)
 };
 
+// Rounds whose draws may be taken ahead.  The draws of a round cost about
+// 0.25 ms of ALU work at 2^28 keys; two rounds fit beside the count pass of
+// the local sort (a pure stream), more spill into the scatter and slow it.
+constexpr uint32_t kPreRounds = 2;
+
 struct RoundArgs {
     int key_bytes;
     const void* B;                 // locally sorted keys of all instances
@@ -452,6 +457,14 @@ struct RoundArgs {
                                    // the probe's interval slice (earlier: by segment chunks)
     uint32_t sample_grid;          // workgroups of the sampler
     uint32_t pair_grid;            // workgroups of the per-pair rank search
+    // one instance: the draws of rounds 1..kPreRounds taken ahead of the
+    // rounds: pre_list[j-1] holds, in any order, every tag whose Philox word
+    // of round j is below the round's threshold (pre_cnt[j-1] of them; more
+    // than pre_cap: the list is incomplete and the sampler draws itself), or
+    // null
+    const uint32_t* pre_list[kPreRounds];
+    const uint32_t* pre_cnt[kPreRounds];
+    uint32_t pre_cap;
     const uint64_t* seg_off;       // S+1 positions
     const uint32_t* seg_inst;      // S
     const uint32_t* row_inst;      // Q
@@ -508,6 +521,12 @@ constexpr uint32_t kRankChunk = 1u << 15;   // keys of a segment per rank workgr
 
 hipError_t launch_counters_reset(RoundCounters* ctr, hipStream_t s);
 // Start of a call's rounds: every splitter unsettled with open bounds.
+// Every tag g < n whose Philox word of round `round` is below `thresh` (the
+// sampler's decision, which does not depend on the keys), appended in any
+// order to list (capacity cap; *count receives the full number).
+hipError_t launch_presample(uint64_t seed, uint64_t n, uint32_t round, uint32_t thresh, uint32_t* list,
+                            uint32_t cap, uint32_t* count, hipStream_t s);
+hipError_t launch_presample_reset(uint32_t* counts, uint32_t n, hipStream_t s);
 hipError_t launch_round_init(const RoundArgs& a, hipStream_t s);
 // One whole round j (section 4.2.2 steps 1-5) for every instance; sizes are
 // read on the device, so nothing here waits for the host.

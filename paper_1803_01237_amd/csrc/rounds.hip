@@ -237,6 +237,54 @@ __global__ __launch_bounds__(kT) void compact_kernel(RoundArgs a) {
     }
 }
 
+// Sampler of a round whose draws were taken ahead (one instance): thread per
+// listed tag g; g is a probe when it lies in the slice of an interval in its
+// segment.  The intervals are disjoint and in key order, so their slices in
+// one segment are disjoint and in position order: the last interval whose
+// slice starts at or before g is the only one that may hold it.
+template <typename K>
+__device__ void sample_from_list(const RoundArgs& a, const uint32_t* list, uint32_t cnt) {
+    const uint32_t n_ivl = a.ctr->n_ivl;
+    if (n_ivl == 0) return;
+    const InstDesc D = a.inst[0];
+    const K* B = (const K*)a.B;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+        const uint64_t g = list[t];
+        if (g >= D.n) continue;
+        uint32_t lo = 0, hi = D.p;   // segment: the last one starting at or before g
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.seg_off[D.seg0 + mid] - D.pos0 <= g) lo = mid; else hi = mid;
+        }
+        const uint32_t s = lo;
+        auto bounds = [&](uint32_t k, uint64_t* ga, uint64_t* gb) {
+            const uint32_t row = a.ivl_row[k];
+            slice_bounds(a, D, row - D.row0, s, a.lrank[row] == kNone, a.urank[row] == kNone, ga, gb);
+        };
+        uint32_t kl = 0, kh = n_ivl;   // the last interval whose slice starts at or before g
+        uint64_t ga, gb;
+        bounds(0, &ga, &gb);
+        if (ga > g) continue;
+        while (kh - kl > 1) {
+            const uint32_t mid = (kl + kh) >> 1;
+            uint64_t ma, mb;
+            bounds(mid, &ma, &mb);
+            if (ma <= g) kl = mid; else kh = mid;
+        }
+        bounds(kl, &ga, &gb);
+        if (g < ga || g >= gb) continue;
+        const uint64_t o = atomicAdd(&a.ctr->m, 1ull);
+        if (o < a.cap) {
+            a.pr_key[o] = (uint64_t)B[D.pos0 + g];
+            a.pr_tag[o] = g;
+            a.pr_ivl[o] = kl;
+            atomicAdd(&a.ivl_pcnt[kl], 1u);
+        } else {
+            atomicOr(&a.ctr->overflow, 1u);
+        }
+    }
+}
+
 // Wave-per-range sampler.  Wave w of W takes the blocks [w T / W, (w+1) T / W)
 // of the flattened block space (T blocks), one block per lane per step.  The
 // slice list is walked with a window of 64 consecutive entries, one per lane:
@@ -246,6 +294,13 @@ __global__ __launch_bounds__(kT) void compact_kernel(RoundArgs a) {
 template <typename K, bool kSingle>
 __global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint32_t round) {
     constexpr uint32_t kNoBlock = 0xFFFFFFFFu;   // start of the entries past the list
+    if (kSingle && round <= kPreRounds && a.pre_list[round - 1]) {
+        const uint32_t cnt = *a.pre_cnt[round - 1];
+        if (cnt <= a.pre_cap) {   // uniform: the round's draws were taken ahead
+            sample_from_list<K>(a, a.pre_list[round - 1], cnt);
+            return;
+        }
+    }
     const uint32_t total = (uint32_t)a.ctr->blocks;
     const uint32_t nsl = a.ctr->n_slices;
     const K* B = (const K*)a.B;
@@ -900,6 +955,65 @@ unsigned grid_for(uint64_t n, unsigned threads, unsigned cap = 1u << 20) {
 
 hipError_t launch_counters_reset(RoundCounters* ctr, hipStream_t s) {
     hipLaunchKernelGGL(counters_reset_kernel, dim3(1), dim3(1), 0, s, ctr);
+    return hipGetLastError();
+}
+
+// Thread per 32 tags (8 Philox blocks); a wave appends its hits with one
+// atomic.  Tags are below 2^32.
+__global__ __launch_bounds__(kT) void presample_kernel(uint64_t seed, uint64_t n, uint32_t round,
+                                                       uint32_t thresh, uint32_t* __restrict__ list,
+                                                       uint32_t cap, uint32_t* __restrict__ count) {
+    const uint64_t words = (n + 31) / 32;
+    const uint64_t stride = (uint64_t)gridDim.x * kT;
+    const uint32_t lane = lane_id();
+    // every lane of a wave runs the same number of steps (the ballot and the
+    // scan below need the whole wave)
+    const uint64_t w0 = (uint64_t)blockIdx.x * kT + (threadIdx.x - lane);
+    for (uint64_t wb = w0; wb < words; wb += stride) {
+        const uint64_t w = wb + lane;
+        uint32_t m = 0;
+        if (w < words) {
+#pragma unroll
+            for (uint32_t i = 0; i < 8; ++i) {
+                const Philox4 r = sample_block(seed, w * 8 + i, round);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (r.v[q] < thresh && w * 32 + i * 4 + q < n) m |= 1u << (i * 4 + q);
+            }
+        }
+        if (__ballot(m != 0)) {
+            const uint32_t c = __popc(m);
+            const uint32_t inc = wave_inclusive_scan<uint32_t>(c);
+            uint32_t base = 0;
+            if (lane == kWave - 1) base = atomicAdd(count, inc);
+            base = (uint32_t)__shfl((int)base, kWave - 1);
+            uint32_t o = base + inc - c;
+            while (m) {
+                const uint32_t b = __ffs(m) - 1;
+                m &= m - 1;
+                if (o < cap) list[o] = (uint32_t)(w * 32 + b);
+                ++o;
+            }
+        }
+    }
+}
+
+__global__ void presample_reset_kernel(uint32_t* counts, uint32_t n) {
+    if (threadIdx.x < n) counts[threadIdx.x] = 0;
+}
+
+hipError_t launch_presample_reset(uint32_t* counts, uint32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(presample_reset_kernel, dim3(1), dim3(64), 0, s, counts, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_presample(uint64_t seed, uint64_t n, uint32_t round, uint32_t thresh, uint32_t* list,
+                            uint32_t cap, uint32_t* count, hipStream_t s) {
+    const uint64_t words = (n + 31) / 32;
+    if (words == 0) return hipSuccess;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((words + kT - 1) / kT, 65536);
+    hipLaunchKernelGGL(presample_kernel, dim3(grid), dim3(kT), 0, s, seed, n, round, thresh, list, cap,
+                       count);
     return hipGetLastError();
 }
 

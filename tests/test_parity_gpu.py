@@ -71,6 +71,7 @@ CASES = [
     ("uniform64", 1 << 22, 256, 0.02, 14, 64, False),    # medium, k = 7
     ("uniform64", 1, 1, 0.5, 15, 64, True),              # a single key
     ("uniform64", 4097, 4096, 0.9, 16, 64, False),       # many tiny segments
+    ("uniform32", 1 << 21, 64, 0.02, 17, 32, True),      # first draws taken ahead, u32
 ]
 
 
@@ -182,6 +183,7 @@ BUDGET_CASES = [
     ("SKEW2", 100_000, 16, 0.05, 32, 64, True, 1),
     ("uniform32", 1 << 17, 32, 0.02, 33, 32, True, 3),
     ("GAUSS", 1 << 16, 128, 0.05, 34, 64, False, 1),
+    ("uniform64", 1 << 20, 64, 0.02, 35, 64, True, 5),    # round 1's draws taken ahead
 ]
 
 
