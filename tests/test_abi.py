@@ -58,3 +58,17 @@ def test_no_oracle_in_product_path():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "liboracle" not in text, fn
                 assert "hss_oracle" not in text, fn
+
+
+def test_bucket_and_staged_plans_reject_invalid_arguments_before_touching_the_device():
+    import paper_1803_01237_amd as lib
+    for n, p, q in [(100, 8, 0), (100, 8, 9), (0, 1, 1), (10, 11, 2)]:
+        with pytest.raises(lib.HssError) as ei:
+            lib.Plan(n, p, 0.05, buckets=q)
+        assert ei.value.status == -1
+    for n, p, r, e1, e2 in [(1000, 16, 3, 0.05, 0.05), (1000, 16, 0, 0.05, 0.05),
+                            (1000, 16, 4, 0.0, 0.05), (1000, 16, 4, 0.05, 1.0),
+                            (10, 16, 4, 0.05, 0.05), (1000, 16, 32, 0.05, 0.05)]:
+        with pytest.raises(lib.HssError) as ei:
+            lib.StagedPlan(n, p, r, e1, e2)
+        assert ei.value.status == -1
