@@ -84,11 +84,31 @@ def cpu_baseline(kind, n_sample, p, eps, dseed, hseed, payload):
     r = oracle.hss(keys, p, eps, hseed, vals=vals, mode="partition", trace_level=0)
     dt = time.perf_counter() - t0
     assert r.status == 0
+    # the small configuration (2^20 uniform keys, p = 16, eps = 0.05), for scale
+    k1 = synth.make("uniform64", 1 << 20, 1)
+    t1 = time.perf_counter()
+    r1 = oracle.hss(k1, 16, 0.05, 1, mode="partition", trace_level=0)
+    d1 = time.perf_counter() - t1
+    assert r1.status == 0
     return {"value": n_sample / dt / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
             "sample": f"hss_partition of the first {n_sample} keys of the same generator "
                       f"(seed {dseed}), p={p}, eps={eps}, single-threaded C++ oracle, "
                       f"{dt:.2f} s",
-            "seconds": round(dt, 3)}
+            "seconds": round(dt, 3),
+            "small_config": {"n": 1 << 20, "p": 16, "eps": 0.05, "seconds": round(d1, 3),
+                             "gkeys_per_s": round((1 << 20) / d1 / 1e9, 5)},
+            "host": {"nproc": os.cpu_count(), "cpu": _cpu_model()}}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def batched_bench(steps, count):
