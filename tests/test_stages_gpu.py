@@ -208,3 +208,64 @@ def test_two_stage_fullsize_uniform_2p28_p4096_r64(hss):
     assert np.all(mx[:-1] <= mn[1:])
     # no bucket above N (1 + eps)^2 / p + 2 keys
     assert int(np.diff(offs).max()) <= int(n * (1 + eps) ** 2 / p) + 2
+
+
+def _random_shapes(seed, count, staged):
+    rng = np.random.default_rng(seed)
+    kinds = ["uniform64", "SKEW1", "SKEW2", "SKEW3", "GAUSS", "zipf_morton", "ALLZEROS"]
+    out = []
+    for i in range(count):
+        kind = kinds[int(rng.integers(0, len(kinds)))]
+        n = int(2 ** rng.uniform(10, 20))
+        if staged:
+            r = int(rng.integers(1, 17))
+            pg = int(rng.integers(1, 17))
+            p = r * pg
+            if p > n // 4:
+                continue
+            out.append((kind, n, p, r, float(rng.choice([0.01, 0.05, 0.2])),
+                        float(rng.choice([0.01, 0.05, 0.2])), 32 if rng.random() < 0.3 else 64,
+                        bool(rng.random() < 0.5), 100 + i))
+        else:
+            p = int(rng.integers(1, min(n, 600) + 1))
+            q = int(rng.integers(1, p + 1))
+            out.append((kind, n, p, q, float(rng.choice([0.01, 0.05, 0.3])),
+                        32 if rng.random() < 0.3 else 64, bool(rng.random() < 0.5), 200 + i))
+    return out
+
+
+@pytest.mark.parametrize("case", _random_shapes(7, 24, False), ids=lambda c: f"{c[0]}-{c[1]}-p{c[2]}-q{c[3]}")
+def test_random_bucket_plans_match_oracle(hss, case):
+    kind, n, p, q, eps, bits, payload, seed = case
+    _say(f"[random-buckets] {case}")
+    keys = _keys(kind, n, seed, bits)
+    vals = np.arange(n, dtype=np.uint64) if payload else None
+    ref = oracle.hss(keys, p, eps, seed, vals=vals, trace_level=0, buckets=q)
+    assert ref.status == 0
+    with hss.Plan(n, p, eps, key_bytes=keys.itemsize, payload=payload, buckets=q) as plan:
+        ko, vo, off = plan.partition(_dev(keys), seed, None if vals is None else _dev(vals))
+        assert np.array_equal(_host(off, np.uint64), ref.offsets)
+        assert np.array_equal(_host(ko, keys.dtype), ref.keys)
+        if payload:
+            assert np.array_equal(_host(vo, np.uint64), ref.vals)
+
+
+@pytest.mark.parametrize("case", _random_shapes(8, 16, True), ids=lambda c: f"{c[0]}-{c[1]}-p{c[2]}-r{c[3]}")
+def test_random_two_stage_plans_match_oracle(hss, case):
+    kind, n, p, r, eps1, eps2, bits, payload, seed = case
+    _say(f"[random-staged] {case}")
+    keys = _keys(kind, n, seed, bits)
+    vals = np.arange(n, dtype=np.uint64) if payload else None
+    ref = oracle.hss_two_stage(keys, p, r, eps1, eps2, seed, vals=vals)
+    with hss.StagedPlan(n, p, r, eps1, eps2, key_bytes=keys.itemsize, payload=payload) as plan:
+        if ref.status != 0:
+            # a group with fewer keys than processors: the library reports it
+            with pytest.raises(hss.HssError):
+                plan.partition(_dev(keys), seed, None if vals is None else _dev(vals))
+            return
+        ko, vo, off, grp = plan.partition(_dev(keys), seed, None if vals is None else _dev(vals))
+        assert np.array_equal(_host(grp, np.uint64), ref.groups)
+        assert np.array_equal(_host(off, np.uint64), ref.offsets)
+        assert np.array_equal(_host(ko, keys.dtype), ref.keys)
+        if payload:
+            assert np.array_equal(_host(vo, np.uint64), ref.vals)
