@@ -456,3 +456,42 @@ def test_autotuned_plan_and_batch(hss):
             assert np.array_equal(_host(off[i], np.uint64), r.offsets), i
             assert np.array_equal(_host(ko[i], np.uint64), r.keys), i
         assert bp.knobs(8)["tuned"] == 1
+
+
+def _random_plan_shapes(seed, count):
+    rng = np.random.default_rng(seed)
+    kinds = ["uniform64", "SKEW1", "SKEW2", "SKEW3", "GAUSS", "zipf_morton", "ALLZEROS"]
+    out = []
+    for i in range(count):
+        n = int(2 ** rng.uniform(8, 21))
+        p = int(min(n, 2 ** rng.uniform(0, 12.5)))
+        out.append((kinds[int(rng.integers(0, len(kinds)))], n, max(p, 1),
+                    float(rng.choice([0.005, 0.02, 0.1, 0.5])), 32 if rng.random() < 0.3 else 64,
+                    bool(rng.random() < 0.5), 300 + i))
+    return out
+
+
+@pytest.mark.parametrize("case", _random_plan_shapes(11, 32), ids=lambda c: f"{c[0]}-{c[1]}-p{c[2]}-b{c[4]}")
+def test_random_plans_match_oracle(hss, case):
+    """Random shapes across the local sort's paths (tiny and large segments,
+    packed first-level jobs, narrow digits, duplicates): partition and sort
+    equal the oracle bit for bit."""
+    kind, n, p, eps, bits, payload, seed = case
+    _say(f"[random-plan] {case}")
+    keys = _keys(kind, n, seed, bits)
+    vals = np.arange(n, dtype=np.uint64) if payload else None
+    kd = _dev(keys)
+    vd = None if vals is None else _dev(vals)
+    ref = oracle.hss(keys, p, eps, seed, vals=vals, mode="partition", trace_level=0)
+    srt = oracle.hss(keys, p, eps, seed, vals=vals, mode="sort", trace_level=0)
+    assert ref.status == 0 and srt.status == 0
+    with hss.Plan(n, p, eps, key_bytes=keys.itemsize, payload=payload) as plan:
+        ko, vo, off = plan.partition(kd, seed, vd)
+        assert np.array_equal(_host(off, np.uint64), ref.offsets)
+        assert np.array_equal(_host(ko, keys.dtype), ref.keys)
+        if payload:
+            assert np.array_equal(_host(vo, np.uint64), ref.vals)
+        ks, vs, _ = plan.sort(kd, seed, vd)
+        assert np.array_equal(_host(ks, keys.dtype), srt.keys)
+        if payload:
+            assert np.array_equal(_host(vs, np.uint64), srt.vals)
