@@ -77,7 +77,10 @@ constexpr uint32_t kMaxRateRounds = 64;  // rounds kept in the rate table
 // sort rather than ranked pairwise inside their interval.
 constexpr uint64_t kBigRound = 16384;
 constexpr uint64_t kPresampleMin = 1ull << 20;   // keys of a plan whose first draws go ahead
-constexpr uint64_t kPresampleCapMax = 1ull << 24; // longest list of draws taken ahead
+// Draws are taken ahead only for sparse samples (at most this many expected
+// per round): the list costs a contended append per wave, and dense samples
+// (one-round HSS, full samples) are better drawn by the per-slice sampler.
+constexpr uint64_t kPresampleExpectMax = 1ull << 16;
 // First round whose ranks are searched inside the probes' interval slices
 // (round 1 has one interval, the whole input: searched by segment chunks).
 constexpr uint32_t kPairRankFrom = 2;
@@ -697,6 +700,7 @@ hss_status engine_init(Engine& E) {
     r.pair_rank_from = E.knobs.pair_rank_from;
     r.sample_grid = E.knobs.sample_workgroups;
     r.pair_grid = E.knobs.pair_rank_workgroups;
+    r.dense_rank = 0;
     r.seg_off = E.seg_off;
     r.seg_inst = E.seg_inst;
     r.row_inst = E.row_inst;
@@ -726,7 +730,7 @@ hss_status engine_init(Engine& E) {
     // a list of twice the expected draws plus 4096 holds all of them except
     // with negligible probability (binomial counts); a longer one is not
     // used (the sampler draws itself)
-    if (E.pre_rounds && expect * 2 + 4096 > (double)kPresampleCapMax) E.pre_rounds = 0;
+    if (E.pre_rounds && expect > (double)kPresampleExpectMax) E.pre_rounds = 0;
     if (E.pre_rounds) {
         E.pre_cap = (uint32_t)(expect * 2 + 4096);
         HIP_TRY(dev_alloc(E.mem, (void**)&E.pre_mem,
@@ -920,7 +924,11 @@ hss_status big_first_round(Engine& E, hipStream_t s) {
     hs.vals_out = r.ps_tag;
     HIP_TRY(hybrid_sort(hs, s, E.hh));
     HIP_TRY(launch_probe_finish(r, s));
-    HIP_TRY(launch_round_tail(r, 1, s, true, &E.prof));
+    // more probes than fences in a segment: rank against the keys in LDS
+    r.dense_rank = m * kFenceStride >= E.max_seg ? 1u : 0u;
+    const hipError_t et = launch_round_tail(r, 1, s, true, &E.prof);
+    r.dense_rank = 0;
+    HIP_TRY(et);
     return HSS_OK;
 }
 

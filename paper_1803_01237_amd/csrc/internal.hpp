@@ -457,6 +457,8 @@ struct RoundArgs {
                                    // the probe's interval slice (earlier: by segment chunks)
     uint32_t sample_grid;          // workgroups of the sampler
     uint32_t pair_grid;            // workgroups of the per-pair rank search
+    uint32_t dense_rank;           // 1: round 1 ranks its probes against the chunk's keys
+                                   // staged in LDS (probes denser than the fences)
     // one instance: the draws of rounds 1..kPreRounds taken ahead of the
     // rounds: pre_list[j-1] holds, in any order, every tag whose Philox word
     // of round j is below the round's threshold (pre_cnt[j-1] of them; more

@@ -40,6 +40,8 @@ namespace {
 constexpr int kT = 256;
 constexpr int kScanT = 1024;            // threads of the one-workgroup scans
 constexpr uint32_t kRankFences = kRankChunk / kFenceStride;
+constexpr uint32_t kDenseTile = 4096;   // keys of a chunk staged at once by rank_dense_kernel
+constexpr uint32_t kSampleStage = 256;  // probes a sampler wave stages in LDS (4 per lane)
 constexpr uint32_t kReduceRows = 16;    // segments summed per reduction workgroup
 constexpr uint32_t kOrderLanes = 64;    // probes per ordering workgroup
 constexpr uint32_t kOrderThreads = 512; // their comparisons split over 8 waves
@@ -237,6 +239,54 @@ __global__ __launch_bounds__(kT) void compact_kernel(RoundArgs a) {
     }
 }
 
+// ivl_pcnt[k] += c for every lane of the wave (c = 0: nothing), with one
+// atomic per distinct interval in the wave instead of one per probe (the
+// probes of a round often share an interval, e.g. round 1's single one).
+__device__ __forceinline__ void add_interval_counts(uint32_t* ivl_pcnt, uint32_t k, uint32_t c) {
+    uint64_t rem = __ballot(c != 0);
+    while (rem) {   // uniform
+        const int leader = __ffsll((long long)rem) - 1;
+        const uint32_t kk = (uint32_t)__shfl((int)k, leader);
+        const uint64_t same = __ballot(c != 0 && k == kk);
+        const uint32_t tot = wave_sum<uint32_t>((same & (1ull << lane_id())) ? c : 0u);
+        if ((int)lane_id() == leader) atomicAdd(&ivl_pcnt[kk], tot);
+        rem &= ~same;
+    }
+}
+
+// Moves a wave's n staged probes to the probe arrays: one reservation, then
+// the per-interval counts, one atomic per run of equal intervals in each
+// 64-entry chunk (the wave's blocks walk the slices in interval order).
+__device__ void flush_stage(const RoundArgs& a, const uint64_t* st_key, const uint32_t* st_tag,
+                            const uint32_t* st_ivl, uint32_t n) {
+    const uint32_t lane = lane_id();
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&a.ctr->m, (unsigned long long)n);
+    base = shfl_u64(base, 0);
+    if (base + n > a.cap && lane == 0) atomicOr(&a.ctr->overflow, 1u);
+    for (uint32_t c0 = 0; c0 < n; c0 += kWave) {
+        const uint32_t i = c0 + lane;
+        const bool valid = i < n;
+        uint32_t k = valid ? st_ivl[i] : 0u;
+        if (valid && base + i < a.cap) {
+            a.pr_key[base + i] = st_key[i];
+            a.pr_tag[base + i] = st_tag[i];
+            a.pr_ivl[base + i] = k;
+        }
+        // run starts: the chunk's first entry and every change of interval
+        const bool start = valid && (lane == 0 || st_ivl[i - 1] != k);
+        const uint64_t starts = __ballot(start);
+        if (start) {
+            const uint64_t later = lane + 1 < kWave ? starts >> (lane + 1) : 0ull;
+            const uint32_t end = later ? lane + 1 + (uint32_t)(__ffsll((long long)later) - 1)
+                                       : min((uint32_t)kWave, n - c0);
+            // probes past the capacity count too: an overrun halts the rest
+            // of the call, which the host repeats with larger buffers
+            atomicAdd(&a.ivl_pcnt[k], end - lane);
+        }
+    }
+}
+
 // Sampler of a round whose draws were taken ahead (one instance): thread per
 // listed tag g; g is a probe when it lies in the slice of an interval in its
 // segment.  The intervals are disjoint and in key order, so their slices in
@@ -248,40 +298,60 @@ __device__ void sample_from_list(const RoundArgs& a, const uint32_t* list, uint3
     if (n_ivl == 0) return;
     const InstDesc D = a.inst[0];
     const K* B = (const K*)a.B;
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
-        const uint64_t g = list[t];
-        if (g >= D.n) continue;
-        uint32_t lo = 0, hi = D.p;   // segment: the last one starting at or before g
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (a.seg_off[D.seg0 + mid] - D.pos0 <= g) lo = mid; else hi = mid;
+    const uint32_t lane = lane_id();
+    const uint32_t stride = gridDim.x * blockDim.x;
+    // whole waves step together (the probe slots are taken once per wave)
+    for (uint32_t tb = blockIdx.x * blockDim.x + (threadIdx.x - lane); tb < cnt; tb += stride) {
+        const uint32_t t = tb + lane;
+        const uint64_t g = t < cnt ? list[t] : D.n;
+        bool take = g < D.n;
+        uint32_t kl = 0;
+        if (take) {
+            uint32_t lo = 0, hi = D.p;   // segment: the last one starting at or before g
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (a.seg_off[D.seg0 + mid] - D.pos0 <= g) lo = mid; else hi = mid;
+            }
+            const uint32_t s = lo;
+            auto bounds = [&](uint32_t k, uint64_t* ga, uint64_t* gb) {
+                const uint32_t row = a.ivl_row[k];
+                slice_bounds(a, D, row - D.row0, s, a.lrank[row] == kNone, a.urank[row] == kNone, ga, gb);
+            };
+            uint32_t kh = n_ivl;   // the last interval whose slice starts at or before g
+            uint64_t ga, gb;
+            bounds(0, &ga, &gb);
+            if (ga > g) {
+                take = false;
+            } else {
+                while (kh - kl > 1) {
+                    const uint32_t mid = (kl + kh) >> 1;
+                    uint64_t ma, mb;
+                    bounds(mid, &ma, &mb);
+                    if (ma <= g) kl = mid; else kh = mid;
+                }
+                bounds(kl, &ga, &gb);
+                take = g >= ga && g < gb;
+            }
         }
-        const uint32_t s = lo;
-        auto bounds = [&](uint32_t k, uint64_t* ga, uint64_t* gb) {
-            const uint32_t row = a.ivl_row[k];
-            slice_bounds(a, D, row - D.row0, s, a.lrank[row] == kNone, a.urank[row] == kNone, ga, gb);
-        };
-        uint32_t kl = 0, kh = n_ivl;   // the last interval whose slice starts at or before g
-        uint64_t ga, gb;
-        bounds(0, &ga, &gb);
-        if (ga > g) continue;
-        while (kh - kl > 1) {
-            const uint32_t mid = (kl + kh) >> 1;
-            uint64_t ma, mb;
-            bounds(mid, &ma, &mb);
-            if (ma <= g) kl = mid; else kh = mid;
+        const uint64_t mask = __ballot(take);
+        if (!mask) continue;   // uniform
+        unsigned long long base = 0;
+        const int leader = __ffsll((long long)mask) - 1;
+        if ((int)lane == leader) base = atomicAdd(&a.ctr->m, (unsigned long long)__popcll(mask));
+        base = shfl_u64(base, leader);
+        bool stored = false;
+        if (take) {
+            const uint64_t o = base + __popcll(mask & lanes_below_mask());
+            if (o < a.cap) {
+                a.pr_key[o] = (uint64_t)B[D.pos0 + g];
+                a.pr_tag[o] = g;
+                a.pr_ivl[o] = kl;
+                stored = true;
+            } else {
+                atomicOr(&a.ctr->overflow, 1u);
+            }
         }
-        bounds(kl, &ga, &gb);
-        if (g < ga || g >= gb) continue;
-        const uint64_t o = atomicAdd(&a.ctr->m, 1ull);
-        if (o < a.cap) {
-            a.pr_key[o] = (uint64_t)B[D.pos0 + g];
-            a.pr_tag[o] = g;
-            a.pr_ivl[o] = kl;
-            atomicAdd(&a.ivl_pcnt[kl], 1u);
-        } else {
-            atomicOr(&a.ctr->overflow, 1u);
-        }
+        add_interval_counts(a.ivl_pcnt, kl, stored ? 1u : 0u);
     }
 }
 
@@ -337,6 +407,17 @@ __global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint32_t round)
         take_all = a.all[round - 1] != 0;
     }
 
+    // per-wave staging of the emitted probes: one slot reservation per
+    // kSampleStage probes instead of one per step (a single counter takes
+    // every reservation of the round)
+    __shared__ uint64_t stage_key[kT / kWave][kSampleStage];
+    __shared__ uint32_t stage_tag[kT / kWave][kSampleStage];
+    __shared__ uint32_t stage_ivl[kT / kWave][kSampleStage];
+    uint64_t* st_key = stage_key[threadIdx.x / kWave];
+    uint32_t* st_tag = stage_tag[threadIdx.x / kWave];
+    uint32_t* st_ivl = stage_ivl[threadIdx.x / kWave];
+    uint32_t fill = 0;
+
     uint4 e = jq + lane < nsl ? sl[jq + lane] : make_uint4(kNoBlock, 0, 0, 0);
     uint32_t nxt = jq + kWave < nsl ? sl[jq + kWave].x : kNoBlock;
     for (uint32_t b0 = b_lo; b0 < b_hi; b0 += kWave) {
@@ -391,32 +472,33 @@ __global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint32_t round)
             }
         }
         if (__ballot(hits != 0)) {
+            // the probes go to the wave's staging area in LDS (at most 4 per
+            // lane, so one step always fits once the area is flushed)
             const uint32_t c = __popc(hits);
             const uint32_t inc = wave_inclusive_scan<uint32_t>(c);
-            unsigned long long base = 0;
-            if (lane == kWave - 1) base = atomicAdd(&a.ctr->m, (unsigned long long)inc);
-            base = shfl_u64(base, kWave - 1);
-            uint64_t o = base + inc - c;
+            const uint32_t total = (uint32_t)__shfl((int)inc, kWave - 1);
+            if (fill + total > kSampleStage) {
+                flush_stage(a, st_key, st_tag, st_ivl, fill);
+                fill = 0;
+            }
+            uint32_t o = fill + inc - c;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if (hits & (1u << q)) {
-                    const uint64_t g = blk * 4 + q;
-                    if (o < a.cap) {
-                        a.pr_key[o] = (uint64_t)B[pos0 + g];
-                        a.pr_tag[o] = g;
-                        a.pr_ivl[o] = k;
-                        atomicAdd(&a.ivl_pcnt[k], 1u);
-                    } else {
-                        atomicOr(&a.ctr->overflow, 1u);
-                    }
+                    const uint32_t g = (uint32_t)(blk * 4 + q);
+                    st_key[o] = (uint64_t)B[pos0 + g];
+                    st_tag[o] = g;
+                    st_ivl[o] = k;
                     ++o;
                 }
             }
+            fill += total;
         }
         e = en;
         nxt = nxtn;
         jq = jn;
     }
+    if (fill) flush_stage(a, st_key, st_tag, st_ivl, fill);
 }
 
 // Fixed probe budget (one instance): the round's acceptance threshold from
@@ -707,6 +789,107 @@ __global__ __launch_bounds__(256) void rank_kernel(RoundArgs a) {
             }
         }
         out[e] = (uint32_t)cnt;
+    }
+}
+
+// First probe of [lo, hi) (sorted by (key, tag)) after the element (bx, bg),
+// hi when none is; all 256 threads of the workgroup call it.  Two parallel
+// steps: 256 evenly spaced probes bracket the answer, then every probe of
+// the bracket is tested (the predicate is monotone over the sorted probes).
+__device__ uint32_t first_after(const uint64_t* pk, const uint64_t* pt, uint32_t lo, uint32_t hi,
+                                uint64_t bx, uint64_t bg, uint32_t* sh_cnt, uint32_t* sh_e) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *sh_cnt = 0;
+        *sh_e = hi;
+    }
+    __syncthreads();
+    const uint32_t n = hi - lo;
+    const uint32_t step = (n + 255) / 256;
+    {
+        const uint64_t j = lo + (uint64_t)threadIdx.x * step;
+        if (j < hi && !after(pk[j], pt[j], bx, bg)) atomicAdd(sh_cnt, 1u);
+    }
+    __syncthreads();
+    const uint32_t cn = *sh_cnt;
+    const uint32_t a0 = cn == 0 ? lo : lo + (cn - 1) * step + 1;
+    const uint32_t a1 = (uint32_t)min((uint64_t)lo + (uint64_t)cn * step + 1, (uint64_t)hi);
+    for (uint32_t e = a0 + threadIdx.x; e < a1; e += blockDim.x)
+        if (after(pk[e], pt[e], bx, bg) && (e == lo || !after(pk[e - 1], pt[e - 1], bx, bg))) *sh_e = e;
+    __syncthreads();
+    return *sh_e;
+}
+
+// Round 1 with probes denser than the fences (one-round HSS, full samples):
+// workgroup per (segment s, chunk of kRankChunk keys) as rank_kernel, but the
+// chunk's keys are staged in LDS tile by tile and every probe whose count
+// falls in a tile is placed by binary search in the tile -- no read of B per
+// (probe, segment).
+template <typename K>
+__global__ __launch_bounds__(256) void rank_dense_kernel(RoundArgs a) {
+    __shared__ K T[kDenseTile];
+    __shared__ uint32_t sh_cnt, sh_e;
+    const uint32_t c = blockIdx.x;
+    if (c >= a.n_chunks || halted(a)) return;
+    const uint32_t s = a.chunk_seg[c];
+    const uint32_t I = a.seg_inst[s];
+    const uint32_t m = a.inst_pm[I];
+    if (m == 0) return;
+    const uint32_t plo = a.inst_plo[I];
+    const InstDesc& D = a.inst[I];
+    const uint32_t s_local = s - D.seg0;
+    const uint64_t sb = a.seg_off[s];
+    const uint64_t ns = a.seg_off[s + 1] - sb;
+    const uint64_t g_sb = sb - D.pos0;
+    const uint64_t lo_pos = a.chunk_lo[c];
+    const uint64_t chunk_end = min(lo_pos + kRankChunk, ns);
+    const K* B = (const K*)a.B + sb;
+    const uint64_t* pk = a.ps_key + plo;
+    const uint64_t* pt = a.ps_tag + plo;
+    uint32_t* out = a.cmat + a.cm_off[I] + (uint64_t)s_local * m;
+    // probes with c_s(e) >= x: from the first probe after element x - 1
+    uint32_t ea = lo_pos == 0 ? 0 : first_after(pk, pt, 0, m, (uint64_t)B[lo_pos - 1], g_sb + lo_pos - 1,
+                                                &sh_cnt, &sh_e);
+    for (uint64_t ta = lo_pos; ta < chunk_end; ta += kDenseTile) {
+        const uint64_t tb = min(ta + (uint64_t)kDenseTile, chunk_end);
+        // [ea, eb): the probes with c_s(e) in [ta, tb) (the segment's last
+        // tile also takes the probes after all its keys)
+        const uint32_t eb = tb == ns ? m
+                                     : first_after(pk, pt, ea, m, (uint64_t)B[tb - 1], g_sb + tb - 1,
+                                                   &sh_cnt, &sh_e);
+        if (ea < eb) {   // uniform over the workgroup
+            __syncthreads();
+            const uint32_t nt = (uint32_t)(tb - ta);
+            for (uint32_t i = threadIdx.x; i < nt; i += blockDim.x) T[i] = B[ta + i];
+            __syncthreads();
+            for (uint32_t e = ea + threadIdx.x; e < eb; e += blockDim.x) {
+                // keys below the probe's key: its count unless the tile holds
+                // its key (then the tie rule of the order (key, tag) decides)
+                const K key = (K)pk[e];
+                uint32_t lo = 0, hi = nt;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (T[mid] < key) lo = mid + 1; else hi = mid;
+                }
+                uint64_t cnt = ta + lo;
+                if (lo < nt && T[lo] == key) {
+                    const uint32_t t = a.ps_seg[plo + e];
+                    if (t == s) {
+                        cnt = pt[e] - g_sb;
+                    } else if (s < t) {
+                        // equal keys of earlier segments precede the probe
+                        uint32_t l2 = lo, h2 = nt;
+                        while (l2 < h2) {
+                            const uint32_t mid = (l2 + h2) >> 1;
+                            if (T[mid] <= key) l2 = mid + 1; else h2 = mid;
+                        }
+                        cnt = ta + l2;
+                    }
+                }
+                out[e] = (uint32_t)cnt;
+            }
+        }
+        ea = eb;
     }
 }
 
@@ -1059,7 +1242,10 @@ hipError_t launch_round_tail(const RoundArgs& a, uint32_t j, hipStream_t s, bool
         const uint64_t tiles_bound = (a.cap + kOrderLanes - 1) / kOrderLanes + interval_bound(a);
         hipLaunchKernelGGL(order_kernel, dim3((unsigned)tiles_bound), dim3(kOrderThreads), 0, s, a);
     }
-    if (j >= a.pair_rank_from) {
+    if (j == 1 && a.dense_rank && a.n_chunks > 0) {
+        if (a.key_bytes == 4) hipLaunchKernelGGL(rank_dense_kernel<uint32_t>, dim3(a.n_chunks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(rank_dense_kernel<uint64_t>, dim3(a.n_chunks), dim3(256), 0, s, a);
+    } else if (j >= a.pair_rank_from) {
         // every probe searched inside its own interval slice
         if (a.key_bytes == 4) hipLaunchKernelGGL(rank_pairs_kernel<uint32_t>, dim3(a.pair_grid), dim3(256), 0, s, a);
         else hipLaunchKernelGGL(rank_pairs_kernel<uint64_t>, dim3(a.pair_grid), dim3(256), 0, s, a);
