@@ -176,3 +176,69 @@ def test_partition_and_sort_zipf_morton_payload_2p28_p4096(hss):
         assert np.array_equal(keys[sv.astype(np.int64)], srt)
         assert np.all((srt[1:] > srt[:-1]) | ((srt[1:] == srt[:-1]) & (sv[1:] > sv[:-1])))
         assert np.array_equal(_host(off2), offs)
+
+
+def _device_digest(x, chunk=1 << 28):
+    """Order-independent digest of int32 keys on the device (wrapping int64
+    sums of the keys, of a splitmix64 hash of each and of its square)."""
+    mask = (1 << 32) - 1
+    c1 = 0x9E3779B97F4A7C15 - (1 << 64)
+    c2 = 0xBF58476D1CE4E5B9 - (1 << 64)
+    c3 = 0x94D049BB133111EB - (1 << 64)
+
+    def lsr(v, k):   # logical shift right of int64
+        return (v >> k) & ((1 << (64 - k)) - 1)
+
+    s0 = s1 = s2 = torch.zeros((), dtype=torch.int64, device=x.device)
+    for a in range(0, x.numel(), chunk):
+        v = x[a:a + chunk].to(torch.int64) & mask
+        z = v + c1
+        z = (z ^ lsr(z, 30)) * c2
+        z = (z ^ lsr(z, 27)) * c3
+        z = z ^ lsr(z, 31)
+        s0 = s0 + v.sum()
+        s1 = s1 + z.sum()
+        s2 = s2 + (z * z).sum()
+    return int(s0), int(s1), int(s2), x.numel()
+
+
+def test_partition_and_sort_at_the_largest_size_u32(hss):
+    """N = 2^32 - 1 u32 keys, the largest plan the library accepts (tags,
+    counts and piece offsets are 32-bit): the sort is in unsigned order and a
+    permutation of the input, every splitter lies in its target range, and
+    every bucket of the partition holds exactly the keys of its rank range
+    (the same keys as the sort's bucket, each between its first and last)."""
+    n, p, eps, hseed = (1 << 32) - 1, 1024, 0.02, 5
+    flip = -(1 << 31)   # xor with the sign bit: signed order of the result = unsigned order
+    _say(f"[fullsize] largest: u32 n={n} p={p} eps={eps}: generating on the device")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(77)
+    kd = torch.randint(-(1 << 31), 1 << 31, (n,), dtype=torch.int32, generator=g, device="cuda")
+    digest_in = _device_digest(kd)
+    with hss.Plan(n, p, eps, key_bytes=4) as plan:
+        tol = plan.constants(1)[0]
+        _say("[fullsize] largest: hss_sort")
+        ks, _, off_s = plan.sort(kd, hseed)
+        offs = _host(off_s).astype(np.int64)
+        _check_offsets(offs.astype(np.uint64), n, p, tol)
+        assert _device_digest(ks) == digest_in
+        ks ^= flip
+        for a in range(0, n - 1, 1 << 28):
+            b = min(a + (1 << 28) + 1, n)
+            assert bool((ks[a + 1:b] >= ks[a:b - 1]).all()), a
+        _say("[fullsize] largest: hss_partition")
+        ko, _, off_p = plan.partition(kd, hseed)
+        assert np.array_equal(_host(off_p).astype(np.int64), offs)
+        ko ^= flip
+        for b0 in range(0, p, 64):
+            b1 = min(b0 + 64, p)
+            a0, a1 = int(offs[b0]), int(offs[b1])
+            part = ko[a0:a1]
+            lens = torch.tensor(np.diff(offs[b0:b1 + 1]), device="cuda")
+            first = torch.tensor(offs[b0:b1], device="cuda")
+            last = torch.tensor(offs[b0 + 1:b1 + 1] - 1, device="cuda")
+            lo = torch.repeat_interleave(ks[first], lens)
+            hi = torch.repeat_interleave(ks[last], lens)
+            assert bool(((part >= lo) & (part <= hi)).all()), b0
+            assert torch.equal(torch.sort(part).values, ks[a0:a1]), b0
+            del lo, hi
