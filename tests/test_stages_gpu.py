@@ -15,7 +15,6 @@ import pytest
 
 import oracle
 import synth
-from tests import refcheck as R
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
