@@ -315,9 +315,15 @@ struct hss_plan_s {
 struct hss_batch_s {
     Engine* eng[2] = {nullptr, nullptr};   // u32 instances, u64 instances
     std::vector<std::pair<int, uint32_t>> where;   // instance -> (engine, index in it)
+    // with both key widths present, the u64 engine runs on a stream of its own
+    // (from a second host thread) beside the u32 engine on the caller's stream
+    hipStream_t side = nullptr;
+    hipEvent_t ev_in = nullptr;
     ~hss_batch_s() {
         delete eng[0];
         delete eng[1];
+        if (side) (void)hipStreamDestroy(side);
+        if (ev_in) (void)hipEventDestroy(ev_in);
     }
 };
 
@@ -1775,9 +1781,9 @@ hss_status hss_batch_partition(hss_batch_t Bt, const hss_instance_io* io, void* 
             if (st != HSS_OK) return fail(st, "instance " + std::to_string(i) + ": " + g_last_error);
         }
         hipStream_t s = (hipStream_t)stream;
-        for (int g = 0; g < 2; ++g) {
+        // one engine's whole call on stream `es`; returns after its work has completed
+        auto run_engine = [&](int g, hipStream_t es) -> hss_status {
             Engine* E = Bt->eng[g];
-            if (!E) continue;
             HIP_TRY(hipSetDevice(E->device));
             for (uint32_t i = 0; i < Bt->where.size(); ++i) {
                 if (Bt->where[i].first != g) continue;
@@ -1787,15 +1793,47 @@ hss_status hss_batch_partition(hss_batch_t Bt, const hss_instance_io* io, void* 
             }
             auto call = [&]() -> hss_status {
                 HIP_TRY(hipMemcpyAsync(E->run_d, E->h_run, E->ih.size() * sizeof(InstRun),
-                                       hipMemcpyHostToDevice, s));
-                HIP_TRY(launch_counters_reset(E->ra.ctr, s));
-                const hss_status r = engine_run(*E, nullptr, nullptr, nullptr, nullptr, s, false);
+                                       hipMemcpyHostToDevice, es));
+                HIP_TRY(launch_counters_reset(E->ra.ctr, es));
+                const hss_status r = engine_run(*E, nullptr, nullptr, nullptr, nullptr, es, false);
                 if (r != HSS_OK) return r;
-                return finish(*E, s);
+                return finish(*E, es);
             };
-            const hss_status st = (E->tune.autotune && !E->knobs.tuned) ? autotune(*E, s, call) : call();
-            if (st != HSS_OK) return st;
+            return (E->tune.autotune && !E->knobs.tuned) ? autotune(*E, es, call) : call();
+        };
+        if (!(Bt->eng[0] && Bt->eng[1])) {
+            const int g = Bt->eng[0] ? 0 : 1;
+            return run_engine(g, s);
         }
+        // both widths: the u64 engine on the side stream, after the caller's
+        // work already queued on its stream (the inputs)
+        Engine* E1 = Bt->eng[1];
+        HIP_TRY(hipSetDevice(E1->device));
+        if (!Bt->side) {
+            HIP_TRY(hipStreamCreateWithFlags(&Bt->side, hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&Bt->ev_in, hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventRecord(Bt->ev_in, s));
+        HIP_TRY(hipStreamWaitEvent(Bt->side, Bt->ev_in, 0));
+        hss_status st1 = HSS_OK;
+        std::string msg1;
+        std::thread side([&]() {
+            try {
+                st1 = run_engine(1, Bt->side);
+            } catch (...) {
+                st1 = fail(HSS_ERR_DEVICE, "unexpected exception");
+            }
+            if (st1 != HSS_OK) msg1 = g_last_error;
+        });
+        hss_status st0;
+        try {
+            st0 = run_engine(0, s);
+        } catch (...) {
+            st0 = fail(HSS_ERR_DEVICE, "unexpected exception");
+        }
+        side.join();
+        if (st0 != HSS_OK) return st0;
+        if (st1 != HSS_OK) return fail(st1, msg1);
         return HSS_OK;
     } catch (...) {
         return fail(HSS_ERR_DEVICE, "unexpected exception");
