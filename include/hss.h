@@ -250,7 +250,9 @@ typedef struct {
  * one workspace per key type present, sized for the sum of the instances.
  * The sum of N per key type must stay below 2^32.  tuning: NULL, or knobs
  * as for hss_plan except lsd_only and trace_level, which must be zero
- * (HSS_ERR_UNSUPPORTED otherwise).  Errors name the failing instance.
+ * (HSS_ERR_UNSUPPORTED otherwise); a probe budget (probes_per_round = c)
+ * applies to every instance, each with its own rate c q / |gamma| from its
+ * own domain.  Errors name the failing instance.
  */
 hss_status hss_batch_plan(hss_batch_t* out, const hss_instance_shape* shapes, uint32_t count,
                           int with_payload, const hss_tuning* tuning);
@@ -386,9 +388,10 @@ typedef struct hss_staged_s* hss_staged_t;
 
 /*
  * hss_staged_plan -- validate and prepare.  groups = r must divide p;
- * n, p, eps1, kt and tuning as for hss_plan (tuning: trace_level, lsd_only
- * and probes_per_round must be zero, HSS_ERR_UNSUPPORTED otherwise; the
- * autotuner, when asked for, tunes stage 1); 0 < eps2 < 1.  The plan holds
+ * n, p, eps1, kt and tuning as for hss_plan (tuning: trace_level and
+ * lsd_only must be zero, HSS_ERR_UNSUPPORTED otherwise; a probe budget
+ * applies to both stages; the autotuner, when asked for, tunes stage 1);
+ * 0 < eps2 < 1.  The plan holds
  * the workspace of stage 1, a staging buffer of N keys (and payload words),
  * and a cache of the device blocks of stage 2, whose layout depends on the
  * group sizes of each call.

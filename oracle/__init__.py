@@ -248,7 +248,7 @@ def stage_seed(seed: int, g: int) -> int:
 
 
 def hss_two_stage(keys: np.ndarray, p: int, r: int, eps1: float, eps2: float, seed: int,
-                  vals: np.ndarray | None = None) -> TwoStage:
+                  vals: np.ndarray | None = None, probes_per_round: int = 0) -> TwoStage:
     """Two-stage HSS (section 5.3), composed from single-stage runs.
 
     Stage 1: the p segments are split into r buckets, one per group of p/r
@@ -258,12 +258,15 @@ def hss_two_stage(keys: np.ndarray, p: int, r: int, eps1: float, eps2: float, se
     the group holds positions floor(s N_g r/p) ..).  Stage 2: every group runs
     HSS on its own keys with p/r segments and buckets (tolerance eps2).  Final
     bucket g p/r + i is bucket i of group g.  Requires r | p and N_g >= p/r.
+    probes_per_round = c > 0: both stages draw c q probes per round in
+    expectation (q = r, then p/r).
     """
     keys = np.ascontiguousarray(keys)
     if r <= 0 or p % r != 0:
         return TwoStage(status=-1)
     pg = p // r
-    st1 = hss(keys, p, eps1, seed, vals=vals, mode="partition", trace_level=0, buckets=r)
+    st1 = hss(keys, p, eps1, seed, vals=vals, mode="partition", trace_level=0, buckets=r,
+              probes_per_round=probes_per_round)
     if st1.status != 0:
         return TwoStage(status=st1.status)
     ko = np.empty_like(keys)
@@ -277,7 +280,8 @@ def hss_two_stage(keys: np.ndarray, p: int, r: int, eps1: float, eps2: float, se
             return TwoStage(status=-1, stage1=st1, groups=chi1)
         kg = st1.keys[lo:hi]
         vg = None if vals is None else st1.vals[lo:hi]
-        st2 = hss(kg, pg, eps2, stage_seed(seed, g), vals=vg, mode="partition", trace_level=0)
+        st2 = hss(kg, pg, eps2, stage_seed(seed, g), vals=vg, mode="partition", trace_level=0,
+                  probes_per_round=probes_per_round)
         if st2.status != 0:
             return TwoStage(status=st2.status, stage1=st1, groups=chi1)
         ko[lo:hi] = st2.keys

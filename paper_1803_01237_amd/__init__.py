@@ -412,8 +412,8 @@ class StagedPlan:
     def __init__(self, n: int, p: int, groups: int, eps1: float, eps2: float, key_bytes: int = 8,
                  payload: bool = False, max_rounds: int = 0, k_override: int = 0,
                  force_full_sample: bool = False, plain_launches: bool = False,
-                 autotune: bool = False):
-        tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, 0, 0, 0,
+                 autotune: bool = False, probes_per_round: int = 0):
+        tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, 0, 0, probes_per_round,
                       1 if plain_launches else 0, 1 if autotune else 0)
         h = _vp()
         kt = HSS_U64 if key_bytes == 8 else HSS_U32
@@ -486,13 +486,13 @@ class BatchPlan:
     (keys, seed[, vals]) per instance, in the same order."""
 
     def __init__(self, shapes, payload: bool = False, max_rounds: int = 0, k_override: int = 0,
-                 force_full_sample: bool = False, autotune: bool = False):
+                 force_full_sample: bool = False, autotune: bool = False, probes_per_round: int = 0):
         self.shapes = [(int(n), int(p), float(e), int(kb)) for (n, p, e, kb) in shapes]
         arr = (_Shape * len(self.shapes))()
         for i, (n, p, e, kb) in enumerate(self.shapes):
             arr[i] = _Shape(n, p, HSS_U64 if kb == 8 else HSS_U32, e)
-        tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, 0, 0, 0, 0,
-                      1 if autotune else 0)
+        tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, 0, 0, probes_per_round,
+                      0, 1 if autotune else 0)
         h = _vp()
         _check(_lib.hss_batch_plan(C.byref(h), arr, len(self.shapes), 1 if payload else 0,
                                    C.byref(tun)), "hss_batch_plan")

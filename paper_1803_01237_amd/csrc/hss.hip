@@ -1705,8 +1705,6 @@ hss_status hss_batch_plan(hss_batch_t* out, const hss_instance_shape* shapes, ui
                 if (x) return fail(HSS_ERR_INVALID_ARG, "reserved tuning fields must be zero");
             if (tuning->lsd_only) return fail(HSS_ERR_UNSUPPORTED, "lsd_only is for single plans");
             if (tuning->trace_level) return fail(HSS_ERR_UNSUPPORTED, "traces are for single plans");
-            if (tuning->probes_per_round)
-                return fail(HSS_ERR_UNSUPPORTED, "a probe budget is for single plans");
         }
         hss_batch_s* Bt = new (std::nothrow) hss_batch_s();
         if (!Bt) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -2124,8 +2122,8 @@ hss_status hss_staged_plan(hss_staged_t* out, uint64_t n, uint32_t p, uint32_t g
         if (groups == 0 || p == 0 || p % groups != 0)
             return fail(HSS_ERR_INVALID_ARG, "need groups >= 1 dividing p");
         if (!(eps2 > 0.0 && eps2 < 1.0)) return fail(HSS_ERR_INVALID_ARG, "need 0 < eps2 < 1");
-        if (tuning && (tuning->trace_level || tuning->lsd_only || tuning->probes_per_round))
-            return fail(HSS_ERR_UNSUPPORTED, "traces, lsd_only and a probe budget are for single plans");
+        if (tuning && (tuning->trace_level || tuning->lsd_only))
+            return fail(HSS_ERR_UNSUPPORTED, "traces and lsd_only are for single plans");
         hss_status st = plan_args(n, p, groups, eps1, kt, tuning);
         if (st != HSS_OK) return st;
         std::unique_ptr<hss_staged_s> P(new (std::nothrow) hss_staged_s());

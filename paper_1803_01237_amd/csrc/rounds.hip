@@ -506,12 +506,23 @@ __global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint32_t round)
 // or every tag when q >= 1.
 __global__ void budget_rate_kernel(RoundArgs a, uint32_t round) {
     if (halted(a)) return;
-    const uint64_t dom = a.ctr->domain;
-    if (dom == 0) return;   // no interval left
-    const double q = ((double)a.budget * (double)a.inst[0].q) / (double)dom;
-    const bool all = q >= 1.0;
-    a.thresh[round - 1] = all ? 0xFFFFFFFFu : (uint32_t)floor(q * 4294967296.0);
-    a.all[round - 1] = all ? 1 : 0;
+    const uint32_t n_ivl = a.ctr->n_ivl;
+    // thread per instance: its intervals are a contiguous run of the list (the
+    // leaders are found in row order, and rows in instance order)
+    for (uint32_t I = blockIdx.x * blockDim.x + threadIdx.x; I < a.n_inst; I += gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = n_ivl;   // first interval of instance I
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (a.ivl_inst[mid] < I) lo = mid + 1; else hi = mid;
+        }
+        uint64_t dom = 0;
+        for (uint32_t k = lo; k < n_ivl && a.ivl_inst[k] == I; ++k) dom += a.ivl_dom[k];
+        if (dom == 0) continue;   // no interval left in this instance
+        const double q = ((double)a.budget * (double)a.inst[I].q) / (double)dom;
+        const bool all = q >= 1.0;
+        a.thresh[(uint64_t)I * a.J + round - 1] = all ? 0xFFFFFFFFu : (uint32_t)floor(q * 4294967296.0);
+        a.all[(uint64_t)I * a.J + round - 1] = all ? 1 : 0;
+    }
 }
 
 // One workgroup: where every interval's probes go in sorted order, how many
@@ -1222,7 +1233,7 @@ hipError_t launch_round_head(const RoundArgs& a, uint32_t j, hipStream_t s) {
     hipLaunchKernelGGL(slices_kernel, dim3(ivl_bound), dim3(kT), 0, s, a);
     hipLaunchKernelGGL(ivl_scan_kernel, dim3(1), dim3(kScanT), 0, s, a);
     hipLaunchKernelGGL(compact_kernel, dim3(ivl_bound), dim3(kT), 0, s, a);
-    if (a.budget) hipLaunchKernelGGL(budget_rate_kernel, dim3(1), dim3(1), 0, s, a, j);
+    if (a.budget) hipLaunchKernelGGL(budget_rate_kernel, dim3(grid_for(a.n_inst, kT, 64)), dim3(kT), 0, s, a, j);
     if (a.n_inst == 1) {
         if (a.key_bytes == 4) hipLaunchKernelGGL((sample_kernel<uint32_t, true>), dim3(a.sample_grid), dim3(kT), 0, s, a, j);
         else hipLaunchKernelGGL((sample_kernel<uint64_t, true>), dim3(a.sample_grid), dim3(kT), 0, s, a, j);

@@ -60,18 +60,19 @@ MIXED = [
 ]
 
 
-def _run_batch(hss, cases, payload, seeds):
+def _run_batch(hss, cases, payload, seeds, budget=0):
     shapes = [(n, p, eps, kb) for (n, p, eps, kb, _, _) in cases]
     host_keys = [_keys(kind, n, s, kb) for (n, p, eps, kb, kind, s) in cases]
     host_vals = ([(np.arange(n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)) ^ np.uint64(i)
                   for i, (n, *_r) in enumerate(cases)] if payload else None)
-    with hss.BatchPlan(shapes, payload=payload) as bp:
+    with hss.BatchPlan(shapes, payload=payload, probes_per_round=budget) as bp:
         ko, vo, off = bp.partition([_dev(k) for k in host_keys], seeds,
                                    [_dev(v) for v in host_vals] if payload else None)
         torch.cuda.synchronize()
         for i, (n, p, eps, kb, kind, s) in enumerate(cases):
             ref = oracle.hss(host_keys[i], p, eps, seeds[i],
-                             vals=host_vals[i] if payload else None, mode="partition")
+                             vals=host_vals[i] if payload else None, mode="partition",
+                             probes_per_round=budget)
             assert ref.status == 0
             dt = np.uint64 if kb == 8 else np.uint32
             assert np.array_equal(_host(off[i], np.uint64), ref.offsets), i
@@ -85,6 +86,15 @@ def test_batch_matches_oracle(hss, payload):
     _say(f"[batch] {len(MIXED)} mixed instances, payload={payload}")
     seeds = [1000 + i for i in range(len(MIXED))]
     _run_batch(hss, MIXED, payload, seeds)
+
+
+@pytest.mark.parametrize("budget", [1, 5])
+def test_batch_with_probe_budget_matches_oracle(hss, budget):
+    """A probe budget in a batch: every instance draws at its own rate
+    c q / |gamma| from its own domain, as its plain plan would."""
+    _say(f"[batch] {len(MIXED)} mixed instances, budget {budget} q probes per round")
+    seeds = [2000 + i for i in range(len(MIXED))]
+    _run_batch(hss, MIXED, budget == 5, seeds, budget=budget)
 
 
 def test_batch_reuse_with_new_seeds(hss):

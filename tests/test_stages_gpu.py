@@ -150,6 +150,19 @@ def test_two_stage_matches_oracle(hss, case):
         assert plan.workspace_bytes > 0
 
 
+def test_two_stage_with_probe_budget_matches_oracle(hss):
+    n, p, r, seed = 600_000, 128, 16, 21
+    keys = _keys("uniform64", n, 3, 64)
+    _say(f"[staged] budget 5: n={n} p={p} r={r}")
+    ref = oracle.hss_two_stage(keys, p, r, 0.02, 0.02, seed, probes_per_round=5)
+    assert ref.status == 0
+    with hss.StagedPlan(n, p, r, 0.02, 0.02, probes_per_round=5) as plan:
+        ko, _, off, grp = plan.partition(_dev(keys), seed)
+        assert np.array_equal(_host(grp, np.uint64), ref.groups)
+        assert np.array_equal(_host(off, np.uint64), ref.offsets)
+        assert np.array_equal(_host(ko, np.uint64), ref.keys)
+
+
 def test_two_stage_rejects_bad_groups(hss):
     with pytest.raises(hss.HssError):
         hss.StagedPlan(1000, 16, 3, 0.05, 0.05)
