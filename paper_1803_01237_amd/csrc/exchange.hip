@@ -97,13 +97,32 @@ __device__ __forceinline__ uint32_t last_le_u32(const uint32_t* v, uint32_t lo, 
     return lo;
 }
 
-template <typename K, bool kPayload>
+// The digit counts of a copy workgroup's outputs for the bucket sort (kCount).
+template <typename K, bool kCount>
+struct TileCount {
+    uint32_t* hist = nullptr;   // LDS, 256 words
+    K base = 0;
+    int shift = 0;
+    uint64_t am = ~0ull, om = 0;
+    __device__ __forceinline__ void add(K k) {
+        if constexpr (kCount) {
+            const uint64_t x = (uint64_t)(K)(k - base);
+            atomicAdd(&hist[(uint32_t)(x >> shift) & 0xFFu], 1u);
+            am &= x;
+            om |= x;
+        }
+    }
+};
+
+template <typename K, bool kPayload, bool kCount>
 __global__ __launch_bounds__(kT) void exchange_copy_kernel(ExchangeArgs a, uint32_t window) {
     // window entries: piece start inside the bucket, source position of the piece
     extern __shared__ uint64_t smem[];
     uint64_t* w_src = smem;
     uint32_t* w_off = (uint32_t*)(smem + window);
     __shared__ uint32_t sh_first, sh_count;
+    __shared__ uint32_t hist[kCount ? 256 : 1];
+    __shared__ uint64_t red[kCount ? kT / kWave : 1][2];
     const uint32_t t = blockIdx.x;
     if (t >= a.chunk0[a.n_rows]) return;
     const uint32_t u = last_le_u32(a.chunk0, 0, a.n_rows, t);
@@ -139,27 +158,64 @@ __global__ __launch_bounds__(kT) void exchange_copy_kernel(ExchangeArgs a, uint3
     // a consistent state keeps every source inside its segment; the clamp only
     // keeps an inconsistent one (reported through err) inside the instance
     const uint64_t src_max = D.pos0 + D.n - 1;
+    TileCount<K, kCount> tc;
+    if constexpr (kCount) {
+        tc.hist = hist;
+        tc.base = (K)a.sort_base[b];
+        tc.shift = a.sort_shift[b];
+        hist[threadIdx.x] = 0;   // kT == 256
+    }
     if (cnt > window) {
         // many empty pieces in the window: search the bucket's row directly
+        if constexpr (kCount) __syncthreads();
         for (uint32_t r = (uint32_t)r0 + threadIdx.x; r < r1; r += kT) {
             const uint32_t s = last_le_u32(row, first, first + cnt, r);
             const uint64_t src = min(a.seg_off[D.seg0 + s] + piece_start(a, D, b, s) + (r - row[s]), src_max);
-            out[r] = B[src];
+            const K k = B[src];
+            out[r] = k;
+            tc.add(k);
             if constexpr (kPayload) vout[r] = a.Bv[src];
         }
-        return;
+    } else {
+        for (uint32_t i = threadIdx.x; i < cnt; i += kT) {
+            const uint32_t s = first + i;
+            w_off[i] = row[s];
+            w_src[i] = a.seg_off[D.seg0 + s] + piece_start(a, D, b, s);
+        }
+        __syncthreads();
+        for (uint32_t r = (uint32_t)r0 + threadIdx.x; r < r1; r += kT) {
+            const uint32_t j = last_le_u32(w_off, 0, cnt, r);
+            const uint64_t src = min(w_src[j] + (r - w_off[j]), src_max);
+            const K k = B[src];
+            out[r] = k;
+            tc.add(k);
+            if constexpr (kPayload) vout[r] = a.Bv[src];
+        }
     }
-    for (uint32_t i = threadIdx.x; i < cnt; i += kT) {
-        const uint32_t s = first + i;
-        w_off[i] = row[s];
-        w_src[i] = a.seg_off[D.seg0 + s] + piece_start(a, D, b, s);
-    }
-    __syncthreads();
-    for (uint32_t r = (uint32_t)r0 + threadIdx.x; r < r1; r += kT) {
-        const uint32_t j = last_le_u32(w_off, 0, cnt, r);
-        const uint64_t src = min(w_src[j] + (r - w_off[j]), src_max);
-        out[r] = B[src];
-        if constexpr (kPayload) vout[r] = a.Bv[src];
+    if constexpr (kCount) {
+        // this workgroup's outputs are tile r0 / 4096 of bucket b
+        uint64_t am = tc.am, om = tc.om;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) {
+            am &= shfl_u64(am, (int)(lane_id() ^ (uint32_t)o));
+            om |= shfl_u64(om, (int)(lane_id() ^ (uint32_t)o));
+        }
+        if (lane_id() == 0) {
+            red[threadIdx.x / kWave][0] = am;
+            red[threadIdx.x / kWave][1] = om;
+        }
+        __syncthreads();
+        const uint64_t tile = (uint64_t)b * a.sort_tps + r0 / kChunk;
+        a.sort_counts[tile * 256 + threadIdx.x] = hist[threadIdx.x];
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int q = 1; q < kT / kWave; ++q) {
+                am &= red[q][0];
+                om |= red[q][1];
+            }
+            atomicAnd((unsigned long long*)&a.sort_and[b], (unsigned long long)am);
+            atomicOr((unsigned long long*)&a.sort_or[b], (unsigned long long)om);
+        }
     }
 }
 
@@ -249,12 +305,23 @@ hipError_t launch_exchange(const ExchangeArgs& a, hipStream_t s) {
     const size_t lds = (size_t)window * (8 + 4);
     // algorithmic bytes: every key (and payload word) read once and written once
     prof.begin(s);
+    const bool cnt = a.sort_counts != nullptr;
     if (a.key_bytes == 4) {
-        if (pay) hipLaunchKernelGGL((exchange_copy_kernel<uint32_t, true>), grid, dim3(kT), lds, s, a, window);
-        else hipLaunchKernelGGL((exchange_copy_kernel<uint32_t, false>), grid, dim3(kT), lds, s, a, window);
+        if (cnt) {
+            if (pay) hipLaunchKernelGGL((exchange_copy_kernel<uint32_t, true, true>), grid, dim3(kT), lds, s, a, window);
+            else hipLaunchKernelGGL((exchange_copy_kernel<uint32_t, false, true>), grid, dim3(kT), lds, s, a, window);
+        } else {
+            if (pay) hipLaunchKernelGGL((exchange_copy_kernel<uint32_t, true, false>), grid, dim3(kT), lds, s, a, window);
+            else hipLaunchKernelGGL((exchange_copy_kernel<uint32_t, false, false>), grid, dim3(kT), lds, s, a, window);
+        }
     } else {
-        if (pay) hipLaunchKernelGGL((exchange_copy_kernel<uint64_t, true>), grid, dim3(kT), lds, s, a, window);
-        else hipLaunchKernelGGL((exchange_copy_kernel<uint64_t, false>), grid, dim3(kT), lds, s, a, window);
+        if (cnt) {
+            if (pay) hipLaunchKernelGGL((exchange_copy_kernel<uint64_t, true, true>), grid, dim3(kT), lds, s, a, window);
+            else hipLaunchKernelGGL((exchange_copy_kernel<uint64_t, false, true>), grid, dim3(kT), lds, s, a, window);
+        } else {
+            if (pay) hipLaunchKernelGGL((exchange_copy_kernel<uint64_t, true, false>), grid, dim3(kT), lds, s, a, window);
+            else hipLaunchKernelGGL((exchange_copy_kernel<uint64_t, false, false>), grid, dim3(kT), lds, s, a, window);
+        }
     }
     prof.end(kProfExchangeCopy, s, a.total * 2 * (a.key_bytes + (pay ? 8 : 0)));
     return hipGetLastError();

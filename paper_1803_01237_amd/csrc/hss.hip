@@ -247,6 +247,7 @@ struct Engine {
     hipStream_t aux = nullptr;
     hipEvent_t ev_start = nullptr, ev_pre = nullptr;
     uint64_t cur_seed = 0;              // seed of the call in progress
+    bool sort_counted = false;          // the bucket sort's first counts came with the exchange
 
     uint64_t counts_words = 0;
 
@@ -835,6 +836,7 @@ hss_status segment_sort(Engine& E, bool first, const void* kin, const uint64_t* 
     hs.sl = E.sl;
     hs.prof = &E.prof;
     hs.cap_large = first && E.knobs.small_sort_cap > 2048;
+    hs.counted = !first && E.sort_counted;
     if (first && E.listed) {
         hs.num_segs = E.n_msd;
         hs.msd_seg = E.msd_seg;
@@ -1126,19 +1128,32 @@ hss_status engine_run(Engine& E, const void* kin, const uint64_t* vin, void* kou
     ex.vout = sort_buckets ? E.Av : nullptr;
     ex.err = &E.ra.ctr->err;
     ex.prof = &E.prof;
+    // sort (one instance): the bucket sort takes its first MSD digit over each
+    // bucket's key range, and the exchange counts those digits as it writes
+    // the buckets (the count pass of the bucket sort's first level)
+    const uint32_t q = E.ih[0].q;
+    const bool counted = sort_buckets && q > 1 && !E.tune.lsd_only;
+    if (sort_buckets && q > 1)
+        HIP_TRY(launch_bucket_shift(q, E.key_bytes * 8, E.ra.s_key, E.bucket_shift, E.bucket_base, s));
+    if (counted) {
+        const uint64_t tps = tiles_of(E.max_bucket);
+        HIP_TRY(launch_sort_count_reset(E.counts, (uint64_t)q * tps * 256, E.lw, q, s));
+        ex.sort_counts = E.counts;
+        ex.sort_tps = (uint32_t)tps;
+        ex.sort_shift = E.bucket_shift;
+        ex.sort_base = E.bucket_base;
+        ex.sort_and = E.lw.and_mask;
+        ex.sort_or = E.lw.or_mask;
+    }
     HIP_TRY(launch_exchange(ex, s));
     // phase 4 (sort, one instance): stable sort of every bucket
     if (sort_buckets) {
-        const uint32_t q = E.ih[0].q;
-        const uint8_t* shifts = nullptr;
-        const uint64_t* bases = nullptr;
-        if (q > 1) {
-            HIP_TRY(launch_bucket_shift(q, E.key_bytes * 8, E.ra.s_key, E.bucket_shift, E.bucket_base, s));
-            shifts = E.bucket_shift;
-            bases = E.bucket_base;
-        }
+        const uint8_t* shifts = q > 1 ? E.bucket_shift : nullptr;
+        const uint64_t* bases = q > 1 ? E.bucket_base : nullptr;
+        E.sort_counted = counted;
         st = segment_sort(E, false, E.A, E.Av, kout, vout, E.B, E.Bv, E.chi_all, q, E.max_bucket,
                           shifts, bases, false, s);
+        E.sort_counted = false;
         if (st != HSS_OK) return st;
     }
     return HSS_OK;

@@ -164,6 +164,9 @@ struct RadixPass {
     // preset to all ones and zero
     uint64_t* and_mask = nullptr;
     uint64_t* or_mask = nullptr;
+    // the counts (and masks) were already taken by the kernel that wrote the
+    // keys: the pass only scans them
+    bool counted = false;
     Profiler* prof = nullptr;
 };
 
@@ -297,6 +300,10 @@ struct HybridSort {
     // (k - seg_base[s]) >> seg_shift[s].  nullptr: base 0, the top digit.
     const uint8_t* seg_shift = nullptr;
     const uint64_t* seg_base = nullptr;
+    // the first level's digit counts per 4096-key tile and the segments'
+    // AND/OR masks were taken while the keys were written (counts laid out as
+    // the count pass would, every tile past a segment's end zero)
+    bool counted = false;
     OversizeList ov;                   // two lists, alternating between levels
     OversizeList ov2;
     EqualList eq;
@@ -572,6 +579,16 @@ struct ExchangeArgs {
     uint32_t* chunk0;              // Q+1: first copy workgroup of every bucket (row)
     uint64_t max_chunks;           // bound on the copy workgroups
     uint64_t total;                // keys of all instances
+    // one instance, before its bucket sort: each copy workgroup also counts
+    // the digits ((key - base[b]) >> shift[b]) & 255 of its 4096 outputs (the
+    // bucket's tile) into counts[(b tps + tile) 256 + digit], and the AND and
+    // OR of key - base[b] into and_mask[b], or_mask[b]; null: no counting
+    uint32_t* sort_counts = nullptr;
+    uint32_t sort_tps = 0;
+    const uint8_t* sort_shift = nullptr;
+    const uint64_t* sort_base = nullptr;
+    uint64_t* sort_and = nullptr;
+    uint64_t* sort_or = nullptr;
     // output: the caller's buffers of every instance, or (when out is set)
     // one buffer at the instance positions
     void* out = nullptr;
@@ -588,6 +605,9 @@ hipError_t launch_exchange(const ExchangeArgs& a, hipStream_t s);
 hipError_t launch_entry_ranges(uint32_t n_msd, const uint32_t* msd_seg, const uint32_t* seg_inst,
                                const uint8_t* ishift, const uint64_t* ibase, uint8_t* shift,
                                uint64_t* base, hipStream_t s);
+// The bucket sort's first level counted by the exchange: zero the count
+// table (words) and preset the n masks.
+hipError_t launch_sort_count_reset(uint32_t* counts, uint64_t words, LevelWork w, uint32_t n, hipStream_t s);
 hipError_t launch_stage_offsets(const uint64_t* chi1, const uint64_t* off2, uint32_t r, uint32_t pg,
                                 uint64_t n, uint64_t* out, hipStream_t s);
 // Per-bucket MSD digit for the bucket sort: all keys of bucket b lie in

@@ -339,7 +339,9 @@ hipError_t count_scan_impl(const RadixPass& a, hipStream_t stream) {
     const uint64_t table = (uint64_t)a.num_tiles * 256ull * 4ull;
     const dim3 grid(a.num_tiles), block(kSortThreads);
     prof.begin(stream);
-    if (a.and_mask)
+    if (a.counted) {
+        // counted where the keys were written
+    } else if (a.and_mask)
         hipLaunchKernelGGL((radix_count_kernel<K, true>), grid, block, 0, stream, (const K*)a.keys_in,
                            a.map, a.shift, a.seg_shift, a.counts, a.and_mask, a.or_mask);
     else

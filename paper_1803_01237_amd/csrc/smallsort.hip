@@ -829,6 +829,11 @@ SmallJobs<K> level_jobs(const HybridSort& a, const OversizeList& cur, uint32_t g
     return jobs;
 }
 
+__global__ void fill_zero_kernel(uint32_t* p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
 hipError_t read_summary(const OversizeList& ov, const SlowList& sl, const EqualList& eq,
                         HybridHost& host, hipStream_t s) {
     hipLaunchKernelGGL(ov_tiles_kernel, dim3(1), dim3(1024), 0, s, ov, sl, eq);
@@ -914,8 +919,10 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         ps.has_payload = pay;
         ps.and_mask = a.lw.and_mask;
         ps.or_mask = a.lw.or_mask;
-        hipLaunchKernelGGL(mask_reset_kernel, dim3(min((msd_segs + 255) / 256, 1024u)), dim3(256), 0, s,
-                           a.lw, msd_segs);
+        ps.counted = a.counted;
+        if (!a.counted)
+            hipLaunchKernelGGL(mask_reset_kernel, dim3(min((msd_segs + 255) / 256, 1024u)), dim3(256), 0, s,
+                               a.lw, msd_segs);
         e = radix_count_scan(ps, s);
         if (e != hipSuccess) return e;
         DecideView v;
@@ -1091,6 +1098,15 @@ hipError_t write_fences(const void* keys, int key_bytes, uint32_t num_segs, cons
 
 // Entries of the oversize and equal lists are disjoint ranges of more than
 // kCapSmall keys; slow-list entries disjoint ranges of more than kGroupMax.
+hipError_t launch_sort_count_reset(uint32_t* counts, uint64_t words, LevelWork w, uint32_t n, hipStream_t s) {
+    if (words) {
+        const uint32_t grid = (uint32_t)std::min<uint64_t>((words + 255) / 256, 4096);
+        hipLaunchKernelGGL(fill_zero_kernel, dim3(grid), dim3(256), 0, s, counts, words);
+    }
+    if (n) hipLaunchKernelGGL(mask_reset_kernel, dim3(std::min((n + 255) / 256, 1024u)), dim3(256), 0, s, w, n);
+    return hipGetLastError();
+}
+
 uint64_t oversize_capacity(uint64_t total_len) { return total_len / (kCapSmall + 1) + 1; }
 
 uint64_t slow_capacity(uint64_t total_len) { return total_len / (kGroupMax + 1) + 1; }
