@@ -41,13 +41,13 @@ WORKLOADS = {
 # figures hold for the kernel sources with the hash below; after any change
 # to them the traffic is reported as null until the counters are taken again.
 TRAFFIC_WORKLOAD = "uniform_u64_2^28_p1024"
-TRAFFIC_SRC_SHA = "abf5f96268818584"
+TRAFFIC_SRC_SHA = "96b1528b909745ec"
 TRAFFIC = {   # family: (fetch bytes, write bytes) per launch
-    "radix_count": (2147722696, 71303168),
+    "radix_count": (2147722460, 71303168),
     "radix_scan": (134381568, 70254592),
-    "radix_scatter": (2214722212, 2316126822),
-    "exchange_copy": (2306309550, 2152674938),
-    "small_sort": (2229541677, 2294237176),
+    "radix_scatter": (2214722217, 2320637219),
+    "exchange_copy": (2306231619, 2152715534),
+    "small_sort": (2229536106, 2294237215),
 }
 
 

@@ -506,7 +506,7 @@ size_t layout(Engine& E, char* base) {
     r.ivl_inst = ar.take<uint32_t>(Q);
     r.ivl_tot = ar.take<uint64_t>(Q + 1);
     r.ivl_nz = ar.take<uint32_t>(Q + 1);
-    r.ivl_dom = ar.take<uint64_t>(Q);
+    r.ivl_dom = ar.take<uint64_t>(Q + 1);
     r.ivl_pcnt = ar.take<uint32_t>(Q);
     r.ivl_poff = ar.take<uint32_t>(Q + 1);
     r.ivl_cursor = ar.take<uint32_t>(Q);

@@ -196,14 +196,12 @@ __global__ __launch_bounds__(kScanT) void ivl_scan_kernel(RoundArgs a) {
     const uint32_t n = a.ctr->n_ivl;
     const uint64_t blocks = wg_scan_inplace(a.ivl_tot, n, scratch);
     const uint64_t slices = wg_scan_inplace(a.ivl_nz, n, scratch);
-    const uint32_t per = (n + kScanT - 1) / kScanT;
-    const uint32_t r0 = min(threadIdx.x * per, n), r1 = min(r0 + per, n);
-    uint64_t d = 0;
-    for (uint32_t k = r0; k < r1; ++k) d += a.ivl_dom[k];
-    d = block_sum<uint64_t, kScanT>(d, scratch);
+    // domain before every interval (an instance's domain is a difference)
+    const uint64_t d = wg_scan_inplace(a.ivl_dom, n, scratch);
     if (threadIdx.x == 0) {
         a.ivl_tot[n] = blocks;
         a.ivl_nz[n] = (uint32_t)slices;
+        a.ivl_dom[n] = d;
         a.ctr->blocks = blocks;
         a.ctr->n_slices = (uint32_t)slices;
         a.ctr->domain = d;
@@ -510,13 +508,18 @@ __global__ void budget_rate_kernel(RoundArgs a, uint32_t round) {
     // thread per instance: its intervals are a contiguous run of the list (the
     // leaders are found in row order, and rows in instance order)
     for (uint32_t I = blockIdx.x * blockDim.x + threadIdx.x; I < a.n_inst; I += gridDim.x * blockDim.x) {
-        uint32_t lo = 0, hi = n_ivl;   // first interval of instance I
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (a.ivl_inst[mid] < I) lo = mid + 1; else hi = mid;
-        }
-        uint64_t dom = 0;
-        for (uint32_t k = lo; k < n_ivl && a.ivl_inst[k] == I; ++k) dom += a.ivl_dom[k];
+        // [k0, k1): the intervals of instance I; ivl_dom holds the domain
+        // before every interval
+        auto first_of = [&](uint32_t inst) {
+            uint32_t lo = 0, hi = n_ivl;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (a.ivl_inst[mid] < inst) lo = mid + 1; else hi = mid;
+            }
+            return lo;
+        };
+        const uint32_t k0 = first_of(I), k1 = first_of(I + 1);
+        const uint64_t dom = a.ivl_dom[k1] - a.ivl_dom[k0];
         if (dom == 0) continue;   // no interval left in this instance
         const double q = ((double)a.budget * (double)a.inst[I].q) / (double)dom;
         const bool all = q >= 1.0;
