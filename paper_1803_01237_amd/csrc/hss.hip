@@ -85,7 +85,7 @@ constexpr uint64_t kPresampleExpectMax = 1ull << 16;
 // (round 1 has one interval, the whole input: searched by segment chunks).
 constexpr uint32_t kPairRankFrom = 2;
 constexpr uint32_t kDefaultSmallCap = 2048;
-constexpr uint32_t kDefaultSampleGrid = 4096;
+constexpr uint32_t kDefaultSampleGrid = 1024;
 constexpr uint32_t kDefaultPairFrom = kPairRankFrom;
 constexpr uint32_t kDefaultPairGrid = 8192;
 
@@ -1215,7 +1215,7 @@ hss_status autotune(Engine& E, hipStream_t s, F call) {
         return HSS_OK;
     };
     hss_knobs best = E.knobs;
-    const uint32_t cands[4][3] = {{2048, 4096, 0}, {2048, 4096, 8192}, {2, 3, 64}, {4096, 8192, 16384}};
+    const uint32_t cands[4][3] = {{2048, 4096, 0}, {512, 1024, 2048}, {2, 3, 64}, {4096, 8192, 16384}};
     for (int knob = 0; knob < 4; ++knob) {
         double best_ms = 1e300;
         hss_knobs pick = best;

@@ -399,7 +399,7 @@ def test_graph_replays_match_plain_launches(hss):
 KNOB_SETTINGS = [
     {},
     {"small_sort_cap": 4096},
-    {"sample_workgroups": 1024},
+    {"sample_workgroups": 4096},
     {"pair_rank_from": 1},                 # round 1 searched per pair as well
     {"pair_rank_from": 64},                # every round by segment chunks
     {"pair_rank_workgroups": 2048, "sample_workgroups": 8192, "small_sort_cap": 4096},
