@@ -46,6 +46,21 @@ __device__ __forceinline__ Philox4 sample_block(uint64_t seed, uint64_t block, u
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// Global-memory view of a pointer.  A pointer taken from a table of device
+// addresses, or chosen between two buffers, is generic to the compiler, which
+// then emits flat accesses; a flat load also counts against the LDS wait
+// counter, so every wait for an LDS result waits for the key loads as well.
+template <typename T>
+using global_ptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ global_ptr<T> as_global(const T* p) {
+    return (global_ptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ uint64_t lanes_below_mask() {
     return (1ull << lane_id()) - 1ull;   // lane 0 -> 0
 }

@@ -280,9 +280,9 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     const FenceSink fs = fence_sink(fences, seg);
     if (n == 1 || bits == 0) {   // already in order: every key equal
         for (uint32_t i = threadIdx.x; i < n; i += kT) {
-            const K k = src[i];
+            const K k = as_global(src)[i];
             kout[base + i] = k;
-            if constexpr (kPayload) vout[base + i] = vsrc[i];
+            if constexpr (kPayload) vout[base + i] = as_global(vsrc)[i];
             if (fs.dst) put_fence(fs, base + i, (uint64_t)k);
         }
         return;
@@ -299,13 +299,14 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     K kr[kRowsT];
     uint32_t dr[kRowsT];
     uint64_t vr[kStage ? kRowsT : 1];
+    const global_ptr<K> gsrc = as_global(src);
 #pragma unroll
     for (int r = 0; r < kRowsT; ++r) {
         const uint32_t i = r * kT + threadIdx.x;
         kr[r] = 0;
         dr[r] = 0;
-        if (i < n) kr[r] = src[i];
-        if constexpr (kStage) vr[r] = i < n ? vsrc[i] : 0;
+        if (i < n) kr[r] = gsrc[i];
+        if constexpr (kStage) vr[r] = i < n ? as_global(vsrc)[i] : 0;
     }
 #pragma unroll
     for (int r = 0; r < kRowsT; ++r) {
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
                 if (i < n) {
                     jobs.stash[base + i] = kr[r];
                     if constexpr (kStage) jobs.vstash[base + i] = vr[r];
-                    else if constexpr (kPayload) jobs.vstash[base + i] = vsrc[i];
+                    else if constexpr (kPayload) jobs.vstash[base + i] = as_global(vsrc)[i];
                 }
             }
         }
@@ -404,7 +405,7 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
             const uint64_t o = base + g0 + rk;
             kout[o] = k;
             if constexpr (kStage) vout[o] = Bv[e];
-            else vout[o] = vsrc[ie];
+            else vout[o] = as_global(vsrc)[ie];
             if (fs.dst) put_fence(fs, o, (uint64_t)k);
         } else {
             // keys only: equal keys are interchangeable, so the ones placed
