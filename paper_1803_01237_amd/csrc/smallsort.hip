@@ -300,20 +300,24 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     uint32_t dr[kRowsT];
     uint64_t vr[kStage ? kRowsT : 1];
     const global_ptr<K> gsrc = as_global(src);
+    // rows wholly past the end are skipped by a branch uniform over the
+    // workgroup; inside a row the lanes past the end hold kbase, whose group
+    // is computed but never counted or placed
 #pragma unroll
     for (int r = 0; r < kRowsT; ++r) {
-        const uint32_t i = r * kT + threadIdx.x;
-        kr[r] = 0;
-        dr[r] = 0;
-        if (i < n) kr[r] = gsrc[i];
-        if constexpr (kStage) vr[r] = i < n ? as_global(vsrc)[i] : 0;
+        kr[r] = kbase;
+        if (r * kT < (int)n) {
+            const uint32_t i = r * kT + threadIdx.x;
+            if (i < n) kr[r] = gsrc[i];
+            if constexpr (kStage) vr[r] = i < n ? as_global(vsrc)[i] : 0;
+        }
     }
 #pragma unroll
     for (int r = 0; r < kRowsT; ++r) {
-        const uint32_t i = r * kT + threadIdx.x;
-        if (i < n) {
+        dr[r] = 0;
+        if (r * kT < (int)n) {
             dr[r] = (uint32_t)((K)(kr[r] - kbase) >> shift2) & (kG - 1);
-            atomicAdd(&hist[dr[r]], 1u);
+            if (r * kT + threadIdx.x < n) atomicAdd(&hist[dr[r]], 1u);
         }
     }
     __syncthreads();
@@ -382,11 +386,20 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
         }
     }
     __syncthreads();
+    // outputs addressed by 32-bit offsets from the sub-bucket's start; a
+    // fence is due where the offset from the segment start is a multiple of
+    // kFenceStride, which the low 32 bits decide
+    const auto ob = as_global(kout + base);
+    const uint64_t frel = fs.dst ? base - fs.org : 0;
+    auto fence = [&](uint32_t o, K k) {
+        if (fs.dst && (((uint32_t)frel + o) & (kFenceStride - 1)) == 0)
+            fs.dst[(frel + o) / kFenceStride] = (uint64_t)k;
+    };
     if (exact) {
         for (uint32_t e = threadIdx.x; e < n; e += kT) {
             const K k = Bk[e];
-            kout[base + e] = k;
-            if (fs.dst) put_fence(fs, base + e, (uint64_t)k);
+            ob[e] = k;
+            fence(e, k);
         }
         return;
     }
@@ -398,23 +411,27 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
         if constexpr (kPayload) {
             // equal keys keep their input order
             const uint16_t ie = Bi[e];
+#pragma unroll 1
             for (uint32_t j = g0; j < g1; ++j) {
                 const K x = Bk[j];
-                rk += (x < k || (x == k && Bi[j] < ie)) ? 1u : 0u;
+                rk += (uint32_t)((x < k) | ((x == k) & (Bi[j] < ie)));
             }
-            const uint64_t o = base + g0 + rk;
-            kout[o] = k;
-            if constexpr (kStage) vout[o] = Bv[e];
-            else vout[o] = as_global(vsrc)[ie];
-            if (fs.dst) put_fence(fs, o, (uint64_t)k);
+            const uint32_t o = g0 + rk;
+            ob[o] = k;
+            if constexpr (kStage) as_global(vout + base)[o] = Bv[e];
+            else as_global(vout + base)[o] = as_global(vsrc)[ie];
+            fence(o, k);
         } else {
             // keys only: equal keys are interchangeable, so the ones placed
-            // before this one in the group go first
-            for (uint32_t j = g0; j < e; ++j) rk += Bk[j] <= k ? 1u : 0u;
-            for (uint32_t j = e + 1; j < g1; ++j) rk += Bk[j] < k ? 1u : 0u;
-            const uint64_t o = base + g0 + rk;
-            kout[o] = k;
-            if (fs.dst) put_fence(fs, o, (uint64_t)k);
+            // before this one in the group go first; one pass over the group
+#pragma unroll 1
+            for (uint32_t j = g0; j < g1; ++j) {
+                const K x = Bk[j];
+                rk += (uint32_t)((x < k) | ((x == k) & (j < e)));
+            }
+            const uint32_t o = g0 + rk;
+            ob[o] = k;
+            fence(o, k);
         }
     }
 }
