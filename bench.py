@@ -41,13 +41,13 @@ WORKLOADS = {
 # figures hold for the kernel sources with the hash below; after any change
 # to them the traffic is reported as null until the counters are taken again.
 TRAFFIC_WORKLOAD = "uniform_u64_2^28_p1024"
-TRAFFIC_SRC_SHA = "96b1528b909745ec"
+TRAFFIC_SRC_SHA = "d51c2d86069f4702"
 TRAFFIC = {   # family: (fetch bytes, write bytes) per launch
-    "radix_count": (2147722460, 71303168),
-    "radix_scan": (134381568, 70254592),
-    "radix_scatter": (2214722217, 2320637219),
-    "exchange_copy": (2306231619, 2152715534),
-    "small_sort": (2229536106, 2294237215),
+    "radix_count": (2147723791, 71303168),
+    "radix_scan": (134381681, 70254592),
+    "radix_scatter": (2214719068, 2321996520),
+    "exchange_copy": (2306265057, 2152692561),
+    "small_sort": (2229539695, 2294236743),
 }
 
 

@@ -1199,45 +1199,58 @@ void set_knobs(Engine& E, const hss_knobs& k) {
 }
 
 // The autotuner: `call` runs one whole call of the engine on the caller's
-// input and returns after its work has completed.  Each knob in turn takes
-// each of its candidate values (the others at their best so far); each
-// setting is timed twice and the fastest kept.  Every run writes the same
-// outputs, so the call's result does not depend on the search.
+// input and returns after its work has completed.  A setting's time is the
+// fastest of three calls (the first call after a change of knobs also
+// captures the round graph again).  The starting knobs are timed first; each
+// knob in turn tries its other candidate values (the others at their best so
+// far), and a candidate replaces the incumbent only when it is faster by more
+// than kTuneMargin, so that run-to-run noise does not move the knobs off a
+// good default.  Every run writes the same outputs, so the call's result
+// does not depend on the search.
+constexpr double kTuneMargin = 0.02;
+
 template <typename F>
 hss_status autotune(Engine& E, hipStream_t s, F call) {
     using Clock = std::chrono::steady_clock;
-    auto time_once = [&](double* ms) -> hss_status {
-        HIP_TRY(hipStreamSynchronize(s));
-        const auto t0 = Clock::now();
-        const hss_status st = call();
-        if (st != HSS_OK) return st;
-        *ms = std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+    auto measure = [&](const hss_knobs& k, double* ms) -> hss_status {
+        set_knobs(E, k);
+        double m = 1e300;
+        for (int r = 0; r < 3; ++r) {
+            HIP_TRY(hipStreamSynchronize(s));
+            const auto t0 = Clock::now();
+            const hss_status st = call();
+            if (st != HSS_OK) return st;
+            m = std::min(m, std::chrono::duration<double, std::milli>(Clock::now() - t0).count());
+        }
+        *ms = m;
         return HSS_OK;
     };
+    auto value = [](const hss_knobs& k, int knob) -> uint32_t {
+        return knob == 0 ? k.small_sort_cap
+                         : knob == 1 ? k.sample_workgroups : knob == 2 ? k.pair_rank_from : k.pair_rank_workgroups;
+    };
     hss_knobs best = E.knobs;
+    double best_ms = 0;
+    hss_status st = measure(best, &best_ms);
+    if (st != HSS_OK) return st;
     const uint32_t cands[4][3] = {{2048, 4096, 0}, {512, 1024, 2048}, {2, 3, 64}, {4096, 8192, 16384}};
     for (int knob = 0; knob < 4; ++knob) {
-        double best_ms = 1e300;
-        hss_knobs pick = best;
         for (int c = 0; c < 3; ++c) {
             const uint32_t v = cands[knob][c];
-            if (v == 0) continue;
+            if (v == 0 || v == value(best, knob)) continue;
             hss_knobs k = best;
             if (knob == 0) k.small_sort_cap = v;
             if (knob == 1) k.sample_workgroups = v;
             if (knob == 2) k.pair_rank_from = v;
             if (knob == 3) k.pair_rank_workgroups = v;
-            set_knobs(E, k);
-            double a = 0, b = 0;
-            hss_status st = time_once(&a);
-            if (st == HSS_OK) st = time_once(&b);
+            double ms = 0;
+            st = measure(k, &ms);
             if (st != HSS_OK) return st;
-            if (std::min(a, b) < best_ms) {
-                best_ms = std::min(a, b);
-                pick = k;
+            if (ms < best_ms * (1.0 - kTuneMargin)) {
+                best_ms = ms;
+                best = k;
             }
         }
-        best = pick;
     }
     best.tuned = 1;
     set_knobs(E, best);
