@@ -424,10 +424,12 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
         } else {
             // keys only: equal keys are interchangeable, so the ones placed
             // before this one in the group go first; one pass over the group
+            const K* const pe = Bk + g1;
+            const K* const pk = Bk + e;
 #pragma unroll 1
-            for (uint32_t j = g0; j < g1; ++j) {
-                const K x = Bk[j];
-                rk += (uint32_t)((x < k) | ((x == k) & (j < e)));
+            for (const K* q = Bk + g0; q < pe; ++q) {
+                const K x = *q;
+                rk += (uint32_t)((x < k) | ((x == k) & (q < pk)));
             }
             const uint32_t o = g0 + rk;
             ob[o] = k;
