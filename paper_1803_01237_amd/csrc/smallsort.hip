@@ -290,6 +290,13 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     // the offsets key - kbase of this sub-bucket agree on every bit at or
     // above `bits`
     const int shift2 = bits >= kGB ? bits - kGB : 0;
+    // a key's group; with 64-bit keys, no offset and the group bits in the
+    // upper word (the first level of the local sort), one bit-field extract
+    const bool hi_group = sizeof(K) == 8 && kbase == (K)0 && shift2 >= 32;
+    auto group_of = [&](K k) -> uint32_t {
+        if (hi_group) return __builtin_amdgcn_ubfe((uint32_t)((uint64_t)k >> 32), (uint32_t)(shift2 - 32), kGB);
+        return (uint32_t)((K)(k - kbase) >> shift2) & (kG - 1);
+    };
     for (uint32_t i = threadIdx.x; i < kG; i += kT) hist[i] = 0;
     if (threadIdx.x == 0) {
         max_count = 0;
@@ -316,7 +323,7 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     for (int r = 0; r < kRowsT; ++r) {
         dr[r] = 0;
         if (r * kT < (int)n) {
-            dr[r] = (uint32_t)((K)(kr[r] - kbase) >> shift2) & (kG - 1);
+            dr[r] = group_of(kr[r]);
             if (r * kT + threadIdx.x < n) atomicAdd(&hist[dr[r]], 1u);
         }
     }
@@ -405,7 +412,7 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     }
     for (uint32_t e = threadIdx.x; e < n; e += kT) {
         const K k = Bk[e];
-        const uint32_t d = (uint32_t)((K)(k - kbase) >> shift2) & (kG - 1);
+        const uint32_t d = group_of(k);
         const uint32_t g1 = cursor[d], g0 = g1 - hist[d];
         uint32_t rk = 0;
         if constexpr (kPayload) {
