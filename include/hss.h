@@ -76,7 +76,7 @@ typedef struct {
                                    again when the probe buffers grow)           */
     uint32_t autotune;          /* 1: the first call tries the launch knobs of
                                    hss_knobs on its own input, one knob at a
-                                   time, and moves off the starting knobs only
+                                   time, and moves off the current knobs only
                                    for a setting more than 2% faster (the
                                    outputs do not depend on the knobs)          */
     uint32_t reserved[2];       /* must be zero */

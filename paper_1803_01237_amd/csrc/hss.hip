@@ -1201,11 +1201,11 @@ void set_knobs(Engine& E, const hss_knobs& k) {
 // The autotuner: `call` runs one whole call of the engine on the caller's
 // input and returns after its work has completed.  A setting's time is the
 // fastest of three calls (the first call after a change of knobs also
-// captures the round graph again).  The starting knobs are timed first; each
-// knob in turn tries its other candidate values (the others at their best so
-// far), and a candidate replaces the incumbent only when it is faster by more
-// than kTuneMargin, so that run-to-run noise does not move the knobs off a
-// good default.  Every run writes the same outputs, so the call's result
+// captures the round graph again).  Each knob in turn tries its other
+// candidate values (the others at their best so far); the incumbent is timed
+// again just before every candidate, so that a slow drift of the machine
+// does not decide, and a candidate replaces it only when it is faster by more
+// than kTuneMargin.  Every run writes the same outputs, so the call's result
 // does not depend on the search.
 constexpr double kTuneMargin = 0.02;
 
@@ -1230,9 +1230,6 @@ hss_status autotune(Engine& E, hipStream_t s, F call) {
                          : knob == 1 ? k.sample_workgroups : knob == 2 ? k.pair_rank_from : k.pair_rank_workgroups;
     };
     hss_knobs best = E.knobs;
-    double best_ms = 0;
-    hss_status st = measure(best, &best_ms);
-    if (st != HSS_OK) return st;
     const uint32_t cands[4][3] = {{2048, 4096, 0}, {512, 1024, 2048}, {2, 3, 64}, {4096, 8192, 16384}};
     for (int knob = 0; knob < 4; ++knob) {
         for (int c = 0; c < 3; ++c) {
@@ -1243,13 +1240,11 @@ hss_status autotune(Engine& E, hipStream_t s, F call) {
             if (knob == 1) k.sample_workgroups = v;
             if (knob == 2) k.pair_rank_from = v;
             if (knob == 3) k.pair_rank_workgroups = v;
-            double ms = 0;
-            st = measure(k, &ms);
+            double inc_ms = 0, ms = 0;
+            hss_status st = measure(best, &inc_ms);
+            if (st == HSS_OK) st = measure(k, &ms);
             if (st != HSS_OK) return st;
-            if (ms < best_ms * (1.0 - kTuneMargin)) {
-                best_ms = ms;
-                best = k;
-            }
+            if (ms < inc_ms * (1.0 - kTuneMargin)) best = k;
         }
     }
     best.tuned = 1;
