@@ -60,7 +60,8 @@ typedef struct {
     uint32_t k_override;        /* 0: k = max(1, ceil(ln(2 ln p / eps))) (section 4.2) */
     uint32_t force_full_sample; /* 1: every key is a probe in round 1 (one round) */
     uint32_t trace_level;       /* 0: per-round counts only; 1: also probes, ranks
-                                   and splitter state per round (host copies)    */
+                                   and splitter state per round (host copies);
+                                   2: also every round's local histograms      */
     uint32_t lsd_only;          /* 1: sort segments and buckets by plain 8-bit LSD
                                    passes instead of the MSD pass + on-chip finish
                                    (same results; for comparison)               */
@@ -189,6 +190,12 @@ hss_status hss_trace_round_info(hss_plan_t plan, uint32_t j, uint64_t* domain, u
  * any pointer may be NULL).  Needs trace_level >= 1. */
 hss_status hss_trace_round_probes(hss_plan_t plan, uint32_t j, uint64_t* keys, uint64_t* tags,
                                   uint64_t* ranks);
+
+/* Round j local histograms (section 4.2.2 step 2): counts[e p + s] = c_s(e),
+ * the number of keys of segment s that precede probe e (in sorted probe
+ * order) in the order (key, segment, index) of section 6.1; m x p words.
+ * Their sum over s is the probe's rank R.  Needs trace_level >= 2. */
+hss_status hss_trace_round_counts(hss_plan_t plan, uint32_t j, uint32_t* counts);
 
 /* Splitter state after round j, p-1 entries each: rank of the bounding probe
  * below / above N i/p (UINT64_MAX for none or settled), settled flag, chi

@@ -44,7 +44,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with g++ (host only)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-shared", "-fPIC",
+        cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-shared", "-fPIC", "-pthread",
                "-Wall", "-Wextra", "-o", tmp, _SRC]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
@@ -63,7 +63,8 @@ def lib():
         L.oracle_philox_word.argtypes = [u64, u64, u32]
         L.oracle_philox_word.restype = u32
         L.oracle_hss.argtypes = [u64, u32, u32, dbl, C.c_int, vp, vp, u64, C.c_int, u32, u32,
-                                 C.c_int, u32, C.c_int, vp, vp, vp]
+                                 C.c_int, u32, C.c_int, vp, vp, vp, C.c_int]
+        L.oracle_times.argtypes = [vp, vp]
         L.oracle_hss.restype = vp
         L.oracle_local_sort.argtypes = [u64, u32, C.c_int, vp, vp, vp, vp]
         L.oracle_local_sort.restype = C.c_int
@@ -159,13 +160,18 @@ class Result:
     s_key: np.ndarray | None = None
     s_tag: np.ndarray | None = None
     pieces: np.ndarray | None = None     # (q+1, p)
+    # seconds per stage: local sort, splitter rounds, exchange, bucket sort
+    times: tuple = (0.0, 0.0, 0.0, 0.0)
 
 
 def hss(keys: np.ndarray, p: int, eps: float, seed: int, vals: np.ndarray | None = None,
         mode: str = "partition", k_override: int = 0, max_rounds: int = 0,
         force_full_sample: bool = False, trace_level: int = 1,
-        probes_per_round: int = 0, buckets: int | None = None) -> Result:
+        probes_per_round: int = 0, buckets: int | None = None, threads: int = 1) -> Result:
     """Run the whole method on the host; returns outputs and the round trace.
+    threads: host threads over which the per-segment work (local sort,
+    slices, draws, local histograms, piece rows) and the per-bucket work
+    (exchange, bucket sort) are split; the result does not depend on it.
     probes_per_round = c > 0: a fixed budget of c q probes per round (rate
     c q / |gamma|) instead of the rate schedule.  buckets = q (default p):
     the p segments are split into q <= p buckets, as in one stage of
@@ -188,7 +194,7 @@ def hss(keys: np.ndarray, p: int, eps: float, seed: int, vals: np.ndarray | None
     h = L.oracle_hss(n, p, q, eps, bits, _ptr(kin), _ptr(vi), seed & NONE,
                      1 if mode == "sort" else 0, k_override, max_rounds,
                      1 if force_full_sample else 0, probes_per_round, trace_level,
-                     _ptr(ko), _ptr(vo), _ptr(off))
+                     _ptr(ko), _ptr(vo), _ptr(off), int(threads))
     try:
         st = L.oracle_status(h)
         res = Result(status=st)
@@ -196,6 +202,9 @@ def hss(keys: np.ndarray, p: int, eps: float, seed: int, vals: np.ndarray | None
             return res
         res.keys, res.vals, res.offsets = ko[:n], (None if vo is None else vo[:n]), off
         res.tol, res.k = int(L.oracle_tol(h)), int(L.oracle_k(h))
+        tm = np.zeros(4, dtype=np.float64)
+        L.oracle_times(h, _ptr(tm))
+        res.times = tuple(float(x) for x in tm)
         for j in range(L.oracle_num_rounds(h)):
             d, m, th, al = C.c_uint64(), C.c_uint64(), C.c_uint32(), C.c_uint32()
             L.oracle_round_info(h, j, C.byref(d), C.byref(m), C.byref(th), C.byref(al))

@@ -19,17 +19,44 @@
 // Parity status of each exported function is stated beside it.
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <map>
 #include <numeric>
+#include <thread>
 #include <utility>
 #include <vector>
 
 namespace {
 
 typedef unsigned __int128 u128;
+
+// ---------------------------------------------------------------------------
+// Work over the p processors (segments) may be split among host threads: the
+// paper's processors do it concurrently, every segment's share is computed
+// on its own, and whatever is added up across segments is an integer sum,
+// whose value does not depend on the order.  Thread t takes the contiguous
+// range of items [t n / T, (t+1) n / T); f(t, lo, hi) runs once per thread.
+// ---------------------------------------------------------------------------
+template <typename F>
+void split_over(uint64_t n, int threads, F f) {
+    int T = threads < 1 ? 1 : threads;
+    if ((uint64_t)T > n) T = n == 0 ? 1 : (int)n;
+    if (T == 1) { f(0, (uint64_t)0, n); return; }
+    std::vector<std::thread> pool;
+    for (int t = 0; t < T; ++t) {
+        uint64_t lo = (uint64_t)(((u128)t * n) / (u128)T);
+        uint64_t hi = (uint64_t)(((u128)(t + 1) * n) / (u128)T);
+        pool.emplace_back([=, &f]() { f(t, lo, hi); });
+    }
+    for (auto& th : pool) th.join();
+}
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10, written from Salmon, Moraes, Dror, Shaw, "Parallel random
@@ -247,30 +274,33 @@ bool valid_params(uint64_t n, uint32_t p, double eps, int key_bits) {
 }
 
 void load_and_local_sort(Problem& P, uint64_t n, uint32_t p, int key_bits,
-                         const void* keys_in, const uint64_t* vals_in) {
+                         const void* keys_in, const uint64_t* vals_in, int threads) {
     P.n = n; P.p = p;
     P.seg_start.resize(p + 1);
     for (uint64_t s = 0; s <= p; ++s) P.seg_start[s] = (uint64_t)(((u128)s * n) / p);
     P.key.resize(n);
     P.val.resize(n);
-    for (uint64_t i = 0; i < n; ++i) {
-        P.key[i] = key_bits == 32 ? (uint64_t)((const uint32_t*)keys_in)[i]
-                                  : ((const uint64_t*)keys_in)[i];
-        P.val[i] = vals_in ? vals_in[i] : 0;
-    }
     // Local sort of each segment (section 6: phase 1), stable so that the tag
-    // order inside a segment is the input order among equal keys.
-    for (uint32_t s = 0; s < p; ++s) {
-        uint64_t b = P.seg_start[s], e = P.seg_start[s + 1];
-        std::vector<uint64_t> idx(e - b);
-        std::iota(idx.begin(), idx.end(), b);
-        std::stable_sort(idx.begin(), idx.end(),
-                         [&](uint64_t x, uint64_t y) { return P.key[x] < P.key[y]; });
-        std::vector<uint64_t> k2(e - b), v2(e - b);
-        for (uint64_t t = 0; t < e - b; ++t) { k2[t] = P.key[idx[t]]; v2[t] = P.val[idx[t]]; }
-        std::copy(k2.begin(), k2.end(), P.key.begin() + b);
-        std::copy(v2.begin(), v2.end(), P.val.begin() + b);
-    }
+    // order inside a segment is the input order among equal keys.  Every
+    // processor loads and sorts its own segment.
+    split_over(p, threads, [&](int, uint64_t s0, uint64_t s1) {
+        for (uint64_t s = s0; s < s1; ++s) {
+            uint64_t b = P.seg_start[s], e = P.seg_start[s + 1];
+            for (uint64_t i = b; i < e; ++i) {
+                P.key[i] = key_bits == 32 ? (uint64_t)((const uint32_t*)keys_in)[i]
+                                          : ((const uint64_t*)keys_in)[i];
+                P.val[i] = vals_in ? vals_in[i] : 0;
+            }
+            std::vector<uint64_t> idx(e - b);
+            std::iota(idx.begin(), idx.end(), b);
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](uint64_t x, uint64_t y) { return P.key[x] < P.key[y]; });
+            std::vector<uint64_t> k2(e - b), v2(e - b);
+            for (uint64_t t = 0; t < e - b; ++t) { k2[t] = P.key[idx[t]]; v2[t] = P.val[idx[t]]; }
+            std::copy(k2.begin(), k2.end(), P.key.begin() + b);
+            std::copy(v2.begin(), v2.end(), P.val.begin() + b);
+        }
+    });
 }
 
 // Strict order of section 6.1 on tags of the locally sorted buffer.
@@ -291,7 +321,7 @@ bool before(const Problem& P, uint64_t g1, uint64_t g2) {
 // histogram still runs over the p segments.
 void determine_splitters(const Problem& P, uint32_t q, double eps, uint64_t seed,
                          uint32_t k_override, uint32_t max_rounds, int force_full,
-                         uint32_t budget, int trace_level, Run& R) {
+                         uint32_t budget, int trace_level, int threads, Run& R) {
     const uint64_t n = P.n;
     const uint32_t p = P.p;
     R.c = make_constants(n, q, eps, k_override);
@@ -313,18 +343,28 @@ void determine_splitters(const Problem& P, uint32_t q, double eps, uint64_t seed
         std::map<std::pair<uint64_t, uint64_t>, bool> intervals;   // (L tag, U tag)
         for (uint32_t i = 1; i < q; ++i)
             if (!sp[i].settled) intervals[{sp[i].L, sp[i].U}] = true;
-        // slice [lo, hi) of every segment inside every interval
-        std::vector<std::pair<uint64_t, uint64_t>> slices;
-        for (auto& kv : intervals) {
-            uint64_t Lg = kv.first.first, Ug = kv.first.second;
-            for (uint32_t s = 0; s < p; ++s) {
-                uint64_t lo = 0, hi = P.seg_len(s);
-                if (Lg != NONE) lo = P.count_below(s, Lg) + (P.segment_of(Lg) == s ? 1 : 0);
-                if (Ug != NONE) hi = P.count_below(s, Ug);
-                slices.push_back({P.seg_start[s] + lo, P.seg_start[s] + std::max(lo, hi)});
-                tr.domain += hi > lo ? hi - lo : 0;
-            }
+        std::vector<std::pair<uint64_t, uint64_t>> ivl(intervals.size());
+        {
+            size_t k = 0;
+            for (auto& kv : intervals) ivl[k++] = kv.first;
         }
+        // slice [lo, hi) of every segment inside every interval, at
+        // slices[k p + s]; each processor finds the slices of its segment
+        std::vector<std::pair<uint64_t, uint64_t>> slices(ivl.size() * p);
+        std::vector<uint64_t> dom_part(threads < 1 ? 1 : threads, 0);
+        split_over(p, threads, [&](int t, uint64_t s0, uint64_t s1) {
+            for (uint64_t s = s0; s < s1; ++s) {
+                for (size_t k = 0; k < ivl.size(); ++k) {
+                    uint64_t Lg = ivl[k].first, Ug = ivl[k].second;
+                    uint64_t lo = 0, hi = P.seg_len((uint32_t)s);
+                    if (Lg != NONE) lo = P.count_below((uint32_t)s, Lg) + (P.segment_of(Lg) == s ? 1 : 0);
+                    if (Ug != NONE) hi = P.count_below((uint32_t)s, Ug);
+                    slices[k * p + s] = {P.seg_start[s] + lo, P.seg_start[s] + std::max(lo, hi)};
+                    dom_part[t] += hi > lo ? hi - lo : 0;
+                }
+            }
+        });
+        for (uint64_t d : dom_part) tr.domain += d;
 
         uint32_t thresh;
         bool all = budget ? budget_threshold(tr.domain, q, budget, &thresh)
@@ -335,10 +375,18 @@ void determine_splitters(const Problem& P, uint32_t q, double eps, uint64_t seed
 
         // Section 4.2.1: each key of the domain is taken independently with
         // the round's probability.
+        // Every processor draws for the keys of its own segment.
+        std::vector<std::vector<uint64_t>> drawn(threads < 1 ? 1 : threads);
+        split_over(p, threads, [&](int t, uint64_t s0, uint64_t s1) {
+            for (uint64_t s = s0; s < s1; ++s)
+                for (size_t k = 0; k < ivl.size(); ++k) {
+                    const auto& sl = slices[k * p + s];
+                    for (uint64_t g = sl.first; g < sl.second; ++g)
+                        if (all || philox_word(seed, g, j) < thresh) drawn[t].push_back(g);
+                }
+        });
         std::vector<uint64_t> probes;
-        for (auto& sl : slices)
-            for (uint64_t g = sl.first; g < sl.second; ++g)
-                if (all || philox_word(seed, g, j) < thresh) probes.push_back(g);
+        for (auto& d : drawn) probes.insert(probes.end(), d.begin(), d.end());
 
         // Gather and sort the probes (section 5.1), in the strict order.
         std::sort(probes.begin(), probes.end(),
@@ -346,16 +394,23 @@ void determine_splitters(const Problem& P, uint32_t q, double eps, uint64_t seed
 
         // Step 2: histogram of the probes against every segment, summed over
         // the segments (the reduction) -> global rank R(e) of each probe.
-        std::vector<uint64_t> rk(probes.size());
-        for (size_t e = 0; e < probes.size(); ++e) {
-            uint64_t r = 0;
-            for (uint32_t s = 0; s < p; ++s) {
-                uint64_t c = P.count_below(s, probes[e]);
-                if (trace_level >= 2) tr.counts.push_back((uint32_t)c);
-                r += c;
-            }
-            rk[e] = r;
-        }
+        // Every processor counts its own segment (the local histogram); the
+        // counts are then added up over the processors.
+        const size_t m = probes.size();
+        std::vector<uint64_t> rk(m, 0);
+        if (trace_level >= 2) tr.counts.assign(m * p, 0);
+        std::vector<std::vector<uint64_t>> part(threads < 1 ? 1 : threads);
+        split_over(p, threads, [&](int t, uint64_t s0, uint64_t s1) {
+            part[t].assign(m, 0);
+            for (uint64_t s = s0; s < s1; ++s)
+                for (size_t e = 0; e < m; ++e) {
+                    uint64_t c = P.count_below((uint32_t)s, probes[e]);
+                    if (trace_level >= 2) tr.counts[e * p + s] = (uint32_t)c;
+                    part[t][e] += c;
+                }
+        });
+        for (auto& pt : part)
+            for (size_t e = 0; e < pt.size(); ++e) rk[e] += pt[e];
 
         // Step 3 and step 5: for every unsettled splitter, a probe whose rank
         // lies in the target range settles it (READING: the closest to Ni/p,
@@ -418,8 +473,12 @@ void determine_splitters(const Problem& P, uint32_t q, double eps, uint64_t seed
         R.chi[i] = sp[i].chi;
         R.S_tag[i] = sp[i].S;
         R.S_key[i] = P.key[sp[i].S];
-        for (uint32_t s = 0; s < p; ++s) R.pieces[(size_t)i * p + s] = P.count_below(s, sp[i].S);
     }
+    split_over(p, threads, [&](int, uint64_t s0, uint64_t s1) {
+        for (uint64_t s = s0; s < s1; ++s)
+            for (uint32_t i = 1; i < q; ++i)
+                R.pieces[(size_t)i * p + s] = P.count_below((uint32_t)s, sp[i].S);
+    });
 }
 
 }  // namespace
@@ -436,52 +495,84 @@ oracle_run* oracle_hss(uint64_t n, uint32_t p, uint32_t q, double eps, int key_b
                        const void* keys_in, const uint64_t* vals_in, uint64_t seed,
                        int mode, uint32_t k_override, uint32_t max_rounds, int force_full,
                        uint32_t probes_per_round, int trace_level, void* keys_out,
-                       uint64_t* vals_out, uint64_t* offsets_out) {
+                       uint64_t* vals_out, uint64_t* offsets_out, int threads) {
     Run* R = new Run();
     if (q == 0) q = p;
     if (!valid_params(n, p, eps, key_bits) || q > p || !keys_in || !keys_out || !offsets_out) {
         R->status = -1;
         return (oracle_run*)R;
     }
+    auto t0 = std::chrono::steady_clock::now();
     Problem P;
-    load_and_local_sort(P, n, p, key_bits, keys_in, vals_in);
+    load_and_local_sort(P, n, p, key_bits, keys_in, vals_in, threads);
+    R->t_local = seconds_since(t0);
+    t0 = std::chrono::steady_clock::now();
     determine_splitters(P, q, eps, seed, k_override, max_rounds, force_full, probes_per_round,
-                        trace_level, *R);
+                        trace_level, threads, *R);
+    R->t_rounds = seconds_since(t0);
     if (R->status != 0) return (oracle_run*)R;
 
     // Data exchange (section 3.1 step 3): bucket b gathers, from every
-    // segment in turn, the keys ranked in [chi(b), chi(b+1)).
+    // segment in turn, the keys ranked in [chi(b), chi(b+1)).  Every
+    // destination processor receives its own bucket.
+    t0 = std::chrono::steady_clock::now();
     std::vector<uint64_t> ok(n), ov(n);
-    uint64_t o = 0;
-    for (uint32_t b = 0; b < q; ++b) {
-        for (uint32_t s = 0; s < p; ++s) {
-            uint64_t from = P.seg_start[s] + R->pieces[(size_t)b * p + s];
-            uint64_t to = P.seg_start[s] + R->pieces[(size_t)(b + 1) * p + s];
-            for (uint64_t g = from; g < to; ++g) { ok[o] = P.key[g]; ov[o] = P.val[g]; ++o; }
+    std::vector<int> bad(q, 0);
+    split_over(q, threads, [&](int, uint64_t b0, uint64_t b1) {
+        for (uint64_t b = b0; b < b1; ++b) {
+            uint64_t total = 0;
+            for (uint32_t s = 0; s < p; ++s)
+                total += R->pieces[(size_t)(b + 1) * p + s] - R->pieces[(size_t)b * p + s];
+            if (total != R->chi[b + 1] - R->chi[b]) { bad[b] = 1; continue; }
+            uint64_t o = R->chi[b];
+            for (uint32_t s = 0; s < p; ++s) {
+                uint64_t from = P.seg_start[s] + R->pieces[(size_t)b * p + s];
+                uint64_t to = P.seg_start[s] + R->pieces[(size_t)(b + 1) * p + s];
+                for (uint64_t g = from; g < to; ++g) { ok[o] = P.key[g]; ov[o] = P.val[g]; ++o; }
+            }
         }
-        if (o != R->chi[b + 1]) { R->status = -4; return (oracle_run*)R; }
-    }
-    // Local merge after the exchange (section 5): a stable sort of the bucket.
+    });
+    for (int x : bad)
+        if (x) { R->status = -4; return (oracle_run*)R; }
+    R->t_exchange = seconds_since(t0);
+    // Local merge after the exchange (section 5): a stable sort of the bucket,
+    // by every destination processor.
+    t0 = std::chrono::steady_clock::now();
     if (mode == 1) {
-        for (uint32_t b = 0; b < q; ++b) {
-            uint64_t lo = R->chi[b], hi = R->chi[b + 1];
-            std::vector<uint64_t> idx(hi - lo);
-            std::iota(idx.begin(), idx.end(), lo);
-            std::stable_sort(idx.begin(), idx.end(),
-                             [&](uint64_t x, uint64_t y) { return ok[x] < ok[y]; });
-            std::vector<uint64_t> k2(hi - lo), v2(hi - lo);
-            for (uint64_t t = 0; t < hi - lo; ++t) { k2[t] = ok[idx[t]]; v2[t] = ov[idx[t]]; }
-            std::copy(k2.begin(), k2.end(), ok.begin() + lo);
-            std::copy(v2.begin(), v2.end(), ov.begin() + lo);
+        split_over(q, threads, [&](int, uint64_t b0, uint64_t b1) {
+            for (uint64_t b = b0; b < b1; ++b) {
+                uint64_t lo = R->chi[b], hi = R->chi[b + 1];
+                std::vector<uint64_t> idx(hi - lo);
+                std::iota(idx.begin(), idx.end(), lo);
+                std::stable_sort(idx.begin(), idx.end(),
+                                 [&](uint64_t x, uint64_t y) { return ok[x] < ok[y]; });
+                std::vector<uint64_t> k2(hi - lo), v2(hi - lo);
+                for (uint64_t t = 0; t < hi - lo; ++t) { k2[t] = ok[idx[t]]; v2[t] = ov[idx[t]]; }
+                std::copy(k2.begin(), k2.end(), ok.begin() + lo);
+                std::copy(v2.begin(), v2.end(), ov.begin() + lo);
+            }
+        });
+    }
+    R->t_final = seconds_since(t0);
+    split_over(q, threads, [&](int, uint64_t b0, uint64_t b1) {
+        for (uint64_t i = R->chi[b0]; i < R->chi[b1]; ++i) {
+            if (key_bits == 32) ((uint32_t*)keys_out)[i] = (uint32_t)ok[i];
+            else ((uint64_t*)keys_out)[i] = ok[i];
+            if (vals_out) vals_out[i] = ov[i];
         }
-    }
-    for (uint64_t i = 0; i < n; ++i) {
-        if (key_bits == 32) ((uint32_t*)keys_out)[i] = (uint32_t)ok[i];
-        else ((uint64_t*)keys_out)[i] = ok[i];
-        if (vals_out) vals_out[i] = ov[i];
-    }
+    });
     for (uint32_t b = 0; b <= q; ++b) offsets_out[b] = R->chi[b];
     return (oracle_run*)R;
+}
+
+// Seconds spent per stage by the run: local sort, splitter rounds, exchange,
+// bucket sort (mode 1; 0 otherwise).
+void oracle_times(const oracle_run* h, double* out) {
+    const Run* R = (const Run*)h;
+    out[0] = R->t_local;
+    out[1] = R->t_rounds;
+    out[2] = R->t_exchange;
+    out[3] = R->t_final;
 }
 
 // Local sort alone (section 6 phase 1).  Pinned: numpy's stable sort.
@@ -489,7 +580,7 @@ int oracle_local_sort(uint64_t n, uint32_t p, int key_bits, const void* keys_in,
                       const uint64_t* vals_in, void* keys_out, uint64_t* vals_out) {
     if (n == 0 || p == 0 || (uint64_t)p > n || (key_bits != 32 && key_bits != 64)) return -1;
     Problem P;
-    load_and_local_sort(P, n, p, key_bits, keys_in, vals_in);
+    load_and_local_sort(P, n, p, key_bits, keys_in, vals_in, 1);
     for (uint64_t i = 0; i < n; ++i) {
         if (key_bits == 32) ((uint32_t*)keys_out)[i] = (uint32_t)P.key[i];
         else ((uint64_t*)keys_out)[i] = P.key[i];

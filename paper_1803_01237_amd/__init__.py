@@ -40,7 +40,8 @@ NONE = (1 << 64) - 1
 EXPORTS = [
     "hss_plan", "hss_plan_destroy", "hss_workspace_bytes", "hss_partition", "hss_sort",
     "hss_local_sort", "hss_get_constants", "hss_trace_rounds", "hss_trace_round_info",
-    "hss_trace_round_probes", "hss_trace_round_state", "hss_trace_splitters",
+    "hss_trace_round_probes", "hss_trace_round_counts", "hss_trace_round_state",
+    "hss_trace_splitters",
     "hss_profile", "hss_profile_reset", "hss_profile_read",
     "hss_batch_plan", "hss_batch_destroy", "hss_batch_workspace_bytes", "hss_batch_partition",
     "hss_batch_profile", "hss_batch_profile_reset", "hss_batch_profile_read",
@@ -113,6 +114,8 @@ _lib.hss_trace_round_info.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp]
 _lib.hss_trace_round_info.restype = C.c_int
 _lib.hss_trace_round_probes.argtypes = [_vp, _u32, _vp, _vp, _vp]
 _lib.hss_trace_round_probes.restype = C.c_int
+_lib.hss_trace_round_counts.argtypes = [_vp, _u32, _vp]
+_lib.hss_trace_round_counts.restype = C.c_int
 _lib.hss_trace_round_state.argtypes = [_vp, _u32, _vp, _vp, _vp, _vp]
 _lib.hss_trace_round_state.restype = C.c_int
 _lib.hss_trace_splitters.argtypes = [_vp, _vp, _vp, _vp, _vp]
@@ -227,6 +230,7 @@ class RoundTrace:
     probe_key: np.ndarray | None = None
     probe_tag: np.ndarray | None = None
     probe_rank: np.ndarray | None = None
+    counts: np.ndarray | None = None     # (m, p): c_s(e), trace level 2
     lo_rank: np.ndarray | None = None
     hi_rank: np.ndarray | None = None
     settled: np.ndarray | None = None
@@ -366,6 +370,11 @@ class Plan:
                 _check(_lib.hss_trace_round_probes(self._h, j, _np_ptr(r.probe_key),
                                                    _np_ptr(r.probe_tag), _np_ptr(r.probe_rank)),
                        "hss_trace_round_probes")
+                if self.trace_level >= 2:
+                    cnt = np.zeros(r.m * self.p, dtype=np.uint32)
+                    _check(_lib.hss_trace_round_counts(self._h, j, _np_ptr(cnt)),
+                           "hss_trace_round_counts")
+                    r.counts = cnt.reshape(r.m, self.p)
                 q = self.q - 1
                 r.lo_rank = np.zeros(q, dtype=np.uint64)
                 r.hi_rank = np.zeros(q, dtype=np.uint64)

@@ -95,6 +95,7 @@ struct RoundRecord {
     std::vector<uint64_t> key, tag, rank;
     std::vector<uint64_t> lo, hi, chi;
     std::vector<uint8_t> settled;
+    std::vector<uint32_t> counts;   // trace level 2: c_s(e) at [e p + s]
 };
 
 // Sub-allocation of one device arena.
@@ -973,6 +974,15 @@ hss_status launch_first_rounds(Engine& E, uint32_t n, hipStream_t s) {
     return HSS_OK;
 }
 
+// The count matrix of a one-instance round as the trace reports it: c_s(e)
+// at [e p + s] (the device keeps it segment-major, c_s(e) at [s m + e]).
+std::vector<uint32_t> counts_probe_major(const std::vector<uint32_t>& cm, uint64_t m, uint64_t p) {
+    std::vector<uint32_t> out(m * p);
+    for (uint64_t s = 0; s < p; ++s)
+        for (uint64_t e = 0; e < m; ++e) out[e * p + s] = cm[s * m + e];
+    return out;
+}
+
 // Splitter rounds of every instance on the locally sorted buffer B; leaves
 // chi in chi_all and in every instance's offsets.
 hss_status determine_splitters(Engine& E, hipStream_t s) {
@@ -1037,7 +1047,11 @@ hss_status determine_splitters(Engine& E, hipStream_t s) {
                 if ((st = d2h(rec.hi, r.urank + 1, q, s)) != HSS_OK) return st;
                 if ((st = d2h(rec.chi, r.chi + 1, q, s)) != HSS_OK) return st;
                 if ((st = d2h(settled, r.settled + 1, q, s)) != HSS_OK) return st;
+                std::vector<uint32_t> cm;
+                const uint64_t p = E.ih[0].p;
+                if (E.tune.trace_level >= 2 && (st = d2h(cm, E.cmat, m * p, s)) != HSS_OK) return st;
                 HIP_TRY(hipStreamSynchronize(s));
+                if (E.tune.trace_level >= 2) rec.counts = counts_probe_major(cm, m, p);
                 rec.settled.resize(q);
                 for (uint32_t i = 0; i < q; ++i) {
                     rec.settled[i] = settled[i] ? 1 : 0;
@@ -1639,6 +1653,14 @@ hss_status hss_trace_round_probes(hss_plan_t P, uint32_t j, uint64_t* keys, uint
     if (keys) std::memcpy(keys, r.key.data(), r.m * 8);
     if (tags) std::memcpy(tags, r.tag.data(), r.m * 8);
     if (ranks) std::memcpy(ranks, r.rank.data(), r.m * 8);
+    return HSS_OK;
+}
+
+hss_status hss_trace_round_counts(hss_plan_t P, uint32_t j, uint32_t* counts) {
+    if (!P || j >= P->e.trace.size()) return fail(HSS_ERR_INVALID_ARG, "no such round");
+    const RoundRecord& r = P->e.trace[j];
+    if (r.counts.size() != r.m * P->e.ih[0].p) return fail(HSS_ERR_INVALID_ARG, "round counts need trace_level >= 2");
+    if (counts && !r.counts.empty()) std::memcpy(counts, r.counts.data(), r.counts.size() * 4);
     return HSS_OK;
 }
 

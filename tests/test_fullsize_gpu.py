@@ -1,20 +1,29 @@
-"""Full-size GPU checks at 2^28 keys, in the launch configuration bench.py times.
+"""Full-size GPU parity at 2^28 keys, in the launch configuration bench.py times.
 
-The oracle cannot run these sizes in test time, so the outputs are checked by
-properties that hold at any size (a permutation of the input, bucket order,
-piece order, balance) and sampled splitters are recomputed one by one from
-their definition: chi(i) is the rank of the splitter element S(i) in the order
-(key, tag) of sections 2 and 6.1, counted segment by segment on the host.
+The uniform configuration (2^28 u64 keys, p = 1024, eps = 0.02) and the
+Zipf-Morton configuration with a payload (2^28 u64 keys + u64 source index,
+p = 4096, eps = 0.05) are compared with the CPU oracle bit for bit: outputs
+and offsets of hss_partition and hss_sort, the splitters (chi, S keys and
+tags), the piece matrix, and every round's domain, probe keys, tags and
+ranks, local histograms c_s(e) and splitter state.  The oracle runs its
+per-segment work on up to 16 host threads (its result does not depend on
+the thread count).  The largest accepted size (2^32 - 1 u32 keys), which the
+oracle cannot hold in host memory, is checked by properties that hold at any
+size.
 """
+import os
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 import synth
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
+
+ORACLE_THREADS = max(1, min(16, os.cpu_count() or 1))
 
 
 def _say(msg):
@@ -38,23 +47,6 @@ def _host(t):
     return t.cpu().numpy().view(np.uint64)
 
 
-def _mix(a):
-    """splitmix64 finaliser of every key (wrapping uint64 arithmetic)."""
-    with np.errstate(over="ignore"):
-        z = a + np.uint64(0x9E3779B97F4A7C15)
-        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
-        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
-        return z ^ (z >> np.uint64(31))
-
-
-def _multiset_digest(a):
-    """Order-independent digest: wrapping sums of the keys and of a mixing hash, and xor."""
-    with np.errstate(over="ignore"):
-        h = _mix(a)
-        return (int(a.sum(dtype=np.uint64)), int(h.sum(dtype=np.uint64)),
-                int(np.bitwise_xor.reduce(h)), len(a))
-
-
 def _check_offsets(off, n, p, tol):
     ideal = (np.arange(p + 1, dtype=np.uint64) * np.uint64(n)) // np.uint64(p)
     assert off[0] == 0 and off[p] == n
@@ -63,119 +55,87 @@ def _check_offsets(off, n, p, tol):
     assert int(dev.max()) <= tol, int(dev.max())
 
 
-def _check_sampled_splitters(keys, p, chi, s_key, s_tag, which):
-    """chi(i) = #{(k, g) < (s_key, s_tag)}: keys below s_key in every segment,
-    plus the equal keys whose tag (local stable position) is below s_tag."""
-    n = len(keys)
-    ns = n // p
-    seg = keys.reshape(p, ns)
-    base = np.arange(p, dtype=np.int64) * ns
-    for i in which:
-        k, g = np.uint64(s_key[i]), int(s_tag[i])
-        lt = (seg < k).sum(axis=1).astype(np.int64)
-        eq = (seg == k).sum(axis=1).astype(np.int64)
-        first_eq_tag = base + lt
-        below = np.clip(g - first_eq_tag, 0, eq)
-        rank = int(lt.sum() + below.sum())
-        assert rank == int(chi[i]), (i, rank, int(chi[i]))
-        # S(i) is the element with tag g: the x-th smallest of its segment
-        t, x = g // ns, g % ns
-        assert np.partition(seg[t], x)[x] == k, i
+def _compare_full(plan, ref, p, tag):
+    """Every round of the trace (level 2) and the splitters, exactly."""
+    tr = plan.trace()
+    assert len(tr) == len(ref.rounds), (len(tr), len(ref.rounds))
+    for j, (a, b) in enumerate(zip(tr, ref.rounds)):
+        _say(f"[fullsize] {tag}: round {j + 1}: domain {a.domain} probes {a.m}")
+        assert (a.domain, a.m, a.thresh, a.all) == (b.domain, b.m, b.thresh, b.all), j
+        for f in ("probe_key", "probe_tag", "probe_rank", "counts", "settled", "chi",
+                  "lo_rank", "hi_rank"):
+            assert np.array_equal(getattr(a, f), getattr(b, f)), (j, f)
+    del tr
+    chi, sk, stg, pieces = plan.splitters()
+    assert np.array_equal(chi, ref.chi)
+    assert np.array_equal(sk[1:p], ref.s_key[1:p])
+    assert np.array_equal(stg[1:p], ref.s_tag[1:p])
+    assert np.array_equal(pieces, ref.pieces)
 
 
-def _bucket_bounds_keys_only(out, off):
-    """Every key of bucket b is <= every key of bucket b+1."""
-    starts = off[:-1].astype(np.int64)
-    ends = off[1:].astype(np.int64)
-    nz = ends > starts
-    mx = np.maximum.reduceat(out, starts[nz])
-    mn = np.minimum.reduceat(out, starts[nz])
-    assert np.all(mx[:-1] <= mn[1:])
-
-
-def test_partition_and_sort_uniform_2p28_p1024(hss):
-    n, p, eps, dseed, hseed = 1 << 28, 1024, 0.02, 2, 2
-    _say(f"[fullsize] uniform u64 n={n} p={p} eps={eps} seed={hseed}: generating")
-    keys = synth.make("uniform64", n, dseed)
-    digest_in = _multiset_digest(keys)
+def _full_parity(hss, name, kind, n, p, eps, dseed, hseed, payload):
+    """The plan bench.py times (default tuning: graph-replayed rounds, draws
+    taken ahead) against the oracle's outputs and splitters; a second plan
+    with trace level 2 (rounds read back one by one) against the oracle's
+    whole round trace."""
+    _say(f"[fullsize] {name}: {kind} u64 n={n} p={p} eps={eps} seeds={dseed}/{hseed} "
+         f"payload={payload}: generating")
+    keys = synth.make(kind, n, dseed)
+    vals = np.arange(n, dtype=np.uint64) if payload else None
     kd = _dev(keys)
-    with hss.Plan(n, p, eps) as plan:
+    vd = None if vals is None else _dev(vals)
+    _say(f"[fullsize] {name}: oracle partition on {ORACLE_THREADS} host threads")
+    ref = oracle.hss(keys, p, eps, hseed, vals=vals, mode="partition", trace_level=2,
+                     threads=ORACLE_THREADS)
+    assert ref.status == 0
+    _say(f"[fullsize] {name}: oracle stages (s): {ref.times}")
+    with hss.Plan(n, p, eps, payload=payload) as plan:
         tol = plan.constants(1)[0]
-        _say("[fullsize] uniform: hss_partition")
-        ko, _, off = plan.partition(kd, hseed)
-        out, offs = _host(ko), _host(off)
-        _check_offsets(offs, n, p, tol)
-        assert _multiset_digest(out) == digest_in
-        _bucket_bounds_keys_only(out, offs)
-        chi, s_key, s_tag, _ = plan.splitters()
-        assert np.array_equal(chi, offs)
-        rng = np.random.default_rng(0)
-        which = sorted(set(rng.integers(1, p, size=12).tolist()) | {1, p // 2, p - 1})
-        _say(f"[fullsize] uniform: {len(which)} sampled splitters from their definition")
-        _check_sampled_splitters(keys, p, chi, s_key, s_tag, which)
-        del out
-        _say("[fullsize] uniform: hss_sort")
-        ks, _, off2 = plan.sort(kd, hseed)
-        srt = _host(ks)
-        assert np.all(srt[1:] >= srt[:-1])
-        assert _multiset_digest(srt) == digest_in
-        assert np.array_equal(_host(off2), offs)
-
-
-def test_partition_and_sort_zipf_morton_payload_2p28_p4096(hss):
-    n, p, eps, dseed, hseed = 1 << 28, 4096, 0.05, 3, 3
-    _say(f"[fullsize] zipf+morton u64+payload n={n} p={p} eps={eps} seed={hseed}: generating")
-    keys = synth.make("zipf_morton", n, dseed)
-    vals = np.arange(n, dtype=np.uint64)
-    ns = n // p
-    kd, vd = _dev(keys), _dev(vals)
-    with hss.Plan(n, p, eps, payload=True) as plan:
-        tol = plan.constants(1)[0]
-        _say("[fullsize] zipf+morton: hss_partition")
+        _say(f"[fullsize] {name}: hss_partition on the GPU")
         ko, vo, off = plan.partition(kd, hseed, vd)
-        out, ov, offs = _host(ko), _host(vo), _host(off)
+        offs = _host(off)
         _check_offsets(offs, n, p, tol)
-        # the payload (source index) names a permutation carrying its key
-        seen = np.zeros(n, dtype=np.uint8)
-        seen[ov.astype(np.int64)] = 1
-        assert int(seen.sum()) == n
-        del seen
-        assert np.array_equal(keys[ov.astype(np.int64)], out)
-        # inside a bucket: pieces by ascending source segment, each in (key,
-        # source index) order; between buckets: (key, source index) order
-        src_seg = ov // np.uint64(ns)
-        start = np.zeros(n, dtype=bool)
-        start[offs[:-1][offs[:-1] < n].astype(np.int64)] = True
-        step_seg = src_seg[1:].astype(np.int64) - src_seg[:-1].astype(np.int64)
-        assert np.all((step_seg >= 0) | start[1:])
-        same = (step_seg == 0) & ~start[1:]
-        inc = (out[1:] > out[:-1]) | ((out[1:] == out[:-1]) & (ov[1:] > ov[:-1]))
-        assert np.all(inc | ~same)
-        del src_seg, step_seg, same, inc, start
-        _say("[fullsize] zipf+morton: bucket order")
-        for b in range(p - 1):
-            a0, a1, a2 = int(offs[b]), int(offs[b + 1]), int(offs[b + 2])
-            if a0 == a1 or a1 == a2:
-                continue
-            kb, vb = out[a0:a1], ov[a0:a1]
-            kc, vc = out[a1:a2], ov[a1:a2]
-            mxk, mnk = kb.max(), kc.min()
-            assert mxk <= mnk, b
-            if mxk == mnk:
-                assert vb[kb == mxk].max() < vc[kc == mnk].min(), b
-        chi, s_key, s_tag, _ = plan.splitters()
-        assert np.array_equal(chi, offs)
-        rng = np.random.default_rng(1)
-        which = sorted(set(rng.integers(1, p, size=12).tolist()) | {1, p // 2, p - 1})
-        _say(f"[fullsize] zipf+morton: {len(which)} sampled splitters from their definition")
-        _check_sampled_splitters(keys, p, chi, s_key, s_tag, which)
-        del out, ov
-        _say("[fullsize] zipf+morton: hss_sort")
+        assert np.array_equal(offs, ref.offsets)
+        assert np.array_equal(_host(ko), ref.keys)
+        if payload:
+            assert np.array_equal(_host(vo), ref.vals)
+        del ko, vo
+        chi, sk, stg, pieces = plan.splitters()
+        assert np.array_equal(chi, ref.chi)
+        assert np.array_equal(sk[1:p], ref.s_key[1:p])
+        assert np.array_equal(stg[1:p], ref.s_tag[1:p])
+        assert np.array_equal(pieces, ref.pieces)
+        _say(f"[fullsize] {name}: hss_sort on the GPU")
         ks, vs, off2 = plan.sort(kd, hseed, vd)
-        srt, sv = _host(ks), _host(vs)
-        assert np.array_equal(keys[sv.astype(np.int64)], srt)
-        assert np.all((srt[1:] > srt[:-1]) | ((srt[1:] == srt[:-1]) & (sv[1:] > sv[:-1])))
-        assert np.array_equal(_host(off2), offs)
+        srt = _host(ks)
+        sv = None if vs is None else _host(vs)
+        assert np.array_equal(_host(off2), ref.offsets)
+        del ks, vs
+    with hss.Plan(n, p, eps, payload=payload, trace_level=2) as plan:
+        _say(f"[fullsize] {name}: hss_partition with the round trace")
+        ko, vo, off = plan.partition(kd, hseed, vd)
+        assert np.array_equal(_host(off), ref.offsets)
+        assert np.array_equal(_host(ko), ref.keys)
+        del ko, vo
+        _compare_full(plan, ref, p, name)
+    del ref
+    _say(f"[fullsize] {name}: oracle sort")
+    ref = oracle.hss(keys, p, eps, hseed, vals=vals, mode="sort", trace_level=0,
+                     threads=ORACLE_THREADS)
+    assert ref.status == 0
+    assert np.array_equal(srt, ref.keys)
+    if payload:
+        assert np.array_equal(sv, ref.vals)
+
+
+@pytest.mark.timeout(1200)
+def test_uniform_2p28_p1024_bit_exact(hss):
+    _full_parity(hss, "uniform", "uniform64", 1 << 28, 1024, 0.02, 2, 2, False)
+
+
+@pytest.mark.timeout(1200)
+def test_zipf_morton_payload_2p28_p4096_bit_exact(hss):
+    _full_parity(hss, "zipf+morton", "zipf_morton", 1 << 28, 4096, 0.05, 3, 3, True)
 
 
 def _device_digest(x, chunk=1 << 28):

@@ -598,3 +598,45 @@ def test_two_stage_invalid_group_counts():
     keys = synth.make("uniform64", 1000, 1)
     assert oracle.hss_two_stage(keys, 16, 3, 0.05, 0.05, 1).status == -1
     assert oracle.hss_two_stage(keys, 16, 0, 0.05, 0.05, 1).status == -1
+
+
+# --------------------------------------------------------------- threads ----
+
+THREAD_CASES = [
+    # kind, n, p, q, eps, seed, bits, payload, mode, budget
+    ("uniform64", 60_000, 37, None, 0.02, 2, 64, True, "partition", 0),
+    ("SKEW2", 20_000, 32, None, 0.05, 5, 64, True, "sort", 0),
+    ("zipf_morton", 40_000, 128, None, 0.05, 9, 64, True, "partition", 0),
+    ("uniform32", 30_001, 64, 8, 0.1, 3, 32, False, "sort", 0),
+    ("uniform64", 50_000, 50, None, 0.05, 4, 64, False, "partition", 5),
+    ("uniform64", 300, 300, None, 0.5, 11, 64, True, "partition", 0),
+]
+
+
+@pytest.mark.parametrize("case", THREAD_CASES, ids=[f"{c[0]}-{c[1]}-{c[2]}-{c[8]}" for c in THREAD_CASES])
+def test_threads_do_not_change_the_result(case):
+    """The per-segment and per-bucket work split over host threads gives the
+    run of one thread, field by field (outputs, splitters, pieces and every
+    round's probes, ranks, local histograms and splitter state)."""
+    kind, n, p, q, eps, seed, bits, payload, mode, budget = case
+    keys = synth.make(kind, n, seed)
+    if bits == 32:
+        keys = keys.astype(np.uint32)
+    vals = np.arange(n, dtype=np.uint64) if payload else None
+    one = oracle.hss(keys, p, eps, seed, vals=vals, mode=mode, trace_level=2, buckets=q,
+                     probes_per_round=budget, threads=1)
+    assert one.status == 0
+    for t in (3, 8):
+        many = oracle.hss(keys, p, eps, seed, vals=vals, mode=mode, trace_level=2, buckets=q,
+                          probes_per_round=budget, threads=t)
+        assert many.status == 0
+        for f in ("keys", "vals", "offsets", "chi", "s_key", "s_tag", "pieces"):
+            a, b = getattr(one, f), getattr(many, f)
+            assert (a is None and b is None) or np.array_equal(a, b), f
+        assert len(one.rounds) == len(many.rounds)
+        for ra, rb in zip(one.rounds, many.rounds):
+            assert (ra.domain, ra.m, ra.thresh, ra.all) == (rb.domain, rb.m, rb.thresh, rb.all)
+            for f in ("probe_key", "probe_tag", "probe_rank", "counts", "lo_rank", "hi_rank",
+                      "settled", "chi"):
+                assert np.array_equal(getattr(ra, f), getattr(rb, f)), f
+    assert all(x >= 0 for x in one.times) and one.times[0] > 0

@@ -6,6 +6,7 @@ round), the splitters, the piece matrix and the outputs.  Full-size cases
 (2^28 keys) check the outputs by properties that hold at any size and
 compare sampled splitters with their definition.
 """
+import os
 import sys
 
 import numpy as np
@@ -17,6 +18,8 @@ from tests import refcheck as R
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
+
+ORACLE_THREADS = max(1, min(16, os.cpu_count() or 1))
 
 
 def _say(msg):
@@ -72,6 +75,9 @@ CASES = [
     ("uniform64", 1, 1, 0.5, 15, 64, True),              # a single key
     ("uniform64", 4097, 4096, 0.9, 16, 64, False),       # many tiny segments
     ("uniform32", 1 << 21, 64, 0.02, 17, 32, True),      # first draws taken ahead, u32
+    # p = 4096 on clustered keys with a payload: 4096-key segments, duplicates
+    # across hundreds of buckets, per-cell tables of 4097 x 4096 words
+    ("zipf_morton", 1 << 24, 4096, 0.05, 18, 64, True),
 ]
 
 
@@ -83,6 +89,8 @@ def _compare_trace(plan, ref, p):
         assert np.array_equal(a.probe_key, b.probe_key), j
         assert np.array_equal(a.probe_tag, b.probe_tag), j
         assert np.array_equal(a.probe_rank, b.probe_rank), j
+        if a.counts is not None or b.counts is not None:
+            assert np.array_equal(a.counts, b.counts), j
         assert np.array_equal(a.settled, b.settled), j
         assert np.array_equal(a.chi, b.chi), j
         assert np.array_equal(a.lo_rank, b.lo_rank), j
@@ -98,7 +106,7 @@ def test_partition_and_sort_match_oracle(hss, case):
     kd = _dev(keys)
     vd = None if vals is None else _dev(vals)
     kt = keys.dtype
-    with hss.Plan(n, p, eps, key_bytes=keys.itemsize, payload=payload, trace_level=1) as plan:
+    with hss.Plan(n, p, eps, key_bytes=keys.itemsize, payload=payload, trace_level=2) as plan:
         # constants
         tol, k, a, th, al = plan.constants(40)
         oc = oracle.constants(n, p, eps, max_j=40)
@@ -112,7 +120,8 @@ def test_partition_and_sort_match_oracle(hss, case):
             assert np.array_equal(_host(lv, np.uint64), ov_)
         # partition
         ko, vo, off = plan.partition(kd, seed, vd)
-        ref = oracle.hss(keys, p, eps, seed, vals=vals, mode="partition")
+        ref = oracle.hss(keys, p, eps, seed, vals=vals, mode="partition", trace_level=2,
+                         threads=ORACLE_THREADS)
         assert ref.status == 0
         assert np.array_equal(_host(off, np.uint64), ref.offsets)
         assert np.array_equal(_host(ko, kt), ref.keys)
