@@ -159,6 +159,44 @@ hss_status hss_sort(hss_plan_t plan, uint64_t seed, const void* d_keys_in,
                     uint64_t* d_offsets, void* stream);
 
 /*
+ * hss_partition_static -- hss_partition for callers that cannot allocate
+ * device memory: code that runs under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  There is no plan: the call takes the
+ * shape (n, p, eps, key type; a payload iff d_vals_in is given) and its
+ * workspace is one fixed device array of the library,
+ * HSS_STATIC_SCRATCH_MIB MiB per device, reserved when the library's code
+ * is loaded on that device and held until the process ends.  The call
+ * allocates no device or pinned host memory (its read-backs go through a
+ * static host buffer); it launches on `stream` only (no side stream, no
+ * graph) and returns after its work has completed, like hss_partition.
+ * Outputs and offsets are exactly those of hss_partition on a plan of the
+ * same shape for the same seed and input.
+ *   Limits: n <= HSS_STATIC_MAX_KEYS and p <= HSS_STATIC_MAX_BUCKETS, and
+ *   the shape's workspace (hss_partition_static_bytes) must fit the array;
+ *   otherwise HSS_ERR_UNSUPPORTED with a message.  A round whose sample
+ *   overruns the probe buffers that fit the array returns
+ *   HSS_ERR_OUT_OF_MEMORY.
+ *   Every call on a device uses that device's one array and leaves its last
+ *   contents there (the kernels clear what they need).  The library runs such
+ *   calls one at a time (a mutex), and each returns after its work has
+ *   completed, so two calls never use the array at once; a caller that
+ *   issued device work touching the array by other means would race with it.
+ */
+#define HSS_STATIC_SCRATCH_MIB 96u
+#define HSS_STATIC_MAX_KEYS (1u << 20)
+#define HSS_STATIC_MAX_BUCKETS 256u
+
+hss_status hss_partition_static(uint64_t n, uint32_t p, double eps, hss_key_type kt, uint64_t seed,
+                                const void* d_keys_in, const uint64_t* d_vals_in, void* d_keys_out,
+                                uint64_t* d_vals_out, uint64_t* d_offsets, void* stream);
+
+/* Bytes of the fixed array a hss_partition_static call of this shape takes,
+ * and the array's size; computed on the host (no device call).  Returns the
+ * status hss_partition_static would give for the shape. */
+hss_status hss_partition_static_bytes(uint64_t n, uint32_t p, double eps, hss_key_type kt,
+                                      int with_payload, size_t* bytes, size_t* capacity);
+
+/*
  * hss_local_sort -- only the first phase (section 6, local sort): every
  * segment sorted stably by key, payload moved with its key.  The output
  * position of an element is its tag g.

@@ -49,7 +49,8 @@ EXPORTS = [
     "hss_server_wait", "hss_server_clock", "hss_server_stats", "hss_server_footprint",
     "hss_plan_knobs", "hss_plan_set_knobs", "hss_batch_knobs", "hss_plan_buckets",
     "hss_staged_plan", "hss_staged_destroy", "hss_staged_workspace_bytes", "hss_staged_partition",
-    "hss_staged_times", "hss_status_string", "hss_last_error",
+    "hss_staged_times", "hss_partition_static", "hss_partition_static_bytes",
+    "hss_status_string", "hss_last_error",
 ]
 
 PROFILE_FAMILIES = ["radix_count", "radix_scan", "radix_scatter", "rounds",
@@ -698,6 +699,48 @@ def sort(keys, p: int, eps: float, seed: int, vals=None, **tuning):
     """Stable sort of `keys` through HSS; returns (keys_out, vals_out, offsets)."""
     with _plan_for(keys, p, eps, vals, tuning) as plan:
         return plan.sort(keys, seed, vals)
+
+
+_lib.hss_partition_static.argtypes = [_u64, _u32, C.c_double, C.c_int, _u64, _vp, _vp, _vp, _vp,
+                                      _vp, _vp]
+_lib.hss_partition_static.restype = C.c_int
+_lib.hss_partition_static_bytes.argtypes = [_u64, _u32, C.c_double, C.c_int, C.c_int, _vp, _vp]
+_lib.hss_partition_static_bytes.restype = C.c_int
+
+
+def partition_static(keys, p: int, eps: float, seed: int, vals=None, keys_out=None,
+                     vals_out=None, offsets=None):
+    """hss_partition_static: the partition of hss_partition with the library's
+    fixed device workspace (no device allocation by the library); outputs
+    are allocated here unless given.  Returns (keys_out, vals_out, offsets)."""
+    torch = _torch()
+    if not keys.is_cuda or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous device tensor")
+    if vals is not None and (vals.numel() != keys.numel() or vals.element_size() != 8
+                             or not vals.is_contiguous() or not vals.is_cuda):
+        raise ValueError("payload must be a contiguous device tensor of N 8-byte words")
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+    if vals is not None and vals_out is None:
+        vals_out = torch.empty_like(vals)
+    if offsets is None:
+        offsets = torch.empty(p + 1, dtype=torch.int64, device=keys.device)
+    st = _lib.hss_partition_static(keys.numel(), p, eps, _key_type(keys), seed & NONE,
+                                   keys.data_ptr(), None if vals is None else vals.data_ptr(),
+                                   keys_out.data_ptr(),
+                                   None if vals_out is None else vals_out.data_ptr(),
+                                   offsets.data_ptr(), _stream_handle())
+    _check(st, "hss_partition_static")
+    return keys_out, vals_out, offsets
+
+
+def static_workspace_bytes(n: int, p: int, eps: float, key_bytes: int = 8,
+                           payload: bool = False):
+    """(status, bytes of the fixed workspace a call of this shape takes, its size)."""
+    b, c = C.c_size_t(), C.c_size_t()
+    st = _lib.hss_partition_static_bytes(n, p, eps, HSS_U64 if key_bytes == 8 else HSS_U32,
+                                         1 if payload else 0, C.byref(b), C.byref(c))
+    return int(st), int(b.value), int(c.value)
 
 
 def exported_symbols():

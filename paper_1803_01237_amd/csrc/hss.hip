@@ -276,6 +276,9 @@ struct Engine {
     // server engine runs on (null: plans and batches, any stream)
     MemSource* mem = nullptr;
     hipStream_t own_stream = nullptr;
+    // the workspace is one fixed region (the static scratch array): no side
+    // stream, no captured graph, probe buffers sized once with headroom
+    bool fixed_mem = false;
 
     // the first rounds of a call as a captured graph, for the probe and
     // count-matrix buffers and the knobs it was captured with
@@ -290,6 +293,7 @@ struct Engine {
     uint32_t knob_gen = 0;
 
     ~Engine() {
+        if (!arena && !probe_mem && !aux) return;   // never set up on a device
         (void)hipSetDevice(device);
         if (own_stream) (void)hipStreamSynchronize(own_stream);
         else (void)hipDeviceSynchronize();
@@ -655,6 +659,21 @@ hipError_t h2d(T* d, const std::vector<T>& v, hipStream_t s = nullptr) {
     return hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
+// Initial probe capacity and count-matrix words: a generous multiple of the
+// expected sample q s_j / s_{j-1} per round and instance (more headroom in a
+// fixed region, which cannot grow); the count matrix holds each instance's
+// probes x p.
+void probe_sizes(const Engine& E, uint64_t* want, uint64_t* cm) {
+    *want = 0;
+    *cm = 0;
+    for (const InstHost& h : E.ih) {
+        const uint64_t m = E.fixed_mem ? std::min<uint64_t>(h.n, 32ull * h.q + 4096)
+                                       : std::min<uint64_t>(h.n, 8ull * h.q + 256);
+        *want += m;
+        *cm += m * h.p;
+    }
+}
+
 // Allocates the engine for its instances (E.ih filled, constants computed).
 hss_status engine_init(Engine& E) {
     HIP_TRY(hipGetDevice(&E.device));
@@ -727,7 +746,7 @@ hss_status engine_init(Engine& E) {
     r.pre_cap = 0;
     E.pre_rounds = 0;
     double expect = 0;   // largest expected number of draws below a threshold
-    if (!E.batch && E.ih.size() == 1 && E.n_tot >= kPresampleMin && !E.tune.lsd_only) {
+    if (!E.batch && !E.fixed_mem && E.ih.size() == 1 && E.n_tot >= kPresampleMin && !E.tune.lsd_only) {
         for (uint32_t j = 1; j <= kPreRounds && j <= E.J; ++j) {
             if (L.all[j - 1] || (j > 1 && E.tune.probes_per_round)) break;
             E.pre_thresh[j - 1] = L.thresh[j - 1];
@@ -755,12 +774,18 @@ hss_status engine_init(Engine& E) {
     // probes: a generous multiple of the expected sample p s_j / s_{j-1} per
     // round and instance; the count matrix holds each instance's probes x p
     uint64_t want = 0, cm = 0;
-    for (const InstHost& h : E.ih) {
-        const uint64_t m = std::min<uint64_t>(h.n, 8ull * h.q + 256);
-        want += m;
-        cm += m * h.p;
-    }
-    return grow(E, want, cm);
+    probe_sizes(E, &want, &cm);
+    hss_status st = grow(E, want, cm);
+    if (st != HSS_OK || !E.fixed_mem) return st;
+    // a fixed region also holds the count tables of the deeper sort levels at
+    // their bounds, so that no later call takes more of it
+    const uint64_t fbw = oversize_tile_capacity(E.n_tot) * 256, fbs = oversize_capacity(E.n_tot) * 256 + 1;
+    HIP_TRY(dev_alloc(E.mem, (void**)&E.hh.fb_counts, fbw * 4));
+    HIP_TRY(dev_alloc(E.mem, (void**)&E.hh.fb_sb_start, fbs * 8));
+    HIP_TRY(dev_alloc(E.mem, (void**)&E.hh.fb_sb_len, fbs * 4));
+    E.hh.fb_words = fbw;
+    E.hh.fb_sb = fbs;
+    return HSS_OK;
 }
 
 hss_status read_counters(Engine& E, hipStream_t s, uint32_t rounds = 0) {
@@ -1610,6 +1635,160 @@ hss_status hss_local_sort(hss_plan_t P, const void* kin, const uint64_t* vin, vo
         HIP_TRY(hipSetDevice(E.device));
         return segment_sort(E, true, kin, vin, kout, vout, E.A, E.Av, E.seg_off, E.S, E.max_seg, nullptr,
                             nullptr, false, (hipStream_t)stream);
+    } catch (...) {
+        return fail(HSS_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- fixed workspace ----
+// hss_partition_static: the whole workspace of a call is carved out of one
+// file-scope device array, so a call allocates no device or pinned memory.
+// In host code `scratch` names a host-side stand-in, not the array: its
+// device address is looked up once per device with hipGetSymbolAddress, and
+// only that address is handed to kernels.
+
+namespace {
+
+constexpr size_t kStaticScratchBytes = (size_t)HSS_STATIC_SCRATCH_MIB << 20;
+constexpr int kStaticMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_static_mu;                         // one call at a time (all devices)
+void* g_static_ptr[kStaticMaxDevices] = {};     // device address of scratch, per device
+alignas(256) unsigned char g_static_host[64 << 10];   // host words of the call in progress
+
+// Bump allocation from a fixed device region and a fixed host buffer;
+// releases return nothing (the region is reused by the next call).
+struct FixedArena : MemSource {
+    char* dev = nullptr;
+    size_t dev_cap = 0, dev_used = 0;
+    char* host = nullptr;
+    size_t host_cap = 0, host_used = 0;
+    static hipError_t take(char* base, size_t cap, size_t* used, void** p, size_t bytes) {
+        const size_t at = (*used + 255) & ~size_t(255);
+        if (at > cap || bytes > cap - at) return hipErrorOutOfMemory;
+        *p = base + at;
+        *used = at + bytes;
+        return hipSuccess;
+    }
+    hipError_t dev_get(void** p, size_t bytes) override { return take(dev, dev_cap, &dev_used, p, bytes); }
+    void dev_put(void*) override {}
+    hipError_t host_get(void** p, size_t bytes) override { return take(host, host_cap, &host_used, p, bytes); }
+    void host_put(void*) override {}
+};
+
+// Device bytes a fixed-region call of this engine takes (its layout, probe
+// buffers, count matrix and the deeper levels' count tables), computed on
+// the host alone.
+size_t fixed_bytes(Engine& E) {
+    Layout L;
+    build_layout(E, L);
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    size_t b = up(layout(E, nullptr) + 256);
+    uint64_t want = 0, cm = 0;
+    probe_sizes(E, &want, &cm);
+    uint64_t cap = 4096;
+    while (cap < want) cap *= 2;
+    Arena ar;
+    ar.take<uint64_t>(cap);   // pr_key
+    ar.take<uint64_t>(cap);   // pr_tag
+    ar.take<uint32_t>(cap);   // pr_ivl
+    ar.take<uint64_t>(cap);   // g_key
+    ar.take<uint64_t>(cap);   // g_tag
+    ar.take<uint64_t>(cap);   // ps_key
+    ar.take<uint64_t>(cap);   // ps_tag
+    ar.take<uint32_t>(cap);   // ps_ivl
+    ar.take<uint32_t>(cap);   // ps_seg
+    ar.take<uint64_t>(cap);   // pr_rank
+    b += up(ar.used + 256);
+    uint64_t words = 1ull << 20;
+    while (words < cm) words *= 2;
+    b += up(words * 4);
+    const uint64_t fbw = oversize_tile_capacity(E.n_tot) * 256, fbs = oversize_capacity(E.n_tot) * 256 + 1;
+    b += up(fbw * 4) + up(fbs * 8) + up(fbs * 4);
+    return b;
+}
+
+hss_status static_shape(Engine& E, uint64_t n, uint32_t p, double eps, hss_key_type kt, bool payload) {
+    hss_status st = plan_args(n, p, p, eps, kt, nullptr);
+    if (st != HSS_OK) return st;
+    if (n > HSS_STATIC_MAX_KEYS || p > HSS_STATIC_MAX_BUCKETS)
+        return fail(HSS_ERR_UNSUPPORTED, "hss_partition_static takes at most " + std::to_string(HSS_STATIC_MAX_KEYS) +
+                                             " keys and " + std::to_string(HSS_STATIC_MAX_BUCKETS) + " buckets");
+    E.key_bytes = kt == HSS_U32 ? 4 : 8;
+    E.payload = payload;
+    E.tune.plain_launches = 1;
+    E.fixed_mem = true;
+    st = new_engine_instance(E, n, p, eps);
+    if (st != HSS_OK) return st;
+    if (fixed_bytes(E) > kStaticScratchBytes)
+        return fail(HSS_ERR_UNSUPPORTED, "the call needs more than the fixed workspace of " +
+                                             std::to_string(kStaticScratchBytes) + " bytes");
+    return HSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hss_status hss_partition_static_bytes(uint64_t n, uint32_t p, double eps, hss_key_type kt, int with_payload,
+                                      size_t* bytes, size_t* capacity) {
+    try {
+        Engine E;
+        const hss_status st = static_shape(E, n, p, eps, kt, with_payload != 0);
+        if (capacity) *capacity = kStaticScratchBytes;
+        // a shape refused before it was laid out has no size
+        if (bytes) *bytes = E.ih.empty() ? 0 : fixed_bytes(E);
+        return st;
+    } catch (...) {
+        return fail(HSS_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+hss_status hss_partition_static(uint64_t n, uint32_t p, double eps, hss_key_type kt, uint64_t seed,
+                                const void* kin, const uint64_t* vin, void* kout, uint64_t* vout,
+                                uint64_t* d_offsets, void* stream) {
+    try {
+        const bool payload = vin != nullptr;
+        hss_status st = check_io_raw(payload, kt == HSS_U32 ? 4 : 8, n, p, kin, vin, kout, vout, d_offsets);
+        if (st != HSS_OK) return st;
+        if (!d_offsets) return fail(HSS_ERR_INVALID_ARG, "null offsets pointer");
+        // shape and size checks on the host, before any device call
+        FixedArena mem;
+        Engine E;   // destroyed before mem
+        st = static_shape(E, n, p, eps, kt, payload);
+        if (st != HSS_OK) return st;
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        if (dev < 0 || dev >= kStaticMaxDevices) return fail(HSS_ERR_UNSUPPORTED, "device ordinal too large");
+        if (!g_static_ptr[dev]) {
+            // once per device, with that device current: the array's address
+            // on it (each device holds its own copy)
+            void* ptr = nullptr;
+            HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr) return fail(HSS_ERR_DEVICE, "no device address for the fixed workspace");
+            g_static_ptr[dev] = ptr;
+        }
+        mem.dev = (char*)g_static_ptr[dev];
+        mem.dev_cap = kStaticScratchBytes;
+        mem.host = (char*)g_static_host;
+        mem.host_cap = sizeof(g_static_host);
+        E.mem = &mem;
+        const hipStream_t s = (hipStream_t)stream;
+        E.own_stream = s;
+        st = engine_init(E);
+        if (st != HSS_OK) return st;
+        E.cur_seed = seed;
+        const InstRun run{seed, kin, vin, kout, vout, d_offsets};
+        HIP_TRY(launch_set_run(run, E.run_d, s));
+        HIP_TRY(launch_counters_reset(E.ra.ctr, s));
+        st = engine_run(E, kin, vin, kout, vout, s, false);
+        if (st != HSS_OK) return st;
+        return finish(E, s);
     } catch (...) {
         return fail(HSS_ERR_DEVICE, "unexpected exception");
     }

@@ -72,3 +72,23 @@ def test_bucket_and_staged_plans_reject_invalid_arguments_before_touching_the_de
         with pytest.raises(lib.HssError) as ei:
             lib.StagedPlan(n, p, r, e1, e2)
         assert ei.value.status == -1
+
+
+def test_static_partition_limits_checked_on_the_host():
+    """The fixed-workspace entry point refuses shapes beyond its limits before
+    any device call, and the largest accepted shapes fit its array."""
+    import ctypes
+    import paper_1803_01237_amd as lib
+    L = lib._lib
+    a = 1 << 40   # aligned, far-apart addresses, never dereferenced
+    for n, p in [((1 << 20) + 1, 16), (1 << 20, 257)]:
+        st = L.hss_partition_static(n, p, 0.05, lib.HSS_U64, 1, a, None, a + (1 << 30), None,
+                                    a + (1 << 31), None)
+        assert st == -2
+        assert b"at most" in L.hss_last_error()
+    for kb in (4, 8):
+        for pay in (False, True):
+            for eps in (1e-6, 0.02, 0.999):
+                st, need, cap = lib.static_workspace_bytes(1 << 20, 256, eps, kb, pay)
+                assert st == 0 and 0 < need <= cap
+    assert lib.static_workspace_bytes(10, 20, 0.05)[0] == -1
