@@ -9,8 +9,9 @@ segments with eps = 0.02, inputs resident in HBM.  Prints one JSON line.
 
 The line carries the throughput, the roofline of the dominant kernel (its
 algorithmic bytes per launch over its average launch time, HIP events on its
-stream over the timed region) and the CPU oracle timed on a bounded sample of
-the same workload.
+stream over the timed region), the rate of a plain streaming copy as the
+achievable HBM reference, the Zipf-Morton payload workload at p = 4096 timed
+the same way, and the CPU oracle on the same keys on the host's cores.
 """
 from __future__ import annotations
 
@@ -75,29 +76,72 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(kind, n_sample, p, eps, dseed, hseed, payload):
+def cpu_baseline(keys, p, eps, hseed, payload, threads):
+    """The oracle on the host cores: hss_partition of the whole workload (the
+    same host keys as the GPU run), its per-segment and per-bucket work split
+    over `threads` threads; then, for scale, the small configuration (2^20
+    uniform keys, p = 16, eps = 0.05) on one thread."""
     import oracle
     import synth
-    keys = synth.make(kind, n_sample, dseed)
-    vals = np.arange(n_sample, dtype=np.uint64) if payload else None
+    n = len(keys)
+    vals = np.arange(n, dtype=np.uint64) if payload else None
     t0 = time.perf_counter()
-    r = oracle.hss(keys, p, eps, hseed, vals=vals, mode="partition", trace_level=0)
+    r = oracle.hss(keys, p, eps, hseed, vals=vals, mode="partition", trace_level=0, threads=threads)
     dt = time.perf_counter() - t0
     assert r.status == 0
-    # the small configuration (2^20 uniform keys, p = 16, eps = 0.05), for scale
+    stages = {"local_sort": r.times[0], "rounds": r.times[1], "exchange": r.times[2]}
+    del r, vals
     k1 = synth.make("uniform64", 1 << 20, 1)
     t1 = time.perf_counter()
-    r1 = oracle.hss(k1, 16, 0.05, 1, mode="partition", trace_level=0)
+    r1 = oracle.hss(k1, 16, 0.05, 1, mode="partition", trace_level=0, threads=1)
     d1 = time.perf_counter() - t1
     assert r1.status == 0
-    return {"value": n_sample / dt / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-            "sample": f"hss_partition of the first {n_sample} keys of the same generator "
-                      f"(seed {dseed}), p={p}, eps={eps}, single-threaded C++ oracle, "
-                      f"{dt:.2f} s",
+    return {"value": n / dt / 1e9, "unit": "Gkeys/s", "cores": threads, "kind": "oracle",
+            "sample": f"hss_partition of the whole workload ({n} keys, p={p}, eps={eps}) by the "
+                      f"C++ oracle on {threads} host threads, {dt:.2f} s",
             "seconds": round(dt, 3),
-            "small_config": {"n": 1 << 20, "p": 16, "eps": 0.05, "seconds": round(d1, 3),
-                             "gkeys_per_s": round((1 << 20) / d1 / 1e9, 5)},
+            "stage_seconds": {k: round(v, 3) for k, v in stages.items()},
+            "small_config": {"n": 1 << 20, "p": 16, "eps": 0.05, "threads": 1,
+                             "seconds": round(d1, 3), "gkeys_per_s": round((1 << 20) / d1 / 1e9, 5)},
             "host": {"nproc": os.cpu_count(), "cpu": _cpu_model()}}
+
+
+def copy_ceiling(nbytes=1 << 31, reps=10):
+    """The achievable HBM rate: the library's 16-byte-per-lane streaming copy
+    of `nbytes` over a few grid sizes, with and without non-temporal hints
+    (best of each), beside torch's device copy; GB/s counts bytes read plus
+    written."""
+    import torch
+    import paper_1803_01237_amd as hss
+    src = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda:0")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+
+    def rate(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        best = 1e30
+        for _ in range(reps):
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            best = min(best, a.elapsed_time(b))
+        return 2 * nbytes / (best * 1e-3) / 1e9
+
+    runs = {}
+    for nt in (False, True):
+        for wg in (1024, 2048, 4096, 8192, 16384):
+            runs[f"wg{wg}{'_nt' if nt else ''}"] = round(rate(lambda: hss.stream_copy(dst, src, wg, nt)), 1)
+    torch_rate = round(rate(lambda: dst.copy_(src)), 1)
+    assert torch.equal(dst, src)
+    best = max(runs, key=runs.get)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes": nbytes, "best": best, "GB_per_s": runs[best],
+            "frac_of_peak": round(runs[best] / HBM_PEAK_GBS, 4), "runs": runs,
+            "torch_copy_GB_per_s": torch_rate}
 
 
 def _cpu_model():
@@ -402,14 +446,95 @@ def served_bench(count, mults, check_every):
             "runs": runs}
 
 
+def run_workload(name, keys, steps, warmup, op, sort_steps):
+    """Time `steps` calls of the plan of workload `name` on `keys` (device)
+    after `warmup` (the first warmup call runs the autotuner); returns the
+    measurements and the plan (still open).  Per-stage times come from HIP
+    events on the library's stream around every launch."""
+    import torch
+    import paper_1803_01237_amd as hss
+    n, p, eps, dseed, hseed, kind, payload = WORKLOADS[name]
+    dev = keys.device
+    vals = torch.arange(n, dtype=torch.int64, device=dev) if payload else None
+    kout = torch.empty_like(keys)
+    vout = torch.empty_like(vals) if payload else None
+    off = torch.empty(p + 1, dtype=torch.int64, device=dev)
+    # the first warmup call runs the autotuner on this input (no warmup: no
+    # autotuning, so that no timed step searches)
+    plan = hss.Plan(n, p, eps, key_bytes=8, payload=payload, autotune=warmup > 0)
+    log(f"[bench] {name}: workspace {plan.workspace_bytes / 2**30:.2f} GiB; warmup {warmup}")
+    step = plan.partition if op == "partition" else plan.sort
+    for _ in range(warmup):
+        step(keys, hseed, vals, kout, vout, off)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    plan.profile_reset()
+    log(f"[bench] {name}: timing {steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(keys, hseed, vals, kout, vout, off)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = plan.profile_read()
+    plan.profile(False)
+    ms_step = (t1 - t0) * 1e3 / steps
+    tr = plan.trace()
+    # check the benched result: every splitter inside its target range
+    tol = plan.constants(1)[0]
+    o = off.cpu().numpy()
+    ideal = (np.arange(p + 1, dtype=object) * n) // p
+    bad = [i for i in range(1, p) if abs(int(o[i]) - int(ideal[i])) > tol]
+    if bad or o[0] != 0 or o[p] != n:
+        log(f"[bench] {name}: BALANCE CHECK FAILED at {bad[:5]}")
+        sys.exit(1)
+    # hss_sort for context (not the headline)
+    sort_ms = None
+    if sort_steps > 0:
+        plan.sort(keys, hseed, vals, kout, vout, off)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for _ in range(sort_steps):
+            plan.sort(keys, hseed, vals, kout, vout, off)
+        torch.cuda.synchronize()
+        sort_ms = (time.perf_counter() - s0) * 1e3 / sort_steps
+    # roofline of the dominant kernel family (largest share of the step)
+    fam = max((f for f in prof if f != "rounds" and prof[f][1] > 0), key=lambda f: prof[f][0])
+    f_ms, f_n, f_bytes = prof[fam]
+    achieved = (f_bytes / f_n) / (f_ms / f_n * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(name, fam), "traffic_unit": "bytes/launch",
+            "avg_launch_ms": round(f_ms / f_n, 4),
+            "bytes_per_launch": f_bytes // f_n}
+    stages = {f: {"ms_per_step": round(prof[f][0] / steps, 4),
+                  "launches_per_step": prof[f][1] // steps,
+                  "GB_per_s": (round(prof[f][2] / (prof[f][0] * 1e-3) / 1e9, 1)
+                               if prof[f][0] > 0 and prof[f][2] else None)}
+              for f in prof}
+    res = {"workload": name, "n": n, "p": p, "eps": eps, "payload": payload, "op": "hss_" + op,
+           "ms_per_step": round(ms_step, 4), "gkeys_per_s": n / (ms_step * 1e-3) / 1e9,
+           "stages": stages, "roofline": roof, "rounds": len(tr),
+           "probes_per_round": [r.m for r in tr], "domain_per_round": [r.domain for r in tr],
+           "knobs": plan.knobs(),
+           "hss_sort_ms": None if sort_ms is None else round(sort_ms, 4),
+           "hss_sort_gkeys_s": None if sort_ms is None else round(n / (sort_ms * 1e-3) / 1e9, 3)}
+    del kout, vout, vals
+    return res, plan
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform_u64_2^28_p1024", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-sample", type=int, default=1 << 25,
-                    help="keys in the CPU oracle sample (0 to skip)")
+    ap.add_argument("--cpu-threads", type=int, default=16,
+                    help="host threads of the CPU oracle baseline (0 to skip)")
+    ap.add_argument("--skewed-steps", type=int, default=10,
+                    help="steps of the Zipf-Morton payload workload at p = 4096 (0 to skip)")
+    ap.add_argument("--no-copy-ceiling", dest="copy_ceiling", action="store_false",
+                    help="skip the streaming-copy bandwidth reference")
     ap.add_argument("--sort-steps", type=int, default=3, help="hss_sort steps timed for context")
     ap.add_argument("--op", default="partition", choices=["partition", "sort"],
                     help="operation timed as the step (the headline is partition)")
@@ -466,74 +591,11 @@ def main():
     log(f"[bench] generating {args.workload}: n={n} p={p} eps={eps}")
     keys_np = synth.make(kind, n, dseed)
     keys = torch.from_numpy(keys_np.view(np.int64)).to(dev)
-    vals = torch.arange(n, dtype=torch.int64, device=dev) if payload else None
-    del keys_np
+    res, plan = run_workload(args.workload, keys, args.steps, args.warmup, args.op, args.sort_steps)
+    ms_step, value, stages, roof = res["ms_per_step"], res["gkeys_per_s"], res["stages"], res["roofline"]
     kout = torch.empty_like(keys)
-    vout = torch.empty_like(vals) if payload else None
     off = torch.empty(p + 1, dtype=torch.int64, device=dev)
-
-    # the first warmup call runs the autotuner on this input (no warmup: no
-    # autotuning, so that no timed step searches)
-    plan = hss.Plan(n, p, eps, key_bytes=8, payload=payload, autotune=args.warmup > 0)
-    log(f"[bench] workspace {plan.workspace_bytes / 2**30:.2f} GiB; warmup {args.warmup}")
-    step = plan.partition if args.op == "partition" else plan.sort
-    for _ in range(args.warmup):
-        step(keys, hseed, vals, kout, vout, off)
-    torch.cuda.synchronize()
-
-    plan.profile(True)
-    plan.profile_reset()
-    log(f"[bench] timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(keys, hseed, vals, kout, vout, off)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = plan.profile_read()
-    plan.profile(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    value = n / (ms_step * 1e-3) / 1e9
-    tr = plan.trace()
-    knobs = plan.knobs()
-    rounds = len(tr)
-    ms_m = [r.m for r in tr]
-    domains = [r.domain for r in tr]
-
-    # check the benched result: every splitter inside its target range
-    tol = plan.constants(1)[0]
-    o = off.cpu().numpy()
-    ideal = (np.arange(p + 1, dtype=object) * n) // p
-    bad = [i for i in range(1, p) if abs(int(o[i]) - int(ideal[i])) > tol]
-    if bad or o[0] != 0 or o[p] != n:
-        log(f"[bench] BALANCE CHECK FAILED at {bad[:5]}")
-        sys.exit(1)
-
-    # hss_sort for context (not the headline)
-    sort_ms = None
-    if args.sort_steps > 0:
-        plan.sort(keys, hseed, vals, kout, vout, off)
-        torch.cuda.synchronize()
-        s0 = time.perf_counter()
-        for _ in range(args.sort_steps):
-            plan.sort(keys, hseed, vals, kout, vout, off)
-        torch.cuda.synchronize()
-        sort_ms = (time.perf_counter() - s0) * 1e3 / args.sort_steps
-
-    # roofline of the dominant kernel family (largest share of the step)
-    fam = max((f for f in prof if f != "rounds" and prof[f][1] > 0), key=lambda f: prof[f][0])
-    f_ms, f_n, f_bytes = prof[fam]
-    achieved = (f_bytes / f_n) / (f_ms / f_n * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(args.workload, fam), "traffic_unit": "bytes/launch",
-            "avg_launch_ms": round(f_ms / f_n, 4),
-            "bytes_per_launch": f_bytes // f_n}
-    stages = {f: {"ms_per_step": round(prof[f][0] / args.steps, 4),
-                  "launches_per_step": prof[f][1] // args.steps,
-                  "GB_per_s": (round(prof[f][2] / (prof[f][0] * 1e-3) / 1e9, 1)
-                               if prof[f][0] > 0 and prof[f][2] else None)}
-              for f in prof}
+    vals = vout = None
 
     # both extra legs only at the headline workload; the options first, while
     # the input buffer still holds the headline keys
@@ -547,14 +609,28 @@ def main():
     plan.close()
     del keys, kout, vout, vals
     torch.cuda.empty_cache()
+    ceiling = copy_ceiling() if args.copy_ceiling else None
+    # the Zipf-Morton configuration with a payload (p = 4096), timed the same way
+    skewed = None
+    if args.skewed_steps > 0 and headline:
+        sname = "zipf_morton_u64+payload_2^28_p4096"
+        sn, sp, seps, sdseed, shseed, skind, _ = WORKLOADS[sname]
+        log(f"[bench] generating {sname}")
+        sk = torch.from_numpy(synth.make(skind, sn, sdseed).view(np.int64)).to(dev)
+        skewed, splan = run_workload(sname, sk, args.skewed_steps, min(args.warmup, 2), "partition", 0)
+        splan.close()
+        del sk
+        torch.cuda.empty_cache()
     batched = batched_bench(args.batch_steps, args.batch_count) if args.batch_count > 0 else None
     served = (served_bench(args.serve_requests, [float(x) for x in args.serve_rates.split(",")],
                            args.serve_check_every) if args.serve_requests > 0 else None)
 
     cpu = None
-    if args.cpu_sample > 0:
-        log(f"[bench] CPU oracle on {args.cpu_sample} keys")
-        cpu = cpu_baseline(kind, min(args.cpu_sample, n), p, eps, dseed, hseed, payload)
+    if args.cpu_threads > 0:
+        threads = min(args.cpu_threads, os.cpu_count() or 1)
+        log(f"[bench] CPU oracle on {threads} threads")
+        cpu = cpu_baseline(keys_np, p, eps, hseed, payload, threads)
+    del keys_np
 
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gkeys/s", "n_gpus": 1,
@@ -566,10 +642,13 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "stages": stages,
-        "rounds": rounds, "probes_per_round": ms_m, "domain_per_round": domains,
-        "knobs": knobs,
-        "hss_sort_ms": None if sort_ms is None else round(sort_ms, 4),
-        "hss_sort_gkeys_s": None if sort_ms is None else round(n / (sort_ms * 1e-3) / 1e9, 3),
+        "rounds": res["rounds"], "probes_per_round": res["probes_per_round"],
+        "domain_per_round": res["domain_per_round"],
+        "knobs": res["knobs"],
+        "hss_sort_ms": res["hss_sort_ms"],
+        "hss_sort_gkeys_s": res["hss_sort_gkeys_s"],
+        "copy_ceiling": ceiling,
+        "zipf_morton_p4096": skewed,
         "batched": batched,
         "served": served,
         "plan_options": options,

@@ -468,6 +468,19 @@ hss_status hss_staged_partition(hss_staged_t plan, uint64_t seed, const void* d_
  * group boundaries), the layout of stage 2, stage 2. */
 hss_status hss_staged_times(hss_staged_t plan, double* stage1_s, double* setup_s, double* stage2_s);
 
+/*
+ * hss_stream_copy -- measurement aid: copies `bytes` (a multiple of 16) from
+ * src to dst (device pointers, 16-byte aligned, not overlapping) with 16-byte
+ * loads and stores per lane, `workgroups` workgroups of 256 threads striding
+ * over the buffer (1..65536), optionally with non-temporal loads and stores.
+ * Its rate is the achievable HBM bandwidth the streaming kernels are compared
+ * with.  Enqueued on `stream`; returns at once.  Errors: HSS_ERR_INVALID_ARG
+ * for bad sizes or pointers (nothing enqueued), HSS_ERR_DEVICE if the launch
+ * fails.
+ */
+hss_status hss_stream_copy(void* dst, const void* src, size_t bytes, uint32_t workgroups,
+                           int nontemporal, void* stream);
+
 const char* hss_status_string(hss_status status);
 
 /* Message of the last failure on the calling thread ("" if none). */

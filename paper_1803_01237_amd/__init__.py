@@ -49,7 +49,7 @@ EXPORTS = [
     "hss_server_wait", "hss_server_clock", "hss_server_stats", "hss_server_footprint",
     "hss_plan_knobs", "hss_plan_set_knobs", "hss_batch_knobs", "hss_plan_buckets",
     "hss_staged_plan", "hss_staged_destroy", "hss_staged_workspace_bytes", "hss_staged_partition",
-    "hss_staged_times", "hss_partition_static", "hss_partition_static_bytes",
+    "hss_staged_times", "hss_partition_static", "hss_partition_static_bytes", "hss_stream_copy",
     "hss_status_string", "hss_last_error",
 ]
 
@@ -741,6 +741,20 @@ def static_workspace_bytes(n: int, p: int, eps: float, key_bytes: int = 8,
     st = _lib.hss_partition_static_bytes(n, p, eps, HSS_U64 if key_bytes == 8 else HSS_U32,
                                          1 if payload else 0, C.byref(b), C.byref(c))
     return int(st), int(b.value), int(c.value)
+
+
+_lib.hss_stream_copy.argtypes = [_vp, _vp, C.c_size_t, _u32, C.c_int, _vp]
+_lib.hss_stream_copy.restype = C.c_int
+
+
+def stream_copy(dst, src, workgroups: int = 4096, nontemporal: bool = False):
+    """Copy the device tensor src into dst (same byte size, a multiple of 16)
+    with the library's streaming copy kernel (a bandwidth reference)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("dst and src differ in size")
+    _check(_lib.hss_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, workgroups,
+                                1 if nontemporal else 0, _stream_handle()), "hss_stream_copy")
 
 
 def exported_symbols():

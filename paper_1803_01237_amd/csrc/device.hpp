@@ -61,6 +61,21 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) 
     return (__attribute__((address_space(1))) T*)p;
 }
 
+// Streaming accesses: loads and stores of data touched once per pass, issued
+// with the non-temporal hint so that they do not displace what is reused.
+// Only for accesses that take whole cache lines at once (a tile read in
+// rows, a sub-bucket written by one workgroup): a line consumed piece by
+// piece (digit runs, short pieces, gathers inside a tile) is fetched or
+// written again for every piece when it is not kept.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+    return __builtin_nontemporal_load(as_global(p));
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(T* p, T v) {
+    __builtin_nontemporal_store(v, as_global(p));
+}
+
 __device__ __forceinline__ uint64_t lanes_below_mask() {
     return (1ull << lane_id()) - 1ull;   // lane 0 -> 0
 }

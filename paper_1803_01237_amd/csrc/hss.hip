@@ -520,6 +520,8 @@ size_t layout(Engine& E, char* base) {
     r.inst_plo = ar.take<uint32_t>(B);
     r.inst_pm = ar.take<uint32_t>(B);
     r.cm_off = ar.take<uint64_t>(B);
+    r.sel_e = ar.take<uint32_t>(2 * (size_t)Q);
+    r.sel_kind = ar.take<uint8_t>(2 * (size_t)Q);
     r.ctr = ar.take<RoundCounters>(1);
     r.hist = ar.take<RoundHist>(E.J);
     E.chi_all = ar.take<uint64_t>(Q);

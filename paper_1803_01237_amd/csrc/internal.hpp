@@ -503,6 +503,11 @@ struct RoundArgs {
     uint32_t* inst_plo;            // first sorted probe of the instance
     uint32_t* inst_pm;             // its probes
     uint64_t* cm_off;              // its count-matrix block
+    // per splitter row, two slots of probes whose per-segment counts become
+    // table rows: slot 2r the new lower bound (or the settling probe), slot
+    // 2r+1 the new upper bound; sel_e = sorted probe index or kNoSel
+    uint32_t* sel_e;
+    uint8_t* sel_kind;             // 0: lpos, 1: upos, 2: prow
     // probes (capacity cap)
     uint64_t cap;
     uint64_t* pr_key;
@@ -527,6 +532,7 @@ struct RoundArgs {
 };
 
 constexpr uint32_t kRankChunk = 1u << 15;   // keys of a segment per rank workgroup
+constexpr uint32_t kNoSel = 0xFFFFFFFFu;    // empty selection slot
 
 hipError_t launch_counters_reset(RoundCounters* ctr, hipStream_t s);
 // Start of a call's rounds: every splitter unsettled with open bounds.

@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(const K* __re
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
             const uint32_t li = w * kKeysPerWave + r * kWave + lane;
-            kr[r] = li < n_tile ? as_global(src)[li] : (K)0;
+            kr[r] = li < n_tile ? ld_stream(src + li) : (K)0;
         }
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
 #pragma unroll
         for (int r = 0; r < kIt; ++r) {
             const uint32_t li = w * kKpw + r * kWave + lane;
-            key[r] = li < n_tile ? as_global(src)[li] : (K)0;
+            key[r] = li < n_tile ? ld_stream(src + li) : (K)0;
         }
         if constexpr (kStable) {
 #pragma unroll
@@ -322,6 +322,8 @@ __global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
             const K k = (K)stage[i];
             const uint32_t d = digit_of((K)(k - kb), shift);
             const uint64_t dst = gofs[d] + (i - tstart[d]);
+            // plain stores: a digit run covers parts of cache lines, which
+            // the L2 merges before they go out
             as_global(ko)[dst] = k;
             if constexpr (kPayload) as_global(vo)[dst] = as_global(vsrc)[sidx[i]];
         }

@@ -1024,14 +1024,14 @@ __global__ __launch_bounds__(256) void reduce_kernel(RoundArgs a) {
 // Workgroup per splitter row (section 4.2.2 steps 3 and 5).  A probe whose
 // rank lies in the target range settles the splitter (closest to N i/p, the
 // lower rank on a tie); otherwise L and U move to the closest probe ranks
-// below and above N i/p.  The per-segment counts of each new bound or
-// splitter probe (its column of the count matrix) then become row i of lpos
-// (L; the probe itself is excluded in its own segment), upos (U) or prow
-// (the splitter).  The grid also checks that ranks increase along every
+// below and above N i/p.  Every new bound or splitter probe is put in the
+// row's two selection slots; its per-segment counts (its column of the count
+// matrix) become row i of lpos (L), upos (U) or prow (the splitter) in
+// settle_copy_kernel.  The grid also checks that ranks increase along every
 // instance's sorted probes.
 template <int kThreads>
 __global__ __launch_bounds__(kThreads) void settle_kernel(RoundArgs a) {
-    __shared__ uint32_t sh_n, sh_e[2], sh_kind[2], sh_cnt, sh_first;
+    __shared__ uint32_t sh_cnt, sh_first;
     if (halted(a)) return;
     const uint64_t m_all = a.ctr->m_stored;
     for (uint64_t e = (uint64_t)blockIdx.x * kThreads + threadIdx.x; e + 1 < m_all;
@@ -1039,7 +1039,11 @@ __global__ __launch_bounds__(kThreads) void settle_kernel(RoundArgs a) {
         if (a.ivl_inst[a.ps_ivl[e]] == a.ivl_inst[a.ps_ivl[e + 1]] && a.pr_rank[e] >= a.pr_rank[e + 1])
             atomicOr(&a.ctr->err, kErrRankOrder);
     const uint32_t r = blockIdx.x;
-    if (r >= a.n_rows || a.settled[r]) return;   // uniform over the workgroup
+    if (r >= a.n_rows) return;
+    if (a.settled[r]) {   // uniform over the workgroup: nothing to copy for this row
+        if (threadIdx.x == 0) a.sel_e[2 * r] = a.sel_e[2 * r + 1] = kNoSel;
+        return;
+    }
     const uint32_t I = a.row_inst[r];
     const uint32_t mI = a.inst_pm[I];
     const uint64_t plo = a.inst_plo[I];
@@ -1063,59 +1067,125 @@ __global__ __launch_bounds__(kThreads) void settle_kernel(RoundArgs a) {
             if (R[e] >= target && (e == 0 || R[e - 1] < target)) sh_first = e;   // one e qualifies
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t n = 0;
-        if (mI == 0) {   // no probe of this instance this round
-            atomicAdd(&a.ctr->n_after, 1u);
+    if (threadIdx.x != 0) return;
+    uint32_t sel0 = kNoSel, sel1 = kNoSel;
+    uint8_t kind0 = 0;
+    if (mI == 0) {   // no probe of this instance this round
+        atomicAdd(&a.ctr->n_after, 1u);
+    } else {
+        const uint64_t tol = a.inst[I].tol;
+        const uint64_t lo = sh_first;
+        const bool has_above = lo < mI;
+        const bool has_below = lo > 0;
+        const uint64_t r_above = has_above ? R[lo] : 0;
+        const uint64_t r_below = has_below ? R[lo - 1] : 0;
+        const uint64_t d_above = r_above - target;
+        const uint64_t d_below = target - r_below;
+        int64_t pick = -1;
+        if (has_below && d_below <= tol) pick = (int64_t)lo - 1;
+        if (has_above && d_above <= tol && (pick < 0 || d_above < d_below)) pick = (int64_t)lo;
+        if (pick >= 0) {
+            const uint64_t e = plo + (uint64_t)pick;
+            a.settled[r] = 1;
+            a.chi[r] = R[pick];
+            a.s_key[r] = a.ps_key[e];
+            a.s_tag[r] = a.ps_tag[e];
+            sel0 = (uint32_t)e;
+            kind0 = 2;
         } else {
-            const uint64_t tol = a.inst[I].tol;
-            const uint64_t lo = sh_first;
-            const bool has_above = lo < mI;
-            const bool has_below = lo > 0;
-            const uint64_t r_above = has_above ? R[lo] : 0;
-            const uint64_t r_below = has_below ? R[lo - 1] : 0;
-            const uint64_t d_above = r_above - target;
-            const uint64_t d_below = target - r_below;
-            int64_t pick = -1;
-            if (has_below && d_below <= tol) pick = (int64_t)lo - 1;
-            if (has_above && d_above <= tol && (pick < 0 || d_above < d_below)) pick = (int64_t)lo;
-            if (pick >= 0) {
-                const uint64_t e = plo + (uint64_t)pick;
-                a.settled[r] = 1;
-                a.chi[r] = R[pick];
-                a.s_key[r] = a.ps_key[e];
-                a.s_tag[r] = a.ps_tag[e];
-                sh_e[n] = (uint32_t)e;
-                sh_kind[n++] = 2u;
-            } else {
-                atomicAdd(&a.ctr->n_after, 1u);
-                if (has_below && (a.lrank[r] == kNone || r_below > a.lrank[r])) {
-                    a.lrank[r] = r_below;
-                    sh_e[n] = (uint32_t)(plo + lo - 1);
-                    sh_kind[n++] = 0u;
-                }
-                if (has_above && r_above < a.urank[r]) {
-                    a.urank[r] = r_above;
-                    sh_e[n] = (uint32_t)(plo + lo);
-                    sh_kind[n++] = 1u;
+            atomicAdd(&a.ctr->n_after, 1u);
+            if (has_below && (a.lrank[r] == kNone || r_below > a.lrank[r])) {
+                a.lrank[r] = r_below;
+                sel0 = (uint32_t)(plo + lo - 1);
+            }
+            if (has_above && r_above < a.urank[r]) {
+                a.urank[r] = r_above;
+                sel1 = (uint32_t)(plo + lo);
+            }
+        }
+    }
+    a.sel_e[2 * r] = sel0;
+    a.sel_kind[2 * r] = kind0;
+    a.sel_e[2 * r + 1] = sel1;
+    a.sel_kind[2 * r + 1] = 1;
+}
+
+// The selected probes' per-segment counts into their table rows: workgroup
+// per tile of kCopySlots consecutive selection slots x kCopySegs segments.
+// The slots of consecutive rows select nearby sorted probes, so the tile's
+// reads of one count-matrix row (segment) are nearly consecutive words; the
+// tile is turned around in LDS and every slot's table row is written as
+// kCopySegs consecutive words.  A lower bound's own segment gets +1 (its
+// slice starts after the probe).
+constexpr uint32_t kCopySlots = 64;
+constexpr uint32_t kCopySegs = 32;
+
+__global__ __launch_bounds__(256) void settle_copy_kernel(RoundArgs a) {
+    __shared__ uint32_t T[kCopySegs][kCopySlots + 1];
+    __shared__ uint32_t* dst_row[kCopySlots];
+    __shared__ uint32_t own_seg[kCopySlots];
+    __shared__ uint32_t seg_n[kCopySlots];
+    if (halted(a)) return;
+    const uint32_t n_slots = 2 * a.n_rows;
+    const uint32_t slot_tiles = (n_slots + kCopySlots - 1) / kCopySlots;
+    const uint32_t seg_tiles = (a.p_max + kCopySegs - 1) / kCopySegs;
+    const uint32_t lane = lane_id(), w = threadIdx.x / kWave;
+    for (uint64_t tile = blockIdx.x; tile < (uint64_t)slot_tiles * seg_tiles; tile += gridDim.x) {   // uniform
+        const uint32_t stile = (uint32_t)(tile % slot_tiles), gtile = (uint32_t)(tile / slot_tiles);
+        const uint32_t s0 = gtile * kCopySegs;
+        // wave 0: the tile's slots (lane = slot)
+        uint32_t e = kNoSel, I = 0, m = 0, sl_base = 0;
+        uint64_t cm = 0;
+        int has = 0;
+        if (w == 0) {
+            const uint32_t slot = stile * kCopySlots + lane;
+            dst_row[lane] = nullptr;
+            seg_n[lane] = 0;
+            if (slot < n_slots) {
+                e = a.sel_e[slot];
+                if (e != kNoSel) {
+                    const uint32_t r = slot / 2;
+                    I = a.row_inst[r];
+                    const InstDesc& D = a.inst[I];
+                    if (s0 < D.p) {
+                        const uint8_t kind = a.sel_kind[slot];
+                        uint32_t* base = kind == 0 ? a.lpos : (kind == 1 ? a.upos : a.prow);
+                        dst_row[lane] = base + D.tab0 + (uint64_t)(r - D.row0) * D.p;
+                        own_seg[lane] = kind == 0 ? a.ps_seg[e] - D.seg0 : 0xFFFFFFFFu;
+                        seg_n[lane] = min(D.p - s0, kCopySegs);
+                        has = 1;
+                    }
                 }
             }
         }
-        sh_n = n;
-    }
-    __syncthreads();
-    const uint32_t n = sh_n;
-    if (n == 0) return;
-    const InstDesc& D = a.inst[I];
-    const uint32_t i = r - D.row0;
-    for (uint32_t q = 0; q < n; ++q) {
-        const uint32_t e = sh_e[q], kind = sh_kind[q];
-        const uint32_t* col = a.cmat + a.cm_off[I] + (e - plo);
-        const uint32_t t = a.ps_seg[e] - D.seg0;
-        uint32_t* dst = (kind == 0 ? a.lpos : (kind == 1 ? a.upos : a.prow)) + D.tab0 + (uint64_t)i * D.p;
-        const uint32_t own = kind == 0 ? 1u : 0u;
-        for (uint32_t s = threadIdx.x; s < D.p; s += kThreads)
-            dst[s] = col[(uint64_t)s * mI] + (s == t ? own : 0u);
+        // a barrier that also tells whether any slot of the tile selects a
+        // probe in these segments (uniform)
+        if (!__syncthreads_or(has)) continue;
+        // loads: wave w reads segments s0 + w, s0 + w + 4, ...; lane = slot
+        {
+            const uint32_t slot = stile * kCopySlots + lane;
+            e = slot < n_slots ? a.sel_e[slot] : kNoSel;
+            const uint32_t nseg = seg_n[lane];
+            if (e != kNoSel && nseg) {
+                I = a.row_inst[slot / 2];
+                m = a.inst_pm[I];
+                cm = a.cm_off[I];
+                sl_base = e - a.inst_plo[I];
+            }
+            for (uint32_t q = w; q < kCopySegs; q += 256 / kWave) {
+                uint32_t v = 0;
+                if (e != kNoSel && q < nseg) v = a.cmat[cm + (uint64_t)(s0 + q) * m + sl_base];
+                T[q][lane] = v;
+            }
+        }
+        __syncthreads();
+        // stores: kCopySegs consecutive words per slot
+        for (uint32_t x = threadIdx.x; x < kCopySlots * kCopySegs; x += 256) {
+            const uint32_t j = x / kCopySegs, q = x % kCopySegs;
+            uint32_t* row = dst_row[j];
+            if (row && q < seg_n[j]) row[s0 + q] = T[q][j] + (s0 + q == own_seg[j] ? 1u : 0u);
+        }
+        __syncthreads();   // the tile's LDS is rewritten by the next tile
     }
 }
 
@@ -1271,6 +1341,9 @@ hipError_t launch_round_tail(const RoundArgs& a, uint32_t j, hipStream_t s, bool
     hipLaunchKernelGGL(reduce_kernel, rgrid, dim3(256), 0, s, a);
     if (a.p_max > 256) hipLaunchKernelGGL(settle_kernel<1024>, dim3(a.n_rows), dim3(1024), 0, s, a);
     else hipLaunchKernelGGL(settle_kernel<256>, dim3(a.n_rows), dim3(256), 0, s, a);
+    const uint64_t copy_tiles = (uint64_t)((2 * a.n_rows + kCopySlots - 1) / kCopySlots) *
+                                ((a.p_max + kCopySegs - 1) / kCopySegs);
+    hipLaunchKernelGGL(settle_copy_kernel, dim3((unsigned)std::min<uint64_t>(copy_tiles, 16384)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -306,7 +306,6 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     K kr[kRowsT];
     uint32_t dr[kRowsT];
     uint64_t vr[kStage ? kRowsT : 1];
-    const global_ptr<K> gsrc = as_global(src);
     // rows wholly past the end are skipped by a branch uniform over the
     // workgroup; inside a row the lanes past the end hold kbase, whose group
     // is computed but never counted or placed
@@ -315,8 +314,8 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
         kr[r] = kbase;
         if (r * kT < (int)n) {
             const uint32_t i = r * kT + threadIdx.x;
-            if (i < n) kr[r] = gsrc[i];
-            if constexpr (kStage) vr[r] = i < n ? as_global(vsrc)[i] : 0;
+            if (i < n) kr[r] = ld_stream(src + i);
+            if constexpr (kStage) vr[r] = i < n ? ld_stream(vsrc + i) : 0;
         }
     }
 #pragma unroll
@@ -393,10 +392,9 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
         }
     }
     __syncthreads();
-    // outputs addressed by 32-bit offsets from the sub-bucket's start; a
-    // fence is due where the offset from the segment start is a multiple of
-    // kFenceStride, which the low 32 bits decide
-    const auto ob = as_global(kout + base);
+    // outputs at offsets from the sub-bucket's start; a fence is due where the
+    // offset from the segment start is a multiple of kFenceStride, which the
+    // low 32 bits decide
     const uint64_t frel = fs.dst ? base - fs.org : 0;
     auto fence = [&](uint32_t o, K k) {
         if (fs.dst && (((uint32_t)frel + o) & (kFenceStride - 1)) == 0)
@@ -405,7 +403,7 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     if (exact) {
         for (uint32_t e = threadIdx.x; e < n; e += kT) {
             const K k = Bk[e];
-            ob[e] = k;
+            st_stream(kout + base + e, k);
             fence(e, k);
         }
         return;
@@ -424,9 +422,9 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
                 rk += (uint32_t)((x < k) | ((x == k) & (Bi[j] < ie)));
             }
             const uint32_t o = g0 + rk;
-            ob[o] = k;
-            if constexpr (kStage) as_global(vout + base)[o] = Bv[e];
-            else as_global(vout + base)[o] = as_global(vsrc)[ie];
+            st_stream(kout + base + o, k);
+            if constexpr (kStage) st_stream(vout + base + o, Bv[e]);
+            else st_stream(vout + base + o, as_global(vsrc)[ie]);
             fence(o, k);
         } else {
             // keys only: equal keys are interchangeable, so the ones placed
@@ -439,7 +437,7 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
                 rk += (uint32_t)((x < k) | ((x == k) & (q < pk)));
             }
             const uint32_t o = g0 + rk;
-            ob[o] = k;
+            st_stream(kout + base + o, k);
             fence(o, k);
         }
     }
