@@ -102,19 +102,21 @@ __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(const K* __re
             const uint32_t li = w * kKeysPerWave + r * kWave + lane;
             kr[r] = li < n_tile ? ld_stream(src + li) : (K)0;
         }
+        // skewed inputs: the lanes holding the wave's current dominant digit
+        // add with one atomic (many lanes on one LDS counter would take turns)
+        uint32_t dom = digit_of((K)(kr[0] - kb), shift);
+        dom = (uint32_t)__shfl((int)dom, 0);
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
             const uint32_t li = w * kKeysPerWave + r * kWave + lane;
             const bool valid = li < n_tile;
             const uint32_t d = digit_of((K)(kr[r] - kb), shift);
-            // a row whose keys all share one digit adds once (skewed inputs)
-            const uint32_t d0 = __shfl(d, 0);
-            const uint64_t live = __ballot(valid);
-            if (__ballot(valid && d != d0) == 0) {
-                if (lane == 0 && live) atomicAdd(&hist[d0], (uint32_t)__popcll(live));
-            } else if (valid) {
-                atomicAdd(&hist[d], 1u);
-            }
+            const uint64_t md = __ballot(valid && d == dom);
+            const uint32_t nd = (uint32_t)__popcll(md);
+            if (nd && (int)lane == __ffsll((unsigned long long)md) - 1) atomicAdd(&hist[dom], nd);
+            if (valid && d != dom) atomicAdd(&hist[d], 1u);
+            // the digit stays dominant while it holds a quarter of a row
+            if (nd < kWave / 4) dom = (uint32_t)__shfl((int)d, 0);
         }
         if constexpr (kMask) {
             uint64_t am = ~0ull, om = 0;
@@ -295,10 +297,25 @@ __global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
             }
         } else {
             uint32_t* hist = &whist[0][0];   // one tile-wide count per digit
+            // the lanes holding the wave's current dominant digit take their
+            // slots with one atomic (skewed inputs), the others one each
+            uint32_t dom = digit_of((K)(key[0] - kb), shift);
+            dom = (uint32_t)__shfl((int)dom, 0);
 #pragma unroll
             for (int r = 0; r < kIt; ++r) {
                 const uint32_t li = w * kKpw + r * kWave + lane;
-                if (li < n_tile) rank[r] = atomicAdd(&hist[digit_of((K)(key[r] - kb), shift)], 1u);
+                const bool valid = li < n_tile;
+                const uint32_t d = digit_of((K)(key[r] - kb), shift);
+                const uint64_t md = __ballot(valid && d == dom);
+                const uint32_t nd = (uint32_t)__popcll(md);
+                uint32_t b0 = 0;
+                if (nd) {   // uniform
+                    const int leader = __ffsll((unsigned long long)md) - 1;
+                    if ((int)lane == leader) b0 = atomicAdd(&hist[dom], nd);
+                    b0 = (uint32_t)__shfl((int)b0, leader);
+                }
+                if (valid) rank[r] = d == dom ? b0 + (uint32_t)__popcll(md & lanes_below_mask()) : atomicAdd(&hist[d], 1u);
+                if (nd < kWave / 4) dom = (uint32_t)__shfl((int)d, 0);
             }
             __syncthreads();
             uint32_t all;
