@@ -413,6 +413,7 @@ def served_bench(count, mults, check_every):
                 del batch
             drain(True)
             st = srv.stats()
+            mem = srv.memory()
         makespan = t_last - (t0 + arrivals[0])
         # each kept result against its solo run
         same = True
@@ -434,6 +435,7 @@ def served_bench(count, mults, check_every):
                      "mean_requests_per_batch": round(count / max(st["batches"], 1), 2),
                      "max_concurrent_batches": st["max_concurrent_batches"],
                      "max_admitted_gb": round(st["max_admitted_bytes"] / 1e9, 2),
+                     "max_held_gb": round(mem["max_held_bytes"] / 1e9, 2),
                      "submit_lag_p99_ms": round(float(np.percentile(np.array(lag) * 1e3, 99)), 3),
                      "checked_against_solo": len(range(0, count, check_every)),
                      "all_equal": bool(same)})
@@ -547,9 +549,9 @@ def main():
                     help="single- vs two-stage partition at p = 4096 (0 to skip)")
     ap.add_argument("--sweep-steps", type=int, default=3,
                     help="steps per distribution of the sweep; 0 to skip")
-    ap.add_argument("--serve-requests", type=int, default=2000,
+    ap.add_argument("--serve-requests", type=int, default=20000,
                     help="requests of the served workload (0 to skip)")
-    ap.add_argument("--serve-rates", default="0.5,0.7,1.0,2.0,4.0",
+    ap.add_argument("--serve-rates", default="0.7,1.0",
                     help="arrival rates as multiples of the plain-path capacity")
     ap.add_argument("--serve-check-every", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true",

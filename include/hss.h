@@ -39,7 +39,10 @@
 extern "C" {
 #endif
 
-typedef enum { HSS_U32 = 0, HSS_U64 = 1 } hss_key_type;
+/* The last enumerator gives the type the range of a 32-bit int, so that any
+ * int a C caller passes is a value of the type (out-of-range values are
+ * rejected with HSS_ERR_INVALID_ARG). */
+typedef enum { HSS_U32 = 0, HSS_U64 = 1, HSS_KEY_TYPE_INT_RANGE_ = 0x7FFFFFFF } hss_key_type;
 
 typedef enum {
     HSS_OK = 0,
@@ -80,7 +83,15 @@ typedef struct {
                                    time, and moves off the current knobs only
                                    for a setting more than 2% faster (the
                                    outputs do not depend on the knobs)          */
-    uint32_t reserved[2];       /* must be zero */
+    uint32_t workspace_limit_mib; /* 0: no limit.  Otherwise the most device
+                                   memory, in MiB, the plan (for a batch: the
+                                   instances of each key type) may take:
+                                   a plan whose workspace (its tables, two key
+                                   buffers and the first probe buffers) would
+                                   exceed it fails with HSS_ERR_OUT_OF_MEMORY
+                                   before any device call, and so does a later
+                                   growth of its probe buffers past it        */
+    uint32_t reserved[1];       /* must be zero */
 } hss_tuning;
 
 /* Launch knobs of a plan (hss_plan_knobs); none changes any output. */
@@ -406,6 +417,13 @@ double hss_server_clock(void);
  * batches on the GPU at once and the most budget bytes admitted at once. */
 hss_status hss_server_stats(hss_server_t server, uint64_t* batches, uint64_t* requests,
                             uint64_t* keys, uint32_t* max_concurrent, uint64_t* max_admitted);
+
+/* Device bytes the server's block cache holds now (blocks of running
+ * batches and idle ones kept for reuse) and the most it has held.  Idle
+ * blocks are freed, largest first, whenever the total would exceed the HBM
+ * budget, so the total stays within it unless the running batches alone
+ * need more. */
+hss_status hss_server_memory(hss_server_t server, uint64_t* held, uint64_t* max_held);
 
 /* The launch knobs a plan (or, for a batch, its instances of one key type)
  * runs with: the defaults, or what the autotuner chose on the first call. */

@@ -47,6 +47,7 @@ EXPORTS = [
     "hss_batch_profile", "hss_batch_profile_reset", "hss_batch_profile_read",
     "hss_server_create", "hss_server_destroy", "hss_server_submit", "hss_server_poll",
     "hss_server_wait", "hss_server_clock", "hss_server_stats", "hss_server_footprint",
+    "hss_server_memory",
     "hss_plan_knobs", "hss_plan_set_knobs", "hss_batch_knobs", "hss_plan_buckets",
     "hss_staged_plan", "hss_staged_destroy", "hss_staged_workspace_bytes", "hss_staged_partition",
     "hss_staged_times", "hss_partition_static", "hss_partition_static_bytes", "hss_stream_copy",
@@ -69,7 +70,7 @@ class _Tuning(C.Structure):
                 ("force_full_sample", C.c_uint32), ("trace_level", C.c_uint32),
                 ("lsd_only", C.c_uint32), ("probes_per_round", C.c_uint32),
                 ("plain_launches", C.c_uint32), ("autotune", C.c_uint32),
-                ("reserved", C.c_uint32 * 2)]
+                ("workspace_limit_mib", C.c_uint32), ("reserved", C.c_uint32 * 1)]
 
 
 class _Knobs(C.Structure):
@@ -183,6 +184,8 @@ _lib.hss_server_clock.restype = _dbl
 _lib.hss_server_stats.argtypes = [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64),
                                   C.POINTER(_u32), C.POINTER(_u64)]
 _lib.hss_server_stats.restype = C.c_int
+_lib.hss_server_memory.argtypes = [_vp, C.POINTER(_u64), C.POINTER(_u64)]
+_lib.hss_server_memory.restype = C.c_int
 _lib.hss_plan_knobs.argtypes = [_vp, C.POINTER(_Knobs)]
 _lib.hss_plan_knobs.restype = C.c_int
 _lib.hss_plan_set_knobs.argtypes = [_vp, C.POINTER(_Knobs)]
@@ -246,10 +249,11 @@ class Plan:
     def __init__(self, n: int, p: int, eps: float, key_bytes: int = 8, payload: bool = False,
                  max_rounds: int = 0, k_override: int = 0, force_full_sample: bool = False,
                  trace_level: int = 0, lsd_only: bool = False, probes_per_round: int = 0,
-                 plain_launches: bool = False, autotune: bool = False, buckets: int | None = None):
+                 plain_launches: bool = False, autotune: bool = False, buckets: int | None = None,
+                 workspace_limit_mib: int = 0):
         tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, trace_level,
                       1 if lsd_only else 0, probes_per_round, 1 if plain_launches else 0,
-                      1 if autotune else 0)
+                      1 if autotune else 0, workspace_limit_mib)
         h = _vp()
         kt = HSS_U64 if key_bytes == 8 else HSS_U32
         if buckets is None:
@@ -496,13 +500,14 @@ class BatchPlan:
     (keys, seed[, vals]) per instance, in the same order."""
 
     def __init__(self, shapes, payload: bool = False, max_rounds: int = 0, k_override: int = 0,
-                 force_full_sample: bool = False, autotune: bool = False, probes_per_round: int = 0):
+                 force_full_sample: bool = False, autotune: bool = False, probes_per_round: int = 0,
+                 workspace_limit_mib: int = 0):
         self.shapes = [(int(n), int(p), float(e), int(kb)) for (n, p, e, kb) in shapes]
         arr = (_Shape * len(self.shapes))()
         for i, (n, p, e, kb) in enumerate(self.shapes):
             arr[i] = _Shape(n, p, HSS_U64 if kb == 8 else HSS_U32, e)
         tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, 0, 0, probes_per_round,
-                      0, 1 if autotune else 0)
+                      0, 1 if autotune else 0, workspace_limit_mib)
         h = _vp()
         _check(_lib.hss_batch_plan(C.byref(h), arr, len(self.shapes), 1 if payload else 0,
                                    C.byref(tun)), "hss_batch_plan")
@@ -657,6 +662,12 @@ class Server:
                                      C.byref(ma)), "hss_server_stats")
         return {"batches": int(b.value), "requests": int(r.value), "keys": int(k.value),
                 "max_concurrent_batches": int(mc.value), "max_admitted_bytes": int(ma.value)}
+
+    def memory(self) -> dict:
+        """Device bytes held by the server's block cache, now and at most."""
+        h, m = _u64(), _u64()
+        _check(_lib.hss_server_memory(self._h, C.byref(h), C.byref(m)), "hss_server_memory")
+        return {"held_bytes": int(h.value), "max_held_bytes": int(m.value)}
 
     @staticmethod
     def footprint(n: int, p: int, key_bytes: int = 8, payload: bool = False) -> int:

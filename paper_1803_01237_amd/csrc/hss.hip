@@ -607,34 +607,52 @@ size_t layout(Engine& E, char* base) {
     return ar.used;
 }
 
+// The probe arrays for `cap` probes laid out from `ar` (a null base only
+// measures); returns the bytes taken.
+size_t probe_layout(RoundArgs& r, Arena& ar, uint64_t cap) {
+    r.pr_key = ar.take<uint64_t>(cap);
+    r.pr_tag = ar.take<uint64_t>(cap);
+    r.pr_ivl = ar.take<uint32_t>(cap);
+    r.g_key = ar.take<uint64_t>(cap);
+    r.g_tag = ar.take<uint64_t>(cap);
+    r.ps_key = ar.take<uint64_t>(cap);
+    r.ps_tag = ar.take<uint64_t>(cap);
+    r.ps_ivl = ar.take<uint32_t>(cap);
+    r.ps_seg = ar.take<uint32_t>(cap);
+    r.pr_rank = ar.take<uint64_t>(cap);
+    return ar.used + 256;
+}
+
+size_t probe_bytes_for(uint64_t cap) {
+    RoundArgs tmp{};
+    Arena ar;
+    return probe_layout(tmp, ar, cap);
+}
+
 // Probe buffers for `need` probes and a count matrix of `cm_need` words.
 hss_status grow(Engine& E, uint64_t need, uint64_t cm_need) {
     RoundArgs& r = E.ra;
+    if (E.tune.workspace_limit_mib) {
+        // the probe buffers and count matrix this growth would leave
+        uint64_t cap = E.cap ? E.cap : 4096, words = E.cm_cap ? E.cm_cap : (1ull << 20);
+        while (cap < need) cap *= 2;
+        while (words < cm_need) words *= 2;
+        const uint64_t total = E.arena_bytes + probe_bytes_for(cap) + words * 4;
+        if (total > ((uint64_t)E.tune.workspace_limit_mib << 20))
+            return fail(HSS_ERR_OUT_OF_MEMORY, "probe buffers of " + std::to_string(cap) +
+                                                   " probes would exceed the workspace limit");
+    }
     if (need > E.cap || !E.probe_mem) {
         uint64_t cap = E.cap ? E.cap : 4096;
         while (cap < need) cap *= 2;
         if (E.probe_mem) dev_release(E.mem, E.probe_mem);
         E.probe_mem = nullptr;
         E.cap = 0;
+        E.probe_bytes = probe_bytes_for(cap);
+        HIP_TRY(dev_alloc(E.mem, &E.probe_mem, E.probe_bytes));
         Arena ar;
-        for (int pass = 0; pass < 2; ++pass) {
-            ar.used = 0;
-            r.pr_key = ar.take<uint64_t>(cap);
-            r.pr_tag = ar.take<uint64_t>(cap);
-            r.pr_ivl = ar.take<uint32_t>(cap);
-            r.g_key = ar.take<uint64_t>(cap);
-            r.g_tag = ar.take<uint64_t>(cap);
-            r.ps_key = ar.take<uint64_t>(cap);
-            r.ps_tag = ar.take<uint64_t>(cap);
-            r.ps_ivl = ar.take<uint32_t>(cap);
-            r.ps_seg = ar.take<uint32_t>(cap);
-            r.pr_rank = ar.take<uint64_t>(cap);
-            if (pass == 0) {
-                E.probe_bytes = ar.used + 256;
-                HIP_TRY(dev_alloc(E.mem, &E.probe_mem, E.probe_bytes));
-                ar.base = (char*)E.probe_mem;
-            }
-        }
+        ar.base = (char*)E.probe_mem;
+        probe_layout(r, ar, cap);
         E.cap = cap;
         r.cap = cap;
     }
@@ -676,14 +694,43 @@ void probe_sizes(const Engine& E, uint64_t* want, uint64_t* cm) {
     }
 }
 
+// Device bytes of an engine's workspace at set-up: its arena (layout), the
+// first probe buffers and count matrix (grown on demand, never shrunk), and,
+// in a fixed region, the deeper levels' count tables at their bounds.
+uint64_t workspace_estimate(Engine& E) {
+    auto up = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+    uint64_t b = up(layout(E, nullptr) + 256);
+    uint64_t want = 0, cm = 0;
+    probe_sizes(E, &want, &cm);
+    uint64_t cap = 4096;
+    while (cap < want) cap *= 2;
+    b += up(probe_bytes_for(cap));
+    uint64_t words = 1ull << 20;
+    while (words < cm) words *= 2;
+    b += up(words * 4);
+    if (E.fixed_mem) {
+        const uint64_t fbw = oversize_tile_capacity(E.n_tot) * 256, fbs = oversize_capacity(E.n_tot) * 256 + 1;
+        b += up(fbw * 4) + up(fbs * 8) + up(fbs * 4);
+    }
+    return b;
+}
+
 // Allocates the engine for its instances (E.ih filled, constants computed).
 hss_status engine_init(Engine& E) {
-    HIP_TRY(hipGetDevice(&E.device));
     Layout L;
     build_layout(E, L);
     if (E.n_tot >= (1ull << 32)) return fail(HSS_ERR_UNSUPPORTED, "more than 2^32 - 1 keys in one plan");
     if (E.max_bucket >= (1ull << 32)) return fail(HSS_ERR_UNSUPPORTED, "bucket bound >= 2^32");
     E.arena_bytes = layout(E, nullptr) + 256;
+    // the workspace limit is checked on the host, before any device call
+    if (E.tune.workspace_limit_mib) {
+        const uint64_t need = workspace_estimate(E);
+        const uint64_t limit = (uint64_t)E.tune.workspace_limit_mib << 20;
+        if (need > limit)
+            return fail(HSS_ERR_OUT_OF_MEMORY, "the workspace needs " + std::to_string(need) +
+                                                   " bytes, above the limit of " + std::to_string(limit));
+    }
+    HIP_TRY(hipGetDevice(&E.device));
     E.hh.mem = E.mem;
     HIP_TRY(dev_alloc(E.mem, &E.arena, E.arena_bytes));
     layout(E, (char*)E.arena);
@@ -1343,13 +1390,31 @@ double clock_s() {
 
 // Device and pinned blocks kept between batches: a released block is handed
 // out again to the smallest request it covers without wasting more than
-// half of it (plus 64 MiB); only a miss allocates.
+// half of it (plus 64 MiB); only a miss allocates.  The device bytes held
+// (blocks in use plus idle ones) are kept within `limit`: idle blocks are
+// freed, largest first, before an allocation would go over it and after a
+// release leaves the total over it (blocks in use are never taken back, so
+// the total exceeds the limit only while they alone do).
 struct BlockCache : MemSource {
     std::mutex mu;
     std::multimap<size_t, void*> dev_free, host_free;
     std::unordered_map<void*, size_t> dev_size, host_size;
+    size_t limit = ~size_t(0);
+    size_t held = 0, max_held = 0;     // device bytes allocated by the cache
 
     static bool fits(size_t have, size_t want) { return have >= want && have <= 2 * want + (64u << 20); }
+
+    // frees idle blocks, largest first, until `held + extra` is within the
+    // limit or nothing idle is left (called with the lock held)
+    void trim(size_t extra) {
+        while (held + extra > limit && !dev_free.empty()) {
+            auto it = std::prev(dev_free.end());
+            (void)hipFree(it->second);
+            dev_size.erase(it->second);
+            held -= it->first;
+            dev_free.erase(it);
+        }
+    }
 
     hipError_t dev_get(void** p, size_t bytes) override {
         std::lock_guard<std::mutex> g(mu);
@@ -1359,22 +1424,27 @@ struct BlockCache : MemSource {
             dev_free.erase(it);
             return hipSuccess;
         }
+        trim(bytes);
         hipError_t e = hipMalloc(p, bytes);
         if (e == hipErrorOutOfMemory && !dev_free.empty()) {   // give back what is idle, then retry
-            for (auto& kv : dev_free) {
-                (void)hipFree(kv.second);
-                dev_size.erase(kv.second);
-            }
-            dev_free.clear();
+            const size_t keep = limit;
+            limit = 0;
+            trim(0);
+            limit = keep;
             (void)hipGetLastError();
             e = hipMalloc(p, bytes);
         }
-        if (e == hipSuccess) dev_size[*p] = bytes;
+        if (e == hipSuccess) {
+            dev_size[*p] = bytes;
+            held += bytes;
+            max_held = std::max(max_held, held);
+        }
         return e;
     }
     void dev_put(void* p) override {
         std::lock_guard<std::mutex> g(mu);
         dev_free.emplace(dev_size[p], p);
+        trim(0);
     }
     hipError_t host_get(void** p, size_t bytes) override {
         std::lock_guard<std::mutex> g(mu);
@@ -1688,30 +1758,7 @@ struct FixedArena : MemSource {
 size_t fixed_bytes(Engine& E) {
     Layout L;
     build_layout(E, L);
-    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-    size_t b = up(layout(E, nullptr) + 256);
-    uint64_t want = 0, cm = 0;
-    probe_sizes(E, &want, &cm);
-    uint64_t cap = 4096;
-    while (cap < want) cap *= 2;
-    Arena ar;
-    ar.take<uint64_t>(cap);   // pr_key
-    ar.take<uint64_t>(cap);   // pr_tag
-    ar.take<uint32_t>(cap);   // pr_ivl
-    ar.take<uint64_t>(cap);   // g_key
-    ar.take<uint64_t>(cap);   // g_tag
-    ar.take<uint64_t>(cap);   // ps_key
-    ar.take<uint64_t>(cap);   // ps_tag
-    ar.take<uint32_t>(cap);   // ps_ivl
-    ar.take<uint32_t>(cap);   // ps_seg
-    ar.take<uint64_t>(cap);   // pr_rank
-    b += up(ar.used + 256);
-    uint64_t words = 1ull << 20;
-    while (words < cm) words *= 2;
-    b += up(words * 4);
-    const uint64_t fbw = oversize_tile_capacity(E.n_tot) * 256, fbs = oversize_capacity(E.n_tot) * 256 + 1;
-    b += up(fbw * 4) + up(fbs * 8) + up(fbs * 4);
-    return b;
+    return workspace_estimate(E);
 }
 
 hss_status static_shape(Engine& E, uint64_t n, uint32_t p, double eps, hss_key_type kt, bool payload) {
@@ -2114,6 +2161,7 @@ hss_status hss_server_create(hss_server_t* out, const hss_server_config* cfg) {
         S->max_keys = c.max_batch_keys ? c.max_batch_keys : (1ull << 30);
         S->max_reqs = c.max_batch_requests ? c.max_batch_requests : 1024u;
         S->budget = c.hbm_budget ? c.hbm_budget : (64ull << 30);
+        S->cache.limit = S->budget;
         const uint32_t nw = c.workers ? c.workers : 2u;
         HIP_TRY(hipGetDevice(&S->device));
         for (uint32_t w = 0; w < nw; ++w) {
@@ -2214,6 +2262,14 @@ hss_status hss_server_stats(hss_server_t S, uint64_t* batches, uint64_t* request
     if (keys) *keys = S->keys;
     if (max_concurrent) *max_concurrent = S->max_running;
     if (max_admitted) *max_admitted = S->max_admitted;
+    return HSS_OK;
+}
+
+hss_status hss_server_memory(hss_server_t S, uint64_t* held, uint64_t* max_held) {
+    if (!S) return fail(HSS_ERR_INVALID_ARG, "null server");
+    std::lock_guard<std::mutex> g(S->cache.mu);
+    if (held) *held = S->cache.held;
+    if (max_held) *max_held = S->cache.max_held;
     return HSS_OK;
 }
 

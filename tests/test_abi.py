@@ -92,3 +92,18 @@ def test_static_partition_limits_checked_on_the_host():
                 st, need, cap = lib.static_workspace_bytes(1 << 20, 256, eps, kb, pay)
                 assert st == 0 and 0 < need <= cap
     assert lib.static_workspace_bytes(10, 20, 0.05)[0] == -1
+
+
+def test_workspace_limit_fails_before_touching_the_device():
+    """A plan or batch whose workspace exceeds tuning.workspace_limit_mib fails
+    with HSS_ERR_OUT_OF_MEMORY on the host: on a host without a GPU any
+    device call would have failed with HSS_ERR_DEVICE first."""
+    import paper_1803_01237_amd as lib
+    for n, p, kb, pay in [(1 << 28, 1024, 8, False), (1 << 24, 4096, 8, True), (1 << 20, 16, 4, False)]:
+        with pytest.raises(lib.HssError) as ei:
+            lib.Plan(n, p, 0.05, key_bytes=kb, payload=pay, workspace_limit_mib=1)
+        assert ei.value.status == -3
+        assert "above the limit" in str(ei.value)
+    with pytest.raises(lib.HssError) as ei:
+        lib.BatchPlan([(1 << 20, 64, 0.05, 8), (1 << 16, 16, 0.05, 4)], workspace_limit_mib=1)
+    assert ei.value.status == -3

@@ -504,3 +504,21 @@ def test_random_plans_match_oracle(hss, case):
         assert np.array_equal(_host(ks, keys.dtype), srt.keys)
         if payload:
             assert np.array_equal(_host(vs, np.uint64), srt.vals)
+
+
+def test_workspace_limit_admits_a_plan_that_fits(hss):
+    """A plan under its workspace limit runs as without one (same outputs)."""
+    import re
+    n, p, eps, seed = 1 << 20, 16, 0.05, 3
+    _say(f"[parity] workspace limit n={n} p={p}")
+    with pytest.raises(hss.HssError) as ei:
+        hss.Plan(n, p, eps, workspace_limit_mib=1)
+    need = int(re.search(r"needs (\d+) bytes", str(ei.value)).group(1))
+    keys = _keys("uniform64", n, 41, 64)
+    kd = _dev(keys)
+    with hss.Plan(n, p, eps, workspace_limit_mib=(need >> 20) + 1) as plan:
+        ko, _, off = plan.partition(kd, seed)
+        assert plan.workspace_bytes <= need + (1 << 20)
+        with hss.Plan(n, p, eps) as ref:
+            rk, _, roff = ref.partition(kd, seed)
+        assert torch.equal(off, roff) and torch.equal(ko, rk)

@@ -166,3 +166,32 @@ def test_budget_bounds_admission(hss):
         st = srv.stats()
     assert st["max_admitted_bytes"] <= 2 * fp
     assert st["max_concurrent_batches"] <= 2
+
+
+def test_cache_stays_within_the_budget(hss):
+    """After a stream of mixed sizes the device memory the server holds
+    (blocks in use and idle) is within its HBM budget: idle blocks are freed,
+    largest first, whenever the total would go over it."""
+    budget = 192 << 20
+    rng = np.random.default_rng(11)
+    sizes = [int(2 ** rng.uniform(12, 21)) for _ in range(40)]
+    _say(f"[server] cache budget {budget}: {len(sizes)} requests of 2^12..2^21 keys")
+    checked = []
+    with hss.Server(workers=2, hbm_budget=budget) as srv:
+        for b0 in range(0, len(sizes), 8):   # in bursts, so that sizes mix in the cache
+            burst = []
+            for i in range(b0, min(b0 + 8, len(sizes))):
+                n = sizes[i]
+                keys, vals = _inputs(n, 8, True, 8600 + i)
+                p = max(1, min(n, 64))
+                burst.append((srv.submit(_dev(keys), p, 0.05, 90 + i, _dev(vals)), keys, vals, p, 90 + i))
+            for t, keys, vals, p, seed in burst:
+                r = srv.wait(t)
+                if len(checked) < 4:
+                    checked.append((r.vals_out.cpu().numpy().view(np.uint64), keys, vals, p, seed))
+        mem = srv.memory()
+        _say(f"[server] held {mem['held_bytes']} max {mem['max_held_bytes']}")
+        assert 0 < mem["held_bytes"] <= budget
+    for got, keys, vals, p, seed in checked:
+        ref = oracle.hss(keys, p, 0.05, seed, vals=vals, mode="partition", trace_level=0)
+        assert np.array_equal(got, ref.vals)
