@@ -224,8 +224,9 @@ def options_bench(keys, n, p, eps, hseed, steps):
     """The plan options of the same kernels at the headline size: HSS with one
     round (k = 1, section 4.1), exact splitting (eps = p / N, tol = 0) and a
     fixed budget of 5 p and of p probes per round (section 6); then the
-    rounds against p at eps = 2% (section 7.1) for the rate schedule and both
-    budgets, on the first 2^26 keys."""
+    rounds against p at eps = 2% (section 7.1) for the rate schedule, both
+    budgets and the same budgets drawn as section 6's picks, on the first
+    2^26 keys."""
     import torch
     import paper_1803_01237_amd as hss
     out = {}
@@ -250,12 +251,12 @@ def options_bench(keys, n, p, eps, hseed, steps):
     sub = keys[:n2]
     kout2 = torch.empty_like(sub)
     curve = {}
-    for c in (0, 5, 1):
-        label = "schedule" if c == 0 else f"budget_{c}p"
+    for c, picks in ((0, False), (5, False), (1, False), (5, True), (1, True)):
+        label = "schedule" if c == 0 else (f"picks_{c}p" if picks else f"budget_{c}p")
         curve[label] = {}
-        for pp in (64, 256, 1024, 4096):
+        for pp in (64, 256, 1024, 2048, 4096):
             off2 = torch.empty(pp + 1, dtype=torch.int64, device=keys.device)
-            with hss.Plan(n2, pp, 0.02, probes_per_round=c) as plan:
+            with hss.Plan(n2, pp, 0.02, probes_per_round=c, pick_sampler=picks) as plan:
                 plan.partition(sub, hseed, keys_out=kout2, offsets=off2)
                 tr = plan.trace()
                 curve[label][str(pp)] = {"rounds": len(tr), "probes": sum(r.m for r in tr)}

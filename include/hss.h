@@ -91,6 +91,17 @@ typedef struct {
                                    exceed it fails with HSS_ERR_OUT_OF_MEMORY
                                    before any device call, and so does a later
                                    growth of its probe buffers past it        */
+    uint32_t pick_sampler;      /* 1 (with probes_per_round = c): draw the probes
+                                   as the implementation of section 6 does:
+                                   every segment picks ceil(c N / |gamma|)
+                                   uniform positions of its whole sorted input
+                                   (with replacement; Philox counter (pick,
+                                   segment, round, 1)) and keeps those inside
+                                   the splitter intervals, each position once;
+                                   when that reaches the largest segment every
+                                   key of the intervals is taken.  The round
+                                   trace reports the pick count as the round's
+                                   threshold.  Single plans only              */
     uint32_t reserved[1];       /* must be zero */
 } hss_tuning;
 

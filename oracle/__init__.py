@@ -63,7 +63,7 @@ def lib():
         L.oracle_philox_word.argtypes = [u64, u64, u32]
         L.oracle_philox_word.restype = u32
         L.oracle_hss.argtypes = [u64, u32, u32, dbl, C.c_int, vp, vp, u64, C.c_int, u32, u32,
-                                 C.c_int, u32, C.c_int, vp, vp, vp, C.c_int]
+                                 C.c_int, u32, C.c_int, vp, vp, vp, C.c_int, C.c_int]
         L.oracle_times.argtypes = [vp, vp]
         L.oracle_hss.restype = vp
         L.oracle_local_sort.argtypes = [u64, u32, C.c_int, vp, vp, vp, vp]
@@ -167,13 +167,18 @@ class Result:
 def hss(keys: np.ndarray, p: int, eps: float, seed: int, vals: np.ndarray | None = None,
         mode: str = "partition", k_override: int = 0, max_rounds: int = 0,
         force_full_sample: bool = False, trace_level: int = 1,
-        probes_per_round: int = 0, buckets: int | None = None, threads: int = 1) -> Result:
+        probes_per_round: int = 0, buckets: int | None = None, threads: int = 1,
+        pick_sampler: bool = False) -> Result:
     """Run the whole method on the host; returns outputs and the round trace.
     threads: host threads over which the per-segment work (local sort,
     slices, draws, local histograms, piece rows) and the per-bucket work
     (exchange, bucket sort) are split; the result does not depend on it.
     probes_per_round = c > 0: a fixed budget of c q probes per round (rate
-    c q / |gamma|) instead of the rate schedule.  buckets = q (default p):
+    c q / |gamma|) instead of the rate schedule; with pick_sampler, drawn as
+    the implementation of section 6 does: ceil(c N / |gamma|) uniform picks
+    of every segment (with replacement), those outside the intervals
+    discarded, each position once (round info's thresh is then the pick
+    count).  buckets = q (default p):
     the p segments are split into q <= p buckets, as in one stage of
     multi-stage HSS (section 5.3); offsets, chi and the splitter state then
     have q+1 (resp. q-1) entries."""
@@ -194,7 +199,7 @@ def hss(keys: np.ndarray, p: int, eps: float, seed: int, vals: np.ndarray | None
     h = L.oracle_hss(n, p, q, eps, bits, _ptr(kin), _ptr(vi), seed & NONE,
                      1 if mode == "sort" else 0, k_override, max_rounds,
                      1 if force_full_sample else 0, probes_per_round, trace_level,
-                     _ptr(ko), _ptr(vo), _ptr(off), int(threads))
+                     _ptr(ko), _ptr(vo), _ptr(off), int(threads), 1 if pick_sampler else 0)
     try:
         st = L.oracle_status(h)
         res = Result(status=st)

@@ -147,6 +147,34 @@ bool budget_threshold(uint64_t domain, uint32_t p, uint32_t c, uint32_t* thresh)
     return false;
 }
 
+// The implementation of section 6 with s = c probes per processor: when the
+// splitter intervals cover the fraction delta = |gamma| / N of the input,
+// every processor picks c / delta keys from its whole (sorted) input and
+// discards those outside the intervals, so c p probes are kept in
+// expectation.  READING: the picks are uniform positions of the processor's
+// segment, drawn with replacement (a position picked twice is one probe);
+// their number is ceil(c N / |gamma|), computed in double; once it reaches
+// the largest segment every key of the intervals is taken instead (the
+// analogue of a rate of 1).  Returns true in that case, else *picks.
+bool pick_count(uint64_t n, uint64_t max_seg, uint64_t domain, uint32_t c, uint32_t* picks) {
+    double d = std::ceil(((double)c * (double)n) / (double)domain);
+    if (d >= (double)max_seg) { *picks = 0xFFFFFFFFu; return true; }
+    *picks = (uint32_t)d;
+    return false;
+}
+
+// Pick l of segment s in round j: a uniform position of the segment's n_s
+// keys from a 32-bit Philox word, floor(word n_s / 2^32).  READING: the
+// counter is (l, s, j, 1) (the last word 1 keeps these draws apart from
+// the per-key draws), the word is the block's first.
+uint64_t pick_position(uint64_t seed, uint32_t l, uint32_t s, uint32_t j, uint64_t n_s) {
+    uint32_t ctr[4] = {l, s, j, 1u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    philox4x32_10(ctr, key, out);
+    return (uint64_t)(((u128)out[0] * (u128)n_s) >> 32);
+}
+
 // Ideal rank N i / p of splitter i, exact (section 2).
 uint64_t ideal_rank(uint64_t n, uint32_t p, uint64_t i) {
     return (uint64_t)(((u128)i * (u128)n) / (u128)p);
@@ -321,7 +349,7 @@ bool before(const Problem& P, uint64_t g1, uint64_t g2) {
 // histogram still runs over the p segments.
 void determine_splitters(const Problem& P, uint32_t q, double eps, uint64_t seed,
                          uint32_t k_override, uint32_t max_rounds, int force_full,
-                         uint32_t budget, int trace_level, int threads, Run& R) {
+                         uint32_t budget, int picks_mode, int trace_level, int threads, Run& R) {
     const uint64_t n = P.n;
     const uint32_t p = P.p;
     R.c = make_constants(n, q, eps, k_override);
@@ -367,8 +395,11 @@ void determine_splitters(const Problem& P, uint32_t q, double eps, uint64_t seed
         for (uint64_t d : dom_part) tr.domain += d;
 
         uint32_t thresh;
-        bool all = budget ? budget_threshold(tr.domain, q, budget, &thresh)
-                          : sampling_threshold(n, q, R.c, j, &thresh);
+        uint64_t max_seg = 0;
+        for (uint32_t s = 0; s < p; ++s) max_seg = std::max(max_seg, P.seg_len(s));
+        bool all = picks_mode ? pick_count(n, max_seg, tr.domain, budget, &thresh)
+                   : budget   ? budget_threshold(tr.domain, q, budget, &thresh)
+                              : sampling_threshold(n, q, R.c, j, &thresh);
         if (force_full) all = true;
         tr.thresh = all ? 0xFFFFFFFFu : thresh;
         tr.all = all ? 1u : 0u;
@@ -377,14 +408,37 @@ void determine_splitters(const Problem& P, uint32_t q, double eps, uint64_t seed
         // the round's probability.
         // Every processor draws for the keys of its own segment.
         std::vector<std::vector<uint64_t>> drawn(threads < 1 ? 1 : threads);
-        split_over(p, threads, [&](int t, uint64_t s0, uint64_t s1) {
-            for (uint64_t s = s0; s < s1; ++s)
-                for (size_t k = 0; k < ivl.size(); ++k) {
-                    const auto& sl = slices[k * p + s];
-                    for (uint64_t g = sl.first; g < sl.second; ++g)
-                        if (all || philox_word(seed, g, j) < thresh) drawn[t].push_back(g);
+        if (picks_mode && !all) {
+            // section 6: thresh picks of the whole segment, those inside an
+            // interval's slice kept, each position once
+            split_over(p, threads, [&](int t, uint64_t s0, uint64_t s1) {
+                for (uint64_t s = s0; s < s1; ++s) {
+                    std::vector<std::pair<uint64_t, uint64_t>> mine;   // the segment's slices
+                    for (size_t k = 0; k < ivl.size(); ++k)
+                        if (slices[k * p + s].second > slices[k * p + s].first) mine.push_back(slices[k * p + s]);
+                    std::sort(mine.begin(), mine.end());
+                    std::vector<uint64_t> kept;
+                    for (uint32_t l = 0; l < thresh; ++l) {
+                        const uint64_t g = P.seg_start[s] + pick_position(seed, l, (uint32_t)s, j, P.seg_len((uint32_t)s));
+                        // the last slice starting at or before g
+                        auto it = std::upper_bound(mine.begin(), mine.end(), std::make_pair(g, ~(uint64_t)0));
+                        if (it != mine.begin() && g < std::prev(it)->second) kept.push_back(g);
+                    }
+                    std::sort(kept.begin(), kept.end());
+                    kept.erase(std::unique(kept.begin(), kept.end()), kept.end());
+                    drawn[t].insert(drawn[t].end(), kept.begin(), kept.end());
                 }
-        });
+            });
+        } else {
+            split_over(p, threads, [&](int t, uint64_t s0, uint64_t s1) {
+                for (uint64_t s = s0; s < s1; ++s)
+                    for (size_t k = 0; k < ivl.size(); ++k) {
+                        const auto& sl = slices[k * p + s];
+                        for (uint64_t g = sl.first; g < sl.second; ++g)
+                            if (all || philox_word(seed, g, j) < thresh) drawn[t].push_back(g);
+                    }
+            });
+        }
         std::vector<uint64_t> probes;
         for (auto& d : drawn) probes.insert(probes.end(), d.begin(), d.end());
 
@@ -495,10 +549,11 @@ oracle_run* oracle_hss(uint64_t n, uint32_t p, uint32_t q, double eps, int key_b
                        const void* keys_in, const uint64_t* vals_in, uint64_t seed,
                        int mode, uint32_t k_override, uint32_t max_rounds, int force_full,
                        uint32_t probes_per_round, int trace_level, void* keys_out,
-                       uint64_t* vals_out, uint64_t* offsets_out, int threads) {
+                       uint64_t* vals_out, uint64_t* offsets_out, int threads, int picks_mode) {
     Run* R = new Run();
     if (q == 0) q = p;
-    if (!valid_params(n, p, eps, key_bits) || q > p || !keys_in || !keys_out || !offsets_out) {
+    if (!valid_params(n, p, eps, key_bits) || q > p || !keys_in || !keys_out || !offsets_out ||
+        (picks_mode && probes_per_round == 0)) {
         R->status = -1;
         return (oracle_run*)R;
     }
@@ -508,7 +563,7 @@ oracle_run* oracle_hss(uint64_t n, uint32_t p, uint32_t q, double eps, int key_b
     R->t_local = seconds_since(t0);
     t0 = std::chrono::steady_clock::now();
     determine_splitters(P, q, eps, seed, k_override, max_rounds, force_full, probes_per_round,
-                        trace_level, threads, *R);
+                        picks_mode, trace_level, threads, *R);
     R->t_rounds = seconds_since(t0);
     if (R->status != 0) return (oracle_run*)R;
 

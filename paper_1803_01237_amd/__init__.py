@@ -70,7 +70,8 @@ class _Tuning(C.Structure):
                 ("force_full_sample", C.c_uint32), ("trace_level", C.c_uint32),
                 ("lsd_only", C.c_uint32), ("probes_per_round", C.c_uint32),
                 ("plain_launches", C.c_uint32), ("autotune", C.c_uint32),
-                ("workspace_limit_mib", C.c_uint32), ("reserved", C.c_uint32 * 1)]
+                ("workspace_limit_mib", C.c_uint32), ("pick_sampler", C.c_uint32),
+                ("reserved", C.c_uint32 * 1)]
 
 
 class _Knobs(C.Structure):
@@ -250,10 +251,10 @@ class Plan:
                  max_rounds: int = 0, k_override: int = 0, force_full_sample: bool = False,
                  trace_level: int = 0, lsd_only: bool = False, probes_per_round: int = 0,
                  plain_launches: bool = False, autotune: bool = False, buckets: int | None = None,
-                 workspace_limit_mib: int = 0):
+                 workspace_limit_mib: int = 0, pick_sampler: bool = False):
         tun = _Tuning(max_rounds, k_override, 1 if force_full_sample else 0, trace_level,
                       1 if lsd_only else 0, probes_per_round, 1 if plain_launches else 0,
-                      1 if autotune else 0, workspace_limit_mib)
+                      1 if autotune else 0, workspace_limit_mib, 1 if pick_sampler else 0)
         h = _vp()
         kt = HSS_U64 if key_bytes == 8 else HSS_U32
         if buckets is None:

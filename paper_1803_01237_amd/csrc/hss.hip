@@ -202,6 +202,7 @@ struct Engine {
     uint32_t* counts = nullptr;
     RoundArgs ra{};
     uint64_t* chi_all = nullptr;
+    uint32_t* pick_bits = nullptr;
     uint32_t* dst = nullptr;
     uint32_t* chunk0 = nullptr;
     Fences fences;
@@ -525,6 +526,8 @@ size_t layout(Engine& E, char* base) {
     r.ctr = ar.take<RoundCounters>(1);
     r.hist = ar.take<RoundHist>(E.J);
     E.chi_all = ar.take<uint64_t>(Q);
+    // section 6's sampler: one bit per tag (each instance starts at a word)
+    E.pick_bits = E.tune.pick_sampler ? ar.take<uint32_t>(n / 32 + 2 * (size_t)B + 1) : nullptr;
     E.dst = ar.take<uint32_t>(E.T > 0 ? E.T : 1);
     E.chunk0 = ar.take<uint32_t>(Q + 1);
     E.fence_base = ar.take<uint64_t>(S + 1);
@@ -773,6 +776,9 @@ hss_status engine_init(Engine& E) {
     r.thresh = E.thresh_d;
     r.all = E.all_d;
     r.budget = E.tune.probes_per_round;
+    r.picks = E.tune.pick_sampler ? 1u : 0u;
+    r.pick_bits = E.pick_bits;
+    r.pick_words = E.pick_bits ? E.n_tot / 32 + 2 * E.ih.size() + 1 : 0;
     r.pair_rank_from = E.knobs.pair_rank_from;
     r.sample_grid = E.knobs.sample_workgroups;
     r.pair_grid = E.knobs.pair_rank_workgroups;
@@ -795,7 +801,8 @@ hss_status engine_init(Engine& E) {
     r.pre_cap = 0;
     E.pre_rounds = 0;
     double expect = 0;   // largest expected number of draws below a threshold
-    if (!E.batch && !E.fixed_mem && E.ih.size() == 1 && E.n_tot >= kPresampleMin && !E.tune.lsd_only) {
+    if (!E.batch && !E.fixed_mem && E.ih.size() == 1 && E.n_tot >= kPresampleMin && !E.tune.lsd_only &&
+        !E.tune.pick_sampler) {
         for (uint32_t j = 1; j <= kPreRounds && j <= E.J; ++j) {
             if (L.all[j - 1] || (j > 1 && E.tune.probes_per_round)) break;
             E.pre_thresh[j - 1] = L.thresh[j - 1];
@@ -1625,6 +1632,8 @@ hss_status plan_args(uint64_t n, uint32_t p, uint32_t q, double eps, hss_key_typ
     if (tuning) {
         for (uint32_t x : tuning->reserved)
             if (x) return fail(HSS_ERR_INVALID_ARG, "reserved tuning fields must be zero");
+        if (tuning->pick_sampler && !tuning->probes_per_round)
+            return fail(HSS_ERR_INVALID_ARG, "pick_sampler needs probes_per_round > 0");
     }
     if (n >= (1ull << 32)) return fail(HSS_ERR_UNSUPPORTED, "N >= 2^32 is not supported");
     return HSS_OK;
@@ -1978,6 +1987,7 @@ hss_status hss_batch_plan(hss_batch_t* out, const hss_instance_shape* shapes, ui
                 if (x) return fail(HSS_ERR_INVALID_ARG, "reserved tuning fields must be zero");
             if (tuning->lsd_only) return fail(HSS_ERR_UNSUPPORTED, "lsd_only is for single plans");
             if (tuning->trace_level) return fail(HSS_ERR_UNSUPPORTED, "traces are for single plans");
+            if (tuning->pick_sampler) return fail(HSS_ERR_UNSUPPORTED, "pick_sampler is for single plans");
         }
         hss_batch_s* Bt = new (std::nothrow) hss_batch_s();
         if (!Bt) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -2404,8 +2414,8 @@ hss_status hss_staged_plan(hss_staged_t* out, uint64_t n, uint32_t p, uint32_t g
         if (groups == 0 || p == 0 || p % groups != 0)
             return fail(HSS_ERR_INVALID_ARG, "need groups >= 1 dividing p");
         if (!(eps2 > 0.0 && eps2 < 1.0)) return fail(HSS_ERR_INVALID_ARG, "need 0 < eps2 < 1");
-        if (tuning && (tuning->trace_level || tuning->lsd_only))
-            return fail(HSS_ERR_UNSUPPORTED, "traces and lsd_only are for single plans");
+        if (tuning && (tuning->trace_level || tuning->lsd_only || tuning->pick_sampler))
+            return fail(HSS_ERR_UNSUPPORTED, "traces, lsd_only and pick_sampler are for single plans");
         hss_status st = plan_args(n, p, groups, eps1, kt, tuning);
         if (st != HSS_OK) return st;
         std::unique_ptr<hss_staged_s> P(new (std::nothrow) hss_staged_s());

@@ -460,6 +460,13 @@ struct RoundArgs {
     uint8_t* all;                  // n_inst x J: 1 = every tag of the domain is a probe
     uint32_t budget;               // c > 0: rate c p / |gamma| set on the device each round
                                    // (one instance)
+    uint32_t picks;                // 1 (with a budget c): section 6's sampler, ceil(c N /
+                                   // |gamma|) picks of every segment per round, kept when
+                                   // inside an interval (one instance); the round's
+                                   // threshold is the pick count
+    uint32_t* pick_bits;           // picks: one bit per tag, set by a kept pick (each
+                                   // position kept once); cleared after every round
+    uint64_t pick_words;           // words of pick_bits
     uint32_t pair_rank_from;       // first round ranked per (probe, segment) pair inside
                                    // the probe's interval slice (earlier: by segment chunks)
     uint32_t sample_grid;          // workgroups of the sampler

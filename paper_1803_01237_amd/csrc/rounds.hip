@@ -362,6 +362,7 @@ __device__ void sample_from_list(const RoundArgs& a, const uint32_t* list, uint3
 template <typename K, bool kSingle>
 __global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint32_t round) {
     constexpr uint32_t kNoBlock = 0xFFFFFFFFu;   // start of the entries past the list
+    if (a.picks && !a.all[round - 1]) return;   // the picks of section 6 draw this round
     if (kSingle && round <= kPreRounds && a.pre_list[round - 1]) {
         const uint32_t cnt = *a.pre_cnt[round - 1];
         if (cnt <= a.pre_cap) {   // uniform: the round's draws were taken ahead
@@ -499,6 +500,97 @@ __global__ __launch_bounds__(kT) void sample_kernel(RoundArgs a, uint32_t round)
     if (fill) flush_stage(a, st_key, st_tag, st_ivl, fill);
 }
 
+// Section 6's sampler (one instance): thread per pick l of segment s, a
+// uniform position of the segment from Philox word 0 of counter (l, s, j, 1),
+// floor(word n_s / 2^32).  The pick is kept when it lies in the slice of an
+// interval in its segment (one binary search, as above) and its tag's bit
+// was not yet set this round (a position picked twice is one probe).
+template <typename K>
+__global__ __launch_bounds__(kT) void pick_sample_kernel(RoundArgs a, uint32_t round) {
+    if (halted(a) || a.all[round - 1]) return;
+    const uint32_t n_ivl = a.ctr->n_ivl;
+    if (n_ivl == 0) return;
+    const InstDesc D = a.inst[0];
+    const uint32_t picks = a.thresh[round - 1];
+    const uint64_t total = (uint64_t)D.p * picks;
+    const uint64_t seed = a.run[0].seed;
+    const K* B = (const K*)a.B;
+    const uint32_t lane = lane_id();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    // whole waves step together (the probe slots are taken once per wave)
+    for (uint64_t xb = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x - lane); xb < total; xb += stride) {
+        const uint64_t x = xb + lane;
+        bool take = x < total;
+        uint32_t kl = 0;
+        uint64_t g = 0;
+        if (take) {
+            const uint32_t s = (uint32_t)(x / picks), l = (uint32_t)(x - (uint64_t)s * picks);
+            const uint32_t seg = D.seg0 + s;
+            const uint64_t sb = a.seg_off[seg] - D.pos0;
+            const uint64_t ns = a.seg_off[seg + 1] - a.seg_off[seg];
+            const Philox4 w = philox10(l, s, round, 1u, (uint32_t)seed, (uint32_t)(seed >> 32));
+            g = sb + (((uint64_t)w.v[0] * ns) >> 32);
+            auto bounds = [&](uint32_t k, uint64_t* ga, uint64_t* gb) {
+                const uint32_t row = a.ivl_row[k];
+                slice_bounds(a, D, row - D.row0, s, a.lrank[row] == kNone, a.urank[row] == kNone, ga, gb);
+            };
+            uint32_t kh = n_ivl;   // the last interval whose slice starts at or before g
+            uint64_t ga, gb;
+            bounds(0, &ga, &gb);
+            if (ga > g) {
+                take = false;
+            } else {
+                while (kh - kl > 1) {
+                    const uint32_t mid = (kl + kh) >> 1;
+                    uint64_t ma, mb;
+                    bounds(mid, &ma, &mb);
+                    if (ma <= g) kl = mid; else kh = mid;
+                }
+                bounds(kl, &ga, &gb);
+                take = g >= ga && g < gb;
+            }
+            if (take) {
+                const uint32_t bit = 1u << (g & 31);
+                take = (atomicOr(&a.pick_bits[(D.pos0 >> 5) + (g >> 5)], bit) & bit) == 0;
+            }
+        }
+        const uint64_t mask = __ballot(take);
+        if (!mask) continue;   // uniform
+        unsigned long long base = 0;
+        const int leader = __ffsll((long long)mask) - 1;
+        if ((int)lane == leader) base = atomicAdd(&a.ctr->m, (unsigned long long)__popcll(mask));
+        base = shfl_u64(base, leader);
+        bool stored = false;
+        if (take) {
+            const uint64_t o = base + __popcll(mask & lanes_below_mask());
+            if (o < a.cap) {
+                a.pr_key[o] = (uint64_t)B[D.pos0 + g];
+                a.pr_tag[o] = g;
+                a.pr_ivl[o] = kl;
+                stored = true;
+            } else {
+                atomicOr(&a.ctr->overflow, 1u);
+            }
+        }
+        add_interval_counts(a.ivl_pcnt, kl, stored ? 1u : 0u);
+    }
+}
+
+// The bits of this round's kept picks, cleared for the next round (every
+// set bit belongs to a stored probe unless the probe buffers overran, when
+// the whole map is cleared before the rounds start again).
+__global__ void pick_clear_kernel(RoundArgs a) {
+    const uint64_t m = min(a.ctr->m_stored, a.cap);
+    const uint64_t pos0 = a.inst[0].pos0;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+        a.pick_bits[(pos0 >> 5) + (a.pr_tag[e] >> 5)] = 0;
+}
+
+__global__ void pick_clear_all_kernel(uint32_t* bits, uint64_t words) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
+        bits[i] = 0;
+}
+
 // Fixed probe budget (one instance): the round's acceptance threshold from
 // the domain just measured, floor(q 2^32) with q = c p / |gamma| in double,
 // or every tag when q >= 1.
@@ -521,9 +613,22 @@ __global__ void budget_rate_kernel(RoundArgs a, uint32_t round) {
         const uint32_t k0 = first_of(I), k1 = first_of(I + 1);
         const uint64_t dom = a.ivl_dom[k1] - a.ivl_dom[k0];
         if (dom == 0) continue;   // no interval left in this instance
-        const double q = ((double)a.budget * (double)a.inst[I].q) / (double)dom;
-        const bool all = q >= 1.0;
-        a.thresh[(uint64_t)I * a.J + round - 1] = all ? 0xFFFFFFFFu : (uint32_t)floor(q * 4294967296.0);
+        const InstDesc& D = a.inst[I];
+        bool all;
+        uint32_t th;
+        if (a.picks) {
+            // section 6: ceil(c N / |gamma|) picks of every segment, or every
+            // key of the intervals once that reaches the largest segment
+            const double d = ceil(((double)a.budget * (double)D.n) / (double)dom);
+            const uint64_t max_seg = (D.n + D.p - 1) / D.p;
+            all = d >= (double)max_seg;
+            th = all ? 0xFFFFFFFFu : (uint32_t)d;
+        } else {
+            const double q = ((double)a.budget * (double)D.q) / (double)dom;
+            all = q >= 1.0;
+            th = all ? 0xFFFFFFFFu : (uint32_t)floor(q * 4294967296.0);
+        }
+        a.thresh[(uint64_t)I * a.J + round - 1] = th;
         a.all[(uint64_t)I * a.J + round - 1] = all ? 1 : 0;
     }
 }
@@ -1286,6 +1391,9 @@ hipError_t launch_presample(uint64_t seed, uint64_t n, uint32_t round, uint32_t 
 
 hipError_t launch_round_init(const RoundArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(round_init_kernel, dim3(grid_for(a.n_rows, kT)), dim3(kT), 0, s, a);
+    if (a.picks)
+        hipLaunchKernelGGL(pick_clear_all_kernel, dim3(grid_for(a.pick_words, kT, 4096)), dim3(kT), 0, s,
+                           a.pick_bits, a.pick_words);
     return hipGetLastError();
 }
 
@@ -1313,6 +1421,10 @@ hipError_t launch_round_head(const RoundArgs& a, uint32_t j, hipStream_t s) {
     } else {
         if (a.key_bytes == 4) hipLaunchKernelGGL((sample_kernel<uint32_t, false>), dim3(a.sample_grid), dim3(kT), 0, s, a, j);
         else hipLaunchKernelGGL((sample_kernel<uint64_t, false>), dim3(a.sample_grid), dim3(kT), 0, s, a, j);
+    }
+    if (a.picks && a.n_inst == 1) {
+        if (a.key_bytes == 4) hipLaunchKernelGGL(pick_sample_kernel<uint32_t>, dim3(a.sample_grid), dim3(kT), 0, s, a, j);
+        else hipLaunchKernelGGL(pick_sample_kernel<uint64_t>, dim3(a.sample_grid), dim3(kT), 0, s, a, j);
     }
     hipLaunchKernelGGL(probe_scan_kernel, dim3(1), dim3(kScanT), 0, s, a, j);
     hipLaunchKernelGGL(group_kernel, dim3(grid_for(a.cap, kT, 4096)), dim3(kT), 0, s, a);
@@ -1344,6 +1456,7 @@ hipError_t launch_round_tail(const RoundArgs& a, uint32_t j, hipStream_t s, bool
     const uint64_t copy_tiles = (uint64_t)((2 * a.n_rows + kCopySlots - 1) / kCopySlots) *
                                 ((a.p_max + kCopySegs - 1) / kCopySegs);
     hipLaunchKernelGGL(settle_copy_kernel, dim3((unsigned)std::min<uint64_t>(copy_tiles, 16384)), dim3(256), 0, s, a);
+    if (a.picks) hipLaunchKernelGGL(pick_clear_kernel, dim3(grid_for(a.cap, kT, 4096)), dim3(kT), 0, s, a);
     return hipGetLastError();
 }
 

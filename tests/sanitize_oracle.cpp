@@ -27,7 +27,7 @@ void check(bool ok, const char* what, uint64_t n, uint32_t p) {
 }
 
 void run(uint64_t n, uint32_t p, uint32_t q, double eps, int bits, bool payload, int mode, int trace,
-         int threads, uint32_t budget, uint64_t seed, int dups) {
+         int threads, uint32_t budget, uint64_t seed, int dups, int picks = 0) {
     uint64_t x = seed * 0x9E3779B97F4A7C15ULL + 1;
     std::vector<uint64_t> k64(n), vals(n);
     std::vector<uint32_t> k32(n);
@@ -44,7 +44,7 @@ void run(uint64_t n, uint32_t p, uint32_t q, double eps, int bits, bool payload,
     std::vector<uint64_t> vo(n), off((q ? q : p) + 1);
     void* kout = bits == 32 ? (void*)ko32.data() : (void*)ko64.data();
     oracle_run* h = oracle_hss(n, p, q, eps, bits, kin, payload ? vals.data() : nullptr, seed, mode, 0, 0, 0,
-                               budget, trace, kout, payload ? vo.data() : nullptr, off.data(), threads);
+                               budget, trace, kout, payload ? vo.data() : nullptr, off.data(), threads, picks);
     const int st = oracle_status(h);
     check(st == 0, "status", n, p);
     if (st == 0) {
@@ -91,6 +91,8 @@ int main() {
     run(20000, 32, 0, 0.05, 64, true, 1, 2, 4, 0, 8, 101);         // many duplicates
     run(20000, 25, 0, 0.05, 64, true, 0, 1, 2, 0, 9, 1);           // all equal
     run(50000, 50, 0, 0.05, 64, false, 0, 1, 3, 5, 10, 0);         // probe budget
+    run(50000, 50, 0, 0.05, 64, true, 1, 2, 3, 5, 11, 0, 1);       // the picks of section 6
+    run(30000, 64, 0, 0.02, 32, false, 0, 1, 2, 1, 12, 300, 1);    // picks, duplicates
     std::vector<uint64_t> k(1000), ko(1000), v(1000), vo(1000);
     uint64_t x = 77;
     for (auto& a : k) a = next(x);
@@ -105,7 +107,7 @@ int main() {
     (void)oracle_philox_word(1, 2, 3);
     // invalid arguments: a handle with status -1, freed
     oracle_run* h = oracle_hss(10, 11, 0, 0.1, 64, k.data(), nullptr, 1, 0, 0, 0, 0, 0, 0, ko.data(), nullptr,
-                               vo.data(), 1);
+                               vo.data(), 1, 0);
     check(oracle_status(h) == -1, "invalid", 10, 11);
     oracle_free(h);
     std::printf(failures ? "oracle sanitize: %d failures\n" : "oracle sanitize: ok\n", failures);

@@ -107,3 +107,10 @@ def test_workspace_limit_fails_before_touching_the_device():
     with pytest.raises(lib.HssError) as ei:
         lib.BatchPlan([(1 << 20, 64, 0.05, 8), (1 << 16, 16, 0.05, 4)], workspace_limit_mib=1)
     assert ei.value.status == -3
+
+
+def test_pick_sampler_options_checked_on_the_host():
+    import paper_1803_01237_amd as lib
+    with pytest.raises(lib.HssError) as ei:
+        lib.Plan(1000, 10, 0.05, pick_sampler=True)   # needs probes_per_round
+    assert ei.value.status == -1

@@ -640,3 +640,66 @@ def test_threads_do_not_change_the_result(case):
                       "settled", "chi"):
                 assert np.array_equal(getattr(ra, f), getattr(rb, f)), f
     assert all(x >= 0 for x in one.times) and one.times[0] > 0
+
+
+# ------------------------------------------------- section 6 pick sampler ----
+
+@pytest.mark.parametrize("kind,n,p,eps,c,seed", [("uniform64", 20_000, 16, 0.02, 5, 3),
+                                                 ("SKEW2", 12_000, 12, 0.05, 1, 4),
+                                                 ("zipf_morton", 30_001, 40, 0.05, 5, 5)])
+def test_pick_sampler_follows_section6(kind, n, p, eps, c, seed, rocrand_philox):
+    """Each round's probes are exactly the distinct positions, among
+    ceil(c N / |gamma|) picks of every segment (rocRAND Philox words of
+    counter (pick, segment, round, 1) scaled to the segment), that lie
+    strictly inside an unsettled interval; every key of the intervals once the
+    picks reach the largest segment."""
+    keys = synth.make(kind, n, seed)
+    r = oracle.hss(keys, p, eps, seed, probes_per_round=c, pick_sampler=True)
+    assert r.status == 0
+    tr = R.tag_rank(keys, p)
+    idl = R.ideal(n, p)
+    starts = [(s * n) // p for s in range(p + 1)]
+    max_seg = max(starts[s + 1] - starts[s] for s in range(p))
+    prev = None
+    for j, rd in enumerate(r.rounds, start=1):
+        dom = _domain_from_state(n, p, tr, prev, idl, r.tol)
+        domain = int(dom.sum())
+        assert rd.domain == domain
+        picks = math.ceil(float(c) * float(n) / float(domain))
+        if picks >= max_seg:
+            assert rd.all == 1
+            chosen = set(np.nonzero(dom)[0].tolist())
+        else:
+            assert rd.all == 0 and rd.thresh == picks
+            S, J, G, where = [], [], [], []
+            for s in range(p):
+                for l in range(picks):
+                    # rocRAND's counter: word 0 of block (offset / 4) in
+                    # subsequence j + 2^32, i.e. counter (l, s, j, 1)
+                    S.append(seed); J.append(j + (1 << 32)); G.append(4 * (l + (s << 32)))
+                    where.append(s)
+            words = rocrand_philox(S, J, G)
+            chosen = set()
+            for s, w in zip(where, words):
+                ns = starts[s + 1] - starts[s]
+                g = starts[s] + ((w * ns) >> 32)
+                if dom[g]:
+                    chosen.add(g)
+        assert sorted(chosen) == sorted(int(t) for t in rd.probe_tag)
+        prev = rd
+    assert all(prev.settled)
+
+
+def test_pick_sampler_draws_cp_probes_per_round():
+    """In expectation c p probes per round: the mean over seeds of every
+    round's probe count lies near c p (the pick count is rounded up, and a
+    position picked twice counts once)."""
+    n, p, c = 1 << 17, 64, 5
+    keys = synth.make("uniform64", n, 9)
+    ms = []
+    for seed in range(12):
+        r = oracle.hss(keys, p, 0.02, 100 + seed, probes_per_round=c, pick_sampler=True,
+                       trace_level=0)
+        assert r.status == 0
+        ms += [rd.m / (c * p) for rd in r.rounds if not rd.all]
+    assert 0.85 < float(np.mean(ms)) < 1.3, np.mean(ms)

@@ -522,3 +522,45 @@ def test_workspace_limit_admits_a_plan_that_fits(hss):
         with hss.Plan(n, p, eps) as ref:
             rk, _, roff = ref.partition(kd, seed)
         assert torch.equal(off, roff) and torch.equal(ko, rk)
+
+
+PICK_CASES = [
+    # kind, n, p, eps, seed, bits, payload, picks per segment per round in expectation
+    ("uniform64", 1 << 18, 64, 0.02, 51, 64, False, 5),
+    ("SKEW2", 100_000, 16, 0.05, 52, 64, True, 1),       # duplicates, many picked twice
+    ("uniform32", 1 << 17, 32, 0.02, 53, 32, True, 3),
+    ("zipf_morton", 1 << 21, 256, 0.05, 54, 64, True, 5),
+    ("uniform64", 1 << 22, 1024, 0.02, 55, 64, False, 5),
+]
+
+
+@pytest.mark.parametrize("case", PICK_CASES, ids=[f"{c[0]}-{c[1]}-p{c[2]}-c{c[7]}" for c in PICK_CASES])
+def test_pick_sampler_matches_oracle(hss, case):
+    """Section 6's sampler (picks of the whole segment, those outside the
+    intervals discarded): every round's picks, probes, ranks, local
+    histograms and splitter state, and the outputs, equal the oracle's; a
+    second call on the same plan as well (the pick bits are cleared)."""
+    kind, n, p, eps, seed, bits, payload, c = case
+    _say(f"[parity] picks {kind} n={n} p={p} eps={eps} c={c} payload={payload}")
+    keys = _keys(kind, n, seed, bits)
+    vals = (np.arange(n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)) if payload else None
+    kd = _dev(keys)
+    vd = None if vals is None else _dev(vals)
+    ref = oracle.hss(keys, p, eps, seed, vals=vals, mode="partition", probes_per_round=c,
+                     pick_sampler=True, trace_level=2, threads=ORACLE_THREADS)
+    assert ref.status == 0
+    for trace in (2, 0):
+        with hss.Plan(n, p, eps, key_bytes=keys.itemsize, payload=payload, trace_level=trace,
+                      probes_per_round=c, pick_sampler=True) as plan:
+            for call in range(2):
+                ko, vo, off = plan.partition(kd, seed, vd)
+                assert np.array_equal(_host(off, np.uint64), ref.offsets), (trace, call)
+                assert np.array_equal(_host(ko, keys.dtype), ref.keys), (trace, call)
+                if payload:
+                    assert np.array_equal(_host(vo, np.uint64), ref.vals), (trace, call)
+                if trace:
+                    _compare_trace(plan, ref, p)
+                else:
+                    tr = plan.trace()
+                    assert [(a.domain, a.m, a.thresh, a.all) for a in tr] == \
+                        [(b.domain, b.m, b.thresh, b.all) for b in ref.rounds]
