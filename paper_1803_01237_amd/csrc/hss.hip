@@ -622,6 +622,7 @@ size_t probe_layout(RoundArgs& r, Arena& ar, uint64_t cap) {
     r.ps_tag = ar.take<uint64_t>(cap);
     r.ps_ivl = ar.take<uint32_t>(cap);
     r.ps_seg = ar.take<uint32_t>(cap);
+    r.ps_row = ar.take<uint32_t>(cap);
     r.pr_rank = ar.take<uint64_t>(cap);
     return ar.used + 256;
 }

@@ -526,6 +526,7 @@ struct RoundArgs {
     uint64_t* ps_tag;
     uint32_t* ps_ivl;
     uint32_t* ps_seg;
+    uint32_t* ps_row;              // the interval's splitter row, with kRowLNone / kRowUNone
     uint64_t* pr_rank;
     uint32_t* cmat;                // count matrix, capacity cm_cap words
     uint64_t cm_cap;
@@ -540,6 +541,11 @@ struct RoundArgs {
 
 constexpr uint32_t kRankChunk = 1u << 15;   // keys of a segment per rank workgroup
 constexpr uint32_t kNoSel = 0xFFFFFFFFu;    // empty selection slot
+// Flags of a sorted probe's splitter row (ps_row): the interval is open below
+// (L = -infinity) or above (U = +infinity); rows are below 2^30.
+constexpr uint32_t kRowLNone = 1u << 31;
+constexpr uint32_t kRowUNone = 1u << 30;
+constexpr uint32_t kRowMask = kRowUNone - 1;
 
 hipError_t launch_counters_reset(RoundCounters* ctr, hipStream_t s);
 // Start of a call's rounds: every splitter unsettled with open bounds.

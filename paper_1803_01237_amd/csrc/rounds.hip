@@ -744,6 +744,13 @@ __global__ void group_kernel(RoundArgs a) {
     }
 }
 
+// The splitter row of interval k with its open-end flags, kept with each
+// sorted probe so that the rank search reads it with the probe.
+__device__ __forceinline__ uint32_t probe_row(const RoundArgs& a, uint32_t k) {
+    const uint32_t row = a.ivl_row[k];
+    return row | (a.lrank[row] == kNone ? kRowLNone : 0u) | (a.urank[row] == kNone ? kRowUNone : 0u);
+}
+
 // Workgroup per kOrderLanes probes of one interval: each probe's place among
 // the interval's probes in the order (key, tag), counted against tiles of
 // the interval staged in LDS, an eighth of every tile per wave; the probe
@@ -802,6 +809,7 @@ __global__ __launch_bounds__(kOrderThreads) void order_kernel(RoundArgs a) {
     a.ps_tag[pos] = tag;
     a.ps_ivl[pos] = k;
     a.ps_seg[pos] = D.seg0 + lo;
+    a.ps_row[pos] = probe_row(a, k);
     a.pr_rank[pos] = 0;   // the rank reduction adds into it
 }
 
@@ -1039,10 +1047,11 @@ __global__ __launch_bounds__(256) void rank_pairs_kernel(RoundArgs a) {
         if (t == s) {
             cnt = a.ps_tag[e] - (s0 - D.pos0);         // its own place
         } else {
-            const uint32_t row = a.ivl_row[a.ps_ivl[e]];
+            const uint32_t rf = a.ps_row[e];
+            const uint32_t row = rf & kRowMask;
             const uint64_t cell = D.tab0 + (uint64_t)(row - D.row0) * D.p + sl;
-            const uint64_t lo = a.lrank[row] == kNone ? 0 : a.lpos[cell];
-            const uint64_t hi = a.urank[row] == kNone ? a.seg_off[s + 1] - s0 : a.upos[cell];
+            const uint64_t lo = (rf & kRowLNone) ? 0 : a.lpos[cell];
+            const uint64_t hi = (rf & kRowUNone) ? a.seg_off[s + 1] - s0 : a.upos[cell];
             if (hi <= lo) {
                 cnt = lo;
             } else {
@@ -1100,6 +1109,7 @@ __global__ void probe_finish_kernel(RoundArgs a) {
         }
         a.ps_ivl[pos] = k;
         a.ps_seg[pos] = D.seg0 + lo;
+        a.ps_row[pos] = probe_row(a, k);
         a.pr_rank[pos] = 0;
     }
 }
