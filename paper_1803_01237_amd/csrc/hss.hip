@@ -588,8 +588,6 @@ size_t layout(Engine& E, char* base) {
     E.sl.count = ar.take<uint32_t>(1);
     E.sl.beg = ar.take<uint64_t>(slc);
     E.sl.len = ar.take<uint32_t>(slc);
-    E.sl.bits = ar.take<uint8_t>(slc);
-    E.sl.base = ar.take<uint64_t>(slc);
     E.sl.seg = ar.take<uint32_t>(slc);
     E.sl.capacity = (uint32_t)slc;
     E.sl.err = list_err;

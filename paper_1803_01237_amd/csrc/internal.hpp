@@ -264,13 +264,11 @@ struct LevelWork {
 };
 
 // Sub-buckets that fit LDS but hold a large group of keys equal in their
-// next 8 bits, collected on the device for the LDS-LSD kernel.
+// next bits, collected on the device for the slow-path kernel.
 struct SlowList {
     uint32_t* count = nullptr;
     uint64_t* beg = nullptr;           // capacity slow_capacity()
     uint32_t* len = nullptr;
-    uint8_t* bits = nullptr;           // bits of key - base below which keys still differ
-    uint64_t* base = nullptr;          // key offset of the entry's segment
     uint32_t* seg = nullptr;           // segment of the entry
     uint32_t capacity = 0;
     uint32_t* err = nullptr;

@@ -13,9 +13,10 @@
 //          each key's place inside its group is counted directly (keys
 //          smaller, or equal and earlier) unless that costs more than
 //          kRankBudget comparisons per key;
-//        - then the sub-bucket is listed for a second kernel that runs LSD
-//          counting passes in LDS over the remaining digits, skipping digits
-//          on which all its keys agree
+//        - then the sub-bucket is listed for a second kernel that sorts
+//          it by an on-chip sample sort: classes between and equal to the
+//          distinct values of 64 sampled keys (a run of equal keys is placed
+//          in one step), the keys of each unequal class ranked directly
 //   3. sub-buckets above kCapT go through deeper levels of the same MSD pass
 //      on the 8 bits below their top, each range taking its own digit and
 //      alternating between the temporary buffer and the output, with the
@@ -38,14 +39,9 @@ static_assert(kDirectSegMax <= (uint32_t)kCapSmall, "direct segments fit the sma
 constexpr int kCapLarge = 4096;              // same for the bucket sort
 constexpr uint32_t kGroupMax = 32;           // groups up to this size never leave the fast path
 // The fast path ranks each key against its group: sum over groups of size^2
-// comparisons.  Above kRankBudget per key the LDS-LSD passes are cheaper.
+// comparisons.  Above kRankBudget per key the slow path below is cheaper.
 constexpr uint32_t kRankBudget = 64;
 constexpr int kGroupBits = 9;                // bits of the second-level groups of the fast path
-
-template <typename K>
-__device__ __forceinline__ uint32_t dig(K k, int shift) {
-    return (uint32_t)(k >> shift) & 0xFFu;
-}
 
 // Records the key written at output position o of segment seg when o falls
 // on a fence position of that segment.
@@ -66,81 +62,12 @@ __device__ __forceinline__ void put_fence(const FenceSink& fs, uint64_t o, uint6
     if ((rel & (kFenceStride - 1)) == 0) fs.dst[rel / kFenceStride] = key;
 }
 
-// Stable counting pass in LDS: the n keys of `sk` (with indices `si`, or the
-// identity when null) are placed by the digit of key - kbase at `shift` into
-// `dk` / `di`.
-// Leaves the digit starts in start[0..256] and the largest digit count in
-// *max_count.  Wave w handles the keys [w*cw, (w+1)*cw) in rows of 64.
-template <typename K, int kCapT>
-__device__ void lds_pass(const K* sk, const uint16_t* si, K* dk, uint16_t* di, uint32_t n,
-                         int shift, K kbase, uint32_t (*whist)[256], uint32_t* start,
-                         uint32_t* scratch, uint32_t* max_count) {
-    const uint32_t cw = ((n + kW * kWave - 1) / (kW * kWave)) * kWave;
-    const uint32_t rows = cw / kWave;
-    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
-    for (int i = threadIdx.x; i < kW * 256; i += kT) (&whist[0][0])[i] = 0;
-    if (threadIdx.x == 0) *max_count = 0;
-    __syncthreads();
-    constexpr int kRows = kCapT / kT;
-    uint32_t rank[kRows];
-    uint32_t dg[kRows];
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        rank[r] = 0;
-        dg[r] = 0;
-        if ((uint32_t)r < rows) {      // uniform over the wave
-            const uint32_t idx = w * cw + r * kWave + lane;
-            const bool valid = idx < n;
-            const uint32_t d = valid ? dig((K)(sk[idx] - kbase), shift) : 0u;
-            const uint64_t live = __ballot(valid);
-            const uint64_t m = match_byte(d, live);
-            const int leader = valid ? (int)(__ffsll((unsigned long long)m) - 1) : (int)lane;
-            uint32_t old = 0;
-            if (valid && (int)lane == leader) {
-                old = whist[w][d];
-                whist[w][d] = old + (uint32_t)__popcll(m);
-            }
-            old = __shfl(old, leader);
-            rank[r] = old + (uint32_t)__popcll(m & lanes_below_mask());
-            dg[r] = d;
-        }
-    }
-    __syncthreads();
-    {
-        const uint32_t d = threadIdx.x;
-        uint32_t c = 0;
-#pragma unroll
-        for (int ww = 0; ww < kW; ++ww) {
-            const uint32_t t = whist[ww][d];
-            whist[ww][d] = c;
-            c += t;
-        }
-        uint32_t all;
-        start[d] = block_exclusive_scan<uint32_t, kT>(c, scratch, &all);
-        if (d == 0) start[256] = all;
-        if (c) atomicMax(max_count, c);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-        if ((uint32_t)r < rows) {
-            const uint32_t idx = w * cw + r * kWave + lane;
-            if (idx < n) {
-                const uint32_t pos = start[dg[r]] + whist[w][dg[r]] + rank[r];
-                dk[pos] = sk[idx];
-                di[pos] = si ? si[idx] : (uint16_t)idx;
-            }
-        }
-    }
-    __syncthreads();
-}
-
 // Fast path, one workgroup per sub-bucket of at most kCapT keys: keys stay in
 // registers, are dropped into their group (next kGB bits) in LDS in any order,
 // and each key's rank inside its group is counted by (key, input index), or
 // by (key, place in the group) for keys without payload.
 // Sub-buckets whose large groups (above kGroupMax) would take more than
-// kRankBudget comparisons per key go to the LDS-LSD list, sub-buckets above
+// kRankBudget comparisons per key go to the slow list, sub-buckets above
 // kCapT to the oversize list.
 // Work of the small sort: entries [0, n_msd) are the sub-buckets of the MSD
 // pass (entry = 256 * pass segment + digit), entries [n_msd, n_msd +
@@ -375,8 +302,6 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
             }
             sl.beg[e] = base;
             sl.len[e] = n;
-            sl.bits[e] = (uint8_t)bits;
-            sl.base[e] = (uint64_t)kbase;
             sl.seg[e] = seg;
         }
         return;
@@ -443,64 +368,204 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
     }
 }
 
-// Sub-buckets of at most kCap keys with large groups (duplicates or
-// clustered keys): LSD counting passes in LDS over the digits below `bits`
-// that vary, from the input order.
+// Sub-buckets of at most kCap keys with large groups: runs of equal keys, or
+// keys clustered in a few groups of their next bits.  An on-chip sample sort.
+// Every key and payload is loaded once, into registers (wave w holds the keys
+// [w cw, (w+1) cw) in rows of 64).  The distinct values S_0 < ... < S_{m-1}
+// of 64 sampled keys split the keys into 2m + 1 classes in key order: class
+// 2j + 1 holds the keys equal to S_j, class 2j those strictly between S_{j-1}
+// and S_j.  A stable counting pass over the classes places every key: a class
+// of equal keys is then in its final place (input order), and the keys of
+// every other class are ranked against each other inside it (a class holds
+// about n / 64 keys; one that the samples miss costs the square of its size,
+// at most kCap^2 comparisons).  The places of those keys come back through
+// LDS, and every key and payload is written from its register.
+constexpr uint32_t kSlowSamples = kWave;
+
+// Sample j: stratum j of 64 equal strata of the n keys, at an offset inside
+// the stratum that varies with j (a permutation of the 64 residues), so that
+// keys periodic in their position are sampled across their period.
+__device__ __forceinline__ uint32_t sample_pos(uint32_t j, uint32_t n) {
+    const uint32_t u = (j * 37u + 11u) & 63u;
+    return (uint32_t)(((uint64_t)(kSlowSamples * j + u) * n) >> 12);
+}
+
+template <typename K>
+__device__ __forceinline__ K shfl_key(K v, int src) {
+    if constexpr (sizeof(K) == 8) return (K)shfl_u64((uint64_t)v, src);
+    else return (K)__shfl((uint32_t)v, src);
+}
+
 template <typename K, bool kPayload, int kCap>
-__global__ __launch_bounds__(kT) void lds_lsd_kernel(const K* __restrict__ kin,
+__global__ __launch_bounds__(kT) void sample_sort_kernel(const K* __restrict__ kin,
                                                      const uint64_t* __restrict__ vin,
                                                      K* __restrict__ kout,
                                                      uint64_t* __restrict__ vout, SlowList sl,
                                                      Fences fences) {
-    __shared__ K A[kCap];
-    __shared__ K Bk[kCap];
-    __shared__ uint16_t Ai[kCap];
-    __shared__ uint16_t Bi[kCap];
-    __shared__ uint32_t whist[kW][256];
-    __shared__ uint32_t start[257];
+    constexpr int kRows = kCap / kT;   // rows of 64 keys per wave
+    constexpr uint32_t kClasses = 2 * kSlowSamples + 1;
+    static_assert(kSlowSamples == 64 && kClasses <= (uint32_t)kT, "one thread per class");
+    __shared__ K Bk[kCap];            // the keys in input order, then the unequal classes
+    __shared__ uint16_t Bi[kCap];     // input index of every key of an unequal class
+    __shared__ uint16_t dest[kCap];   // input index -> place in the sub-bucket
+    __shared__ uint8_t cpos[kCap];    // class of every place
+    __shared__ uint32_t whist[kW][kClasses];
+    __shared__ uint32_t start[kClasses + 1];
     __shared__ uint32_t scratch[kW];
-    __shared__ uint32_t max_count;
-    __shared__ uint32_t diff_lo, diff_hi;
+    __shared__ K split[kSlowSamples];
+    __shared__ uint32_t n_split;
 
     const uint64_t base = sl.beg[blockIdx.x];
     const uint32_t n = sl.len[blockIdx.x];
-    const int bits = sl.bits[blockIdx.x];
-    const K kbase = (K)sl.base[blockIdx.x];
-    if (threadIdx.x == 0) { diff_lo = 0; diff_hi = 0; }
-    for (uint32_t i = threadIdx.x; i < n; i += kT) A[i] = kin[base + i];
+    const FenceSink fs = fence_sink(fences, sl.seg[blockIdx.x]);
+    const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+    const uint32_t cw = ((n + kW * kWave - 1) / (kW * kWave)) * kWave;
+    const uint32_t rows = cw / kWave;
+    auto index_of = [&](int r) { return w * cw + (uint32_t)r * kWave + lane; };
+    K kr[kRows];
+    uint64_t vr[kPayload ? kRows : 1];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        kr[r] = 0;
+        if constexpr (kPayload) vr[r] = 0;
+        if ((uint32_t)r < rows) {   // uniform over the workgroup
+            const uint32_t i = index_of(r);
+            if (i < n) {
+                kr[r] = kin[base + i];
+                if constexpr (kPayload) vr[r] = vin[base + i];
+            }
+        }
+    }
+    for (uint32_t i = threadIdx.x; i < kW * kClasses; i += kT) (&whist[0][0])[i] = 0;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t i = index_of(r);
+        if ((uint32_t)r < rows && i < n) Bk[i] = kr[r];
+    }
     __syncthreads();
-    {
-        const uint64_t k0 = (uint64_t)(K)(A[0] - kbase);
-        uint64_t acc = 0;
-        for (uint32_t i = threadIdx.x; i < n; i += kT) acc |= (uint64_t)(K)(A[i] - kbase) ^ k0;
-        if (acc) {
-            atomicOr(&diff_lo, (uint32_t)acc);
-            atomicOr(&diff_hi, (uint32_t)(acc >> 32));
+    if (w == 0) {
+        // the samples sorted across the wave (bitonic network), then their
+        // distinct values in order; the table is padded with the largest key,
+        // which no key is below
+        K v = Bk[sample_pos(lane, n)];
+#pragma unroll
+        for (uint32_t k = 2; k <= kSlowSamples; k <<= 1) {
+#pragma unroll
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                const K x = shfl_key(v, (int)(lane ^ j));
+                const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+                v = keep_min ? (x < v ? x : v) : (x < v ? v : x);
+            }
+        }
+        const K prev = shfl_key(v, (int)(lane == 0 ? 0 : lane - 1));
+        const bool first = lane == 0 || prev != v;
+        const uint64_t fm = __ballot(first);
+        const uint32_t m = (uint32_t)__popcll(fm);
+        if (first) split[__popcll(fm & lanes_below_mask())] = v;
+        if (lane >= m) split[lane] = (K)~(K)0;
+        if (lane == 0) n_split = m;
+    }
+    __syncthreads();
+    const uint32_t m = n_split;
+    // splitters below every key: binary lifting over the padded table, all
+    // rows in step
+    uint32_t lo[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) lo[r] = 0;
+#pragma unroll
+    for (uint32_t half = kSlowSamples / 2; half > 0; half >>= 1) {
+#pragma unroll
+        for (int r = 0; r < kRows; ++r)
+            if ((uint32_t)r < rows && split[lo[r] + half - 1] < kr[r]) lo[r] += half;
+    }
+    // class of every key and its rank among the keys of its class in the
+    // same wave, in input order (rows in order, lanes in order)
+    uint32_t cl[kRows], pw[kRows];
+    const uint64_t lanes_below = lanes_below_mask();
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        cl[r] = 0xFFu;
+        pw[r] = 0;
+        if ((uint32_t)r < rows) {   // uniform
+            const bool valid = index_of(r) < n;
+            const K k = kr[r];
+            uint32_t s = lo[r];
+            if (split[s] < k) ++s;   // s <= 63 before: all 64 below k
+            const uint32_t c = 2 * s + ((s < m && split[s] == k) ? 1u : 0u);
+            const uint64_t live = __ballot(valid);
+            const uint64_t same = match_byte(c, live);
+            const int leader = valid ? (int)(__ffsll((unsigned long long)same) - 1) : (int)lane;
+            uint32_t old = 0;
+            if (valid && (int)lane == leader) {
+                old = whist[w][c];
+                whist[w][c] = old + (uint32_t)__popcll(same);
+            }
+            old = __shfl(old, leader);
+            if (valid) {
+                cl[r] = c;
+                pw[r] = old + (uint32_t)__popcll(same & lanes_below);
+            }
         }
     }
     __syncthreads();
-    const uint64_t diff = ((uint64_t)diff_hi << 32) | diff_lo;
-    const K* sk = A;
-    const uint16_t* si = nullptr;
-    K* dk = Bk;
-    uint16_t* di = Bi;
-    for (int sh = 0; sh < bits; sh += 8) {
-        if (((diff >> sh) & 0xFFu) == 0) continue;   // uniform digit: order unchanged
-        lds_pass<K, kCap>(sk, si, dk, di, n, sh, kbase, whist, start, scratch, &max_count);
-        // the pass output becomes the next input; the buffer pair (keys,
-        // indices) it read from becomes the next output
-        K* old = (K*)sk;
-        sk = dk;
-        si = di;
-        dk = old;
-        di = old == A ? Ai : Bi;
+    {
+        // class starts, and every wave's offset inside each class
+        const uint32_t d = threadIdx.x;
+        uint32_t c = 0;
+        if (d < kClasses) {
+#pragma unroll
+            for (int ww = 0; ww < kW; ++ww) {
+                const uint32_t t = whist[ww][d];
+                whist[ww][d] = c;
+                c += t;
+            }
+        }
+        uint32_t all;
+        const uint32_t st = block_exclusive_scan<uint32_t, kT>(c, scratch, &all);
+        if (d < kClasses) start[d] = st;
+        if (d == 0) start[kClasses] = all;
     }
-    const uint32_t seg = sl.seg[blockIdx.x];
-    const FenceSink fs = fence_sink(fences, seg);
-    for (uint32_t i = threadIdx.x; i < n; i += kT) {
-        kout[base + i] = sk[i];
-        if constexpr (kPayload) vout[base + i] = vin[base + (si ? si[i] : i)];
-        if (fs.dst) put_fence(fs, base + i, (uint64_t)sk[i]);
+    __syncthreads();
+    // equal classes straight to their place; the others into LDS by class
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t c = cl[r];
+        if (c == 0xFFu) continue;
+        const uint32_t pos = start[c] + whist[w][c] + pw[r];
+        if (c & 1u) {
+            kout[base + pos] = kr[r];
+            if constexpr (kPayload) vout[base + pos] = vr[r];
+            if (fs.dst) put_fence(fs, base + pos, (uint64_t)kr[r]);
+        } else {
+            Bk[pos] = kr[r];
+            Bi[pos] = (uint16_t)index_of(r);
+        }
+        cpos[pos] = (uint8_t)c;
+    }
+    __syncthreads();
+    // every key of an unequal class: its rank inside the class (equal keys
+    // of a class are in input order)
+    for (uint32_t e = threadIdx.x; e < n; e += kT) {
+        const uint32_t c = cpos[e];
+        if (c & 1u) continue;
+        const uint32_t g0 = start[c], g1 = start[c + 1];
+        const K k = Bk[e];
+        uint32_t rk = 0;
+        for (uint32_t j = g0; j < g1; ++j) {
+            const K x = Bk[j];
+            rk += (uint32_t)((x < k) | ((x == k) & (j < e)));
+        }
+        dest[Bi[e]] = (uint16_t)(g0 + rk);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t c = cl[r];
+        if (c == 0xFFu || (c & 1u)) continue;
+        const uint32_t o = dest[index_of(r)];
+        kout[base + o] = kr[r];
+        if constexpr (kPayload) vout[base + o] = vr[r];
+        if (fs.dst) put_fence(fs, base + o, (uint64_t)kr[r]);
     }
 }
 
@@ -813,12 +878,12 @@ void launch_small_any(bool pay, bool large, bool stage, dim3 grid, hipStream_t s
 }
 
 template <typename K, int kCapT>
-void launch_lds_lsd(bool pay, dim3 g, hipStream_t s, const HybridSort& a) {
+void launch_sample_sort(bool pay, dim3 g, hipStream_t s, const HybridSort& a) {
     if (pay)
-        hipLaunchKernelGGL((lds_lsd_kernel<K, true, kCapT>), g, dim3(kT), 0, s, (const K*)a.keys_tmp,
+        hipLaunchKernelGGL((sample_sort_kernel<K, true, kCapT>), g, dim3(kT), 0, s, (const K*)a.keys_tmp,
                            a.vals_tmp, (K*)a.keys_out, a.vals_out, a.sl, a.fences);
     else
-        hipLaunchKernelGGL((lds_lsd_kernel<K, false, kCapT>), g, dim3(kT), 0, s, (const K*)a.keys_tmp,
+        hipLaunchKernelGGL((sample_sort_kernel<K, false, kCapT>), g, dim3(kT), 0, s, (const K*)a.keys_tmp,
                            nullptr, (K*)a.keys_out, nullptr, a.sl, a.fences);
 }
 
@@ -1086,15 +1151,15 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     }
     const uint32_t SL = host.pinned[2], EQ = host.pinned[3];
     host.last_slow = SL;
-    // 4. sub-buckets with a large group: LSD passes in LDS (from the MSD buffer)
+    // 4. sub-buckets with a large group: the slow path (from the MSD buffer)
     if (SL > 0) {
         const dim3 g(SL);
         if (a.key_bytes == 4) {
-            if (large) launch_lds_lsd<uint32_t, kCapLarge>(pay, g, s, a);
-            else launch_lds_lsd<uint32_t, kCapSmall>(pay, g, s, a);
+            if (large) launch_sample_sort<uint32_t, kCapLarge>(pay, g, s, a);
+            else launch_sample_sort<uint32_t, kCapSmall>(pay, g, s, a);
         } else {
-            if (large) launch_lds_lsd<uint64_t, kCapLarge>(pay, g, s, a);
-            else launch_lds_lsd<uint64_t, kCapSmall>(pay, g, s, a);
+            if (large) launch_sample_sort<uint64_t, kCapLarge>(pay, g, s, a);
+            else launch_sample_sort<uint64_t, kCapSmall>(pay, g, s, a);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -3,9 +3,12 @@
 Inputs are built to reach each path of the hybrid sort with segments far above
 the on-chip capacity: segments whose top digit holds every key (all equal, or
 varying only in low bits), clusters that stay above the capacity for two more
-levels (so one level sorts in place in the output), and clustered duplicates
-that end in the LDS-LSD kernel from an in-place level.  Local sort, partition
-and sort must equal the oracle bit for bit, keys alone and with a payload.
+levels (so one level sorts in place in the output), clustered duplicates
+that end in the slow path (an on-chip sample sort) from an in-place level, and
+segments of at most 2048 keys whose 64 sampled places all hold one value, so
+that the sample sort is left with one class of almost every key to rank.
+Local sort, partition and sort must equal the oracle bit for bit, keys alone
+and with a payload.
 """
 import sys
 
@@ -42,10 +45,17 @@ def _host(t, dtype):
     return t.cpu().numpy().view(dtype)
 
 
-def _keys(kind, n, seed, bits):
+def _keys(kind, n, seed, bits, p):
     rng = np.random.default_rng(seed)
     top = np.uint64(1) << np.uint64(bits - 1)
-    if kind == "narrow_gauss":       # around 0.7 2^b, sigma 2^(b-24): the top bits agree
+    if kind == "planted_samples":    # top bits agree; the sampled places of every segment hold 7
+        # (the slow path samples stratum j of 64 at offset (37 j + 11) mod 64 of 64)
+        k = top + rng.integers(0, 1 << (bits - 12), n).astype(np.uint64)
+        j = np.arange(64)
+        for s in range(p):
+            a, b = s * n // p, (s + 1) * n // p
+            k[a + (((64 * j + ((37 * j + 11) & 63)) * (b - a)) >> 12)] = 7
+    elif kind == "narrow_gauss":       # around 0.7 2^b, sigma 2^(b-24): the top bits agree
         sig = 2.0 ** (bits - 24)
         k = (0.7 * 2.0 ** bits + rng.normal(0.0, sig, n)).astype(np.uint64)
     elif kind == "clustered_dups":   # 3000 values 2^(b-13) apart, ~n/3000 copies each
@@ -76,6 +86,8 @@ CASES = [
     ("low7", 200_000, 32, 64, False),          # many small entries, 101 sub-buckets each
     ("clustered_dups", 300_000, 16, 64, True),
     ("SKEW1", 400_000, 16, 32, False),
+    ("planted_samples", 2048 * 8, 8, 64, True),   # sample sort: one class of 1984 keys
+    ("planted_samples", 1500 * 16, 16, 32, False),
 ]
 
 
@@ -84,7 +96,7 @@ def test_deep_levels_match_oracle(hss, case):
     kind, n, p, bits, payload = case
     seed = 31
     _say(f"[deep] {kind} n={n} p={p} bits={bits} payload={payload}")
-    keys = _keys(kind, n, seed, bits)
+    keys = _keys(kind, n, seed, bits, p)
     vals = (np.arange(n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)) if payload else None
     kd = _dev(keys)
     vd = None if vals is None else _dev(vals)
