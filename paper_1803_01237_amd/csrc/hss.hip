@@ -505,6 +505,8 @@ size_t layout(Engine& E, char* base) {
     r.urank = ar.take<uint64_t>(Q);
     r.s_key = ar.take<uint64_t>(Q);
     r.s_tag = ar.take<uint64_t>(Q);
+    r.l_tag = ar.take<uint64_t>(Q);
+    r.u_tag = ar.take<uint64_t>(Q);
     r.lpos = ar.take<uint32_t>(E.T);
     r.upos = ar.take<uint32_t>(E.T);
     r.prow = ar.take<uint32_t>(E.T);
@@ -517,6 +519,10 @@ size_t layout(Engine& E, char* base) {
     r.ivl_poff = ar.take<uint32_t>(Q + 1);
     r.ivl_cursor = ar.take<uint32_t>(Q);
     r.ivl_tile0 = ar.take<uint32_t>(Q + 1);
+    r.ivl_lkey = ar.take<uint64_t>(Q);
+    r.ivl_ltag = ar.take<int64_t>(Q);
+    r.ivl_ukey = ar.take<uint64_t>(Q);
+    r.ivl_utag = ar.take<int64_t>(Q);
     r.slices = ar.take<uint4>(E.T > 0 ? E.T : 1);
     r.inst_plo = ar.take<uint32_t>(B);
     r.inst_pm = ar.take<uint32_t>(B);
@@ -804,15 +810,17 @@ hss_status engine_init(Engine& E) {
         !E.tune.pick_sampler) {
         for (uint32_t j = 1; j <= kPreRounds && j <= E.J; ++j) {
             if (L.all[j - 1] || (j > 1 && E.tune.probes_per_round)) break;
+            // rounds whose lists would be long draw by themselves
+            const double e = (double)E.n_tot * ((double)L.thresh[j - 1] / 4294967296.0);
+            if (e > (double)kPresampleExpectMax) break;
             E.pre_thresh[j - 1] = L.thresh[j - 1];
-            expect = std::max(expect, (double)E.n_tot * ((double)L.thresh[j - 1] / 4294967296.0));
+            expect = std::max(expect, e);
             E.pre_rounds = j;
         }
     }
     // a list of twice the expected draws plus 4096 holds all of them except
-    // with negligible probability (binomial counts); a longer one is not
+    // with negligible probability (binomial counts); a fuller one is not
     // used (the sampler draws itself)
-    if (E.pre_rounds && expect > (double)kPresampleExpectMax) E.pre_rounds = 0;
     if (E.pre_rounds) {
         E.pre_cap = (uint32_t)(expect * 2 + 4096);
         HIP_TRY(dev_alloc(E.mem, (void**)&E.pre_mem,

@@ -490,6 +490,8 @@ struct RoundArgs {
     uint64_t* urank;
     uint64_t* s_key;
     uint64_t* s_tag;
+    uint64_t* l_tag;               // tags of the probes at the bounds L and U (when set)
+    uint64_t* u_tag;
     uint32_t* lpos;                // sum over instances of (p+1) p
     uint32_t* upos;
     uint32_t* prow;
@@ -503,6 +505,12 @@ struct RoundArgs {
     uint32_t* ivl_poff;            // their first sorted index
     uint32_t* ivl_cursor;
     uint32_t* ivl_tile0;           // first ranking workgroup of the interval
+    // the interval's bounds in the order (key, tag): keys as unsigned, tags
+    // as signed; an open end is (0, -1) below and (all ones, INT64_MAX) above
+    uint64_t* ivl_lkey;
+    int64_t* ivl_ltag;
+    uint64_t* ivl_ukey;
+    int64_t* ivl_utag;
     uint4* slices;                 // {first block, first tag, end tag, interval}
     // per instance, per round
     uint32_t* inst_plo;            // first sorted probe of the instance

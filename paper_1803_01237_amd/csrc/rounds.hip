@@ -38,19 +38,24 @@ namespace hss {
 namespace {
 
 constexpr int kT = 256;
-constexpr int kScanT = 1024;            // threads of the one-workgroup scans
+// threads of the one-workgroup scans: kScanSmall up to kScanSmallRows rows
+constexpr int kScanLarge = 1024;
+constexpr int kScanSmall = 256;
+constexpr uint32_t kScanSmallRows = 4096;
 constexpr uint32_t kRankFences = kRankChunk / kFenceStride;
 constexpr uint32_t kDenseTile = 4096;   // keys of a chunk staged at once by rank_dense_kernel
 constexpr uint32_t kSampleStage = 256;  // probes a sampler wave stages in LDS (4 per lane)
-constexpr uint32_t kReduceRows = 16;    // segments summed per reduction workgroup
-constexpr uint32_t kOrderLanes = 64;    // probes per ordering workgroup
-constexpr uint32_t kOrderThreads = 512; // their comparisons split over 8 waves
+constexpr uint32_t kReduceRows = 16;    // segments summed per reduction tile
+constexpr uint32_t kReduceGrid = 2048;  // reduction workgroups (they stride over the tiles)
+constexpr uint32_t kOrderLanes = 16;    // probes per ordering tile
+constexpr uint32_t kOrderThreads = 512; // their comparisons split 32 ways (half a wave per probe)
+constexpr uint32_t kOrderGrid = 1024;   // ordering workgroups (they stride over the tiles)
 
 __device__ __forceinline__ bool halted(const RoundArgs& a) { return a.ctr->overflow != 0; }
 
 // Exclusive scan of v[0, n) in place by one workgroup of kScanT threads
 // (thread t scans a contiguous run serially); returns the total.
-template <typename T>
+template <int kScanT, typename T>
 __device__ uint64_t wg_scan_inplace(T* v, uint32_t n, uint64_t* scratch) {
     const uint32_t per = (n + kScanT - 1) / kScanT;
     const uint32_t r0 = min(threadIdx.x * per, n), r1 = min(r0 + per, n);
@@ -89,12 +94,15 @@ __global__ void round_init_kernel(RoundArgs a) {
         a.urank[r] = kNone;
         a.s_key[r] = 0;
         a.s_tag[r] = 0;
+        a.l_tag[r] = 0;
+        a.u_tag[r] = 0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.ctr = RoundCounters{};
 }
 
 // One workgroup: leaders of runs of identical unsettled intervals, in row
 // order (instance by instance, splitter by splitter).
+template <int kScanT>
 __global__ __launch_bounds__(kScanT) void leaders_kernel(RoundArgs a, uint32_t round) {
     __shared__ uint32_t scratch[kScanT / kWave];
     if (halted(a)) {
@@ -158,8 +166,12 @@ __device__ __forceinline__ uint64_t blocks_of(uint64_t ga, uint64_t gb) {
     return gb > ga ? ((gb - 1) >> 2) - (ga >> 2) + 1 : 0;
 }
 
+__device__ __forceinline__ uint64_t key_at(const RoundArgs& a, uint64_t i) {
+    return a.key_bytes == 4 ? (uint64_t)((const uint32_t*)a.B)[i] : ((const uint64_t*)a.B)[i];
+}
+
 // Workgroup per interval k: Philox blocks, non-empty slices and tags of its
-// slices; clears its probe counters.
+// slices, its bounds as (key, tag); clears its probe counters.
 __global__ __launch_bounds__(kT) void slices_kernel(RoundArgs a) {
     __shared__ uint64_t scratch[kT / kWave];
     const uint32_t k = blockIdx.x;
@@ -187,17 +199,22 @@ __global__ __launch_bounds__(kT) void slices_kernel(RoundArgs a) {
         a.ivl_dom[k] = dom;
         a.ivl_pcnt[k] = 0;
         a.ivl_cursor[k] = 0;
+        a.ivl_lkey[k] = lnone ? 0ull : key_at(a, D.pos0 + a.l_tag[row]);
+        a.ivl_ltag[k] = lnone ? -1ll : (int64_t)a.l_tag[row];
+        a.ivl_ukey[k] = unone ? ~0ull : key_at(a, D.pos0 + a.u_tag[row]);
+        a.ivl_utag[k] = unone ? INT64_MAX : (int64_t)a.u_tag[row];
     }
 }
 
 // One workgroup: exclusive scans of the interval block and slice totals.
+template <int kScanT>
 __global__ __launch_bounds__(kScanT) void ivl_scan_kernel(RoundArgs a) {
     __shared__ uint64_t scratch[kScanT / kWave];
     const uint32_t n = a.ctr->n_ivl;
-    const uint64_t blocks = wg_scan_inplace(a.ivl_tot, n, scratch);
-    const uint64_t slices = wg_scan_inplace(a.ivl_nz, n, scratch);
+    const uint64_t blocks = wg_scan_inplace<kScanT>(a.ivl_tot, n, scratch);
+    const uint64_t slices = wg_scan_inplace<kScanT>(a.ivl_nz, n, scratch);
     // domain before every interval (an instance's domain is a difference)
-    const uint64_t d = wg_scan_inplace(a.ivl_dom, n, scratch);
+    const uint64_t d = wg_scan_inplace<kScanT>(a.ivl_dom, n, scratch);
     if (threadIdx.x == 0) {
         a.ivl_tot[n] = blocks;
         a.ivl_nz[n] = (uint32_t)slices;
@@ -285,11 +302,17 @@ __device__ void flush_stage(const RoundArgs& a, const uint64_t* st_key, const ui
     }
 }
 
+// (key x, tag gx) before (key y, tag gy) in the order of section 6.1.
+__device__ __forceinline__ bool key_tag_less(uint64_t x, int64_t gx, uint64_t y, int64_t gy) {
+    return x < y || (x == y && gx < gy);
+}
+
 // Sampler of a round whose draws were taken ahead (one instance): thread per
-// listed tag g; g is a probe when it lies in the slice of an interval in its
-// segment.  The intervals are disjoint and in key order, so their slices in
-// one segment are disjoint and in position order: the last interval whose
-// slice starts at or before g is the only one that may hold it.
+// listed tag g.  g is a probe when (key, g) lies strictly inside an interval
+// in the order (key, tag) -- the same as lying in the interval's slice of its
+// segment, whose ends are the per-segment counts of the interval's bounds.
+// The intervals are disjoint and in key order: the last one whose lower
+// bound precedes (key, g) is the only one that may hold it.
 template <typename K>
 __device__ void sample_from_list(const RoundArgs& a, const uint32_t* list, uint32_t cnt) {
     const uint32_t n_ivl = a.ctr->n_ivl;
@@ -304,31 +327,19 @@ __device__ void sample_from_list(const RoundArgs& a, const uint32_t* list, uint3
         const uint64_t g = t < cnt ? list[t] : D.n;
         bool take = g < D.n;
         uint32_t kl = 0;
+        uint64_t key = 0;
         if (take) {
-            uint32_t lo = 0, hi = D.p;   // segment: the last one starting at or before g
-            while (hi - lo > 1) {
+            key = (uint64_t)B[D.pos0 + g];
+            uint32_t lo = 0, hi = n_ivl;   // intervals whose lower bound precedes (key, g): [0, lo)
+            while (lo < hi) {
                 const uint32_t mid = (lo + hi) >> 1;
-                if (a.seg_off[D.seg0 + mid] - D.pos0 <= g) lo = mid; else hi = mid;
+                if (key_tag_less(a.ivl_lkey[mid], a.ivl_ltag[mid], key, (int64_t)g)) lo = mid + 1;
+                else hi = mid;
             }
-            const uint32_t s = lo;
-            auto bounds = [&](uint32_t k, uint64_t* ga, uint64_t* gb) {
-                const uint32_t row = a.ivl_row[k];
-                slice_bounds(a, D, row - D.row0, s, a.lrank[row] == kNone, a.urank[row] == kNone, ga, gb);
-            };
-            uint32_t kh = n_ivl;   // the last interval whose slice starts at or before g
-            uint64_t ga, gb;
-            bounds(0, &ga, &gb);
-            if (ga > g) {
-                take = false;
-            } else {
-                while (kh - kl > 1) {
-                    const uint32_t mid = (kl + kh) >> 1;
-                    uint64_t ma, mb;
-                    bounds(mid, &ma, &mb);
-                    if (ma <= g) kl = mid; else kh = mid;
-                }
-                bounds(kl, &ga, &gb);
-                take = g >= ga && g < gb;
+            take = lo > 0;
+            if (take) {
+                kl = lo - 1;
+                take = key_tag_less(key, (int64_t)g, a.ivl_ukey[kl], a.ivl_utag[kl]);
             }
         }
         const uint64_t mask = __ballot(take);
@@ -341,7 +352,7 @@ __device__ void sample_from_list(const RoundArgs& a, const uint32_t* list, uint3
         if (take) {
             const uint64_t o = base + __popcll(mask & lanes_below_mask());
             if (o < a.cap) {
-                a.pr_key[o] = (uint64_t)B[D.pos0 + g];
+                a.pr_key[o] = key;
                 a.pr_tag[o] = g;
                 a.pr_ivl[o] = kl;
                 stored = true;
@@ -636,6 +647,7 @@ __global__ void budget_rate_kernel(RoundArgs a, uint32_t round) {
 // One workgroup: where every interval's probes go in sorted order, how many
 // ordering workgroups it takes, every instance's probe range and count-matrix
 // block; flags a capacity overrun.
+template <int kScanT>
 __global__ __launch_bounds__(kScanT) void probe_scan_kernel(RoundArgs a, uint32_t round) {
     __shared__ uint64_t scratch[kScanT / kWave];
     RoundCounters* c = a.ctr;
@@ -751,66 +763,63 @@ __device__ __forceinline__ uint32_t probe_row(const RoundArgs& a, uint32_t k) {
     return row | (a.lrank[row] == kNone ? kRowLNone : 0u) | (a.urank[row] == kNone ? kRowUNone : 0u);
 }
 
-// Workgroup per kOrderLanes probes of one interval: each probe's place among
-// the interval's probes in the order (key, tag), counted against tiles of
-// the interval staged in LDS, an eighth of every tile per wave; the probe
-// goes to that place of the sorted arrays, with its segment, and its rank
-// sum is cleared.
+// Tile of kOrderLanes probes of one interval: each probe's place among the
+// interval's probes in the order (key, tag), counted by 32 lanes of a wave
+// (every 32nd probe of the interval each) against chunks of the interval
+// staged in LDS; the probe goes to that place of the sorted arrays, with its
+// segment, and its rank sum is cleared.  Workgroups stride over the tiles.
 __global__ __launch_bounds__(kOrderThreads) void order_kernel(RoundArgs a) {
     constexpr uint32_t kTile = 1024;
     constexpr uint32_t kParts = kOrderThreads / kOrderLanes;
+    static_assert(kParts == kWave / 2, "a probe's parts are half a wave");
     __shared__ uint64_t tk[kTile];
     __shared__ uint64_t tt[kTile];
-    __shared__ uint32_t part[kParts][kOrderLanes];
     if (halted(a)) return;
-    const uint32_t t = blockIdx.x;
-    if (t >= a.ctr->tiles) return;
+    const uint32_t tiles = a.ctr->tiles;
     const uint32_t n_ivl = a.ctr->n_ivl;
-    const uint32_t k = last_le(a.ivl_tile0, n_ivl, t);
-    const uint32_t base = a.ivl_poff[k];
-    const uint32_t nk = a.ivl_poff[k + 1] - base;
-    const uint32_t lane = threadIdx.x % kOrderLanes, w = threadIdx.x / kOrderLanes;
-    const uint32_t i = (t - a.ivl_tile0[k]) * kOrderLanes + lane;
-    const bool valid = i < nk;
-    const uint64_t key = valid ? a.g_key[base + i] : 0;
-    const uint64_t tag = valid ? a.g_tag[base + i] : 0;
-    uint32_t c = 0;
-    for (uint32_t c0 = 0; c0 < nk; c0 += kTile) {
-        const uint32_t nc = min(kTile, nk - c0);
-        __syncthreads();   // the previous tile is no longer read
-        for (uint32_t x = threadIdx.x; x < nc; x += kOrderThreads) {
-            tk[x] = a.g_key[base + c0 + x];
-            tt[x] = a.g_tag[base + c0 + x];
+    const uint32_t part = threadIdx.x % kParts, pl = threadIdx.x / kParts;
+    for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {   // uniform
+        const uint32_t k = last_le(a.ivl_tile0, n_ivl, t);
+        const uint32_t base = a.ivl_poff[k];
+        const uint32_t nk = a.ivl_poff[k + 1] - base;
+        const uint32_t i = (t - a.ivl_tile0[k]) * kOrderLanes + pl;
+        const bool valid = i < nk;
+        const uint64_t key = valid ? a.g_key[base + i] : 0;
+        const uint64_t tag = valid ? a.g_tag[base + i] : 0;
+        uint32_t c = 0;
+        for (uint32_t c0 = 0; c0 < nk; c0 += kTile) {
+            const uint32_t nc = min(kTile, nk - c0);
+            __syncthreads();   // the previous chunk is no longer read
+            for (uint32_t x = threadIdx.x; x < nc; x += kOrderThreads) {
+                tk[x] = a.g_key[base + c0 + x];
+                tt[x] = a.g_tag[base + c0 + x];
+            }
+            __syncthreads();
+#pragma unroll 4
+            for (uint32_t j = part; j < nc; j += kParts) {
+                const uint64_t kj = tk[j], tj = tt[j];
+                c += (kj < key || (kj == key && tj < tag)) ? 1u : 0u;
+            }
         }
-        __syncthreads();
-        const uint32_t q = (nc + kParts - 1) / kParts;
-        const uint32_t j0 = min(w * q, nc), j1 = min(j0 + q, nc);
-#pragma unroll 8
-        for (uint32_t j = j0; j < j1; ++j) {
-            const uint64_t kj = tk[j], tj = tt[j];
-            c += (kj < key || (kj == key && tj < tag)) ? 1u : 0u;
-        }
-    }
-    part[w][lane] = c;
-    __syncthreads();
-    if (w != 0 || !valid) return;
-    uint32_t rank = 0;
 #pragma unroll
-    for (uint32_t q = 0; q < kParts; ++q) rank += part[q][lane];
-    const uint64_t pos = base + rank;
-    const InstDesc& D = a.inst[a.ivl_inst[k]];
-    // segment of the probe: the last segment of the instance starting at or before it
-    uint32_t lo = 0, hi = D.p;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (a.seg_off[D.seg0 + mid] - D.pos0 <= tag) lo = mid; else hi = mid;
+        for (uint32_t off = kParts / 2; off > 0; off >>= 1) c += (uint32_t)__shfl_xor((int)c, (int)off);
+        if (part == 0 && valid) {
+            const uint64_t pos = base + c;
+            const InstDesc& D = a.inst[a.ivl_inst[k]];
+            // segment of the probe: the last segment of the instance starting at or before it
+            uint32_t lo = 0, hi = D.p;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (a.seg_off[D.seg0 + mid] - D.pos0 <= tag) lo = mid; else hi = mid;
+            }
+            a.ps_key[pos] = key;
+            a.ps_tag[pos] = tag;
+            a.ps_ivl[pos] = k;
+            a.ps_seg[pos] = D.seg0 + lo;
+            a.ps_row[pos] = probe_row(a, k);
+            a.pr_rank[pos] = 0;   // the rank reduction adds into it
+        }
     }
-    a.ps_key[pos] = key;
-    a.ps_tag[pos] = tag;
-    a.ps_ivl[pos] = k;
-    a.ps_seg[pos] = D.seg0 + lo;
-    a.ps_row[pos] = probe_row(a, k);
-    a.pr_rank[pos] = 0;   // the rank reduction adds into it
 }
 
 // (key_e, g_e) after (kx, gx) in the order (key, tag)?
@@ -1120,20 +1129,26 @@ __global__ void probe_finish_kernel(RoundArgs a) {
 // atomic additions does not change R(e).
 __global__ __launch_bounds__(256) void reduce_kernel(RoundArgs a) {
     if (halted(a)) return;
-    const uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= a.ctr->m_stored) return;
-    const uint32_t I = a.ivl_inst[a.ps_ivl[e]];
-    const uint32_t p = a.inst[I].p;
-    const uint32_t s0 = blockIdx.y * kReduceRows;
-    if (s0 >= p) return;
-    const uint32_t s1 = min(s0 + kReduceRows, p);
-    const uint32_t m = a.inst_pm[I];
-    const uint32_t* col = a.cmat + a.cm_off[I] + (e - a.inst_plo[I]);
-    uint64_t sum = 0;
+    const uint64_t m_all = a.ctr->m_stored;
+    const uint64_t etiles = (m_all + 255) / 256;
+    const uint64_t tiles = etiles * ((a.p_max + kReduceRows - 1) / kReduceRows);
+    // consecutive workgroups take consecutive probe tiles of one segment group
+    for (uint64_t x = blockIdx.x; x < tiles; x += gridDim.x) {
+        const uint64_t e = (x % etiles) * 256 + threadIdx.x;
+        const uint32_t s0 = (uint32_t)(x / etiles) * kReduceRows;
+        if (e >= m_all) continue;
+        const uint32_t I = a.ivl_inst[a.ps_ivl[e]];
+        const uint32_t p = a.inst[I].p;
+        if (s0 >= p) continue;
+        const uint32_t s1 = min(s0 + kReduceRows, p);
+        const uint32_t m = a.inst_pm[I];
+        const uint32_t* col = a.cmat + a.cm_off[I] + (e - a.inst_plo[I]);
+        uint64_t sum = 0;
 #pragma unroll
-    for (uint32_t q = 0; q < kReduceRows; ++q)
-        if (s0 + q < s1) sum += col[(uint64_t)(s0 + q) * m];
-    atomicAdd((unsigned long long*)&a.pr_rank[e], (unsigned long long)sum);
+        for (uint32_t q = 0; q < kReduceRows; ++q)
+            if (s0 + q < s1) sum += col[(uint64_t)(s0 + q) * m];
+        atomicAdd((unsigned long long*)&a.pr_rank[e], (unsigned long long)sum);
+    }
 }
 
 // Workgroup per splitter row (section 4.2.2 steps 3 and 5).  A probe whose
@@ -1212,10 +1227,12 @@ __global__ __launch_bounds__(kThreads) void settle_kernel(RoundArgs a) {
             if (has_below && (a.lrank[r] == kNone || r_below > a.lrank[r])) {
                 a.lrank[r] = r_below;
                 sel0 = (uint32_t)(plo + lo - 1);
+                a.l_tag[r] = a.ps_tag[sel0];
             }
             if (has_above && r_above < a.urank[r]) {
                 a.urank[r] = r_above;
                 sel1 = (uint32_t)(plo + lo);
+                a.u_tag[r] = a.ps_tag[sel1];
             }
         }
     }
@@ -1420,9 +1437,12 @@ hipError_t launch_round(const RoundArgs& a, uint32_t j, hipStream_t s, Profiler*
 
 hipError_t launch_round_head(const RoundArgs& a, uint32_t j, hipStream_t s) {
     const uint32_t ivl_bound = interval_bound(a);
-    hipLaunchKernelGGL(leaders_kernel, dim3(1), dim3(kScanT), 0, s, a, j);
+    const bool small = a.n_rows <= kScanSmallRows;
+    if (small) hipLaunchKernelGGL(leaders_kernel<kScanSmall>, dim3(1), dim3(kScanSmall), 0, s, a, j);
+    else hipLaunchKernelGGL(leaders_kernel<kScanLarge>, dim3(1), dim3(kScanLarge), 0, s, a, j);
     hipLaunchKernelGGL(slices_kernel, dim3(ivl_bound), dim3(kT), 0, s, a);
-    hipLaunchKernelGGL(ivl_scan_kernel, dim3(1), dim3(kScanT), 0, s, a);
+    if (small) hipLaunchKernelGGL(ivl_scan_kernel<kScanSmall>, dim3(1), dim3(kScanSmall), 0, s, a);
+    else hipLaunchKernelGGL(ivl_scan_kernel<kScanLarge>, dim3(1), dim3(kScanLarge), 0, s, a);
     hipLaunchKernelGGL(compact_kernel, dim3(ivl_bound), dim3(kT), 0, s, a);
     if (a.budget) hipLaunchKernelGGL(budget_rate_kernel, dim3(grid_for(a.n_inst, kT, 64)), dim3(kT), 0, s, a, j);
     if (a.n_inst == 1) {
@@ -1436,7 +1456,8 @@ hipError_t launch_round_head(const RoundArgs& a, uint32_t j, hipStream_t s) {
         if (a.key_bytes == 4) hipLaunchKernelGGL(pick_sample_kernel<uint32_t>, dim3(a.sample_grid), dim3(kT), 0, s, a, j);
         else hipLaunchKernelGGL(pick_sample_kernel<uint64_t>, dim3(a.sample_grid), dim3(kT), 0, s, a, j);
     }
-    hipLaunchKernelGGL(probe_scan_kernel, dim3(1), dim3(kScanT), 0, s, a, j);
+    if (small) hipLaunchKernelGGL(probe_scan_kernel<kScanSmall>, dim3(1), dim3(kScanSmall), 0, s, a, j);
+    else hipLaunchKernelGGL(probe_scan_kernel<kScanLarge>, dim3(1), dim3(kScanLarge), 0, s, a, j);
     hipLaunchKernelGGL(group_kernel, dim3(grid_for(a.cap, kT, 4096)), dim3(kT), 0, s, a);
     return hipGetLastError();
 }
@@ -1446,7 +1467,8 @@ hipError_t launch_round_tail(const RoundArgs& a, uint32_t j, hipStream_t s, bool
     (void)prof;
     if (!probes_sorted) {
         const uint64_t tiles_bound = (a.cap + kOrderLanes - 1) / kOrderLanes + interval_bound(a);
-        hipLaunchKernelGGL(order_kernel, dim3((unsigned)tiles_bound), dim3(kOrderThreads), 0, s, a);
+        hipLaunchKernelGGL(order_kernel, dim3((unsigned)std::min<uint64_t>(tiles_bound, kOrderGrid)),
+                           dim3(kOrderThreads), 0, s, a);
     }
     if (j == 1 && a.dense_rank && a.n_chunks > 0) {
         if (a.key_bytes == 4) hipLaunchKernelGGL(rank_dense_kernel<uint32_t>, dim3(a.n_chunks), dim3(256), 0, s, a);
@@ -1459,10 +1481,9 @@ hipError_t launch_round_tail(const RoundArgs& a, uint32_t j, hipStream_t s, bool
         if (a.key_bytes == 4) hipLaunchKernelGGL(rank_kernel<uint32_t>, dim3(a.n_chunks), dim3(256), 0, s, a);
         else hipLaunchKernelGGL(rank_kernel<uint64_t>, dim3(a.n_chunks), dim3(256), 0, s, a);
     }
-    const dim3 rgrid((unsigned)((a.cap + 255) / 256), (a.p_max + kReduceRows - 1) / kReduceRows);
-    hipLaunchKernelGGL(reduce_kernel, rgrid, dim3(256), 0, s, a);
-    if (a.p_max > 256) hipLaunchKernelGGL(settle_kernel<1024>, dim3(a.n_rows), dim3(1024), 0, s, a);
-    else hipLaunchKernelGGL(settle_kernel<256>, dim3(a.n_rows), dim3(256), 0, s, a);
+    const uint64_t rtiles = (a.cap + 255) / 256 * ((a.p_max + kReduceRows - 1) / kReduceRows);
+    hipLaunchKernelGGL(reduce_kernel, dim3((unsigned)std::min<uint64_t>(rtiles, kReduceGrid)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(settle_kernel<256>, dim3(a.n_rows), dim3(256), 0, s, a);
     const uint64_t copy_tiles = (uint64_t)((2 * a.n_rows + kCopySlots - 1) / kCopySlots) *
                                 ((a.p_max + kCopySegs - 1) / kCopySegs);
     hipLaunchKernelGGL(settle_copy_kernel, dim3((unsigned)std::min<uint64_t>(copy_tiles, 16384)), dim3(256), 0, s, a);
