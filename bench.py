@@ -335,11 +335,12 @@ def sweep_bench(plan, keys, n, p, eps, hseed, steps):
 
 def served_bench(count, mults, check_every):
     """The served workload: u64 requests with a payload arriving as a Poisson
-    process, served by the library's request server.  The rate is set from
-    the plain-path capacity (keys per second of one plan per request: create,
-    partition, release) times each multiplier.  Latency is completion minus
-    the scheduled arrival; every check_every-th request is compared with its
-    solo run."""
+    process, served by the library's request server; requests alternate
+    between partition (even index) and sort (odd index).  The rate is set
+    from the plain-path capacity (keys per second of one plan per request:
+    create, partition or sort, release) times each multiplier.  Latency is
+    completion minus the scheduled arrival; every check_every-th request is
+    compared with its solo run."""
     import torch
     import paper_1803_01237_amd as hss
     import synth
@@ -351,14 +352,17 @@ def served_bench(count, mults, check_every):
     def inputs(sh):
         return synth.device_keys(sh[0], sh[3], dev), torch.arange(sh[0], dtype=torch.int64, device=dev)
 
+    def op_of(i):
+        return "sort" if i % 2 else "partition"
+
     # plain-path capacity on the first requests
     cap_keys, cap_s = 0, 0.0
-    for sh in shapes[:min(48, count)]:
+    for i, sh in enumerate(shapes[:min(48, count)]):
         keys, vals = inputs(sh)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         with hss.Plan(sh[0], sh[1], sh[2], payload=True) as pl:
-            pl.partition(keys, sh[4], vals)
+            (pl.sort if op_of(i) == "sort" else pl.partition)(keys, sh[4], vals)
             torch.cuda.synchronize()
         cap_s += time.perf_counter() - t0
         cap_keys += sh[0]
@@ -409,7 +413,7 @@ def served_bench(count, mults, check_every):
                         if i0 % check_every == 0:
                             kept.append((i0, r))
                     lag.append(max(0.0, srv.clock() - arr))
-                    t = srv.submit(keys, sh[1], sh[2], sh[4], vals, sync=False)
+                    t = srv.submit(keys, sh[1], sh[2], sh[4], vals, sync=False, op=op_of(i))
                     pending[t] = (i, arr)
                 del batch
             drain(True)
@@ -422,7 +426,7 @@ def served_bench(count, mults, check_every):
             sh = shapes[i]
             keys, vals = inputs(sh)
             with hss.Plan(sh[0], sh[1], sh[2], payload=True) as pl:
-                ko, vo, off = pl.partition(keys, sh[4], vals)
+                ko, vo, off = (pl.sort if op_of(i) == "sort" else pl.partition)(keys, sh[4], vals)
                 torch.cuda.synchronize()
                 same = same and torch.equal(off, r.offsets) and torch.equal(ko, r.keys_out) \
                     and torch.equal(vo, r.vals_out)
@@ -445,7 +449,8 @@ def served_bench(count, mults, check_every):
     return {"requests": count, "keys": total, "plain_capacity_gkeys_s": round(capacity / 1e9, 3),
             "shape": "N = floor(2^U(14,26)) u64 keys + u64 payload, p = clamp(floor(e^U(ln 64, ln 2049)), "
                      "64, 2048), eps in {0.02, 0.05}, keys drawn on the device (torch generator per request), "
-                     "Poisson arrivals", "server": "2 workers (streams), 64 GiB HBM budget",
+                     "Poisson arrivals; requests alternate partition and sort",
+            "server": "2 workers (streams), 64 GiB HBM budget",
             "runs": runs}
 
 
@@ -552,7 +557,7 @@ def main():
                     help="steps per distribution of the sweep; 0 to skip")
     ap.add_argument("--serve-requests", type=int, default=20000,
                     help="requests of the served workload (0 to skip)")
-    ap.add_argument("--serve-rates", default="0.7,1.0",
+    ap.add_argument("--serve-rates", default="0.7,1.0,2.0",
                     help="arrival rates as multiples of the plain-path capacity")
     ap.add_argument("--serve-check-every", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true",

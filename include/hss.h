@@ -308,7 +308,8 @@ typedef struct {
     uint64_t seed;              /* Philox stream of the instance's rounds   */
     const void* keys_in;        /* N keys                                   */
     const uint64_t* vals_in;    /* N payload words, or NULL without payload */
-    void* keys_out;             /* N keys, bucket order as hss_partition    */
+    void* keys_out;             /* N keys in buckets (each bucket sorted    */
+                                /* for HSS_OP_SORT)                         */
     uint64_t* vals_out;         /* N payload words, or NULL                 */
     uint64_t* offsets;          /* p+1 words: chi                           */
 } hss_instance_io;
@@ -346,21 +347,28 @@ hss_status hss_batch_profile_read(hss_batch_t batch, uint32_t family, double* ms
                                   uint64_t* launches, uint64_t* bytes);
 
 /*
- * Server: requests of any shape arriving over time, each an hss_partition of
- * its own input (the served workload: independent sorts submitted by
- * clients), with continuous batching.  Worker threads of the server, each on
- * a stream of its own, take the requests queued when they become free -- in
- * submission order, of one key type and payload choice, within the batch
- * limits -- and run them as one batch; requests that arrive while other
+ * Server: requests of any shape arriving over time, each an hss_partition or
+ * an hss_sort of its own input (the served workload: independent sorts
+ * submitted by clients), with continuous batching.  Worker threads of the
+ * server, each on a stream of its own, take the requests queued when they
+ * become free -- in submission order, of one operation, key type and payload
+ * choice, within the batch limits; a sort request runs alone (its bucket sort
+ * is per plan) -- and run them as one batch; requests that arrive while other
  * batches are on the GPU start on a free worker as soon as the HBM budget
  * admits them, so their work overlaps on the device.  A request is admitted
  * when its footprint (inputs, outputs and its share of the workspace)
  * fits the budget left by the batches running (a request above the whole
  * budget runs when nothing else does).  Device memory comes from a cache of
  * blocks kept between batches (no allocation once the cache covers the
- * load).  Every request's outputs equal those of hss_partition of a plan
- * with its (N, p, eps, key type, payload) for its seed and input.
+ * load).  Every request's outputs equal those of hss_partition (or hss_sort)
+ * of a plan with its (N, p, eps, key type, payload) for its seed and input.
  */
+typedef enum {
+    HSS_OP_PARTITION = 0,       /* hss_partition: buckets of locally sorted pieces */
+    HSS_OP_SORT = 1,            /* hss_sort: every bucket sorted                   */
+    HSS_OP_INT_RANGE_ = 0x7FFFFFFF
+} hss_op;
+
 typedef struct hss_server_s* hss_server_t;
 
 typedef struct {
@@ -376,6 +384,7 @@ typedef struct {
     void* keys_out;             /* N keys, bucket order as hss_partition    */
     uint64_t* vals_out;         /* N payload words iff vals_in              */
     uint64_t* offsets;          /* p+1 words: chi                           */
+    hss_op op;                  /* HSS_OP_PARTITION (0) or HSS_OP_SORT      */
 } hss_request;
 
 typedef struct {

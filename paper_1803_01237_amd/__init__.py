@@ -159,7 +159,12 @@ _lib.hss_batch_profile_read.restype = C.c_int
 class _Request(C.Structure):
     _fields_ = [("n", C.c_uint64), ("p", C.c_uint32), ("key_type", C.c_int), ("eps", C.c_double),
                 ("seed", C.c_uint64), ("keys_in", C.c_void_p), ("vals_in", C.c_void_p),
-                ("keys_out", C.c_void_p), ("vals_out", C.c_void_p), ("offsets", C.c_void_p)]
+                ("keys_out", C.c_void_p), ("vals_out", C.c_void_p), ("offsets", C.c_void_p),
+                ("op", C.c_int)]
+
+
+HSS_OP_PARTITION, HSS_OP_SORT = 0, 1
+_OPS = {"partition": HSS_OP_PARTITION, "sort": HSS_OP_SORT}
 
 
 class _ServerConfig(C.Structure):
@@ -598,9 +603,10 @@ class Served:
 class Server:
     """Requests of any shape served as they arrive, with continuous batching:
     the library's worker threads (each on its own stream) run the queued
-    requests (same key width and payload choice) as batches, admitted under
-    an HBM budget, so batches overlap on the device; each result equals the
-    plain partition of that request."""
+    requests (same operation, key width and payload choice) as batches, a
+    sort request alone, admitted under an HBM budget, so batches overlap on
+    the device; each result equals the plain partition (or sort) of that
+    request."""
 
     def __init__(self, max_batch_keys: int = 0, max_batch_requests: int = 0, workers: int = 0,
                  hbm_budget: int = 0):
@@ -615,9 +621,10 @@ class Server:
         return float(_lib.hss_server_clock())
 
     def submit(self, keys, p: int, eps: float, seed: int, vals=None, keys_out=None, vals_out=None,
-               offsets=None, sync: bool = True) -> int:
-        """Queue one request; returns its ticket.  With sync, the current
-        stream is synchronised first, so that the inputs are complete."""
+               offsets=None, sync: bool = True, op: str = "partition") -> int:
+        """Queue one request (op "partition" or "sort"); returns its ticket.
+        With sync, the current stream is synchronised first, so that the
+        inputs are complete."""
         torch = _torch()
         if not keys.is_cuda or not keys.is_contiguous():
             raise ValueError("keys must be a contiguous device tensor")
@@ -629,9 +636,12 @@ class Server:
                    if offsets is None else offsets)
         if sync:
             torch.cuda.current_stream().synchronize()
+        if op not in _OPS:
+            raise ValueError(f"op must be one of {sorted(_OPS)}")
         req = _Request(n, p, _key_type(keys), eps, seed & NONE, keys.data_ptr(),
                        vals.data_ptr() if vals is not None else None, keys_out.data_ptr(),
-                       vals_out.data_ptr() if vals_out is not None else None, offsets.data_ptr())
+                       vals_out.data_ptr() if vals_out is not None else None, offsets.data_ptr(),
+                       _OPS[op])
         t = _u64()
         _check(_lib.hss_server_submit(self._h, C.byref(req), C.byref(t)), "hss_server_submit")
         self._live[int(t.value)] = (keys, vals, keys_out, vals_out, offsets)

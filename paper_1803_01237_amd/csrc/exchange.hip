@@ -37,10 +37,17 @@ __device__ __forceinline__ uint64_t piece_start(const ExchangeArgs& a, const Ins
     return a.prow[D.tab0 + (uint64_t)b * D.p + s];
 }
 
+// Rounds queued ahead of their read-back that did not settle every splitter
+// (or overran a buffer): the exchange waits for the rounds that follow.
+__device__ __forceinline__ bool gated(const ExchangeArgs& a) {
+    return a.gate && (a.gate->n_after != 0 || a.gate->overflow != 0);
+}
+
 // Workgroup per row u = bucket b of its instance (the last row of an
 // instance is none: no copy work).
 __global__ __launch_bounds__(kT) void piece_offsets_kernel(ExchangeArgs a) {
     __shared__ uint64_t scratch[kT / kWave];
+    if (gated(a)) return;
     const uint32_t u = blockIdx.x;
     const InstDesc D = a.inst[a.row_inst[u]];
     const uint32_t b = u - D.row0;
@@ -72,6 +79,7 @@ __global__ __launch_bounds__(kT) void piece_offsets_kernel(ExchangeArgs a) {
 // One workgroup: exclusive scan of the copy workgroups per bucket.
 __global__ __launch_bounds__(kScanT) void chunk_scan_kernel(ExchangeArgs a) {
     __shared__ uint64_t scratch[kScanT / kWave];
+    if (gated(a)) return;
     const uint32_t n = a.n_rows;
     const uint32_t per = (n + kScanT - 1) / kScanT;
     const uint32_t r0 = min(threadIdx.x * per, n), r1 = min(r0 + per, n);
@@ -124,7 +132,7 @@ __global__ __launch_bounds__(kT) void exchange_copy_kernel(ExchangeArgs a, uint3
     __shared__ uint32_t hist[kCount ? 256 : 1];
     __shared__ uint64_t red[kCount ? kT / kWave : 1][2];
     const uint32_t t = blockIdx.x;
-    if (t >= a.chunk0[a.n_rows]) return;
+    if (gated(a) || t >= a.chunk0[a.n_rows]) return;
     const uint32_t u = last_le_u32(a.chunk0, 0, a.n_rows, t);
     const InstDesc D = a.inst[a.row_inst[u]];
     const uint32_t b = u - D.row0;

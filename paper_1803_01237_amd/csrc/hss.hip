@@ -243,6 +243,8 @@ struct Engine {
     // stream while the memory-bound local sort runs (they depend on the
     // seed and the tags only)
     uint32_t pre_rounds = 0;
+    // rounds queued ahead of the exchange, not yet read back (0: none)
+    uint32_t ahead_rounds = 0;
     uint32_t pre_thresh[kPreRounds] = {};
     uint32_t pre_cap = 0;
     uint32_t* pre_mem = nullptr;        // kPreRounds counts, then pre_rounds lists of pre_cap tags
@@ -806,8 +808,8 @@ hss_status engine_init(Engine& E) {
     r.pre_cap = 0;
     E.pre_rounds = 0;
     double expect = 0;   // largest expected number of draws below a threshold
-    if (!E.batch && !E.fixed_mem && E.ih.size() == 1 && E.n_tot >= kPresampleMin && !E.tune.lsd_only &&
-        !E.tune.pick_sampler) {
+    if (!E.batch && !E.fixed_mem && !E.own_stream && E.ih.size() == 1 && E.n_tot >= kPresampleMin &&
+        !E.tune.lsd_only && !E.tune.pick_sampler) {
         for (uint32_t j = 1; j <= kPreRounds && j <= E.J; ++j) {
             if (L.all[j - 1] || (j > 1 && E.tune.probes_per_round)) break;
             // rounds whose lists would be long draw by themselves
@@ -955,6 +957,18 @@ void record_round(Engine& E, RoundRecord& rec, uint32_t j) {
     rec.all = h.all;
 }
 
+// The trace without tracing: counts of every round up to j that had
+// unsettled splitters, from the history read back with the counters.
+void record_history(Engine& E, uint32_t j) {
+    for (uint32_t q = 0; q < j; ++q) {
+        const RoundHist& h = E.h_hist[q];
+        if (h.unsettled == 0) break;
+        RoundRecord rec;
+        record_round(E, rec, q + 1);
+        E.trace.push_back(std::move(rec));
+    }
+}
+
 // Round 1 of a plan whose first sample is large (one-round HSS, a full
 // sample): the probes of its one interval are put in (key, tag) order by two
 // stable segmented sorts, by tag and then by key, instead of the pairwise
@@ -1071,24 +1085,24 @@ std::vector<uint32_t> counts_probe_major(const std::vector<uint32_t>& cm, uint64
     return out;
 }
 
-// Splitter rounds of every instance on the locally sorted buffer B; leaves
-// chi in chi_all and in every instance's offsets.
-hss_status determine_splitters(Engine& E, hipStream_t s) {
+// The rounds after round j0 (0: from the start), until every splitter is
+// settled.  With counters_ready the counters after round j0 were already
+// read back (the rounds queued ahead of an exchange).
+hss_status run_rounds(Engine& E, hipStream_t s, uint32_t j0, bool counters_ready) {
     RoundArgs& r = E.ra;
-    E.trace.clear();
     const bool tracing = E.tune.trace_level >= 1;
-    if (E.Q > 2 * (uint32_t)E.ih.size()) {
-        uint32_t restarts = 0;
-        HIP_TRY(launch_round_init(r, s));
-        uint32_t j = 0;
-        // the rounds that usually settle every splitter (k - 1 of them at the
-        // configurations measured), queued in one go; each further round is
-        // queued and read back on its own
-        const uint32_t first_chunk = std::min(std::max(E.k_max, 2u) - 1, E.J);
-        uint32_t chunk = tracing ? 1u : first_chunk;
-        for (;;) {
-            uint32_t stop = E.J;
-            if (E.tune.max_rounds) stop = std::min(stop, E.tune.max_rounds);
+    uint32_t restarts = 0;
+    uint32_t j = j0;
+    // the rounds that usually settle every splitter (k - 1 of them at the
+    // configurations measured), queued in one go; each further round is
+    // queued and read back on its own
+    const uint32_t first_chunk = std::min(std::max(E.k_max, 2u) - 1, E.J);
+    uint32_t chunk = tracing ? 1u : (j == 0 ? first_chunk : 1u);
+    bool queue = !counters_ready;
+    for (;;) {
+        uint32_t stop = E.J;
+        if (E.tune.max_rounds) stop = std::min(stop, E.tune.max_rounds);
+        if (queue) {
             const uint32_t upto = std::min(j + chunk, stop);
             if (j == 0 && upto > 1 && !E.big_first) {
                 const hss_status sg = launch_first_rounds(E, upto, s);
@@ -1106,70 +1120,116 @@ hss_status determine_splitters(Engine& E, hipStream_t s) {
             }
             hss_status st = read_counters(E, s, j);
             if (st != HSS_OK) return st;
-            const RoundCounters c = *E.h_ctr;
-            if (c.overflow) {
-                if (++restarts > kMaxRestarts) return fail(HSS_ERR_DEVICE, "probe buffers keep overflowing");
-                // the recorded needs, and at least twice what overflowed
-                const bool probes_short = c.m_max > E.cap || c.cm_max <= E.cm_cap;
-                const uint64_t need = probes_short ? std::max<uint64_t>(c.m_max + c.m_max / 4 + 1024, 2 * E.cap) : E.cap;
-                const uint64_t cm_need = c.cm_max > E.cm_cap ? std::max<uint64_t>(c.cm_max + c.cm_max / 4, 2 * E.cm_cap) : E.cm_cap;
-                st = grow(E, need, cm_need);
-                if (st != HSS_OK) return st;
-                E.trace.clear();
-                HIP_TRY(launch_round_init(r, s));
-                j = 0;
-                chunk = tracing ? 1u : first_chunk;
-                continue;
+        }
+        queue = true;
+        const RoundCounters c = *E.h_ctr;
+        if (c.overflow) {
+            if (++restarts > kMaxRestarts) return fail(HSS_ERR_DEVICE, "probe buffers keep overflowing");
+            // the recorded needs, and at least twice what overflowed
+            const bool probes_short = c.m_max > E.cap || c.cm_max <= E.cm_cap;
+            const uint64_t need = probes_short ? std::max<uint64_t>(c.m_max + c.m_max / 4 + 1024, 2 * E.cap) : E.cap;
+            const uint64_t cm_need = c.cm_max > E.cm_cap ? std::max<uint64_t>(c.cm_max + c.cm_max / 4, 2 * E.cm_cap) : E.cm_cap;
+            hss_status st = grow(E, need, cm_need);
+            if (st != HSS_OK) return st;
+            E.trace.clear();
+            HIP_TRY(launch_round_init(r, s));
+            j = 0;
+            chunk = tracing ? 1u : first_chunk;
+            continue;
+        }
+        if (c.err) return fail(HSS_ERR_DEVICE, "device consistency check failed (code " + std::to_string(c.err) + ")");
+        if (tracing && c.n_unsettled > 0) {
+            RoundRecord rec;
+            record_round(E, rec, j);
+            const uint64_t m = c.m_stored;
+            const uint32_t q = E.ih[0].q - 1;
+            std::vector<uint32_t> settled;
+            hss_status st;
+            if ((st = d2h(rec.key, r.ps_key, m, s)) != HSS_OK) return st;
+            if ((st = d2h(rec.tag, r.ps_tag, m, s)) != HSS_OK) return st;
+            if ((st = d2h(rec.rank, r.pr_rank, m, s)) != HSS_OK) return st;
+            if ((st = d2h(rec.lo, r.lrank + 1, q, s)) != HSS_OK) return st;
+            if ((st = d2h(rec.hi, r.urank + 1, q, s)) != HSS_OK) return st;
+            if ((st = d2h(rec.chi, r.chi + 1, q, s)) != HSS_OK) return st;
+            if ((st = d2h(settled, r.settled + 1, q, s)) != HSS_OK) return st;
+            std::vector<uint32_t> cm;
+            const uint64_t p = E.ih[0].p;
+            if (E.tune.trace_level >= 2 && (st = d2h(cm, E.cmat, m * p, s)) != HSS_OK) return st;
+            HIP_TRY(hipStreamSynchronize(s));
+            if (E.tune.trace_level >= 2) rec.counts = counts_probe_major(cm, m, p);
+            rec.settled.resize(q);
+            for (uint32_t i = 0; i < q; ++i) {
+                rec.settled[i] = settled[i] ? 1 : 0;
+                if (settled[i]) { rec.lo[i] = kNone; rec.hi[i] = kNone; }
             }
-            if (c.err) return fail(HSS_ERR_DEVICE, "device consistency check failed (code " + std::to_string(c.err) + ")");
-            if (tracing && c.n_unsettled > 0) {
-                RoundRecord rec;
-                record_round(E, rec, j);
-                const uint64_t m = c.m_stored;
-                const uint32_t q = E.ih[0].q - 1;
-                std::vector<uint32_t> settled;
-                if ((st = d2h(rec.key, r.ps_key, m, s)) != HSS_OK) return st;
-                if ((st = d2h(rec.tag, r.ps_tag, m, s)) != HSS_OK) return st;
-                if ((st = d2h(rec.rank, r.pr_rank, m, s)) != HSS_OK) return st;
-                if ((st = d2h(rec.lo, r.lrank + 1, q, s)) != HSS_OK) return st;
-                if ((st = d2h(rec.hi, r.urank + 1, q, s)) != HSS_OK) return st;
-                if ((st = d2h(rec.chi, r.chi + 1, q, s)) != HSS_OK) return st;
-                if ((st = d2h(settled, r.settled + 1, q, s)) != HSS_OK) return st;
-                std::vector<uint32_t> cm;
-                const uint64_t p = E.ih[0].p;
-                if (E.tune.trace_level >= 2 && (st = d2h(cm, E.cmat, m * p, s)) != HSS_OK) return st;
-                HIP_TRY(hipStreamSynchronize(s));
-                if (E.tune.trace_level >= 2) rec.counts = counts_probe_major(cm, m, p);
-                rec.settled.resize(q);
-                for (uint32_t i = 0; i < q; ++i) {
-                    rec.settled[i] = settled[i] ? 1 : 0;
-                    if (settled[i]) { rec.lo[i] = kNone; rec.hi[i] = kNone; }
-                }
-                E.trace.push_back(std::move(rec));
-            }
-            if (c.n_after == 0) {
-                if (!tracing) {
-                    // counts of every round that had unsettled splitters
-                    for (uint32_t q = 0; q < j; ++q) {
-                        const RoundHist& h = E.h_hist[q];
-                        if (h.unsettled == 0) break;
-                        RoundRecord rec;
-                        record_round(E, rec, q + 1);
-                        E.trace.push_back(std::move(rec));
-                    }
-                }
-                break;
-            }
-            if (j >= stop) {
-                if (E.tune.max_rounds && j >= E.tune.max_rounds)
-                    return fail(HSS_ERR_NOT_CONVERGED, "round cap reached with " + std::to_string(c.n_after) + " splitters unsettled");
-                return fail(HSS_ERR_DEVICE, "splitters unsettled after the rate reached 1");
-            }
-            chunk = 1;
+            E.trace.push_back(std::move(rec));
+        }
+        if (c.n_after == 0) {
+            if (!tracing) record_history(E, j);
+            return HSS_OK;
+        }
+        if (j >= stop) {
+            if (E.tune.max_rounds && j >= E.tune.max_rounds)
+                return fail(HSS_ERR_NOT_CONVERGED, "round cap reached with " + std::to_string(c.n_after) + " splitters unsettled");
+            return fail(HSS_ERR_DEVICE, "splitters unsettled after the rate reached 1");
+        }
+        chunk = 1;
+    }
+}
+
+// Splitter rounds of every instance on the locally sorted buffer B; leaves
+// chi in chi_all and in every instance's offsets.  With `ahead`, the rounds
+// that usually settle every splitter are queued without reading anything
+// back; the call's closing read-back checks them (finish()), and what follows
+// on the stream must do nothing unless they did.
+hss_status determine_splitters(Engine& E, hipStream_t s, bool ahead) {
+    RoundArgs& r = E.ra;
+    E.trace.clear();
+    E.ahead_rounds = 0;
+    if (E.Q > 2 * (uint32_t)E.ih.size()) {
+        HIP_TRY(launch_round_init(r, s));
+        const uint32_t first_chunk = std::min(std::max(E.k_max, 2u) - 1, E.J);
+        const uint32_t upto = E.tune.max_rounds ? std::min(first_chunk, E.tune.max_rounds) : first_chunk;
+        if (ahead && upto > 1 && !E.big_first && E.tune.trace_level == 0) {
+            const hss_status sg = launch_first_rounds(E, upto, s);
+            if (sg != HSS_OK) return sg;
+            E.ahead_rounds = upto;
+        } else {
+            const hss_status st = run_rounds(E, s, 0, false);
+            if (st != HSS_OK) return st;
         }
     }
     HIP_TRY(launch_finalize(r, E.chi_all, s));
     return HSS_OK;
+}
+
+// The exchange of the engine's call: into the callers' outputs, or into A
+// before the bucket sort.  Behind rounds queued ahead of their read-back it
+// waits for them (the gate).
+ExchangeArgs exchange_args(Engine& E, bool sort_buckets) {
+    ExchangeArgs ex;
+    ex.key_bytes = E.key_bytes;
+    ex.B = E.B;
+    ex.Bv = E.payload ? E.Bv : nullptr;
+    ex.n_inst = (uint32_t)E.ih.size();
+    ex.n_rows = E.Q;
+    ex.p_max = E.p_max;
+    ex.inst = E.inst_d;
+    ex.run = E.run_d;
+    ex.seg_off = E.seg_off;
+    ex.row_inst = E.row_inst;
+    ex.prow = E.ra.prow;
+    ex.chi_all = E.chi_all;
+    ex.dst = E.dst;
+    ex.chunk0 = E.chunk0;
+    ex.max_chunks = exchange_chunk_bound(E.n_tot, E.Q);
+    ex.total = E.n_tot;
+    ex.out = sort_buckets ? E.A : nullptr;
+    ex.vout = sort_buckets ? E.Av : nullptr;
+    ex.err = &E.ra.ctr->err;
+    ex.prof = &E.prof;
+    ex.gate = E.ahead_rounds ? E.ra.ctr : nullptr;
+    return ex;
 }
 
 // One call on an engine: local sort, rounds, exchange (and, for one
@@ -1199,9 +1259,12 @@ hss_status engine_run(Engine& E, const void* kin, const uint64_t* vin, void* kou
                                  E.first_shift, E.first_base, true, s);
     if (st != HSS_OK) return st;
     if (E.pre_rounds) HIP_TRY(hipStreamWaitEvent(s, E.ev_pre, 0));
-    // phase 2: splitter rounds
+    // phase 2: splitter rounds; a plain partition of one instance queues its
+    // exchange right behind the rounds that usually settle every splitter,
+    // and the call's closing read-back checks that they did
     E.prof.begin(s);
-    st = determine_splitters(E, s);
+    const bool ahead = !sort_buckets && !E.chi_out_host && E.ih.size() == 1 && E.tune.trace_level == 0;
+    st = determine_splitters(E, s, ahead);
     if (st != HSS_OK) return st;
     E.prof.end(kProfRounds, s, 0);
     if (E.chi_out_host) {
@@ -1209,27 +1272,7 @@ hss_status engine_run(Engine& E, const void* kin, const uint64_t* vin, void* kou
         HIP_TRY(hipEventRecord(E.chi_ready, s));
     }
     // phase 3: exchange into the outputs (or into A before the bucket sort)
-    ExchangeArgs ex;
-    ex.key_bytes = E.key_bytes;
-    ex.B = E.B;
-    ex.Bv = E.payload ? E.Bv : nullptr;
-    ex.n_inst = (uint32_t)E.ih.size();
-    ex.n_rows = E.Q;
-    ex.p_max = E.p_max;
-    ex.inst = E.inst_d;
-    ex.run = E.run_d;
-    ex.seg_off = E.seg_off;
-    ex.row_inst = E.row_inst;
-    ex.prow = E.ra.prow;
-    ex.chi_all = E.chi_all;
-    ex.dst = E.dst;
-    ex.chunk0 = E.chunk0;
-    ex.max_chunks = exchange_chunk_bound(E.n_tot, E.Q);
-    ex.total = E.n_tot;
-    ex.out = sort_buckets ? E.A : nullptr;
-    ex.vout = sort_buckets ? E.Av : nullptr;
-    ex.err = &E.ra.ctr->err;
-    ex.prof = &E.prof;
+    ExchangeArgs ex = exchange_args(E, sort_buckets);
     // sort (one instance): the bucket sort takes its first MSD digit over each
     // bucket's key range, and the exchange counts those digits as it writes
     // the buckets (the count pass of the bucket sort's first level)
@@ -1284,6 +1327,27 @@ hss_status check_io(const Engine& E, const InstHost& h, const void* kin, const u
 }
 
 hss_status finish(Engine& E, hipStream_t s) {
+    if (E.ahead_rounds) {
+        // rounds queued ahead of the exchange: one read-back for both
+        const uint32_t j = E.ahead_rounds;
+        hss_status st = read_counters(E, s, j);
+        if (st != HSS_OK) return st;
+        const RoundCounters c = *E.h_ctr;
+        if (!c.overflow && c.n_after == 0) {
+            E.ahead_rounds = 0;
+            if (c.err)
+                return fail(HSS_ERR_DEVICE, "device consistency check failed (code " + std::to_string(c.err) + ")");
+            record_history(E, j);
+            return HSS_OK;
+        }
+        // splitters left (or a buffer overran): the exchange did nothing; go
+        // on with the rounds, then exchange
+        st = run_rounds(E, s, j, true);
+        if (st != HSS_OK) return st;
+        HIP_TRY(launch_finalize(E.ra, E.chi_all, s));
+        HIP_TRY(launch_exchange(exchange_args(E, false), s));
+        E.ahead_rounds = 0;
+    }
     // the exchange checks that every bucket's pieces add up to its size
     hss_status st = read_counters(E, s);
     if (st != HSS_OK) return st;
@@ -1521,9 +1585,32 @@ uint64_t footprint(const hss_request& r) {
     return 4 * r.n * w + r.n / 2 + 12ull * ((uint64_t)r.p + 1) * r.p + (1ull << 20);
 }
 
-// One batch of queued requests (same key type and payload choice), run like
-// hss_batch_partition on a worker's stream with memory from the cache.
+// One sort request, run like hss_sort of a plan of its shape on a worker's
+// stream with memory from the cache.
+hss_status run_server_sort(hss_server_s* S, hipStream_t stream, const hss_request& r) {
+    std::unique_ptr<Engine> E(new (std::nothrow) Engine());
+    if (!E) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    E->key_bytes = r.key_type == HSS_U32 ? 4 : 8;
+    E->payload = r.vals_in != nullptr;
+    E->mem = &S->cache;
+    E->own_stream = stream;
+    hss_status st = new_engine_instance(*E, r.n, r.p, r.eps);
+    if (st == HSS_OK) st = engine_init(*E);
+    if (st != HSS_OK) return st;
+    E->cur_seed = r.seed;
+    HIP_TRY(launch_set_run(InstRun{r.seed, r.keys_in, r.vals_in, r.keys_out, r.vals_out, r.offsets}, E->run_d,
+                           stream));
+    HIP_TRY(launch_counters_reset(E->ra.ctr, stream));
+    st = engine_run(*E, r.keys_in, r.vals_in, r.keys_out, r.vals_out, stream, true);
+    if (st != HSS_OK) return st;
+    return finish(*E, stream);   // synchronises the stream
+}
+
+// One batch of queued requests (same operation, key type and payload
+// choice), run like hss_batch_partition on a worker's stream with memory from
+// the cache; a sort request is a batch of its own.
 hss_status run_server_batch(hss_server_s* S, hipStream_t stream, const std::vector<hss_request>& rq) {
+    if (rq[0].op == HSS_OP_SORT) return run_server_sort(S, stream, rq[0]);
     std::unique_ptr<Engine> E(new (std::nothrow) Engine());
     if (!E) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
     E->batch = true;
@@ -1547,10 +1634,12 @@ hss_status run_server_batch(hss_server_s* S, hipStream_t stream, const std::vect
     return finish(*E, stream);   // synchronises the stream
 }
 
-// A worker: takes the requests at the head of the queue that the budget
-// admits (in submission order, of the head's class, within the batch limits)
-// and runs them as one batch on its stream; the head waits while the
-// batches already running leave it no room, unless none is running.
+// A worker: takes the head of the queue and the later queued requests of its
+// class (operation, key type, payload choice) that the budget admits, in
+// submission order and within the batch limits -- requests of other classes
+// keep their places -- and runs them as one batch on its stream; the head
+// waits while the batches already running leave it no room, unless none is
+// running.
 void server_loop(hss_server_s* S, uint32_t wid) {
     (void)hipSetDevice(S->device);
     const hipStream_t stream = S->streams[wid];
@@ -1570,17 +1659,22 @@ void server_loop(hss_server_s* S, uint32_t wid) {
             const hss_request& f = S->reqs[S->queue.front()].r;
             const bool pay = f.vals_in != nullptr;
             const hss_key_type kt = f.key_type;
+            const hss_op op = f.op;
+            const uint32_t max_reqs = op == HSS_OP_SORT ? 1u : S->max_reqs;
             uint64_t total = 0;
-            while (!S->queue.empty() && rq.size() < S->max_reqs) {
-                const hss_request& r = S->reqs[S->queue.front()].r;
-                if (r.key_type != kt || (r.vals_in != nullptr) != pay) break;
+            for (auto it = S->queue.begin(); it != S->queue.end() && rq.size() < max_reqs;) {
+                const hss_request& r = S->reqs[*it].r;
+                if (r.op != op || r.key_type != kt || (r.vals_in != nullptr) != pay) {
+                    ++it;   // another class: keeps its place for a later batch
+                    continue;
+                }
                 const uint64_t fp = footprint(r);
                 if (!rq.empty() && (total + r.n > S->max_keys || S->admitted + fp_total + fp > S->budget)) break;
                 total += r.n;
                 fp_total += fp;
                 rq.push_back(r);
-                tickets.push_back(S->queue.front());
-                S->queue.pop_front();
+                tickets.push_back(*it);
+                it = S->queue.erase(it);
             }
             S->admitted += fp_total;
             S->running += 1;
@@ -2222,6 +2316,7 @@ hss_status hss_server_submit(hss_server_t S, const hss_request* req, uint64_t* t
         if (!S || !req || !ticket) return fail(HSS_ERR_INVALID_ARG, "null server, request or ticket");
         const hss_request& r = *req;
         if (r.key_type != HSS_U32 && r.key_type != HSS_U64) return fail(HSS_ERR_INVALID_ARG, "bad key type");
+        if (r.op != HSS_OP_PARTITION && r.op != HSS_OP_SORT) return fail(HSS_ERR_INVALID_ARG, "bad operation");
         if (r.n == 0 || r.p == 0 || (uint64_t)r.p > r.n) return fail(HSS_ERR_INVALID_ARG, "need 1 <= p <= N");
         if (r.n >= (1ull << 32)) return fail(HSS_ERR_UNSUPPORTED, "N must be below 2^32");
         if (!(r.eps > 0.0 && r.eps < 1.0)) return fail(HSS_ERR_INVALID_ARG, "need 0 < eps < 1");

@@ -620,6 +620,10 @@ struct ExchangeArgs {
     uint64_t* vout = nullptr;
     unsigned int* err;
     Profiler* prof = nullptr;      // optional
+    // when set, every kernel does nothing unless the rounds before it left
+    // no splitter unsettled and no buffer overrun (rounds queued ahead of
+    // their read-back)
+    const RoundCounters* gate = nullptr;
 };
 
 hipError_t launch_exchange(const ExchangeArgs& a, hipStream_t s);

@@ -564,3 +564,32 @@ def test_pick_sampler_matches_oracle(hss, case):
                     tr = plan.trace()
                     assert [(a.domain, a.m, a.thresh, a.all) for a in tr] == \
                         [(b.domain, b.m, b.thresh, b.all) for b in ref.rounds]
+
+
+def test_rounds_queued_ahead_of_the_exchange(hss):
+    """A plain partition queues the k - 1 rounds that usually settle every
+    splitter and its exchange behind them with no read-back in between; the
+    exchange runs only if they did, and the closing read-back goes on with the
+    rounds and exchanges again otherwise.  Over 24 seeds (5 of which take a
+    k-th round in the oracle) outputs, offsets, splitters and the per-round
+    counts must equal the oracle's, through both paths."""
+    n, p, eps = 1 << 18, 64, 0.05
+    _say(f"[parity] rounds queued ahead: uniform64 n={n} p={p} eps={eps}, seeds 1000..1023")
+    keys = _keys("uniform64", n, 9, 64)
+    kd = _dev(keys)
+    longer = 0
+    with hss.Plan(n, p, eps) as plan:
+        k = plan.constants(1)[1]
+        for seed in range(1000, 1024):
+            ref = oracle.hss(keys, p, eps, seed, mode="partition", trace_level=0)
+            assert ref.status == 0
+            ko, _, off = plan.partition(kd, seed)
+            assert np.array_equal(_host(off, np.uint64), ref.offsets), seed
+            assert np.array_equal(_host(ko, np.uint64), ref.keys), seed
+            chi = plan.splitters()[0]
+            assert np.array_equal(chi, ref.chi), seed
+            tr = plan.trace()
+            assert [(r.domain, r.m) for r in tr] == [(r.domain, r.m) for r in ref.rounds], seed
+            longer += len(ref.rounds) > k - 1
+    _say(f"[parity] rounds queued ahead: {longer} of 24 seeds needed more than k - 1 = {k - 1} rounds")
+    assert longer > 0

@@ -1,6 +1,7 @@
 """GPU tests of the request server: every served request equals the plain
-hss_partition of the same request bit for bit (keys, payload, offsets),
-whatever else was batched with it; a few small ones also equal the oracle."""
+hss_partition (or hss_sort) of the same request bit for bit (keys, payload,
+offsets), whatever else was batched with it; a few small ones also equal the
+oracle."""
 import sys
 import time
 
@@ -110,6 +111,7 @@ def test_server_polls_and_reuses_memory(hss):
 
 
 def test_server_rejects_bad_requests(hss):
+    import ctypes as C
     with hss.Server() as srv:
         k = torch.zeros(100, dtype=torch.int64, device="cuda")
         with pytest.raises(hss.HssError):
@@ -118,7 +120,56 @@ def test_server_rejects_bad_requests(hss):
             srv.submit(k, 4, 1.5, 1)                   # eps >= 1
         with pytest.raises(hss.HssError):
             srv.submit(k[1:], 4, 0.05, 1)              # misaligned keys
+        with pytest.raises(ValueError):
+            srv.submit(k, 4, 0.05, 1, op="merge")      # no such operation
+        ko = torch.empty_like(k)
+        off = torch.empty(5, dtype=torch.int64, device="cuda")
+        req = hss._Request(100, 4, hss.HSS_U64, 0.05, 1, k.data_ptr(), None, ko.data_ptr(), None,
+                           off.data_ptr(), 7)           # an operation code the library does not know
+        t = C.c_uint64()
+        assert hss._lib.hss_server_submit(srv._h, C.byref(req), C.byref(t)) == -1   # invalid argument
         assert srv.stats()["requests"] == 0
+
+
+def test_served_sorts_and_partitions_equal_plain_calls(hss):
+    """A stream mixing sort and partition requests: a sort request runs as a
+    batch of its own, partitions batch together; every result equals the
+    plain hss_sort or hss_partition of the same request, and small sorts the
+    oracle's."""
+    reqs = _requests(24, 8)
+    reqs.append(((1 << 20) + 5, 96, 0.02, 8, True, 7999))   # a sort above the early-draw size
+    ops = ["sort" if i % 2 == 0 else "partition" for i in range(len(reqs))]
+    ops[-1] = "sort"
+    _say(f"[server] {len(reqs)} requests, sorts and partitions mixed")
+    with hss.Server(max_batch_keys=1 << 20, max_batch_requests=16) as srv:
+        tickets, held = [], []
+        for i, ((n, p, eps, kb, pay, dseed), op) in enumerate(zip(reqs, ops)):
+            keys, vals = _inputs(n, kb, pay, dseed)
+            kd = _dev(keys)
+            vd = _dev(vals) if pay else None
+            tickets.append(srv.submit(kd, p, eps, dseed, vd, op=op))
+            held.append((keys, vals, kd, vd))
+        done = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+        assert st["requests"] == len(reqs)
+        assert st["batches"] >= ops.count("sort")
+        for i, ((n, p, eps, kb, pay, dseed), op, r) in enumerate(zip(reqs, ops, done)):
+            keys, vals, kd, vd = held[i]
+            with hss.Plan(n, p, eps, key_bytes=kb, payload=pay) as plan:
+                fn = plan.sort if op == "sort" else plan.partition
+                ko, vo, off = fn(kd, dseed, vd)
+                torch.cuda.synchronize()
+                assert torch.equal(off, r.offsets), (i, op)
+                assert torch.equal(ko, r.keys_out), (i, op)
+                if pay:
+                    assert torch.equal(vo, r.vals_out), (i, op)
+            if op == "sort" and n < (1 << 17):
+                ref = oracle.hss(keys, p, eps, dseed, vals=vals, mode="sort", trace_level=0)
+                assert np.array_equal(r.offsets.cpu().numpy().view(np.uint64), ref.offsets), i
+                kt = np.uint64 if kb == 8 else np.uint32
+                assert np.array_equal(r.keys_out.cpu().numpy().view(kt), ref.keys), i
+                if pay:
+                    assert np.array_equal(r.vals_out.cpu().numpy().view(np.uint64), ref.vals), i
 
 
 def test_batches_overlap_and_match_alone(hss):
