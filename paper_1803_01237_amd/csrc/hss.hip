@@ -583,6 +583,10 @@ size_t layout(Engine& E, char* base) {
     E.lw.vdst = ar.take<uint64_t>(lwc);
     E.lw.and_mask = ar.take<uint64_t>(lwc);
     E.lw.or_mask = ar.take<uint64_t>(lwc);
+    // splitter tables of the deeper levels' entries
+    E.lw.splits = ar.take<uint64_t>(ovc * kSplitSlots);
+    E.lw.n_splits = ar.take<uint32_t>(ovc);
+    E.lw.split_entries = ar.take<uint32_t>(1);
     const uint64_t pjc = packed_capacity(n);
     E.pj.count = ar.take<uint32_t>(1);
     E.pj.start = ar.take<uint64_t>(pjc);
@@ -592,6 +596,14 @@ size_t layout(Engine& E, char* base) {
     E.pj.bits = ar.take<uint8_t>(pjc);
     E.pj.capacity = (uint32_t)pjc;
     E.pj.err = list_err;
+    const uint64_t stc = stage_capacity(msd_segs, n);
+    E.pj.s_start = ar.take<uint64_t>(stc);
+    E.pj.s_len = ar.take<uint32_t>(stc);
+    E.pj.s_base = ar.take<uint64_t>(stc);
+    E.pj.s_bits = ar.take<uint8_t>(stc);
+    E.pj.s_capacity = stc;
+    E.pj.n_of = ar.take<uint32_t>(lwc + 1);
+    E.pj.chunk_sum = ar.take<uint32_t>(lwc / kPackChunk + 2);
     const uint64_t slc = slow_capacity(n);
     E.sl.count = ar.take<uint32_t>(1);
     E.sl.beg = ar.take<uint64_t>(slc);

@@ -137,7 +137,17 @@ struct TileMap {
     const uint64_t* vdst = nullptr;
     // optional: segments flagged here are left alone by the scatter
     const uint8_t* skip = nullptr;
+    // optional (splitter levels): per-segment tables of kSplitSlots keys,
+    // n_splits[s] splitters ascending then all ones; a key's "digit" is its
+    // class among them (2 j + 1: equal to splitter j; 2 j: between splitters
+    // j - 1 and j)
+    const uint64_t* splits = nullptr;
+    const uint32_t* n_splits = nullptr;
 };
+
+// Splitter table of one entry of a splitter level: at most kSplitSlots - 1
+// splitters, so that classes 0 .. 2 (kSplitSlots - 1) fit 256 digits.
+constexpr uint32_t kSplitSlots = 128;
 
 // One stable counting pass on digit [shift, shift+8) of every segment.
 struct RadixPass {
@@ -250,7 +260,20 @@ struct PackedJobs {
     uint8_t* bits = nullptr;           // free bits of key - base inside the job
     uint32_t capacity = 0;
     uint32_t* err = nullptr;
+    // Staging: entry e writes its jobs at slots from stage_slot(e) (room for
+    // the at most 8 jobs per tile of 4096 keys plus one it can give) and
+    // their number in n_of[e]; a scan over the entries then packs them into
+    // the arrays above.  No counter is shared between entries: one atomic
+    // per entry on one word would take its turn with every other entry's.
+    uint64_t* s_start = nullptr;       // capacity stage_capacity()
+    uint32_t* s_len = nullptr;
+    uint64_t* s_base = nullptr;
+    uint8_t* s_bits = nullptr;
+    uint64_t s_capacity = 0;
+    uint32_t* n_of = nullptr;          // level_capacity() + 1
+    uint32_t* chunk_sum = nullptr;     // level_capacity() / kPackChunk + 2
 };
+constexpr uint32_t kPackChunk = 1024;  // entries per workgroup of the packing
 
 // Per-entry work arrays of one MSD level (level 1: the MSD segments; deeper:
 // the entries of an OversizeList), capacity level_capacity().
@@ -261,6 +284,9 @@ struct LevelWork {
     uint64_t* vdst = nullptr;
     uint64_t* and_mask = nullptr;
     uint64_t* or_mask = nullptr;
+    uint64_t* splits = nullptr;        // deeper levels: kSplitSlots keys per entry
+    uint32_t* n_splits = nullptr;      // splitters of every entry
+    uint32_t* split_entries = nullptr; // nonzero when an entry of the level has splitters
 };
 
 // Sub-buckets that fit LDS but hold a large group of keys equal in their
@@ -375,6 +401,7 @@ uint64_t oversize_capacity(uint64_t total_len);
 uint64_t oversize_tile_capacity(uint64_t total_len);
 uint64_t level_capacity(uint32_t num_segs, uint64_t total_len);
 uint64_t packed_capacity(uint64_t total_len);
+uint64_t stage_capacity(uint32_t num_segs, uint64_t total_len);
 uint64_t slow_capacity(uint64_t total_len);
 
 // --------------------------------------------------------------- rounds ----

@@ -31,6 +31,26 @@ __device__ __forceinline__ uint32_t digit_of(K k, int shift) {
     return (uint32_t)(k >> shift) & 0xFFu;
 }
 
+// Class of key k among the m splitters of a table T of kSplitSlots keys (the
+// m splitters ascending, then all ones): with s the number of splitters below
+// k, 2 s + 1 when k equals splitter s, else 2 s.  Binary lifting over the
+// first kSplitSlots - 1 slots; the last slot is always padding.  A segment
+// with no splitters keeps its digit.
+__device__ __forceinline__ uint32_t split_class(const uint64_t* T, uint32_t m, uint64_t k) {
+    uint32_t s = 0;
+#pragma unroll
+    for (uint32_t h = kSplitSlots / 2; h > 0; h >>= 1)
+        if (T[s + h - 1] < k) s += h;
+    return 2 * s + ((s < m && T[s] == k) ? 1u : 0u);
+}
+
+// A segment's splitter table into LDS (threads below kSplitSlots), with its
+// splitter count.
+__device__ __forceinline__ void load_splits(const TileMap& m, uint32_t seg, uint64_t* T, uint32_t* tm) {
+    if (threadIdx.x < kSplitSlots) T[threadIdx.x] = m.splits[(uint64_t)seg * kSplitSlots + threadIdx.x];
+    if (threadIdx.x == 0) *tm = m.n_splits[seg];
+}
+
 // Key range [base, stop) of workgroup tile `bid`; false when it is empty.
 __device__ __forceinline__ bool tile_range(const TileMap& m, uint32_t bid, uint64_t* base,
                                            uint64_t* stop, uint32_t* seg) {
@@ -70,23 +90,31 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
 }
 
 // kMask: also the AND and OR of every key - base of the segment (which bits
-// vary inside it), one pair of atomics per tile.
-template <typename K, bool kMask>
+// vary inside it), one pair of atomics per tile.  kSplit: the "digit" of a
+// key is its class among the segment's splitters.
+template <typename K, bool kMask, bool kSplit>
 __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(const K* __restrict__ keys,
                                                                    TileMap m, int shift,
                                                                    const uint8_t* __restrict__ seg_shift,
                                                                    uint32_t* __restrict__ counts,
                                                                    uint64_t* __restrict__ and_mask,
                                                                    uint64_t* __restrict__ or_mask) {
+    static_assert(kSortThreads >= (int)kSplitSlots, "one thread per splitter slot");
     __shared__ uint32_t hist[256];
     __shared__ uint64_t wmask[kMask ? kSortThreads / kWave : 1][2];
+    __shared__ uint64_t T[kSplit ? kSplitSlots : 1];
+    __shared__ uint32_t tm;
     hist[threadIdx.x] = 0;
-    __syncthreads();
     bool in_seg = false;
     uint32_t mseg = 0;
     uint64_t base, e;
     uint32_t seg;
-    if (tile_range(m, blockIdx.x, &base, &e, &seg)) {
+    const bool has = tile_range(m, blockIdx.x, &base, &e, &seg);
+    if constexpr (kSplit) {
+        if (has) load_splits(m, seg, T, &tm);
+    }
+    __syncthreads();
+    if (has) {
         in_seg = true;
         mseg = seg;
         if (seg_shift) shift = seg_shift[seg];
@@ -102,15 +130,27 @@ __global__ __launch_bounds__(kSortThreads) void radix_count_kernel(const K* __re
             const uint32_t li = w * kKeysPerWave + r * kWave + lane;
             kr[r] = li < n_tile ? ld_stream(src + li) : (K)0;
         }
+        // a class: every row's search in flight together
+        uint32_t dg[kSplit ? kSortItems : 1];
+        if constexpr (kSplit) {
+            const uint32_t nsp = tm;
+#pragma unroll
+            for (int r = 0; r < kSortItems; ++r)
+                dg[r] = nsp ? split_class(T, nsp, (uint64_t)kr[r]) : digit_of((K)(kr[r] - kb), shift);
+        }
+        auto dk = [&](int r) -> uint32_t {
+            if constexpr (kSplit) return dg[r];
+            else return digit_of((K)(kr[r] - kb), shift);
+        };
         // skewed inputs: the lanes holding the wave's current dominant digit
         // add with one atomic (many lanes on one LDS counter would take turns)
-        uint32_t dom = digit_of((K)(kr[0] - kb), shift);
+        uint32_t dom = dk(0);
         dom = (uint32_t)__shfl((int)dom, 0);
 #pragma unroll
         for (int r = 0; r < kSortItems; ++r) {
             const uint32_t li = w * kKeysPerWave + r * kWave + lane;
             const bool valid = li < n_tile;
-            const uint32_t d = digit_of((K)(kr[r] - kb), shift);
+            const uint32_t d = dk(r);
             const uint64_t md = __ballot(valid && d == dom);
             const uint32_t nd = (uint32_t)__popcll(md);
             if (nd && (int)lane == __ffsll((unsigned long long)md) - 1) atomicAdd(&hist[dom], nd);
@@ -205,8 +245,9 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n) {
 // equal digits with ballots (a wave owns a contiguous quarter of the tile,
 // rows of 64 keys in order) and per-wave digit counts give the offsets, so
 // equal digits keep their input order.  Otherwise one LDS atomic per key
-// hands out the slots of its digit in arbitrary order.
-template <typename K, bool kPayload, bool kStable>
+// hands out the slots of its digit in arbitrary order.  kSplit: the digit of
+// a key is its class among the segment's splitters.
+template <typename K, bool kPayload, bool kStable, bool kSplit>
 __global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
     const K* __restrict__ kin, const uint64_t* __restrict__ vin, K* __restrict__ kout,
     uint64_t* __restrict__ vout, TileMap m, int shift0, const uint8_t* __restrict__ seg_shift,
@@ -222,6 +263,9 @@ __global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
     __shared__ uint32_t scratch[kScatterThreads / kWave];
     __shared__ uint64_t stage[kSortTile];
     __shared__ uint16_t sidx[kPayload ? kSortTile : 1];   // input index of each staged key
+    __shared__ uint64_t T[kSplit ? kSplitSlots : 1];
+    __shared__ uint32_t tm;
+    __shared__ uint8_t sdig[kSplit ? kSortTile : 1];      // class of each staged key
 
     const uint32_t w = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
@@ -241,7 +285,12 @@ __global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
         if (sub) __syncthreads();   // the previous tile is done with the LDS
         for (int i = threadIdx.x; i < (kStable ? kWv : 1) * 256; i += kScatterThreads) (&whist[0][0])[i] = 0;
         if (digit_thread) gofs[threadIdx.x] = counts[(uint64_t)tile * 256 + threadIdx.x];
+        if constexpr (kSplit) load_splits(m, seg, T, &tm);
         __syncthreads();
+        auto dig = [&](K k) -> uint32_t {
+            if constexpr (kSplit) return tm ? split_class(T, tm, (uint64_t)k) : digit_of((K)(k - kb), shift);
+            else return digit_of((K)(k - kb), shift);
+        };
 
         const K* src = tile_source(m, kin, seg, base);
         K key[kIt];
@@ -251,12 +300,23 @@ __global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
             const uint32_t li = w * kKpw + r * kWave + lane;
             key[r] = li < n_tile ? ld_stream(src + li) : (K)0;
         }
+        // a class is found once per key (all rows' searches in flight
+        // together) and kept beside the staged key; a digit is recomputed
+        uint32_t dg[kSplit ? kIt : 1];
+        if constexpr (kSplit) {
+#pragma unroll
+            for (int r = 0; r < kIt; ++r) dg[r] = dig(key[r]);
+        }
+        auto dk = [&](int r) -> uint32_t {
+            if constexpr (kSplit) return dg[r];
+            else return dig(key[r]);
+        };
         if constexpr (kStable) {
 #pragma unroll
             for (int r = 0; r < kIt; ++r) {
                 const uint32_t li = w * kKpw + r * kWave + lane;
                 const bool valid = li < n_tile;
-                const uint32_t d = digit_of((K)(key[r] - kb), shift);
+                const uint32_t d = dk(r);
                 const uint64_t live = __ballot(valid);
                 const uint64_t mm = match_byte(d, live);
                 const int leader = valid ? (int)(__ffsll((unsigned long long)mm) - 1) : (int)lane;
@@ -289,23 +349,24 @@ __global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
             for (int r = 0; r < kIt; ++r) {
                 const uint32_t li = w * kKpw + r * kWave + lane;
                 if (li < n_tile) {
-                    const uint32_t d = digit_of((K)(key[r] - kb), shift);
+                    const uint32_t d = dk(r);
                     const uint32_t pos = tstart[d] + whist[w][d] + rank[r];
                     stage[pos] = (uint64_t)key[r];
                     if constexpr (kPayload) sidx[pos] = (uint16_t)li;
+                    if constexpr (kSplit) sdig[pos] = (uint8_t)d;
                 }
             }
         } else {
             uint32_t* hist = &whist[0][0];   // one tile-wide count per digit
             // the lanes holding the wave's current dominant digit take their
             // slots with one atomic (skewed inputs), the others one each
-            uint32_t dom = digit_of((K)(key[0] - kb), shift);
+            uint32_t dom = dk(0);
             dom = (uint32_t)__shfl((int)dom, 0);
 #pragma unroll
             for (int r = 0; r < kIt; ++r) {
                 const uint32_t li = w * kKpw + r * kWave + lane;
                 const bool valid = li < n_tile;
-                const uint32_t d = digit_of((K)(key[r] - kb), shift);
+                const uint32_t d = dk(r);
                 const uint64_t md = __ballot(valid && d == dom);
                 const uint32_t nd = (uint32_t)__popcll(md);
                 uint32_t b0 = 0;
@@ -326,7 +387,11 @@ __global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
 #pragma unroll
             for (int r = 0; r < kIt; ++r) {
                 const uint32_t li = w * kKpw + r * kWave + lane;
-                if (li < n_tile) stage[tstart[digit_of((K)(key[r] - kb), shift)] + rank[r]] = (uint64_t)key[r];
+                if (li < n_tile) {
+                    const uint32_t d = dk(r);
+                    stage[tstart[d] + rank[r]] = (uint64_t)key[r];
+                    if constexpr (kSplit) sdig[tstart[d] + rank[r]] = (uint8_t)d;
+                }
             }
         }
         __syncthreads();
@@ -335,14 +400,39 @@ __global__ __launch_bounds__(kScatterThreads) void radix_scatter_kernel(
         // at its listed destination
         K* ko = m.dst ? (K*)(uintptr_t)m.dst[seg] : kout + b;
         uint64_t* vo = kPayload ? (m.vdst ? (uint64_t*)(uintptr_t)m.vdst[seg] : vout + b) : nullptr;
-        for (uint32_t i = threadIdx.x; i < n_tile; i += kScatterThreads) {
-            const K k = (K)stage[i];
-            const uint32_t d = digit_of((K)(k - kb), shift);
-            const uint64_t dst = gofs[d] + (i - tstart[d]);
-            // plain stores: a digit run covers parts of cache lines, which
-            // the L2 merges before they go out
-            as_global(ko)[dst] = k;
-            if constexpr (kPayload) as_global(vo)[dst] = as_global(vsrc)[sidx[i]];
+        if constexpr (kPayload) {
+            // every payload word of the thread's outputs is gathered (from
+            // the tile's input, which the L2 holds) before the first store
+            uint64_t pv[kIt];
+#pragma unroll
+            for (int r = 0; r < kIt; ++r) {
+                const uint32_t i = r * kScatterThreads + threadIdx.x;
+                pv[r] = i < n_tile ? as_global(vsrc)[sidx[i]] : 0;
+            }
+#pragma unroll
+            for (int r = 0; r < kIt; ++r) {
+                const uint32_t i = r * kScatterThreads + threadIdx.x;
+                if (i < n_tile) {
+                    const K k = (K)stage[i];
+                    uint32_t d;
+                    if constexpr (kSplit) d = sdig[i];
+                    else d = dig(k);
+                    const uint64_t dst = gofs[d] + (i - tstart[d]);
+                    as_global(ko)[dst] = k;
+                    as_global(vo)[dst] = pv[r];
+                }
+            }
+        } else {
+            for (uint32_t i = threadIdx.x; i < n_tile; i += kScatterThreads) {
+                const K k = (K)stage[i];
+                uint32_t d;
+                if constexpr (kSplit) d = sdig[i];
+                else d = dig(k);
+                const uint64_t dst = gofs[d] + (i - tstart[d]);
+                // plain stores: a digit run covers parts of cache lines, which
+                // the L2 merges before they go out
+                as_global(ko)[dst] = k;
+            }
         }
     }
 }
@@ -360,11 +450,14 @@ hipError_t count_scan_impl(const RadixPass& a, hipStream_t stream) {
     prof.begin(stream);
     if (a.counted) {
         // counted where the keys were written
-    } else if (a.and_mask)
-        hipLaunchKernelGGL((radix_count_kernel<K, true>), grid, block, 0, stream, (const K*)a.keys_in,
+    } else if (a.map.splits)   // a splitter level (its masks are always taken)
+        hipLaunchKernelGGL((radix_count_kernel<K, true, true>), grid, block, 0, stream, (const K*)a.keys_in,
+                           a.map, a.shift, a.seg_shift, a.counts, a.and_mask, a.or_mask);
+    else if (a.and_mask)
+        hipLaunchKernelGGL((radix_count_kernel<K, true, false>), grid, block, 0, stream, (const K*)a.keys_in,
                            a.map, a.shift, a.seg_shift, a.counts, a.and_mask, a.or_mask);
     else
-        hipLaunchKernelGGL((radix_count_kernel<K, false>), grid, block, 0, stream, (const K*)a.keys_in,
+        hipLaunchKernelGGL((radix_count_kernel<K, false, false>), grid, block, 0, stream, (const K*)a.keys_in,
                            a.map, a.shift, a.seg_shift, a.counts, nullptr, nullptr);
     prof.end(kProfRadixCount, stream, a.total_len * sizeof(K) + table);
     prof.begin(stream);
@@ -384,18 +477,35 @@ hipError_t scatter_impl(const RadixPass& a, hipStream_t stream) {
     prof.begin(stream);
     const dim3 sgrid((a.num_tiles + kScatterTilesPerGroup - 1) / kScatterTilesPerGroup);
     const dim3 sblock(kScatterThreads);
-    if (pay)
-        hipLaunchKernelGGL((radix_scatter_kernel<K, true, true>), sgrid, sblock, 0, stream,
-                           (const K*)a.keys_in, a.vals_in, (K*)a.keys_out, a.vals_out, a.map,
-                           a.shift, a.seg_shift, a.counts, a.num_tiles);
-    else if (a.any_order)
-        hipLaunchKernelGGL((radix_scatter_kernel<K, false, false>), sgrid, sblock, 0, stream,
-                           (const K*)a.keys_in, nullptr, (K*)a.keys_out, nullptr, a.map, a.shift,
-                           a.seg_shift, a.counts, a.num_tiles);
-    else
-        hipLaunchKernelGGL((radix_scatter_kernel<K, false, true>), sgrid, sblock, 0, stream,
-                           (const K*)a.keys_in, nullptr, (K*)a.keys_out, nullptr, a.map, a.shift,
-                           a.seg_shift, a.counts, a.num_tiles);
+    const bool split = a.map.splits != nullptr;
+    if (pay) {
+        if (split)
+            hipLaunchKernelGGL((radix_scatter_kernel<K, true, true, true>), sgrid, sblock, 0, stream,
+                               (const K*)a.keys_in, a.vals_in, (K*)a.keys_out, a.vals_out, a.map,
+                               a.shift, a.seg_shift, a.counts, a.num_tiles);
+        else
+            hipLaunchKernelGGL((radix_scatter_kernel<K, true, true, false>), sgrid, sblock, 0, stream,
+                               (const K*)a.keys_in, a.vals_in, (K*)a.keys_out, a.vals_out, a.map,
+                               a.shift, a.seg_shift, a.counts, a.num_tiles);
+    } else if (a.any_order) {
+        if (split)
+            hipLaunchKernelGGL((radix_scatter_kernel<K, false, false, true>), sgrid, sblock, 0, stream,
+                               (const K*)a.keys_in, nullptr, (K*)a.keys_out, nullptr, a.map, a.shift,
+                               a.seg_shift, a.counts, a.num_tiles);
+        else
+            hipLaunchKernelGGL((radix_scatter_kernel<K, false, false, false>), sgrid, sblock, 0, stream,
+                               (const K*)a.keys_in, nullptr, (K*)a.keys_out, nullptr, a.map, a.shift,
+                               a.seg_shift, a.counts, a.num_tiles);
+    } else {
+        if (split)
+            hipLaunchKernelGGL((radix_scatter_kernel<K, false, true, true>), sgrid, sblock, 0, stream,
+                               (const K*)a.keys_in, nullptr, (K*)a.keys_out, nullptr, a.map, a.shift,
+                               a.seg_shift, a.counts, a.num_tiles);
+        else
+            hipLaunchKernelGGL((radix_scatter_kernel<K, false, true, false>), sgrid, sblock, 0, stream,
+                               (const K*)a.keys_in, nullptr, (K*)a.keys_out, nullptr, a.map, a.shift,
+                               a.seg_shift, a.counts, a.num_tiles);
+    }
     prof.end(kProfRadixScatter, stream,
              a.total_len * 2 * (sizeof(K) + (pay ? 8 : 0)) + table);
     return hipGetLastError();

@@ -17,11 +17,16 @@
 //          it by an on-chip sample sort: classes between and equal to the
 //          distinct values of 64 sampled keys (a run of equal keys is placed
 //          in one step), the keys of each unequal class ranked directly
-//   3. sub-buckets above kCapT go through deeper levels of the same MSD pass
-//      on the 8 bits below their top, each range taking its own digit and
-//      alternating between the temporary buffer and the output, with the
-//      same skip rule; each level's sub-buckets are packed into on-chip jobs
-//      of at most kCapT keys.  Every level lowers the top by at least 8 bits.
+//   3. sub-buckets above kCapT go through deeper levels of the same
+//      count / scan / scatter pass, where a key's "digit" is its class among
+//      up to 127 splitters drawn from a sample of its sub-bucket (classes of
+//      keys equal to a splitter, and between two): a value repeated through
+//      the sub-bucket becomes one class of equal keys, and the other classes
+//      hold about n / 128 keys each whatever the bits look like.  Levels
+//      alternate between the temporary buffer and the output; each level's
+//      classes are packed into on-chip jobs of at most kCapT keys (the job's
+//      key range from its classes' bounds), and a class still above kCapT
+//      takes another level.
 // With a payload every step is stable, so equal keys keep their input order;
 // keys alone may swap places with equal keys, which leaves the output the same.
 
@@ -341,6 +346,8 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
         if constexpr (kPayload) {
             // equal keys keep their input order
             const uint16_t ie = Bi[e];
+            // the payload word is loaded while the rank is counted
+            const uint64_t v = kStage ? Bv[e] : as_global(vsrc)[ie];
 #pragma unroll 1
             for (uint32_t j = g0; j < g1; ++j) {
                 const K x = Bk[j];
@@ -348,8 +355,7 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
             }
             const uint32_t o = g0 + rk;
             st_stream(kout + base + o, k);
-            if constexpr (kStage) st_stream(vout + base + o, Bv[e]);
-            else st_stream(vout + base + o, as_global(vsrc)[ie]);
+            st_stream(vout + base + o, v);
             fence(o, k);
         } else {
             // keys only: equal keys are interchangeable, so the ones placed
@@ -682,6 +688,89 @@ __global__ void level_prep_kernel(OversizeList ov, LevelWork w, uint64_t tmp, ui
     }
 }
 
+// Splitters of the entries of a deeper level whose digit (the 8 bits below
+// their top, set by level_prep_kernel) would leave most keys for another
+// level: one digit value holds a quarter of 64 keys taken one per stratum of
+// 64.  Such an entry samples 128 keys (16 consecutive keys from a jittered
+// place of each of 8 strata, one cache line a stratum), sorts them across the
+// wave (bitonic network on lane shuffles, two keys a lane), and its distinct
+// sample values, at most kSplitSlots - 1 of them, become its splitters S_0 <
+// ... < S_{m-1}; the table is padded with all ones.  The level then places
+// the entry's keys by their class among them instead of by the digit: a value
+// with a key in the sample is one of the splitters, so its keys form a class
+// of equal keys, sorted at once; the other classes hold about n / 128 keys
+// each, however the key bits are spread.  Other entries keep their digit (no
+// splitters).  A wave per entry; the waves stride over the entries.
+template <typename K>
+__global__ __launch_bounds__(256) void split_build_kernel(OversizeList ov, LevelWork w) {
+    constexpr uint32_t kS = 2 * kWave;   // sample keys: element i is register i / 64 of lane i % 64
+    constexpr uint32_t kRun = 16;        // consecutive keys per stratum
+    static_assert(kS == kSplitSlots, "the distinct sample values fill at most the table");
+    const uint32_t lane = lane_id();
+    const uint64_t below = lanes_below_mask();
+    const uint32_t E = min(*ov.count, ov.capacity);
+    const uint32_t wpb = blockDim.x / kWave, waves = gridDim.x * wpb;
+    for (uint32_t e = blockIdx.x * wpb + threadIdx.x / kWave; e < E; e += waves) {   // uniform over the wave
+        const uint64_t n = ov.end[e] - ov.beg[e];
+        const K* src = (const K*)(uintptr_t)ov.src[e];
+        const K kb = (K)ov.base[e];
+        const int shift = w.shift[e];
+        {
+            const uint64_t u = (lane * 37u + 11u) & 63u;
+            const K x = src[((64ull * lane + u) * n) / (64ull * kWave)];
+            const uint32_t d = (uint32_t)((K)(x - kb) >> shift) & 0xFFu;
+            if (!__ballot(__popcll(match_byte(d, ~0ull)) >= kWave / 4)) {   // the digit spreads the keys
+                if (lane == 0) w.n_splits[e] = 0;
+                continue;
+            }
+        }
+        uint64_t v[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const uint64_t i = lane + kWave * q, st = i / kRun, u = (st * 37u + 11u) & 63u;
+            const uint64_t at = min(((64ull * st + u) * n) / (64ull * (kS / kRun)), n - kRun);
+            v[q] = (uint64_t)src[at + i % kRun];
+        }
+        for (uint32_t k = 2; k <= kS; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                if (j == kWave) {   // the pair (lane, lane + 64): this lane's two keys
+                    const bool up = (lane & k) == 0;
+                    const uint64_t lo = min(v[0], v[1]), hi = max(v[0], v[1]);
+                    v[0] = up ? lo : hi;
+                    v[1] = up ? hi : lo;
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const uint32_t i = lane + kWave * q;
+                        const uint64_t y = shfl_u64(v[q], (int)(lane ^ j));
+                        const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+                        v[q] = keep_min ? min(v[q], y) : max(v[q], y);
+                    }
+                }
+            }
+        }
+        // the distinct values in order: element i stays when i == 0 or it
+        // differs from element i - 1 (the last element, rank 127, is left out)
+        const uint64_t p0 = shfl_u64(v[0], (int)((lane + kWave - 1) % kWave));
+        const uint64_t p1 = shfl_u64(v[1], (int)((lane + kWave - 1) % kWave));
+        const uint64_t last0 = shfl_u64(v[0], kWave - 1);
+        const bool keep0 = lane == 0 || v[0] != p0;
+        const bool keep1 = lane + 1 < (uint32_t)kWave && v[1] != (lane == 0 ? last0 : p1);
+        const uint64_t b0 = __ballot(keep0), b1 = __ballot(keep1);
+        const uint32_t m0 = (uint32_t)__popcll(b0), m = m0 + (uint32_t)__popcll(b1);
+        uint64_t* T = w.splits + (uint64_t)e * kSplitSlots;
+        if (keep0) T[__popcll(b0 & below)] = v[0];
+        if (keep1) T[m0 + __popcll(b1 & below)] = v[1];
+        for (uint32_t c = m + lane; c < kSplitSlots; c += kWave) T[c] = ~0ull;
+        if (lane == 0) {
+            w.n_splits[e] = m;
+            // a flag, not a count: one atomic per entry on one word would
+            // take its turn with every other entry's
+            if (*(volatile uint32_t*)w.split_entries == 0) *(volatile uint32_t*)w.split_entries = 1;
+        }
+    }
+}
+
 // The entries a level decides on: level 1 takes them from the MSD pass map
 // (keys at the sort's input), deeper levels from their list.
 struct DecideView {
@@ -701,7 +790,22 @@ struct DecideView {
     uint32_t min_len = 0;              // entries of at most this many keys stay
     const uint8_t* shift = nullptr;    // digit of entry e at bits shift[e]..+7,
     int shift_all = 0;                 // or at shift_all when null
+    // splitter levels: entry e's "digits" are its classes among the
+    // n_splits[e] splitters of its table (kSplitSlots keys)
+    const uint64_t* splits = nullptr;
+    const uint32_t* n_splits = nullptr;
+    // first tile of entry e (its jobs are staged from slot 8 tile0[e] + e);
+    // null: entries lie in order of position from 0 and the tile of beg[e]
+    // plus e stands for it
+    const uint32_t* tile0 = nullptr;
 };
+
+// First staging slot of entry e: room for 8 jobs per tile it spans and one
+// more, below the first slot of any later entry.
+__device__ inline uint64_t stage_slot(const DecideView& v, uint32_t e) {
+    const uint64_t t = v.tile0 ? (uint64_t)v.tile0[e] : v.beg[e] / kSortTile + e;
+    return 8 * t + e;
+}
 
 // Workgroup per entry, between scan and scatter.  When one digit holds all
 // of an entry's keys the scatter would only copy them: the entry skips it,
@@ -725,7 +829,6 @@ __global__ __launch_bounds__(256) void level_decide_kernel(DecideView v, LevelWo
     __shared__ uint32_t job_d0[256], job_d1[256], job_len[256];
     __shared__ uint32_t scan_tmp[256 / kWave];
     __shared__ int last_ne[256 / kWave];
-    __shared__ uint32_t n_jobs, job0;
     const uint32_t E = v.count ? min(*v.count, v.capacity) : v.n;
     const uint32_t e = blockIdx.x;
     if (e >= E) return;
@@ -742,7 +845,8 @@ __global__ __launch_bounds__(256) void level_decide_kernel(DecideView v, LevelWo
     __syncthreads();
     bool narrow = false;
     const int sh = v.shift ? (int)v.shift[e] : v.shift_all;
-    if (nz > 1 && !small) {   // uniform over the workgroup
+    const bool by_splits = v.splits && v.n_splits[e] > 0;
+    if (nz > 1 && !small && !by_splits) {   // uniform over the workgroup
         const uint64_t vary = w.and_mask[e] ^ w.or_mask[e];
         const int hb = 63 - __clzll((long long)vary);
         // 2^(hb - sh + 1) digit values can occur; each sub-bucket would
@@ -782,11 +886,15 @@ __global__ __launch_bounds__(256) void level_decide_kernel(DecideView v, LevelWo
             job_len[d] = 0;
             job_d0[d] = 0;   // last non-empty digit of the job
         }
+        // an entry of t tiles gives at most 4 n / cap + 1 <= 8 t + 1 jobs
+        // (cap >= 2048), the room its staging slots have
+        const uint64_t q0 = stage_slot(v, e);
+        const bool fits = tot <= 8 * ((n + kSortTile - 1) / kSortTile) + 1 && q0 + tot <= pj.s_capacity;
         if (d == 0) {
-            n_jobs = tot;
-            job0 = atomicAdd(pj.count, tot);
-            if (job0 + tot > pj.capacity) atomicOr(pj.err, 1u);
+            pj.n_of[e] = fits ? tot : 0u;
+            if (!fits) atomicOr(pj.err, 1u);
         }
+        if (!fits) return;   // uniform over the workgroup
         __syncthreads();
         if (ne) {
             atomicAdd(&job_len[jid], len);
@@ -794,25 +902,39 @@ __global__ __launch_bounds__(256) void level_decide_kernel(DecideView v, LevelWo
             if (first) job_d1[jid] = d;   // first sub-bucket of the job
         }
         __syncthreads();
-        const uint32_t nj = n_jobs, q0 = job0;
-        if (q0 + nj > pj.capacity) return;
+        const uint32_t nj = tot;
         const uint32_t shift = (uint32_t)sh;
         if (d < nj) {
-            pj.start[q0 + d] = sb_start[(uint64_t)e * 256 + job_d1[d]];
-            pj.len[q0 + d] = job_len[d];
-            pj.entry[q0 + d] = e;
-            // the job's digits lie in [first, last]: taken from the first
-            // digit on, key - base has digit (d - first) and the same bits
-            // above the digit, so only the bits of last - first and those
-            // below the digit vary (one sub-bucket: the bits below its digit)
-            const uint32_t x = job_d0[d] - job_d1[d];
-            pj.base[q0 + d] = (v.base ? v.base[e] : 0) + ((uint64_t)job_d1[d] << shift);
-            pj.bits[q0 + d] = (uint8_t)(shift + (x ? 32 - __clz(x) : 0));
+            pj.s_start[q0 + d] = sb_start[(uint64_t)e * 256 + job_d1[d]];
+            pj.s_len[q0 + d] = job_len[d];
+            const uint64_t eb = v.base ? v.base[e] : 0;
+            if (by_splits) {
+                // the job's classes lie in [first, last]: its keys lie between
+                // the least key the first class can hold and the largest the
+                // last can (the entry's own ends from its AND and OR)
+                const uint64_t* T = v.splits + (uint64_t)e * kSplitSlots;
+                const uint32_t m = v.n_splits[e];
+                const uint32_t c1 = job_d1[d], c0 = job_d0[d];
+                const uint32_t j1 = c1 >> 1, j0 = c0 >> 1;
+                const uint64_t lo = (c1 & 1u) ? T[j1] : (j1 == 0 ? eb + w.and_mask[e] : T[j1 - 1] + 1);
+                const uint64_t hi = (c0 & 1u) ? T[j0] : (j0 >= m ? eb + w.or_mask[e] : T[j0] - 1);
+                pj.s_base[q0 + d] = lo;
+                pj.s_bits[q0 + d] = (uint8_t)(hi > lo ? 64 - __clzll((long long)(hi - lo)) : 0);
+            } else {
+                // the job's digits lie in [first, last]: taken from the first
+                // digit on, key - base has digit (d - first) and the same bits
+                // above the digit, so only the bits of last - first and those
+                // below the digit vary (one sub-bucket: the bits below its digit)
+                const uint32_t x = job_d0[d] - job_d1[d];
+                pj.s_base[q0 + d] = eb + ((uint64_t)job_d1[d] << shift);
+                pj.s_bits[q0 + d] = (uint8_t)(shift + (x ? 32 - __clz(x) : 0));
+            }
         }
         return;
     }
     sb_len[(uint64_t)e * 256 + threadIdx.x] = 0;
     if (threadIdx.x != 0) return;
+    if (pj.count) pj.n_of[e] = 0;
     w.skip[e] = 1;
     const uint32_t seg = v.seg ? v.seg[e] : e;
     const uint8_t loc = v.loc ? v.loc[e] : kLocIn;
@@ -845,6 +967,76 @@ __global__ __launch_bounds__(256) void level_decide_kernel(DecideView v, LevelWo
         next.loc[q] = loc;
         next.src[q] = src;
         next.vsrc[q] = vsrc;
+    }
+}
+
+// Packing of the staged jobs, in three launches: the job count of every
+// chunk of kPackChunk entries (4 per thread); per chunk its offset (the
+// counts of the chunks before it) and a scan of its entries, which turns
+// n_of into each entry's first place in the list (n_of[E]: the list's size,
+// stored by the first workgroup with the count); then the copy, a thread per
+// job, each finding its entry among those places.
+__global__ __launch_bounds__(256) void pack_count_kernel(PackedJobs pj, uint32_t E) {
+    __shared__ uint32_t scratch[256 / kWave];
+    const uint32_t i0 = blockIdx.x * kPackChunk + threadIdx.x * 4;
+    uint32_t t = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k)
+        if (i0 + k < E) t += pj.n_of[i0 + k];
+    uint32_t tot;
+    (void)block_exclusive_scan<uint32_t, 256>(t, scratch, &tot);
+    if (threadIdx.x == 0) pj.chunk_sum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void pack_offsets_kernel(PackedJobs pj, uint32_t E) {
+    __shared__ uint32_t scratch[256 / kWave];
+    const uint32_t c = blockIdx.x;
+    uint32_t before = 0, all = 0;
+    for (uint32_t j = threadIdx.x; j < gridDim.x; j += 256) {
+        const uint32_t x = pj.chunk_sum[j];
+        if (j < c) before += x;
+        all += x;
+    }
+    uint32_t off, tot;
+    (void)block_exclusive_scan<uint32_t, 256>(before, scratch, &off);
+    if (c == 0) {
+        (void)block_exclusive_scan<uint32_t, 256>(all, scratch, &tot);
+        if (threadIdx.x == 0) {
+            *pj.count = tot;
+            pj.n_of[E] = tot;
+            if (tot > pj.capacity) atomicOr(pj.err, 1u);
+        }
+    }
+    const uint32_t i0 = c * kPackChunk + threadIdx.x * 4;
+    uint32_t cnt[4], t = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        cnt[k] = i0 + k < E ? pj.n_of[i0 + k] : 0u;
+        t += cnt[k];
+    }
+    uint32_t q = off + block_exclusive_scan<uint32_t, 256>(t, scratch, &tot);
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+        if (i0 + k < E) pj.n_of[i0 + k] = q;
+        q += cnt[k];
+    }
+}
+
+__global__ __launch_bounds__(256) void pack_copy_kernel(PackedJobs pj, DecideView v, uint32_t E) {
+    const uint32_t J = min(pj.n_of[E], pj.capacity);
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < J; q += gridDim.x * blockDim.x) {
+        // the entry whose places hold q: the last e with n_of[e] <= q
+        uint32_t lo = 0, hi = E - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (pj.n_of[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        const uint64_t sl = stage_slot(v, lo) + (q - pj.n_of[lo]);
+        pj.start[q] = pj.s_start[sl];
+        pj.len[q] = pj.s_len[sl];
+        pj.entry[q] = lo;
+        pj.base[q] = pj.s_base[sl];
+        pj.bits[q] = pj.s_bits[sl];
     }
 }
 
@@ -933,6 +1125,14 @@ hipError_t read_summary(const OversizeList& ov, const SlowList& sl, const EqualL
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess && host.pinned[4]) e = hipErrorOutOfMemory;   // a list overran
     return e;
+}
+
+// The staged jobs of a level's E entries into the packed list.
+void pack_jobs(const PackedJobs& pj, const DecideView& v, uint32_t E, hipStream_t s) {
+    const uint32_t g = (E + kPackChunk - 1) / kPackChunk;
+    hipLaunchKernelGGL(pack_count_kernel, dim3(g), dim3(256), 0, s, pj, E);
+    hipLaunchKernelGGL(pack_offsets_kernel, dim3(g), dim3(256), 0, s, pj, E);
+    hipLaunchKernelGGL(pack_copy_kernel, dim3(1024), dim3(256), 0, s, pj, v, E);
 }
 
 template <typename T>
@@ -1029,9 +1229,10 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         v.min_len = cap;
         v.shift = a.seg_shift;
         v.shift_all = bits;
-        if (pack1) hipLaunchKernelGGL(count_reset_kernel, dim3(1), dim3(1), 0, s, a.pj.count);
+        v.tile0 = listed ? a.msd_tile0 : nullptr;
         hipLaunchKernelGGL(level_decide_kernel, dim3(msd_segs), dim3(256), 0, s, v, a.lw, a.sb_start,
                            a.sb_len, a.ov, a.eq, pack1 ? a.pj : PackedJobs{}, cap);
+        if (pack1) pack_jobs(a.pj, v, msd_segs, s);
         e = radix_scatter(ps, s);
         if (e != hipSuccess) return e;
     }
@@ -1081,6 +1282,18 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         const uint64_t vt = pay ? (uint64_t)(uintptr_t)a.vals_tmp : 0, vo = pay ? (uint64_t)(uintptr_t)a.vals_out : 0;
         hipLaunchKernelGGL(level_prep_kernel, dim3(min((E + 255) / 256, 1024u)), dim3(256), 0, s, cur, a.lw,
                            kt, ko, vt, vo, a.key_bytes);
+        // splitters for the entries whose digit would leave most keys for
+        // another level; the level takes the splitter kernels only when one
+        // entry has them (a flag read back)
+        hipLaunchKernelGGL(count_reset_kernel, dim3(1), dim3(1), 0, s, a.lw.split_entries);
+        if (a.key_bytes == 4)
+            hipLaunchKernelGGL(split_build_kernel<uint32_t>, dim3(min((E + 3) / 4, 16384u)), dim3(256), 0, s, cur, a.lw);
+        else
+            hipLaunchKernelGGL(split_build_kernel<uint64_t>, dim3(min((E + 3) / 4, 16384u)), dim3(256), 0, s, cur, a.lw);
+        e = hipMemcpyAsync(host.pinned + 5, a.lw.split_entries, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        const bool by_splits = host.pinned[5] > 0;
         RadixPass ps;
         ps.key_bytes = a.key_bytes;
         ps.keys_in = a.keys_tmp;        // unused: every entry has its source
@@ -1097,6 +1310,8 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         ps.map.dst = a.lw.dst;
         ps.map.vdst = pay ? a.lw.vdst : nullptr;
         ps.map.skip = a.lw.skip;
+        ps.map.splits = by_splits ? a.lw.splits : nullptr;
+        ps.map.n_splits = by_splits ? a.lw.n_splits : nullptr;
         ps.num_segs = E;
         ps.num_tiles = T;
         ps.seg_shift = a.lw.shift;
@@ -1112,7 +1327,6 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         e = radix_count_scan(ps, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(ov_reset_kernel, dim3(1), dim3(1), 0, s, nxt, SlowList{}, EqualList{});
-        hipLaunchKernelGGL(count_reset_kernel, dim3(1), dim3(1), 0, s, a.pj.count);
         DecideView v;
         v.beg = cur.beg;
         v.end = cur.end;
@@ -1125,8 +1339,12 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         v.count = cur.count;
         v.capacity = cur.capacity;
         v.shift = a.lw.shift;
+        v.splits = by_splits ? a.lw.splits : nullptr;
+        v.n_splits = by_splits ? a.lw.n_splits : nullptr;
+        v.tile0 = cur.tile0;
         hipLaunchKernelGGL(level_decide_kernel, dim3(E), dim3(256), 0, s, v, a.lw, host.fb_sb_start,
                            host.fb_sb_len, nxt, a.eq, a.pj, cap);
+        pack_jobs(a.pj, v, E, s);
         e = radix_scatter(ps, s);
         if (e != hipSuccess) return e;
         // packed jobs: an entry of n keys gives at most n / (cap/2) jobs of
@@ -1215,6 +1433,15 @@ uint64_t packed_capacity(uint64_t total_len) {
 uint64_t level_capacity(uint32_t num_segs, uint64_t total_len) {
     const uint64_t o = oversize_capacity(total_len);
     return num_segs > o ? num_segs : o;
+}
+
+// Staging slots of the packed jobs: 8 per tile and one per entry, for the
+// tiles of a level (at most total_len / kSortTile plus one per entry) or the
+// tile of each entry's first position plus one per entry before it (level 1
+// in fixed mode).
+uint64_t stage_capacity(uint32_t num_segs, uint64_t total_len) {
+    const uint64_t l = level_capacity(num_segs, total_len);
+    return 8 * (total_len / kSortTile + l + 1) + l + 1;
 }
 
 }  // namespace hss
