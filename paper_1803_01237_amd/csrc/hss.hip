@@ -178,6 +178,7 @@ struct Engine {
     uint32_t S = 0, Q = 0;    // segments, splitter rows
     uint64_t T = 0;           // entries of the (q+1) x p tables
     uint32_t p_max = 0, J = 1, k_max = 1;
+    uint64_t min_seg = 0;              // shortest segment the local sort's first level takes
     uint64_t max_seg = 0, max_bucket = 0;
     // engines of a batch read their inputs through per-segment source
     // addresses; segments above kDirectSegMax take the MSD pass from a list,
@@ -308,6 +309,7 @@ struct Engine {
         }
         if (ev_start) (void)hipEventDestroy(ev_start);
         if (ev_pre) (void)hipEventDestroy(ev_pre);
+        if (hh.flag_ev) (void)hipEventDestroy(hh.flag_ev);
         if (pre_mem) dev_release(mem, pre_mem);
         for (void* q : {probe_mem, psort_mem, (void*)cmat, (void*)hh.fb_counts, (void*)hh.fb_sb_start,
                         (void*)hh.fb_sb_len, arena})
@@ -355,6 +357,7 @@ void build_layout(Engine& E, Layout& L) {
     E.k_max = 1;
     E.max_seg = 0;
     E.max_bucket = 0;
+    E.min_seg = ~0ull;
     for (InstHost& h : E.ih) {
         h.pos0 = pos;
         h.seg0 = seg;
@@ -367,6 +370,7 @@ void build_layout(Engine& E, Layout& L) {
         E.p_max = std::max(E.p_max, h.p);
         E.k_max = std::max(E.k_max, h.k);
         E.max_seg = std::max(E.max_seg, h.max_seg);
+        E.min_seg = std::min(E.min_seg, h.n / h.p);   // segments of floor(n / p) keys or one more
         E.max_bucket = std::max(E.max_bucket, h.max_bucket);
     }
     E.n_tot = pos;
@@ -431,6 +435,8 @@ void build_layout(Engine& E, Layout& L) {
                 L.direct_seg.push_back(s);
                 continue;
             }
+            if (L.msd_seg.empty()) E.min_seg = len;
+            E.min_seg = std::min(E.min_seg, len);
             const uint32_t li = (uint32_t)L.msd_seg.size();
             L.msd_seg.push_back(s);
             L.msd_beg.push_back(L.seg_off[s]);
@@ -583,9 +589,9 @@ size_t layout(Engine& E, char* base) {
     E.lw.vdst = ar.take<uint64_t>(lwc);
     E.lw.and_mask = ar.take<uint64_t>(lwc);
     E.lw.or_mask = ar.take<uint64_t>(lwc);
-    // splitter tables of the deeper levels' entries
-    E.lw.splits = ar.take<uint64_t>(ovc * kSplitSlots);
-    E.lw.n_splits = ar.take<uint32_t>(ovc);
+    // splitter tables of a level's entries
+    E.lw.splits = ar.take<uint64_t>(lwc * kSplitSlots);
+    E.lw.n_splits = ar.take<uint32_t>(lwc);
     E.lw.split_entries = ar.take<uint32_t>(1);
     const uint64_t pjc = packed_capacity(n);
     E.pj.count = ar.take<uint32_t>(1);
@@ -758,6 +764,7 @@ hss_status engine_init(Engine& E) {
     layout(E, (char*)E.arena);
     HIP_TRY(host_alloc(E.mem, (void**)&E.h_ctr, sizeof(RoundCounters) + 32));
     E.hh.pinned = (uint32_t*)((char*)E.h_ctr + sizeof(RoundCounters));
+    if (!E.fixed_mem) HIP_TRY(hipEventCreateWithFlags(&E.hh.flag_ev, hipEventDisableTiming));
     HIP_TRY(host_alloc(E.mem, (void**)&E.h_run, E.ih.size() * sizeof(InstRun)));
     HIP_TRY(host_alloc(E.mem, (void**)&E.h_hist, E.J * sizeof(RoundHist)));
     hipStream_t cs = E.own_stream;
@@ -940,6 +947,7 @@ hss_status segment_sort(Engine& E, bool first, const void* kin, const uint64_t* 
     hs.prof = &E.prof;
     hs.cap_large = first && E.knobs.small_sort_cap > 2048;
     hs.counted = !first && E.sort_counted;
+    hs.min_seg_len = first ? E.min_seg : 0;
     if (first && E.listed) {
         hs.num_segs = E.n_msd;
         hs.msd_seg = E.msd_seg;

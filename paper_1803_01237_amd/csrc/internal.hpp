@@ -284,7 +284,7 @@ struct LevelWork {
     uint64_t* vdst = nullptr;
     uint64_t* and_mask = nullptr;
     uint64_t* or_mask = nullptr;
-    uint64_t* splits = nullptr;        // deeper levels: kSplitSlots keys per entry
+    uint64_t* splits = nullptr;        // kSplitSlots keys per entry of a level
     uint32_t* n_splits = nullptr;      // splitters of every entry
     uint32_t* split_entries = nullptr; // nonzero when an entry of the level has splitters
 };
@@ -313,6 +313,7 @@ struct HybridSort {
     uint64_t* vals_tmp = nullptr;
     const uint64_t* seg_off = nullptr;
     uint32_t num_segs = 0;
+    uint64_t min_seg_len = 0;          // shortest segment of the first level (0: not known)
     uint64_t max_seg_len = 0;
     uint64_t total_len = 0;
     uint32_t* counts = nullptr;        // >= radix_count_words(num_segs, max_seg_len)
@@ -392,6 +393,11 @@ struct HybridHost {
     uint32_t last_oversize = 0;        // entries of the first deeper level
     uint32_t last_slow = 0;
     uint32_t last_levels = 0;          // deeper levels run
+    // the first level's splitter flag: waited for through this event (the
+    // count by digits queued behind its copy), unless the last call took
+    // splitters there; null: the stream is waited for
+    hipEvent_t flag_ev = nullptr;
+    bool split1_last = false;
 };
 
 hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host);

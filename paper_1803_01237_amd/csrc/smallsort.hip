@@ -688,6 +688,46 @@ __global__ void level_prep_kernel(OversizeList ov, LevelWork w, uint64_t tmp, ui
     }
 }
 
+// The entries a level decides on: level 1 takes them from the MSD pass map
+// (keys at the sort's input), deeper levels from their list.
+struct DecideView {
+    const uint64_t* beg = nullptr;
+    const uint64_t* end = nullptr;
+    const uint64_t* base = nullptr;    // null: 0
+    const uint32_t* seg = nullptr;     // null: the entry index
+    const uint8_t* loc = nullptr;      // null: kLocIn
+    const uint64_t* src = nullptr;     // null: keys_in at beg
+    const uint64_t* vsrc = nullptr;
+    uint64_t keys_in = 0;
+    uint64_t vals_in = 0;
+    int key_bytes = 8;
+    const uint32_t* count = nullptr;   // entries (null: n)
+    uint32_t capacity = 0;             // of the list behind count
+    uint32_t n = 0;
+    uint32_t min_len = 0;              // entries of at most this many keys stay
+    const uint8_t* shift = nullptr;    // digit of entry e at bits shift[e]..+7,
+    int shift_all = 0;                 // or at shift_all when null
+    // splitter levels: entry e's "digits" are its classes among the
+    // n_splits[e] splitters of its table (kSplitSlots keys)
+    const uint64_t* splits = nullptr;
+    const uint32_t* n_splits = nullptr;
+    // first level: entries of at most 64 look_cap keys take splitters when
+    // most keys' digits would hold above look_cap keys (sub-buckets the level
+    // would pass on); 0: when one digit holds a quarter of the keys
+    uint32_t look_cap = 0;
+    // first tile of entry e (its jobs are staged from slot 8 tile0[e] + e);
+    // null: entries lie in order of position from 0 and the tile of beg[e]
+    // plus e stands for it
+    const uint32_t* tile0 = nullptr;
+};
+
+// First staging slot of entry e: room for 8 jobs per tile it spans and one
+// more, below the first slot of any later entry.
+__device__ inline uint64_t stage_slot(const DecideView& v, uint32_t e) {
+    const uint64_t t = v.tile0 ? (uint64_t)v.tile0[e] : v.beg[e] / kSortTile + e;
+    return 8 * t + e;
+}
+
 // Splitters of the entries of a deeper level whose digit (the 8 bits below
 // their top, set by level_prep_kernel) would leave most keys for another
 // level: one digit value holds a quarter of 64 keys taken one per stratum of
@@ -702,24 +742,41 @@ __global__ void level_prep_kernel(OversizeList ov, LevelWork w, uint64_t tmp, ui
 // each, however the key bits are spread.  Other entries keep their digit (no
 // splitters).  A wave per entry; the waves stride over the entries.
 template <typename K>
-__global__ __launch_bounds__(256) void split_build_kernel(OversizeList ov, LevelWork w) {
+__global__ __launch_bounds__(256) void split_build_kernel(DecideView v, LevelWork w) {
     constexpr uint32_t kS = 2 * kWave;   // sample keys: element i is register i / 64 of lane i % 64
     constexpr uint32_t kRun = 16;        // consecutive keys per stratum
     static_assert(kS == kSplitSlots, "the distinct sample values fill at most the table");
     const uint32_t lane = lane_id();
     const uint64_t below = lanes_below_mask();
-    const uint32_t E = min(*ov.count, ov.capacity);
+    const uint32_t E = v.count ? min(*v.count, v.capacity) : v.n;
     const uint32_t wpb = blockDim.x / kWave, waves = gridDim.x * wpb;
     for (uint32_t e = blockIdx.x * wpb + threadIdx.x / kWave; e < E; e += waves) {   // uniform over the wave
-        const uint64_t n = ov.end[e] - ov.beg[e];
-        const K* src = (const K*)(uintptr_t)ov.src[e];
-        const K kb = (K)ov.base[e];
-        const int shift = w.shift[e];
+        const uint64_t n = v.end[e] - v.beg[e];
+        if (n <= v.min_len || n < 2 * kSplitSlots || (v.look_cap && n > 64ull * v.look_cap)) {
+            // sorted whole, too few keys to sample, or (first level) classes
+            // of about n / 128 keys would not fit the small sort
+            if (lane == 0) w.n_splits[e] = 0;
+            continue;
+        }
+        const K* src = v.src ? (const K*)(uintptr_t)v.src[e]
+                             : (const K*)(uintptr_t)(v.keys_in + v.beg[e] * (uint64_t)v.key_bytes);
+        const K kb = v.base ? (K)v.base[e] : (K)0;
+        const int shift = v.shift ? (int)v.shift[e] : v.shift_all;
         {
             const uint64_t u = (lane * 37u + 11u) & 63u;
             const K x = src[((64ull * lane + u) * n) / (64ull * kWave)];
             const uint32_t d = (uint32_t)((K)(x - kb) >> shift) & 0xFFu;
-            if (!__ballot(__popcll(match_byte(d, ~0ull)) >= kWave / 4)) {   // the digit spreads the keys
+            const uint32_t c = (uint32_t)__popcll(match_byte(d, ~0ull));   // sampled keys in this digit
+            bool split;
+            if (v.look_cap) {
+                // a sampled key's digit holds about c n / 64 keys: splitters
+                // when half the sampled keys sit in digits above look_cap
+                const bool big = (uint64_t)c * n > (uint64_t)kWave * v.look_cap;
+                split = __popcll(__ballot(big)) >= kWave / 2;
+            } else {
+                split = __ballot(c >= kWave / 4) != 0;
+            }
+            if (!split) {   // uniform over the wave
                 if (lane == 0) w.n_splits[e] = 0;
                 continue;
             }
@@ -771,41 +828,6 @@ __global__ __launch_bounds__(256) void split_build_kernel(OversizeList ov, Level
     }
 }
 
-// The entries a level decides on: level 1 takes them from the MSD pass map
-// (keys at the sort's input), deeper levels from their list.
-struct DecideView {
-    const uint64_t* beg = nullptr;
-    const uint64_t* end = nullptr;
-    const uint64_t* base = nullptr;    // null: 0
-    const uint32_t* seg = nullptr;     // null: the entry index
-    const uint8_t* loc = nullptr;      // null: kLocIn
-    const uint64_t* src = nullptr;     // null: keys_in at beg
-    const uint64_t* vsrc = nullptr;
-    uint64_t keys_in = 0;
-    uint64_t vals_in = 0;
-    int key_bytes = 8;
-    const uint32_t* count = nullptr;   // entries (null: n)
-    uint32_t capacity = 0;             // of the list behind count
-    uint32_t n = 0;
-    uint32_t min_len = 0;              // entries of at most this many keys stay
-    const uint8_t* shift = nullptr;    // digit of entry e at bits shift[e]..+7,
-    int shift_all = 0;                 // or at shift_all when null
-    // splitter levels: entry e's "digits" are its classes among the
-    // n_splits[e] splitters of its table (kSplitSlots keys)
-    const uint64_t* splits = nullptr;
-    const uint32_t* n_splits = nullptr;
-    // first tile of entry e (its jobs are staged from slot 8 tile0[e] + e);
-    // null: entries lie in order of position from 0 and the tile of beg[e]
-    // plus e stands for it
-    const uint32_t* tile0 = nullptr;
-};
-
-// First staging slot of entry e: room for 8 jobs per tile it spans and one
-// more, below the first slot of any later entry.
-__device__ inline uint64_t stage_slot(const DecideView& v, uint32_t e) {
-    const uint64_t t = v.tile0 ? (uint64_t)v.tile0[e] : v.beg[e] / kSortTile + e;
-    return 8 * t + e;
-}
 
 // Workgroup per entry, between scan and scatter.  When one digit holds all
 // of an entry's keys the scatter would only copy them: the entry skips it,
@@ -916,8 +938,12 @@ __global__ __launch_bounds__(256) void level_decide_kernel(DecideView v, LevelWo
                 const uint32_t m = v.n_splits[e];
                 const uint32_t c1 = job_d1[d], c0 = job_d0[d];
                 const uint32_t j1 = c1 >> 1, j0 = c0 >> 1;
+                // (the OR of the offsets may pass the largest key: the sum
+                // is held to the key width)
+                const uint64_t kmax = v.key_bytes == 4 ? 0xFFFFFFFFull : ~0ull;
+                const uint64_t top = eb + w.or_mask[e];
                 const uint64_t lo = (c1 & 1u) ? T[j1] : (j1 == 0 ? eb + w.and_mask[e] : T[j1 - 1] + 1);
-                const uint64_t hi = (c0 & 1u) ? T[j0] : (j0 >= m ? eb + w.or_mask[e] : T[j0] - 1);
+                const uint64_t hi = (c0 & 1u) ? T[j0] : (j0 >= m ? (top < eb || top > kmax ? kmax : top) : T[j0] - 1);
                 pj.s_base[q0 + d] = lo;
                 pj.s_bits[q0 + d] = (uint8_t)(hi > lo ? 64 - __clzll((long long)(hi - lo)) : 0);
             } else {
@@ -1127,6 +1153,27 @@ hipError_t read_summary(const OversizeList& ov, const SlowList& sl, const EqualL
     return e;
 }
 
+// Splitters for the entries of a level whose digit would leave most of their
+// keys for another level; the level takes the splitter kernels only when one
+// entry has them (a flag read back).
+hipError_t launch_splits(const HybridSort& a, const DecideView& v, uint32_t E, HybridHost& host, hipStream_t s) {
+    const dim3 grid(min((E + 3) / 4, 16384u));
+    hipLaunchKernelGGL(count_reset_kernel, dim3(1), dim3(1), 0, s, a.lw.split_entries);
+    if (a.key_bytes == 4)
+        hipLaunchKernelGGL(split_build_kernel<uint32_t>, grid, dim3(256), 0, s, v, a.lw);
+    else
+        hipLaunchKernelGGL(split_build_kernel<uint64_t>, grid, dim3(256), 0, s, v, a.lw);
+    return hipMemcpyAsync(host.pinned + 5, a.lw.split_entries, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+}
+
+hipError_t build_splits(const HybridSort& a, const DecideView& v, uint32_t E, HybridHost& host, hipStream_t s,
+                        bool* by_splits) {
+    hipError_t e = launch_splits(a, v, E, host, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    *by_splits = e == hipSuccess && host.pinned[5] > 0;
+    return e;
+}
+
 // The staged jobs of a level's E entries into the packed list.
 void pack_jobs(const PackedJobs& pj, const DecideView& v, uint32_t E, hipStream_t s) {
     const uint32_t g = (E + kPackChunk - 1) / kPackChunk;
@@ -1173,12 +1220,27 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
     // jobs.
     const uint64_t msd_keys = listed ? (uint64_t)msd_tiles * kSortTile : a.total_len;
     const uint64_t job_bound1 = 4 * msd_keys / cap + msd_segs;
-    const bool pack1 = msd_segs > 0 && msd_tiles > 0 && a.pj.count &&
-                       msd_keys < (uint64_t)msd_segs * 256 * (cap / 4) && job_bound1 <= a.pj.capacity;
+    const bool can_pack1 = msd_segs > 0 && msd_tiles > 0 && a.pj.count && job_bound1 <= a.pj.capacity;
+    bool pack1 = can_pack1 && msd_keys < (uint64_t)msd_segs * 256 * (cap / 4);
     // 1. MSD pass of the large segments into the temporary buffer.  A segment
     //    above the small-sort capacity whose top digit holds all its keys
     //    skips the scatter and goes on to the deeper levels.
     if (msd_segs > 0 && msd_tiles > 0) {
+        DecideView v;
+        v.beg = listed ? a.msd_beg : a.seg_off;
+        v.end = listed ? a.msd_end : a.seg_off + 1;
+        v.base = a.seg_base;
+        v.seg = a.msd_seg;
+        v.src = a.msd_src;
+        v.vsrc = a.msd_vsrc;
+        v.keys_in = (uint64_t)(uintptr_t)a.keys_in;
+        v.vals_in = (uint64_t)(uintptr_t)a.vals_in;
+        v.key_bytes = a.key_bytes;
+        v.n = msd_segs;
+        v.min_len = cap;
+        v.shift = a.seg_shift;
+        v.shift_all = bits;
+        v.tile0 = listed ? a.msd_tile0 : nullptr;
         RadixPass ps;
         ps.key_bytes = a.key_bytes;
         ps.keys_in = a.keys_in;
@@ -1213,23 +1275,39 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         if (!a.counted)
             hipLaunchKernelGGL(mask_reset_kernel, dim3(min((msd_segs + 255) / 256, 1024u)), dim3(256), 0, s,
                                a.lw, msd_segs);
-        e = radix_count_scan(ps, s);
-        if (e != hipSuccess) return e;
-        DecideView v;
-        v.beg = ps.map.beg;
-        v.end = ps.map.end;
-        v.base = a.seg_base;
-        v.seg = a.msd_seg;
-        v.src = a.msd_src;
-        v.vsrc = a.msd_vsrc;
-        v.keys_in = (uint64_t)(uintptr_t)a.keys_in;
-        v.vals_in = (uint64_t)(uintptr_t)a.vals_in;
-        v.key_bytes = a.key_bytes;
-        v.n = msd_segs;
-        v.min_len = cap;
-        v.shift = a.seg_shift;
-        v.shift_all = bits;
-        v.tile0 = listed ? a.msd_tile0 : nullptr;
+        // A segment of few distinct digits, whose sub-buckets would mostly
+        // pass to the next level, takes splitters here (its sub-buckets then
+        // go through packed jobs, which carry their key ranges); not when the
+        // digits were counted already by the kernel that wrote the keys.
+        // Unless the plan's last call took them, the count by digits is
+        // queued behind the flag's copy and the host waits for the copy
+        // alone; with splitters the count is taken again by class.
+        bool by_splits = false, counted_digits = false;
+        if (can_pack1 && !a.counted && (a.min_seg_len == 0 || a.min_seg_len <= 64ull * cap)) {
+            v.look_cap = cap;
+            e = launch_splits(a, v, msd_segs, host, s);
+            if (e == hipSuccess && host.flag_ev && !host.split1_last) {
+                e = hipEventRecord(host.flag_ev, s);
+                if (e == hipSuccess) e = radix_count_scan(ps, s);
+                if (e == hipSuccess) e = hipEventSynchronize(host.flag_ev);
+                counted_digits = true;
+            } else if (e == hipSuccess) {
+                e = hipStreamSynchronize(s);
+            }
+            if (e != hipSuccess) return e;
+            by_splits = host.pinned[5] > 0;
+            host.split1_last = by_splits;
+            pack1 = pack1 || by_splits;
+        }
+        v.look_cap = 0;
+        v.splits = by_splits ? a.lw.splits : nullptr;
+        v.n_splits = by_splits ? a.lw.n_splits : nullptr;
+        ps.map.splits = v.splits;
+        ps.map.n_splits = v.n_splits;
+        if (!counted_digits || by_splits) {
+            e = radix_count_scan(ps, s);
+            if (e != hipSuccess) return e;
+        }
         hipLaunchKernelGGL(level_decide_kernel, dim3(msd_segs), dim3(256), 0, s, v, a.lw, a.sb_start,
                            a.sb_len, a.ov, a.eq, pack1 ? a.pj : PackedJobs{}, cap);
         if (pack1) pack_jobs(a.pj, v, msd_segs, s);
@@ -1282,18 +1360,22 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         const uint64_t vt = pay ? (uint64_t)(uintptr_t)a.vals_tmp : 0, vo = pay ? (uint64_t)(uintptr_t)a.vals_out : 0;
         hipLaunchKernelGGL(level_prep_kernel, dim3(min((E + 255) / 256, 1024u)), dim3(256), 0, s, cur, a.lw,
                            kt, ko, vt, vo, a.key_bytes);
-        // splitters for the entries whose digit would leave most keys for
-        // another level; the level takes the splitter kernels only when one
-        // entry has them (a flag read back)
-        hipLaunchKernelGGL(count_reset_kernel, dim3(1), dim3(1), 0, s, a.lw.split_entries);
-        if (a.key_bytes == 4)
-            hipLaunchKernelGGL(split_build_kernel<uint32_t>, dim3(min((E + 3) / 4, 16384u)), dim3(256), 0, s, cur, a.lw);
-        else
-            hipLaunchKernelGGL(split_build_kernel<uint64_t>, dim3(min((E + 3) / 4, 16384u)), dim3(256), 0, s, cur, a.lw);
-        e = hipMemcpyAsync(host.pinned + 5, a.lw.split_entries, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        DecideView v;
+        v.beg = cur.beg;
+        v.end = cur.end;
+        v.base = cur.base;
+        v.seg = cur.seg;
+        v.loc = cur.loc;
+        v.src = cur.src;
+        v.vsrc = cur.vsrc;
+        v.key_bytes = a.key_bytes;
+        v.count = cur.count;
+        v.capacity = cur.capacity;
+        v.shift = a.lw.shift;
+        v.tile0 = cur.tile0;
+        bool by_splits = false;
+        e = build_splits(a, v, E, host, s, &by_splits);
         if (e != hipSuccess) return e;
-        const bool by_splits = host.pinned[5] > 0;
         RadixPass ps;
         ps.key_bytes = a.key_bytes;
         ps.keys_in = a.keys_tmp;        // unused: every entry has its source
@@ -1327,21 +1409,8 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         e = radix_count_scan(ps, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(ov_reset_kernel, dim3(1), dim3(1), 0, s, nxt, SlowList{}, EqualList{});
-        DecideView v;
-        v.beg = cur.beg;
-        v.end = cur.end;
-        v.base = cur.base;
-        v.seg = cur.seg;
-        v.loc = cur.loc;
-        v.src = cur.src;
-        v.vsrc = cur.vsrc;
-        v.key_bytes = a.key_bytes;
-        v.count = cur.count;
-        v.capacity = cur.capacity;
-        v.shift = a.lw.shift;
         v.splits = by_splits ? a.lw.splits : nullptr;
         v.n_splits = by_splits ? a.lw.n_splits : nullptr;
-        v.tile0 = cur.tile0;
         hipLaunchKernelGGL(level_decide_kernel, dim3(E), dim3(256), 0, s, v, a.lw, host.fb_sb_start,
                            host.fb_sb_len, nxt, a.eq, a.pj, cap);
         pack_jobs(a.pj, v, E, s);

@@ -7,6 +7,9 @@ levels (so one level sorts in place in the output), clustered duplicates
 that end in the slow path (an on-chip sample sort) from an in-place level, and
 segments of at most 2048 keys whose 64 sampled places all hold one value, so
 that the sample sort is left with one class of almost every key to rank.
+Keys from the top sixth of a Zipf-Morton draw (few heavy values near the
+largest key) take splitters at the first level and again below it, where the
+last class of an entry ends at the largest key of the key width.
 Local sort, partition and sort must equal the oracle bit for bit, keys alone
 and with a payload.
 """
@@ -61,6 +64,12 @@ def _keys(kind, n, seed, bits, p):
     elif kind == "clustered_dups":   # 3000 values 2^(b-13) apart, ~n/3000 copies each
         step = np.uint64(1) << np.uint64(bits - 13)
         k = top + rng.integers(0, 3000, n).astype(np.uint64) * step
+    elif kind == "top_zipf":         # the largest sixth of 6 n Zipf-Morton keys, shuffled
+        k = synth.make("zipf_morton", 6 * n, seed)
+        k = np.sort(k)[-n:]
+        if bits == 32:
+            k = k >> np.uint64(32)
+        k = k[rng.permutation(n)]
     elif kind == "low7":             # only the lowest 7 bits vary
         k = rng.integers(0, 101, n).astype(np.uint64)
     else:
@@ -88,6 +97,9 @@ CASES = [
     ("SKEW1", 400_000, 16, 32, False),
     ("planted_samples", 2048 * 8, 8, 64, True),   # sample sort: one class of 1984 keys
     ("planted_samples", 1500 * 16, 16, 32, False),
+    ("top_zipf", 320_000, 4, 64, True),        # splitter classes up to the largest key
+    ("top_zipf", 320_000, 4, 32, True),
+    ("top_zipf", 1 << 20, 16, 64, False),
 ]
 
 
