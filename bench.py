@@ -42,13 +42,13 @@ WORKLOADS = {
 # figures hold for the kernel sources with the hash below; after any change
 # to them the traffic is reported as null until the counters are taken again.
 TRAFFIC_WORKLOAD = "uniform_u64_2^28_p1024"
-TRAFFIC_SRC_SHA = "87999ba4c003bc07"
+TRAFFIC_SRC_SHA = "a86a37c3b41c1f97"
 TRAFFIC = {   # family: (fetch bytes, write bytes) per launch
-    "radix_count": (2147721975, 71303168),
-    "radix_scan": (134381568, 70254592),
-    "radix_scatter": (2214718895, 2320545851),
-    "exchange_copy": (2306259810, 2152709971),
-    "small_sort": (2229538527, 2294236820),
+    "radix_count": (2147692925, 71303168),
+    "radix_scan": (134379863, 70254592),
+    "radix_scatter": (2214719125, 2190512500),
+    "exchange_copy": (2306318377, 2152691854),
+    "small_sort": (2229671624, 2474584868),
 }
 
 
