@@ -333,14 +333,16 @@ def sweep_bench(plan, keys, n, p, eps, hseed, steps):
     return out
 
 
-def served_bench(count, mults, check_every):
+def served_bench(count, mults, check_every, wait_us=0):
     """The served workload: u64 requests with a payload arriving as a Poisson
     process, served by the library's request server; requests alternate
     between partition (even index) and sort (odd index).  The rate is set
     from the plain-path capacity (keys per second of one plan per request:
     create, partition or sort, release) times each multiplier.  Latency is
     completion minus the scheduled arrival; every check_every-th request is
-    compared with its solo run."""
+    compared with its solo run.  With wait_us, one more run at 1.0 times
+    the capacity lets a lone partition request wait that long for another
+    to share its batch (latency for batching)."""
     import torch
     import paper_1803_01237_amd as hss
     import synth
@@ -371,11 +373,11 @@ def served_bench(count, mults, check_every):
     runs = []
     window = 32
     inflight = 96
-    for mult in mults:
+    for mult, wait in [(m, 0) for m in mults] + ([(1.0, wait_us)] if wait_us else []):
         rate = mult * capacity / mean_n                 # requests per second
         arrivals = np.cumsum(np.random.default_rng(5).exponential(1.0 / rate, count))
         lat, lag, kept = [], [], []
-        with hss.Server() as srv:
+        with hss.Server(batch_wait_us=wait) as srv:
             t0 = srv.clock() + 0.05
             pending = {}
             t_last = 0.0
@@ -432,7 +434,7 @@ def served_bench(count, mults, check_every):
                     and torch.equal(vo, r.vals_out)
         del kept
         lat_ms = np.array(lat) * 1e3
-        runs.append({"rate_x_capacity": mult, "requests_per_s": round(rate, 1),
+        runs.append({"rate_x_capacity": mult, "batch_wait_us": wait, "requests_per_s": round(rate, 1),
                      "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
                      "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
                      "throughput_gkeys_s": round(total / makespan / 1e9, 3),
@@ -444,7 +446,7 @@ def served_bench(count, mults, check_every):
                      "submit_lag_p99_ms": round(float(np.percentile(np.array(lag) * 1e3, 99)), 3),
                      "checked_against_solo": len(range(0, count, check_every)),
                      "all_equal": bool(same)})
-        log(f"[bench] served x{mult}: p50 {runs[-1]['p50_ms']} ms, p99 {runs[-1]['p99_ms']} ms, "
+        log(f"[bench] served x{mult} (wait {wait} us): p50 {runs[-1]['p50_ms']} ms, p99 {runs[-1]['p99_ms']} ms, "
             f"{runs[-1]['throughput_gkeys_s']} Gkeys/s, {st['batches']} batches")
     return {"requests": count, "keys": total, "plain_capacity_gkeys_s": round(capacity / 1e9, 3),
             "shape": "N = floor(2^U(14,26)) u64 keys + u64 payload, p = clamp(floor(e^U(ln 64, ln 2049)), "
@@ -560,6 +562,8 @@ def main():
     ap.add_argument("--serve-rates", default="0.7,1.0,2.0",
                     help="arrival rates as multiples of the plain-path capacity")
     ap.add_argument("--serve-check-every", type=int, default=50)
+    ap.add_argument("--serve-wait-us", type=int, default=2000,
+                    help="one more served run at 1.0x with this batching wait (0 to skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of 2 GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -631,7 +635,7 @@ def main():
         torch.cuda.empty_cache()
     batched = batched_bench(args.batch_steps, args.batch_count) if args.batch_count > 0 else None
     served = (served_bench(args.serve_requests, [float(x) for x in args.serve_rates.split(",")],
-                           args.serve_check_every) if args.serve_requests > 0 else None)
+                           args.serve_check_every, args.serve_wait_us) if args.serve_requests > 0 else None)
 
     cpu = None
     if args.cpu_threads > 0:

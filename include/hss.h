@@ -394,6 +394,11 @@ typedef struct {
     uint32_t workers;           /* batches on the GPU at once (0: 2)        */
     uint64_t hbm_budget;        /* bytes of admitted requests' footprints   */
                                 /* at once (0: 64 GiB)                      */
+    uint32_t batch_wait_us;     /* a free worker whose queue head is a      */
+                                /* partition request with no other of its   */
+                                /* class queued waits up to this long after */
+                                /* the head's submission for one (0: never; */
+                                /* batching for latency)                    */
 } hss_server_config;
 
 /* hss_server_create -- start a server on the current device; cfg NULL: the

@@ -169,7 +169,7 @@ _OPS = {"partition": HSS_OP_PARTITION, "sort": HSS_OP_SORT}
 
 class _ServerConfig(C.Structure):
     _fields_ = [("max_batch_keys", C.c_uint64), ("max_batch_requests", C.c_uint32),
-                ("workers", C.c_uint32), ("hbm_budget", C.c_uint64)]
+                ("workers", C.c_uint32), ("hbm_budget", C.c_uint64), ("batch_wait_us", C.c_uint32)]
 
 
 _lib.hss_server_create.argtypes = [C.POINTER(_vp), C.POINTER(_ServerConfig)]
@@ -609,9 +609,9 @@ class Server:
     request."""
 
     def __init__(self, max_batch_keys: int = 0, max_batch_requests: int = 0, workers: int = 0,
-                 hbm_budget: int = 0):
+                 hbm_budget: int = 0, batch_wait_us: int = 0):
         h = _vp()
-        cfg = _ServerConfig(max_batch_keys, max_batch_requests, workers, hbm_budget)
+        cfg = _ServerConfig(max_batch_keys, max_batch_requests, workers, hbm_budget, batch_wait_us)
         _check(_lib.hss_server_create(C.byref(h), C.byref(cfg)), "hss_server_create")
         self._h = h
         self._live = {}

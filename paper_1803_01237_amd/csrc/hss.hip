@@ -1581,6 +1581,7 @@ struct hss_server_s {
     uint64_t max_keys = 0;
     uint32_t max_reqs = 0;
     uint64_t budget = 0;
+    double wait_s = 0;                  // a lone partition request's wait for company
     BlockCache cache;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -1660,6 +1661,20 @@ hss_status run_server_batch(hss_server_s* S, hipStream_t stream, const std::vect
 // keep their places -- and runs them as one batch on its stream; the head
 // waits while the batches already running leave it no room, unless none is
 // running.
+// Queued requests of the head's class (operation, key width, payload), at
+// most 2 counted; called with the lock held.
+uint32_t same_class_queued(const hss_server_s* S) {
+    if (S->queue.empty()) return 0;
+    const hss_request& f = S->reqs.at(S->queue.front()).r;
+    uint32_t c = 0;
+    for (uint64_t t : S->queue) {
+        const hss_request& r = S->reqs.at(t).r;
+        if (r.op == f.op && r.key_type == f.key_type && (r.vals_in != nullptr) == (f.vals_in != nullptr) && ++c >= 2)
+            break;
+    }
+    return c;
+}
+
 void server_loop(hss_server_s* S, uint32_t wid) {
     (void)hipSetDevice(S->device);
     const hipStream_t stream = S->streams[wid];
@@ -1676,6 +1691,16 @@ void server_loop(hss_server_s* S, uint32_t wid) {
                 return S->running == 0 || S->admitted + fp <= S->budget;
             });
             if (S->queue.empty()) return;   // stopping, nothing left
+            if (S->wait_s > 0 && !S->stop && S->reqs[S->queue.front()].r.op == HSS_OP_PARTITION &&
+                same_class_queued(S) < 2) {
+                // a lone partition request waits, up to wait_s after its
+                // submission, for another of its class to share its batch
+                const double left = S->reqs[S->queue.front()].t_submit + S->wait_s - clock_s();
+                if (left > 0)
+                    S->cv_work.wait_for(lk, std::chrono::duration<double>(left),
+                                        [S] { return S->stop || S->queue.empty() || same_class_queued(S) >= 2; });
+                if (S->queue.empty()) continue;   // another worker took it
+            }
             const hss_request& f = S->reqs[S->queue.front()].r;
             const bool pay = f.vals_in != nullptr;
             const hss_key_type kt = f.key_type;
@@ -2291,6 +2316,7 @@ hss_status hss_server_create(hss_server_t* out, const hss_server_config* cfg) {
         if (!S) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
         S->max_keys = c.max_batch_keys ? c.max_batch_keys : (1ull << 30);
         S->max_reqs = c.max_batch_requests ? c.max_batch_requests : 1024u;
+        S->wait_s = c.batch_wait_us * 1e-6;
         S->budget = c.hbm_budget ? c.hbm_budget : (64ull << 30);
         S->cache.limit = S->budget;
         const uint32_t nw = c.workers ? c.workers : 2u;

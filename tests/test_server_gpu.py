@@ -246,3 +246,30 @@ def test_cache_stays_within_the_budget(hss):
     for got, keys, vals, p, seed in checked:
         ref = oracle.hss(keys, p, 0.05, seed, vals=vals, mode="partition", trace_level=0)
         assert np.array_equal(got, ref.vals)
+
+
+def test_batching_wait_gathers_a_lone_request(hss):
+    """With a batching wait, a partition request queued alone waits for a
+    second of its class (submitted 5 ms later, well inside the wait) and both
+    run as one batch; a request that stays alone runs once its wait ends.
+    Results equal the oracle."""
+    _say("[server] batching wait")
+    with hss.Server(workers=1, batch_wait_us=500_000) as srv:
+        a = _inputs(40_000, 8, True, 1201)
+        b = _inputs(30_000, 8, True, 1202)
+        ta = srv.submit(_dev(a[0]), 16, 0.05, 21, _dev(a[1]))
+        time.sleep(0.005)
+        tb = srv.submit(_dev(b[0]), 16, 0.05, 22, _dev(b[1]))
+        ra, rb = srv.wait(ta), srv.wait(tb)
+        assert srv.stats()["batches"] == 1
+        for (keys, vals), seed, r in ((a, 21, ra), (b, 22, rb)):
+            ref = oracle.hss(keys, 16, 0.05, seed, vals=vals, mode="partition", trace_level=0)
+            assert np.array_equal(r.offsets.cpu().numpy().view(np.uint64), ref.offsets)
+            assert np.array_equal(r.keys_out.cpu().numpy().view(np.uint64), ref.keys)
+            assert np.array_equal(r.vals_out.cpu().numpy().view(np.uint64), ref.vals)
+        c, _ = _inputs(20_000, 8, False, 1203)
+        rc = srv.wait(srv.submit(_dev(c), 8, 0.05, 23))
+        assert rc.t_done - rc.t_submit >= 0.45
+        assert srv.stats()["batches"] == 2
+        ref = oracle.hss(c, 8, 0.05, 23, mode="partition", trace_level=0)
+        assert np.array_equal(rc.keys_out.cpu().numpy().view(np.uint64), ref.keys)
