@@ -42,13 +42,13 @@ WORKLOADS = {
 # figures hold for the kernel sources with the hash below; after any change
 # to them the traffic is reported as null until the counters are taken again.
 TRAFFIC_WORKLOAD = "uniform_u64_2^28_p1024"
-TRAFFIC_SRC_SHA = "a86a37c3b41c1f97"
+TRAFFIC_SRC_SHA = "376791e254671c53"
 TRAFFIC = {   # family: (fetch bytes, write bytes) per launch
-    "radix_count": (2147692925, 71303168),
-    "radix_scan": (134379863, 70254592),
-    "radix_scatter": (2214719125, 2190512500),
-    "exchange_copy": (2306318377, 2152691854),
-    "small_sort": (2229671624, 2474584868),
+    "radix_count": (2147693515, 71303168),
+    "radix_scan": (134379945, 70254592),
+    "radix_scatter": (2214719253, 2190789102),
+    "exchange_copy": (2304355872, 2161983801),
+    "small_sort": (2229690115, 2471505420),
 }
 
 

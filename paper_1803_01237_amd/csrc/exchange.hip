@@ -191,13 +191,39 @@ __global__ __launch_bounds__(kT) void exchange_copy_kernel(ExchangeArgs a, uint3
             w_src[i] = a.seg_off[D.seg0 + s] + piece_start(a, D, b, s);
         }
         __syncthreads();
-        for (uint32_t r = (uint32_t)r0 + threadIdx.x; r < r1; r += kT) {
-            const uint32_t j = last_le_u32(w_off, 0, cnt, r);
-            const uint64_t src = min(w_src[j] + (r - w_off[j]), src_max);
-            const K k = B[src];
-            out[r] = k;
-            tc.add(k);
-            if constexpr (kPayload) vout[r] = a.Bv[src];
+        // kG keys a thread at a time: their sources first, then all their
+        // loads in flight together, then the stores (the loads of one key
+        // after another waited out each one's latency; all of a thread's
+        // keys at once cost occupancy)
+        constexpr int kG = 4;
+        for (uint32_t rb = (uint32_t)r0 + threadIdx.x; rb < r1; rb += kG * kT) {
+            uint64_t src[kG];
+#pragma unroll
+            for (int q = 0; q < kG; ++q) {
+                const uint32_t r = rb + (uint32_t)q * kT;
+                src[q] = 0;
+                if (r < r1) {
+                    const uint32_t j = last_le_u32(w_off, 0, cnt, r);
+                    src[q] = min(w_src[j] + (r - w_off[j]), src_max);
+                }
+            }
+            K kv[kG];
+            uint64_t vv[kPayload ? kG : 1];
+#pragma unroll
+            for (int q = 0; q < kG; ++q) {
+                const bool in = rb + (uint32_t)q * kT < r1;
+                kv[q] = in ? as_global(B)[src[q]] : (K)0;
+                if constexpr (kPayload) vv[q] = in ? as_global(a.Bv)[src[q]] : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < kG; ++q) {
+                const uint32_t r = rb + (uint32_t)q * kT;
+                if (r < r1) {
+                    as_global(out)[r] = kv[q];
+                    tc.add(kv[q]);
+                    if constexpr (kPayload) as_global(vout)[r] = vv[q];
+                }
+            }
         }
     }
     if constexpr (kCount) {

@@ -728,10 +728,12 @@ __device__ inline uint64_t stage_slot(const DecideView& v, uint32_t e) {
     return 8 * t + e;
 }
 
-// Splitters of the entries of a deeper level whose digit (the 8 bits below
-// their top, set by level_prep_kernel) would leave most keys for another
-// level: one digit value holds a quarter of 64 keys taken one per stratum of
-// 64.  Such an entry samples 128 keys (16 consecutive keys from a jittered
+// Splitters of the entries of a level whose digit would leave most keys for
+// another level, judged from 64 keys taken one per stratum of 64: at a deeper
+// level (digit: the 8 bits below the entry's top, set by level_prep_kernel)
+// when one digit value holds a quarter of them; at the first level (look_cap
+// set) when half of them sit in digits estimated above look_cap keys.  Such
+// an entry samples 128 keys (16 consecutive keys from a jittered
 // place of each of 8 strata, one cache line a stratum), sorts them across the
 // wave (bitonic network on lane shuffles, two keys a lane), and its distinct
 // sample values, at most kSplitSlots - 1 of them, become its splitters S_0 <
