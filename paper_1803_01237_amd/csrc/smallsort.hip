@@ -576,25 +576,42 @@ __global__ __launch_bounds__(kT) void sample_sort_kernel(const K* __restrict__ k
 }
 
 // Ranges whose keys are all equal: copied to the output unless already
-// there, with their fences.  Workgroups stride over the entries.
+// there, with their fences.  The range's key is read once; the payload is
+// copied four words a thread at a time (all four loads in flight before the
+// stores).  Workgroups stride over the entries.
 template <typename K>
 __global__ void equal_copy_kernel(K* __restrict__ kout, uint64_t* __restrict__ vout, EqualList eq,
                                   Fences fences) {
+    constexpr uint32_t kG = 4;
     const uint32_t E = min(*eq.count, eq.capacity);
     for (uint32_t e = blockIdx.x; e < E; e += gridDim.x) {
         const uint64_t b = eq.beg[e], n = eq.end[e] - b;
+        if (n == 0) continue;   // uniform over the workgroup
         const uint32_t seg = eq.seg[e];
         const FenceSink fs = fence_sink(fences, seg);
-        const K* src = (const K*)(uintptr_t)eq.src[e];
+        const K k = *(const K*)(uintptr_t)eq.src[e];   // every key of the range
         const uint64_t* vsrc = (const uint64_t*)(uintptr_t)eq.vsrc[e];
         const bool copy = eq.loc[e] != kLocOut;
-        for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const K k = src[i];
-            if (copy) {
-                kout[b + i] = k;
-                if (vout) vout[b + i] = vsrc[i];
+        if (!copy && !fs.dst) continue;   // in place, no fences: nothing to write
+        for (uint64_t i0 = threadIdx.x; i0 < n; i0 += kG * blockDim.x) {
+            uint64_t v[kG];
+            if (copy && vout) {
+#pragma unroll
+                for (uint32_t q = 0; q < kG; ++q) {
+                    const uint64_t i = i0 + (uint64_t)q * blockDim.x;
+                    v[q] = i < n ? vsrc[i] : 0;
+                }
             }
-            if (fs.dst) put_fence(fs, b + i, (uint64_t)k);
+#pragma unroll
+            for (uint32_t q = 0; q < kG; ++q) {
+                const uint64_t i = i0 + (uint64_t)q * blockDim.x;
+                if (i >= n) break;
+                if (copy) {
+                    kout[b + i] = k;
+                    if (vout) vout[b + i] = v[q];
+                }
+                if (fs.dst) put_fence(fs, b + i, (uint64_t)k);
+            }
         }
     }
 }
