@@ -299,6 +299,12 @@ def staged_bench(keys, n, hseed, steps, p=4096, r=64):
                                              "stage2": round(t2 * 1e3, 3)},
                             "max_bucket": int(np.diff(o).max()), "max_group": int(np.diff(g).max()),
                             "workspace_gib": round(plan.workspace_bytes / 2**30, 2)}
+        log(f"[bench] two-stage sort p={p} r={r}")
+        ms = _timed(lambda: plan.sort(keys, hseed, keys_out=kout, offsets=off, groups_out=grp), steps)
+        ku = kout[: 1 << 20].cpu().numpy().view(np.uint64)   # the first 2^20 keys in order
+        if not np.all(ku[1:] >= ku[:-1]):
+            raise RuntimeError("two-stage sort order check failed")
+        out["two_stage_sort"] = {"ms_per_step": round(ms, 4), "gkeys_per_s": round(n / (ms * 1e-3) / 1e9, 3)}
     return out
 
 

@@ -507,6 +507,19 @@ hss_status hss_staged_partition(hss_staged_t plan, uint64_t seed, const void* d_
                                 const uint64_t* d_vals_in, void* d_keys_out, uint64_t* d_vals_out,
                                 uint64_t* d_offsets, uint64_t* d_groups, void* stream);
 
+/*
+ * hss_staged_sort -- the two-stage partition (section 5.3) followed by a
+ * stable sort of every final bucket (the local sort after the last exchange):
+ * d_keys_out (and d_vals_out) receive the keys in ascending order, equal keys
+ * (with their payload) in input order; d_offsets and d_groups as for
+ * hss_staged_partition.  The plan keeps a second buffer of N keys (and
+ * payload words) from the first sort on, and reads the p+1 final offsets
+ * back once to bound the bucket sort.  Errors as hss_staged_partition.
+ */
+hss_status hss_staged_sort(hss_staged_t plan, uint64_t seed, const void* d_keys_in, const uint64_t* d_vals_in,
+                           void* d_keys_out, uint64_t* d_vals_out, uint64_t* d_offsets, uint64_t* d_groups,
+                           void* stream);
+
 /* Host wall time of the last call, in seconds: stage 1 (with the read of the
  * group boundaries), the layout of stage 2, stage 2. */
 hss_status hss_staged_times(hss_staged_t plan, double* stage1_s, double* setup_s, double* stage2_s);

@@ -50,6 +50,7 @@ EXPORTS = [
     "hss_server_memory",
     "hss_plan_knobs", "hss_plan_set_knobs", "hss_batch_knobs", "hss_plan_buckets",
     "hss_staged_plan", "hss_staged_destroy", "hss_staged_workspace_bytes", "hss_staged_partition",
+    "hss_staged_sort",
     "hss_staged_times", "hss_partition_static", "hss_partition_static_bytes", "hss_stream_copy",
     "hss_status_string", "hss_last_error",
 ]
@@ -98,6 +99,8 @@ _lib.hss_staged_workspace_bytes.argtypes = [_vp]
 _lib.hss_staged_workspace_bytes.restype = C.c_size_t
 _lib.hss_staged_partition.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.hss_staged_partition.restype = C.c_int
+_lib.hss_staged_sort.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.hss_staged_sort.restype = C.c_int
 _lib.hss_staged_times.argtypes = [_vp, C.POINTER(_dbl), C.POINTER(_dbl), C.POINTER(_dbl)]
 _lib.hss_staged_times.restype = C.c_int
 _lib.hss_plan_destroy.argtypes = [_vp]
@@ -472,6 +475,15 @@ class StagedPlan:
 
     def partition(self, keys, seed: int, vals=None, keys_out=None, vals_out=None, offsets=None,
                   groups_out=None):
+        return self._run(_lib.hss_staged_partition, "hss_staged_partition", keys, seed, vals, keys_out,
+                         vals_out, offsets, groups_out)
+
+    def sort(self, keys, seed: int, vals=None, keys_out=None, vals_out=None, offsets=None, groups_out=None):
+        """The two-stage partition, then every final bucket sorted (stably)."""
+        return self._run(_lib.hss_staged_sort, "hss_staged_sort", keys, seed, vals, keys_out, vals_out,
+                         offsets, groups_out)
+
+    def _run(self, fn, name, keys, seed, vals, keys_out, vals_out, offsets, groups_out):
         torch = _torch()
         if not keys.is_cuda or not keys.is_contiguous():
             raise ValueError("keys must be a contiguous device tensor")
@@ -490,12 +502,10 @@ class StagedPlan:
             offsets = torch.empty(self.p + 1, dtype=torch.int64, device=keys.device)
         if groups_out is None:
             groups_out = torch.empty(self.r + 1, dtype=torch.int64, device=keys.device)
-        st = _lib.hss_staged_partition(self._h, seed & NONE, keys.data_ptr(),
-                                       None if vals is None else vals.data_ptr(),
-                                       keys_out.data_ptr(),
-                                       None if vals_out is None else vals_out.data_ptr(),
-                                       offsets.data_ptr(), groups_out.data_ptr(), _stream_handle())
-        _check(st, "hss_staged_partition")
+        st = fn(self._h, seed & NONE, keys.data_ptr(), None if vals is None else vals.data_ptr(),
+                keys_out.data_ptr(), None if vals_out is None else vals_out.data_ptr(),
+                offsets.data_ptr(), groups_out.data_ptr(), _stream_handle())
+        _check(st, name)
         return keys_out, vals_out, offsets, groups_out
 
 

@@ -2474,6 +2474,11 @@ struct hss_staged_s {
     hss_tuning tune2{};
     void* T = nullptr;              // stage-1 output: N keys
     uint64_t* Tv = nullptr;         // and payload
+    void* T2 = nullptr;             // sort: stage-2 output (N keys, payload),
+    uint64_t* T2v = nullptr;        // allocated by the first sort
+    uint32_t* sort_counts = nullptr;   // sort: count table of the final buckets
+    uint64_t sort_words = 0;
+    uint64_t* h_off = nullptr;      // sort: pinned copy of the p+1 final offsets
     uint64_t* chi1 = nullptr;       // r+1 group boundaries (device)
     uint64_t* off2 = nullptr;       // r x (p/r + 1): offsets of every group
     uint64_t* h_chi1 = nullptr;     // pinned copy of chi1
@@ -2484,9 +2489,10 @@ struct hss_staged_s {
     ~hss_staged_s() {
         (void)hipSetDevice(st1.e.device);
         (void)hipDeviceSynchronize();
-        for (void* q : {T, (void*)Tv, (void*)chi1, (void*)off2})
+        for (void* q : {T, (void*)Tv, T2, (void*)T2v, (void*)sort_counts, (void*)chi1, (void*)off2})
             if (q) (void)hipFree(q);
         if (h_chi1) (void)hipHostFree(h_chi1);
+        if (h_off) (void)hipHostFree(h_off);
         if (chi_ready) (void)hipEventDestroy(chi_ready);
         if (setup) (void)hipStreamDestroy(setup);
     }
@@ -2614,58 +2620,139 @@ size_t hss_staged_workspace_bytes(hss_staged_t P) {
     return b;
 }
 
+}  // extern "C"
+
+namespace {
+
+hss_status staged_check(hss_staged_s* P, const void* d_keys_in, const uint64_t* d_vals_in, void* d_keys_out,
+                        uint64_t* d_vals_out, uint64_t* d_offsets, uint64_t* d_groups) {
+    Engine& E = P->st1.e;
+    hss_status st = check_io_raw(E.payload, E.key_bytes, P->n, P->p, d_keys_in, d_vals_in, d_keys_out,
+                                 d_vals_out, d_offsets);
+    if (st != HSS_OK) return st;
+    if (!d_offsets) return fail(HSS_ERR_INVALID_ARG, "null offsets pointer");
+    if (d_groups && !aligned16(d_groups)) return fail(HSS_ERR_INVALID_ARG, "device pointers must be 16-byte aligned");
+    const size_t kb = P->n * (size_t)E.key_bytes, vb = P->n * 8, gb = ((size_t)P->r + 1) * 8,
+                 ob = ((size_t)P->p + 1) * 8;
+    if (d_groups && (overlap(d_groups, gb, d_keys_in, kb) || overlap(d_groups, gb, d_keys_out, kb) ||
+                     overlap(d_groups, gb, d_vals_in, vb) || overlap(d_groups, gb, d_vals_out, vb) ||
+                     overlap(d_groups, gb, d_offsets, ob)))
+        return fail(HSS_ERR_INVALID_ARG, "outputs overlap inputs or each other");
+    return HSS_OK;
+}
+
+// The two stages into (kout, vout); returns after the stream has completed.
+hss_status staged_run(hss_staged_s* P, uint64_t seed, const void* d_keys_in, const uint64_t* d_vals_in,
+                      void* kout, uint64_t* vout, uint64_t* d_offsets, uint64_t* d_groups, hipStream_t s) {
+    Engine& E = P->st1.e;
+    hss_status st = HSS_OK;
+    const size_t gb = ((size_t)P->r + 1) * 8;
+    HIP_TRY(hipSetDevice(E.device));
+    const double t0 = clock_s();
+    bool stage1_done = false;
+    if (E.tune.autotune && !E.knobs.tuned) {
+        // the first call tunes stage 1 through whole plain calls
+        st = run_plain(&P->st1, seed, d_keys_in, d_vals_in, P->T, P->Tv, P->chi1, s, false);
+        if (st != HSS_OK) return st;
+        HIP_TRY(hipMemcpyAsync(P->h_chi1, P->chi1, ((size_t)P->r + 1) * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        stage1_done = true;
+    } else {
+        // the group boundaries come back as soon as the rounds end: stage
+        // 2 is laid out on the host while stage 1's exchange still runs
+        HIP_TRY(launch_set_run(InstRun{seed, d_keys_in, d_vals_in, P->T, P->Tv, P->chi1}, E.run_d, s));
+        HIP_TRY(launch_counters_reset(E.ra.ctr, s));
+        E.chi_out_host = P->h_chi1;
+        E.chi_ready = P->chi_ready;
+        E.cur_seed = seed;
+        st = engine_run(E, d_keys_in, d_vals_in, P->T, P->Tv, s, false);
+        E.chi_out_host = nullptr;
+        E.chi_ready = nullptr;
+        if (st != HSS_OK) return st;
+        HIP_TRY(hipEventSynchronize(P->chi_ready));
+    }
+    P->t_stage[0] = clock_s() - t0;
+    st = staged_stage2(P, seed, kout, vout, s);
+    // stage 1's own checks (its exchange ran before stage 2 on the stream)
+    if (!stage1_done) {
+        const hss_status s1 = finish(E, s);
+        if (s1 != HSS_OK) return s1;
+    }
+    if (st != HSS_OK) return st;
+    HIP_TRY(launch_stage_offsets(P->chi1, P->off2, P->r, P->pg, P->n, d_offsets, s));
+    if (d_groups) HIP_TRY(hipMemcpyAsync(d_groups, P->chi1, gb, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return HSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 hss_status hss_staged_partition(hss_staged_t P, uint64_t seed, const void* d_keys_in,
                                 const uint64_t* d_vals_in, void* d_keys_out, uint64_t* d_vals_out,
                                 uint64_t* d_offsets, uint64_t* d_groups, void* stream) {
     if (!P) return fail(HSS_ERR_INVALID_ARG, "null plan");
     try {
-        Engine& E = P->st1.e;
-        hss_status st = check_io_raw(E.payload, E.key_bytes, P->n, P->p, d_keys_in, d_vals_in, d_keys_out,
-                                     d_vals_out, d_offsets);
+        hss_status st = staged_check(P, d_keys_in, d_vals_in, d_keys_out, d_vals_out, d_offsets, d_groups);
         if (st != HSS_OK) return st;
-        if (!d_offsets) return fail(HSS_ERR_INVALID_ARG, "null offsets pointer");
-        if (d_groups && !aligned16(d_groups)) return fail(HSS_ERR_INVALID_ARG, "device pointers must be 16-byte aligned");
-        const size_t kb = P->n * (size_t)E.key_bytes, vb = P->n * 8, gb = ((size_t)P->r + 1) * 8,
-                     ob = ((size_t)P->p + 1) * 8;
-        if (d_groups && (overlap(d_groups, gb, d_keys_in, kb) || overlap(d_groups, gb, d_keys_out, kb) ||
-                         overlap(d_groups, gb, d_vals_in, vb) || overlap(d_groups, gb, d_vals_out, vb) ||
-                         overlap(d_groups, gb, d_offsets, ob)))
-            return fail(HSS_ERR_INVALID_ARG, "outputs overlap inputs or each other");
+        return staged_run(P, seed, d_keys_in, d_vals_in, d_keys_out, d_vals_out, d_offsets, d_groups,
+                          (hipStream_t)stream);
+    } catch (...) {
+        return fail(HSS_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+hss_status hss_staged_sort(hss_staged_t P, uint64_t seed, const void* d_keys_in, const uint64_t* d_vals_in,
+                           void* d_keys_out, uint64_t* d_vals_out, uint64_t* d_offsets, uint64_t* d_groups,
+                           void* stream) {
+    if (!P) return fail(HSS_ERR_INVALID_ARG, "null plan");
+    try {
+        Engine& E = P->st1.e;
+        hss_status st = staged_check(P, d_keys_in, d_vals_in, d_keys_out, d_vals_out, d_offsets, d_groups);
+        if (st != HSS_OK) return st;
         hipStream_t s = (hipStream_t)stream;
         HIP_TRY(hipSetDevice(E.device));
-        const double t0 = clock_s();
-        bool stage1_done = false;
-        if (E.tune.autotune && !E.knobs.tuned) {
-            // the first call tunes stage 1 through whole plain calls
-            st = run_plain(&P->st1, seed, d_keys_in, d_vals_in, P->T, P->Tv, P->chi1, stream, false);
-            if (st != HSS_OK) return st;
-            HIP_TRY(hipMemcpyAsync(P->h_chi1, P->chi1, ((size_t)P->r + 1) * 8, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            stage1_done = true;
-        } else {
-            // the group boundaries come back as soon as the rounds end: stage
-            // 2 is laid out on the host while stage 1's exchange still runs
-            HIP_TRY(launch_set_run(InstRun{seed, d_keys_in, d_vals_in, P->T, P->Tv, P->chi1}, E.run_d, s));
-            HIP_TRY(launch_counters_reset(E.ra.ctr, s));
-            E.chi_out_host = P->h_chi1;
-            E.chi_ready = P->chi_ready;
-            E.cur_seed = seed;
-            st = engine_run(E, d_keys_in, d_vals_in, P->T, P->Tv, s, false);
-            E.chi_out_host = nullptr;
-            E.chi_ready = nullptr;
-            if (st != HSS_OK) return st;
-            HIP_TRY(hipEventSynchronize(P->chi_ready));
+        const size_t kb = P->n * (size_t)E.key_bytes;
+        if (!P->T2) {
+            HIP_TRY(hipMalloc(&P->T2, kb));
+            if (E.payload) HIP_TRY(hipMalloc((void**)&P->T2v, P->n * 8));
+            HIP_TRY(hipHostMalloc((void**)&P->h_off, ((size_t)P->p + 1) * 8, hipHostMallocDefault));
+            P->bytes += kb + (E.payload ? P->n * 8 : 0);
         }
-        P->t_stage[0] = clock_s() - t0;
-        st = staged_stage2(P, seed, d_keys_out, d_vals_out, s);
-        // stage 1's own checks (its exchange ran before stage 2 on the stream)
-        if (!stage1_done) {
-            const hss_status s1 = finish(E, s);
-            if (s1 != HSS_OK) return s1;
-        }
+        // the two-stage partition into the second buffer
+        st = staged_run(P, seed, d_keys_in, d_vals_in, P->T2, P->T2v, d_offsets, d_groups, s);
         if (st != HSS_OK) return st;
-        HIP_TRY(launch_stage_offsets(P->chi1, P->off2, P->r, P->pg, P->n, d_offsets, s));
-        if (d_groups) HIP_TRY(hipMemcpyAsync(d_groups, P->chi1, gb, hipMemcpyDeviceToDevice, s));
+        // the final buckets' sizes bound the sort's tiles
+        HIP_TRY(hipMemcpyAsync(P->h_off, d_offsets, ((size_t)P->p + 1) * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        uint64_t maxb = 0;
+        for (uint32_t b = 0; b < P->p; ++b) {
+            if (P->h_off[b + 1] < P->h_off[b] || P->h_off[b + 1] > P->n)
+                return fail(HSS_ERR_DEVICE, "the two stages returned bad offsets");
+            maxb = std::max(maxb, P->h_off[b + 1] - P->h_off[b]);
+        }
+        if (P->h_off[0] != 0 || P->h_off[P->p] != P->n) return fail(HSS_ERR_DEVICE, "the two stages returned bad offsets");
+        const uint64_t words = radix_count_words(P->p, maxb) + 256;
+        if (words > P->sort_words) {
+            if (P->sort_counts) HIP_TRY(hipFree(P->sort_counts));
+            P->sort_counts = nullptr;
+            P->sort_words = 0;
+            HIP_TRY(hipMalloc((void**)&P->sort_counts, words * 4));
+            P->sort_words = words;
+        }
+        // stable sort of every final bucket into the caller's output, through
+        // stage 1's engine (its lists and tables serve p segments of N keys)
+        // with the plan's count table and stage 1's output as the MSD buffer
+        uint32_t* const keep = E.counts;
+        const uint64_t keep_words = E.counts_words;
+        E.counts = P->sort_counts;
+        E.counts_words = P->sort_words;
+        st = segment_sort(E, false, P->T2, P->T2v, d_keys_out, d_vals_out, P->T, P->Tv, d_offsets, P->p, maxb,
+                          nullptr, nullptr, false, s);
+        E.counts = keep;
+        E.counts_words = keep_words;
+        if (st != HSS_OK) return st;
         HIP_TRY(hipStreamSynchronize(s));
         return HSS_OK;
     } catch (...) {

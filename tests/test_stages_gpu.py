@@ -281,3 +281,33 @@ def test_random_two_stage_plans_match_oracle(hss, case):
         assert np.array_equal(_host(ko, keys.dtype), ref.keys)
         if payload:
             assert np.array_equal(_host(vo, np.uint64), ref.vals)
+
+
+SORT_CASES = _random_shapes(8, 16, True)[:8] + [
+    ("zipf_morton", 1 << 22, 256, 16, 0.02, 0.02, 64, True, 301),
+    ("uniform64", 1 << 22, 256, 16, 0.02, 0.02, 32, False, 302),
+]
+
+
+@pytest.mark.parametrize("case", SORT_CASES, ids=lambda c: f"{c[0]}-{c[1]}-p{c[2]}-r{c[3]}")
+def test_two_stage_sort_matches_stable_sort(hss, case):
+    """hss_staged_sort: the keys (and payload) in stable sorted order, with
+    the offsets and groups of the oracle's two-stage partition."""
+    kind, n, p, r, eps1, eps2, bits, payload, seed = case
+    _say(f"[staged-sort] {case}")
+    keys = _keys(kind, n, seed, bits)
+    vals = np.arange(n, dtype=np.uint64) if payload else None
+    ref = oracle.hss_two_stage(keys, p, r, eps1, eps2, seed, vals=vals)
+    with hss.StagedPlan(n, p, r, eps1, eps2, key_bytes=keys.itemsize, payload=payload) as plan:
+        if ref.status != 0:
+            with pytest.raises(hss.HssError):
+                plan.sort(_dev(keys), seed, None if vals is None else _dev(vals))
+            return
+        for _ in range(2):   # the second call reuses the plan's sort buffers
+            ko, vo, off, grp = plan.sort(_dev(keys), seed, None if vals is None else _dev(vals))
+            order = np.argsort(keys, kind="stable")
+            assert np.array_equal(_host(grp, np.uint64), ref.groups)
+            assert np.array_equal(_host(off, np.uint64), ref.offsets)
+            assert np.array_equal(_host(ko, keys.dtype), keys[order])
+            if payload:
+                assert np.array_equal(_host(vo, np.uint64), vals[order])
