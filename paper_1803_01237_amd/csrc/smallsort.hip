@@ -98,6 +98,11 @@ struct SmallJobs {
     const uint32_t* lvl_seg = nullptr;
     const uint8_t* lvl_loc = nullptr;
     EqualList eq;                          // all-equal sub-buckets above the capacity
+    // jobs of at most len_lo keys or of more than len_hi keys are another
+    // launch's (the first level's sub-buckets split by size between the two
+    // capacities)
+    uint32_t len_lo = 0;
+    uint32_t len_hi = ~0u;
 };
 
 // kStage: the payload is staged in LDS as well, so that a sub-bucket may be
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(kT) void small_sort_kernel(const K* __restrict__ ki
                                             : jobs.vals_in + base)
                         : nullptr;
     }
-    if (n == 0) return;
+    if (n <= jobs.len_lo || n > jobs.len_hi) return;   // uniform; also n == 0
     if (n > (uint32_t)kCapT) {   // sub-buckets of an MSD pass only
         if (threadIdx.x == 0) {
             if (bits == 0) {     // every key equal: nothing left to sort
@@ -1339,21 +1344,25 @@ hipError_t hybrid_sort(const HybridSort& a, hipStream_t s, HybridHost& host) {
         const uint32_t n_first = pack1 ? (uint32_t)job_bound1 : msd_segs * 256u;
         const dim3 grid(n_first + a.n_direct);
         prof.begin(s);
-        if (a.key_bytes == 4) {
-            SmallJobs<uint32_t> jobs = level1_jobs<uint32_t>(a, msd_segs, kb);
+        auto run = [&](auto key) {
+            using K = decltype(key);
+            SmallJobs<K> jobs = level1_jobs<K>(a, msd_segs, kb);
             if (pack1) {
                 jobs.n_msd = n_first;
                 jobs.pj = a.pj;
             }
-            launch_small_any<uint32_t>(pay, large, false, grid, s, a, a.sb_start, a.sb_len, bits, a.ov, jobs);
-        } else {
-            SmallJobs<uint64_t> jobs = level1_jobs<uint64_t>(a, msd_segs, kb);
-            if (pack1) {
-                jobs.n_msd = n_first;
-                jobs.pj = a.pj;
+            if (large && !pack1) {
+                // sub-buckets within the small capacity take its kernel (fewer
+                // keys per group to rank), the larger ones the large kernel
+                SmallJobs<K> fit = jobs;
+                fit.len_hi = kCapSmall;
+                launch_small_any<K>(pay, false, false, grid, s, a, a.sb_start, a.sb_len, bits, a.ov, fit);
+                jobs.len_lo = kCapSmall;
             }
-            launch_small_any<uint64_t>(pay, large, false, grid, s, a, a.sb_start, a.sb_len, bits, a.ov, jobs);
-        }
+            launch_small_any<K>(pay, large, false, grid, s, a, a.sb_start, a.sb_len, bits, a.ov, jobs);
+        };
+        if (a.key_bytes == 4) run(uint32_t{});
+        else run(uint64_t{});
         prof.end(kProfSmallSort, s, a.total_len * 2 * (a.key_bytes + (pay ? 8 : 0)));
     }
     e = read_summary(a.ov, a.sl, a.eq, host, s);
