@@ -131,6 +131,11 @@ typedef struct {
  * The plan owns a device workspace of hss_workspace_bytes(plan) bytes,
  * allocated on the current device.  A plan may be reused for any number of
  * calls; calls on one plan must not overlap in time.
+ * N must be below 2^32 (HSS_ERR_UNSUPPORTED otherwise): tags, counts and
+ * piece offsets are 32-bit words.  That is 16 GiB of u32 or 32 GiB of u64
+ * keys on one device; 64-bit tags would double the count matrix, the
+ * per-cell tables and the probe arrays for inputs that one device does not
+ * hold with its workspace anyway.
  */
 hss_status hss_plan(hss_plan_t* out, uint64_t n, uint32_t p, double eps, hss_key_type kt,
                     int with_payload, const hss_tuning* tuning);
