@@ -42,13 +42,13 @@ WORKLOADS = {
 # figures hold for the kernel sources with the hash below; after any change
 # to them the traffic is reported as null until the counters are taken again.
 TRAFFIC_WORKLOAD = "uniform_u64_2^28_p1024"
-TRAFFIC_SRC_SHA = "68f3d276343def19"
+TRAFFIC_SRC_SHA = "e225b15e6edd7780"
 TRAFFIC = {   # family: (fetch bytes, write bytes) per launch
-    "radix_count": (2147720863, 71303168),
-    "radix_scan": (134381656, 70254592),
-    "radix_scatter": (2214747357, 2189920024),
-    "exchange_copy": (2304410157, 2162061680),
-    "small_sort": (2229678683, 2470368155),
+    "radix_count": (2147719848, 71303168),
+    "radix_scan": (134381585, 70254592),
+    "radix_scatter": (2214747286, 2190616733),
+    "exchange_copy": (2304444498, 2162073238),
+    "small_sort": (2229693871, 2472052229),
 }
 
 

@@ -18,15 +18,18 @@
 //          distinct values of 64 sampled keys (a run of equal keys is placed
 //          in one step), the keys of each unequal class ranked directly
 //   3. sub-buckets above kCapT go through deeper levels of the same
-//      count / scan / scatter pass, where a key's "digit" is its class among
-//      up to 127 splitters drawn from a sample of its sub-bucket (classes of
-//      keys equal to a splitter, and between two): a value repeated through
-//      the sub-bucket becomes one class of equal keys, and the other classes
-//      hold about n / 128 keys each whatever the bits look like.  Levels
-//      alternate between the temporary buffer and the output; each level's
-//      classes are packed into on-chip jobs of at most kCapT keys (the job's
-//      key range from its classes' bounds), and a class still above kCapT
-//      takes another level.
+//      count / scan / scatter pass on the 8 bits below their top.  An entry
+//      (at the first level, a segment of at most 64 kCapT keys) whose digit
+//      would leave most of its keys for another level takes splitters
+//      instead: a key's "digit" is its class among up to 127 splitters drawn
+//      from a sample of the entry (classes of keys equal to a splitter, and
+//      between two), so a value repeated through the entry becomes one class
+//      of equal keys, and the other classes hold about n / 128 keys each
+//      whatever the bits look like.  Levels alternate between the temporary
+//      buffer and the output; each level's sub-buckets are packed into
+//      on-chip jobs of at most kCapT keys (the job's key range from its
+//      first and last digit or class), and one still above kCapT takes
+//      another level.
 // With a payload every step is stable, so equal keys keep their input order;
 // keys alone may swap places with equal keys, which leaves the output the same.
 
