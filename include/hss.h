@@ -50,7 +50,8 @@ typedef enum {
     HSS_ERR_UNSUPPORTED = -2,    /* a valid request this build does not handle      */
     HSS_ERR_OUT_OF_MEMORY = -3,  /* device allocation failed                        */
     HSS_ERR_DEVICE = -4,         /* HIP error or a failed device-side consistency check */
-    HSS_ERR_NOT_CONVERGED = -5   /* tuning.max_rounds reached with splitters unsettled */
+    HSS_ERR_NOT_CONVERGED = -5,  /* tuning.max_rounds reached with splitters unsettled */
+    HSS_ERR_CANCELLED = -6       /* a server request taken out of the queue         */
 } hss_status;
 
 typedef struct hss_plan_s* hss_plan_t;
@@ -435,6 +436,15 @@ hss_status hss_server_submit(hss_server_t server, const hss_request* req, uint64
  */
 hss_status hss_server_poll(hss_server_t server, uint64_t ticket, int* done, hss_status* result,
                            double* t_submit, double* t_done);
+
+/*
+ * hss_server_cancel -- take a queued request out of the queue: *cancelled = 1
+ * and the request is done with result HSS_ERR_CANCELLED, its outputs
+ * untouched (poll or wait still retires the ticket).  A request that a worker
+ * has already taken (running or done) is left to finish: *cancelled = 0.
+ * Unknown tickets: HSS_ERR_INVALID_ARG.  cancelled may be NULL.
+ */
+hss_status hss_server_cancel(hss_server_t server, uint64_t ticket, int* cancelled);
 
 /* hss_server_wait -- as hss_server_poll, blocking until the request is done. */
 hss_status hss_server_wait(hss_server_t server, uint64_t ticket, hss_status* result,

@@ -34,7 +34,8 @@ _lib = C.CDLL(LIB_PATH)
 
 HSS_U32, HSS_U64 = 0, 1
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "out of memory",
-          -4: "device error", -5: "not converged"}
+          -4: "device error", -5: "not converged", -6: "cancelled"}
+HSS_ERR_CANCELLED = -6
 NONE = (1 << 64) - 1
 
 EXPORTS = [
@@ -46,7 +47,7 @@ EXPORTS = [
     "hss_batch_plan", "hss_batch_destroy", "hss_batch_workspace_bytes", "hss_batch_partition",
     "hss_batch_profile", "hss_batch_profile_reset", "hss_batch_profile_read",
     "hss_server_create", "hss_server_destroy", "hss_server_submit", "hss_server_poll",
-    "hss_server_wait", "hss_server_clock", "hss_server_stats", "hss_server_footprint",
+    "hss_server_wait", "hss_server_cancel", "hss_server_clock", "hss_server_stats", "hss_server_footprint",
     "hss_server_memory",
     "hss_plan_knobs", "hss_plan_set_knobs", "hss_batch_knobs", "hss_plan_buckets",
     "hss_staged_plan", "hss_staged_destroy", "hss_staged_workspace_bytes", "hss_staged_partition",
@@ -188,6 +189,8 @@ _lib.hss_server_poll.argtypes = [_vp, _u64, C.POINTER(C.c_int), C.POINTER(C.c_in
 _lib.hss_server_poll.restype = C.c_int
 _lib.hss_server_wait.argtypes = [_vp, _u64, C.POINTER(C.c_int), C.POINTER(_dbl), C.POINTER(_dbl)]
 _lib.hss_server_wait.restype = C.c_int
+_lib.hss_server_cancel.argtypes = [_vp, _u64, C.POINTER(C.c_int)]
+_lib.hss_server_cancel.restype = C.c_int
 _lib.hss_server_clock.argtypes = []
 _lib.hss_server_clock.restype = _dbl
 _lib.hss_server_stats.argtypes = [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64),
@@ -676,6 +679,14 @@ class Server:
         _check(_lib.hss_server_wait(self._h, ticket, C.byref(st), C.byref(ts), C.byref(td)),
                "hss_server_wait")
         return self._retire(ticket, st.value, ts.value, td.value)
+
+    def cancel(self, ticket: int) -> bool:
+        """Take a queued request out of the queue (True); False when a worker
+        already took it (it finishes).  A cancelled ticket is still retired by
+        poll or wait, which raise HssError with status "cancelled"."""
+        c = C.c_int()
+        _check(_lib.hss_server_cancel(self._h, ticket, C.byref(c)), "hss_server_cancel")
+        return bool(c.value)
 
     def stats(self) -> dict:
         b, r, k, mc, ma = _u64(), _u64(), _u64(), _u32(), _u64()

@@ -2409,6 +2409,28 @@ hss_status hss_server_wait(hss_server_t S, uint64_t ticket, hss_status* result, 
     return retire(S, it, result, t_submit, t_done);
 }
 
+hss_status hss_server_cancel(hss_server_t S, uint64_t ticket, int* cancelled) {
+    if (!S) return fail(HSS_ERR_INVALID_ARG, "null server");
+    if (cancelled) *cancelled = 0;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->reqs.find(ticket);
+        if (it == S->reqs.end()) return fail(HSS_ERR_INVALID_ARG, "unknown ticket");
+        auto q = std::find(S->queue.begin(), S->queue.end(), ticket);
+        if (q == S->queue.end()) return HSS_OK;   // taken by a worker: it finishes
+        S->queue.erase(q);
+        ServerReq& r = it->second;
+        r.st = HSS_ERR_CANCELLED;
+        r.msg = "request cancelled";
+        r.t_done = clock_s();
+        r.done = true;
+        if (cancelled) *cancelled = 1;
+    }
+    S->cv_done.notify_all();
+    S->cv_work.notify_all();   // a worker waiting for this request's company
+    return HSS_OK;
+}
+
 double hss_server_clock(void) { return clock_s(); }
 
 hss_status hss_server_stats(hss_server_t S, uint64_t* batches, uint64_t* requests, uint64_t* keys,

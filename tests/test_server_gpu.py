@@ -273,3 +273,36 @@ def test_batching_wait_gathers_a_lone_request(hss):
         assert srv.stats()["batches"] == 2
         ref = oracle.hss(c, 8, 0.05, 23, mode="partition", trace_level=0)
         assert np.array_equal(rc.keys_out.cpu().numpy().view(np.uint64), ref.keys)
+
+
+def test_cancel_takes_a_queued_request_out(hss):
+    """A request queued behind a running one is cancelled: waiting on it
+    raises 'cancelled' and its output is untouched; the others complete and
+    equal the oracle; a retired ticket is unknown to cancel."""
+    _say("[server] cancel")
+    with hss.Server(workers=1, max_batch_requests=1) as srv:
+        big = synth.make("uniform64", 1 << 25, 1301)         # keeps the worker busy
+        tb = srv.submit(_dev(big), 1024, 0.05, 31)
+        small = [_inputs(20_000 + 1000 * i, 8, False, 1310 + i)[0] for i in range(3)]
+        outs = [torch.zeros(len(k), dtype=torch.int64, device="cuda") for k in small]
+        ts = [srv.submit(_dev(k), 8, 0.05, 40 + i, keys_out=o) for i, (k, o) in enumerate(zip(small, outs))]
+        assert srv.cancel(ts[1]) is True
+        srv.wait(tb)
+        done = {i: srv.wait(ts[i]) for i in (0, 2)}
+        with pytest.raises(hss.HssError) as err:
+            srv.wait(ts[1])
+        assert err.value.status == hss.HSS_ERR_CANCELLED
+        assert int(outs[1].abs().sum()) == 0
+        with pytest.raises(hss.HssError):
+            srv.cancel(ts[1])                                 # retired
+        for i, r in done.items():
+            ref = oracle.hss(small[i], 8, 0.05, 40 + i, mode="partition", trace_level=0)
+            assert np.array_equal(r.keys_out.cpu().numpy().view(np.uint64), ref.keys)
+            assert np.array_equal(r.offsets.cpu().numpy().view(np.uint64), ref.offsets)
+        # a request the idle worker has taken (running or done) is not cancelled
+        t = srv.submit(_dev(small[0]), 8, 0.05, 40)
+        time.sleep(0.05)
+        assert srv.cancel(t) is False
+        r = srv.wait(t)
+        ref = oracle.hss(small[0], 8, 0.05, 40, mode="partition", trace_level=0)
+        assert np.array_equal(r.keys_out.cpu().numpy().view(np.uint64), ref.keys)
