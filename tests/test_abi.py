@@ -2,6 +2,7 @@
 point that include/hss.h declares.  No compute call is made here."""
 import os
 import re
+import sys
 
 import pytest
 
@@ -114,3 +115,13 @@ def test_pick_sampler_options_checked_on_the_host():
     with pytest.raises(lib.HssError) as ei:
         lib.Plan(1000, 10, 0.05, pick_sampler=True)   # needs probes_per_round
     assert ei.value.status == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message and a
+    non-zero status before touching the device."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
