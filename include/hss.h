@@ -47,7 +47,7 @@ typedef enum { HSS_U32 = 0, HSS_U64 = 1, HSS_KEY_TYPE_INT_RANGE_ = 0x7FFFFFFF } 
 typedef enum {
     HSS_OK = 0,
     HSS_ERR_INVALID_ARG = -1,    /* bad sizes, null or misaligned pointers, overlap */
-    HSS_ERR_UNSUPPORTED = -2,    /* a valid request this build does not handle      */
+    HSS_ERR_UNSUPPORTED = -2,    /* a valid request the library does not handle     */
     HSS_ERR_OUT_OF_MEMORY = -3,  /* device allocation failed                        */
     HSS_ERR_DEVICE = -4,         /* HIP error or a failed device-side consistency check */
     HSS_ERR_NOT_CONVERGED = -5,  /* tuning.max_rounds reached with splitters unsettled */
