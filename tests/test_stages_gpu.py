@@ -286,6 +286,8 @@ def test_random_two_stage_plans_match_oracle(hss, case):
 SORT_CASES = _random_shapes(8, 16, True)[:8] + [
     ("zipf_morton", 1 << 22, 256, 16, 0.02, 0.02, 64, True, 301),
     ("uniform64", 1 << 22, 256, 16, 0.02, 0.02, 32, False, 302),
+    ("SKEW2", 300_000, 32, 4, 0.05, 0.05, 32, True, 303),       # 101 values: equal runs
+    ("GAUSS", 1 << 21, 64, 8, 0.02, 0.05, 32, True, 304),
 ]
 
 
