@@ -225,6 +225,29 @@ hss_status hss_partition_static_bytes(uint64_t n, uint32_t p, double eps, hss_ke
                                       int with_payload, size_t* bytes, size_t* capacity);
 
 /*
+ * hss_partition_ws -- hss_partition with the caller's device workspace: a
+ * call on no plan that takes every device word it needs from d_workspace
+ * (256-byte aligned, workspace_bytes long, not overlapping the inputs or
+ * outputs) and allocates no device memory.  Section 2's problem, as
+ * hss_partition: the same outputs for the same seed.  The workspace must hold
+ * at least hss_partition_workspace_bytes for the shape (else
+ * HSS_ERR_INVALID_ARG before any device call); a call whose probe rounds
+ * overrun the 4x headroom that size includes fails with
+ * HSS_ERR_OUT_OF_MEMORY, its outputs unwritten.  The workspace's contents
+ * are scratch between calls; calls sharing one workspace must not overlap in
+ * time.  Returns after the work on `stream` has completed.
+ */
+hss_status hss_partition_ws(uint64_t n, uint32_t p, double eps, hss_key_type kt, uint64_t seed,
+                            const void* d_keys_in, const uint64_t* d_vals_in, void* d_keys_out,
+                            uint64_t* d_vals_out, uint64_t* d_offsets, void* d_workspace,
+                            size_t workspace_bytes, void* stream);
+
+/* Bytes of workspace a hss_partition_ws call of this shape needs (*bytes = 0
+ * and the shape's error for a shape hss_partition would refuse). */
+hss_status hss_partition_workspace_bytes(uint64_t n, uint32_t p, double eps, hss_key_type kt,
+                                         int with_payload, size_t* bytes);
+
+/*
  * hss_local_sort -- only the first phase (section 6, local sort): every
  * segment sorted stably by key, payload moved with its key.  The output
  * position of an element is its tag g.

@@ -53,6 +53,7 @@ EXPORTS = [
     "hss_staged_plan", "hss_staged_destroy", "hss_staged_workspace_bytes", "hss_staged_partition",
     "hss_staged_sort",
     "hss_staged_times", "hss_partition_static", "hss_partition_static_bytes", "hss_stream_copy",
+    "hss_partition_ws", "hss_partition_workspace_bytes",
     "hss_status_string", "hss_last_error",
 ]
 
@@ -749,6 +750,12 @@ _lib.hss_partition_static.argtypes = [_u64, _u32, C.c_double, C.c_int, _u64, _vp
 _lib.hss_partition_static.restype = C.c_int
 _lib.hss_partition_static_bytes.argtypes = [_u64, _u32, C.c_double, C.c_int, C.c_int, _vp, _vp]
 _lib.hss_partition_static_bytes.restype = C.c_int
+_lib.hss_partition_ws.argtypes = [_u64, _u32, C.c_double, C.c_int, _u64, _vp, _vp, _vp, _vp, _vp, _vp,
+                                  C.c_size_t, _vp]
+_lib.hss_partition_ws.restype = C.c_int
+_lib.hss_partition_workspace_bytes.argtypes = [_u64, _u32, C.c_double, C.c_int, C.c_int,
+                                               C.POINTER(C.c_size_t)]
+_lib.hss_partition_workspace_bytes.restype = C.c_int
 
 
 def partition_static(keys, p: int, eps: float, seed: int, vals=None, keys_out=None,
@@ -775,6 +782,44 @@ def partition_static(keys, p: int, eps: float, seed: int, vals=None, keys_out=No
                                    offsets.data_ptr(), _stream_handle())
     _check(st, "hss_partition_static")
     return keys_out, vals_out, offsets
+
+
+def partition_ws(keys, p: int, eps: float, seed: int, workspace, vals=None, keys_out=None,
+                 vals_out=None, offsets=None):
+    """hss_partition_ws: the partition of hss_partition in the caller's device
+    workspace (a contiguous device tensor of at least workspace_bytes(...)
+    bytes); the library allocates no device memory.  Returns (keys_out,
+    vals_out, offsets)."""
+    torch = _torch()
+    if not keys.is_cuda or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous device tensor")
+    if not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("the workspace must be a contiguous device tensor")
+    if vals is not None and (vals.numel() != keys.numel() or vals.element_size() != 8
+                             or not vals.is_contiguous() or not vals.is_cuda):
+        raise ValueError("payload must be a contiguous device tensor of N 8-byte words")
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+    if vals is not None and vals_out is None:
+        vals_out = torch.empty_like(vals)
+    if offsets is None:
+        offsets = torch.empty(p + 1, dtype=torch.int64, device=keys.device)
+    st = _lib.hss_partition_ws(keys.numel(), p, eps, _key_type(keys), seed & NONE,
+                               keys.data_ptr(), None if vals is None else vals.data_ptr(),
+                               keys_out.data_ptr(), None if vals_out is None else vals_out.data_ptr(),
+                               offsets.data_ptr(), workspace.data_ptr(),
+                               workspace.numel() * workspace.element_size(), _stream_handle())
+    _check(st, "hss_partition_ws")
+    return keys_out, vals_out, offsets
+
+
+def workspace_bytes(n: int, p: int, eps: float, key_bytes: int = 8, payload: bool = False) -> int:
+    """Bytes of workspace a hss_partition_ws call of this shape needs."""
+    b = C.c_size_t()
+    _check(_lib.hss_partition_workspace_bytes(n, p, eps, HSS_U64 if key_bytes == 8 else HSS_U32,
+                                              1 if payload else 0, C.byref(b)),
+           "hss_partition_workspace_bytes")
+    return int(b.value)
 
 
 def static_workspace_bytes(n: int, p: int, eps: float, key_bytes: int = 8,

@@ -1916,22 +1916,44 @@ size_t fixed_bytes(Engine& E) {
     return workspace_estimate(E);
 }
 
-hss_status static_shape(Engine& E, uint64_t n, uint32_t p, double eps, hss_key_type kt, bool payload) {
+// A one-instance engine laid out for a fixed region (no growth beyond it,
+// plain launches, no second stream).
+hss_status fixed_shape(Engine& E, uint64_t n, uint32_t p, double eps, hss_key_type kt, bool payload) {
     hss_status st = plan_args(n, p, p, eps, kt, nullptr);
     if (st != HSS_OK) return st;
-    if (n > HSS_STATIC_MAX_KEYS || p > HSS_STATIC_MAX_BUCKETS)
-        return fail(HSS_ERR_UNSUPPORTED, "hss_partition_static takes at most " + std::to_string(HSS_STATIC_MAX_KEYS) +
-                                             " keys and " + std::to_string(HSS_STATIC_MAX_BUCKETS) + " buckets");
     E.key_bytes = kt == HSS_U32 ? 4 : 8;
     E.payload = payload;
     E.tune.plain_launches = 1;
     E.fixed_mem = true;
-    st = new_engine_instance(E, n, p, eps);
+    return new_engine_instance(E, n, p, eps);
+}
+
+hss_status static_shape(Engine& E, uint64_t n, uint32_t p, double eps, hss_key_type kt, bool payload) {
+    if (n > HSS_STATIC_MAX_KEYS || p > HSS_STATIC_MAX_BUCKETS)
+        return fail(HSS_ERR_UNSUPPORTED, "hss_partition_static takes at most " + std::to_string(HSS_STATIC_MAX_KEYS) +
+                                             " keys and " + std::to_string(HSS_STATIC_MAX_BUCKETS) + " buckets");
+    hss_status st = fixed_shape(E, n, p, eps, kt, payload);
     if (st != HSS_OK) return st;
     if (fixed_bytes(E) > kStaticScratchBytes)
         return fail(HSS_ERR_UNSUPPORTED, "the call needs more than the fixed workspace of " +
                                              std::to_string(kStaticScratchBytes) + " bytes");
     return HSS_OK;
+}
+
+// One partition in a fixed device region (mem.dev set) and its host words.
+hss_status fixed_call(FixedArena& mem, Engine& E, uint64_t seed, const void* kin, const uint64_t* vin, void* kout,
+                      uint64_t* vout, uint64_t* d_offsets, hipStream_t s) {
+    E.mem = &mem;
+    E.own_stream = s;
+    hss_status st = engine_init(E);
+    if (st != HSS_OK) return st;
+    E.cur_seed = seed;
+    const InstRun run{seed, kin, vin, kout, vout, d_offsets};
+    HIP_TRY(launch_set_run(run, E.run_d, s));
+    HIP_TRY(launch_counters_reset(E.ra.ctr, s));
+    st = engine_run(E, kin, vin, kout, vout, s, false);
+    if (st != HSS_OK) return st;
+    return finish(E, s);
 }
 
 }  // namespace
@@ -1981,18 +2003,59 @@ hss_status hss_partition_static(uint64_t n, uint32_t p, double eps, hss_key_type
         mem.dev_cap = kStaticScratchBytes;
         mem.host = (char*)g_static_host;
         mem.host_cap = sizeof(g_static_host);
-        E.mem = &mem;
-        const hipStream_t s = (hipStream_t)stream;
-        E.own_stream = s;
-        st = engine_init(E);
+        return fixed_call(mem, E, seed, kin, vin, kout, vout, d_offsets, (hipStream_t)stream);
+    } catch (...) {
+        return fail(HSS_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+hss_status hss_partition_workspace_bytes(uint64_t n, uint32_t p, double eps, hss_key_type kt, int with_payload,
+                                         size_t* bytes) {
+    try {
+        if (!bytes) return fail(HSS_ERR_INVALID_ARG, "null bytes pointer");
+        *bytes = 0;
+        Engine E;
+        const hss_status st = fixed_shape(E, n, p, eps, kt, with_payload != 0);
         if (st != HSS_OK) return st;
-        E.cur_seed = seed;
-        const InstRun run{seed, kin, vin, kout, vout, d_offsets};
-        HIP_TRY(launch_set_run(run, E.run_d, s));
-        HIP_TRY(launch_counters_reset(E.ra.ctr, s));
-        st = engine_run(E, kin, vin, kout, vout, s, false);
+        *bytes = fixed_bytes(E);
+        return HSS_OK;
+    } catch (...) {
+        return fail(HSS_ERR_DEVICE, "unexpected exception");
+    }
+}
+
+hss_status hss_partition_ws(uint64_t n, uint32_t p, double eps, hss_key_type kt, uint64_t seed, const void* kin,
+                            const uint64_t* vin, void* kout, uint64_t* vout, uint64_t* d_offsets,
+                            void* d_workspace, size_t workspace_bytes, void* stream) {
+    try {
+        const bool payload = vin != nullptr;
+        const int kb = kt == HSS_U32 ? 4 : 8;
+        hss_status st = check_io_raw(payload, kb, n, p, kin, vin, kout, vout, d_offsets);
         if (st != HSS_OK) return st;
-        return finish(E, s);
+        if (!d_offsets) return fail(HSS_ERR_INVALID_ARG, "null offsets pointer");
+        if (!d_workspace || ((uintptr_t)d_workspace & 255))
+            return fail(HSS_ERR_INVALID_ARG, "the workspace must be a 256-byte aligned device pointer");
+        const size_t kbytes = n * (size_t)kb, vb = n * 8, ob = ((size_t)p + 1) * 8;
+        if (overlap(d_workspace, workspace_bytes, kin, kbytes) || overlap(d_workspace, workspace_bytes, kout, kbytes) ||
+            overlap(d_workspace, workspace_bytes, vin, vb) || overlap(d_workspace, workspace_bytes, vout, vb) ||
+            overlap(d_workspace, workspace_bytes, d_offsets, ob))
+            return fail(HSS_ERR_INVALID_ARG, "the workspace overlaps an input or output");
+        // shape and size on the host, before any device call
+        std::unique_ptr<unsigned char[]> host(new (std::nothrow) unsigned char[(64 << 10) + 256]);
+        if (!host) return fail(HSS_ERR_OUT_OF_MEMORY, "host allocation failed");
+        FixedArena mem;
+        Engine E;   // destroyed before mem
+        st = fixed_shape(E, n, p, eps, kt, payload);
+        if (st != HSS_OK) return st;
+        const size_t need = fixed_bytes(E);
+        if (need > workspace_bytes)
+            return fail(HSS_ERR_INVALID_ARG, "the workspace holds " + std::to_string(workspace_bytes) +
+                                                 " bytes; the call needs " + std::to_string(need));
+        mem.dev = (char*)d_workspace;
+        mem.dev_cap = workspace_bytes;
+        mem.host = (char*)(((uintptr_t)host.get() + 255) & ~(uintptr_t)255);
+        mem.host_cap = 64 << 10;
+        return fixed_call(mem, E, seed, kin, vin, kout, vout, d_offsets, (hipStream_t)stream);
     } catch (...) {
         return fail(HSS_ERR_DEVICE, "unexpected exception");
     }

@@ -593,3 +593,42 @@ def test_rounds_queued_ahead_of_the_exchange(hss):
             longer += len(ref.rounds) > k - 1
     _say(f"[parity] rounds queued ahead: {longer} of 24 seeds needed more than k - 1 = {k - 1} rounds")
     assert longer > 0
+
+
+def test_partition_in_caller_workspace(hss):
+    """hss_partition_ws: the partition in the caller's device workspace, at a
+    shape above the fixed array's limits and again, smaller and with a payload,
+    in the same workspace; no device memory taken by the library on the
+    second call; a workspace below the shape's size is refused before any
+    device work."""
+    _say("[parity] caller workspace")
+    n, p = 1 << 22, 1024
+    keys = synth.uniform64(n, 91)
+    need = hss.workspace_bytes(n, p, 0.02)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    ko, _, off = hss.partition_ws(_dev(keys), p, 0.02, 7, ws)
+    ref = oracle.hss(keys, p, 0.02, 7, mode="partition", trace_level=0)
+    assert np.array_equal(_host(off, np.uint64), ref.offsets)
+    assert np.array_equal(_host(ko, np.uint64), ref.keys)
+    # a smaller shape with a payload, in the same workspace
+    n2, p2 = 200_003, 64
+    k2 = synth.uniform64(n2, 92)
+    v2 = np.arange(n2, dtype=np.uint64)
+    assert hss.workspace_bytes(n2, p2, 0.05, payload=True) <= need
+    kd, vd = _dev(k2), _dev(v2)
+    ko2, vo2 = torch.empty_like(kd), torch.empty_like(vd)
+    off2 = torch.empty(p2 + 1, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    hss.partition_ws(kd, p2, 0.05, 8, ws, vals=vd, keys_out=ko2, vals_out=vo2, offsets=off2)
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] == free0
+    ref2 = oracle.hss(k2, p2, 0.05, 8, vals=v2, mode="partition", trace_level=0)
+    assert np.array_equal(_host(off2, np.uint64), ref2.offsets)
+    assert np.array_equal(_host(ko2, np.uint64), ref2.keys)
+    assert np.array_equal(_host(vo2, np.uint64), ref2.vals)
+    # too small: refused on the host, outputs untouched
+    out = torch.zeros(n, dtype=torch.int64, device="cuda")
+    with pytest.raises(hss.HssError):
+        hss.partition_ws(_dev(keys), p, 0.02, 7, ws[: need // 2], keys_out=out)
+    assert int(out.abs().sum()) == 0
